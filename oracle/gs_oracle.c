@@ -1,0 +1,458 @@
+/*
+ * GridShift FP64 CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, single-threaded
+ * reference that the GPU path is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * library path never calls it and shares no code with it.
+ *
+ * What it computes (GridShift, Kumar et al., arXiv 2206.02200):
+ *   - Section 2.1 (i) and Algorithm 1 (initialisation): every point x_i is put
+ *     in the grid cell with integer index floor(x_i / h), element-wise.  A cell
+ *     holding at least one point is active; it keeps a point count C and a
+ *     coordinate sum S (the running-mean centroid of Algorithm 1 times C).
+ *   - Section 2.1 (ii), Eq. 1-2, in the parallel form of Eq. 6 (Section 2.2)
+ *     and of the supplement's update of r_j: every active cell j moves to the
+ *     count-weighted mean of the centroids of the active cells j+v,
+ *     v in {-1,0,1}^d (itself included), all read from the same iteration.
+ *   - Section 2.1 (iii): the moved cell gets the key floor(p_j / h).
+ *   - Section 2.1 (iv), Eq. 3-4: cells that land on one key merge; counts add,
+ *     the centroid is the count-weighted mean, the point sets are united.
+ *   - Section 2.1 (v) and Theorem 2: stop when no active cell has an active
+ *     neighbour.  The iteration is also capped at max_iter rounds, and it stops
+ *     early when one round leaves the state bitwise unchanged.
+ *
+ * Readings where the paper leaves floating point open (all FP64,
+ * round-to-nearest-even, no fused multiply-add):
+ *   - key of a value v: floor(fl(v / h)) (IEEE division, then floor);
+ *   - point-to-cell sum: R over the members in ascending point index, where
+ *     R(a_0..a_{L-1}) = a_0 if L = 1, else R(first P) + R(rest) with P the
+ *     largest power of two below L;
+ *   - 3^d neighbourhood sum: left fold over the active neighbours in
+ *     ascending lexicographic key order (dimension 0 most significant);
+ *     the weight sum is an exact integer;
+ *   - merge sum: R over fl(C_j * p_j) for the merging cells in ascending old
+ *     key order; the merged cell's key is the landing key, never recomputed
+ *     from the merged mean;
+ *   - cells and final clusters are numbered in ascending lexicographic key.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC (x86-64 SSE2
+ * doubles, so every operation is a single IEEE binary64 rounding).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum {
+    GSO_OK = 0,
+    GSO_ERR_INVALID_ARG = 1,
+    GSO_ERR_NONFINITE = 2,
+    GSO_ERR_KEY_RANGE = 3,
+    GSO_ERR_ALLOC = 4
+};
+
+enum { GSO_CONVERGED = 1u, GSO_STATIONARY = 2u, GSO_CAPPED = 4u };
+
+/* ---------------------------------------------------------------------- */
+/* Canonical pairwise sum R (the reading used for every multi-term sum).    */
+/* ---------------------------------------------------------------------- */
+
+double gso_pairwise_sum(const double* a, int64_t L)
+{
+    if (L <= 0)
+        return -0.0; /* empty sum: the additive identity that keeps signed zeros */
+    if (L == 1)
+        return a[0];
+    int64_t P = 1;
+    while (P * 2 < L)
+        P *= 2;
+    return gso_pairwise_sum(a, P) + gso_pairwise_sum(a + P, L - P);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Lexicographic helpers on integer key vectors.                          */
+/* ---------------------------------------------------------------------- */
+
+static int cmp_keyvec(const int64_t* a, const int64_t* b, int d)
+{
+    for (int k = 0; k < d; k++) {
+        if (a[k] < b[k])
+            return -1;
+        if (a[k] > b[k])
+            return 1;
+    }
+    return 0;
+}
+
+/* qsort context: the oracle is single-threaded and not re-entrant. */
+static const int64_t* g_sort_keys;
+static int g_sort_d;
+
+/* Order row indices by (key vector, index): a stable grouping by key. */
+static int cmp_rows_by_key_then_index(const void* A, const void* B)
+{
+    int64_t i = *(const int64_t*)A, j = *(const int64_t*)B;
+    int c = cmp_keyvec(g_sort_keys + i * g_sort_d, g_sort_keys + j * g_sort_d, g_sort_d);
+    if (c)
+        return c;
+    return (i < j) ? -1 : (i > j);
+}
+
+/* Binary search of key vector q among m sorted, distinct key vectors. */
+static int64_t find_cell(const int64_t* cell_key, int64_t m, int d, const int64_t* q)
+{
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        int c = cmp_keyvec(cell_key + mid * d, q, d);
+        if (c == 0)
+            return mid;
+        if (c < 0)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return -1;
+}
+
+/* floor(fl(v / h)) as int64; fails if the result does not fit comfortably. */
+static int key_of(double v, double h, int64_t* out)
+{
+    double q = floor(v / h);
+    if (!(q > -4611686018427387904.0 && q < 4611686018427387904.0)) /* |q| < 2^62 */
+        return GSO_ERR_KEY_RANGE;
+    *out = (int64_t)q;
+    return GSO_OK;
+}
+
+/* Enumerate v in {-1,0,1}^d in lexicographic order (dimension 0 most
+ * significant): offset index r in [0, 3^d) has digit k equal to
+ * (r / 3^(d-1-k)) % 3, minus one. */
+static void offset_of(int64_t r, int d, int64_t* v)
+{
+    for (int k = d - 1; k >= 0; k--) {
+        v[k] = (r % 3) - 1;
+        r /= 3;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Step 1: binning (Section 2.1 (i), Algorithm 1 initialisation).          */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * x [n][d] binary64.  Outputs with capacity n cells: keys [m][d], counts [m],
+ * sums [m][d] (R over members in ascending point index), cell0 [n] (cell of
+ * every point), *m_out.  Cells ascend in lexicographic key order.
+ */
+int gso_bin(const double* x, int64_t n, int32_t d, double h, int64_t* keys, int64_t* counts,
+            double* sums, int64_t* cell0, int64_t* m_out)
+{
+    if (n < 0 || d < 1 || d > 16 || !(h > 0.0) || !isfinite(h))
+        return GSO_ERR_INVALID_ARG;
+    *m_out = 0;
+    for (int64_t i = 0; i < n * d; i++)
+        if (!isfinite(x[i]))
+            return GSO_ERR_NONFINITE;
+    if (n == 0)
+        return GSO_OK;
+    int rc = GSO_OK;
+    int64_t* pkey = malloc(sizeof(int64_t) * n * d);
+    int64_t* order = malloc(sizeof(int64_t) * n);
+    double* tmp = malloc(sizeof(double) * n);
+    if (!pkey || !order || !tmp) {
+        rc = GSO_ERR_ALLOC;
+        goto done;
+    }
+    for (int64_t i = 0; i < n; i++)
+        for (int k = 0; k < d; k++)
+            if ((rc = key_of(x[i * d + k], h, &pkey[i * d + k])) != GSO_OK)
+                goto done;
+    for (int64_t i = 0; i < n; i++)
+        order[i] = i;
+    g_sort_keys = pkey;
+    g_sort_d = d;
+    qsort(order, (size_t)n, sizeof(int64_t), cmp_rows_by_key_then_index);
+    int64_t m = 0;
+    for (int64_t a = 0; a < n;) {
+        int64_t b = a + 1;
+        while (b < n && cmp_keyvec(pkey + order[a] * d, pkey + order[b] * d, d) == 0)
+            b++;
+        memcpy(keys + m * d, pkey + order[a] * d, sizeof(int64_t) * d);
+        counts[m] = b - a;
+        for (int k = 0; k < d; k++) {
+            for (int64_t r = a; r < b; r++)
+                tmp[r - a] = x[order[r] * d + k];
+            sums[m * d + k] = gso_pairwise_sum(tmp, b - a);
+        }
+        for (int64_t r = a; r < b; r++)
+            cell0[order[r]] = m;
+        m++;
+        a = b;
+    }
+    *m_out = m;
+done:
+    free(pkey);
+    free(order);
+    free(tmp);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Step 2: stopping test (Section 2.1 (v), Theorem 2).                     */
+/* ---------------------------------------------------------------------- */
+
+/* 1 if some active cell has another active cell j+v, v != 0, else 0. */
+int gso_has_neighbours(const int64_t* keys, int64_t m, int32_t d)
+{
+    int64_t n_off = 1, v[16], q[16];
+    for (int k = 0; k < d; k++)
+        n_off *= 3;
+    for (int64_t j = 0; j < m; j++)
+        for (int64_t r = 0; r < n_off; r++) {
+            offset_of(r, d, v);
+            int zero = 1;
+            for (int k = 0; k < d; k++) {
+                q[k] = keys[j * d + k] + v[k];
+                zero &= (v[k] == 0);
+            }
+            if (!zero && find_cell(keys, m, d, q) >= 0)
+                return 1;
+        }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Step 3: shift (Eq. 1-2 in the parallel form of Eq. 6).                  */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * For every cell j: W_j = sum of C over the active cells j+v (v in
+ * {-1,0,1}^d, self included), N_j = left fold of their sums S in ascending
+ * key order, p_j = N_j / W_j.  Every read is of the given (round-t) table.
+ * weights [m] receives W_j (may be NULL).
+ */
+void gso_shift(const int64_t* keys, const int64_t* counts, const double* sums, int64_t m, int32_t d,
+               double* p, int64_t* weights)
+{
+    int64_t n_off = 1, v[16], q[16];
+    for (int k = 0; k < d; k++)
+        n_off *= 3;
+    for (int64_t j = 0; j < m; j++) {
+        int64_t W = 0;
+        int first = 1;
+        double* pj = p + j * d;
+        for (int64_t r = 0; r < n_off; r++) {
+            offset_of(r, d, v);
+            for (int k = 0; k < d; k++)
+                q[k] = keys[j * d + k] + v[k];
+            int64_t nb = find_cell(keys, m, d, q);
+            if (nb < 0)
+                continue;
+            W += counts[nb];
+            for (int k = 0; k < d; k++)
+                pj[k] = first ? sums[nb * d + k] : pj[k] + sums[nb * d + k];
+            first = 0;
+        }
+        for (int k = 0; k < d; k++)
+            pj[k] = pj[k] / (double)W;
+        if (weights)
+            weights[j] = W;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Step 4: relocation and merge (Section 2.1 (iii)-(iv), Eq. 3-4).         */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Cell j (count C_j, shifted position p_j) lands on key floor(fl(p_j / h)).
+ * Cells sharing a landing key merge: C = sum C_j, S = R(fl(C_j * p_j)) over
+ * the members in ascending j; the new key is the landing key.  Outputs with
+ * capacity m: nkeys [nm][d], ncounts [nm], nsums [nm][d], g [m] (new index
+ * of old cell j), *nm_out.  New cells ascend in key order.
+ */
+int gso_merge(const int64_t* counts, const double* p, int64_t m, int32_t d, double h, int64_t* nkeys,
+              int64_t* ncounts, double* nsums, int64_t* g, int64_t* nm_out)
+{
+    *nm_out = 0;
+    if (m == 0)
+        return GSO_OK;
+    int rc = GSO_OK;
+    int64_t* kap = malloc(sizeof(int64_t) * m * d);
+    int64_t* order = malloc(sizeof(int64_t) * m);
+    double* tmp = malloc(sizeof(double) * m);
+    if (!kap || !order || !tmp) {
+        rc = GSO_ERR_ALLOC;
+        goto done;
+    }
+    for (int64_t j = 0; j < m; j++)
+        for (int k = 0; k < d; k++)
+            if ((rc = key_of(p[j * d + k], h, &kap[j * d + k])) != GSO_OK)
+                goto done;
+    for (int64_t j = 0; j < m; j++)
+        order[j] = j;
+    g_sort_keys = kap;
+    g_sort_d = d;
+    qsort(order, (size_t)m, sizeof(int64_t), cmp_rows_by_key_then_index);
+    int64_t nm = 0;
+    for (int64_t a = 0; a < m;) {
+        int64_t b = a + 1;
+        while (b < m && cmp_keyvec(kap + order[a] * d, kap + order[b] * d, d) == 0)
+            b++;
+        memcpy(nkeys + nm * d, kap + order[a] * d, sizeof(int64_t) * d);
+        int64_t C = 0;
+        for (int64_t r = a; r < b; r++)
+            C += counts[order[r]];
+        ncounts[nm] = C;
+        for (int k = 0; k < d; k++) {
+            for (int64_t r = a; r < b; r++) {
+                int64_t j = order[r];
+                tmp[r - a] = (double)counts[j] * p[j * d + k];
+            }
+            nsums[nm * d + k] = gso_pairwise_sum(tmp, b - a);
+        }
+        for (int64_t r = a; r < b; r++)
+            g[order[r]] = nm;
+        nm++;
+        a = b;
+    }
+    *nm_out = nm;
+done:
+    free(kap);
+    free(order);
+    free(tmp);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* The whole fit.                                                         */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * x        [n][d] row-major binary64 points (f32 data is widened exactly first)
+ * h        cell side, finite and > 0
+ * max_iter maximum number of shift+merge rounds (>= 0)
+ * Outputs (caller-allocated, capacity n for the cluster arrays):
+ *   labels [n]      cluster id of every point (ids ascend with final key)
+ *   modes  [K][d]   fl(S_c / C_c)
+ *   counts [K]      C_c
+ *   sums   [K][d]   S_c (may be NULL)
+ *   keys   [K][d]   final integer cell keys (may be NULL)
+ *   m_hist [max_iter+1] active cells before each round and after the last
+ *                   (may be NULL)
+ *   K, n_iter (rounds executed), flags (GSO_CONVERGED / STATIONARY / CAPPED)
+ * Loop: stop with CONVERGED when no cell has an active neighbour; else stop
+ * with CAPPED when max_iter rounds have run; else shift and merge; stop with
+ * STATIONARY when the round left keys, counts and sums bitwise unchanged.
+ */
+int gso_fit(const double* x, int64_t n, int32_t d, double h, int32_t max_iter,
+            int32_t* labels, double* modes, int64_t* counts, double* sums, int64_t* keys_out,
+            int64_t* m_hist, int64_t* K_out, int32_t* n_iter_out, uint32_t* flags_out)
+{
+    if (n < 0 || d < 1 || d > 16 || max_iter < 0 || !(h > 0.0) || !isfinite(h))
+        return GSO_ERR_INVALID_ARG;
+    *K_out = 0;
+    *n_iter_out = 0;
+    *flags_out = 0;
+    if (n == 0) {
+        *flags_out = GSO_CONVERGED;
+        if (m_hist)
+            m_hist[0] = 0;
+        return GSO_OK;
+    }
+    int rc = GSO_OK;
+    int64_t* cell0 = malloc(sizeof(int64_t) * n);
+    int64_t* ckey = malloc(sizeof(int64_t) * n * d);
+    int64_t* ccnt = malloc(sizeof(int64_t) * n);
+    double* csum = malloc(sizeof(double) * n * d);
+    int64_t *cur = NULL, *g = NULL, *nkey = NULL, *ncnt = NULL;
+    double *p = NULL, *nsum = NULL;
+    if (!cell0 || !ckey || !ccnt || !csum) {
+        rc = GSO_ERR_ALLOC;
+        goto done;
+    }
+    int64_t m = 0;
+    if ((rc = gso_bin(x, n, d, h, ckey, ccnt, csum, cell0, &m)) != GSO_OK)
+        goto done;
+    const int64_t m0 = m;
+    cur = malloc(sizeof(int64_t) * m0);
+    g = malloc(sizeof(int64_t) * m0);
+    nkey = malloc(sizeof(int64_t) * m0 * d);
+    ncnt = malloc(sizeof(int64_t) * m0);
+    p = malloc(sizeof(double) * m0 * d);
+    nsum = malloc(sizeof(double) * m0 * d);
+    if (!cur || !g || !nkey || !ncnt || !p || !nsum) {
+        rc = GSO_ERR_ALLOC;
+        goto done;
+    }
+    for (int64_t c = 0; c < m0; c++)
+        cur[c] = c;
+
+    uint32_t flags = 0;
+    int32_t t = 0;
+    for (;;) {
+        if (m_hist)
+            m_hist[t] = m;
+        if (!gso_has_neighbours(ckey, m, d)) {
+            flags |= GSO_CONVERGED;
+            break;
+        }
+        if (t == max_iter) {
+            flags |= GSO_CAPPED;
+            break;
+        }
+        gso_shift(ckey, ccnt, csum, m, d, p, NULL);
+        int64_t nm = 0;
+        if ((rc = gso_merge(ccnt, p, m, d, h, nkey, ncnt, nsum, g, &nm)) != GSO_OK)
+            goto done;
+        int same = (nm == m);
+        for (int64_t c = 0; same && c < m; c++) {
+            same = (ccnt[c] == ncnt[c]) && cmp_keyvec(ckey + c * d, nkey + c * d, d) == 0;
+            for (int k = 0; same && k < d; k++)
+                same = memcmp(&csum[c * d + k], &nsum[c * d + k], sizeof(double)) == 0;
+        }
+        for (int64_t c = 0; c < m0; c++)
+            cur[c] = g[cur[c]];
+        memcpy(ckey, nkey, sizeof(int64_t) * nm * d);
+        memcpy(ccnt, ncnt, sizeof(int64_t) * nm);
+        memcpy(csum, nsum, sizeof(double) * nm * d);
+        m = nm;
+        t++;
+        if (same) {
+            flags |= GSO_STATIONARY;
+            if (m_hist)
+                m_hist[t] = m;
+            break;
+        }
+    }
+
+    for (int64_t i = 0; i < n; i++)
+        labels[i] = (int32_t)cur[cell0[i]];
+    for (int64_t c = 0; c < m; c++) {
+        counts[c] = ccnt[c];
+        for (int k = 0; k < d; k++) {
+            modes[c * d + k] = csum[c * d + k] / (double)ccnt[c];
+            if (sums)
+                sums[c * d + k] = csum[c * d + k];
+            if (keys_out)
+                keys_out[c * d + k] = ckey[c * d + k];
+        }
+    }
+    *K_out = m;
+    *n_iter_out = t;
+    *flags_out = flags;
+done:
+    free(cell0);
+    free(ckey);
+    free(ccnt);
+    free(csum);
+    free(cur);
+    free(g);
+    free(nkey);
+    free(ncnt);
+    free(p);
+    free(nsum);
+    return rc;
+}

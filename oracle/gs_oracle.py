@@ -1,0 +1,205 @@
+"""Python bindings of the GridShift FP64 CPU oracle.
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the plain, slow reference the GPU
+path is checked against.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module.  It shares no code with
+the GPU library: it compiles ``gs_oracle.c`` with gcc into
+``liboracle_gs.so`` next to this file and calls it through ctypes.
+
+The semantics (GridShift, arXiv 2206.02200, Section 2.1 and Algorithm 1, in
+the parallel update form of Eq. 6) are documented at the top of
+``gs_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gs_oracle.c")
+LIB_PATH = os.path.join(_HERE, "liboracle_gs.so")
+
+CONVERGED = 1
+STATIONARY = 2
+CAPPED = 4
+
+_ERRORS = {
+    1: "invalid argument",
+    2: "non-finite input",
+    3: "cell key out of range",
+    4: "out of memory",
+}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle error {code}: {_ERRORS.get(code, 'unknown')}")
+        self.code = code
+
+
+def build() -> str:
+    """Compile the oracle with gcc (binary64 SSE2 arithmetic, no contraction)."""
+    cmd = [
+        "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+        "-fno-strict-aliasing", "-shared", "-fPIC", "-Wall", "-Wextra",
+        "-o", LIB_PATH + ".tmp", _SRC, "-lm",
+    ]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        build()
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.gso_pairwise_sum.restype = ctypes.c_double
+    lib.gso_pairwise_sum.argtypes = [P, ctypes.c_int64]
+    lib.gso_bin.restype = ctypes.c_int
+    lib.gso_bin.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, P, P, P, P, P]
+    lib.gso_has_neighbours.restype = ctypes.c_int
+    lib.gso_has_neighbours.argtypes = [P, ctypes.c_int64, ctypes.c_int32]
+    lib.gso_shift.restype = None
+    lib.gso_shift.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, P, P]
+    lib.gso_merge.restype = ctypes.c_int
+    lib.gso_merge.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, P, P, P, P, P]
+    lib.gso_fit.restype = ctypes.c_int
+    lib.gso_fit.argtypes = [
+        P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+        P, P, P, P, P, P, P, P, P,
+    ]
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def pairwise_sum(a) -> float:
+    """R(a_0..a_{L-1}): a_0 if L == 1, else R(first P) + R(rest), P the largest
+    power of two below L."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return _load().gso_pairwise_sum(_ptr(a), a.size)
+
+
+@dataclass
+class OracleResult:
+    labels: np.ndarray  # int32 [n]
+    modes: np.ndarray  # float64 [K, d]
+    counts: np.ndarray  # int64 [K]
+    sums: np.ndarray  # float64 [K, d]
+    keys: np.ndarray  # int64 [K, d]
+    m_hist: np.ndarray  # int64 [n_iter + 1]: active cells before each round
+    K: int
+    n_iter: int
+    flags: int
+
+
+def fit(x, h: float, max_iter: int = 100) -> OracleResult:
+    """Run GridShift on points ``x`` ([n, d]; float32 is widened exactly)."""
+    x = np.asarray(x)
+    if x.ndim != 2:
+        raise ValueError("x must be [n, d]")
+    xd = np.ascontiguousarray(x, dtype=np.float64)
+    n, d = xd.shape
+    cap = max(n, 1)
+    labels = np.empty(cap, np.int32)
+    modes = np.empty((cap, d), np.float64)
+    counts = np.empty(cap, np.int64)
+    sums = np.empty((cap, d), np.float64)
+    keys = np.empty((cap, d), np.int64)
+    m_hist = np.zeros(max_iter + 2, np.int64)
+    K = ctypes.c_int64(0)
+    T = ctypes.c_int32(0)
+    flags = ctypes.c_uint32(0)
+    rc = _load().gso_fit(
+        _ptr(xd), n, d, float(h), int(max_iter),
+        _ptr(labels), _ptr(modes), _ptr(counts), _ptr(sums), _ptr(keys), _ptr(m_hist),
+        ctypes.byref(K), ctypes.byref(T), ctypes.byref(flags),
+    )
+    if rc != 0:
+        raise OracleError(rc)
+    k = K.value
+    return OracleResult(
+        labels=labels[:n].copy(), modes=modes[:k].copy(), counts=counts[:k].copy(),
+        sums=sums[:k].copy(), keys=keys[:k].copy(), m_hist=m_hist[: T.value + 1].copy(),
+        K=k, n_iter=T.value, flags=flags.value,
+    )
+
+
+# --------------------------------------------------------------------------
+# the individual steps, exposed so that tests can pin each one
+# --------------------------------------------------------------------------
+@dataclass
+class CellTable:
+    keys: np.ndarray  # int64 [m, d], ascending lexicographic
+    counts: np.ndarray  # int64 [m]
+    sums: np.ndarray  # float64 [m, d]
+
+
+def bin_points(x, h: float) -> tuple[CellTable, np.ndarray]:
+    """Section 2.1 (i): cells of side h, counts, R-sums; returns (table, cell0)."""
+    xd = np.ascontiguousarray(np.asarray(x), dtype=np.float64)
+    n, d = xd.shape
+    cap = max(n, 1)
+    keys = np.empty((cap, d), np.int64)
+    counts = np.empty(cap, np.int64)
+    sums = np.empty((cap, d), np.float64)
+    cell0 = np.empty(cap, np.int64)
+    m = ctypes.c_int64(0)
+    rc = _load().gso_bin(_ptr(xd), n, d, float(h), _ptr(keys), _ptr(counts), _ptr(sums), _ptr(cell0),
+                         ctypes.byref(m))
+    if rc != 0:
+        raise OracleError(rc)
+    k = m.value
+    return CellTable(keys[:k].copy(), counts[:k].copy(), sums[:k].copy()), cell0[:n].copy()
+
+
+def has_neighbours(table: CellTable) -> bool:
+    """Section 2.1 (v): does any active cell have an active neighbour?"""
+    keys = np.ascontiguousarray(table.keys, dtype=np.int64)
+    m, d = keys.shape
+    return bool(_load().gso_has_neighbours(_ptr(keys), m, d))
+
+
+def shift(table: CellTable) -> tuple[np.ndarray, np.ndarray]:
+    """Eq. 1-2 (parallel form, Eq. 6): returns (p [m, d], W [m])."""
+    keys = np.ascontiguousarray(table.keys, dtype=np.int64)
+    counts = np.ascontiguousarray(table.counts, dtype=np.int64)
+    sums = np.ascontiguousarray(table.sums, dtype=np.float64)
+    m, d = keys.shape
+    p = np.empty((max(m, 1), d), np.float64)
+    W = np.empty(max(m, 1), np.int64)
+    _load().gso_shift(_ptr(keys), _ptr(counts), _ptr(sums), m, d, _ptr(p), _ptr(W))
+    return p[:m].copy(), W[:m].copy()
+
+
+def merge(counts, p, h: float) -> tuple[CellTable, np.ndarray]:
+    """Section 2.1 (iii)-(iv), Eq. 3-4: returns (new table, g [m])."""
+    counts = np.ascontiguousarray(counts, dtype=np.int64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    m, d = p.shape
+    cap = max(m, 1)
+    nkeys = np.empty((cap, d), np.int64)
+    ncounts = np.empty(cap, np.int64)
+    nsums = np.empty((cap, d), np.float64)
+    g = np.empty(cap, np.int64)
+    nm = ctypes.c_int64(0)
+    rc = _load().gso_merge(_ptr(counts), _ptr(p), m, d, float(h), _ptr(nkeys), _ptr(ncounts), _ptr(nsums),
+                           _ptr(g), ctypes.byref(nm))
+    if rc != 0:
+        raise OracleError(rc)
+    k = nm.value
+    return CellTable(nkeys[:k].copy(), ncounts[:k].copy(), nsums[:k].copy()), g[:m].copy()

@@ -1,0 +1,102 @@
+"""Exact-rational brute-force GridShift for tiny inputs (test helper).
+
+Written from the paper independently of the FP64 oracle, in exact rational
+arithmetic (fractions.Fraction), so it pins the mathematics apart from
+floating-point rounding:
+
+* keys are floor(x / h) of the exact quotient (Section 2.1 (i));
+* the neighbour relation is the supplement's cell distance
+  M(z, x; h) = max_k |floor(x_k/h) - floor(z_k/h)| <= 1, evaluated over all
+  pairs of active cells (no 3^d offset enumeration);
+* the shift is the exact count-weighted mean of Eq. 1-2, parallel form Eq. 6;
+* merges use the exact weighted mean of Eq. 3-4;
+* stopping follows Section 2.1 (v) / Theorem 2, capped at max_iter, with the
+  same early exit on an unchanged state.
+
+It also records the smallest distance of any floor decision to an integer,
+so that a test can tell when FP64 rounding could legitimately flip a key.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+from math import floor
+
+
+def _cheb_adjacent(a, b):
+    return max(abs(x - y) for x, y in zip(a, b)) <= 1
+
+
+def exact_fit(x, h, max_iter=100):
+    hq = Fraction(h)
+    pts = [[Fraction(float(v)) for v in row] for row in x]
+    n = len(pts)
+    d = len(pts[0]) if n else 0
+    margin = [None]
+
+    def key(vec):
+        out = []
+        for v in vec:
+            q = v / hq
+            f = floor(q)
+            frac = q - f
+            dist = min(frac, 1 - frac)
+            if margin[0] is None or dist < margin[0]:
+                margin[0] = dist
+            out.append(f)
+        return tuple(out)
+
+    # cells: key -> [count, sum vector, member point indices]
+    cells = {}
+    for i, p in enumerate(pts):
+        k = key(p)
+        if k not in cells:
+            cells[k] = [0, [Fraction(0)] * d, []]
+        c = cells[k]
+        c[0] += 1
+        c[1] = [s + v for s, v in zip(c[1], p)]
+        c[2].append(i)
+
+    t = 0
+    flags = 0
+    while True:
+        ks = sorted(cells)
+        any_nb = any(_cheb_adjacent(a, b) for a in ks for b in ks if a != b)
+        if not any_nb:
+            flags |= 1
+            break
+        if t == max_iter:
+            flags |= 4
+            break
+        moved = {}
+        for j in ks:
+            nb = [k for k in ks if _cheb_adjacent(j, k)]
+            W = sum(cells[k][0] for k in nb)
+            N = [sum(cells[k][1][dd] for k in nb) for dd in range(d)]
+            p = [v / W for v in N]
+            kap = key(p)
+            C = cells[j][0]
+            if kap not in moved:
+                moved[kap] = [0, [Fraction(0)] * d, []]
+            m = moved[kap]
+            m[0] += C
+            m[1] = [s + C * v for s, v in zip(m[1], p)]
+            m[2].extend(cells[j][2])
+        same = sorted(moved) == ks and all(
+            moved[k][0] == cells[k][0] and moved[k][1] == cells[k][1] for k in ks)
+        cells = moved
+        t += 1
+        if same:
+            flags |= 2
+            break
+
+    ks = sorted(cells)
+    labels = [0] * n
+    for cid, k in enumerate(ks):
+        for i in cells[k][2]:
+            labels[i] = cid
+    modes = [[s / cells[k][0] for s in cells[k][1]] for k in ks]
+    counts = [cells[k][0] for k in ks]
+    return {
+        "labels": labels, "modes": modes, "counts": counts, "keys": [list(k) for k in ks],
+        "n_iter": t, "flags": flags, "margin": margin[0],
+    }

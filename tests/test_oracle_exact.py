@@ -1,0 +1,55 @@
+"""Oracle vs an exact-rational brute force on tiny inputs.
+
+The brute force (tests/exact_reference.py) follows Section 2.1, Eq. 1-4 and
+Eq. 6 in exact arithmetic, with the neighbourhood found over all pairs by the
+supplement's cell distance M <= 1.  On inputs whose floor decisions all stay
+clear of integers (margin > 1e-9, so FP64 rounding cannot flip a key), keys,
+labels, counts, round count and flags must agree exactly and the modes to
+within a few rounding errors per round.
+"""
+import numpy as np
+import pytest
+
+from exact_reference import exact_fit
+from paper_2206_02200_amd import synth
+
+
+def _case(seed):
+    rng = np.random.default_rng(seed)
+    d = int(rng.integers(1, 4))
+    n = int(rng.integers(5, 60))
+    k = int(rng.integers(1, 5))
+    c = rng.uniform(0, 12, size=(k, d))
+    x = c[rng.integers(0, k, size=n)] + 1.2 * rng.standard_normal(size=(n, d))
+    h = float(rng.choice([0.5, 1.0, 2.0]))
+    return synth.dyadic(x, bits=10), h
+
+
+@pytest.mark.parametrize("seed", list(range(300, 340)))
+def test_against_exact_rationals(oracle, seed):
+    x, h = _case(seed)
+    ex = exact_fit(x, h, max_iter=50)
+    if ex["margin"] is not None and ex["margin"] < 1e-9:
+        pytest.skip("a floor decision sits within rounding of a cell boundary")
+    r = oracle.fit(x, h, max_iter=50)
+    assert r.n_iter == ex["n_iter"]
+    assert r.flags == ex["flags"]
+    assert r.keys.tolist() == ex["keys"]
+    assert r.counts.tolist() == ex["counts"]
+    assert r.labels.tolist() == ex["labels"]
+    want = np.array([[float(v) for v in row] for row in ex["modes"]])
+    tol = 1e-15 * (4 * r.n_iter + 4)
+    np.testing.assert_allclose(r.modes, want, rtol=tol, atol=tol * np.abs(want).max())
+
+
+def test_worked_examples_agree_with_exact(oracle):
+    import json
+    import os
+
+    ex_all = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))
+    for e in ex_all["examples"]:
+        if "labels" not in e:
+            continue
+        ex = exact_fit(np.array(e["x"]), e["h"])
+        assert ex["labels"] == e["labels"] and ex["counts"] == e["counts"]
+        assert ex["n_iter"] == e["n_iter"]
