@@ -1,0 +1,145 @@
+/*
+ * gridshift.h - C ABI of the MI355X (gfx950) GridShift library.
+ *
+ * GridShift (Kumar et al., arXiv 2206.02200) clusters points by grid-based
+ * mode seeking.  Section 2.1 (i) and Algorithm 1 bin the points into cells of
+ * side h; every active cell keeps a point count and a coordinate sum.  Each
+ * round (Section 2.1 (ii)-(iv), Eq. 1-4, in the parallel form of Eq. 6) moves
+ * every active cell to the count-weighted mean of the active cells among its
+ * 3^d neighbours, re-bins the moved cells and merges the cells that land on
+ * the same key.  The rounds stop when no active cell has an active neighbour
+ * (Section 2.1 (v), Theorem 2), after max_iter rounds, or when a round leaves
+ * the state bitwise unchanged.  Labels are then propagated back to the points.
+ *
+ * Arithmetic: every sum, division and floor runs in IEEE binary64 without
+ * contraction, in a fixed order, so results do not depend on launch shapes:
+ *   key(v)       = floor(fl(v / h)) per coordinate (Section 2.1 (i), (iii));
+ *   cell sum     = R over the cell's points in ascending point index, where
+ *                  R(a_0..a_{L-1}) = a_0 if L = 1, else R(first P) + R(rest),
+ *                  P the largest power of two below L;
+ *   3^d sum      = left fold over the active neighbours in ascending key
+ *                  (lexicographic, dimension 0 most significant), integer
+ *                  weight sum (Eq. 1-2);
+ *   merge sum    = R over fl(C_j * p_j) for the merging cells in ascending old
+ *                  key (Eq. 3); the merged cell keeps the landing key;
+ *   mode         = fl(S / C).
+ * Clusters are numbered per instance in ascending lexicographic key.
+ *
+ * Conventions:
+ *   - "device" pointers are HIP device memory on the context's device;
+ *     "host" pointers are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work of a call is ordered on it.  gs_fit / gs_fit_batched
+ *     synchronise the stream before returning, because cluster counts and
+ *     flags are returned in host memory.
+ *   - The caller owns every array it passes.  The context owns its scratch
+ *     device memory, which grows on demand (hipMalloc) and is reused by later
+ *     calls; results of a fit stay in the context until its next fit.
+ *   - Errors are returned as gs_status codes; gs_last_error() gives text.  The
+ *     library never aborts the process.  On error the context holds no result.
+ *   - A context is used by one host thread at a time; different contexts may
+ *     be used concurrently on different streams.
+ *   - Limits: 1 <= d <= 6, 0 <= n < 2^31 points in total, h finite and > 0,
+ *     |floor(x/h)| < 2^52, and the per-instance key boxes
+ *     prod_k (max_k - min_k + 3) must sum to less than 2^62 (else
+ *     GS_ERR_KEY_RANGE).
+ */
+#ifndef GRIDSHIFT_H
+#define GRIDSHIFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_ABI_VERSION 1
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID_ARG = 1, /* bad sizes, pointers, h, d, max_iter */
+    GS_ERR_NONFINITE = 2,   /* a NaN or infinite coordinate */
+    GS_ERR_KEY_RANGE = 3,   /* cell keys do not fit the packed 62-bit key space */
+    GS_ERR_ALLOC = 4,       /* device allocation failed */
+    GS_ERR_DEVICE = 5,      /* a HIP runtime error */
+    GS_ERR_UNSUPPORTED = 6, /* d outside 1..6 */
+    GS_ERR_STATE = 7        /* no fit result in the context */
+} gs_status;
+
+typedef enum { GS_F32 = 0, GS_F64 = 1 } gs_dtype;
+
+/* gs_info.flags bits */
+#define GS_CONVERGED 1u  /* no active cell had an active neighbour */
+#define GS_STATIONARY 2u /* the last round left keys, counts and sums unchanged */
+#define GS_CAPPED 4u     /* stopped after max_iter rounds with neighbours left */
+
+typedef struct {
+    int64_t n_points;   /* points of the instance */
+    int64_t n_cells0;   /* active cells after binning (m_0) */
+    int64_t n_clusters; /* K: active cells at exit */
+    int32_t n_iter;     /* shift+merge rounds executed */
+    uint32_t flags;     /* GS_CONVERGED | GS_STATIONARY | GS_CAPPED */
+} gs_info;
+
+typedef struct gs_context gs_context;
+
+/* ABI version (GS_ABI_VERSION). */
+int32_t gs_abi_version(void);
+
+/* Text of the last error on the calling thread (valid until its next call). */
+const char* gs_last_error(void);
+
+/* Create a context bound to the current HIP device.  *out receives it. */
+gs_status gs_context_create(gs_context** out);
+
+/* Destroy a context and free its device memory (NULL is a no-op).  The caller
+ * must make sure no work of the context is still running. */
+void gs_context_destroy(gs_context* ctx);
+
+/*
+ * Plain fit of one point set (Section 2.1, Algorithm 1).
+ *   points  device, n rows of `ld` elements of `dtype`; row i holds x_i in its
+ *           first d elements (ld >= d).  float32 is widened exactly.
+ *   h       cell side (bandwidth), finite and > 0.
+ *   max_iter maximum number of rounds (>= 0; 0 = binning only).
+ *   labels  device int32 [n]: cluster id of every point (0..K-1).
+ *   info    host, receives the result summary.
+ * The cluster table stays in the context (gs_copy_modes, gs_copy_keys).
+ */
+gs_status gs_fit(gs_context* ctx, const void* points, gs_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                 double h, int32_t max_iter, int32_t* labels, gs_info* info, void* stream);
+
+/*
+ * Batched fit: B independent instances, concatenated, each with its own h,
+ * in one pass of the pipeline (keys carry the instance as top digit; the
+ * per-round tail runs one workgroup per instance in a single launch).
+ * Results are bitwise those of B separate gs_fit calls.
+ *   points  device [offsets[B]][ld] of dtype; instance b owns rows
+ *           offsets[b] .. offsets[b+1]-1.
+ *   offsets host int64 [B+1], offsets[0] = 0, non-decreasing.
+ *   h       host double [B].
+ *   labels  device int32 [offsets[B]]: per-instance cluster ids.
+ *   info    host gs_info [B].
+ */
+gs_status gs_fit_batched(gs_context* ctx, const void* points, gs_dtype dtype, int32_t d, int64_t ld, int32_t B,
+                         const int64_t* offsets, const double* h, int32_t max_iter, int32_t* labels,
+                         gs_info* info, void* stream);
+
+/*
+ * Copy the cluster table of the last fit, instances concatenated in order
+ * (instance b's K_b clusters start at row sum_{b'<b} K_b').
+ *   modes   device double [sum K][d]: fl(S / C)           (may be NULL)
+ *   counts  device int64 [sum K]: C                       (may be NULL)
+ *   sums    device double [sum K][d]: S                   (may be NULL)
+ */
+gs_status gs_copy_modes(gs_context* ctx, double* modes, int64_t* counts, double* sums, void* stream);
+
+/* Integer cell keys floor(.) of the last fit's clusters: device int64 [sum K][d]. */
+gs_status gs_copy_keys(gs_context* ctx, int64_t* keys, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRIDSHIFT_H */

@@ -1,0 +1,618 @@
+// Host side of the GridShift library: context, buffers, the fit pipelines and
+// the C ABI declared in include/gridshift.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gridshift.h"
+#include "gs_kernels.inl"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gs_status fail(gs_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+#define GS_HIP(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(GS_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+struct DBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace
+
+struct gs_context {
+    int device = 0;
+    // point level
+    DBuf kA, kB, vA, vB, cell0;
+    // cell tables (ping-pong) and per-round scratch
+    DBuf tkey[2], tcnt[2], tsum[2], tinst[2], tstart[2], tlen[2], tfirst[2], tnch[2], tchoff[2];
+    DBuf kappa, pbuf, gmap, cur, tmap, part, partc, hk, hv, ckA, ckB, cvA, cvB;
+    // instances
+    DBuf param, state, rowoff, hs, bbox, koff;
+    // scans and sorts
+    DBuf counters, look, tilectr, shist, sdbase, sctr, slook;
+    gs::SortScratch sort;
+    uint32_t scan_epoch = 0;
+    void* pinned = nullptr;
+    size_t pinned_cap = 0;
+    // result of the last fit
+    bool has_result = false;
+    int B = 0, d = 0, cur_tab = 0;
+    int64_t capM = 0;
+    std::vector<gs::InstState> st;
+    std::vector<gs::InstParam> prm;
+};
+
+namespace {
+
+gs_status ensure(DBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    if (b.cap >= bytes) return GS_OK;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    const size_t want = bytes + bytes / 8;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ERR_ALLOC, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    b.cap = want;
+    return GS_OK;
+}
+
+#define GS_TRY(expr)                  \
+    do {                              \
+        gs_status s_ = (expr);        \
+        if (s_ != GS_OK) return s_;   \
+    } while (0)
+
+template <typename T>
+T* P(DBuf& b) {
+    return static_cast<T*>(b.p);
+}
+
+// Grid size for n items (at least one block, so that empty launches are valid).
+inline unsigned blocks_for(int64_t n, int threads) {
+    return n <= 0 ? 1u : unsigned((n + threads - 1) / threads);
+}
+
+gs_status pinned_ensure(gs_context* c, size_t bytes) {
+    if (c->pinned_cap >= bytes) return GS_OK;
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    c->pinned_cap = 0;
+    if (hipHostMalloc(&c->pinned, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ERR_ALLOC, "hipHostMalloc failed");
+    }
+    c->pinned_cap = bytes;
+    return GS_OK;
+}
+
+// Copy device -> host through pinned memory and wait for the stream.
+gs_status d2h(gs_context* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
+    GS_TRY(pinned_ensure(c, bytes));
+    GS_HIP(hipMemcpyAsync(c->pinned, src, bytes, hipMemcpyDeviceToHost, s));
+    GS_HIP(hipStreamSynchronize(s));
+    std::memcpy(dst, c->pinned, bytes);
+    return GS_OK;
+}
+
+gs_status h2d(gs_context* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
+    GS_TRY(pinned_ensure(c, bytes));
+    // the previous use of the staging buffer has completed (every d2h waits)
+    GS_HIP(hipStreamSynchronize(s));
+    std::memcpy(c->pinned, src, bytes);
+    GS_HIP(hipMemcpyAsync(dst, c->pinned, bytes, hipMemcpyHostToDevice, s));
+    GS_HIP(hipStreamSynchronize(s));
+    return GS_OK;
+}
+
+__global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_set_i64(int64_t* __restrict__ p, int64_t v) { *p = v; }
+__global__ void k_iota32(uint32_t* __restrict__ p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = uint32_t(i);
+}
+
+// Look-back storage of the tile scans: tiles status words, cleared on growth.
+gs_status scan_prepare(gs_context* c, int64_t n_bound, hipStream_t s, uint32_t* epoch_out) {
+    const int64_t tiles = std::max<int64_t>(1, (n_bound + gs::kScanTile - 1) / gs::kScanTile);
+    if (c->look.cap < size_t(tiles) * 8) {
+        GS_TRY(ensure(c->look, size_t(tiles) * 8));
+        k_fill_u64<<<blocks_for(c->look.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->look), c->look.cap / 8, 0);
+        c->scan_epoch = 0;
+    }
+    GS_TRY(ensure(c->tilectr, 64));
+    if (c->scan_epoch >= 0xffffu) {
+        k_fill_u64<<<blocks_for(c->look.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->look), c->look.cap / 8, 0);
+        c->scan_epoch = 0;
+    }
+    *epoch_out = ++c->scan_epoch;
+    k_fill_u32<<<1, 64, 0, s>>>(P<uint32_t>(c->tilectr), 16, 0);
+    return GS_OK;
+}
+
+template <class Op>
+gs_status run_scan(gs_context* c, Op op, const int64_t* n_dev, int64_t n_bound, int64_t* total_dev, hipStream_t s) {
+    uint32_t epoch = 0;
+    GS_TRY(scan_prepare(c, n_bound, s, &epoch));
+    const int64_t tiles = std::max<int64_t>(1, (n_bound + gs::kScanTile - 1) / gs::kScanTile);
+    gs::k_scan<Op><<<unsigned(tiles), gs::kScanThreads, 0, s>>>(op, n_dev, P<uint64_t>(c->look),
+                                                                P<uint32_t>(c->tilectr), epoch, total_dev);
+    GS_HIP(hipGetLastError());
+    return GS_OK;
+}
+
+gs::CellTable table(gs_context* c, int i) {
+    gs::CellTable t;
+    t.key = P<uint64_t>(c->tkey[i]);
+    t.cnt = P<int64_t>(c->tcnt[i]);
+    t.sum = P<double>(c->tsum[i]);
+    t.inst = P<int32_t>(c->tinst[i]);
+    t.start = P<uint32_t>(c->tstart[i]);
+    t.len = P<uint32_t>(c->tlen[i]);
+    t.first = P<uint32_t>(c->tfirst[i]);
+    t.nch = P<uint32_t>(c->tnch[i]);
+    t.choff = P<uint32_t>(c->tchoff[i]);
+    t.cap = c->capM;
+    return t;
+}
+
+// Canonical sums R of every cell's members (cells [0, m) of t, m on device).
+template <int D, class Src>
+gs_status segsum_d(gs_context* c, Src src, gs::CellTable t, int64_t m_bound, int64_t npos, hipStream_t s) {
+    int64_t* ctr = P<int64_t>(c->counters);
+    GS_TRY(run_scan(c, gs::ExclOp{t.nch, t.choff}, ctr + 0, m_bound, ctr + 1, s));
+    const int64_t tasks_bound = npos / gs::kChunk + m_bound + 1;
+    GS_TRY(ensure(c->part, size_t(tasks_bound) * D * sizeof(double)));
+    GS_TRY(ensure(c->partc, size_t(tasks_bound) * sizeof(int64_t)));
+    gs::k_segsum_chunks<D, Src><<<blocks_for(tasks_bound * gs::kWave, gs::kSegThreads), gs::kSegThreads, 0, s>>>(
+        src, t, ctr + 0, ctr + 1, P<double>(c->part), P<int64_t>(c->partc), tasks_bound);
+    gs::k_segsum_levels<D><<<blocks_for(m_bound * gs::kWave, gs::kSegThreads), gs::kSegThreads, 0, s>>>(
+        t, ctr + 0, P<double>(c->part), P<int64_t>(c->partc), tasks_bound);
+    GS_HIP(hipGetLastError());
+    return GS_OK;
+}
+
+template <class Src>
+gs_status segsum(gs_context* c, int d, Src src, gs::CellTable t, int64_t m_bound, int64_t npos, hipStream_t s) {
+    switch (d) {
+        case 1: return segsum_d<1>(c, src, t, m_bound, npos, s);
+        case 2: return segsum_d<2>(c, src, t, m_bound, npos, s);
+        case 3: return segsum_d<3>(c, src, t, m_bound, npos, s);
+        case 4: return segsum_d<4>(c, src, t, m_bound, npos, s);
+        case 5: return segsum_d<5>(c, src, t, m_bound, npos, s);
+        case 6: return segsum_d<6>(c, src, t, m_bound, npos, s);
+    }
+    return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+}
+
+gs_status launch_shift(int d, gs::CellTable t, int64_t m, const gs::InstParam* prm, gs::InstState* st,
+                       const uint64_t* hk, const uint32_t* hv, int logcap, double* pbuf, uint64_t* kappa,
+                       hipStream_t s) {
+    const unsigned g = blocks_for(m, 256);
+    switch (d) {
+        case 1: gs::k_shift<1><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
+        case 2: gs::k_shift<2><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
+        case 3: gs::k_shift<3><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
+        case 4: gs::k_shift<4><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
+        case 5: gs::k_shift<5><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
+        case 6: gs::k_shift<6><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
+        default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+    }
+    GS_HIP(hipGetLastError());
+    return GS_OK;
+}
+
+gs_status launch_tail(int d, int B, gs::CellTable t, const gs::InstParam* prm, gs::InstState* st, uint32_t* tmap,
+                      int max_iter, hipStream_t s) {
+    switch (d) {
+        case 1: gs::k_tail<1><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
+        case 2: gs::k_tail<2><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
+        case 3: gs::k_tail<3><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
+        case 4: gs::k_tail<4><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
+        case 5: gs::k_tail<5><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
+        case 6: gs::k_tail<6><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
+        default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+    }
+    GS_HIP(hipGetLastError());
+    return GS_OK;
+}
+
+// Host computation of the per-instance key packing from the device boxes.
+gs_status build_params(gs_context* c, int B, int d, const int64_t* offsets, const double* h,
+                       const std::vector<int64_t>& box, int* bits_out) {
+    c->prm.assign(B, gs::InstParam{});
+    const uint64_t kLimit = 1ull << 62;
+    uint64_t total = 0;
+    for (int b = 0; b < B; ++b) {
+        gs::InstParam& p = c->prm[b];
+        p.h = h[b];
+        p.row0 = offsets[b];
+        p.row1 = offsets[b + 1];
+        p.base = total;
+        for (int k = 0; k < gs::kMaxDim; ++k) {
+            p.lo[k] = 0;
+            p.E[k] = 1;
+            p.stride[k] = 1;
+        }
+        if (p.row1 == p.row0) {
+            p.span = 0;
+            continue;
+        }
+        long double span = 1.0L;
+        for (int k = 0; k < d; ++k) {
+            const int64_t mn = box[(int64_t(b) * gs::kMaxDim + k) * 2 + 0];
+            const int64_t mx = box[(int64_t(b) * gs::kMaxDim + k) * 2 + 1];
+            p.lo[k] = mn - 1;
+            p.E[k] = mx - mn + 3;
+            span *= (long double)p.E[k];
+        }
+        if (span >= (long double)kLimit)
+            return fail(GS_ERR_KEY_RANGE, "the key box of instance " + std::to_string(b) + " exceeds 2^62 cells");
+        p.stride[d - 1] = 1;
+        for (int k = d - 2; k >= 0; --k) p.stride[k] = p.stride[k + 1] * uint64_t(p.E[k + 1]);
+        p.span = p.stride[0] * uint64_t(p.E[0]);
+        total += p.span;
+        if (total >= kLimit) return fail(GS_ERR_KEY_RANGE, "the instances' key boxes exceed 2^62 cells in total");
+    }
+    *bits_out = total <= 1 ? 0 : 64 - __builtin_clzll(total - 1);
+    return GS_OK;
+}
+
+template <typename T, typename K>
+gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const int64_t* offsets, int max_iter,
+                    int bits, int32_t* labels, hipStream_t s) {
+    const int64_t N = offsets[B];
+    int64_t* ctr = P<int64_t>(c->counters);
+    gs::InstParam* prm = P<gs::InstParam>(c->param);
+    gs::InstState* st = P<gs::InstState>(c->state);
+    const int64_t* row_off = P<int64_t>(c->rowoff);
+
+    // ---- keys and the stable sort of (key, point)
+    GS_TRY(ensure(c->kA, size_t(N) * sizeof(K)));
+    GS_TRY(ensure(c->kB, size_t(N) * sizeof(K)));
+    GS_TRY(ensure(c->vA, size_t(N) * 4));
+    GS_TRY(ensure(c->vB, size_t(N) * 4));
+    GS_TRY(ensure(c->cell0, size_t(N) * 4));
+    GS_TRY(ensure(c->shist, gs::kSortMaxPasses * 256 * 4));
+    GS_TRY(ensure(c->sdbase, gs::kSortMaxPasses * 256 * 4));
+    GS_TRY(ensure(c->sctr, 64));
+    const int64_t sort_tiles = gs::sort_look_tiles(N);
+    if (c->slook.cap < size_t(sort_tiles) * 256 * 8) {
+        GS_TRY(ensure(c->slook, size_t(sort_tiles) * 256 * 8));
+        k_fill_u64<<<blocks_for(c->slook.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->slook), c->slook.cap / 8, 0);
+        c->sort.epoch = 0;
+    }
+    c->sort.hist = P<uint32_t>(c->shist);
+    c->sort.dbase = P<uint32_t>(c->sdbase);
+    c->sort.ctr = P<uint32_t>(c->sctr);
+    c->sort.look = P<uint64_t>(c->slook);
+    c->sort.look_tiles = int64_t(c->slook.cap / (256 * 8));
+
+    const int np = gs::sort_passes(bits);
+    k_fill_u32<<<blocks_for(gs::kSortMaxPasses * 256, 256), 256, 0, s>>>(c->sort.hist, gs::kSortMaxPasses * 256, 0);
+    {
+        int64_t blocks = (N + 256 * 8 - 1) / (256 * 8);
+        blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, 4096));
+        gs::k_make_keys<T, K><<<unsigned(blocks), gs::kKeyThreads, 0, s>>>(x, ld, d, row_off, B, N, prm,
+                                                                           P<K>(c->kA), np, c->sort.hist);
+        GS_HIP(hipGetLastError());
+    }
+    K* skeys = nullptr;
+    uint32_t* perm = nullptr;
+    GS_HIP(gs::radix_sort<K>(P<K>(c->kA), P<K>(c->kB), P<uint32_t>(c->vA), P<uint32_t>(c->vB), N, bits, true,
+                             c->sort, s, &skeys, &perm));
+
+    // ---- run heads -> cell ids (table 0 key/start/first have capacity N)
+    GS_TRY(ensure(c->tkey[0], size_t(N) * 8));
+    GS_TRY(ensure(c->tstart[0], size_t(N) * 4));
+    GS_TRY(ensure(c->tfirst[0], size_t(N) * 4));
+    {
+        k_set_i64<<<1, 1, 0, s>>>(ctr + 3, N);
+        gs::HeadsOp<K> op{skeys, perm, P<uint64_t>(c->tkey[0]), P<uint32_t>(c->tstart[0]), P<uint32_t>(c->tfirst[0]),
+                          P<uint32_t>(c->cell0)};
+        GS_TRY(run_scan(c, op, ctr + 3, N, ctr + 0, s));
+    }
+    int64_t m0 = 0;
+    GS_TRY(d2h(c, &m0, ctr + 0, sizeof(int64_t), s));
+
+    // ---- cell tables with capacity m0
+    c->capM = std::max<int64_t>(m0, 1);
+    for (int i = 0; i < 2; ++i) {
+        if (i == 1) {
+            GS_TRY(ensure(c->tkey[1], size_t(c->capM) * 8));
+            GS_TRY(ensure(c->tstart[1], size_t(c->capM) * 4));
+            GS_TRY(ensure(c->tfirst[1], size_t(c->capM) * 4));
+        }
+        GS_TRY(ensure(c->tcnt[i], size_t(c->capM) * 8));
+        GS_TRY(ensure(c->tsum[i], size_t(c->capM) * d * 8));
+        GS_TRY(ensure(c->tinst[i], size_t(c->capM) * 4));
+        GS_TRY(ensure(c->tlen[i], size_t(c->capM) * 4));
+        GS_TRY(ensure(c->tnch[i], size_t(c->capM) * 4));
+        GS_TRY(ensure(c->tchoff[i], size_t(c->capM) * 4));
+    }
+    gs::CellTable T0 = table(c, 0);
+    gs::k_cell_setup<<<blocks_for(c->capM, 256), 256, 0, s>>>(ctr + 0, N, T0, 0, row_off, B, nullptr, st);
+    GS_HIP(hipGetLastError());
+    GS_TRY(segsum(c, d, gs::SrcPoints<T>{x, ld, perm}, T0, m0, N, s));
+    gs::k_clear_ranges<<<blocks_for(B, 256), 256, 0, s>>>(st, B);
+    gs::k_inst_ranges<<<blocks_for(c->capM, 256), 256, 0, s>>>(T0.inst, ctr + 0, st);
+    GS_HIP(hipGetLastError());
+
+    c->st.assign(B, gs::InstState{});
+    GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
+    std::vector<int64_t> m0_of(B);
+    for (int b = 0; b < B; ++b) m0_of[b] = c->st[b].ce - c->st[b].cs;
+
+    // ---- wide rounds while some active instance has more cells than a tail holds
+    GS_TRY(ensure(c->tmap, size_t(c->capM) * 4));
+    int cur = 0;
+    int64_t M = m0;
+    int wide = 0;
+    for (;;) {
+        bool need = false;
+        for (int b = 0; b < B; ++b)
+            if (c->st[b].active && c->st[b].ce - c->st[b].cs > gs::kTailCells) need = true;
+        if (!need) break;
+        if (wide == 0) {
+            GS_TRY(ensure(c->cur, size_t(c->capM) * 4));
+            k_iota32<<<blocks_for(m0, 256), 256, 0, s>>>(P<uint32_t>(c->cur), m0);
+            GS_TRY(ensure(c->kappa, size_t(c->capM) * 8));
+            GS_TRY(ensure(c->pbuf, size_t(c->capM) * d * 8));
+            GS_TRY(ensure(c->gmap, size_t(c->capM) * 4));
+            GS_TRY(ensure(c->ckA, size_t(c->capM) * sizeof(K)));
+            GS_TRY(ensure(c->ckB, size_t(c->capM) * sizeof(K)));
+            GS_TRY(ensure(c->cvA, size_t(c->capM) * 4));
+            GS_TRY(ensure(c->cvB, size_t(c->capM) * 4));
+        }
+        ++wide;
+        gs::CellTable TT = table(c, cur), U = table(c, 1 - cur);
+        int logcap = 1;
+        while ((int64_t(1) << logcap) < 2 * M) ++logcap;
+        const int64_t hcap = int64_t(1) << logcap;
+        GS_TRY(ensure(c->hk, size_t(hcap) * 8));
+        GS_TRY(ensure(c->hv, size_t(hcap) * 4));
+        gs::k_hash_clear<<<blocks_for(hcap, 256), 256, 0, s>>>(P<uint64_t>(c->hk), hcap);
+        gs::k_hash_insert<<<blocks_for(M, 256), 256, 0, s>>>(TT.key, M, P<uint64_t>(c->hk), P<uint32_t>(c->hv),
+                                                              logcap);
+        GS_HIP(hipGetLastError());
+        GS_TRY(launch_shift(d, TT, M, prm, st, P<uint64_t>(c->hk), P<uint32_t>(c->hv), logcap, P<double>(c->pbuf),
+                            P<uint64_t>(c->kappa), s));
+        gs::k_decide<<<blocks_for(B, 256), 256, 0, s>>>(st, B, max_iter);
+        gs::k_merge_prep<K><<<blocks_for(M, 256), 256, 0, s>>>(TT, M, st, st, P<double>(c->pbuf),
+                                                                P<uint64_t>(c->kappa), P<K>(c->ckA), d);
+        GS_HIP(hipGetLastError());
+        K* mk = nullptr;
+        uint32_t* mperm = nullptr;
+        GS_HIP(gs::radix_sort<K>(P<K>(c->ckA), P<K>(c->ckB), P<uint32_t>(c->cvA), P<uint32_t>(c->cvB), M, bits,
+                                 false, c->sort, s, &mk, &mperm));
+        k_set_i64<<<1, 1, 0, s>>>(ctr + 3, M);
+        gs::HeadsOp<K> op{mk, mperm, U.key, U.start, U.first, P<uint32_t>(c->gmap)};
+        GS_TRY(run_scan(c, op, ctr + 3, M, ctr + 0, s));
+        gs::k_cell_setup<<<blocks_for(M, 256), 256, 0, s>>>(ctr + 0, M, U, 1, row_off, B, TT.inst, st);
+        GS_HIP(hipGetLastError());
+        gs::SrcMerge src{P<double>(c->pbuf), TT.sum, TT.cnt, TT.inst, st, mperm, c->capM};
+        GS_TRY(segsum(c, d, src, U, M, M, s));
+        gs::k_compose<<<blocks_for(m0, 256), 256, 0, s>>>(P<uint32_t>(c->cur), m0, P<uint32_t>(c->gmap));
+        gs::k_round_end<<<blocks_for(B, 256), 256, 0, s>>>(st, B);
+        gs::k_clear_ranges<<<blocks_for(B, 256), 256, 0, s>>>(st, B);
+        gs::k_inst_ranges<<<blocks_for(M, 256), 256, 0, s>>>(U.inst, ctr + 0, st);
+        GS_HIP(hipGetLastError());
+        cur = 1 - cur;
+        GS_TRY(d2h(c, &M, ctr + 0, sizeof(int64_t), s));
+        GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
+        for (int b = 0; b < B; ++b)
+            if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");
+    }
+
+    // ---- remaining rounds: one LDS-resident workgroup per instance
+    gs::CellTable TC = table(c, cur);
+    GS_TRY(launch_tail(d, B, TC, prm, st, P<uint32_t>(c->tmap), max_iter, s));
+    if (N > 0) {
+        gs::k_labels<<<blocks_for(N, 256), 256, 0, s>>>(P<uint32_t>(c->cell0), wide ? P<uint32_t>(c->cur) : nullptr,
+                                                        P<uint32_t>(c->tmap), labels, N);
+        GS_HIP(hipGetLastError());
+    }
+    GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
+    for (int b = 0; b < B; ++b) {
+        if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");
+        c->st[b].m0 = m0_of[b];
+    }
+    c->cur_tab = cur;
+    return GS_OK;
+}
+
+gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int64_t ld, int B,
+                   const int64_t* offsets, const double* h, int max_iter, int32_t* labels, gs_info* info,
+                   hipStream_t s) {
+    if (!c) return fail(GS_ERR_INVALID_ARG, "null context");
+    c->has_result = false;
+    if (d < 1 || d > gs::kMaxDim) return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+    if (B < 1 || !offsets || !h || !info) return fail(GS_ERR_INVALID_ARG, "B >= 1, offsets, h and info are required");
+    if (dtype != GS_F32 && dtype != GS_F64) return fail(GS_ERR_INVALID_ARG, "dtype must be GS_F32 or GS_F64");
+    if (ld < d) return fail(GS_ERR_INVALID_ARG, "ld must be >= d");
+    if (max_iter < 0) return fail(GS_ERR_INVALID_ARG, "max_iter must be >= 0");
+    if (offsets[0] != 0) return fail(GS_ERR_INVALID_ARG, "offsets[0] must be 0");
+    for (int b = 0; b < B; ++b) {
+        if (offsets[b + 1] < offsets[b]) return fail(GS_ERR_INVALID_ARG, "offsets must be non-decreasing");
+        if (!(h[b] > 0.0) || !std::isfinite(h[b])) return fail(GS_ERR_INVALID_ARG, "h must be finite and > 0");
+    }
+    const int64_t N = offsets[B];
+    if (N >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "at most 2^31 - 1 points");
+    if (N > 0 && (!points || !labels)) return fail(GS_ERR_INVALID_ARG, "points and labels are required");
+    GS_HIP(hipSetDevice(c->device));
+
+    GS_TRY(ensure(c->param, sizeof(gs::InstParam) * B));
+    GS_TRY(ensure(c->state, sizeof(gs::InstState) * B));
+    GS_TRY(ensure(c->rowoff, sizeof(int64_t) * (B + 1)));
+    GS_TRY(ensure(c->hs, sizeof(double) * B));
+    GS_TRY(ensure(c->bbox, sizeof(int64_t) * B * gs::kMaxDim * 2));
+    GS_TRY(ensure(c->counters, 8 * sizeof(int64_t)));
+    GS_TRY(h2d(c, c->rowoff.p, offsets, sizeof(int64_t) * (B + 1), s));
+    GS_TRY(h2d(c, c->hs.p, h, sizeof(double) * B, s));
+    gs::k_init_state<<<blocks_for(std::max(B, 8), 256), 256, 0, s>>>(P<gs::InstState>(c->state), B,
+                                                                      P<int64_t>(c->bbox), d,
+                                                                      P<int64_t>(c->counters));
+    GS_HIP(hipGetLastError());
+
+    std::vector<int64_t> box(size_t(B) * gs::kMaxDim * 2, 0);
+    if (N > 0) {
+        const unsigned g = blocks_for(N, gs::kBoxRows);
+        if (dtype == GS_F32)
+            gs::k_bbox<float><<<g, gs::kBoxThreads, 0, s>>>(static_cast<const float*>(points), ld, d,
+                                                            P<int64_t>(c->rowoff), B, N, P<double>(c->hs),
+                                                            P<int64_t>(c->bbox), P<int64_t>(c->counters));
+        else
+            gs::k_bbox<double><<<g, gs::kBoxThreads, 0, s>>>(static_cast<const double*>(points), ld, d,
+                                                             P<int64_t>(c->rowoff), B, N, P<double>(c->hs),
+                                                             P<int64_t>(c->bbox), P<int64_t>(c->counters));
+        GS_HIP(hipGetLastError());
+        GS_TRY(d2h(c, box.data(), c->bbox.p, box.size() * sizeof(int64_t), s));
+        int64_t errbits = 0;
+        GS_TRY(d2h(c, &errbits, P<int64_t>(c->counters) + 2, sizeof(int64_t), s));
+        if (errbits & 1) return fail(GS_ERR_NONFINITE, "a coordinate is NaN or infinite");
+        if (errbits & 2) return fail(GS_ERR_KEY_RANGE, "|floor(x/h)| >= 2^52");
+    }
+    int bits = 0;
+    GS_TRY(build_params(c, B, d, offsets, h, box, &bits));
+    GS_TRY(h2d(c, c->param.p, c->prm.data(), sizeof(gs::InstParam) * B, s));
+
+    gs_status rc;
+    if (bits <= 32) {
+        rc = dtype == GS_F32 ? fit_typed<float, uint32_t>(c, static_cast<const float*>(points), d, ld, B, offsets,
+                                                          max_iter, bits, labels, s)
+                             : fit_typed<double, uint32_t>(c, static_cast<const double*>(points), d, ld, B, offsets,
+                                                           max_iter, bits, labels, s);
+    } else {
+        rc = dtype == GS_F32 ? fit_typed<float, uint64_t>(c, static_cast<const float*>(points), d, ld, B, offsets,
+                                                          max_iter, bits, labels, s)
+                             : fit_typed<double, uint64_t>(c, static_cast<const double*>(points), d, ld, B, offsets,
+                                                           max_iter, bits, labels, s);
+    }
+    if (rc != GS_OK) return rc;
+    for (int b = 0; b < B; ++b) {
+        info[b].n_points = offsets[b + 1] - offsets[b];
+        info[b].n_cells0 = c->st[b].m0;
+        info[b].n_clusters = c->st[b].K;
+        info[b].n_iter = c->st[b].t;
+        info[b].flags = c->st[b].flags;
+    }
+    c->B = B;
+    c->d = d;
+    c->has_result = true;
+    return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gs_abi_version(void) { return GS_ABI_VERSION; }
+
+const char* gs_last_error(void) { return g_last_error.c_str(); }
+
+gs_status gs_context_create(gs_context** out) {
+    if (!out) return fail(GS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int dev = 0;
+    GS_HIP(hipGetDevice(&dev));
+    gs_context* c = new (std::nothrow) gs_context();
+    if (!c) return fail(GS_ERR_ALLOC, "out of host memory");
+    c->device = dev;
+    *out = c;
+    return GS_OK;
+}
+
+void gs_context_destroy(gs_context* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    DBuf* all[] = {&c->kA, &c->kB, &c->vA, &c->vB, &c->cell0, &c->kappa, &c->pbuf, &c->gmap, &c->cur, &c->tmap,
+                   &c->part, &c->partc, &c->hk, &c->hv, &c->ckA, &c->ckB, &c->cvA, &c->cvB, &c->param, &c->state,
+                   &c->rowoff, &c->hs, &c->bbox, &c->koff, &c->counters, &c->look, &c->tilectr, &c->shist,
+                   &c->sdbase, &c->sctr, &c->slook};
+    for (DBuf* b : all)
+        if (b->p) (void)hipFree(b->p);
+    for (int i = 0; i < 2; ++i) {
+        DBuf* tb[] = {&c->tkey[i], &c->tcnt[i], &c->tsum[i], &c->tinst[i], &c->tstart[i],
+                      &c->tlen[i], &c->tfirst[i], &c->tnch[i], &c->tchoff[i]};
+        for (DBuf* b : tb)
+            if (b->p) (void)hipFree(b->p);
+    }
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+}
+
+gs_status gs_fit(gs_context* ctx, const void* points, gs_dtype dtype, int64_t n, int32_t d, int64_t ld, double h,
+                 int32_t max_iter, int32_t* labels, gs_info* info, void* stream) {
+    if (n < 0) return fail(GS_ERR_INVALID_ARG, "n must be >= 0");
+    const int64_t offsets[2] = {0, n};
+    return fit_impl(ctx, points, dtype, d, ld, 1, offsets, &h, max_iter, labels, info,
+                    static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_fit_batched(gs_context* ctx, const void* points, gs_dtype dtype, int32_t d, int64_t ld, int32_t B,
+                         const int64_t* offsets, const double* h, int32_t max_iter, int32_t* labels, gs_info* info,
+                         void* stream) {
+    return fit_impl(ctx, points, dtype, d, ld, B, offsets, h, max_iter, labels, info,
+                    static_cast<hipStream_t>(stream));
+}
+
+static gs_status prepare_copy(gs_context* c, hipStream_t s, int64_t* rows) {
+    if (!c) return fail(GS_ERR_INVALID_ARG, "null context");
+    if (!c->has_result) return fail(GS_ERR_STATE, "the context holds no fit result");
+    GS_HIP(hipSetDevice(c->device));
+    std::vector<int64_t> koff(c->B + 1, 0);
+    for (int b = 0; b < c->B; ++b) koff[b + 1] = koff[b] + c->st[b].K;
+    GS_TRY(ensure(c->koff, sizeof(int64_t) * (c->B + 1)));
+    GS_TRY(h2d(c, c->koff.p, koff.data(), sizeof(int64_t) * (c->B + 1), s));
+    *rows = koff[c->B];
+    return GS_OK;
+}
+
+gs_status gs_copy_modes(gs_context* ctx, double* modes, int64_t* counts, double* sums, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int64_t rows = 0;
+    GS_TRY(prepare_copy(ctx, s, &rows));
+    if (rows == 0) return GS_OK;
+    gs::CellTable t = table(ctx, ctx->cur_tab);
+    gs::k_copy_modes<<<blocks_for(rows, 256), 256, 0, s>>>(t, P<gs::InstState>(ctx->state), P<int64_t>(ctx->koff),
+                                                           ctx->B, rows, ctx->d, modes, counts, sums);
+    GS_HIP(hipGetLastError());
+    return GS_OK;
+}
+
+gs_status gs_copy_keys(gs_context* ctx, int64_t* keys, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int64_t rows = 0;
+    GS_TRY(prepare_copy(ctx, s, &rows));
+    if (rows == 0) return GS_OK;
+    if (!keys) return fail(GS_ERR_INVALID_ARG, "keys is NULL");
+    gs::CellTable t = table(ctx, ctx->cur_tab);
+    gs::k_copy_keys<<<blocks_for(rows, 256), 256, 0, s>>>(t, P<gs::InstState>(ctx->state), P<gs::InstParam>(ctx->param),
+                                                          P<int64_t>(ctx->koff), ctx->B, rows, ctx->d, keys);
+    GS_HIP(hipGetLastError());
+    return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Device-side building blocks shared by the GridShift kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+constexpr int kMaxDim = 6;
+constexpr int kWave = 64;
+
+// Per-instance key packing.  The cell with integer key q (d coordinates) of
+// instance b has the packed key  base + sum_k (q_k - lo_k) * stride_k, with
+// lo_k = min_k - 1, E_k = max_k - min_k + 3 (one empty margin cell on each
+// side), stride_{d-1} = 1 and stride_k = stride_{k+1} * E_{k+1}.  Ascending
+// packed order is ascending (instance, lexicographic key) order.
+struct InstParam {
+    double h;
+    int64_t lo[kMaxDim];
+    int64_t E[kMaxDim];
+    uint64_t stride[kMaxDim];
+    uint64_t base;   // first packed key of the instance
+    uint64_t span;   // prod_k E_k (0 for an empty instance)
+    int64_t row0;    // first point row
+    int64_t row1;    // one past the last point row
+};
+
+// Per-instance iteration state.
+struct InstState {
+    int32_t t;        // rounds executed
+    uint32_t flags;   // GS_CONVERGED / GS_STATIONARY / GS_CAPPED
+    int32_t active;   // still iterating
+    int32_t apply;    // this round shifts and merges
+    int32_t any_nb;   // some cell had an active neighbour this round
+    int32_t changed;  // this round changed keys, counts or sums
+    int32_t err;      // error code raised on the device (GS_ERR_*)
+    int32_t pad;
+    int64_t cs, ce;   // cell range [cs, ce) in the current cell table
+    int64_t K;        // clusters at exit
+    int64_t m0;       // cells after binning
+};
+
+// ---------------------------------------------------------------------------
+// wave helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Perfect binary tree over the 64 lane values (lane l holds leaf l): after the
+// loop lane 0 holds ((v0+v1)+(v2+v3))+... with the pairing of R.  Missing
+// leaves must hold -0.0, the exact additive identity.
+__device__ __forceinline__ double wave_tree_sum(double v) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) v = v + __shfl_down(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_tree_sum_i64(int64_t v) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) v = v + __shfl_down(v, off, kWave);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// look-back status words: [epoch:16][flag:2][value:46]
+// ---------------------------------------------------------------------------
+constexpr uint64_t kFlagAgg = 1;
+constexpr uint64_t kFlagPrefix = 2;
+
+__device__ __forceinline__ uint64_t lb_pack(uint32_t epoch, uint64_t flag, uint64_t value) {
+    return (uint64_t(epoch & 0xffffu) << 48) | (flag << 46) | (value & ((1ull << 46) - 1));
+}
+__device__ __forceinline__ uint32_t lb_epoch(uint64_t w) { return uint32_t(w >> 48); }
+__device__ __forceinline__ uint64_t lb_flag(uint64_t w) { return (w >> 46) & 3ull; }
+__device__ __forceinline__ uint64_t lb_value(uint64_t w) { return w & ((1ull << 46) - 1); }
+
+__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t w) {
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of `total` over all earlier tiles (decoupled look-back).
+// The caller has already published its own aggregate.  Tile 0 returns 0.
+__device__ __forceinline__ uint64_t lb_exclusive(const uint64_t* status, int64_t tile, int64_t stride,
+                                                 uint32_t epoch) {
+    uint64_t excl = 0;
+    for (int64_t p = tile - 1; p >= 0; --p) {
+        uint64_t w;
+        do {
+            w = lb_load(status + p * stride);
+        } while (lb_epoch(w) != (epoch & 0xffffu) || lb_flag(w) == 0);
+        excl += lb_value(w);
+        if (lb_flag(w) == kFlagPrefix) break;
+    }
+    return excl;
+}
+
+// Instance of a row / packed key by binary search over the sorted bounds.
+__device__ __forceinline__ int inst_of_row(const int64_t* __restrict__ row_off, int B, int64_t row) {
+    int lo = 0, hi = B;  // row_off[lo] <= row < row_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (row_off[mid] <= row) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace gs

@@ -1,0 +1,931 @@
+// GridShift pipeline kernels for gfx950 (included by gs_api.hip: one translation unit).
+//
+// Binning (Section 2.1 (i), Algorithm 1 initialisation):
+//   k_bbox        per-instance box of the integer keys floor(fl(x/h)), plus the
+//                 non-finite and key-range checks
+//   k_make_keys   packed 32/64-bit key per point (instance = top digit) and the
+//                 digit histograms of every radix pass
+//   (radix sort)  stable sort of (key, point index), gs_sort.hip
+//   k_scan        one-pass look-back scans: run heads -> cell ids, chunk offsets
+//   k_cell_setup  run lengths, chunk counts, instance of every cell
+//   k_segsum_*    canonical pairwise sums R over every cell's members (one wave
+//                 per aligned 256-member chunk, then the chunk subtrees)
+// Rounds while some instance still has many cells (Section 2.1 (ii)-(v)):
+//   k_hash_*      open-addressing table packed key -> cell index
+//   k_shift       3^d neighbour fold in ascending key, p = N / W, landing key
+//   k_decide      per-instance stop test (no neighbour / max_iter)
+//   k_merge_prep  landing keys of applying instances, stationarity check
+//   (radix sort + k_scan + k_cell_setup + k_segsum) the merge of Eq. 3-4
+//   k_compose     initial cell -> current cell maps
+// Remaining rounds: k_tail, one 1024-thread workgroup per instance with its
+// whole cell table in LDS, looping on the device until it stops.
+// Outputs: k_labels, k_copy_modes, k_copy_keys.
+//
+// All floating point is binary64 without contraction (-ffp-contract=off).
+#include <math.h>
+
+#include "gs_device.hpp"
+#include "gs_pipeline.hpp"
+
+namespace gs {
+
+// ===========================================================================
+// small helpers
+// ===========================================================================
+template <typename T>
+__device__ __forceinline__ double load_coord(const T* __restrict__ x, int64_t row, int64_t ld, int k) {
+    return double(x[row * ld + k]);
+}
+
+__device__ __forceinline__ uint64_t dbits(double v) { return __double_as_longlong(v); }
+
+// floor(fl(v / h)) as a double.
+__device__ __forceinline__ double cell_floor(double v, double h) { return floor(v / h); }
+
+// ===========================================================================
+// state initialisation
+// ===========================================================================
+__global__ void k_init_state(InstState* __restrict__ st, int B, int64_t* __restrict__ bbox, int d,
+                             int64_t* __restrict__ counters) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) {
+        InstState z = {};
+        z.active = 1;
+        st[b] = z;
+        for (int k = 0; k < d; ++k) {
+            bbox[(int64_t(b) * kMaxDim + k) * 2 + 0] = INT64_MAX;
+            bbox[(int64_t(b) * kMaxDim + k) * 2 + 1] = INT64_MIN;
+        }
+    }
+    if (b < 8) counters[b] = 0;
+}
+
+// ===========================================================================
+// bbox: per instance and dimension, min/max of floor(fl(x/h))
+// ===========================================================================
+constexpr int kBoxThreads = 256;
+constexpr int kBoxRows = 4096;
+
+template <typename T>
+__global__ __launch_bounds__(kBoxThreads) void k_bbox(const T* __restrict__ x, int64_t ld, int d,
+                                                      const int64_t* __restrict__ row_off, int B, int64_t n,
+                                                      const double* __restrict__ hs, int64_t* __restrict__ bbox,
+                                                      int64_t* __restrict__ counters) {
+    __shared__ int64_t red[kBoxThreads / kWave][2 * kMaxDim];
+    __shared__ int s_err;
+    const int64_t r0 = int64_t(blockIdx.x) * kBoxRows;
+    if (r0 >= n) return;
+    const int64_t r1 = (r0 + kBoxRows < n) ? r0 + kBoxRows : n;
+    const int b0 = inst_of_row(row_off, B, r0);
+    const int b1 = inst_of_row(row_off, B, r1 - 1);
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    if (tid == 0) s_err = 0;
+    __syncthreads();
+    int err = 0;
+    for (int b = b0; b <= b1; ++b) {
+        const int64_t a0 = row_off[b] > r0 ? row_off[b] : r0;
+        const int64_t a1 = row_off[b + 1] < r1 ? row_off[b + 1] : r1;
+        if (a0 >= a1) continue;  // block-uniform
+        const double h = hs[b];
+        int64_t mn[kMaxDim], mx[kMaxDim];
+        for (int k = 0; k < kMaxDim; ++k) {
+            mn[k] = INT64_MAX;
+            mx[k] = INT64_MIN;
+        }
+        for (int64_t r = a0 + tid; r < a1; r += kBoxThreads) {
+            for (int k = 0; k < d; ++k) {
+                const double v = load_coord(x, r, ld, k);
+                if (!isfinite(v)) {
+                    err |= 1;
+                    continue;
+                }
+                const double q = cell_floor(v, h);
+                if (!(q > -4503599627370496.0 && q < 4503599627370496.0)) {  // |q| < 2^52
+                    err |= 2;
+                    continue;
+                }
+                const int64_t qi = int64_t(q);
+                mn[k] = qi < mn[k] ? qi : mn[k];
+                mx[k] = qi > mx[k] ? qi : mx[k];
+            }
+        }
+        for (int k = 0; k < d; ++k) {
+            for (int off = 32; off >= 1; off >>= 1) {
+                const int64_t a = __shfl_xor(mn[k], off, kWave);
+                const int64_t c = __shfl_xor(mx[k], off, kWave);
+                mn[k] = a < mn[k] ? a : mn[k];
+                mx[k] = c > mx[k] ? c : mx[k];
+            }
+            if (lane == 0) {
+                red[w][2 * k] = mn[k];
+                red[w][2 * k + 1] = mx[k];
+            }
+        }
+        __syncthreads();
+        if (tid < d) {
+            int64_t a = INT64_MAX, c = INT64_MIN;
+            for (int ww = 0; ww < kBoxThreads / kWave; ++ww) {
+                a = red[ww][2 * tid] < a ? red[ww][2 * tid] : a;
+                c = red[ww][2 * tid + 1] > c ? red[ww][2 * tid + 1] : c;
+            }
+            if (a != INT64_MAX) {
+                atomicMin((long long*)&bbox[(int64_t(b) * kMaxDim + tid) * 2 + 0], (long long)a);
+                atomicMax((long long*)&bbox[(int64_t(b) * kMaxDim + tid) * 2 + 1], (long long)c);
+            }
+        }
+        __syncthreads();
+    }
+    if (err) atomicOr(&s_err, err);
+    __syncthreads();
+    if (tid == 0 && s_err) atomicOr((unsigned long long*)&counters[2], (unsigned long long)s_err);
+}
+
+// ===========================================================================
+// packed keys + radix digit histograms
+// ===========================================================================
+constexpr int kKeyThreads = 256;
+
+template <typename T, typename K>
+__global__ __launch_bounds__(kKeyThreads) void k_make_keys(const T* __restrict__ x, int64_t ld, int d,
+                                                           const int64_t* __restrict__ row_off, int B, int64_t n,
+                                                           const InstParam* __restrict__ param,
+                                                           K* __restrict__ keys, int npasses,
+                                                           uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[kSortMaxPasses * 256];
+    for (int i = threadIdx.x; i < npasses * 256; i += kKeyThreads) h[i] = 0;
+    __syncthreads();
+    const int64_t stride = int64_t(gridDim.x) * kKeyThreads;
+    for (int64_t r = int64_t(blockIdx.x) * kKeyThreads + threadIdx.x; r < n; r += stride) {
+        const int b = inst_of_row(row_off, B, r);
+        const InstParam& P = param[b];
+        uint64_t key = P.base;
+        for (int k = 0; k < d; ++k) {
+            const double q = cell_floor(load_coord(x, r, ld, k), P.h);
+            key += uint64_t(int64_t(q) - P.lo[k]) * P.stride[k];
+        }
+        keys[r] = K(key);
+        sort_hist_add<K>(h, K(key), npasses);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < npasses * 256; i += kKeyThreads)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// ===========================================================================
+// one-pass look-back scan over positions (tile = 4096, wave-striped slots)
+// ===========================================================================
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = kScanTile / kScanThreads;  // 16
+
+// Run heads of a sorted key array: emits the cell table rows and the map
+// member -> cell.
+template <typename K>
+struct HeadsOp {
+    const K* key;            // sorted keys [n]
+    const uint32_t* perm;    // sorted position -> member index
+    uint64_t* cell_key;      // [m] packed key of every cell
+    uint32_t* cell_start;    // [m]
+    uint32_t* cell_first;    // [m] member at the start of the run
+    uint32_t* member_cell;   // [n] member index -> cell id
+    __device__ uint32_t value(int64_t p) const { return (p == 0 || key[p] != key[p - 1]) ? 1u : 0u; }
+    __device__ void emit(int64_t p, uint64_t excl, uint32_t v) const {
+        const uint64_t cid = excl + v - 1;
+        const uint32_t mem = perm[p];
+        if (v) {
+            cell_key[cid] = uint64_t(key[p]);
+            cell_start[cid] = uint32_t(p);
+            cell_first[cid] = mem;
+        }
+        member_cell[mem] = uint32_t(cid);
+    }
+};
+
+// Exclusive scan of a u32 array.
+struct ExclOp {
+    const uint32_t* in;
+    uint32_t* out;
+    __device__ uint32_t value(int64_t p) const { return in[p]; }
+    __device__ void emit(int64_t p, uint64_t excl, uint32_t) const { out[p] = uint32_t(excl); }
+};
+
+// n_ptr: device count of positions (read once per block); total: device
+// result (sum of all values).  Tiles take their index from tile_ctr.
+template <class Op>
+__global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __restrict__ n_ptr,
+                                                       uint64_t* __restrict__ look, uint32_t* __restrict__ tile_ctr,
+                                                       uint32_t epoch, int64_t* __restrict__ total) {
+    constexpr int W = kScanThreads / kWave;
+    __shared__ int64_t s_tile;
+    __shared__ uint64_t wtot[W];
+    __shared__ uint64_t s_excl;
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t n = *n_ptr;
+    const int64_t t0 = tile * kScanTile;
+    if (t0 >= n && tile > 0) return;
+
+    uint32_t v[kScanItems];
+    uint64_t incl[kScanItems];
+    uint64_t run = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t p = t0 + int64_t(w) * (kWave * kScanItems) + i * kWave + lane;
+        v[i] = p < n ? op.value(p) : 0u;
+        uint64_t xs = v[i];
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint64_t y = __shfl_up(xs, off, kWave);
+            if (lane >= off) xs += y;
+        }
+        incl[i] = run + xs;
+        run += __shfl(xs, kWave - 1, kWave);
+    }
+    if (lane == 0) wtot[w] = run;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t tot = 0;
+        for (int ww = 0; ww < W; ++ww) {
+            const uint64_t c = wtot[ww];
+            wtot[ww] = tot;
+            tot += c;
+        }
+        uint64_t excl = 0;
+        if (tile == 0) {
+            lb_store(look, lb_pack(epoch, kFlagPrefix, tot));
+        } else {
+            lb_store(look + tile, lb_pack(epoch, kFlagAgg, tot));
+            excl = lb_exclusive(look, tile, 1, epoch);
+            lb_store(look + tile, lb_pack(epoch, kFlagPrefix, excl + tot));
+        }
+        s_excl = excl;
+        if (t0 + kScanTile >= n) *total = int64_t(excl + tot);
+    }
+    __syncthreads();
+    const uint64_t base = s_excl + wtot[w];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t p = t0 + int64_t(w) * (kWave * kScanItems) + i * kWave + lane;
+        if (p < n) op.emit(p, base + incl[i] - v[i], v[i]);
+    }
+}
+
+// ===========================================================================
+// cell setup after a heads scan
+// ===========================================================================
+// mode 0 (binning): instance from the member's row; mode 1 (merge): from the
+// member cell's instance, and flag instances whose round merged cells.
+__global__ void k_cell_setup(const int64_t* __restrict__ m_ptr, int64_t npos, CellTable t, int mode,
+                             const int64_t* __restrict__ row_off, int B, const int32_t* __restrict__ old_inst,
+                             InstState* __restrict__ st) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t m = *m_ptr;
+    if (c >= m) return;
+    const uint32_t s0 = t.start[c];
+    const uint32_t s1 = (c + 1 < m) ? t.start[c + 1] : uint32_t(npos);
+    const uint32_t len = s1 - s0;
+    t.len[c] = len;
+    t.nch[c] = (len + kChunk - 1) / kChunk;
+    int b;
+    if (mode == 0) {
+        b = inst_of_row(row_off, B, int64_t(t.first[c]));
+    } else {
+        b = old_inst[t.first[c]];
+        if (len > 1 && st[b].apply) atomicOr(&st[b].changed, 1);
+    }
+    t.inst[c] = b;
+}
+
+// ===========================================================================
+// canonical segmented sums
+// ===========================================================================
+// Point members: value = (double)x[row][k], count 1.
+template <typename T>
+struct SrcPoints {
+    const T* x;
+    int64_t ld;
+    const uint32_t* perm;
+    __device__ int64_t load(int64_t p, double* v, int d) const {
+        const int64_t r = perm[p];
+        for (int k = 0; k < d; ++k) v[k] = load_coord(x, r, ld, k);
+        return 1;
+    }
+};
+
+// Merge members (old cells): value fl(C_j * p_j) if the instance applies the
+// round, else the unchanged sum S_j; count C_j.
+struct SrcMerge {
+    const double* pbuf;   // [d][cap] shifted positions
+    const double* sum;    // [d][cap] old sums
+    const int64_t* cnt;   // old counts
+    const int32_t* inst;  // old instance ids
+    const InstState* st;
+    const uint32_t* perm;
+    int64_t cap;
+    __device__ int64_t load(int64_t p, double* v, int d) const {
+        const int64_t j = perm[p];
+        const int64_t C = cnt[j];
+        if (st[inst[j]].apply) {
+            for (int k = 0; k < d; ++k) v[k] = double(C) * pbuf[k * cap + j];
+        } else {
+            for (int k = 0; k < d; ++k) v[k] = sum[k * cap + j];
+        }
+        return C;
+    }
+};
+
+constexpr int kSegThreads = 256;
+
+// One wave per chunk task: the R subtree of 256 members aligned at the
+// cell's first member.  Lane l holds members 4l..4l+3 of the chunk.
+template <int D, class Src>
+__global__ __launch_bounds__(kSegThreads) void k_segsum_chunks(Src src, CellTable t, const int64_t* __restrict__ m_ptr,
+                                                               const int64_t* __restrict__ tasks_ptr,
+                                                               double* __restrict__ part,
+                                                               int64_t* __restrict__ partc, int64_t pcap) {
+    const int64_t task = (int64_t(blockIdx.x) * kSegThreads + threadIdx.x) / kWave;
+    const int lane = lane_id();
+    if (task >= *tasks_ptr) return;
+    const int64_t m = *m_ptr;
+    int64_t lo = 0, hi = m;  // last cell with choff <= task
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (t.choff[mid] <= uint32_t(task)) lo = mid; else hi = mid;
+    }
+    const int64_t c = lo;
+    const int64_t ch = task - t.choff[c];
+    const int64_t len = t.len[c];
+    const int64_t p0 = int64_t(t.start[c]) + ch * kChunk;
+    const int64_t cnt = (len - ch * kChunk) < kChunk ? (len - ch * kChunk) : kChunk;
+    double acc[D];
+    int64_t cacc = 0;
+    {
+        double a[4][D];
+        int64_t ca[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = 4 * lane + i;
+            if (r < cnt) {
+                ca[i] = src.load(p0 + r, a[i], D);
+            } else {
+                ca[i] = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) a[i][k] = -0.0;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = (a[0][k] + a[1][k]) + (a[2][k] + a[3][k]);
+        cacc = (ca[0] + ca[1]) + (ca[2] + ca[3]);
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] = wave_tree_sum(acc[k]);
+    cacc = wave_tree_sum_i64(cacc);
+    if (lane == 0) {
+        if (t.nch[c] == 1) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) t.sum[k * t.cap + c] = acc[k];
+            t.cnt[c] = cacc;
+        } else {
+#pragma unroll
+            for (int k = 0; k < D; ++k) part[k * pcap + task] = acc[k];
+            partc[task] = cacc;
+        }
+    }
+}
+
+__device__ __forceinline__ double ld_agent(const double* p) {
+    return __longlong_as_double(
+        (long long)__hip_atomic_load((uint64_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
+    __hip_atomic_store((uint64_t*)p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int64_t ld_agent_i(const int64_t* p) {
+    return __hip_atomic_load(const_cast<int64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent_i(int64_t* p, int64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One wave per cell with more than one chunk: combine the chunk subtrees 64
+// at a time (aligned, -0 padded) until one value is left; that is R.
+template <int D>
+__global__ __launch_bounds__(kSegThreads) void k_segsum_levels(CellTable t, const int64_t* __restrict__ m_ptr,
+                                                               double* __restrict__ part, int64_t* __restrict__ partc,
+                                                               int64_t pcap) {
+    const int64_t c = (int64_t(blockIdx.x) * kSegThreads + threadIdx.x) / kWave;
+    const int lane = lane_id();
+    if (c >= *m_ptr) return;
+    int64_t len = t.nch[c];
+    if (len <= 1) return;
+    const int64_t base = t.choff[c];
+    while (len > 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int64_t pieces = (len + kWave - 1) / kWave;
+        for (int64_t pc = 0; pc < pieces; ++pc) {
+            const int64_t i = pc * kWave + lane;
+            double v[D];
+            int64_t cv = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[k] = i < len ? ld_agent(&part[k * pcap + base + i]) : -0.0;
+            cv = i < len ? ld_agent_i(&partc[base + i]) : 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[k] = wave_tree_sum(v[k]);
+            cv = wave_tree_sum_i64(cv);
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) st_agent(&part[k * pcap + base + pc], v[k]);
+                st_agent_i(&partc[base + pc], cv);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        }
+        len = pieces;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) t.sum[k * t.cap + c] = ld_agent(&part[k * pcap + base]);
+        t.cnt[c] = ld_agent_i(&partc[base]);
+    }
+}
+
+// ===========================================================================
+// instance ranges in a cell table
+// ===========================================================================
+__global__ void k_clear_ranges(InstState* __restrict__ st, int B) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) {
+        st[b].cs = 0;
+        st[b].ce = 0;
+    }
+}
+
+__global__ void k_inst_ranges(const int32_t* __restrict__ inst, const int64_t* __restrict__ m_ptr,
+                              InstState* __restrict__ st) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t m = *m_ptr;
+    if (c >= m) return;
+    const int b = inst[c];
+    if (c == 0 || inst[c - 1] != b) st[b].cs = c;
+    if (c == m - 1 || inst[c + 1] != b) st[b].ce = c + 1;
+}
+
+// ===========================================================================
+// wide rounds
+// ===========================================================================
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ __forceinline__ uint64_t hash_slot(uint64_t key, int logcap) {
+    uint64_t z = key + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z >> (64 - logcap);
+}
+
+__global__ void k_hash_clear(uint64_t* __restrict__ hk, int64_t cap) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < cap) hk[i] = kEmpty;
+}
+
+__global__ void k_hash_insert(const uint64_t* __restrict__ key, int64_t m, uint64_t* __restrict__ hk,
+                              uint32_t* __restrict__ hv, int logcap) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const uint64_t k = key[j];
+    const uint64_t mask = (1ull << logcap) - 1;
+    uint64_t s = hash_slot(k, logcap);
+    for (;;) {
+        const uint64_t prev = atomicCAS((unsigned long long*)&hk[s], (unsigned long long)kEmpty,
+                                        (unsigned long long)k);
+        if (prev == kEmpty || prev == k) {
+            hv[s] = uint32_t(j);
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
+__device__ __forceinline__ int64_t hash_find(const uint64_t* __restrict__ hk, const uint32_t* __restrict__ hv,
+                                             uint64_t k, int logcap) {
+    const uint64_t mask = (1ull << logcap) - 1;
+    uint64_t s = hash_slot(k, logcap);
+    for (;;) {
+        const uint64_t e = hk[s];
+        if (e == k) return hv[s];
+        if (e == kEmpty) return -1;
+        s = (s + 1) & mask;
+    }
+}
+
+// Shift of every cell of an active instance (Eq. 1-2, parallel form Eq. 6):
+// neighbours j+v, v in {-1,0,1}^D enumerated lexicographically (= ascending
+// packed key), W exact, N a left fold, p = N / W, landing key floor(p/h).
+template <int D>
+__global__ void k_shift(CellTable t, int64_t m, const InstParam* __restrict__ param, InstState* __restrict__ st,
+                        const uint64_t* __restrict__ hk, const uint32_t* __restrict__ hv, int logcap,
+                        double* __restrict__ pbuf, uint64_t* __restrict__ kappa) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int b = t.inst[j];
+    if (!st[b].active) return;
+    const InstParam& P = param[b];
+    const uint64_t key = t.key[j];
+    uint64_t local = key - P.base;
+    int64_t crd[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) crd[k] = int64_t((local / P.stride[k]) % uint64_t(P.E[k]));
+    int64_t W = 0;
+    double N[D];
+    bool first = true, nb = false;
+    int v[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = -1;
+    for (;;) {
+        bool inside = true;
+        uint64_t nk = key;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int64_t c = crd[k] + v[k];
+            inside = inside && c >= 0 && c < P.E[k];
+            nk += uint64_t(int64_t(v[k])) * P.stride[k];
+        }
+        if (inside) {
+            const int64_t idx = hash_find(hk, hv, nk, logcap);
+            if (idx >= 0) {
+                W += t.cnt[idx];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double s = t.sum[k * t.cap + idx];
+                    N[k] = first ? s : N[k] + s;
+                }
+                first = false;
+                nb = nb || (idx != j);
+            }
+        }
+        // odometer over {-1,0,1}^D, last dimension fastest
+        int k = D - 1;
+        while (k >= 0 && v[k] == 1) {
+            v[k] = -1;
+            --k;
+        }
+        if (k < 0) break;
+        ++v[k];
+    }
+    uint64_t kap = P.base;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double p = N[k] / double(W);
+        pbuf[k * t.cap + j] = p;
+        const double q = cell_floor(p, P.h);
+        const double rel = q - double(P.lo[k]);
+        if (!(rel >= 0.0 && rel < double(P.E[k]))) bad = true;
+        kap += uint64_t(int64_t(q) - P.lo[k]) * P.stride[k];
+    }
+    kappa[j] = kap;
+    if (nb) atomicOr(&st[b].any_nb, 1);
+    if (bad) atomicOr(&st[b].err, 3);  // GS_ERR_KEY_RANGE
+}
+
+// Stop test of the round (Section 2.1 (v)): decides whether each instance
+// applies the shift and merge computed by k_shift.
+__global__ void k_decide(InstState* __restrict__ st, int B, int max_iter) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    InstState s = st[b];
+    s.apply = 0;
+    s.changed = 0;
+    if (s.active) {
+        if (!s.any_nb) {
+            s.flags |= 1u;  // converged
+            s.active = 0;
+        } else if (s.t >= max_iter) {
+            s.flags |= 4u;  // capped
+            s.active = 0;
+        } else {
+            s.apply = 1;
+        }
+    }
+    s.any_nb = 0;
+    st[b] = s;
+}
+
+// Landing keys for the merge sort; stationarity of applying instances.
+template <typename K>
+__global__ void k_merge_prep(CellTable t, int64_t m, const InstState* __restrict__ stc, InstState* __restrict__ st,
+                             const double* __restrict__ pbuf, const uint64_t* __restrict__ kappa, K* __restrict__ skey,
+                             int d) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int b = t.inst[j];
+    const uint64_t key = t.key[j];
+    if (!stc[b].apply) {
+        skey[j] = K(key);
+        return;
+    }
+    const uint64_t kap = kappa[j];
+    skey[j] = K(kap);
+    bool chg = kap != key;
+    const double C = double(t.cnt[j]);
+    for (int k = 0; k < d; ++k) chg = chg || dbits(C * pbuf[k * t.cap + j]) != dbits(t.sum[k * t.cap + j]);
+    if (chg) atomicOr(&st[b].changed, 1);
+}
+
+__global__ void k_compose(uint32_t* __restrict__ cur, int64_t m0, const uint32_t* __restrict__ g) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c < m0) cur[c] = g[cur[c]];
+}
+
+__global__ void k_round_end(InstState* __restrict__ st, int B) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    InstState s = st[b];
+    if (s.apply) {
+        s.t += 1;
+        if (!s.changed) {
+            s.flags |= 2u;  // stationary
+            s.active = 0;
+        }
+    }
+    s.apply = 0;
+    s.changed = 0;
+    st[b] = s;
+}
+
+// ===========================================================================
+// tail: one workgroup per instance, whole cell table in LDS
+// ===========================================================================
+template <int D>
+__global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstParam* __restrict__ param,
+                                                       InstState* __restrict__ st, uint32_t* __restrict__ tmap,
+                                                       int max_iter) {
+    constexpr int MT = kTailCells;
+    constexpr int NW = kTailThreads / kWave;
+    __shared__ uint64_t lkey[MT];     // local packed key (key - base), ascending
+    __shared__ int32_t crd[D][MT];    // unpacked coordinates relative to lo
+    __shared__ int32_t cnt[MT];       // counts
+    __shared__ double sm[D][MT];      // sums; reused as the sorted merge values
+    __shared__ uint64_t kap[MT];      // landing keys
+    __shared__ uint64_t skey[MT];     // landing keys sorted
+    __shared__ int32_t scnt[MT];      // counts sorted
+    __shared__ uint16_t gmap[MT];     // old cell -> new cell
+    __shared__ uint16_t lmap[MT];     // entry cell -> current cell
+    __shared__ uint16_t gid_of[MT];   // sorted position -> group
+    __shared__ uint16_t hstart[MT + 1];
+    __shared__ int32_t wsum[NW];
+    __shared__ int32_t s_maxsz;
+
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    InstState* S = st + b;
+    const int64_t cs = S->cs, ce = S->ce;
+    const int m_entry = int(ce - cs);
+    if (!S->active) {
+        for (int e = tid; e < m_entry; e += kTailThreads) tmap[cs + e] = uint32_t(e);
+        if (tid == 0) S->K = m_entry;
+        return;
+    }
+    const InstParam& P = param[b];
+    const double h = P.h;
+    int64_t lo[D], E[D];
+    uint64_t stride[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        lo[k] = P.lo[k];
+        E[k] = P.E[k];
+        stride[k] = P.stride[k];
+    }
+
+    if (tid < m_entry) {
+        const int64_t c = cs + tid;
+        const uint64_t lk = t.key[c] - P.base;
+        lkey[tid] = lk;
+        cnt[tid] = int32_t(t.cnt[c]);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            sm[k][tid] = t.sum[k * t.cap + c];
+            crd[k][tid] = int32_t((lk / stride[k]) % uint64_t(E[k]));
+        }
+        lmap[tid] = uint16_t(tid);
+    }
+    __syncthreads();
+
+    int m = m_entry;
+    int tt = S->t;
+    uint32_t flags = S->flags;
+    int err = 0;
+    const uint64_t lt = lanemask_lt();
+    for (;;) {
+        // ---- shift (one cell per thread)
+        bool nb = false, bad = false;
+        double p[D];
+        int32_t q[D];
+        uint64_t kj = 0;
+        if (tid < m) {
+            const int32_t c0 = crd[0][tid];
+            int a = 0, z = m;  // first cell with crd0 >= c0 - 1
+            while (a < z) {
+                const int mid = (a + z) >> 1;
+                if (crd[0][mid] < c0 - 1) a = mid + 1; else z = mid;
+            }
+            int64_t W = 0;
+            bool first = true;
+            for (int k = a; k < m && crd[0][k] <= c0 + 1; ++k) {
+                bool ok = true;
+#pragma unroll
+                for (int dd = 1; dd < D; ++dd) ok = ok && (uint32_t(crd[dd][k] - crd[dd][tid] + 1) <= 2u);
+                if (ok) {
+                    W += cnt[k];
+#pragma unroll
+                    for (int dd = 0; dd < D; ++dd) p[dd] = first ? sm[dd][k] : p[dd] + sm[dd][k];
+                    first = false;
+                    nb = nb || (k != tid);
+                }
+            }
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) {
+                p[dd] = p[dd] / double(W);
+                const double qq = cell_floor(p[dd], h);
+                const double rel = qq - double(lo[dd]);
+                if (!(rel >= 0.0 && rel < double(E[dd]))) bad = true;
+                q[dd] = int32_t(int64_t(qq) - lo[dd]);
+                kj += uint64_t(int64_t(qq) - lo[dd]) * stride[dd];
+            }
+        }
+        const int any = __syncthreads_or(nb);
+        if (!any) {
+            flags |= 1u;
+            break;
+        }
+        if (tt >= max_iter) {
+            flags |= 4u;
+            break;
+        }
+        if (__syncthreads_or(bad)) {
+            err = 3;
+            break;
+        }
+        // ---- merge values, stationarity, landing keys
+        bool chg = false;
+        double val[D];
+        if (tid < m) {
+            chg = kj != lkey[tid];
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) {
+                val[dd] = double(cnt[tid]) * p[dd];
+                chg = chg || dbits(val[dd]) != dbits(sm[dd][tid]);
+            }
+            kap[tid] = kj;
+        }
+        __syncthreads();
+        // ---- stable rank by (landing key, old index)
+        int rank = 0;
+        if (tid < m) {
+            for (int k = 0; k < m; ++k) {
+                const uint64_t u = kap[k];
+                rank += (u < kj) || (u == kj && k < tid);
+            }
+            skey[rank] = kj;
+            scnt[rank] = cnt[tid];
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) {
+                sm[dd][rank] = val[dd];
+                crd[dd][rank] = q[dd];
+            }
+        }
+        __syncthreads();
+        // ---- groups of equal landing keys
+        const bool head = tid < m && (tid == 0 || skey[tid] != skey[tid - 1]);
+        const uint64_t hb = __ballot(head);
+        if (lane == 0) wsum[w] = __popcll(hb);
+        if (tid == 0) s_maxsz = 1;
+        __syncthreads();
+        int gex = 0, mnew = 0;
+        for (int ww = 0; ww < NW; ++ww) {
+            const int c = wsum[ww];
+            gex += ww < w ? c : 0;
+            mnew += c;
+        }
+        const int gid = gex + __popcll(hb & lt) + (head ? 1 : 0) - 1;
+        if (tid < m) gid_of[tid] = uint16_t(gid);
+        if (head) hstart[gid] = uint16_t(tid);
+        if (tid == 0) hstart[mnew] = uint16_t(m);
+        __syncthreads();
+        if (head) {
+            const int sz = int(hstart[gid + 1]) - tid;
+            if (sz > 1) atomicMax(&s_maxsz, sz);
+        }
+        __syncthreads();
+        const int maxsz = s_maxsz;
+        for (int s = 1; s < maxsz; s <<= 1) {
+            if (tid < m) {
+                const int g0 = hstart[gid];
+                const int rel = tid - g0;
+                const int sz = int(hstart[gid + 1]) - g0;
+                if ((rel & (2 * s - 1)) == 0 && rel + s < sz) {
+#pragma unroll
+                    for (int dd = 0; dd < D; ++dd) sm[dd][tid] = sm[dd][tid] + sm[dd][tid + s];
+                    scnt[tid] = scnt[tid] + scnt[tid + s];
+                }
+            }
+            __syncthreads();
+        }
+        // ---- new table
+        uint64_t nk = 0;
+        int32_t nc = 0;
+        double ns[D];
+        int32_t nq[D];
+        if (head) {
+            nk = skey[tid];
+            nc = scnt[tid];
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) {
+                ns[dd] = sm[dd][tid];
+                nq[dd] = crd[dd][tid];
+            }
+        }
+        if (tid < m) gmap[tid] = gid_of[rank];
+        __syncthreads();
+        if (head) {
+            lkey[gid] = nk;
+            cnt[gid] = nc;
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) {
+                sm[dd][gid] = ns[dd];
+                crd[dd][gid] = nq[dd];
+            }
+        }
+        __syncthreads();
+        if (tid < m_entry) lmap[tid] = gmap[lmap[tid]];
+        const int changed = __syncthreads_or(chg) || (mnew != m);
+        m = mnew;
+        ++tt;
+        if (!changed) {
+            flags |= 2u;
+            break;
+        }
+    }
+    __syncthreads();
+    if (err) {
+        if (tid == 0) S->err = err;
+        return;
+    }
+    if (tid < m) {
+        const int64_t c = cs + tid;
+        t.key[c] = lkey[tid] + P.base;
+        t.cnt[c] = cnt[tid];
+#pragma unroll
+        for (int k = 0; k < D; ++k) t.sum[k * t.cap + c] = sm[k][tid];
+    }
+    if (tid < m_entry) tmap[cs + tid] = lmap[tid];
+    if (tid == 0) {
+        S->t = tt;
+        S->flags = flags;
+        S->K = m;
+        S->active = 0;
+    }
+}
+
+// ===========================================================================
+// outputs
+// ===========================================================================
+__global__ void k_labels(const uint32_t* __restrict__ cell0, const uint32_t* __restrict__ cur,
+                         const uint32_t* __restrict__ tmap, int32_t* __restrict__ labels, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t c0 = cell0[i];
+    const uint32_t c = cur ? cur[c0] : c0;
+    labels[i] = int32_t(tmap[c]);
+}
+
+// Row r of the concatenated output belongs to instance b with
+// koff[b] <= r < koff[b+1]; its cell is cs[b] + (r - koff[b]).
+__global__ void k_copy_modes(CellTable t, const InstState* __restrict__ st, const int64_t* __restrict__ koff, int B,
+                             int64_t rows, int d, double* __restrict__ modes, int64_t* __restrict__ counts,
+                             double* __restrict__ sums) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const int b = inst_of_row(koff, B, r);
+    const int64_t c = st[b].cs + (r - koff[b]);
+    const int64_t C = t.cnt[c];
+    if (counts) counts[r] = C;
+    for (int k = 0; k < d; ++k) {
+        const double s = t.sum[k * t.cap + c];
+        if (modes) modes[r * d + k] = s / double(C);
+        if (sums) sums[r * d + k] = s;
+    }
+}
+
+__global__ void k_copy_keys(CellTable t, const InstState* __restrict__ st, const InstParam* __restrict__ param,
+                            const int64_t* __restrict__ koff, int B, int64_t rows, int d, int64_t* __restrict__ out) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const int b = inst_of_row(koff, B, r);
+    const int64_t c = st[b].cs + (r - koff[b]);
+    const InstParam& P = param[b];
+    const uint64_t local = t.key[c] - P.base;
+    for (int k = 0; k < d; ++k) out[r * d + k] = int64_t((local / P.stride[k]) % uint64_t(P.E[k])) + P.lo[k];
+}
+
+}  // namespace gs

@@ -1,0 +1,31 @@
+// Data structures and constants of the GridShift pipeline.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs_device.hpp"
+#include "gs_sort.hpp"
+
+namespace gs {
+
+constexpr int kTailCells = 1024;    // cells one tail workgroup holds in LDS
+constexpr int kTailThreads = 1024;  // one cell per thread
+constexpr int kChunk = 256;         // leaves of one wave's sum subtree (64 lanes x 4)
+constexpr int kScanTile = 4096;     // positions per look-back scan tile
+
+// Device pointers of one cell table (struct of arrays with capacity cap).
+struct CellTable {
+    uint64_t* key = nullptr;    // packed key, ascending
+    int64_t* cnt = nullptr;     // point count C
+    double* sum = nullptr;      // coordinate sums S, [d][cap]
+    int32_t* inst = nullptr;    // instance of the cell
+    uint32_t* start = nullptr;  // first sorted position of the cell's members
+    uint32_t* len = nullptr;    // number of members (points, or merged cells)
+    uint32_t* first = nullptr;  // member index at `start`
+    uint32_t* nch = nullptr;    // chunks of kChunk members
+    uint32_t* choff = nullptr;  // exclusive scan of nch
+    int64_t cap = 0;
+};
+
+}  // namespace gs

@@ -1,0 +1,227 @@
+// Stable LSD radix sort of (key, index) pairs, one read and one write of the
+// pairs per 8-bit digit (a single-pass "onesweep" scheme):
+//   * all digit histograms come from one up-front pass (or from the key
+//     producer, which fuses it);
+//   * every pass ranks its 4096-key tile in LDS with wave64 ballots, stably
+//     (positions ascend with the input order), publishes the tile's digit
+//     counts and finds the counts of all earlier tiles by decoupled look-back;
+//   * the tile is reordered by digit in LDS and written out in digit runs, so
+//     consecutive lanes store consecutive addresses.
+// Tiles take their index from an atomic counter, so a tile only ever waits on
+// tiles that started before it: the look-back always terminates.
+#include "gs_device.hpp"
+#include "gs_sort.hpp"
+
+namespace gs {
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const K* __restrict__ keys, int64_t n, int npasses,
+                                                            uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[kSortMaxPasses * 256];
+    for (int i = threadIdx.x; i < npasses * 256; i += kSortThreads) h[i] = 0;
+    __syncthreads();
+    const int64_t stride = int64_t(gridDim.x) * kSortThreads;
+    for (int64_t i = int64_t(blockIdx.x) * kSortThreads + threadIdx.x; i < n; i += stride)
+        sort_hist_add<K>(h, keys[i], npasses);
+    __syncthreads();
+    for (int i = threadIdx.x; i < npasses * 256; i += kSortThreads)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// Exclusive scan of each pass's histogram; also resets the tile counters.
+__global__ __launch_bounds__(256) void k_sort_bases(const uint32_t* __restrict__ hist, uint32_t* __restrict__ dbase,
+                                                    uint32_t* __restrict__ ctr, int npasses) {
+    __shared__ uint32_t s[256];
+    const int t = threadIdx.x;
+    if (t < kSortMaxPasses) ctr[t] = 0;
+    for (int p = 0; p < npasses; ++p) {
+        s[t] = hist[p * 256 + t];
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const uint32_t v = t >= off ? s[t - off] : 0u;
+            __syncthreads();
+            s[t] += v;
+            __syncthreads();
+        }
+        dbase[p * 256 + t] = s[t] - hist[p * 256 + t];
+        __syncthreads();
+    }
+}
+
+__global__ void k_iota(uint32_t* __restrict__ v, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = uint32_t(i);
+}
+
+__global__ void k_clear_u32(uint32_t* __restrict__ p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void k_clear_u64(uint64_t* __restrict__ p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                            K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                            int64_t n, int shift, const uint32_t* __restrict__ dbase,
+                                                            uint64_t* __restrict__ look, uint32_t* __restrict__ ctr,
+                                                            uint32_t epoch) {
+    constexpr int W = kSortThreads / kWave;
+    __shared__ uint32_t wcnt[W][256];    // per-wave digit counts, then their exclusive scan over waves
+    __shared__ uint32_t doff[256];       // tile-local exclusive digit offsets
+    __shared__ uint32_t gbase[256];      // global position of the tile's first key of each digit
+    __shared__ K skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
+    __shared__ int64_t s_tile;
+
+    const int tid = threadIdx.x;
+    const int w = tid / kWave;
+    const int lane = lane_id();
+    if (tid == 0) s_tile = atomicAdd(ctr, 1u);
+    for (int i = tid; i < W * 256; i += kSortThreads) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t t0 = tile * kSortTile;
+
+    // Load: wave w owns keys [w*64*ITEMS, (w+1)*64*ITEMS) of the tile, slot i
+    // covers 64 consecutive keys, so (slot, lane) order is input order.
+    K key[kSortItems];
+    uint32_t val[kSortItems];
+    uint32_t rank[kSortItems];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t pos = t0 + int64_t(w) * (kWave * kSortItems) + i * kWave + lane;
+        const bool valid = pos < n;
+        key[i] = valid ? kin[pos] : K(0);
+        val[i] = valid ? (vin ? vin[pos] : uint32_t(pos)) : 0u;
+        const uint32_t dgt = uint32_t(key[i] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dgt >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        uint32_t prior = 0;
+        if (valid) prior = wcnt[w][dgt];
+        rank[i] = prior + uint32_t(__popcll(peers & lt));
+        if (valid && lane == 63 - __clzll(peers)) wcnt[w][dgt] = prior + uint32_t(__popcll(peers));
+    }
+    __syncthreads();
+
+    // Scan the per-wave counts over waves (digit = thread) and publish the
+    // tile total for the look-back.
+    {
+        const int dgt = tid;
+        uint32_t run = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) {
+            const uint32_t c = wcnt[ww][dgt];
+            wcnt[ww][dgt] = run;
+            run += c;
+        }
+        uint64_t* st = look + tile * 256 + dgt;
+        if (tile == 0) {
+            lb_store(st, lb_pack(epoch, kFlagPrefix, run));
+            gbase[dgt] = dbase[dgt];
+        } else {
+            lb_store(st, lb_pack(epoch, kFlagAgg, run));
+            const uint64_t excl = lb_exclusive(look + dgt, tile, 256, epoch);
+            lb_store(st, lb_pack(epoch, kFlagPrefix, excl + run));
+            gbase[dgt] = dbase[dgt] + uint32_t(excl);
+        }
+        doff[dgt] = run;  // inclusive scan over digits follows
+    }
+    __syncthreads();
+    // tile-local exclusive scan over the 256 digit totals
+    {
+        const uint32_t mine = doff[tid];
+        for (int off = 1; off < 256; off <<= 1) {
+            const uint32_t v = tid >= off ? doff[tid - off] : 0u;
+            __syncthreads();
+            doff[tid] += v;
+            __syncthreads();
+        }
+        doff[tid] -= mine;
+    }
+    __syncthreads();
+
+    // Reorder the tile by digit in LDS.
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t pos = t0 + int64_t(w) * (kWave * kSortItems) + i * kWave + lane;
+        if (pos < n) {
+            const uint32_t dgt = uint32_t(key[i] >> shift) & 255u;
+            const uint32_t lp = doff[dgt] + wcnt[w][dgt] + rank[i];
+            skey[lp] = key[i];
+            sval[lp] = val[i];
+        }
+    }
+    __syncthreads();
+
+    // Write out: entry j of the reordered tile goes to gbase[digit] + (j - doff[digit]).
+    const int64_t cnt = (n - t0) < kSortTile ? (n - t0) : kSortTile;
+    for (int j = tid; j < cnt; j += kSortThreads) {
+        const K k = skey[j];
+        const uint32_t dgt = uint32_t(k >> shift) & 255u;
+        const uint32_t g = gbase[dgt] + (uint32_t(j) - doff[dgt]);
+        kout[g] = k;
+        vout[g] = sval[j];
+    }
+}
+
+template <typename K>
+hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int bits, bool hist_ready,
+                      SortScratch& sc, hipStream_t s, K** kout, uint32_t** vout) {
+    const int np = sort_passes(bits);
+    *kout = kA;
+    *vout = vA;
+    if (n <= 0) return hipSuccess;
+    if (np == 0) {
+        k_iota<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, s>>>(vA, n);
+        return hipGetLastError();
+    }
+    const int64_t tiles = sort_look_tiles(n);
+    if (tiles > sc.look_tiles) return hipErrorInvalidValue;
+    if (!hist_ready) {
+        k_clear_u32<<<dim3(kSortMaxPasses), dim3(256), 0, s>>>(sc.hist, kSortMaxPasses * 256);
+        int64_t blocks = (n + kSortThreads * 16 - 1) / (kSortThreads * 16);
+        if (blocks > 2048) blocks = 2048;
+        k_sort_hist<K><<<dim3(unsigned(blocks)), dim3(kSortThreads), 0, s>>>(kA, n, np, sc.hist);
+    }
+    k_sort_bases<<<1, 256, 0, s>>>(sc.hist, sc.dbase, sc.ctr, np);
+    K* ki = kA;
+    K* ko = kB;
+    uint32_t* vi = nullptr;
+    uint32_t* vo = vA;
+    for (int p = 0; p < np; ++p) {
+        if (sc.epoch >= 0xffffu) {  // epochs wrap: clear the status words once
+            k_clear_u64<<<dim3(unsigned((sc.look_tiles * 256 + 255) / 256)), dim3(256), 0, s>>>(
+                sc.look, sc.look_tiles * 256);
+            sc.epoch = 0;
+        }
+        const uint32_t ep = ++sc.epoch;
+        k_sort_pass<K><<<dim3(unsigned(tiles)), dim3(kSortThreads), 0, s>>>(ki, vi, ko, vo, n, 8 * p,
+                                                                            sc.dbase + p * 256, sc.look,
+                                                                            sc.ctr + p, ep);
+        K* kt = ki;
+        ki = ko;
+        ko = kt;
+        vi = vo;
+        vo = (vo == vA) ? vB : vA;
+    }
+    *kout = ki;
+    *vout = vi;
+    return hipGetLastError();
+}
+
+template hipError_t radix_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, int, bool,
+                                         SortScratch&, hipStream_t, uint32_t**, uint32_t**);
+template hipError_t radix_sort<uint64_t>(uint64_t*, uint64_t*, uint32_t*, uint32_t*, int64_t, int, bool,
+                                         SortScratch&, hipStream_t, uint64_t**, uint32_t**);
+
+}  // namespace gs

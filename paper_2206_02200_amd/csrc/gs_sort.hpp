@@ -1,0 +1,47 @@
+// Stable LSD radix sort of (key, index) pairs for gfx950 (host interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+constexpr int kSortThreads = 256;                        // 4 waves
+constexpr int kSortItems = 16;                           // keys per thread
+constexpr int kSortTile = kSortThreads * kSortItems;     // 4096 keys per tile
+constexpr int kSortMaxPasses = 8;                        // 8-bit digits, up to 64 bits
+
+struct SortScratch {
+    uint32_t* hist = nullptr;   // [kSortMaxPasses][256] digit histograms
+    uint32_t* dbase = nullptr;  // [kSortMaxPasses][256] exclusive digit bases
+    uint32_t* ctr = nullptr;    // [kSortMaxPasses] tile counters
+    uint64_t* look = nullptr;   // [tiles][256] look-back status words
+    int64_t look_tiles = 0;     // capacity of `look` in tiles
+    uint32_t epoch = 0;         // last epoch used in `look`
+};
+
+inline int sort_passes(int bits) { return (bits + 7) / 8; }
+
+// Bytes of look-back storage needed for n keys.
+inline int64_t sort_look_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+// Sort n pairs by the low `bits` bits of the key, stably.  The keys are in
+// kA; the values are implicitly 0..n-1.  kB, vA, vB are ping-pong buffers of
+// n entries.  If `hist_ready`, sc.hist already holds the digit histograms of
+// kA for every pass (computed by the key producer).  On return *kout/*vout
+// point at the sorted keys and the permutation (inside kA/kB, vA/vB).
+template <typename K>
+hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int bits, bool hist_ready,
+                      SortScratch& sc, hipStream_t s, K** kout, uint32_t** vout);
+
+// Per-pass digit histogram accumulation for a key (device helper used by
+// producers that compute keys and histograms in one pass).
+template <typename K>
+__device__ __forceinline__ void sort_hist_add(uint32_t* lds_hist, K key, int npasses) {
+    for (int p = 0; p < npasses; ++p) {
+        const uint32_t dgt = uint32_t(key >> (8 * p)) & 255u;
+        atomicAdd(&lds_hist[p * 256 + dgt], 1u);
+    }
+}
+
+}  // namespace gs

@@ -1,0 +1,225 @@
+"""Python binding of the GridShift HIP library (``libgridshift.so``).
+
+Argument marshalling only: every step of the fit runs in the library's
+kernels on the GPU.  PyTorch supplies device memory (tensors) and the stream
+(``torch.cuda.current_stream()``).  The C ABI is declared in
+``include/gridshift.h``; the method is GridShift (arXiv 2206.02200,
+Section 2.1, Algorithm 1, parallel update Eq. 6).
+
+If the library has not been built, every call raises ``RuntimeError``: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgridshift.so")
+
+GS_F32, GS_F64 = 0, 1
+CONVERGED, STATIONARY, CAPPED = 1, 2, 4
+STATUS = {
+    0: "GS_OK", 1: "GS_ERR_INVALID_ARG", 2: "GS_ERR_NONFINITE", 3: "GS_ERR_KEY_RANGE",
+    4: "GS_ERR_ALLOC", 5: "GS_ERR_DEVICE", 6: "GS_ERR_UNSUPPORTED", 7: "GS_ERR_STATE",
+}
+EXPORTED = [
+    "gs_abi_version", "gs_last_error", "gs_context_create", "gs_context_destroy",
+    "gs_fit", "gs_fit_batched", "gs_copy_modes", "gs_copy_keys",
+]
+
+
+class GridShiftError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("n_points", ctypes.c_int64),
+        ("n_cells0", ctypes.c_int64),
+        ("n_clusters", ctypes.c_int64),
+        ("n_iter", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(
+                f"GridShift HIP library not found at {path}; build it with "
+                "`python paper_2206_02200_amd/build.py` (no CPU fallback exists)")
+        lib = ctypes.CDLL(path)
+        V, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        lib.gs_abi_version.restype = I32
+        lib.gs_last_error.restype = ctypes.c_char_p
+        lib.gs_context_create.argtypes = [ctypes.POINTER(V)]
+        lib.gs_context_create.restype = ctypes.c_int
+        lib.gs_context_destroy.argtypes = [V]
+        lib.gs_context_destroy.restype = None
+        lib.gs_fit.argtypes = [V, V, ctypes.c_int, I64, I32, I64, D, I32, V, ctypes.POINTER(Info), V]
+        lib.gs_fit.restype = ctypes.c_int
+        lib.gs_fit_batched.argtypes = [V, V, ctypes.c_int, I32, I64, I32, V, V, I32, V, V, V]
+        lib.gs_fit_batched.restype = ctypes.c_int
+        lib.gs_copy_modes.argtypes = [V, V, V, V, V]
+        lib.gs_copy_modes.restype = ctypes.c_int
+        lib.gs_copy_keys.argtypes = [V, V, V]
+        lib.gs_copy_keys.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise GridShiftError(rc, _lib.gs_last_error().decode())
+
+
+class Context:
+    """Owns a ``gs_context`` (device scratch memory reused across fits)."""
+
+    def __init__(self, device: int | None = None):
+        lib = load_library()
+        self.device = torch.cuda.current_device() if device is None else device
+        with torch.cuda.device(self.device):
+            h = ctypes.c_void_p()
+            _check(lib.gs_context_create(ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            _lib.gs_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts: dict[int, Context] = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    dev = torch.cuda.current_device() if device is None else device
+    ctx = _contexts.get(dev)
+    if ctx is None:
+        ctx = Context(dev)
+        _contexts[dev] = ctx
+    return ctx
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _points(x: torch.Tensor) -> tuple[torch.Tensor, int, int]:
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError("points must be a CUDA (HIP) tensor")
+    if x.dim() != 2:
+        raise ValueError("points must be [n, d]")
+    if x.dtype == torch.float32:
+        dt = GS_F32
+    elif x.dtype == torch.float64:
+        dt = GS_F64
+    else:
+        raise TypeError("points must be float32 or float64")
+    if x.stride(1) != 1:
+        x = x.contiguous()
+    ld = x.stride(0) if x.shape[0] > 1 else x.shape[1]
+    return x, dt, max(ld, x.shape[1])
+
+
+@dataclass
+class FitResult:
+    labels: torch.Tensor  # int32 [n]
+    modes: torch.Tensor  # float64 [K, d]
+    counts: torch.Tensor  # int64 [K]
+    info: dict
+    sums: torch.Tensor | None = None  # float64 [K, d]
+    keys: torch.Tensor | None = None  # int64 [K, d]
+
+
+def fit(x: torch.Tensor, h: float, max_iter: int = 100, *, with_sums: bool = False, with_keys: bool = False,
+        ctx: Context | None = None, stream=None) -> FitResult:
+    """GridShift of one point set ``x`` ([n, d] float32/float64 on the GPU)."""
+    lib = load_library()
+    x, dt, ld = _points(x)
+    n, d = x.shape
+    ctx = ctx or default_context(x.device.index)
+    sp = _stream_ptr(stream)
+    labels = torch.empty(n, dtype=torch.int32, device=x.device)
+    info = Info()
+    _check(lib.gs_fit(ctx.handle, ctypes.c_void_p(x.data_ptr()), dt, n, d, ld, float(h), int(max_iter),
+                      ctypes.c_void_p(labels.data_ptr()), ctypes.byref(info), sp))
+    K = info.n_clusters
+    modes = torch.empty((K, d), dtype=torch.float64, device=x.device)
+    counts = torch.empty(K, dtype=torch.int64, device=x.device)
+    sums = torch.empty((K, d), dtype=torch.float64, device=x.device) if with_sums else None
+    _check(lib.gs_copy_modes(ctx.handle, ctypes.c_void_p(modes.data_ptr()), ctypes.c_void_p(counts.data_ptr()),
+                             ctypes.c_void_p(sums.data_ptr() if sums is not None else 0), sp))
+    keys = None
+    if with_keys:
+        keys = torch.empty((K, d), dtype=torch.int64, device=x.device)
+        _check(lib.gs_copy_keys(ctx.handle, ctypes.c_void_p(keys.data_ptr()), sp))
+    return FitResult(labels, modes, counts, info.as_dict(), sums, keys)
+
+
+@dataclass
+class BatchedResult:
+    labels: torch.Tensor  # int32 [N], per-instance ids
+    modes: torch.Tensor  # float64 [sum K, d]
+    counts: torch.Tensor  # int64 [sum K]
+    k_offsets: np.ndarray  # int64 [B+1]
+    infos: list
+    sums: torch.Tensor | None = None
+
+
+def fit_batched(x: torch.Tensor, offsets, h, max_iter: int = 100, *, with_sums: bool = False,
+                ctx: Context | None = None, stream=None) -> BatchedResult:
+    """GridShift of B independent point sets concatenated in ``x``; instance b
+    owns rows offsets[b]..offsets[b+1]-1 and uses bandwidth h[b]."""
+    lib = load_library()
+    x, dt, ld = _points(x)
+    d = x.shape[1]
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    B = off.size - 1
+    hs = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (B,)))
+    if off[-1] != x.shape[0]:
+        raise ValueError("offsets[-1] must equal the number of rows")
+    ctx = ctx or default_context(x.device.index)
+    sp = _stream_ptr(stream)
+    labels = torch.empty(x.shape[0], dtype=torch.int32, device=x.device)
+    infos = (Info * B)()
+    _check(lib.gs_fit_batched(ctx.handle, ctypes.c_void_p(x.data_ptr()), dt, d, ld, B,
+                              off.ctypes.data_as(ctypes.c_void_p), hs.ctypes.data_as(ctypes.c_void_p), int(max_iter),
+                              ctypes.c_void_p(labels.data_ptr()), ctypes.cast(infos, ctypes.c_void_p), sp))
+    ks = np.array([infos[b].n_clusters for b in range(B)], dtype=np.int64)
+    koff = np.concatenate([[0], np.cumsum(ks)]).astype(np.int64)
+    tot = int(koff[-1])
+    modes = torch.empty((tot, d), dtype=torch.float64, device=x.device)
+    counts = torch.empty(tot, dtype=torch.int64, device=x.device)
+    sums = torch.empty((tot, d), dtype=torch.float64, device=x.device) if with_sums else None
+    _check(lib.gs_copy_modes(ctx.handle, ctypes.c_void_p(modes.data_ptr()), ctypes.c_void_p(counts.data_ptr()),
+                             ctypes.c_void_p(sums.data_ptr() if sums is not None else 0), sp))
+    return BatchedResult(labels, modes, counts, koff, [infos[b].as_dict() for b in range(B)], sums)

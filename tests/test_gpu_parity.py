@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar: labels, counts, K, round count, flags and integer keys bit-exact; cell
+sums and modes bit-exact as well (both sides run the same binary64
+operations in the same order), which is stricter than the 1e-12 relative
+tolerance the modes are specified to.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import gs_oracle  # noqa: E402
+from paper_2206_02200_amd import gridshift, synth  # noqa: E402
+
+DEV = torch.device("cuda:0")
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))["examples"]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _bits(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64)).view(np.uint64)
+
+
+def _gpu(x_np, h, max_iter=100, dtype=None):
+    x = torch.from_numpy(np.ascontiguousarray(x_np)).to(DEV)
+    if dtype is not None:
+        x = x.to(dtype)
+    r = gridshift.fit(x, h, max_iter, with_sums=True, with_keys=True)
+    torch.cuda.synchronize()
+    return r
+
+
+def assert_parity(x_np, h, max_iter=100, what=""):
+    """Run both sides on the same bytes and compare everything."""
+    _say(f"parity case {what}: n={x_np.shape[0]} d={x_np.shape[1]} dtype={x_np.dtype} h={h} max_iter={max_iter}")
+    g = _gpu(x_np, h, max_iter)
+    o = gs_oracle.fit(x_np.astype(np.float64), h, max_iter)
+    info = g.info
+    assert info["n_clusters"] == o.K, what
+    assert info["n_iter"] == o.n_iter, what
+    assert info["flags"] == o.flags, what
+    assert info["n_cells0"] == o.m_hist[0], what
+    np.testing.assert_array_equal(g.labels.cpu().numpy(), o.labels, err_msg=what)
+    np.testing.assert_array_equal(g.counts.cpu().numpy(), o.counts, err_msg=what)
+    np.testing.assert_array_equal(g.keys.cpu().numpy(), o.keys, err_msg=what)
+    np.testing.assert_array_equal(_bits(g.sums.cpu().numpy()), _bits(o.sums), err_msg=what)
+    np.testing.assert_array_equal(_bits(g.modes.cpu().numpy()), _bits(o.modes), err_msg=what)
+    return g, o
+
+
+def _blobs(seed, n, d, k=8, scale=5.0, spread=12.0):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0, spread * scale, size=(k, d))
+    lab = rng.integers(0, k, size=n)
+    return c[lab] + scale * 0.8 * rng.standard_normal(size=(n, d))
+
+
+# ---------------------------------------------------------------------------
+# worked examples
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ex", GOLDEN, ids=[e["name"] for e in GOLDEN])
+def test_worked_examples_round_by_round(ex):
+    x = np.array(ex["x"], dtype=np.float64)
+    for t, state in enumerate(ex["states"]):
+        g = _gpu(x, ex["h"], max_iter=t)
+        assert g.keys.cpu().numpy().tolist() == [s[0] for s in state], f"round {t}"
+        assert g.counts.cpu().numpy().tolist() == [s[1] for s in state], f"round {t}"
+        np.testing.assert_array_equal(_bits(g.sums.cpu().numpy()), _bits([s[2] for s in state]))
+    if "labels" in ex:
+        g = _gpu(x, ex["h"])
+        assert g.labels.cpu().numpy().tolist() == ex["labels"]
+        np.testing.assert_array_equal(_bits(g.modes.cpu().numpy()), _bits(ex["modes"]))
+        assert g.info["n_iter"] == ex["n_iter"] and g.info["flags"] == ex["flags"]
+
+
+# ---------------------------------------------------------------------------
+# random inputs: every d, both dtypes, ragged sizes spanning several tiles
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("n", [1, 37, 4097, 20011])
+def test_random_blobs_f64(d, n):
+    x = _blobs(1000 + 7 * d + n, n, d)
+    assert_parity(x, 4.0, 100, f"blobs f64 d={d} n={n}")
+
+
+@pytest.mark.parametrize("d", [2, 3, 5])
+def test_random_blobs_f32(d):
+    x = _blobs(2000 + d, 30000, d).astype(np.float32)
+    assert_parity(x, 3.0, 100, f"blobs f32 d={d}")
+
+
+@pytest.mark.parametrize("t", [0, 1, 2, 3, 5])
+def test_state_after_each_round(t):
+    x = _blobs(3001, 8000, 3)
+    assert_parity(x, 2.5, t, f"max_iter={t}")
+
+
+def test_many_cells_uses_wide_rounds():
+    # m0 well above one tail workgroup's capacity: wide rounds, then the tail
+    x = _blobs(3002, 150000, 3, k=30, scale=8.0, spread=20.0)
+    g, o = assert_parity(x, 1.0, 100, "wide rounds")
+    assert o.m_hist[0] > 4096
+
+
+def test_wide_rounds_hit_the_cap():
+    x = _blobs(3003, 60000, 2, k=20, scale=6.0, spread=30.0)
+    assert_parity(x, 0.5, 2, "wide rounds capped")
+
+
+def test_voronoi_image_rgb_f64():
+    w = synth.image_rgb_f64()
+    assert_parity(w.x, w.h, w.max_iter, w.name)
+
+
+def test_voronoi_1080p_xylab_f32_full_size():
+    w = synth.image_xylab_f32()
+    assert_parity(w.x, w.h, w.max_iter, w.name)
+
+
+def test_gmm_d4_f32():
+    w = synth.gmm_f32(200000, 4, seed=44)
+    assert_parity(w.x, w.h, w.max_iter, w.name)
+
+
+# ---------------------------------------------------------------------------
+# degenerate inputs and errors
+# ---------------------------------------------------------------------------
+def test_empty_input():
+    g = _gpu(np.zeros((0, 3)), 1.0)
+    assert g.info["n_clusters"] == 0 and g.labels.numel() == 0 and g.modes.shape == (0, 3)
+
+
+def test_identical_points():
+    assert_parity(np.full((5000, 4), -3.25), 0.5, 100, "identical")
+
+
+def test_negative_and_boundary_coordinates():
+    rng = np.random.default_rng(5)
+    x = rng.integers(-40, 40, size=(3000, 2)).astype(np.float64) * 0.5  # many exact boundaries
+    assert_parity(x, 0.5, 100, "boundaries")
+
+
+def test_strided_rows():
+    x = _blobs(3004, 5000, 6)
+    t = torch.from_numpy(x).to(DEV)
+    view = t[:, :4]  # ld = 6 > d = 4
+    r = gridshift.fit(view, 4.0, 100, with_sums=True)
+    o = gs_oracle.fit(x[:, :4], 4.0, 100)
+    np.testing.assert_array_equal(r.labels.cpu().numpy(), o.labels)
+    np.testing.assert_array_equal(_bits(r.sums.cpu().numpy()), _bits(o.sums))
+
+
+def test_errors():
+    with pytest.raises(gridshift.GridShiftError) as e:
+        _gpu(np.array([[np.nan, 1.0]]), 1.0)
+    assert e.value.code == 2
+    with pytest.raises(gridshift.GridShiftError) as e:
+        _gpu(np.ones((3, 2)), 0.0)
+    assert e.value.code == 1
+    with pytest.raises(gridshift.GridShiftError) as e:
+        _gpu(np.ones((3, 7)), 1.0)
+    assert e.value.code == 6
+    with pytest.raises(gridshift.GridShiftError) as e:
+        _gpu(np.array([[1e300]]), 1e-300)
+    assert e.value.code == 3
+    # the context still works after errors
+    assert_parity(_blobs(3005, 500, 2), 2.0, 100, "after errors")
+
+
+def test_deterministic_repeat():
+    x = torch.from_numpy(_blobs(3006, 100000, 5).astype(np.float32)).to(DEV)
+    a = gridshift.fit(x, 3.0, 100, with_sums=True)
+    b = gridshift.fit(x, 3.0, 100, with_sums=True)
+    assert torch.equal(a.labels, b.labels) and torch.equal(a.counts, b.counts)
+    assert torch.equal(a.sums.view(torch.int64), b.sums.view(torch.int64))
+
+
+# ---------------------------------------------------------------------------
+# batched form: bitwise equal to the plain form per instance
+# ---------------------------------------------------------------------------
+def test_batched_equals_plain_and_oracle():
+    rng = np.random.default_rng(77)
+    sizes = [0, 1, 500, 12000, 3, 40000, 2048]
+    xs = [_blobs(4000 + i, s, 3) for i, s in enumerate(sizes)]
+    hs = [float(rng.choice([1.5, 2.0, 3.0])) for _ in sizes]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    X = torch.from_numpy(np.concatenate(xs, axis=0)).to(DEV)
+    br = gridshift.fit_batched(X, off, hs, 100, with_sums=True)
+    labels = br.labels.cpu().numpy()
+    sums = br.sums.cpu().numpy()
+    counts = br.counts.cpu().numpy()
+    for b, (x, h) in enumerate(zip(xs, hs)):
+        _say(f"batched instance {b}: n={len(x)} h={h}")
+        o = gs_oracle.fit(x, h, 100)
+        ko = slice(br.k_offsets[b], br.k_offsets[b + 1])
+        assert br.infos[b]["n_clusters"] == o.K
+        assert br.infos[b]["n_iter"] == o.n_iter and br.infos[b]["flags"] == o.flags
+        np.testing.assert_array_equal(labels[off[b]:off[b + 1]], o.labels)
+        np.testing.assert_array_equal(counts[ko], o.counts)
+        np.testing.assert_array_equal(_bits(sums[ko]), _bits(o.sums))
+
+
+def test_batched_with_wide_instances():
+    sizes = [150000, 700, 90000]
+    xs = [_blobs(4100 + i, s, 3, k=30, scale=8.0, spread=20.0) for i, s in enumerate(sizes)]
+    hs = [1.0, 2.0, 1.25]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    X = torch.from_numpy(np.concatenate(xs, axis=0).astype(np.float32)).to(DEV)
+    br = gridshift.fit_batched(X, off, hs, 100, with_sums=True)
+    labels = br.labels.cpu().numpy()
+    sums = br.sums.cpu().numpy()
+    for b, (x, h) in enumerate(zip(xs, hs)):
+        _say(f"batched wide instance {b}: n={len(x)} h={h}")
+        o = gs_oracle.fit(x.astype(np.float32).astype(np.float64), h, 100)
+        ko = slice(br.k_offsets[b], br.k_offsets[b + 1])
+        assert br.infos[b]["n_clusters"] == o.K and br.infos[b]["n_iter"] == o.n_iter
+        np.testing.assert_array_equal(labels[off[b]:off[b + 1]], o.labels)
+        np.testing.assert_array_equal(_bits(sums[ko]), _bits(o.sums))
