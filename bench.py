@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Benchmark of the GridShift hot path on one MI355X.
+
+Workload: the plain fit of a synthetic 1920x1080 Voronoi image (40 regions,
+colour ramps, noise sigma 6) with features (0.25x, 0.25y, L*, a*, b*) as
+float32 (d = 5, n = 2,073,600), h = 16, at most 100 rounds.  Inputs are
+resident in HBM before the timed region; one step is one complete gs_fit
+(binning, every shift/merge round, labels) plus the mode copy.
+
+Prints one JSON line with points/s, the roofline of the dominant kernel
+(algorithmic bytes per launch over its HIP-event-timed average duration) and
+the FP64 oracle timed on the host cores as the CPU baseline.
+
+  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "points/sec + HBM GB/s: GridShift 1080p d=5 plain vs batched vs fwd+bwd"
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(w, seconds: float) -> dict:
+    """The FP64 oracle (single-threaded C) on the same image, repeated for a
+    bounded wall time."""
+    import numpy as np
+
+    from oracle import gs_oracle
+
+    xd = w.x.astype(np.float64)
+    runs = 0
+    t0 = time.perf_counter()
+    while True:
+        gs_oracle.fit(xd, w.h, w.max_iter)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {
+        "value": runs * len(xd) / el,
+        "unit": "points/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{runs} full fits of the same {len(xd)}-point image in {el:.1f} s "
+                  f"(single thread; host: {os.cpu_count()} logical CPUs, {cpu_model()})",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the GridShift fit here runs on a single MI355X; "
+              "run it with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2206_02200_amd import gridshift, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.image_xylab_f32()
+    n, d = w.x.shape
+    x = torch.from_numpy(w.x).to(dev)
+    ctx = gridshift.Context(0)
+
+    def step():
+        return gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
+
+    for _ in range(max(1, args.warmup)):
+        r = step()
+    torch.cuda.synchronize()
+    info = r.info
+
+    # every kernel timed over a few untimed steps: per-kernel split
+    ctx.profile("")
+    ctx.profile_reset()
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    full = ctx.profile_table()
+    ctx.profile(None)
+    dominant = max(full, key=lambda k: full[k]["ms"])
+
+    # timed region: HIP events around the dominant kernel's launches only
+    ctx.profile_reset()
+    ctx.profile(dominant)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile(None)
+    dom = ctx.profile_table()[dominant]
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms_per_step * 1e-3)
+    avg_ms = dom["ms"] / dom["launches"]
+    bytes_per_launch = dom["bytes"] / dom["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    s_in = w.x.dtype.itemsize
+    k = info["n_clusters"]
+    # point-level algorithmic bytes of the whole fit: read x once, write and
+    # read the point->cell map, write labels; plus the first round's cell table
+    b_alg = n * (d * s_in + 12) + 2 * info["n_cells0"] * (16 + 8 * d) + k * (8 * d + 8)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain GridShift, 1920x1080 Voronoi image (40 regions, ramps, sigma 6), "
+                        "features (0.25x, 0.25y, L, a, b) float32, d=5, h=16, max_iter=100",
+            "n": n, "d": d, "h": w.h, "max_iter": w.max_iter, "input_dtype": "f32",
+            "cells0": info["n_cells0"], "clusters": k, "rounds": info["n_iter"], "flags": info["flags"],
+        },
+        "hbm_GBps_step_alg": b_alg / (ms_per_step * 1e-3) / 1e9,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dominant,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": None,
+            "avg_launch_us": avg_ms * 1e3,
+            "alg_bytes_per_launch": bytes_per_launch,
+        },
+        "kernels_ms_per_step": {kk: vv["ms"] / 3 for kk, vv in sorted(full.items(), key=lambda t: -t[1]["ms"])},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -138,6 +138,22 @@ gs_status gs_copy_modes(gs_context* ctx, double* modes, int64_t* counts, double*
 /* Integer cell keys floor(.) of the last fit's clusters: device int64 [sum K][d]. */
 gs_status gs_copy_keys(gs_context* ctx, int64_t* keys, void* stream);
 
+/*
+ * Kernel timing (instrumentation, not part of the method).  When enabled,
+ * every kernel launch of later fits whose name starts with `prefix` is
+ * bracketed by HIP events on the launch stream; the elapsed times, launch
+ * counts and the algorithmic bytes each launch had to move (its inputs read
+ * once and its outputs written once) accumulate per kernel name until
+ * gs_profile_reset.  prefix NULL disables timing; "" times every kernel.
+ */
+gs_status gs_profile_enable(gs_context* ctx, const char* prefix);
+gs_status gs_profile_reset(gs_context* ctx);
+/* Number of kernel names with accumulated timings. */
+int32_t gs_profile_count(const gs_context* ctx);
+/* Entry i: *name stays valid until gs_profile_reset / gs_context_destroy. */
+gs_status gs_profile_entry(const gs_context* ctx, int32_t i, const char** name, double* total_ms, int64_t* launches,
+                           double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

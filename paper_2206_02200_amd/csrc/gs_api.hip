@@ -30,6 +30,24 @@ struct DBuf {
     size_t cap = 0;
 };
 
+// Optional per-kernel timing with HIP events on the launch stream.  Only
+// kernels whose name starts with `filter` are timed.
+struct Profiler {
+    bool on = false;
+    std::string filter;
+    std::vector<hipEvent_t> ev;
+    size_t next = 0;
+    struct Rec {
+        int id;
+        size_t e0, e1;
+        double bytes;
+    };
+    std::vector<Rec> recs;
+    std::vector<std::string> names;
+    std::vector<double> ms, bytes;
+    std::vector<int64_t> launches;
+};
+
 }  // namespace
 
 struct gs_context {
@@ -40,7 +58,8 @@ struct gs_context {
     DBuf tkey[2], tcnt[2], tsum[2], tinst[2], tstart[2], tlen[2], tfirst[2], tnch[2], tchoff[2];
     DBuf kappa, pbuf, gmap, cur, tmap, part, partc, hk, hv, ckA, ckB, cvA, cvB;
     // instances
-    DBuf param, state, rowoff, hs, bbox, koff;
+    DBuf param, state, rowoff, hs, bbox, koff, tiles, tileoff, bpart;
+    int64_t ntiles = 0;
     // scans and sorts
     DBuf counters, look, tilectr, shist, sdbase, sctr, slook;
     gs::SortScratch sort;
@@ -53,6 +72,7 @@ struct gs_context {
     int64_t capM = 0;
     std::vector<gs::InstState> st;
     std::vector<gs::InstParam> prm;
+    Profiler prof;
 };
 
 namespace {
@@ -88,6 +108,68 @@ inline unsigned blocks_for(int64_t n, int threads) {
     return n <= 0 ? 1u : unsigned((n + threads - 1) / threads);
 }
 
+int prof_begin(gs_context* c, hipStream_t s, const char* name) {
+    Profiler& p = c->prof;
+    if (!p.on || std::strncmp(name, p.filter.c_str(), p.filter.size()) != 0) return -1;
+    int id = -1;
+    for (size_t i = 0; i < p.names.size(); ++i)
+        if (p.names[i] == name) id = int(i);
+    if (id < 0) {
+        id = int(p.names.size());
+        p.names.emplace_back(name);
+        p.ms.push_back(0.0);
+        p.bytes.push_back(0.0);
+        p.launches.push_back(0);
+    }
+    while (p.ev.size() < p.next + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        p.ev.push_back(e);
+    }
+    const size_t e0 = p.next++, e1 = p.next++;
+    if (hipEventRecord(p.ev[e0], s) != hipSuccess) return -1;
+    p.recs.push_back({id, e0, e1, 0.0});
+    return int(p.recs.size() - 1);
+}
+
+void prof_end(gs_context* c, hipStream_t s, int tok, double bytes) {
+    if (tok < 0) return;
+    Profiler& p = c->prof;
+    (void)hipEventRecord(p.ev[p.recs[tok].e1], s);
+    p.recs[tok].bytes = bytes;
+}
+
+// Accumulate the recorded intervals (the stream has been synchronised).
+void prof_flush(gs_context* c, bool keep) {
+    Profiler& p = c->prof;
+    if (keep) {
+        for (const Profiler::Rec& r : p.recs) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p.ev[r.e0], p.ev[r.e1]) == hipSuccess) {
+                p.ms[r.id] += ms;
+                p.bytes[r.id] += r.bytes;
+                p.launches[r.id] += 1;
+            }
+        }
+    }
+    p.recs.clear();
+    p.next = 0;
+}
+
+int sort_prof_begin(void* ctx, hipStream_t s, const char* name) {
+    return prof_begin(static_cast<gs_context*>(ctx), s, name);
+}
+void sort_prof_end(void* ctx, hipStream_t s, int tok, double bytes) {
+    prof_end(static_cast<gs_context*>(ctx), s, tok, bytes);
+}
+
+#define PROF_LAUNCH(name, nbytes, ...)                 \
+    do {                                              \
+        const int tk_ = prof_begin(c, s, name);       \
+        __VA_ARGS__;                                  \
+        prof_end(c, s, tk_, double(nbytes));          \
+    } while (0)
+
 gs_status pinned_ensure(gs_context* c, size_t bytes) {
     if (c->pinned_cap >= bytes) return GS_OK;
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -107,6 +189,47 @@ gs_status d2h(gs_context* c, void* dst, const void* src, size_t bytes, hipStream
     GS_HIP(hipMemcpyAsync(c->pinned, src, bytes, hipMemcpyDeviceToHost, s));
     GS_HIP(hipStreamSynchronize(s));
     std::memcpy(dst, c->pinned, bytes);
+    return GS_OK;
+}
+
+struct Xfer {
+    void* dev;
+    const void* host;
+    size_t bytes;
+};
+
+// Several host -> device copies through one staging pass and one wait.
+gs_status h2d_batch(gs_context* c, const std::vector<Xfer>& xs, hipStream_t s) {
+    size_t total = 0;
+    for (const Xfer& x : xs) total += (x.bytes + 255) & ~size_t(255);
+    GS_TRY(pinned_ensure(c, total));
+    GS_HIP(hipStreamSynchronize(s));
+    size_t off = 0;
+    for (const Xfer& x : xs) {
+        std::memcpy(static_cast<char*>(c->pinned) + off, x.host, x.bytes);
+        GS_HIP(hipMemcpyAsync(x.dev, static_cast<char*>(c->pinned) + off, x.bytes, hipMemcpyHostToDevice, s));
+        off += (x.bytes + 255) & ~size_t(255);
+    }
+    GS_HIP(hipStreamSynchronize(s));
+    return GS_OK;
+}
+
+// Several device -> host copies with one wait.
+gs_status d2h_batch(gs_context* c, const std::vector<Xfer>& xs, hipStream_t s) {
+    size_t total = 0;
+    for (const Xfer& x : xs) total += (x.bytes + 255) & ~size_t(255);
+    GS_TRY(pinned_ensure(c, total));
+    size_t off = 0;
+    for (const Xfer& x : xs) {
+        GS_HIP(hipMemcpyAsync(static_cast<char*>(c->pinned) + off, x.host, x.bytes, hipMemcpyDeviceToHost, s));
+        off += (x.bytes + 255) & ~size_t(255);
+    }
+    GS_HIP(hipStreamSynchronize(s));
+    off = 0;
+    for (const Xfer& x : xs) {
+        std::memcpy(x.dev, static_cast<char*>(c->pinned) + off, x.bytes);
+        off += (x.bytes + 255) & ~size_t(255);
+    }
     return GS_OK;
 }
 
@@ -153,12 +276,14 @@ gs_status scan_prepare(gs_context* c, int64_t n_bound, hipStream_t s, uint32_t* 
 }
 
 template <class Op>
-gs_status run_scan(gs_context* c, Op op, const int64_t* n_dev, int64_t n_bound, int64_t* total_dev, hipStream_t s) {
+gs_status run_scan(gs_context* c, Op op, const int64_t* n_dev, int64_t n_bound, int64_t* total_dev, hipStream_t s,
+                   const char* name, double nbytes) {
     uint32_t epoch = 0;
     GS_TRY(scan_prepare(c, n_bound, s, &epoch));
     const int64_t tiles = std::max<int64_t>(1, (n_bound + gs::kScanTile - 1) / gs::kScanTile);
-    gs::k_scan<Op><<<unsigned(tiles), gs::kScanThreads, 0, s>>>(op, n_dev, P<uint64_t>(c->look),
-                                                                P<uint32_t>(c->tilectr), epoch, total_dev);
+    PROF_LAUNCH(name, nbytes,
+                gs::k_scan<Op><<<unsigned(tiles), gs::kScanThreads, 0, s>>>(op, n_dev, P<uint64_t>(c->look),
+                                                                            P<uint32_t>(c->tilectr), epoch, total_dev));
     GS_HIP(hipGetLastError());
     return GS_OK;
 }
@@ -180,37 +305,45 @@ gs::CellTable table(gs_context* c, int i) {
 
 // Canonical sums R of every cell's members (cells [0, m) of t, m on device).
 template <int D, class Src>
-gs_status segsum_d(gs_context* c, Src src, gs::CellTable t, int64_t m_bound, int64_t npos, hipStream_t s) {
+gs_status segsum_d(gs_context* c, Src src, gs::CellTable t, int64_t m_bound, int64_t npos, hipStream_t s,
+                   double member_bytes) {
     int64_t* ctr = P<int64_t>(c->counters);
-    GS_TRY(run_scan(c, gs::ExclOp{t.nch, t.choff}, ctr + 0, m_bound, ctr + 1, s));
+    GS_TRY(run_scan(c, gs::ExclOp{t.nch, t.choff}, ctr + 0, m_bound, ctr + 1, s, "scan_chunks", 8.0 * m_bound));
     const int64_t tasks_bound = npos / gs::kChunk + m_bound + 1;
     GS_TRY(ensure(c->part, size_t(tasks_bound) * D * sizeof(double)));
     GS_TRY(ensure(c->partc, size_t(tasks_bound) * sizeof(int64_t)));
-    gs::k_segsum_chunks<D, Src><<<blocks_for(tasks_bound * gs::kWave, gs::kSegThreads), gs::kSegThreads, 0, s>>>(
-        src, t, ctr + 0, ctr + 1, P<double>(c->part), P<int64_t>(c->partc), tasks_bound);
-    gs::k_segsum_levels<D><<<blocks_for(m_bound * gs::kWave, gs::kSegThreads), gs::kSegThreads, 0, s>>>(
-        t, ctr + 0, P<double>(c->part), P<int64_t>(c->partc), tasks_bound);
+    // members are read once (index + value); every cell row is written once
+    PROF_LAUNCH("segsum_chunks", npos * member_bytes + m_bound * (8.0 * D + 8.0),
+                gs::k_segsum_chunks<D, Src><<<blocks_for(tasks_bound * gs::kWave, gs::kSegThreads), gs::kSegThreads,
+                                              0, s>>>(src, t, ctr + 0, ctr + 1, P<double>(c->part),
+                                                      P<int64_t>(c->partc), tasks_bound));
+    PROF_LAUNCH("segsum_levels", 0.0,
+                gs::k_segsum_levels<D><<<blocks_for(m_bound * gs::kWave, gs::kSegThreads), gs::kSegThreads, 0, s>>>(
+                    t, ctr + 0, P<double>(c->part), P<int64_t>(c->partc), tasks_bound));
     GS_HIP(hipGetLastError());
     return GS_OK;
 }
 
 template <class Src>
-gs_status segsum(gs_context* c, int d, Src src, gs::CellTable t, int64_t m_bound, int64_t npos, hipStream_t s) {
+gs_status segsum(gs_context* c, int d, Src src, gs::CellTable t, int64_t m_bound, int64_t npos, hipStream_t s,
+                 double member_bytes) {
     switch (d) {
-        case 1: return segsum_d<1>(c, src, t, m_bound, npos, s);
-        case 2: return segsum_d<2>(c, src, t, m_bound, npos, s);
-        case 3: return segsum_d<3>(c, src, t, m_bound, npos, s);
-        case 4: return segsum_d<4>(c, src, t, m_bound, npos, s);
-        case 5: return segsum_d<5>(c, src, t, m_bound, npos, s);
-        case 6: return segsum_d<6>(c, src, t, m_bound, npos, s);
+        case 1: return segsum_d<1>(c, src, t, m_bound, npos, s, member_bytes);
+        case 2: return segsum_d<2>(c, src, t, m_bound, npos, s, member_bytes);
+        case 3: return segsum_d<3>(c, src, t, m_bound, npos, s, member_bytes);
+        case 4: return segsum_d<4>(c, src, t, m_bound, npos, s, member_bytes);
+        case 5: return segsum_d<5>(c, src, t, m_bound, npos, s, member_bytes);
+        case 6: return segsum_d<6>(c, src, t, m_bound, npos, s, member_bytes);
     }
     return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
 }
 
-gs_status launch_shift(int d, gs::CellTable t, int64_t m, const gs::InstParam* prm, gs::InstState* st,
+gs_status launch_shift(gs_context* c, int d, gs::CellTable t, int64_t m, const gs::InstParam* prm, gs::InstState* st,
                        const uint64_t* hk, const uint32_t* hv, int logcap, double* pbuf, uint64_t* kappa,
                        hipStream_t s) {
-    const unsigned g = blocks_for(m, 256);
+    const unsigned g = blocks_for(m, gs::kShiftWaves);  // one wave per cell
+    // reads every cell row once, writes p and the landing key
+    const int tk = prof_begin(c, s, "shift");
     switch (d) {
         case 1: gs::k_shift<1><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
         case 2: gs::k_shift<2><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
@@ -220,12 +353,14 @@ gs_status launch_shift(int d, gs::CellTable t, int64_t m, const gs::InstParam* p
         case 6: gs::k_shift<6><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
         default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
     }
+    prof_end(c, s, tk, double(m) * (8.0 + 8.0 + 4.0 + 8.0 * d) + double(m) * (8.0 * d + 8.0));
     GS_HIP(hipGetLastError());
     return GS_OK;
 }
 
-gs_status launch_tail(int d, int B, gs::CellTable t, const gs::InstParam* prm, gs::InstState* st, uint32_t* tmap,
-                      int max_iter, hipStream_t s) {
+gs_status launch_tail(gs_context* c, int d, int B, gs::CellTable t, const gs::InstParam* prm, gs::InstState* st, uint32_t* tmap,
+                      int max_iter, hipStream_t s, double nbytes) {
+    const int tk = prof_begin(c, s, "tail");
     switch (d) {
         case 1: gs::k_tail<1><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
         case 2: gs::k_tail<2><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
@@ -235,6 +370,7 @@ gs_status launch_tail(int d, int B, gs::CellTable t, const gs::InstParam* prm, g
         case 6: gs::k_tail<6><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
         default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
     }
+    prof_end(c, s, tk, nbytes);
     GS_HIP(hipGetLastError());
     return GS_OK;
 }
@@ -309,14 +445,17 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     c->sort.ctr = P<uint32_t>(c->sctr);
     c->sort.look = P<uint64_t>(c->slook);
     c->sort.look_tiles = int64_t(c->slook.cap / (256 * 8));
+    c->sort.prof_ctx = c;
+    c->sort.prof_begin = sort_prof_begin;
+    c->sort.prof_end = sort_prof_end;
 
     const int np = gs::sort_passes(bits);
     k_fill_u32<<<blocks_for(gs::kSortMaxPasses * 256, 256), 256, 0, s>>>(c->sort.hist, gs::kSortMaxPasses * 256, 0);
     {
-        int64_t blocks = (N + 256 * 8 - 1) / (256 * 8);
-        blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, 4096));
-        gs::k_make_keys<T, K><<<unsigned(blocks), gs::kKeyThreads, 0, s>>>(x, ld, d, row_off, B, N, prm,
-                                                                           P<K>(c->kA), np, c->sort.hist);
+        if (c->ntiles > 0)
+            PROF_LAUNCH("make_keys", N * (double(d) * sizeof(T) + sizeof(K)),
+                        gs::k_make_keys<T, K><<<unsigned(c->ntiles), gs::kBoxThreads, 0, s>>>(
+                            x, ld, d, P<gs::RowTile>(c->tiles), prm, P<K>(c->kA), np, c->sort.hist));
         GS_HIP(hipGetLastError());
     }
     K* skeys = nullptr;
@@ -332,7 +471,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         k_set_i64<<<1, 1, 0, s>>>(ctr + 3, N);
         gs::HeadsOp<K> op{skeys, perm, P<uint64_t>(c->tkey[0]), P<uint32_t>(c->tstart[0]), P<uint32_t>(c->tfirst[0]),
                           P<uint32_t>(c->cell0)};
-        GS_TRY(run_scan(c, op, ctr + 3, N, ctr + 0, s));
+        GS_TRY(run_scan(c, op, ctr + 3, N, ctr + 0, s, "scan_heads", N * (sizeof(K) + 8.0)));
     }
     int64_t m0 = 0;
     GS_TRY(d2h(c, &m0, ctr + 0, sizeof(int64_t), s));
@@ -353,9 +492,11 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         GS_TRY(ensure(c->tchoff[i], size_t(c->capM) * 4));
     }
     gs::CellTable T0 = table(c, 0);
-    gs::k_cell_setup<<<blocks_for(c->capM, 256), 256, 0, s>>>(ctr + 0, N, T0, 0, row_off, B, nullptr, st);
+    PROF_LAUNCH("cell_setup", m0 * 20.0,
+                gs::k_cell_setup<<<blocks_for(c->capM, 256), 256, 0, s>>>(ctr + 0, N, T0, 0, row_off, B, nullptr,
+                                                                           st));
     GS_HIP(hipGetLastError());
-    GS_TRY(segsum(c, d, gs::SrcPoints<T>{x, ld, perm}, T0, m0, N, s));
+    GS_TRY(segsum(c, d, gs::SrcPoints<T>{x, ld, perm}, T0, m0, N, s, 4.0 + double(d) * sizeof(T)));
     gs::k_clear_ranges<<<blocks_for(B, 256), 256, 0, s>>>(st, B);
     gs::k_inst_ranges<<<blocks_for(c->capM, 256), 256, 0, s>>>(T0.inst, ctr + 0, st);
     GS_HIP(hipGetLastError());
@@ -393,15 +534,18 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         const int64_t hcap = int64_t(1) << logcap;
         GS_TRY(ensure(c->hk, size_t(hcap) * 8));
         GS_TRY(ensure(c->hv, size_t(hcap) * 4));
-        gs::k_hash_clear<<<blocks_for(hcap, 256), 256, 0, s>>>(P<uint64_t>(c->hk), hcap);
-        gs::k_hash_insert<<<blocks_for(M, 256), 256, 0, s>>>(TT.key, M, P<uint64_t>(c->hk), P<uint32_t>(c->hv),
-                                                              logcap);
+        PROF_LAUNCH("hash_clear", hcap * 8.0,
+                    gs::k_hash_clear<<<blocks_for(hcap, 256), 256, 0, s>>>(P<uint64_t>(c->hk), hcap));
+        PROF_LAUNCH("hash_insert", M * 20.0,
+                    gs::k_hash_insert<<<blocks_for(M, 256), 256, 0, s>>>(TT.key, M, P<uint64_t>(c->hk),
+                                                                          P<uint32_t>(c->hv), logcap));
         GS_HIP(hipGetLastError());
-        GS_TRY(launch_shift(d, TT, M, prm, st, P<uint64_t>(c->hk), P<uint32_t>(c->hv), logcap, P<double>(c->pbuf),
+        GS_TRY(launch_shift(c, d, TT, M, prm, st, P<uint64_t>(c->hk), P<uint32_t>(c->hv), logcap, P<double>(c->pbuf),
                             P<uint64_t>(c->kappa), s));
         gs::k_decide<<<blocks_for(B, 256), 256, 0, s>>>(st, B, max_iter);
-        gs::k_merge_prep<K><<<blocks_for(M, 256), 256, 0, s>>>(TT, M, st, st, P<double>(c->pbuf),
-                                                                P<uint64_t>(c->kappa), P<K>(c->ckA), d);
+        PROF_LAUNCH("merge_prep", M * (8.0 * 3 + 16.0 * d + sizeof(K)),
+                    gs::k_merge_prep<K><<<blocks_for(M, 256), 256, 0, s>>>(TT, M, st, st, P<double>(c->pbuf),
+                                                                            P<uint64_t>(c->kappa), P<K>(c->ckA), d));
         GS_HIP(hipGetLastError());
         K* mk = nullptr;
         uint32_t* mperm = nullptr;
@@ -409,12 +553,14 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
                                  false, c->sort, s, &mk, &mperm));
         k_set_i64<<<1, 1, 0, s>>>(ctr + 3, M);
         gs::HeadsOp<K> op{mk, mperm, U.key, U.start, U.first, P<uint32_t>(c->gmap)};
-        GS_TRY(run_scan(c, op, ctr + 3, M, ctr + 0, s));
-        gs::k_cell_setup<<<blocks_for(M, 256), 256, 0, s>>>(ctr + 0, M, U, 1, row_off, B, TT.inst, st);
+        GS_TRY(run_scan(c, op, ctr + 3, M, ctr + 0, s, "scan_heads", M * (sizeof(K) + 8.0)));
+        PROF_LAUNCH("cell_setup", M * 24.0,
+                    gs::k_cell_setup<<<blocks_for(M, 256), 256, 0, s>>>(ctr + 0, M, U, 1, row_off, B, TT.inst, st));
         GS_HIP(hipGetLastError());
         gs::SrcMerge src{P<double>(c->pbuf), TT.sum, TT.cnt, TT.inst, st, mperm, c->capM};
-        GS_TRY(segsum(c, d, src, U, M, M, s));
-        gs::k_compose<<<blocks_for(m0, 256), 256, 0, s>>>(P<uint32_t>(c->cur), m0, P<uint32_t>(c->gmap));
+        GS_TRY(segsum(c, d, src, U, M, M, s, 4.0 + 4.0 + 8.0 + 8.0 * d));
+        PROF_LAUNCH("compose", m0 * 12.0,
+                    gs::k_compose<<<blocks_for(m0, 256), 256, 0, s>>>(P<uint32_t>(c->cur), m0, P<uint32_t>(c->gmap)));
         gs::k_round_end<<<blocks_for(B, 256), 256, 0, s>>>(st, B);
         gs::k_clear_ranges<<<blocks_for(B, 256), 256, 0, s>>>(st, B);
         gs::k_inst_ranges<<<blocks_for(M, 256), 256, 0, s>>>(U.inst, ctr + 0, st);
@@ -428,10 +574,11 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
 
     // ---- remaining rounds: one LDS-resident workgroup per instance
     gs::CellTable TC = table(c, cur);
-    GS_TRY(launch_tail(d, B, TC, prm, st, P<uint32_t>(c->tmap), max_iter, s));
+    GS_TRY(launch_tail(c, d, B, TC, prm, st, P<uint32_t>(c->tmap), max_iter, s, 2.0 * M * (16.0 + 8.0 * d)));
     if (N > 0) {
-        gs::k_labels<<<blocks_for(N, 256), 256, 0, s>>>(P<uint32_t>(c->cell0), wide ? P<uint32_t>(c->cur) : nullptr,
-                                                        P<uint32_t>(c->tmap), labels, N);
+        PROF_LAUNCH("labels", N * 8.0,
+                    gs::k_labels<<<blocks_for(N, 256), 256, 0, s>>>(
+                        P<uint32_t>(c->cell0), wide ? P<uint32_t>(c->cur) : nullptr, P<uint32_t>(c->tmap), labels, N));
         GS_HIP(hipGetLastError());
     }
     GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
@@ -462,6 +609,7 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
     if (N >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "at most 2^31 - 1 points");
     if (N > 0 && (!points || !labels)) return fail(GS_ERR_INVALID_ARG, "points and labels are required");
     GS_HIP(hipSetDevice(c->device));
+    prof_flush(c, false);  // drop records of an earlier failed call
 
     GS_TRY(ensure(c->param, sizeof(gs::InstParam) * B));
     GS_TRY(ensure(c->state, sizeof(gs::InstState) * B));
@@ -469,8 +617,24 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
     GS_TRY(ensure(c->hs, sizeof(double) * B));
     GS_TRY(ensure(c->bbox, sizeof(int64_t) * B * gs::kMaxDim * 2));
     GS_TRY(ensure(c->counters, 8 * sizeof(int64_t)));
-    GS_TRY(h2d(c, c->rowoff.p, offsets, sizeof(int64_t) * (B + 1), s));
-    GS_TRY(h2d(c, c->hs.p, h, sizeof(double) * B, s));
+    // row tiles of at most kTileRows rows, each inside one instance
+    std::vector<gs::RowTile> tiles;
+    std::vector<int64_t> tile_off(B + 1, 0);
+    for (int b = 0; b < B; ++b) {
+        for (int64_t r = offsets[b]; r < offsets[b + 1]; r += gs::kTileRows)
+            tiles.push_back({r, std::min<int64_t>(r + gs::kTileRows, offsets[b + 1]), b, 0});
+        tile_off[b + 1] = int64_t(tiles.size());
+    }
+    c->ntiles = int64_t(tiles.size());
+    GS_TRY(ensure(c->tiles, sizeof(gs::RowTile) * std::max<size_t>(tiles.size(), 1)));
+    GS_TRY(ensure(c->tileoff, sizeof(int64_t) * (B + 1)));
+    GS_TRY(ensure(c->bpart, sizeof(int64_t) * 2 * gs::kMaxDim * std::max<size_t>(tiles.size(), 1)));
+    GS_TRY(h2d_batch(c,
+                     {{c->rowoff.p, offsets, sizeof(int64_t) * (B + 1)},
+                      {c->hs.p, h, sizeof(double) * B},
+                      {c->tiles.p, tiles.data(), sizeof(gs::RowTile) * tiles.size()},
+                      {c->tileoff.p, tile_off.data(), sizeof(int64_t) * (B + 1)}},
+                     s));
     gs::k_init_state<<<blocks_for(std::max(B, 8), 256), 256, 0, s>>>(P<gs::InstState>(c->state), B,
                                                                       P<int64_t>(c->bbox), d,
                                                                       P<int64_t>(c->counters));
@@ -478,19 +642,26 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
 
     std::vector<int64_t> box(size_t(B) * gs::kMaxDim * 2, 0);
     if (N > 0) {
-        const unsigned g = blocks_for(N, gs::kBoxRows);
+        const unsigned g = unsigned(tiles.size());
+        const double xb = double(N) * d * (dtype == GS_F32 ? 4.0 : 8.0);
         if (dtype == GS_F32)
-            gs::k_bbox<float><<<g, gs::kBoxThreads, 0, s>>>(static_cast<const float*>(points), ld, d,
-                                                            P<int64_t>(c->rowoff), B, N, P<double>(c->hs),
-                                                            P<int64_t>(c->bbox), P<int64_t>(c->counters));
+            PROF_LAUNCH("bbox", xb,
+                        gs::k_bbox_tiles<float><<<g, gs::kBoxThreads, 0, s>>>(
+                            static_cast<const float*>(points), ld, d, P<gs::RowTile>(c->tiles), P<double>(c->hs),
+                            P<int64_t>(c->bpart), P<int64_t>(c->counters)));
         else
-            gs::k_bbox<double><<<g, gs::kBoxThreads, 0, s>>>(static_cast<const double*>(points), ld, d,
-                                                             P<int64_t>(c->rowoff), B, N, P<double>(c->hs),
-                                                             P<int64_t>(c->bbox), P<int64_t>(c->counters));
+            PROF_LAUNCH("bbox", xb,
+                        gs::k_bbox_tiles<double><<<g, gs::kBoxThreads, 0, s>>>(
+                            static_cast<const double*>(points), ld, d, P<gs::RowTile>(c->tiles), P<double>(c->hs),
+                            P<int64_t>(c->bpart), P<int64_t>(c->counters)));
+        PROF_LAUNCH("bbox_reduce", tiles.size() * 96.0,
+                    gs::k_bbox_reduce<<<B, 256, 0, s>>>(P<int64_t>(c->bpart), P<int64_t>(c->tileoff),
+                                                        P<int64_t>(c->bbox)));
         GS_HIP(hipGetLastError());
-        GS_TRY(d2h(c, box.data(), c->bbox.p, box.size() * sizeof(int64_t), s));
         int64_t errbits = 0;
-        GS_TRY(d2h(c, &errbits, P<int64_t>(c->counters) + 2, sizeof(int64_t), s));
+        GS_TRY(d2h_batch(c, {{box.data(), c->bbox.p, box.size() * sizeof(int64_t)},
+                             {&errbits, P<int64_t>(c->counters) + 2, sizeof(int64_t)}},
+                         s));
         if (errbits & 1) return fail(GS_ERR_NONFINITE, "a coordinate is NaN or infinite");
         if (errbits & 2) return fail(GS_ERR_KEY_RANGE, "|floor(x/h)| >= 2^52");
     }
@@ -510,7 +681,12 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
                              : fit_typed<double, uint64_t>(c, static_cast<const double*>(points), d, ld, B, offsets,
                                                            max_iter, bits, labels, s);
     }
-    if (rc != GS_OK) return rc;
+    if (rc != GS_OK) {
+        (void)hipStreamSynchronize(s);
+        prof_flush(c, false);
+        return rc;
+    }
+    prof_flush(c, true);
     for (int b = 0; b < B; ++b) {
         info[b].n_points = offsets[b + 1] - offsets[b];
         info[b].n_cells0 = c->st[b].m0;
@@ -549,7 +725,7 @@ void gs_context_destroy(gs_context* c) {
     (void)hipSetDevice(c->device);
     DBuf* all[] = {&c->kA, &c->kB, &c->vA, &c->vB, &c->cell0, &c->kappa, &c->pbuf, &c->gmap, &c->cur, &c->tmap,
                    &c->part, &c->partc, &c->hk, &c->hv, &c->ckA, &c->ckB, &c->cvA, &c->cvB, &c->param, &c->state,
-                   &c->rowoff, &c->hs, &c->bbox, &c->koff, &c->counters, &c->look, &c->tilectr, &c->shist,
+                   &c->rowoff, &c->hs, &c->bbox, &c->koff, &c->tiles, &c->tileoff, &c->bpart, &c->counters, &c->look, &c->tilectr, &c->shist,
                    &c->sdbase, &c->sctr, &c->slook};
     for (DBuf* b : all)
         if (b->p) (void)hipFree(b->p);
@@ -560,6 +736,7 @@ void gs_context_destroy(gs_context* c) {
             if (b->p) (void)hipFree(b->p);
     }
     if (c->pinned) (void)hipHostFree(c->pinned);
+    for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -576,6 +753,34 @@ gs_status gs_fit_batched(gs_context* ctx, const void* points, gs_dtype dtype, in
                          void* stream) {
     return fit_impl(ctx, points, dtype, d, ld, B, offsets, h, max_iter, labels, info,
                     static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_profile_enable(gs_context* ctx, const char* prefix) {
+    if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
+    ctx->prof.on = prefix != nullptr;
+    ctx->prof.filter = prefix ? prefix : "";
+    return GS_OK;
+}
+
+gs_status gs_profile_reset(gs_context* ctx) {
+    if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
+    ctx->prof.names.clear();
+    ctx->prof.ms.clear();
+    ctx->prof.bytes.clear();
+    ctx->prof.launches.clear();
+    return GS_OK;
+}
+
+int32_t gs_profile_count(const gs_context* ctx) { return ctx ? int32_t(ctx->prof.names.size()) : 0; }
+
+gs_status gs_profile_entry(const gs_context* ctx, int32_t i, const char** name, double* total_ms, int64_t* launches,
+                           double* bytes) {
+    if (!ctx || i < 0 || i >= int32_t(ctx->prof.names.size())) return fail(GS_ERR_INVALID_ARG, "bad profile index");
+    if (name) *name = ctx->prof.names[i].c_str();
+    if (total_ms) *total_ms = ctx->prof.ms[i];
+    if (launches) *launches = ctx->prof.launches[i];
+    if (bytes) *bytes = ctx->prof.bytes[i];
+    return GS_OK;
 }
 
 static gs_status prepare_copy(gs_context* c, hipStream_t s, int64_t* rows) {

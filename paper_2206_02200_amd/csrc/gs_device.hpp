@@ -87,18 +87,77 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
 
 // Exclusive prefix of `total` over all earlier tiles (decoupled look-back).
 // The caller has already published its own aggregate.  Tile 0 returns 0.
+// kWin predecessors are read per round trip; their words are consumed
+// nearest first until an inclusive prefix is found.
+template <int kWin>
 __device__ __forceinline__ uint64_t lb_exclusive(const uint64_t* status, int64_t tile, int64_t stride,
                                                  uint32_t epoch) {
+    const uint32_t ep = epoch & 0xffffu;
     uint64_t excl = 0;
-    for (int64_t p = tile - 1; p >= 0; --p) {
-        uint64_t w;
-        do {
-            w = lb_load(status + p * stride);
-        } while (lb_epoch(w) != (epoch & 0xffffu) || lb_flag(w) == 0);
-        excl += lb_value(w);
-        if (lb_flag(w) == kFlagPrefix) break;
+    int64_t p = tile - 1;
+    while (p >= 0) {
+        uint64_t w[kWin];
+#pragma unroll
+        for (int i = 0; i < kWin; ++i) w[i] = (p - i >= 0) ? lb_load(status + (p - i) * stride) : 0ull;
+        int used = 0;
+        bool done = false;
+#pragma unroll
+        for (int i = 0; i < kWin; ++i) {
+            if (done || used != i) continue;
+            if (p - i < 0) {
+                done = true;
+                continue;
+            }
+            if (lb_epoch(w[i]) != ep || lb_flag(w[i]) == 0) continue;  // not published yet
+            excl += lb_value(w[i]);
+            ++used;
+            if (lb_flag(w[i]) == kFlagPrefix) done = true;
+        }
+        if (done) break;
+        p -= used;  // unpublished predecessor: read again from there
     }
     return excl;
+}
+
+// Look-back by a whole wave for one status word per tile: lane l reads
+// predecessor p - l, so 64 predecessors cost one round trip.  Every lane
+// returns the exclusive prefix.
+__device__ __forceinline__ uint64_t lb_exclusive_wave(const uint64_t* status, int64_t tile, uint32_t epoch) {
+    const uint32_t ep = epoch & 0xffffu;
+    const int lane = __lane_id();
+    uint64_t excl = 0;
+    int64_t p = tile - 1;
+    while (p >= 0) {
+        const int64_t q = p - lane;
+        // before tile 0 sits a virtual inclusive prefix of 0
+        const uint64_t w = q >= 0 ? lb_load(status + q) : lb_pack(ep, kFlagPrefix, 0);
+        const bool ready = lb_epoch(w) == ep && lb_flag(w) != 0;
+        const uint64_t notready = __ballot(!ready);
+        const uint64_t isprefix = __ballot(ready && lb_flag(w) == kFlagPrefix);
+        const int first_nr = notready ? __ffsll((unsigned long long)notready) - 1 : 64;
+        const uint64_t below = first_nr == 64 ? ~0ull : ((1ull << first_nr) - 1);
+        const uint64_t pre = isprefix & below;
+        const int upto = pre ? __ffsll((unsigned long long)pre) : first_nr;  // lanes consumed
+        uint64_t v = lane < upto ? lb_value(w) : 0ull;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor((unsigned long long)v, off, 64);
+        excl += v;
+        p -= upto;
+        if (pre) break;
+    }
+    return excl;
+}
+
+// Raise *flag (set it to 1) for every lane with `pred`, with one atomic per
+// distinct flag address in the wave (skipped when the flag is already set):
+// many lanes raising one flag at once would serialise on that address.
+__device__ __forceinline__ void wave_flag_or(int32_t* flag, bool pred) {
+    const uint64_t bal = __ballot(pred);
+    if (!bal) return;
+    const int leader = __ffsll((unsigned long long)bal) - 1;
+    const uint64_t lf = __shfl((unsigned long long)(uintptr_t)flag, leader, 64);
+    const bool mine = (__lane_id() == leader) || (pred && (uint64_t)(uintptr_t)flag != lf);
+    if (mine && __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) atomicOr(flag, 1);
 }
 
 // Instance of a row / packed key by binary search over the sorted bounds.

@@ -63,111 +63,189 @@ __global__ void k_init_state(InstState* __restrict__ st, int B, int64_t* __restr
 // ===========================================================================
 // bbox: per instance and dimension, min/max of floor(fl(x/h))
 // ===========================================================================
+// Rows are cut into tiles of kTileRows that never straddle two instances;
+// each block reduces one tile to a partial box, then one block per instance
+// reduces its tiles' partials.
 constexpr int kBoxThreads = 256;
-constexpr int kBoxRows = 4096;
+constexpr int kTileRows = 2048;
+constexpr int kRowsPerThread = kTileRows / kBoxThreads;  // 8
+
+struct RowTile {
+    int64_t r0, r1;  // rows [r0, r1) of one instance
+    int32_t inst;
+    int32_t pad;
+};
 
 template <typename T>
-__global__ __launch_bounds__(kBoxThreads) void k_bbox(const T* __restrict__ x, int64_t ld, int d,
-                                                      const int64_t* __restrict__ row_off, int B, int64_t n,
-                                                      const double* __restrict__ hs, int64_t* __restrict__ bbox,
-                                                      int64_t* __restrict__ counters) {
+__global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict__ x, int64_t ld, int d,
+                                                            const RowTile* __restrict__ tiles,
+                                                            const double* __restrict__ hs,
+                                                            int64_t* __restrict__ part,  // [tiles][kMaxDim][2]
+                                                            int64_t* __restrict__ counters) {
     __shared__ int64_t red[kBoxThreads / kWave][2 * kMaxDim];
-    __shared__ int s_err;
-    const int64_t r0 = int64_t(blockIdx.x) * kBoxRows;
-    if (r0 >= n) return;
-    const int64_t r1 = (r0 + kBoxRows < n) ? r0 + kBoxRows : n;
-    const int b0 = inst_of_row(row_off, B, r0);
-    const int b1 = inst_of_row(row_off, B, r1 - 1);
+    const RowTile tl = tiles[blockIdx.x];
+    const double h = hs[tl.inst];
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-    if (tid == 0) s_err = 0;
-    __syncthreads();
-    int err = 0;
-    for (int b = b0; b <= b1; ++b) {
-        const int64_t a0 = row_off[b] > r0 ? row_off[b] : r0;
-        const int64_t a1 = row_off[b + 1] < r1 ? row_off[b + 1] : r1;
-        if (a0 >= a1) continue;  // block-uniform
-        const double h = hs[b];
-        int64_t mn[kMaxDim], mx[kMaxDim];
-        for (int k = 0; k < kMaxDim; ++k) {
-            mn[k] = INT64_MAX;
-            mx[k] = INT64_MIN;
-        }
-        for (int64_t r = a0 + tid; r < a1; r += kBoxThreads) {
-            for (int k = 0; k < d; ++k) {
-                const double v = load_coord(x, r, ld, k);
-                if (!isfinite(v)) {
-                    err |= 1;
-                    continue;
-                }
-                const double q = cell_floor(v, h);
-                if (!(q > -4503599627370496.0 && q < 4503599627370496.0)) {  // |q| < 2^52
-                    err |= 2;
-                    continue;
-                }
-                const int64_t qi = int64_t(q);
-                mn[k] = qi < mn[k] ? qi : mn[k];
-                mx[k] = qi > mx[k] ? qi : mx[k];
-            }
-        }
-        for (int k = 0; k < d; ++k) {
-            for (int off = 32; off >= 1; off >>= 1) {
-                const int64_t a = __shfl_xor(mn[k], off, kWave);
-                const int64_t c = __shfl_xor(mx[k], off, kWave);
-                mn[k] = a < mn[k] ? a : mn[k];
-                mx[k] = c > mx[k] ? c : mx[k];
-            }
-            if (lane == 0) {
-                red[w][2 * k] = mn[k];
-                red[w][2 * k + 1] = mx[k];
-            }
-        }
-        __syncthreads();
-        if (tid < d) {
-            int64_t a = INT64_MAX, c = INT64_MIN;
-            for (int ww = 0; ww < kBoxThreads / kWave; ++ww) {
-                a = red[ww][2 * tid] < a ? red[ww][2 * tid] : a;
-                c = red[ww][2 * tid + 1] > c ? red[ww][2 * tid + 1] : c;
-            }
-            if (a != INT64_MAX) {
-                atomicMin((long long*)&bbox[(int64_t(b) * kMaxDim + tid) * 2 + 0], (long long)a);
-                atomicMax((long long*)&bbox[(int64_t(b) * kMaxDim + tid) * 2 + 1], (long long)c);
-            }
-        }
-        __syncthreads();
+    int64_t mn[kMaxDim], mx[kMaxDim];
+#pragma unroll
+    for (int k = 0; k < kMaxDim; ++k) {
+        mn[k] = INT64_MAX;
+        mx[k] = INT64_MIN;
     }
-    if (err) atomicOr(&s_err, err);
+    int err = 0;
+    double v[kRowsPerThread][kMaxDim];
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i) {
+        const int64_t r = tl.r0 + tid + int64_t(i) * kBoxThreads;
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) v[i][k] = (r < tl.r1 && k < d) ? load_coord(x, r, ld, k) : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i) {
+        const int64_t r = tl.r0 + tid + int64_t(i) * kBoxThreads;
+        if (r >= tl.r1) continue;
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) {
+            if (k >= d) continue;
+            if (!isfinite(v[i][k])) {
+                err |= 1;
+                continue;
+            }
+            const double q = cell_floor(v[i][k], h);
+            if (!(q > -4503599627370496.0 && q < 4503599627370496.0)) {  // |q| < 2^52
+                err |= 2;
+                continue;
+            }
+            const int64_t qi = int64_t(q);
+            mn[k] = qi < mn[k] ? qi : mn[k];
+            mx[k] = qi > mx[k] ? qi : mx[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxDim; ++k) {
+        for (int off = 32; off >= 1; off >>= 1) {
+            const int64_t a = __shfl_xor(mn[k], off, kWave);
+            const int64_t c = __shfl_xor(mx[k], off, kWave);
+            mn[k] = a < mn[k] ? a : mn[k];
+            mx[k] = c > mx[k] ? c : mx[k];
+        }
+        if (lane == 0) {
+            red[w][2 * k] = mn[k];
+            red[w][2 * k + 1] = mx[k];
+        }
+    }
+    const uint64_t eb = __ballot(err != 0);
+    if (eb) {
+        int e = err;
+        for (int off = 32; off >= 1; off >>= 1) e |= __shfl_xor(e, off, kWave);
+        if (lane == 0) atomicOr((unsigned long long*)&counters[2], (unsigned long long)e);
+    }
     __syncthreads();
-    if (tid == 0 && s_err) atomicOr((unsigned long long*)&counters[2], (unsigned long long)s_err);
+    if (tid < 2 * kMaxDim) {
+        const bool isMin = (tid & 1) == 0;
+        int64_t a = isMin ? INT64_MAX : INT64_MIN;
+        for (int ww = 0; ww < kBoxThreads / kWave; ++ww) {
+            const int64_t c = red[ww][tid];
+            a = isMin ? (c < a ? c : a) : (c > a ? c : a);
+        }
+        part[int64_t(blockIdx.x) * 2 * kMaxDim + tid] = a;
+    }
+}
+
+// One block per instance: reduce the partial boxes of its tiles.
+__global__ __launch_bounds__(256) void k_bbox_reduce(const int64_t* __restrict__ part,
+                                                     const int64_t* __restrict__ tile_off, int64_t* __restrict__ bbox) {
+    __shared__ int64_t red[4][2 * kMaxDim];
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    const int64_t t0 = tile_off[b], t1 = tile_off[b + 1];
+    int64_t acc[2 * kMaxDim];
+#pragma unroll
+    for (int i = 0; i < 2 * kMaxDim; ++i) acc[i] = (i & 1) ? INT64_MIN : INT64_MAX;
+    for (int64_t t = t0 + tid; t < t1; t += 256) {
+#pragma unroll
+        for (int i = 0; i < 2 * kMaxDim; ++i) {
+            const int64_t c = part[t * 2 * kMaxDim + i];
+            acc[i] = (i & 1) ? (c > acc[i] ? c : acc[i]) : (c < acc[i] ? c : acc[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * kMaxDim; ++i) {
+        for (int off = 32; off >= 1; off >>= 1) {
+            const int64_t c = __shfl_xor(acc[i], off, kWave);
+            acc[i] = (i & 1) ? (c > acc[i] ? c : acc[i]) : (c < acc[i] ? c : acc[i]);
+        }
+        if (lane == 0) red[w][i] = acc[i];
+    }
+    __syncthreads();
+    if (tid < 2 * kMaxDim) {
+        int64_t a = red[0][tid];
+        for (int ww = 1; ww < 4; ++ww) a = (tid & 1) ? (red[ww][tid] > a ? red[ww][tid] : a)
+                                                     : (red[ww][tid] < a ? red[ww][tid] : a);
+        bbox[int64_t(b) * 2 * kMaxDim + tid] = a;
+    }
 }
 
 // ===========================================================================
 // packed keys + radix digit histograms
 // ===========================================================================
-constexpr int kKeyThreads = 256;
-
 template <typename T, typename K>
-__global__ __launch_bounds__(kKeyThreads) void k_make_keys(const T* __restrict__ x, int64_t ld, int d,
-                                                           const int64_t* __restrict__ row_off, int B, int64_t n,
+__global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__ x, int64_t ld, int d,
+                                                           const RowTile* __restrict__ tiles,
                                                            const InstParam* __restrict__ param,
                                                            K* __restrict__ keys, int npasses,
                                                            uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kSortMaxPasses * 256];
-    for (int i = threadIdx.x; i < npasses * 256; i += kKeyThreads) h[i] = 0;
+    __shared__ InstParam sp;
+    const RowTile tl = tiles[blockIdx.x];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < npasses * 256; i += kBoxThreads) h[i] = 0;
+    if (tid == 0) sp = param[tl.inst];
     __syncthreads();
-    const int64_t stride = int64_t(gridDim.x) * kKeyThreads;
-    for (int64_t r = int64_t(blockIdx.x) * kKeyThreads + threadIdx.x; r < n; r += stride) {
-        const int b = inst_of_row(row_off, B, r);
-        const InstParam& P = param[b];
-        uint64_t key = P.base;
-        for (int k = 0; k < d; ++k) {
-            const double q = cell_floor(load_coord(x, r, ld, k), P.h);
-            key += uint64_t(int64_t(q) - P.lo[k]) * P.stride[k];
+    const double hh = sp.h;
+    double v[kRowsPerThread][kMaxDim];
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i) {
+        const int64_t r = tl.r0 + tid + int64_t(i) * kBoxThreads;
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) v[i][k] = (r < tl.r1 && k < d) ? load_coord(x, r, ld, k) : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i) {
+        const int64_t r = tl.r0 + tid + int64_t(i) * kBoxThreads;
+        if (r >= tl.r1) continue;
+        uint64_t key = sp.base;
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) {
+            if (k >= d) continue;
+            const double q = cell_floor(v[i][k], hh);
+            key += uint64_t(int64_t(q) - sp.lo[k]) * sp.stride[k];
         }
         keys[r] = K(key);
-        sort_hist_add<K>(h, K(key), npasses);
+    }
+    // digit histograms: one LDS atomic per wave when all its lanes share the
+    // digit (neighbouring points usually share a cell), else one per lane
+    const int lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i) {
+        const int64_t r = tl.r0 + tid + int64_t(i) * kBoxThreads;
+        const bool valid = r < tl.r1;
+        const K key = valid ? keys[r] : K(0);
+        const uint64_t act = __ballot(valid);
+        if (!act) continue;
+        const int lead = __ffsll((unsigned long long)act) - 1;
+        for (int p = 0; p < npasses; ++p) {
+            const uint32_t dgt = uint32_t(key >> (8 * p)) & 255u;
+            const uint32_t d0 = __shfl(dgt, lead, kWave);
+            if (__ballot(valid && dgt == d0) == act) {
+                if (lane == lead) atomicAdd(&h[p * 256 + d0], uint32_t(__popcll(act)));
+            } else if (valid) {
+                atomicAdd(&h[p * 256 + dgt], 1u);
+            }
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < npasses * 256; i += kKeyThreads)
+    for (int i = tid; i < npasses * 256; i += kBoxThreads)
         if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
@@ -229,10 +307,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __r
     uint32_t v[kScanItems];
     uint64_t incl[kScanItems];
     uint64_t run = 0;
+    // all values first, so that their loads overlap
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t p = t0 + int64_t(w) * (kWave * kScanItems) + i * kWave + lane;
         v[i] = p < n ? op.value(p) : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
         uint64_t xs = v[i];
 #pragma unroll
         for (int off = 1; off < kWave; off <<= 1) {
@@ -244,23 +326,30 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __r
     }
     if (lane == 0) wtot[w] = run;
     __syncthreads();
-    if (tid == 0) {
+    if (w == 0) {  // wave 0 publishes the tile total and looks back
         uint64_t tot = 0;
-        for (int ww = 0; ww < W; ++ww) {
-            const uint64_t c = wtot[ww];
-            wtot[ww] = tot;
-            tot += c;
-        }
+        for (int ww = 0; ww < W; ++ww) tot += wtot[ww];
         uint64_t excl = 0;
         if (tile == 0) {
-            lb_store(look, lb_pack(epoch, kFlagPrefix, tot));
+            if (lane == 0) lb_store(look, lb_pack(epoch, kFlagPrefix, tot));
         } else {
-            lb_store(look + tile, lb_pack(epoch, kFlagAgg, tot));
-            excl = lb_exclusive(look, tile, 1, epoch);
-            lb_store(look + tile, lb_pack(epoch, kFlagPrefix, excl + tot));
+            if (lane == 0) lb_store(look + tile, lb_pack(epoch, kFlagAgg, tot));
+            excl = lb_exclusive_wave(look, tile, epoch);
+            if (lane == 0) lb_store(look + tile, lb_pack(epoch, kFlagPrefix, excl + tot));
         }
-        s_excl = excl;
-        if (t0 + kScanTile >= n) *total = int64_t(excl + tot);
+        if (lane == 0) {
+            s_excl = excl;
+            if (t0 + kScanTile >= n) *total = int64_t(excl + tot);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t acc = 0;
+        for (int ww = 0; ww < W; ++ww) {
+            const uint64_t c = wtot[ww];
+            wtot[ww] = acc;
+            acc += c;
+        }
     }
     __syncthreads();
     const uint64_t base = s_excl + wtot[w];
@@ -281,20 +370,23 @@ __global__ void k_cell_setup(const int64_t* __restrict__ m_ptr, int64_t npos, Ce
                              InstState* __restrict__ st) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t m = *m_ptr;
-    if (c >= m) return;
-    const uint32_t s0 = t.start[c];
-    const uint32_t s1 = (c + 1 < m) ? t.start[c + 1] : uint32_t(npos);
-    const uint32_t len = s1 - s0;
-    t.len[c] = len;
-    t.nch[c] = (len + kChunk - 1) / kChunk;
-    int b;
-    if (mode == 0) {
-        b = inst_of_row(row_off, B, int64_t(t.first[c]));
-    } else {
-        b = old_inst[t.first[c]];
-        if (len > 1 && st[b].apply) atomicOr(&st[b].changed, 1);
+    bool merged = false;
+    int b = 0;
+    if (c < m) {
+        const uint32_t s0 = t.start[c];
+        const uint32_t s1 = (c + 1 < m) ? t.start[c + 1] : uint32_t(npos);
+        const uint32_t len = s1 - s0;
+        t.len[c] = len;
+        t.nch[c] = (len + kChunk - 1) / kChunk;
+        if (mode == 0) {
+            b = inst_of_row(row_off, B, int64_t(t.first[c]));
+        } else {
+            b = old_inst[t.first[c]];
+            merged = len > 1 && st[b].apply;
+        }
+        t.inst[c] = b;
     }
-    t.inst[c] = b;
+    if (mode == 1) wave_flag_or(&st[b].changed, merged);
 }
 
 // ===========================================================================
@@ -420,6 +512,21 @@ __global__ __launch_bounds__(kSegThreads) void k_segsum_levels(CellTable t, cons
     int64_t len = t.nch[c];
     if (len <= 1) return;
     const int64_t base = t.choff[c];
+    if (len <= kWave) {  // one level: the partials come from the previous kernel
+        double v[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[k] = lane < len ? part[k * pcap + base + lane] : -0.0;
+        int64_t cv = lane < len ? partc[base + lane] : 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[k] = wave_tree_sum(v[k]);
+        cv = wave_tree_sum_i64(cv);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) t.sum[k * t.cap + c] = v[k];
+            t.cnt[c] = cv;
+        }
+        return;
+    }
     while (len > 1) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int64_t pieces = (len + kWave - 1) / kWave;
@@ -518,74 +625,101 @@ __device__ __forceinline__ int64_t hash_find(const uint64_t* __restrict__ hk, co
     }
 }
 
-// Shift of every cell of an active instance (Eq. 1-2, parallel form Eq. 6):
-// neighbours j+v, v in {-1,0,1}^D enumerated lexicographically (= ascending
-// packed key), W exact, N a left fold, p = N / W, landing key floor(p/h).
+// Shift of every cell of an active instance (Eq. 1-2, parallel form Eq. 6).
+// One wave per cell: the lanes probe the 3^D neighbour keys j+v in parallel,
+// v enumerated lexicographically (dimension 0 most significant, which is
+// ascending packed key); the cells found are compacted in that order; then
+// lane k folds dimension k left to right and lane D adds the integer weight.
+// p = N / W and the landing key floor(p/h) follow.
+constexpr int kShiftWaves = 4;
+constexpr int kSlabMax = 2048;  // largest dimension-0 extent with a slab table in the tail
+
+__host__ __device__ constexpr int pow3(int d) { return d == 0 ? 1 : 3 * pow3(d - 1); }
+
 template <int D>
-__global__ void k_shift(CellTable t, int64_t m, const InstParam* __restrict__ param, InstState* __restrict__ st,
-                        const uint64_t* __restrict__ hk, const uint32_t* __restrict__ hv, int logcap,
-                        double* __restrict__ pbuf, uint64_t* __restrict__ kappa) {
-    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j >= m) return;
+__global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int64_t m,
+                                                               const InstParam* __restrict__ param,
+                                                               InstState* __restrict__ st,
+                                                               const uint64_t* __restrict__ hk,
+                                                               const uint32_t* __restrict__ hv, int logcap,
+                                                               double* __restrict__ pbuf,
+                                                               uint64_t* __restrict__ kappa) {
+    constexpr int NOFF = pow3(D);
+    __shared__ int32_t list[kShiftWaves][NOFF];
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int64_t j = int64_t(blockIdx.x) * kShiftWaves + w;
+    if (j >= m) return;  // wave-uniform
     const int b = t.inst[j];
     if (!st[b].active) return;
     const InstParam& P = param[b];
     const uint64_t key = t.key[j];
-    uint64_t local = key - P.base;
+    const uint64_t local = key - P.base;
     int64_t crd[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) crd[k] = int64_t((local / P.stride[k]) % uint64_t(P.E[k]));
-    int64_t W = 0;
-    double N[D];
-    bool first = true, nb = false;
-    int v[D];
+    const uint64_t lt = lanemask_lt();
+    int nfound = 0;
+    for (int r0 = 0; r0 < NOFF; r0 += kWave) {
+        const int r = r0 + lane;
+        int64_t idx = -1;
+        if (r < NOFF) {
+            int rr = r;
+            bool inside = true;
+            uint64_t nk = key;
 #pragma unroll
-    for (int k = 0; k < D; ++k) v[k] = -1;
-    for (;;) {
-        bool inside = true;
-        uint64_t nk = key;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const int64_t c = crd[k] + v[k];
-            inside = inside && c >= 0 && c < P.E[k];
-            nk += uint64_t(int64_t(v[k])) * P.stride[k];
-        }
-        if (inside) {
-            const int64_t idx = hash_find(hk, hv, nk, logcap);
-            if (idx >= 0) {
-                W += t.cnt[idx];
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const double s = t.sum[k * t.cap + idx];
-                    N[k] = first ? s : N[k] + s;
-                }
-                first = false;
-                nb = nb || (idx != j);
+            for (int k = D - 1; k >= 0; --k) {
+                const int v = rr % 3 - 1;
+                rr /= 3;
+                const int64_t c = crd[k] + v;
+                inside = inside && c >= 0 && c < P.E[k];
+                nk += uint64_t(int64_t(v)) * P.stride[k];
             }
+            if (inside) idx = hash_find(hk, hv, nk, logcap);
         }
-        // odometer over {-1,0,1}^D, last dimension fastest
-        int k = D - 1;
-        while (k >= 0 && v[k] == 1) {
-            v[k] = -1;
-            --k;
-        }
-        if (k < 0) break;
-        ++v[k];
+        const uint64_t bal = __ballot(idx >= 0);
+        if (idx >= 0) list[w][nfound + __popcll(bal & lt)] = int32_t(idx);
+        nfound += __popcll(bal);
     }
-    uint64_t kap = P.base;
+    __builtin_amdgcn_wave_barrier();
+    double acc = 0.0;
+    int64_t W = 0;
+    if (lane < D) {
+        const double* col = t.sum + int64_t(lane) * t.cap;
+        int q = 0;
+        for (; q + 4 <= nfound; q += 4) {
+            const double s0 = col[list[w][q]], s1 = col[list[w][q + 1]];
+            const double s2 = col[list[w][q + 2]], s3 = col[list[w][q + 3]];
+            acc = (q == 0) ? s0 : acc + s0;
+            acc = acc + s1;
+            acc = acc + s2;
+            acc = acc + s3;
+        }
+        for (; q < nfound; ++q) {
+            const double s0 = col[list[w][q]];
+            acc = (q == 0) ? s0 : acc + s0;
+        }
+    } else if (lane == D) {
+        for (int q = 0; q < nfound; ++q) W += t.cnt[list[w][q]];
+    }
+    W = __shfl(W, D, kWave);
     bool bad = false;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const double p = N[k] / double(W);
-        pbuf[k * t.cap + j] = p;
+    uint64_t term = 0;
+    if (lane < D) {
+        const double p = acc / double(W);
+        pbuf[int64_t(lane) * t.cap + j] = p;
         const double q = cell_floor(p, P.h);
-        const double rel = q - double(P.lo[k]);
-        if (!(rel >= 0.0 && rel < double(P.E[k]))) bad = true;
-        kap += uint64_t(int64_t(q) - P.lo[k]) * P.stride[k];
+        const double rel = q - double(P.lo[lane]);
+        bad = !(rel >= 0.0 && rel < double(P.E[lane]));
+        term = bad ? 0 : uint64_t(int64_t(q) - P.lo[lane]) * P.stride[lane];
     }
-    kappa[j] = kap;
-    if (nb) atomicOr(&st[b].any_nb, 1);
-    if (bad) atomicOr(&st[b].err, 3);  // GS_ERR_KEY_RANGE
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) term += __shfl_xor((unsigned long long)term, off, kWave);
+    if (lane == 0) {
+        kappa[j] = P.base + term;
+        if (nfound > 1 && __hip_atomic_load(&st[b].any_nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+            atomicOr(&st[b].any_nb, 1);
+    }
+    if (__ballot(bad) && lane == 0) atomicOr(&st[b].err, 3);  // GS_ERR_KEY_RANGE
 }
 
 // Stop test of the round (Section 2.1 (v)): decides whether each instance
@@ -616,20 +750,22 @@ template <typename K>
 __global__ void k_merge_prep(CellTable t, int64_t m, const InstState* __restrict__ stc, InstState* __restrict__ st,
                              const double* __restrict__ pbuf, const uint64_t* __restrict__ kappa, K* __restrict__ skey,
                              int d) {
-    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j >= m) return;
+    const int64_t j0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool valid = j0 < m;
+    const int64_t j = valid ? j0 : m - 1;  // idle lanes shadow the last cell and raise nothing
     const int b = t.inst[j];
     const uint64_t key = t.key[j];
     if (!stc[b].apply) {
-        skey[j] = K(key);
+        if (valid) skey[j] = K(key);
+        wave_flag_or(&st[b].changed, false);
         return;
     }
     const uint64_t kap = kappa[j];
-    skey[j] = K(kap);
-    bool chg = kap != key;
+    if (valid) skey[j] = K(kap);
+    bool chg = valid && kap != key;
     const double C = double(t.cnt[j]);
     for (int k = 0; k < d; ++k) chg = chg || dbits(C * pbuf[k * t.cap + j]) != dbits(t.sum[k * t.cap + j]);
-    if (chg) atomicOr(&st[b].changed, 1);
+    wave_flag_or(&st[b].changed, chg);
 }
 
 __global__ void k_compose(uint32_t* __restrict__ cur, int64_t m0, const uint32_t* __restrict__ g) {
@@ -675,6 +811,9 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
     __shared__ uint16_t hstart[MT + 1];
     __shared__ int32_t wsum[NW];
     __shared__ int32_t s_maxsz;
+    __shared__ uint16_t slab[kSlabMax + 1];  // slab[c]: first cell with dimension-0 coordinate >= c
+    __shared__ uint16_t rank_of[MT];         // old cell -> sorted position
+    __shared__ int32_t s_flag[2][3];         // per round parity: any neighbour, bad key, changed
 
     const int b = blockIdx.x;
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
@@ -716,7 +855,23 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
     uint32_t flags = S->flags;
     int err = 0;
     const uint64_t lt = lanemask_lt();
-    for (;;) {
+    const int E0 = int(E[0]);
+    const bool use_slab = E0 <= kSlabMax;
+    const bool fast_rank = P.span <= (1ull << 53);  // (key << 10 | index) fits in 63 bits
+    if (tid < 6) (&s_flag[0][0])[tid] = 0;
+    for (int round = 0;; ++round) {
+        int32_t* flg = s_flag[round & 1];
+        // ---- dimension-0 slab starts of the current table
+        if (use_slab && tid < m) {
+            const int hi = crd[0][tid];
+            const int lo = tid == 0 ? 0 : crd[0][tid - 1] + 1;
+            for (int c = lo; c <= hi; ++c) slab[c] = uint16_t(tid);
+            if (tid == m - 1)
+                for (int c = hi + 1; c <= E0; ++c) slab[c] = uint16_t(m);
+        }
+        __syncthreads();
+        // every thread has finished reading the other parity's flags
+        if (tid < 3) s_flag[(round + 1) & 1][tid] = 0;
         // ---- shift (one cell per thread)
         bool nb = false, bad = false;
         double p[D];
@@ -724,25 +879,54 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         uint64_t kj = 0;
         if (tid < m) {
             const int32_t c0 = crd[0][tid];
-            int a = 0, z = m;  // first cell with crd0 >= c0 - 1
-            while (a < z) {
-                const int mid = (a + z) >> 1;
-                if (crd[0][mid] < c0 - 1) a = mid + 1; else z = mid;
+            int a, z;  // cells with dimension-0 coordinate in [c0 - 1, c0 + 1]
+            if (use_slab) {
+                a = slab[c0 - 1 < 0 ? 0 : c0 - 1];
+                z = slab[c0 + 2 > E0 ? E0 : c0 + 2];
+            } else {
+                a = 0;
+                z = m;
+                while (a < z) {
+                    const int mid = (a + z) >> 1;
+                    if (crd[0][mid] < c0 - 1) a = mid + 1; else z = mid;
+                }
+                z = a;
+                while (z < m && crd[0][z] <= c0 + 1) ++z;
             }
+            int32_t me[D];
+#pragma unroll
+            for (int dd = 1; dd < D; ++dd) me[dd] = crd[dd][tid];
+            // Straight-line fold: a non-neighbour adds -0.0, the exact additive
+            // identity, and the fold starts from -0.0, so the result is
+            // bitwise the left fold over the neighbours alone.
             int64_t W = 0;
-            bool first = true;
-            for (int k = a; k < m && crd[0][k] <= c0 + 1; ++k) {
-                bool ok = true;
 #pragma unroll
-                for (int dd = 1; dd < D; ++dd) ok = ok && (uint32_t(crd[dd][k] - crd[dd][tid] + 1) <= 2u);
-                if (ok) {
-                    W += cnt[k];
+            for (int dd = 0; dd < D; ++dd) p[dd] = -0.0;
+            int nbs = 0;
+            for (int k0 = a; k0 < z; k0 += 4) {
+                int okm[4];
+                int kk[4];
 #pragma unroll
-                    for (int dd = 0; dd < D; ++dd) p[dd] = first ? sm[dd][k] : p[dd] + sm[dd][k];
-                    first = false;
-                    nb = nb || (k != tid);
+                for (int u = 0; u < 4; ++u) {
+                    kk[u] = (k0 + u < z) ? k0 + u : k0;
+                    okm[u] = (k0 + u < z) ? 1 : 0;
+                }
+#pragma unroll
+                for (int dd = 1; dd < D; ++dd) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) okm[u] &= (uint32_t(crd[dd][kk[u]] - me[dd] + 1) <= 2u) ? 1 : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = kk[u];
+                    const bool ok = okm[u] != 0;
+                    W += ok ? int64_t(cnt[k]) : 0;
+                    nbs += ok ? 1 : 0;
+#pragma unroll
+                    for (int dd = 0; dd < D; ++dd) p[dd] = p[dd] + (ok ? sm[dd][k] : -0.0);
                 }
             }
+            nb = nbs > 1;  // the cell itself is always among the candidates
 #pragma unroll
             for (int dd = 0; dd < D; ++dd) {
                 p[dd] = p[dd] / double(W);
@@ -753,8 +937,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
                 kj += uint64_t(int64_t(qq) - lo[dd]) * stride[dd];
             }
         }
-        const int any = __syncthreads_or(nb);
-        if (!any) {
+        if (__ballot(nb) && lane == 0) atomicOr(&flg[0], 1);
+        if (__ballot(bad) && lane == 0) atomicOr(&flg[1], 1);
+        __syncthreads();
+        if (!flg[0]) {
             flags |= 1u;
             break;
         }
@@ -762,7 +948,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
             flags |= 4u;
             break;
         }
-        if (__syncthreads_or(bad)) {
+        if (flg[1]) {
             err = 3;
             break;
         }
@@ -781,11 +967,57 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         __syncthreads();
         // ---- stable rank by (landing key, old index)
         int rank = 0;
-        if (tid < m) {
-            for (int k = 0; k < m; ++k) {
+        if (fast_rank) {
+            // (key, index) packed in one word; each wave sorts its 64 words in
+            // registers (bitonic network over lanes), then the rank of a word
+            // is its place in its own run plus its lower bound in every other
+            // run (binary search in LDS)
+            const int nruns = (m + kWave - 1) / kWave;
+            uint64_t v = tid < m ? ((kj << 10) | uint64_t(tid)) : ~0ull;
+            if (w < nruns) {
+#pragma unroll
+                for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+                    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                        const uint64_t o = __shfl_xor((unsigned long long)v, stride, kWave);
+                        const bool keep_min = ((lane & stride) == 0) == ((lane & size) == 0);
+                        v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+                    }
+                }
+            }
+            skey[tid] = v;
+            __syncthreads();
+            if (w < nruns) {
+                int r = lane;
+                for (int rr = 0; rr < nruns; ++rr) {
+                    if (rr == w) continue;
+                    const uint64_t* run = skey + rr * kWave;
+                    int pos = 0;
+#pragma unroll
+                    for (int step = 32; step >= 1; step >>= 1)
+                        if (run[pos + step - 1] < v) pos += step;
+                    if (pos == kWave - 1 && run[kWave - 1] < v) pos = kWave;
+                    r += pos;
+                }
+                if (v != ~0ull) rank_of[v & 1023u] = uint16_t(r);
+            }
+            __syncthreads();
+            if (tid < m) rank = rank_of[tid];
+        } else if (tid < m) {
+            int k = 0;
+            for (; k + 8 <= m; k += 8) {
+                uint64_t u[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) u[e] = kap[k + e];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) rank += (u[e] < kj) || (u[e] == kj && k + e < tid);
+            }
+            for (; k < m; ++k) {
                 const uint64_t u = kap[k];
                 rank += (u < kj) || (u == kj && k < tid);
             }
+        }
+        if (tid < m) {
             skey[rank] = kj;
             scnt[rank] = cnt[tid];
 #pragma unroll
@@ -858,7 +1090,9 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         }
         __syncthreads();
         if (tid < m_entry) lmap[tid] = gmap[lmap[tid]];
-        const int changed = __syncthreads_or(chg) || (mnew != m);
+        if (__ballot(chg) && lane == 0) atomicOr(&flg[2], 1);
+        __syncthreads();
+        const int changed = flg[2] || (mnew != m);
         m = mnew;
         ++tt;
         if (!changed) {

@@ -92,12 +92,26 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict_
     uint32_t val[kSortItems];
     uint32_t rank[kSortItems];
     const uint64_t lt = lanemask_lt();
+    const int64_t wbase = t0 + int64_t(w) * (kWave * kSortItems) + lane;
+    // all loads first, so that the 16 slots' memory latency overlaps
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-        const int64_t pos = t0 + int64_t(w) * (kWave * kSortItems) + i * kWave + lane;
-        const bool valid = pos < n;
-        key[i] = valid ? kin[pos] : K(0);
-        val[i] = valid ? (vin ? vin[pos] : uint32_t(pos)) : 0u;
+        const int64_t pos = wbase + i * kWave;
+        key[i] = pos < n ? kin[pos] : K(0);
+    }
+    if (vin) {
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const int64_t pos = wbase + i * kWave;
+            val[i] = pos < n ? vin[pos] : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) val[i] = uint32_t(wbase + i * kWave);
+    }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const bool valid = wbase + i * kWave < n;
         const uint32_t dgt = uint32_t(key[i] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -130,7 +144,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict_
             gbase[dgt] = dbase[dgt];
         } else {
             lb_store(st, lb_pack(epoch, kFlagAgg, run));
-            const uint64_t excl = lb_exclusive(look + dgt, tile, 256, epoch);
+            const uint64_t excl = lb_exclusive<8>(look + dgt, tile, 256, epoch);
             lb_store(st, lb_pack(epoch, kFlagPrefix, excl + run));
             gbase[dgt] = dbase[dgt] + uint32_t(excl);
         }
@@ -191,7 +205,9 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
         k_clear_u32<<<dim3(kSortMaxPasses), dim3(256), 0, s>>>(sc.hist, kSortMaxPasses * 256);
         int64_t blocks = (n + kSortThreads * 16 - 1) / (kSortThreads * 16);
         if (blocks > 2048) blocks = 2048;
+        const int tk = sc.prof_begin ? sc.prof_begin(sc.prof_ctx, s, "sort_hist") : -1;
         k_sort_hist<K><<<dim3(unsigned(blocks)), dim3(kSortThreads), 0, s>>>(kA, n, np, sc.hist);
+        if (sc.prof_end) sc.prof_end(sc.prof_ctx, s, tk, double(n) * sizeof(K));
     }
     k_sort_bases<<<1, 256, 0, s>>>(sc.hist, sc.dbase, sc.ctr, np);
     K* ki = kA;
@@ -205,9 +221,13 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
             sc.epoch = 0;
         }
         const uint32_t ep = ++sc.epoch;
+        const int tk = sc.prof_begin ? sc.prof_begin(sc.prof_ctx, s, "sort_pass") : -1;
         k_sort_pass<K><<<dim3(unsigned(tiles)), dim3(kSortThreads), 0, s>>>(ki, vi, ko, vo, n, 8 * p,
                                                                             sc.dbase + p * 256, sc.look,
                                                                             sc.ctr + p, ep);
+        // reads keys (and values after the first pass), writes keys and values
+        if (sc.prof_end)
+            sc.prof_end(sc.prof_ctx, s, tk, double(n) * (sizeof(K) + (p ? 4 : 0) + sizeof(K) + 4));
         K* kt = ki;
         ki = ko;
         ko = kt;

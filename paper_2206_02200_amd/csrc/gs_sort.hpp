@@ -11,6 +11,11 @@ constexpr int kSortItems = 16;                           // keys per thread
 constexpr int kSortTile = kSortThreads * kSortItems;     // 4096 keys per tile
 constexpr int kSortMaxPasses = 8;                        // 8-bit digits, up to 64 bits
 
+// Optional timing hooks: begin returns a token (or -1), end closes it with the
+// algorithmic bytes the launch had to move.
+typedef int (*ProfBeginFn)(void* ctx, hipStream_t s, const char* name);
+typedef void (*ProfEndFn)(void* ctx, hipStream_t s, int token, double bytes);
+
 struct SortScratch {
     uint32_t* hist = nullptr;   // [kSortMaxPasses][256] digit histograms
     uint32_t* dbase = nullptr;  // [kSortMaxPasses][256] exclusive digit bases
@@ -18,6 +23,9 @@ struct SortScratch {
     uint64_t* look = nullptr;   // [tiles][256] look-back status words
     int64_t look_tiles = 0;     // capacity of `look` in tiles
     uint32_t epoch = 0;         // last epoch used in `look`
+    void* prof_ctx = nullptr;
+    ProfBeginFn prof_begin = nullptr;
+    ProfEndFn prof_end = nullptr;
 };
 
 inline int sort_passes(int bits) { return (bits + 7) / 8; }

@@ -31,6 +31,7 @@ STATUS = {
 EXPORTED = [
     "gs_abi_version", "gs_last_error", "gs_context_create", "gs_context_destroy",
     "gs_fit", "gs_fit_batched", "gs_copy_modes", "gs_copy_keys",
+    "gs_profile_enable", "gs_profile_reset", "gs_profile_count", "gs_profile_entry",
 ]
 
 
@@ -83,6 +84,15 @@ def load_library(path: str = LIB_PATH):
         lib.gs_copy_modes.restype = ctypes.c_int
         lib.gs_copy_keys.argtypes = [V, V, V]
         lib.gs_copy_keys.restype = ctypes.c_int
+        lib.gs_profile_enable.argtypes = [V, ctypes.c_char_p]
+        lib.gs_profile_enable.restype = ctypes.c_int
+        lib.gs_profile_reset.argtypes = [V]
+        lib.gs_profile_reset.restype = ctypes.c_int
+        lib.gs_profile_count.argtypes = [V]
+        lib.gs_profile_count.restype = I32
+        lib.gs_profile_entry.argtypes = [V, I32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(D),
+                                         ctypes.POINTER(I64), ctypes.POINTER(D)]
+        lib.gs_profile_entry.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -102,6 +112,23 @@ class Context:
             h = ctypes.c_void_p()
             _check(lib.gs_context_create(ctypes.byref(h)))
         self.handle = h
+
+    def profile(self, prefix: str | None = ""):
+        """Time later fits' kernels whose name starts with ``prefix`` (None: off)."""
+        _check(_lib.gs_profile_enable(self.handle, None if prefix is None else prefix.encode()))
+
+    def profile_reset(self):
+        _check(_lib.gs_profile_reset(self.handle))
+
+    def profile_table(self) -> dict:
+        """{kernel: {"ms": total, "launches": n, "bytes": algorithmic bytes}}"""
+        out = {}
+        for i in range(_lib.gs_profile_count(self.handle)):
+            name, ms, nl, by = ctypes.c_char_p(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+            _check(_lib.gs_profile_entry(self.handle, i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(nl),
+                                         ctypes.byref(by)))
+            out[name.value.decode()] = {"ms": ms.value, "launches": nl.value, "bytes": by.value}
+        return out
 
     def close(self):
         if getattr(self, "handle", None):
