@@ -327,39 +327,115 @@ done:
 }
 
 /* ---------------------------------------------------------------------- */
-/* The whole fit.                                                         */
+/* Trajectory tape (for the adjoint of the differentiable form).           */
 /* ---------------------------------------------------------------------- */
 
 /*
- * x        [n][d] row-major binary64 points (f32 data is widened exactly first)
- * h        cell side, finite and > 0
- * max_iter maximum number of shift+merge rounds (>= 0)
- * Outputs (caller-allocated, capacity n for the cluster arrays):
- *   labels [n]      cluster id of every point (ids ascend with final key)
- *   modes  [K][d]   fl(S_c / C_c)
- *   counts [K]      C_c
- *   sums   [K][d]   S_c (may be NULL)
- *   keys   [K][d]   final integer cell keys (may be NULL)
- *   m_hist [max_iter+1] active cells before each round and after the last
- *                   (may be NULL)
- *   K, n_iter (rounds executed), flags (GSO_CONVERGED / STATIONARY / CAPPED)
- * Loop: stop with CONVERGED when no cell has an active neighbour; else stop
- * with CAPPED when max_iter rounds have run; else shift and merge; stop with
- * STATIONARY when the round left keys, counts and sums bitwise unchanged.
+ * The discrete trajectory of one fit: the point -> initial cell map, the
+ * initial sums, and for every round t the cell table it started from (keys,
+ * counts), the integer weights W_j of its shift and its merge map g_t.  The
+ * table of index T is the final one.  With all of it fixed, the map from the
+ * coordinates to the modes is linear (Eq. 1-4 with constant keys, counts,
+ * weights and groups).
  */
-int gso_fit(const double* x, int64_t n, int32_t d, double h, int32_t max_iter,
-            int32_t* labels, double* modes, int64_t* counts, double* sums, int64_t* keys_out,
-            int64_t* m_hist, int64_t* K_out, int32_t* n_iter_out, uint32_t* flags_out)
+typedef struct gso_tape {
+    int64_t n, m0;
+    int32_t d, T;
+    int64_t* cell0;  /* [n] */
+    double* sums0;   /* [m0][d] */
+    int64_t cap;     /* capacity of the per-round arrays, in cells */
+    int32_t off_cap;
+    int64_t* off;    /* [T+2]: round t's table is [off[t], off[t+1]) */
+    int64_t* keys;   /* [.][d] */
+    int64_t* counts;
+    int64_t* W;
+    int64_t* g;
+} gso_tape;
+
+static int tape_push_table(gso_tape* tp, int32_t t, const int64_t* key, const int64_t* cnt, int64_t m, int d)
+{
+    if (t + 2 > tp->off_cap) {
+        int32_t nc = tp->off_cap ? 2 * tp->off_cap : 16;
+        int64_t* o = realloc(tp->off, sizeof(int64_t) * nc);
+        if (!o)
+            return GSO_ERR_ALLOC;
+        tp->off = o;
+        tp->off_cap = nc;
+    }
+    const int64_t start = t == 0 ? 0 : tp->off[t];
+    if (start + m > tp->cap) {
+        int64_t nc = tp->cap ? 2 * tp->cap : 1024;
+        while (nc < start + m)
+            nc *= 2;
+        int64_t* k2 = realloc(tp->keys, sizeof(int64_t) * nc * d);
+        if (!k2)
+            return GSO_ERR_ALLOC;
+        tp->keys = k2;
+        int64_t* c2 = realloc(tp->counts, sizeof(int64_t) * nc);
+        if (!c2)
+            return GSO_ERR_ALLOC;
+        tp->counts = c2;
+        int64_t* w2 = realloc(tp->W, sizeof(int64_t) * nc);
+        if (!w2)
+            return GSO_ERR_ALLOC;
+        tp->W = w2;
+        int64_t* g2 = realloc(tp->g, sizeof(int64_t) * nc);
+        if (!g2)
+            return GSO_ERR_ALLOC;
+        tp->g = g2;
+        tp->cap = nc;
+    }
+    tp->off[t] = start;
+    tp->off[t + 1] = start + m;
+    memcpy(tp->keys + start * d, key, sizeof(int64_t) * m * d);
+    memcpy(tp->counts + start, cnt, sizeof(int64_t) * m);
+    for (int64_t j = 0; j < m; j++) {
+        tp->W[start + j] = 0;
+        tp->g[start + j] = -1;
+    }
+    return GSO_OK;
+}
+
+void gso_tape_free(gso_tape* tp)
+{
+    if (!tp)
+        return;
+    free(tp->cell0);
+    free(tp->sums0);
+    free(tp->off);
+    free(tp->keys);
+    free(tp->counts);
+    free(tp->W);
+    free(tp->g);
+    free(tp);
+}
+
+/* ---------------------------------------------------------------------- */
+/* The whole fit.                                                         */
+/* ---------------------------------------------------------------------- */
+
+static int fit_impl(const double* x, int64_t n, int32_t d, double h, int32_t max_iter, int32_t* labels,
+                    double* modes, int64_t* counts, double* sums, int64_t* keys_out, int64_t* m_hist,
+                    int64_t* K_out, int32_t* n_iter_out, uint32_t* flags_out, gso_tape* tp)
 {
     if (n < 0 || d < 1 || d > 16 || max_iter < 0 || !(h > 0.0) || !isfinite(h))
         return GSO_ERR_INVALID_ARG;
     *K_out = 0;
     *n_iter_out = 0;
     *flags_out = 0;
+    if (tp) {
+        tp->n = n;
+        tp->d = d;
+        tp->T = 0;
+    }
     if (n == 0) {
         *flags_out = GSO_CONVERGED;
         if (m_hist)
             m_hist[0] = 0;
+        if (tp) {
+            tp->m0 = 0;
+            return tape_push_table(tp, 0, NULL, NULL, 0, d);
+        }
         return GSO_OK;
     }
     int rc = GSO_OK;
@@ -367,7 +443,7 @@ int gso_fit(const double* x, int64_t n, int32_t d, double h, int32_t max_iter,
     int64_t* ckey = malloc(sizeof(int64_t) * n * d);
     int64_t* ccnt = malloc(sizeof(int64_t) * n);
     double* csum = malloc(sizeof(double) * n * d);
-    int64_t *cur = NULL, *g = NULL, *nkey = NULL, *ncnt = NULL;
+    int64_t *cur = NULL, *g = NULL, *nkey = NULL, *ncnt = NULL, *W = NULL;
     double *p = NULL, *nsum = NULL;
     if (!cell0 || !ckey || !ccnt || !csum) {
         rc = GSO_ERR_ALLOC;
@@ -381,11 +457,23 @@ int gso_fit(const double* x, int64_t n, int32_t d, double h, int32_t max_iter,
     g = malloc(sizeof(int64_t) * m0);
     nkey = malloc(sizeof(int64_t) * m0 * d);
     ncnt = malloc(sizeof(int64_t) * m0);
+    W = malloc(sizeof(int64_t) * m0);
     p = malloc(sizeof(double) * m0 * d);
     nsum = malloc(sizeof(double) * m0 * d);
-    if (!cur || !g || !nkey || !ncnt || !p || !nsum) {
+    if (!cur || !g || !nkey || !ncnt || !W || !p || !nsum) {
         rc = GSO_ERR_ALLOC;
         goto done;
+    }
+    if (tp) {
+        tp->m0 = m0;
+        tp->cell0 = malloc(sizeof(int64_t) * n);
+        tp->sums0 = malloc(sizeof(double) * m0 * d);
+        if (!tp->cell0 || !tp->sums0) {
+            rc = GSO_ERR_ALLOC;
+            goto done;
+        }
+        memcpy(tp->cell0, cell0, sizeof(int64_t) * n);
+        memcpy(tp->sums0, csum, sizeof(double) * m0 * d);
     }
     for (int64_t c = 0; c < m0; c++)
         cur[c] = c;
@@ -395,6 +483,8 @@ int gso_fit(const double* x, int64_t n, int32_t d, double h, int32_t max_iter,
     for (;;) {
         if (m_hist)
             m_hist[t] = m;
+        if (tp && (rc = tape_push_table(tp, t, ckey, ccnt, m, d)) != GSO_OK)
+            goto done;
         if (!gso_has_neighbours(ckey, m, d)) {
             flags |= GSO_CONVERGED;
             break;
@@ -403,10 +493,14 @@ int gso_fit(const double* x, int64_t n, int32_t d, double h, int32_t max_iter,
             flags |= GSO_CAPPED;
             break;
         }
-        gso_shift(ckey, ccnt, csum, m, d, p, NULL);
+        gso_shift(ckey, ccnt, csum, m, d, p, W);
         int64_t nm = 0;
         if ((rc = gso_merge(ccnt, p, m, d, h, nkey, ncnt, nsum, g, &nm)) != GSO_OK)
             goto done;
+        if (tp) {
+            memcpy(tp->W + tp->off[t], W, sizeof(int64_t) * m);
+            memcpy(tp->g + tp->off[t], g, sizeof(int64_t) * m);
+        }
         int same = (nm == m);
         for (int64_t c = 0; same && c < m; c++) {
             same = (ccnt[c] == ncnt[c]) && cmp_keyvec(ckey + c * d, nkey + c * d, d) == 0;
@@ -424,9 +518,13 @@ int gso_fit(const double* x, int64_t n, int32_t d, double h, int32_t max_iter,
             flags |= GSO_STATIONARY;
             if (m_hist)
                 m_hist[t] = m;
+            if (tp && (rc = tape_push_table(tp, t, ckey, ccnt, m, d)) != GSO_OK)
+                goto done;
             break;
         }
     }
+    if (tp)
+        tp->T = t;
 
     for (int64_t i = 0; i < n; i++)
         labels[i] = (int32_t)cur[cell0[i]];
@@ -452,7 +550,326 @@ done:
     free(g);
     free(nkey);
     free(ncnt);
+    free(W);
     free(p);
     free(nsum);
     return rc;
+}
+
+/*
+ * x        [n][d] row-major binary64 points (f32 data is widened exactly first)
+ * h        cell side, finite and > 0
+ * max_iter maximum number of shift+merge rounds (>= 0)
+ * Outputs (caller-allocated, capacity n for the cluster arrays):
+ *   labels [n]      cluster id of every point (ids ascend with final key)
+ *   modes  [K][d]   fl(S_c / C_c)
+ *   counts [K]      C_c
+ *   sums   [K][d]   S_c (may be NULL)
+ *   keys   [K][d]   final integer cell keys (may be NULL)
+ *   m_hist [max_iter+1] active cells before each round and after the last
+ *                   (may be NULL)
+ *   K, n_iter (rounds executed), flags (GSO_CONVERGED / STATIONARY / CAPPED)
+ * Loop: stop with CONVERGED when no cell has an active neighbour; else stop
+ * with CAPPED when max_iter rounds have run; else shift and merge; stop with
+ * STATIONARY when the round left keys, counts and sums bitwise unchanged.
+ */
+int gso_fit(const double* x, int64_t n, int32_t d, double h, int32_t max_iter,
+            int32_t* labels, double* modes, int64_t* counts, double* sums, int64_t* keys_out,
+            int64_t* m_hist, int64_t* K_out, int32_t* n_iter_out, uint32_t* flags_out)
+{
+    return fit_impl(x, n, d, h, max_iter, labels, modes, counts, sums, keys_out, m_hist, K_out, n_iter_out,
+                    flags_out, NULL);
+}
+
+/* The same fit, also recording the trajectory tape (*tape_out, freed with
+ * gso_tape_free). */
+int gso_fit_tape(const double* x, int64_t n, int32_t d, double h, int32_t max_iter,
+                 int32_t* labels, double* modes, int64_t* counts, double* sums, int64_t* keys_out,
+                 int64_t* m_hist, int64_t* K_out, int32_t* n_iter_out, uint32_t* flags_out, gso_tape** tape_out)
+{
+    gso_tape* tp = calloc(1, sizeof(gso_tape));
+    *tape_out = NULL;
+    if (!tp)
+        return GSO_ERR_ALLOC;
+    int rc = fit_impl(x, n, d, h, max_iter, labels, modes, counts, sums, keys_out, m_hist, K_out, n_iter_out,
+                      flags_out, tp);
+    if (rc != GSO_OK) {
+        gso_tape_free(tp);
+        return rc;
+    }
+    *tape_out = tp;
+    return GSO_OK;
+}
+
+/* Tape accessors: sizes, and copies of one round's table. */
+void gso_tape_sizes(const gso_tape* tp, int64_t* n, int64_t* m0, int32_t* d, int32_t* T)
+{
+    *n = tp->n;
+    *m0 = tp->m0;
+    *d = tp->d;
+    *T = tp->T;
+}
+
+int64_t gso_tape_round_cells(const gso_tape* tp, int32_t t) { return tp->off[t + 1] - tp->off[t]; }
+
+void gso_tape_round(const gso_tape* tp, int32_t t, int64_t* keys, int64_t* counts, int64_t* W, int64_t* g)
+{
+    const int64_t a = tp->off[t], m = tp->off[t + 1] - tp->off[t];
+    memcpy(keys, tp->keys + a * tp->d, sizeof(int64_t) * m * tp->d);
+    memcpy(counts, tp->counts + a, sizeof(int64_t) * m);
+    memcpy(W, tp->W + a, sizeof(int64_t) * m);
+    memcpy(g, tp->g + a, sizeof(int64_t) * m);
+}
+
+void gso_tape_points(const gso_tape* tp, int64_t* cell0, double* sums0)
+{
+    memcpy(cell0, tp->cell0, sizeof(int64_t) * tp->n);
+    memcpy(sums0, tp->sums0, sizeof(double) * tp->m0 * tp->d);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Adjoint along a fixed trajectory.                                       */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * With the tape fixed the modes are mu_c = S^T_c / C_c, S^{t+1}_G =
+ * sum_{j in G} C_j p_j, p_j = N_j / W_j, N_j = sum_{k in N(j)} S^t_k and
+ * S^0_c = sum_{i in c} x_i.  Reverse mode, in the same FP64 order for every
+ * implementation:
+ *   Sbar^T_c = mubar_c / C_c;
+ *   q_j      = (C_j * Sbar^{t+1}_{g_t(j)}) / W_j;
+ *   Sbar^t_k = left fold, over the active cells j+v of round t in ascending
+ *              key (the neighbour relation is symmetric), of q_j;
+ * and the gradient of point i is Sbar^0_{cell0(i)}.
+ * mubar [K][d], sbar0 [m0][d].
+ */
+int gso_tape_adjoint(const gso_tape* tp, const double* mubar, double* sbar0)
+{
+    const int d = tp->d;
+    const int32_t T = tp->T;
+    const int64_t m0 = tp->m0;
+    if (m0 == 0)
+        return GSO_OK;
+    double* sb = malloc(sizeof(double) * m0 * d);
+    double* q = malloc(sizeof(double) * m0 * d);
+    if (!sb || !q) {
+        free(sb);
+        free(q);
+        return GSO_ERR_ALLOC;
+    }
+    {
+        const int64_t a = tp->off[T], K = tp->off[T + 1] - tp->off[T];
+        for (int64_t c = 0; c < K; c++)
+            for (int k = 0; k < d; k++)
+                sb[c * d + k] = mubar[c * d + k] / (double)tp->counts[a + c];
+    }
+    int64_t n_off = 1, v[16], qk[16];
+    for (int k = 0; k < d; k++)
+        n_off *= 3;
+    for (int32_t t = T - 1; t >= 0; t--) {
+        const int64_t a = tp->off[t], m = tp->off[t + 1] - tp->off[t];
+        const int64_t* key = tp->keys + a * d;
+        for (int64_t j = 0; j < m; j++)
+            for (int k = 0; k < d; k++)
+                q[j * d + k] = ((double)tp->counts[a + j] * sb[tp->g[a + j] * d + k]) / (double)tp->W[a + j];
+        for (int64_t kc = 0; kc < m; kc++) {
+            int first = 1;
+            for (int64_t r = 0; r < n_off; r++) {
+                offset_of(r, d, v);
+                for (int k = 0; k < d; k++)
+                    qk[k] = key[kc * d + k] + v[k];
+                const int64_t j = find_cell(key, m, d, qk);
+                if (j < 0)
+                    continue;
+                for (int k = 0; k < d; k++)
+                    sb[kc * d + k] = first ? q[j * d + k] : sb[kc * d + k] + q[j * d + k];
+                first = 0;
+            }
+        }
+    }
+    memcpy(sbar0, sb, sizeof(double) * m0 * d);
+    free(sb);
+    free(q);
+    return GSO_OK;
+}
+
+/* Coordinate sums of every final cluster over its points, as R over the
+ * cluster's initial cells in ascending cell order of their (initial) sums.
+ * X [K][d]. */
+int gso_tape_cluster_sums(const gso_tape* tp, double* X)
+{
+    const int d = tp->d;
+    const int32_t T = tp->T;
+    const int64_t m0 = tp->m0;
+    const int64_t K = tp->off[T + 1] - tp->off[T];
+    if (m0 == 0)
+        return GSO_OK;
+    int64_t* fin = malloc(sizeof(int64_t) * m0);
+    double* tmp = malloc(sizeof(double) * m0);
+    if (!fin || !tmp) {
+        free(fin);
+        free(tmp);
+        return GSO_ERR_ALLOC;
+    }
+    for (int64_t c = 0; c < m0; c++) {
+        int64_t cur = c;
+        for (int32_t t = 0; t < T; t++)
+            cur = tp->g[tp->off[t] + cur];
+        fin[c] = cur;
+    }
+    for (int64_t c = 0; c < K; c++)
+        for (int k = 0; k < d; k++) {
+            int64_t L = 0;
+            for (int64_t c0 = 0; c0 < m0; c0++)
+                if (fin[c0] == c)
+                    tmp[L++] = tp->sums0[c0 * d + k];
+            X[c * d + k] = gso_pairwise_sum(tmp, L);
+        }
+    free(fin);
+    free(tmp);
+    return GSO_OK;
+}
+
+/* Point-to-mode loss L = R over points in ascending index of the left fold
+ * over k of (x_ik - mu_{l(i),k})^2. */
+double gso_point_mode_loss(const double* x, int64_t n, int32_t d, const int32_t* labels, const double* modes)
+{
+    if (n <= 0)
+        return 0.0;
+    double* tmp = malloc(sizeof(double) * n);
+    if (!tmp)
+        return NAN;
+    for (int64_t i = 0; i < n; i++) {
+        double acc = 0.0;
+        for (int k = 0; k < d; k++) {
+            const double e = x[i * d + k] - modes[(int64_t)labels[i] * d + k];
+            acc = k == 0 ? e * e : acc + e * e;
+        }
+        tmp[i] = acc;
+    }
+    const double L = gso_pairwise_sum(tmp, n);
+    free(tmp);
+    return L;
+}
+
+/* ---------------------------------------------------------------------- */
+/* binary128 replay of the loss along a fixed trajectory (for finite        */
+/* differences).                                                          */
+/* ---------------------------------------------------------------------- */
+
+typedef __float128 q128;
+
+static int replay_loss_q(const gso_tape* tp, const double* x, q128* out)
+{
+    const int d = tp->d;
+    const int32_t T = tp->T;
+    const int64_t n = tp->n, m0 = tp->m0;
+    if (n == 0) {
+        *out = 0;
+        return GSO_OK;
+    }
+    q128* S = calloc((size_t)(m0 * d), sizeof(q128));
+    q128* P = malloc(sizeof(q128) * m0 * d);
+    q128* S2 = malloc(sizeof(q128) * m0 * d);
+    int64_t* fin = malloc(sizeof(int64_t) * m0);
+    if (!S || !P || !S2 || !fin) {
+        free(S);
+        free(P);
+        free(S2);
+        free(fin);
+        return GSO_ERR_ALLOC;
+    }
+    for (int64_t i = 0; i < n; i++)
+        for (int k = 0; k < d; k++)
+            S[tp->cell0[i] * d + k] += (q128)x[i * d + k];
+    int64_t n_off = 1, v[16], qk[16];
+    for (int k = 0; k < d; k++)
+        n_off *= 3;
+    for (int32_t t = 0; t < T; t++) {
+        const int64_t a = tp->off[t], m = tp->off[t + 1] - tp->off[t];
+        const int64_t mn = tp->off[t + 2] - tp->off[t + 1];
+        const int64_t* key = tp->keys + a * d;
+        for (int64_t j = 0; j < m; j++) {
+            for (int k = 0; k < d; k++)
+                P[j * d + k] = 0;
+            for (int64_t r = 0; r < n_off; r++) {
+                offset_of(r, d, v);
+                for (int k = 0; k < d; k++)
+                    qk[k] = key[j * d + k] + v[k];
+                const int64_t nb = find_cell(key, m, d, qk);
+                if (nb >= 0)
+                    for (int k = 0; k < d; k++)
+                        P[j * d + k] += S[nb * d + k];
+            }
+            for (int k = 0; k < d; k++)
+                P[j * d + k] /= (q128)tp->W[a + j];
+        }
+        for (int64_t c = 0; c < mn * d; c++)
+            S2[c] = 0;
+        for (int64_t j = 0; j < m; j++)
+            for (int k = 0; k < d; k++)
+                S2[tp->g[a + j] * d + k] += (q128)tp->counts[a + j] * P[j * d + k];
+        memcpy(S, S2, sizeof(q128) * mn * d);
+    }
+    for (int64_t c = 0; c < m0; c++) {
+        int64_t cur = c;
+        for (int32_t t = 0; t < T; t++)
+            cur = tp->g[tp->off[t] + cur];
+        fin[c] = cur;
+    }
+    const int64_t af = tp->off[T];
+    q128 L = 0;
+    for (int64_t i = 0; i < n; i++) {
+        const int64_t c = fin[tp->cell0[i]];
+        const q128 C = (q128)tp->counts[af + c];
+        for (int k = 0; k < d; k++) {
+            const q128 e = (q128)x[i * d + k] - S[c * d + k] / C;
+            L += e * e;
+        }
+    }
+    *out = L;
+    free(S);
+    free(P);
+    free(S2);
+    free(fin);
+    return GSO_OK;
+}
+
+/* Central difference of the replayed loss in coordinate (i, k):
+ * (L(x with x_ik = fl(x_ik + eps)) - L(x with x_ik = fl(x_ik - eps))) / (step),
+ * step being the exact difference of the two perturbed values; binary128
+ * throughout.  The caller checks that both perturbed inputs follow the same
+ * trajectory as x. */
+int gso_tape_fd_q(const gso_tape* tp, const double* x, int64_t i, int32_t k, double eps, double* out)
+{
+    const int d = tp->d;
+    const int64_t n = tp->n;
+    double* xx = malloc(sizeof(double) * n * d);
+    if (!xx)
+        return GSO_ERR_ALLOC;
+    memcpy(xx, x, sizeof(double) * n * d);
+    const double xp = x[i * d + k] + eps, xm = x[i * d + k] - eps;
+    q128 Lp = 0, Lm = 0;
+    xx[i * d + k] = xp;
+    int rc = replay_loss_q(tp, xx, &Lp);
+    xx[i * d + k] = xm;
+    if (rc == GSO_OK)
+        rc = replay_loss_q(tp, xx, &Lm);
+    free(xx);
+    if (rc != GSO_OK)
+        return rc;
+    *out = (double)((Lp - Lm) / ((q128)xp - (q128)xm));
+    return GSO_OK;
+}
+
+/* The replayed loss itself, as hi + lo. */
+int gso_tape_replay_loss(const gso_tape* tp, const double* x, double* hi, double* lo)
+{
+    q128 L = 0;
+    int rc = replay_loss_q(tp, x, &L);
+    if (rc != GSO_OK)
+        return rc;
+    *hi = (double)L;
+    *lo = (double)(L - (q128)*hi);
+    return GSO_OK;
 }

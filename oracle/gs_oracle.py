@@ -44,7 +44,7 @@ class OracleError(RuntimeError):
 def build() -> str:
     """Compile the oracle with gcc (binary64 SSE2 arithmetic, no contraction)."""
     cmd = [
-        "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+        "gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
         "-fno-strict-aliasing", "-shared", "-fPIC", "-Wall", "-Wextra",
         "-o", LIB_PATH + ".tmp", _SRC, "-lm",
     ]
@@ -74,6 +74,31 @@ def _load():
     lib.gso_shift.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, P, P]
     lib.gso_merge.restype = ctypes.c_int
     lib.gso_merge.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, P, P, P, P, P]
+    lib.gso_fit_tape.restype = ctypes.c_int
+    lib.gso_fit_tape.argtypes = [
+        P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+        P, P, P, P, P, P, P, P, P, ctypes.POINTER(P),
+    ]
+    lib.gso_tape_free.restype = None
+    lib.gso_tape_free.argtypes = [P]
+    lib.gso_tape_sizes.restype = None
+    lib.gso_tape_sizes.argtypes = [P, P, P, P, P]
+    lib.gso_tape_round_cells.restype = ctypes.c_int64
+    lib.gso_tape_round_cells.argtypes = [P, ctypes.c_int32]
+    lib.gso_tape_round.restype = None
+    lib.gso_tape_round.argtypes = [P, ctypes.c_int32, P, P, P, P]
+    lib.gso_tape_points.restype = None
+    lib.gso_tape_points.argtypes = [P, P, P]
+    lib.gso_tape_adjoint.restype = ctypes.c_int
+    lib.gso_tape_adjoint.argtypes = [P, P, P]
+    lib.gso_tape_cluster_sums.restype = ctypes.c_int
+    lib.gso_tape_cluster_sums.argtypes = [P, P]
+    lib.gso_point_mode_loss.restype = ctypes.c_double
+    lib.gso_point_mode_loss.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, P]
+    lib.gso_tape_fd_q.restype = ctypes.c_int
+    lib.gso_tape_fd_q.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, P]
+    lib.gso_tape_replay_loss.restype = ctypes.c_int
+    lib.gso_tape_replay_loss.argtypes = [P, P, P, P]
     lib.gso_fit.restype = ctypes.c_int
     lib.gso_fit.argtypes = [
         P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
@@ -203,3 +228,144 @@ def merge(counts, p, h: float) -> tuple[CellTable, np.ndarray]:
         raise OracleError(rc)
     k = nm.value
     return CellTable(nkeys[:k].copy(), ncounts[:k].copy(), nsums[:k].copy()), g[:m].copy()
+
+
+# --------------------------------------------------------------------------
+# differentiable form: trajectory tape, adjoint, point-to-mode loss
+# --------------------------------------------------------------------------
+class Tape:
+    """Discrete trajectory of one fit (owned C object; see gs_oracle.c)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        lib = _load()
+        n, m0, d, T = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        lib.gso_tape_sizes(handle, ctypes.byref(n), ctypes.byref(m0), ctypes.byref(d), ctypes.byref(T))
+        self.n, self.m0, self.d, self.T = n.value, m0.value, d.value, T.value
+        self.cell0 = np.empty(max(self.n, 1), np.int64)
+        self.sums0 = np.empty((max(self.m0, 1), self.d), np.float64)
+        if self.n:
+            lib.gso_tape_points(handle, _ptr(self.cell0), _ptr(self.sums0))
+        self.cell0 = self.cell0[: self.n]
+        self.sums0 = self.sums0[: self.m0]
+        self.rounds = []
+        for t in range(self.T + 1):
+            m = lib.gso_tape_round_cells(handle, t)
+            keys = np.empty((max(m, 1), self.d), np.int64)
+            counts = np.empty(max(m, 1), np.int64)
+            W = np.empty(max(m, 1), np.int64)
+            g = np.empty(max(m, 1), np.int64)
+            if m:
+                lib.gso_tape_round(handle, t, _ptr(keys), _ptr(counts), _ptr(W), _ptr(g))
+            self.rounds.append({"keys": keys[:m], "counts": counts[:m], "W": W[:m], "g": g[:m]})
+
+    def same_trajectory(self, other: "Tape") -> bool:
+        """Identical discrete path: initial cells, and every round's keys,
+        counts, weights and merge maps."""
+        if (self.n, self.m0, self.d, self.T) != (other.n, other.m0, other.d, other.T):
+            return False
+        if not np.array_equal(self.cell0, other.cell0):
+            return False
+        for a, b in zip(self.rounds, other.rounds):
+            for f in ("keys", "counts", "W", "g"):
+                if not np.array_equal(a[f], b[f]):
+                    return False
+        return True
+
+    def adjoint(self, mubar) -> np.ndarray:
+        """Sbar^0 [m0, d] for a mode cotangent mubar [K, d]."""
+        mubar = np.ascontiguousarray(mubar, dtype=np.float64)
+        out = np.zeros((max(self.m0, 1), self.d), np.float64)
+        rc = _load().gso_tape_adjoint(self._h, _ptr(mubar), _ptr(out))
+        if rc:
+            raise OracleError(rc)
+        return out[: self.m0]
+
+    def point_adjoint(self, mubar) -> np.ndarray:
+        """Gradient of sum(mubar * modes) with respect to the points [n, d]."""
+        return self.adjoint(mubar)[self.cell0]
+
+    def cluster_point_sums(self) -> np.ndarray:
+        """[K, d]: sum of the points of every final cluster (R over initial cells)."""
+        K = len(self.rounds[-1]["counts"])
+        X = np.zeros((max(K, 1), self.d), np.float64)
+        rc = _load().gso_tape_cluster_sums(self._h, _ptr(X))
+        if rc:
+            raise OracleError(rc)
+        return X[:K]
+
+    def fd_q(self, x, i: int, k: int, eps: float) -> float:
+        """binary128 central difference of the replayed loss in x[i, k]."""
+        xd = np.ascontiguousarray(x, dtype=np.float64)
+        out = ctypes.c_double()
+        rc = _load().gso_tape_fd_q(self._h, _ptr(xd), int(i), int(k), float(eps), ctypes.byref(out))
+        if rc:
+            raise OracleError(rc)
+        return out.value
+
+    def replay_loss(self, x) -> float:
+        xd = np.ascontiguousarray(x, dtype=np.float64)
+        hi, lo = ctypes.c_double(), ctypes.c_double()
+        rc = _load().gso_tape_replay_loss(self._h, _ptr(xd), ctypes.byref(hi), ctypes.byref(lo))
+        if rc:
+            raise OracleError(rc)
+        return hi.value + lo.value
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _load().gso_tape_free(self._h)
+            self._h = None
+
+
+def fit_tape(x, h: float, max_iter: int = 100) -> tuple[OracleResult, Tape]:
+    """fit() that also records the trajectory tape."""
+    x = np.asarray(x)
+    xd = np.ascontiguousarray(x, dtype=np.float64)
+    n, d = xd.shape
+    cap = max(n, 1)
+    labels = np.empty(cap, np.int32)
+    modes = np.empty((cap, d), np.float64)
+    counts = np.empty(cap, np.int64)
+    sums = np.empty((cap, d), np.float64)
+    keys = np.empty((cap, d), np.int64)
+    m_hist = np.zeros(max_iter + 2, np.int64)
+    K = ctypes.c_int64(0)
+    T = ctypes.c_int32(0)
+    flags = ctypes.c_uint32(0)
+    h_tape = ctypes.c_void_p()
+    rc = _load().gso_fit_tape(
+        _ptr(xd), n, d, float(h), int(max_iter),
+        _ptr(labels), _ptr(modes), _ptr(counts), _ptr(sums), _ptr(keys), _ptr(m_hist),
+        ctypes.byref(K), ctypes.byref(T), ctypes.byref(flags), ctypes.byref(h_tape),
+    )
+    if rc != 0:
+        raise OracleError(rc)
+    k = K.value
+    res = OracleResult(
+        labels=labels[:n].copy(), modes=modes[:k].copy(), counts=counts[:k].copy(),
+        sums=sums[:k].copy(), keys=keys[:k].copy(), m_hist=m_hist[: T.value + 1].copy(),
+        K=k, n_iter=T.value, flags=flags.value,
+    )
+    return res, Tape(h_tape)
+
+
+def point_mode_loss(x, labels, modes) -> float:
+    """L = R over points (ascending) of the left fold over k of (x_ik - mu)^2."""
+    xd = np.ascontiguousarray(x, dtype=np.float64)
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    md = np.ascontiguousarray(modes, dtype=np.float64)
+    n, d = xd.shape
+    return _load().gso_point_mode_loss(_ptr(xd), n, d, _ptr(lab), _ptr(md))
+
+
+def loss_and_grad(x, h: float, max_iter: int = 100):
+    """Point-to-mode loss and its gradient with the trajectory held fixed:
+    grad_i = 2 (x_i - mu_l(i)) + [J^T mubar]_i,  mubar_c = -2 (X_c - C_c mu_c),
+    X_c the sum of the points of cluster c."""
+    xd = np.ascontiguousarray(np.asarray(x), dtype=np.float64)
+    res, tape = fit_tape(xd, h, max_iter)
+    L = point_mode_loss(xd, res.labels, res.modes)
+    X = tape.cluster_point_sums()
+    mubar = -2.0 * (X - res.counts[:, None].astype(np.float64) * res.modes)
+    grad = 2.0 * (xd - res.modes[res.labels]) + tape.point_adjoint(mubar)
+    return L, grad, res, tape

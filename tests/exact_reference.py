@@ -100,3 +100,67 @@ def exact_fit(x, h, max_iter=100):
         "labels": labels, "modes": modes, "counts": counts, "keys": [list(k) for k in ks],
         "n_iter": t, "flags": flags, "margin": margin[0],
     }
+
+
+def exact_jacobian(x, h, max_iter=100):
+    """Exact Jacobian of the modes with respect to the points, with the
+    trajectory of the exact fit held fixed: every cell carries, besides its
+    count, the weight vector w over the points such that its sum is
+    S = sum_i w_i x_i (the same weights for every coordinate).  Binning gives
+    indicator weights; a shift gives (sum of neighbour weights) / W; a merge
+    gives sum C_j * (shifted weights).  Mode c = S_c / C_c, so J_c = w_c / C_c.
+    Returns (J [K][n] of Fractions, margin)."""
+    hq = Fraction(h)
+    pts = [[Fraction(float(v)) for v in row] for row in x]
+    n = len(pts)
+    margin = [None]
+
+    def key(vec):
+        out = []
+        for v in vec:
+            q = v / hq
+            f = floor(q)
+            frac = q - f
+            dist = min(frac, 1 - frac)
+            if margin[0] is None or dist < margin[0]:
+                margin[0] = dist
+            out.append(f)
+        return tuple(out)
+
+    cells = {}
+    for i, p in enumerate(pts):
+        k = key(p)
+        if k not in cells:
+            cells[k] = [0, [Fraction(0)] * len(p), [Fraction(0)] * n]
+        c = cells[k]
+        c[0] += 1
+        c[1] = [s + v for s, v in zip(c[1], p)]
+        c[2][i] += 1
+    t = 0
+    while True:
+        ks = sorted(cells)
+        if not any(_cheb_adjacent(a, b) for a in ks for b in ks if a != b):
+            break
+        if t == max_iter:
+            break
+        moved = {}
+        for j in ks:
+            nb = [k for k in ks if _cheb_adjacent(j, k)]
+            W = sum(cells[k][0] for k in nb)
+            p = [sum(cells[k][1][dd] for k in nb) / W for dd in range(len(cells[j][1]))]
+            pw = [sum(cells[k][2][i] for k in nb) / W for i in range(n)]
+            kap = key(p)
+            C = cells[j][0]
+            if kap not in moved:
+                moved[kap] = [0, [Fraction(0)] * len(p), [Fraction(0)] * n]
+            m = moved[kap]
+            m[0] += C
+            m[1] = [s + C * v for s, v in zip(m[1], p)]
+            m[2] = [s + C * v for s, v in zip(m[2], pw)]
+        same = sorted(moved) == ks and all(moved[k][0] == cells[k][0] and moved[k][1] == cells[k][1] for k in ks)
+        cells = moved
+        t += 1
+        if same:
+            break
+    J = [[w / cells[k][0] for w in cells[k][2]] for k in sorted(cells)]
+    return J, margin[0]
