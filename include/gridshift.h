@@ -139,6 +139,46 @@ gs_status gs_copy_modes(gs_context* ctx, double* modes, int64_t* counts, double*
 gs_status gs_copy_keys(gs_context* ctx, int64_t* keys, void* stream);
 
 /*
+ * Differentiable form.  With the discrete trajectory of a fit held fixed
+ * (initial cells, and every round's neighbour sets, weights W and merge
+ * groups), the modes are a linear function of the points (Eq. 1-4 with
+ * constant keys, counts and groups), with the same weights for every
+ * coordinate.  gs_context_set_tape(ctx, 1) makes later fits record that
+ * trajectory in the context (device memory: the initial cells, and per round
+ * the cell keys, counts, weights and merge maps); the calls below then act on
+ * the context's last fit.  Reverse mode, in binary64 in a fixed order:
+ *   Sbar_c = grad_mode_c / C_c for the final cells;
+ *   for every round, last first:  q_j = (C_j * Sbar_{g(j)}) / W_j  and
+ *   Sbar_k = left fold, over the round's active cells j with Chebyshev key
+ *   distance <= 1 from k, in ascending key, of q_j;
+ *   grad_point_i = Sbar_{initial cell of i}.
+ */
+gs_status gs_context_set_tape(gs_context* ctx, int32_t on);
+
+/* grad_modes device double [sum K][d] (the concatenated cluster rows of
+ * gs_copy_modes); grad_points device double [N][d], overwritten.  Returns
+ * GS_ERR_STATE if the last fit was not recorded. */
+gs_status gs_backward(gs_context* ctx, const double* grad_modes, double* grad_points, void* stream);
+
+/*
+ * Point-to-mode loss of every instance, L_b = sum over its points of
+ * ||x_i - mode(label_i)||^2, summed as R over the points in ascending index of
+ * the left fold over the coordinates.  points and labels are the arrays of
+ * the recorded fit (same layout); loss device double [B].
+ */
+gs_status gs_point_mode_loss(gs_context* ctx, const void* points, const int32_t* labels, double* loss, void* stream);
+
+/*
+ * Gradient of sum_b grad_loss[b] * L_b with respect to the points, the
+ * trajectory held fixed:  grad_i = gL * 2 (x_i - mode_c) + [J^T mubar]_i with
+ * mubar_c = gL * (-2 (X_c - C_c mode_c)), X_c the sum of the points of
+ * cluster c (R over its initial cells' sums in ascending cell order).
+ * grad_loss device double [B]; grad_points device double [N][d], overwritten.
+ */
+gs_status gs_point_mode_loss_backward(gs_context* ctx, const void* points, const int32_t* labels,
+                                      const double* grad_loss, double* grad_points, void* stream);
+
+/*
  * Kernel timing (instrumentation, not part of the method).  When enabled,
  * every kernel launch of later fits whose name starts with `prefix` is
  * bracketed by HIP events on the launch stream; the elapsed times, launch

@@ -312,8 +312,13 @@ class Tape:
         return hi.value + lo.value
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            _load().gso_tape_free(self._h)
+        h = getattr(self, "_h", None)
+        lib = _lib
+        if h and lib is not None:
+            try:
+                lib.gso_tape_free(h)
+            except Exception:
+                pass
             self._h = None
 
 

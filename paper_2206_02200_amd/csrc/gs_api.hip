@@ -73,6 +73,16 @@ struct gs_context {
     std::vector<gs::InstState> st;
     std::vector<gs::InstParam> prm;
     Profiler prof;
+    // differentiable form: trajectory tape of the last fit
+    bool tape_on = false, tape_valid = false;
+    DBuf sums0, inst0, wt_key, wt_cnt, wt_inst, wt_W, wt_g, wt_app;
+    DBuf tt_key, tt_cnt, tt_W, tt_g, tt_m;
+    DBuf sbA, sbB, qbuf, gmodes, modes_i, counts_i, frows, lossc, ltab;
+    DBuf xkA, xkB, xvA, xvB;
+    std::vector<int64_t> w_off, w_M;
+    int64_t wt_used = 0;
+    int tail_rounds = 0, wide_rounds = 0, dtype = 0, sort_bits = 0;
+    int64_t N = 0, ld = 0, m0 = 0;
 };
 
 namespace {
@@ -88,6 +98,28 @@ gs_status ensure(DBuf& b, size_t bytes) {
         (void)hipGetLastError();
         return fail(GS_ERR_ALLOC, "hipMalloc of " + std::to_string(want) + " bytes failed");
     }
+    b.cap = want;
+    return GS_OK;
+}
+
+// Grow a buffer keeping its first `used` bytes (stream-ordered copy).
+gs_status ensure_keep(DBuf& b, size_t bytes, size_t used, hipStream_t s) {
+    if (b.cap >= bytes) return GS_OK;
+    const size_t want = bytes + bytes / 2;
+    void* np = nullptr;
+    if (hipMalloc(&np, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ERR_ALLOC, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    if (b.p && used) {
+        if (hipMemcpyAsync(np, b.p, used, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            (void)hipFree(np);
+            return fail(GS_ERR_DEVICE, "tape copy failed");
+        }
+    }
+    if (b.p) (void)hipFree(b.p);
+    b.p = np;
     b.cap = want;
     return GS_OK;
 }
@@ -340,17 +372,17 @@ gs_status segsum(gs_context* c, int d, Src src, gs::CellTable t, int64_t m_bound
 
 gs_status launch_shift(gs_context* c, int d, gs::CellTable t, int64_t m, const gs::InstParam* prm, gs::InstState* st,
                        const uint64_t* hk, const uint32_t* hv, int logcap, double* pbuf, uint64_t* kappa,
-                       hipStream_t s) {
+                       int32_t* Wout, hipStream_t s) {
     const unsigned g = blocks_for(m, gs::kShiftWaves);  // one wave per cell
     // reads every cell row once, writes p and the landing key
     const int tk = prof_begin(c, s, "shift");
     switch (d) {
-        case 1: gs::k_shift<1><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
-        case 2: gs::k_shift<2><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
-        case 3: gs::k_shift<3><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
-        case 4: gs::k_shift<4><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
-        case 5: gs::k_shift<5><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
-        case 6: gs::k_shift<6><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa); break;
+        case 1: gs::k_shift<1><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa, Wout); break;
+        case 2: gs::k_shift<2><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa, Wout); break;
+        case 3: gs::k_shift<3><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa, Wout); break;
+        case 4: gs::k_shift<4><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa, Wout); break;
+        case 5: gs::k_shift<5><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa, Wout); break;
+        case 6: gs::k_shift<6><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa, Wout); break;
         default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
     }
     prof_end(c, s, tk, double(m) * (8.0 + 8.0 + 4.0 + 8.0 * d) + double(m) * (8.0 * d + 8.0));
@@ -359,15 +391,15 @@ gs_status launch_shift(gs_context* c, int d, gs::CellTable t, int64_t m, const g
 }
 
 gs_status launch_tail(gs_context* c, int d, int B, gs::CellTable t, const gs::InstParam* prm, gs::InstState* st, uint32_t* tmap,
-                      int max_iter, hipStream_t s, double nbytes) {
+                      int max_iter, const gs::TailTape& tape, hipStream_t s, double nbytes) {
     const int tk = prof_begin(c, s, "tail");
     switch (d) {
-        case 1: gs::k_tail<1><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
-        case 2: gs::k_tail<2><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
-        case 3: gs::k_tail<3><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
-        case 4: gs::k_tail<4><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
-        case 5: gs::k_tail<5><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
-        case 6: gs::k_tail<6><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter); break;
+        case 1: gs::k_tail<1><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape); break;
+        case 2: gs::k_tail<2><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape); break;
+        case 3: gs::k_tail<3><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape); break;
+        case 4: gs::k_tail<4><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape); break;
+        case 5: gs::k_tail<5><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape); break;
+        case 6: gs::k_tail<6><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape); break;
         default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
     }
     prof_end(c, s, tk, nbytes);
@@ -500,6 +532,15 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     gs::k_clear_ranges<<<blocks_for(B, 256), 256, 0, s>>>(st, B);
     gs::k_inst_ranges<<<blocks_for(c->capM, 256), 256, 0, s>>>(T0.inst, ctr + 0, st);
     GS_HIP(hipGetLastError());
+    if (c->tape_on && m0 > 0) {  // the initial cells, for the adjoint and the loss
+        GS_TRY(ensure(c->sums0, size_t(m0) * d * 8));
+        GS_TRY(ensure(c->inst0, size_t(m0) * 4));
+        GS_HIP(hipMemcpyAsync(c->sums0.p, T0.sum, size_t(m0) * d * 8, hipMemcpyDeviceToDevice, s));
+        GS_HIP(hipMemcpyAsync(c->inst0.p, T0.inst, size_t(m0) * 4, hipMemcpyDeviceToDevice, s));
+    }
+    c->w_off.clear();
+    c->w_M.clear();
+    c->wt_used = 0;
 
     c->st.assign(B, gs::InstState{});
     GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
@@ -540,8 +581,29 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
                     gs::k_hash_insert<<<blocks_for(M, 256), 256, 0, s>>>(TT.key, M, P<uint64_t>(c->hk),
                                                                           P<uint32_t>(c->hv), logcap));
         GS_HIP(hipGetLastError());
+        int32_t* Wrec = nullptr;
+        int32_t* apprec = nullptr;
+        const int64_t woff = c->wt_used;
+        if (c->tape_on) {  // the round's starting table, weights, merge map and applying instances
+            const size_t used = size_t(woff), need = size_t(woff + M);
+            GS_TRY(ensure_keep(c->wt_key, need * 8, used * 8, s));
+            GS_TRY(ensure_keep(c->wt_cnt, need * 8, used * 8, s));
+            GS_TRY(ensure_keep(c->wt_inst, need * 4, used * 4, s));
+            GS_TRY(ensure_keep(c->wt_W, need * 4, used * 4, s));
+            GS_TRY(ensure_keep(c->wt_g, need * 4, used * 4, s));
+            const size_t r = c->w_off.size();
+            GS_TRY(ensure_keep(c->wt_app, (r + 1) * B * 4, r * B * 4, s));
+            GS_HIP(hipMemcpyAsync(P<uint64_t>(c->wt_key) + woff, TT.key, M * 8, hipMemcpyDeviceToDevice, s));
+            GS_HIP(hipMemcpyAsync(P<int64_t>(c->wt_cnt) + woff, TT.cnt, M * 8, hipMemcpyDeviceToDevice, s));
+            GS_HIP(hipMemcpyAsync(P<int32_t>(c->wt_inst) + woff, TT.inst, M * 4, hipMemcpyDeviceToDevice, s));
+            Wrec = P<int32_t>(c->wt_W) + woff;
+            apprec = P<int32_t>(c->wt_app) + r * B;
+            c->w_off.push_back(woff);
+            c->w_M.push_back(M);
+            c->wt_used = woff + M;
+        }
         GS_TRY(launch_shift(c, d, TT, M, prm, st, P<uint64_t>(c->hk), P<uint32_t>(c->hv), logcap, P<double>(c->pbuf),
-                            P<uint64_t>(c->kappa), s));
+                            P<uint64_t>(c->kappa), Wrec, s));
         gs::k_decide<<<blocks_for(B, 256), 256, 0, s>>>(st, B, max_iter);
         PROF_LAUNCH("merge_prep", M * (8.0 * 3 + 16.0 * d + sizeof(K)),
                     gs::k_merge_prep<K><<<blocks_for(M, 256), 256, 0, s>>>(TT, M, st, st, P<double>(c->pbuf),
@@ -554,6 +616,8 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         k_set_i64<<<1, 1, 0, s>>>(ctr + 3, M);
         gs::HeadsOp<K> op{mk, mperm, U.key, U.start, U.first, P<uint32_t>(c->gmap)};
         GS_TRY(run_scan(c, op, ctr + 3, M, ctr + 0, s, "scan_heads", M * (sizeof(K) + 8.0)));
+        if (c->tape_on)
+            GS_HIP(hipMemcpyAsync(P<uint32_t>(c->wt_g) + woff, c->gmap.p, M * 4, hipMemcpyDeviceToDevice, s));
         PROF_LAUNCH("cell_setup", M * 24.0,
                     gs::k_cell_setup<<<blocks_for(M, 256), 256, 0, s>>>(ctr + 0, M, U, 1, row_off, B, TT.inst, st));
         GS_HIP(hipGetLastError());
@@ -561,7 +625,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         GS_TRY(segsum(c, d, src, U, M, M, s, 4.0 + 4.0 + 8.0 + 8.0 * d));
         PROF_LAUNCH("compose", m0 * 12.0,
                     gs::k_compose<<<blocks_for(m0, 256), 256, 0, s>>>(P<uint32_t>(c->cur), m0, P<uint32_t>(c->gmap)));
-        gs::k_round_end<<<blocks_for(B, 256), 256, 0, s>>>(st, B);
+        gs::k_round_end<<<blocks_for(B, 256), 256, 0, s>>>(st, B, apprec);
         gs::k_clear_ranges<<<blocks_for(B, 256), 256, 0, s>>>(st, B);
         gs::k_inst_ranges<<<blocks_for(M, 256), 256, 0, s>>>(U.inst, ctr + 0, st);
         GS_HIP(hipGetLastError());
@@ -574,7 +638,23 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
 
     // ---- remaining rounds: one LDS-resident workgroup per instance
     gs::CellTable TC = table(c, cur);
-    GS_TRY(launch_tail(c, d, B, TC, prm, st, P<uint32_t>(c->tmap), max_iter, s, 2.0 * M * (16.0 + 8.0 * d)));
+    gs::TailTape tape;
+    if (c->tape_on && max_iter > 0) {
+        const size_t per = size_t(max_iter) * gs::kTailCells;
+        GS_TRY(ensure(c->tt_key, per * B * 8));
+        GS_TRY(ensure(c->tt_cnt, per * B * 4));
+        GS_TRY(ensure(c->tt_W, per * B * 4));
+        GS_TRY(ensure(c->tt_g, per * B * 4));
+        GS_TRY(ensure(c->tt_m, size_t(max_iter) * B * 4));
+        tape.key = P<uint64_t>(c->tt_key);
+        tape.cnt = P<int32_t>(c->tt_cnt);
+        tape.W = P<int32_t>(c->tt_W);
+        tape.g = P<uint32_t>(c->tt_g);
+        tape.m = P<int32_t>(c->tt_m);
+        tape.stride = int64_t(per);
+        tape.max_rounds = max_iter;
+    }
+    GS_TRY(launch_tail(c, d, B, TC, prm, st, P<uint32_t>(c->tmap), max_iter, tape, s, 2.0 * M * (16.0 + 8.0 * d)));
     if (N > 0) {
         PROF_LAUNCH("labels", N * 8.0,
                     gs::k_labels<<<blocks_for(N, 256), 256, 0, s>>>(
@@ -587,6 +667,133 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         c->st[b].m0 = m0_of[b];
     }
     c->cur_tab = cur;
+    c->tail_rounds = max_iter;
+    c->wide_rounds = wide;
+    c->sort_bits = bits;
+    c->m0 = m0;
+    return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// differentiable form
+// ---------------------------------------------------------------------------
+gs_status upload_koff(gs_context* c, hipStream_t s, std::vector<int64_t>& koff) {
+    koff.assign(c->B + 1, 0);
+    for (int b = 0; b < c->B; ++b) koff[b + 1] = koff[b] + c->st[b].K;
+    GS_TRY(ensure(c->koff, sizeof(int64_t) * (c->B + 1)));
+    GS_TRY(h2d(c, c->koff.p, koff.data(), sizeof(int64_t) * (c->B + 1), s));
+    return GS_OK;
+}
+
+gs_status launch_tail_adj(gs_context* c, int d, const gs::TailTape& tape, double* sbar, hipStream_t s) {
+    const gs::InstParam* prm = P<gs::InstParam>(c->param);
+    const gs::InstState* st = P<gs::InstState>(c->state);
+    const int B = c->B;
+    const int tk = prof_begin(c, s, "tail_adj");
+    switch (d) {
+        case 1: gs::k_tail_adj<1><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, c->capM); break;
+        case 2: gs::k_tail_adj<2><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, c->capM); break;
+        case 3: gs::k_tail_adj<3><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, c->capM); break;
+        case 4: gs::k_tail_adj<4><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, c->capM); break;
+        case 5: gs::k_tail_adj<5><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, c->capM); break;
+        case 6: gs::k_tail_adj<6><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, c->capM); break;
+        default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+    }
+    prof_end(c, s, tk, 0.0);
+    GS_HIP(hipGetLastError());
+    return GS_OK;
+}
+
+gs_status launch_adj_stencil(gs_context* c, int d, const uint64_t* key, const int32_t* inst, const int32_t* applied,
+                             int64_t m, const uint64_t* hk, const uint32_t* hv, int logcap, const double* q,
+                             double* out, hipStream_t s) {
+    const gs::InstParam* prm = P<gs::InstParam>(c->param);
+    const unsigned g = blocks_for(m, gs::kShiftWaves);
+    const int64_t cap = c->capM;
+    const int tk = prof_begin(c, s, "adj_stencil");
+    switch (d) {
+        case 1: gs::k_adj_stencil<1><<<g, 256, 0, s>>>(key, inst, applied, m, prm, hk, hv, logcap, q, out, cap); break;
+        case 2: gs::k_adj_stencil<2><<<g, 256, 0, s>>>(key, inst, applied, m, prm, hk, hv, logcap, q, out, cap); break;
+        case 3: gs::k_adj_stencil<3><<<g, 256, 0, s>>>(key, inst, applied, m, prm, hk, hv, logcap, q, out, cap); break;
+        case 4: gs::k_adj_stencil<4><<<g, 256, 0, s>>>(key, inst, applied, m, prm, hk, hv, logcap, q, out, cap); break;
+        case 5: gs::k_adj_stencil<5><<<g, 256, 0, s>>>(key, inst, applied, m, prm, hk, hv, logcap, q, out, cap); break;
+        case 6: gs::k_adj_stencil<6><<<g, 256, 0, s>>>(key, inst, applied, m, prm, hk, hv, logcap, q, out, cap); break;
+        default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+    }
+    prof_end(c, s, tk, double(m) * (8.0 + 8.0 * d) * 2);
+    GS_HIP(hipGetLastError());
+    return GS_OK;
+}
+
+// Reverse of every round: mode cotangents gm [sum K][d] -> Sbar of the
+// initial cells (returned pointer, [d][capM]).
+gs_status adjoint_core(gs_context* c, const double* gm, hipStream_t s, double** sbar0_out) {
+    const int d = c->d, B = c->B;
+    std::vector<int64_t> koff;
+    GS_TRY(upload_koff(c, s, koff));
+    const int64_t rows = koff[B];
+    const size_t cellbytes = size_t(c->capM) * d * 8;
+    GS_TRY(ensure(c->sbA, cellbytes));
+    GS_TRY(ensure(c->sbB, cellbytes));
+    GS_TRY(ensure(c->qbuf, cellbytes));
+    double* sa = P<double>(c->sbA);
+    double* sb = P<double>(c->sbB);
+    gs::CellTable TC = table(c, c->cur_tab);
+    if (rows > 0)
+        PROF_LAUNCH("adj_final", rows * (16.0 * d + 8.0),
+                    gs::k_adj_final<<<blocks_for(rows, 256), 256, 0, s>>>(TC, P<gs::InstState>(c->state),
+                                                                          P<int64_t>(c->koff), B, rows, d, gm, sa));
+    gs::TailTape tape;
+    if (c->tail_rounds > 0) {
+        tape.key = P<uint64_t>(c->tt_key);
+        tape.cnt = P<int32_t>(c->tt_cnt);
+        tape.W = P<int32_t>(c->tt_W);
+        tape.g = P<uint32_t>(c->tt_g);
+        tape.m = P<int32_t>(c->tt_m);
+        tape.stride = int64_t(c->tail_rounds) * gs::kTailCells;
+        tape.max_rounds = c->tail_rounds;
+        GS_TRY(launch_tail_adj(c, d, tape, sa, s));
+    }
+    for (int r = int(c->w_off.size()) - 1; r >= 0; --r) {
+        const int64_t off = c->w_off[r], M = c->w_M[r];
+        const int32_t* applied = P<int32_t>(c->wt_app) + int64_t(r) * B;
+        PROF_LAUNCH("adj_q", M * (24.0 + 16.0 * d),
+                    gs::k_adj_q<<<blocks_for(M, 256), 256, 0, s>>>(
+                        P<int32_t>(c->wt_inst) + off, P<int64_t>(c->wt_cnt) + off, P<int32_t>(c->wt_W) + off,
+                        P<uint32_t>(c->wt_g) + off, applied, M, d, sa, P<double>(c->qbuf), c->capM));
+        int logcap = 1;
+        while ((int64_t(1) << logcap) < 2 * M) ++logcap;
+        const int64_t hcap = int64_t(1) << logcap;
+        GS_TRY(ensure(c->hk, size_t(hcap) * 8));
+        GS_TRY(ensure(c->hv, size_t(hcap) * 4));
+        gs::k_hash_clear<<<blocks_for(hcap, 256), 256, 0, s>>>(P<uint64_t>(c->hk), hcap);
+        gs::k_hash_insert<<<blocks_for(M, 256), 256, 0, s>>>(P<uint64_t>(c->wt_key) + off, M, P<uint64_t>(c->hk),
+                                                              P<uint32_t>(c->hv), logcap);
+        GS_HIP(hipGetLastError());
+        GS_TRY(launch_adj_stencil(c, d, P<uint64_t>(c->wt_key) + off, P<int32_t>(c->wt_inst) + off, applied, M,
+                                  P<uint64_t>(c->hk), P<uint32_t>(c->hv), logcap, P<double>(c->qbuf), sb, s));
+        std::swap(sa, sb);
+    }
+    *sbar0_out = sa;
+    return GS_OK;
+}
+
+gs_status check_tape(gs_context* c) {
+    if (!c) return fail(GS_ERR_INVALID_ARG, "null context");
+    if (!c->has_result || !c->tape_valid)
+        return fail(GS_ERR_STATE, "the context holds no fit recorded with gs_context_set_tape(ctx, 1)");
+    return GS_OK;
+}
+
+// Modes and counts of every cluster row into the context's buffers.
+gs_status cluster_modes(gs_context* c, hipStream_t s, int64_t rows) {
+    GS_TRY(ensure(c->modes_i, size_t(std::max<int64_t>(rows, 1)) * c->d * 8));
+    GS_TRY(ensure(c->counts_i, size_t(std::max<int64_t>(rows, 1)) * 8));
+    if (rows > 0)
+        gs::k_copy_modes<<<blocks_for(rows, 256), 256, 0, s>>>(table(c, c->cur_tab), P<gs::InstState>(c->state),
+                                                               P<int64_t>(c->koff), c->B, rows, c->d,
+                                                               P<double>(c->modes_i), P<int64_t>(c->counts_i), nullptr);
+    GS_HIP(hipGetLastError());
     return GS_OK;
 }
 
@@ -595,6 +802,7 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
                    hipStream_t s) {
     if (!c) return fail(GS_ERR_INVALID_ARG, "null context");
     c->has_result = false;
+    c->tape_valid = false;
     if (d < 1 || d > gs::kMaxDim) return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
     if (B < 1 || !offsets || !h || !info) return fail(GS_ERR_INVALID_ARG, "B >= 1, offsets, h and info are required");
     if (dtype != GS_F32 && dtype != GS_F64) return fail(GS_ERR_INVALID_ARG, "dtype must be GS_F32 or GS_F64");
@@ -696,7 +904,98 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
     }
     c->B = B;
     c->d = d;
+    c->dtype = int(dtype);
+    c->N = N;
+    c->ld = ld;
     c->has_result = true;
+    c->tape_valid = c->tape_on;
+    return GS_OK;
+}
+
+}  // namespace
+
+namespace {
+
+template <typename T>
+static gs_status loss_fwd(gs_context* c, const T* x, const int32_t* labels, double* loss, hipStream_t s) {
+    const int B = c->B;
+    std::vector<int64_t> koff;
+    GS_TRY(upload_koff(c, s, koff));
+    GS_TRY(cluster_modes(c, s, koff[B]));
+    // one "cell" per instance, whose members are its points in index order
+    std::vector<uint32_t> host(4 * size_t(B));
+    for (int b = 0; b < B; ++b) {
+        const int64_t n0 = c->prm[b].row0, n1 = c->prm[b].row1;
+        host[b] = uint32_t(n0);
+        host[B + b] = uint32_t(n1 - n0);
+        host[2 * B + b] = uint32_t((n1 - n0 + gs::kChunk - 1) / gs::kChunk);
+        host[3 * B + b] = 0;
+    }
+    GS_TRY(ensure(c->ltab, host.size() * 4));
+    GS_TRY(ensure(c->lossc, size_t(B) * 8));
+    GS_TRY(h2d(c, c->ltab.p, host.data(), host.size() * 4, s));
+    gs::CellTable t;
+    t.start = P<uint32_t>(c->ltab);
+    t.len = t.start + B;
+    t.nch = t.start + 2 * B;
+    t.choff = t.start + 3 * B;
+    t.sum = loss;
+    t.cnt = P<int64_t>(c->lossc);
+    t.cap = B;
+    int64_t* ctr = P<int64_t>(c->counters);
+    k_set_i64<<<1, 1, 0, s>>>(ctr + 0, B);
+    gs::SrcLoss<T> src{x, c->ld, labels, P<double>(c->modes_i), P<int64_t>(c->rowoff), P<int64_t>(c->koff), B, c->d};
+    return segsum_d<1>(c, src, t, B, c->N, s, 4.0 + 4.0 + c->d * double(sizeof(T)));
+}
+
+template <typename T>
+static gs_status loss_bwd(gs_context* c, const T* x, const int32_t* labels, const double* gloss, double* grad,
+                          hipStream_t s) {
+    const int B = c->B, d = c->d;
+    std::vector<int64_t> koff;
+    GS_TRY(upload_koff(c, s, koff));
+    const int64_t rows = koff[B];
+    GS_TRY(cluster_modes(c, s, rows));
+    const int64_t m0 = c->m0;
+    // point sums of every cluster: R over its initial cells in ascending order
+    GS_TRY(ensure(c->frows, size_t(std::max<int64_t>(m0, 1)) * 4));
+    GS_TRY(ensure(c->xkA, size_t(std::max<int64_t>(m0, 1)) * 4));
+    GS_TRY(ensure(c->xkB, size_t(std::max<int64_t>(m0, 1)) * 4));
+    GS_TRY(ensure(c->xvA, size_t(std::max<int64_t>(m0, 1)) * 4));
+    GS_TRY(ensure(c->xvB, size_t(std::max<int64_t>(m0, 1)) * 4));
+    gs::k_final_rows<<<blocks_for(m0, 256), 256, 0, s>>>(P<int32_t>(c->inst0),
+                                                          c->wide_rounds ? P<uint32_t>(c->cur) : nullptr,
+                                                          P<uint32_t>(c->tmap), P<int64_t>(c->koff), m0,
+                                                          P<uint32_t>(c->xkA));
+    GS_HIP(hipGetLastError());
+    int bits = 0;
+    while ((int64_t(1) << bits) < rows) ++bits;
+    uint32_t* sk = nullptr;
+    uint32_t* sperm = nullptr;
+    GS_HIP(gs::radix_sort<uint32_t>(P<uint32_t>(c->xkA), P<uint32_t>(c->xkB), P<uint32_t>(c->xvA),
+                                    P<uint32_t>(c->xvB), m0, bits, false, c->sort, s, &sk, &sperm));
+    gs::CellTable X = table(c, 1 - c->cur_tab);  // the idle ping-pong table holds the groups
+    int64_t* ctr = P<int64_t>(c->counters);
+    k_set_i64<<<1, 1, 0, s>>>(ctr + 3, m0);
+    gs::HeadsOp<uint32_t> op{sk, sperm, X.key, X.start, X.first, P<uint32_t>(c->frows)};
+    GS_TRY(run_scan(c, op, ctr + 3, m0, ctr + 0, s, "scan_heads", m0 * 12.0));
+    gs::k_cell_setup<<<blocks_for(rows, 256), 256, 0, s>>>(ctr + 0, m0, X, 0, P<int64_t>(c->rowoff), B, nullptr,
+                                                           P<gs::InstState>(c->state));
+    GS_HIP(hipGetLastError());
+    GS_TRY(segsum(c, d, gs::SrcInit{P<double>(c->sums0), sperm, m0}, X, rows, m0, s, 4.0 + 8.0 * d));
+    GS_TRY(ensure(c->gmodes, size_t(std::max<int64_t>(rows, 1)) * d * 8));
+    if (rows > 0)
+        gs::k_loss_mubar<<<blocks_for(rows, 256), 256, 0, s>>>(X.sum, X.cap, P<int64_t>(c->counts_i),
+                                                               P<double>(c->modes_i), P<int64_t>(c->koff), B, rows,
+                                                               d, gloss, P<double>(c->gmodes));
+    GS_HIP(hipGetLastError());
+    double* sb0 = nullptr;
+    GS_TRY(adjoint_core(c, P<double>(c->gmodes), s, &sb0));
+    PROF_LAUNCH("adj_points", c->N * (4.0 + 8.0 * d + d * double(sizeof(T)) + 4.0),
+                gs::k_adj_points<T><<<blocks_for(c->N, 256), 256, 0, s>>>(
+                    P<uint32_t>(c->cell0), sb0, c->capM, c->N, d, grad, x, c->ld, labels, P<double>(c->modes_i),
+                    P<int64_t>(c->rowoff), P<int64_t>(c->koff), B, gloss));
+    GS_HIP(hipGetLastError());
     return GS_OK;
 }
 
@@ -737,6 +1036,11 @@ void gs_context_destroy(gs_context* c) {
     }
     if (c->pinned) (void)hipHostFree(c->pinned);
     for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
+    DBuf* tb2[] = {&c->sums0, &c->inst0, &c->wt_key, &c->wt_cnt, &c->wt_inst, &c->wt_W, &c->wt_g, &c->wt_app,
+                   &c->tt_key, &c->tt_cnt, &c->tt_W, &c->tt_g, &c->tt_m, &c->sbA, &c->sbB, &c->qbuf, &c->gmodes,
+                   &c->modes_i, &c->counts_i, &c->frows, &c->lossc, &c->ltab, &c->xkA, &c->xkB, &c->xvA, &c->xvB};
+    for (DBuf* b : tb2)
+        if (b->p) (void)hipFree(b->p);
     delete c;
 }
 
@@ -781,6 +1085,54 @@ gs_status gs_profile_entry(const gs_context* ctx, int32_t i, const char** name, 
     if (launches) *launches = ctx->prof.launches[i];
     if (bytes) *bytes = ctx->prof.bytes[i];
     return GS_OK;
+}
+
+gs_status gs_context_set_tape(gs_context* ctx, int32_t on) {
+    if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
+    ctx->tape_on = on != 0;
+    return GS_OK;
+}
+
+gs_status gs_backward(gs_context* ctx, const double* grad_modes, double* grad_points, void* stream) {
+    GS_TRY(check_tape(ctx));
+    gs_context* c = ctx;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GS_HIP(hipSetDevice(c->device));
+    if (c->N == 0) return GS_OK;
+    if (!grad_points) return fail(GS_ERR_INVALID_ARG, "grad_points is NULL");
+    double* sb0 = nullptr;
+    GS_TRY(adjoint_core(c, grad_modes, s, &sb0));
+    PROF_LAUNCH("adj_points", c->N * (4.0 + 8.0 * c->d),
+                gs::k_adj_points<float><<<blocks_for(c->N, 256), 256, 0, s>>>(
+                    P<uint32_t>(c->cell0), sb0, c->capM, c->N, c->d, grad_points, nullptr, 0, nullptr, nullptr,
+                    nullptr, nullptr, c->B, nullptr));
+    GS_HIP(hipGetLastError());
+    return GS_OK;
+}
+
+gs_status gs_point_mode_loss(gs_context* ctx, const void* points, const int32_t* labels, double* loss, void* stream) {
+    GS_TRY(check_tape(ctx));
+    gs_context* c = ctx;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GS_HIP(hipSetDevice(c->device));
+    if (!loss) return fail(GS_ERR_INVALID_ARG, "loss is NULL");
+    if (c->N > 0 && (!points || !labels)) return fail(GS_ERR_INVALID_ARG, "points and labels are required");
+    if (c->dtype == GS_F32) return loss_fwd(c, static_cast<const float*>(points), labels, loss, s);
+    return loss_fwd(c, static_cast<const double*>(points), labels, loss, s);
+}
+
+gs_status gs_point_mode_loss_backward(gs_context* ctx, const void* points, const int32_t* labels,
+                                      const double* grad_loss, double* grad_points, void* stream) {
+    GS_TRY(check_tape(ctx));
+    gs_context* c = ctx;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GS_HIP(hipSetDevice(c->device));
+    if (c->N == 0) return GS_OK;
+    if (!points || !labels || !grad_loss || !grad_points)
+        return fail(GS_ERR_INVALID_ARG, "points, labels, grad_loss and grad_points are required");
+    if (c->dtype == GS_F32)
+        return loss_bwd(c, static_cast<const float*>(points), labels, grad_loss, grad_points, s);
+    return loss_bwd(c, static_cast<const double*>(points), labels, grad_loss, grad_points, s);
 }
 
 static gs_status prepare_copy(gs_context* c, hipStream_t s, int64_t* rows) {

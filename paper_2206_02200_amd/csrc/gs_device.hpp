@@ -34,7 +34,7 @@ struct InstState {
     int32_t any_nb;   // some cell had an active neighbour this round
     int32_t changed;  // this round changed keys, counts or sums
     int32_t err;      // error code raised on the device (GS_ERR_*)
-    int32_t pad;
+    int32_t t_tail0;  // rounds executed before the tail workgroup took over
     int64_t cs, ce;   // cell range [cs, ce) in the current cell table
     int64_t K;        // clusters at exit
     int64_t m0;       // cells after binning

@@ -643,7 +643,8 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
                                                                const uint64_t* __restrict__ hk,
                                                                const uint32_t* __restrict__ hv, int logcap,
                                                                double* __restrict__ pbuf,
-                                                               uint64_t* __restrict__ kappa) {
+                                                               uint64_t* __restrict__ kappa,
+                                                               int32_t* __restrict__ Wout) {
     constexpr int NOFF = pow3(D);
     __shared__ int32_t list[kShiftWaves][NOFF];
     const int w = threadIdx.x / kWave, lane = lane_id();
@@ -716,6 +717,7 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
     for (int off = 1; off < 8; off <<= 1) term += __shfl_xor((unsigned long long)term, off, kWave);
     if (lane == 0) {
         kappa[j] = P.base + term;
+        if (Wout) Wout[j] = int32_t(W);
         if (nfound > 1 && __hip_atomic_load(&st[b].any_nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
             atomicOr(&st[b].any_nb, 1);
     }
@@ -773,10 +775,11 @@ __global__ void k_compose(uint32_t* __restrict__ cur, int64_t m0, const uint32_t
     if (c < m0) cur[c] = g[cur[c]];
 }
 
-__global__ void k_round_end(InstState* __restrict__ st, int B) {
+__global__ void k_round_end(InstState* __restrict__ st, int B, int32_t* __restrict__ applied) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     InstState s = st[b];
+    if (applied) applied[b] = s.apply;
     if (s.apply) {
         s.t += 1;
         if (!s.changed) {
@@ -795,7 +798,7 @@ __global__ void k_round_end(InstState* __restrict__ st, int B) {
 template <int D>
 __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstParam* __restrict__ param,
                                                        InstState* __restrict__ st, uint32_t* __restrict__ tmap,
-                                                       int max_iter) {
+                                                       int max_iter, TailTape tape) {
     constexpr int MT = kTailCells;
     constexpr int NW = kTailThreads / kWave;
     __shared__ uint64_t lkey[MT];     // local packed key (key - base), ascending
@@ -822,7 +825,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
     const int m_entry = int(ce - cs);
     if (!S->active) {
         for (int e = tid; e < m_entry; e += kTailThreads) tmap[cs + e] = uint32_t(e);
-        if (tid == 0) S->K = m_entry;
+        if (tid == 0) {
+            S->K = m_entry;
+            S->t_tail0 = S->t;  // no tail round: the adjoint skips this instance's tail
+        }
         return;
     }
     const InstParam& P = param[b];
@@ -852,6 +858,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
 
     int m = m_entry;
     int tt = S->t;
+    const int t_entry = tt;
+    if (tid == 0) S->t_tail0 = t_entry;
     uint32_t flags = S->flags;
     int err = 0;
     const uint64_t lt = lanemask_lt();
@@ -877,6 +885,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         double p[D];
         int32_t q[D];
         uint64_t kj = 0;
+        int32_t Wj = 0;
         if (tid < m) {
             const int32_t c0 = crd[0][tid];
             int a, z;  // cells with dimension-0 coordinate in [c0 - 1, c0 + 1]
@@ -927,6 +936,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
                 }
             }
             nb = nbs > 1;  // the cell itself is always among the candidates
+            Wj = int32_t(W);
 #pragma unroll
             for (int dd = 0; dd < D; ++dd) {
                 p[dd] = p[dd] / double(W);
@@ -1077,7 +1087,17 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
                 nq[dd] = crd[dd][tid];
             }
         }
-        if (tid < m) gmap[tid] = gid_of[rank];
+        if (tid < m) {
+            gmap[tid] = gid_of[rank];
+            if (tape.key) {  // the round's starting table, weights and merge map
+                const int64_t e = int64_t(b) * tape.stride + int64_t(tt - t_entry) * kTailCells + tid;
+                tape.key[e] = lkey[tid];
+                tape.cnt[e] = cnt[tid];
+                tape.W[e] = Wj;
+                tape.g[e] = gid_of[rank];
+                if (tid == 0) tape.m[int64_t(b) * tape.max_rounds + (tt - t_entry)] = m;
+            }
+        }
         __syncthreads();
         if (head) {
             lkey[gid] = nk;
@@ -1119,6 +1139,296 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         S->K = m;
         S->active = 0;
     }
+}
+
+// ===========================================================================
+// adjoint along the recorded trajectory
+// ===========================================================================
+// Sbar of the final cells: the mode cotangent over the count.
+__global__ void k_adj_final(CellTable t, const InstState* __restrict__ st, const int64_t* __restrict__ koff, int B,
+                            int64_t rows, int d, const double* __restrict__ gmodes, double* __restrict__ sbar) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const int b = inst_of_row(koff, B, r);
+    const int64_t c = st[b].cs + (r - koff[b]);
+    const double C = double(t.cnt[c]);
+    for (int k = 0; k < d; ++k) sbar[k * t.cap + c] = gmodes[r * d + k] / C;
+}
+
+// Reverse of the tail rounds of one instance per workgroup: Sbar of the final
+// cells -> Sbar of the cells the tail started from.  For round t (reversed):
+// q_j = (C_j * Sbar_{g(j)}) / W_j, then Sbar_k = left fold in ascending key
+// of q_j over the round's cells j with Chebyshev key distance <= 1.
+template <int D>
+__global__ __launch_bounds__(kTailThreads) void k_tail_adj(const InstParam* __restrict__ param,
+                                                           const InstState* __restrict__ st, TailTape tape,
+                                                           double* __restrict__ sbar, int64_t cap) {
+    constexpr int MT = kTailCells;
+    __shared__ int32_t crd[D][MT];
+    __shared__ int32_t cnt[MT];
+    __shared__ int32_t Wt[MT];
+    __shared__ uint16_t gt[MT];
+    __shared__ double A[D][MT];
+    __shared__ double Q[D][MT];
+    __shared__ uint16_t slab[kSlabMax + 1];
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x;
+    const InstState S = st[b];
+    const int rounds = S.t - S.t_tail0;
+    if (rounds <= 0) return;  // nothing ran in the tail: Sbar is already that of its entry cells
+    const InstParam& P = param[b];
+    int64_t E[D];
+    uint64_t stride[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        E[k] = P.E[k];
+        stride[k] = P.stride[k];
+    }
+    const int E0 = int(E[0]);
+    const bool use_slab = E0 <= kSlabMax;
+    int mnext = int(S.K);
+    if (tid < mnext)
+#pragma unroll
+        for (int k = 0; k < D; ++k) A[k][tid] = sbar[k * cap + S.cs + tid];
+    int m = 0;
+    for (int tl = rounds - 1; tl >= 0; --tl) {
+        m = tape.m[int64_t(b) * tape.max_rounds + tl];
+        const int64_t e0 = int64_t(b) * tape.stride + int64_t(tl) * kTailCells;
+        __syncthreads();  // A of the later round is complete; the previous round's reads are done
+        if (tid < m) {
+            const uint64_t lk = tape.key[e0 + tid];
+#pragma unroll
+            for (int k = 0; k < D; ++k) crd[k][tid] = int32_t((lk / stride[k]) % uint64_t(E[k]));
+            const int32_t C = tape.cnt[e0 + tid];
+            const int32_t W = tape.W[e0 + tid];
+            const uint32_t g = tape.g[e0 + tid];
+            cnt[tid] = C;
+            Wt[tid] = W;
+            gt[tid] = uint16_t(g);
+#pragma unroll
+            for (int k = 0; k < D; ++k) Q[k][tid] = (double(C) * A[k][g]) / double(W);
+        }
+        __syncthreads();
+        if (use_slab && tid < m) {
+            const int hi = crd[0][tid];
+            const int lo = tid == 0 ? 0 : crd[0][tid - 1] + 1;
+            for (int c = lo; c <= hi; ++c) slab[c] = uint16_t(tid);
+            if (tid == m - 1)
+                for (int c = hi + 1; c <= E0; ++c) slab[c] = uint16_t(m);
+        }
+        __syncthreads();
+        if (tid < m) {
+            const int32_t c0 = crd[0][tid];
+            int a, z;
+            if (use_slab) {
+                a = slab[c0 - 1 < 0 ? 0 : c0 - 1];
+                z = slab[c0 + 2 > E0 ? E0 : c0 + 2];
+            } else {
+                a = 0;
+                z = m;
+                while (a < z) {
+                    const int mid = (a + z) >> 1;
+                    if (crd[0][mid] < c0 - 1) a = mid + 1; else z = mid;
+                }
+                z = a;
+                while (z < m && crd[0][z] <= c0 + 1) ++z;
+            }
+            int32_t me[D];
+#pragma unroll
+            for (int dd = 1; dd < D; ++dd) me[dd] = crd[dd][tid];
+            double acc[D];
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) acc[dd] = -0.0;
+            for (int k0 = a; k0 < z; k0 += 4) {
+                int okm[4], kk[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    kk[u] = (k0 + u < z) ? k0 + u : k0;
+                    okm[u] = (k0 + u < z) ? 1 : 0;
+                }
+#pragma unroll
+                for (int dd = 1; dd < D; ++dd) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) okm[u] &= (uint32_t(crd[dd][kk[u]] - me[dd] + 1) <= 2u) ? 1 : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool ok = okm[u] != 0;
+#pragma unroll
+                    for (int dd = 0; dd < D; ++dd) acc[dd] = acc[dd] + (ok ? Q[dd][kk[u]] : -0.0);
+                }
+            }
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) A[dd][tid] = acc[dd];
+        }
+        mnext = m;
+    }
+    __syncthreads();
+    if (tid < m)
+#pragma unroll
+        for (int k = 0; k < D; ++k) sbar[k * cap + S.cs + tid] = A[k][tid];
+}
+
+// Wide round r, reversed: q_j from the later round's Sbar (identity for
+// instances that did not apply the round).
+__global__ void k_adj_q(const int32_t* __restrict__ inst, const int64_t* __restrict__ cnt,
+                        const int32_t* __restrict__ W, const uint32_t* __restrict__ g,
+                        const int32_t* __restrict__ applied, int64_t m, int d, const double* __restrict__ sbar,
+                        double* __restrict__ q, int64_t cap) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t gj = g[j];
+    if (applied[inst[j]]) {
+        const double C = double(cnt[j]), Wd = double(W[j]);
+        for (int k = 0; k < d; ++k) q[k * cap + j] = (C * sbar[k * cap + gj]) / Wd;
+    } else {
+        for (int k = 0; k < d; ++k) q[k * cap + j] = sbar[k * cap + gj];
+    }
+}
+
+// Wide round r, reversed: Sbar_k = fold over the 3^D neighbour keys (ascending)
+// of q; one wave per cell, the probes in parallel as in k_shift.
+template <int D>
+__global__ __launch_bounds__(kShiftWaves * kWave) void k_adj_stencil(const uint64_t* __restrict__ key,
+                                                                     const int32_t* __restrict__ inst,
+                                                                     const int32_t* __restrict__ applied, int64_t m,
+                                                                     const InstParam* __restrict__ param,
+                                                                     const uint64_t* __restrict__ hk,
+                                                                     const uint32_t* __restrict__ hv, int logcap,
+                                                                     const double* __restrict__ q,
+                                                                     double* __restrict__ out, int64_t cap) {
+    constexpr int NOFF = pow3(D);
+    __shared__ int32_t list[kShiftWaves][NOFF];
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int64_t j = int64_t(blockIdx.x) * kShiftWaves + w;
+    if (j >= m) return;
+    const int b = inst[j];
+    if (!applied[b]) {
+        if (lane < D) out[int64_t(lane) * cap + j] = q[int64_t(lane) * cap + j];
+        return;
+    }
+    const InstParam& P = param[b];
+    const uint64_t kj = key[j];
+    const uint64_t local = kj - P.base;
+    int64_t crd[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) crd[k] = int64_t((local / P.stride[k]) % uint64_t(P.E[k]));
+    const uint64_t lt = lanemask_lt();
+    int nfound = 0;
+    for (int r0 = 0; r0 < NOFF; r0 += kWave) {
+        const int r = r0 + lane;
+        int64_t idx = -1;
+        if (r < NOFF) {
+            int rr = r;
+            bool inside = true;
+            uint64_t nk = kj;
+#pragma unroll
+            for (int k = D - 1; k >= 0; --k) {
+                const int v = rr % 3 - 1;
+                rr /= 3;
+                const int64_t c = crd[k] + v;
+                inside = inside && c >= 0 && c < P.E[k];
+                nk += uint64_t(int64_t(v)) * P.stride[k];
+            }
+            if (inside) idx = hash_find(hk, hv, nk, logcap);
+        }
+        const uint64_t bal = __ballot(idx >= 0);
+        if (idx >= 0) list[w][nfound + __popcll(bal & lt)] = int32_t(idx);
+        nfound += __popcll(bal);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < D) {
+        const double* col = q + int64_t(lane) * cap;
+        double acc = -0.0;
+        for (int e = 0; e < nfound; ++e) acc = acc + col[list[w][e]];
+        out[int64_t(lane) * cap + j] = acc;
+    }
+}
+
+// Gradient of the points: the Sbar of their initial cell, plus (for the loss)
+// the direct term gL * (2 * (x - mode)).
+template <typename T>
+__global__ void k_adj_points(const uint32_t* __restrict__ cell0, const double* __restrict__ sbar0, int64_t cap,
+                             int64_t n, int d, double* __restrict__ grad, const T* __restrict__ x, int64_t ld,
+                             const int32_t* __restrict__ labels, const double* __restrict__ modes,
+                             const int64_t* __restrict__ row_off, const int64_t* __restrict__ koff, int B,
+                             const double* __restrict__ gloss) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t c = cell0[i];
+    if (!x) {
+        for (int k = 0; k < d; ++k) grad[i * d + k] = sbar0[k * cap + c];
+        return;
+    }
+    const int b = inst_of_row(row_off, B, i);
+    const int64_t r = koff[b] + labels[i];
+    const double gl = gloss[b];
+    for (int k = 0; k < d; ++k) {
+        const double direct = gl * (2.0 * (load_coord(x, i, ld, k) - modes[r * d + k]));
+        grad[i * d + k] = direct + sbar0[k * cap + c];
+    }
+}
+
+// ===========================================================================
+// point-to-mode loss
+// ===========================================================================
+// Member p of instance b's "cell" is point p: value = left fold over k of
+// (x_pk - mode_k)^2 of its cluster's mode.
+template <typename T>
+struct SrcLoss {
+    const T* x;
+    int64_t ld;
+    const int32_t* labels;
+    const double* modes;    // [sum K][d]
+    const int64_t* row_off;
+    const int64_t* koff;
+    int B;
+    int d;
+    __device__ int64_t load(int64_t p, double* v, int) const {
+        const int b = inst_of_row(row_off, B, p);
+        const int64_t r = koff[b] + labels[p];
+        double acc = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double e = load_coord(x, p, ld, k) - modes[r * d + k];
+            acc = k == 0 ? e * e : acc + e * e;
+        }
+        v[0] = acc;
+        return 1;
+    }
+};
+
+// Member p of a cluster group is initial cell perm[p]: its initial sums.
+struct SrcInit {
+    const double* sums0;  // [d][m0]
+    const uint32_t* perm;
+    int64_t m0;
+    __device__ int64_t load(int64_t p, double* v, int d) const {
+        const int64_t c = perm[p];
+        for (int k = 0; k < d; ++k) v[k] = sums0[k * m0 + c];
+        return 1;
+    }
+};
+
+// Final cluster row of every initial cell.
+__global__ void k_final_rows(const int32_t* __restrict__ inst0, const uint32_t* __restrict__ cur,
+                             const uint32_t* __restrict__ tmap, const int64_t* __restrict__ koff, int64_t m0,
+                             uint32_t* __restrict__ rows) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= m0) return;
+    const uint32_t cc = cur ? cur[c] : uint32_t(c);
+    rows[c] = uint32_t(koff[inst0[c]] + tmap[cc]);
+}
+
+// mubar_c = gL_b * (-2 * (X_c - C_c * mode_c)) for every cluster row.
+__global__ void k_loss_mubar(const double* __restrict__ X, int64_t xcap, const int64_t* __restrict__ counts,
+                             const double* __restrict__ modes, const int64_t* __restrict__ koff, int B, int64_t rows,
+                             int d, const double* __restrict__ gloss, double* __restrict__ mubar) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const int b = inst_of_row(koff, B, r);
+    const double C = double(counts[r]);
+    for (int k = 0; k < d; ++k)
+        mubar[r * d + k] = gloss[b] * (-2.0 * (X[k * xcap + r] - C * modes[r * d + k]));
 }
 
 // ===========================================================================

@@ -28,4 +28,16 @@ struct CellTable {
     int64_t cap = 0;
 };
 
+// Per-round record of the tail rounds of every instance (for the adjoint):
+// round tl of instance b occupies entries [b * stride + tl * kTailCells, ...).
+struct TailTape {
+    uint64_t* key = nullptr;  // local packed key of the cells the round started from
+    int32_t* cnt = nullptr;   // their counts
+    int32_t* W = nullptr;     // their shift weights
+    uint32_t* g = nullptr;    // their merge map
+    int32_t* m = nullptr;     // [B][max_rounds] cells of each round
+    int64_t stride = 0;       // entries per instance
+    int32_t max_rounds = 0;
+};
+
 }  // namespace gs

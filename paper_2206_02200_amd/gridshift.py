@@ -32,6 +32,7 @@ EXPORTED = [
     "gs_abi_version", "gs_last_error", "gs_context_create", "gs_context_destroy",
     "gs_fit", "gs_fit_batched", "gs_copy_modes", "gs_copy_keys",
     "gs_profile_enable", "gs_profile_reset", "gs_profile_count", "gs_profile_entry",
+    "gs_context_set_tape", "gs_backward", "gs_point_mode_loss", "gs_point_mode_loss_backward",
 ]
 
 
@@ -93,6 +94,14 @@ def load_library(path: str = LIB_PATH):
         lib.gs_profile_entry.argtypes = [V, I32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(D),
                                          ctypes.POINTER(I64), ctypes.POINTER(D)]
         lib.gs_profile_entry.restype = ctypes.c_int
+        lib.gs_context_set_tape.argtypes = [V, I32]
+        lib.gs_context_set_tape.restype = ctypes.c_int
+        lib.gs_backward.argtypes = [V, V, V, V]
+        lib.gs_backward.restype = ctypes.c_int
+        lib.gs_point_mode_loss.argtypes = [V, V, V, V, V]
+        lib.gs_point_mode_loss.restype = ctypes.c_int
+        lib.gs_point_mode_loss_backward.argtypes = [V, V, V, V, V, V]
+        lib.gs_point_mode_loss_backward.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -112,6 +121,10 @@ class Context:
             h = ctypes.c_void_p()
             _check(lib.gs_context_create(ctypes.byref(h)))
         self.handle = h
+
+    def set_tape(self, on: bool = True):
+        """Record the trajectory of later fits (needed by the backward calls)."""
+        _check(_lib.gs_context_set_tape(self.handle, 1 if on else 0))
 
     def profile(self, prefix: str | None = ""):
         """Time later fits' kernels whose name starts with ``prefix`` (None: off)."""
@@ -250,3 +263,109 @@ def fit_batched(x: torch.Tensor, offsets, h, max_iter: int = 100, *, with_sums: 
     _check(lib.gs_copy_modes(ctx.handle, ctypes.c_void_p(modes.data_ptr()), ctypes.c_void_p(counts.data_ptr()),
                              ctypes.c_void_p(sums.data_ptr() if sums is not None else 0), sp))
     return BatchedResult(labels, modes, counts, koff, [infos[b].as_dict() for b in range(B)], sums)
+
+
+# ---------------------------------------------------------------------------
+# differentiable form
+# ---------------------------------------------------------------------------
+def _vp(t: torch.Tensor | None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def backward_modes(ctx: Context, grad_modes: torch.Tensor, n: int, d: int, stream=None) -> torch.Tensor:
+    """Gradient of sum(grad_modes * modes) with respect to the points of the
+    context's last (recorded) fit; float64 [n, d]."""
+    g = grad_modes.to(torch.float64).contiguous()
+    out = torch.empty((n, d), dtype=torch.float64, device=g.device)
+    _check(_lib.gs_backward(ctx.handle, _vp(g), _vp(out), _stream_ptr(stream)))
+    return out
+
+
+def point_mode_loss_values(ctx: Context, x: torch.Tensor, labels: torch.Tensor, B: int, stream=None) -> torch.Tensor:
+    """Per-instance loss sum_i ||x_i - mode(label_i)||^2 of the last recorded fit."""
+    x, _, _ = _points(x)
+    loss = torch.empty(B, dtype=torch.float64, device=x.device)
+    _check(_lib.gs_point_mode_loss(ctx.handle, _vp(x), _vp(labels), _vp(loss), _stream_ptr(stream)))
+    return loss
+
+
+def point_mode_loss_grad(ctx: Context, x: torch.Tensor, labels: torch.Tensor, grad_loss: torch.Tensor,
+                         stream=None) -> torch.Tensor:
+    """Gradient of sum_b grad_loss[b] * L_b with respect to the points (float64)."""
+    x, _, _ = _points(x)
+    gl = grad_loss.to(torch.float64).contiguous()
+    out = torch.empty(x.shape, dtype=torch.float64, device=x.device)
+    _check(_lib.gs_point_mode_loss_backward(ctx.handle, _vp(x), _vp(labels), _vp(gl), _vp(out),
+                                            _stream_ptr(stream)))
+    return out
+
+
+def _fit_any(x, offsets, h, max_iter, ctx):
+    if offsets is None:
+        r = fit(x, h, max_iter, ctx=ctx)
+        return r.labels, r.modes, r.counts, np.array([0, r.modes.shape[0]], dtype=np.int64), [r.info]
+    r = fit_batched(x, offsets, h, max_iter, ctx=ctx)
+    return r.labels, r.modes, r.counts, r.k_offsets, r.infos
+
+
+class GridShiftModes(torch.autograd.Function):
+    """modes, labels, counts = GridShiftModes.apply(x, h, max_iter, offsets, ctx)
+
+    Forward: the GridShift fit of x (one point set, or B concatenated ones when
+    ``offsets`` is given), recording its trajectory.  Backward: the adjoint of
+    the shift-and-merge rounds with that trajectory held fixed.  labels and
+    counts are not differentiable.  A context, if given, must not run another
+    fit before the backward pass."""
+
+    @staticmethod
+    def forward(actx, x, h, max_iter=100, offsets=None, ctx=None):
+        gctx = ctx or Context(x.device.index)
+        gctx.set_tape(True)
+        labels, modes, counts, koff, infos = _fit_any(x, offsets, h, max_iter, gctx)
+        actx.gctx = gctx
+        actx.shape = tuple(x.shape)
+        actx.x_dtype = x.dtype
+        actx.mark_non_differentiable(labels, counts)
+        return modes, labels, counts
+
+    @staticmethod
+    def backward(actx, g_modes, g_labels, g_counts):
+        n, d = actx.shape
+        grad = backward_modes(actx.gctx, g_modes, n, d)
+        return grad.to(actx.x_dtype), None, None, None, None
+
+
+class PointModeLoss(torch.autograd.Function):
+    """loss = PointModeLoss.apply(x, h, max_iter, offsets, ctx)
+
+    loss[b] = sum over the points of instance b of ||x_i - mode(label_i)||^2
+    after a GridShift fit; the gradient holds the fit's trajectory fixed (the
+    direct term 2 (x_i - mode) plus the adjoint of the modes)."""
+
+    @staticmethod
+    def forward(actx, x, h, max_iter=100, offsets=None, ctx=None):
+        gctx = ctx or Context(x.device.index)
+        gctx.set_tape(True)
+        labels, modes, counts, koff, infos = _fit_any(x, offsets, h, max_iter, gctx)
+        B = 1 if offsets is None else len(offsets) - 1
+        loss = point_mode_loss_values(gctx, x, labels, B)
+        actx.gctx = gctx
+        actx.save_for_backward(x, labels)
+        actx.x_dtype = x.dtype
+        return loss
+
+    @staticmethod
+    def backward(actx, g_loss):
+        x, labels = actx.saved_tensors
+        grad = point_mode_loss_grad(actx.gctx, x, labels, g_loss)
+        return grad.to(actx.x_dtype), None, None, None, None
+
+
+def point_mode_loss(x, h, max_iter=100, offsets=None, ctx=None):
+    """Differentiable point-to-mode loss (per instance, float64)."""
+    return PointModeLoss.apply(x, h, max_iter, offsets, ctx)
+
+
+def gridshift_modes(x, h, max_iter=100, offsets=None, ctx=None):
+    """Differentiable modes (float64) with labels and counts."""
+    return GridShiftModes.apply(x, h, max_iter, offsets, ctx)
