@@ -9,9 +9,16 @@ resident in HBM before the timed region; one step is one complete gs_fit
 
 Prints one JSON line with points/s, the roofline of the dominant kernel
 (algorithmic bytes per launch over its HIP-event-timed average duration) and
-the FP64 oracle timed on the host cores as the CPU baseline.
+the FP64 oracle timed on the host cores as the CPU baseline.  The same line
+carries, under "forms", the other two forms of the workload family:
+  batched  256 Voronoi images of uneven size (heights 240..1080, widths
+           320..1920, 5..60 regions, noise 4..12), RGB float32, per-image
+           h in {12, 16, 24}, one gs_fit_batched call;
+  fwd_bwd  64 Voronoi images of 512x512, (x, y, L, a, b) float32, h = 16:
+           the point-to-mode loss and its gradient (fit with the trajectory
+           recorded, loss, backward).
 
-  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--forms plain,batched,fwd_bwd]
 """
 from __future__ import annotations
 
@@ -73,7 +80,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="plain,batched,fwd_bwd")
     args = ap.parse_args()
+    forms = set(args.forms.split(","))
     if args.gpus != 1:
         print("bench.py measures one GPU only: the GridShift fit here runs on a single MI355X; "
               "run it with --gpus 1", file=sys.stderr)
@@ -165,11 +174,83 @@ def main() -> int:
         },
         "kernels_ms_per_step": {kk: vv["ms"] / 3 for kk, vv in sorted(full.items(), key=lambda t: -t[1]["ms"])},
     }
+    out["forms"] = {"plain": {"value": value, "unit": "points/s", "ms_per_step": ms_per_step,
+                              "hbm_GBps_alg": out["hbm_GBps_step_alg"]}}
+    if "batched" in forms:
+        out["forms"]["batched"] = bench_batched(ctx, dev, max(1, args.steps // 10))
+    if "fwd_bwd" in forms:
+        out["forms"]["fwd_bwd"] = bench_fwd_bwd(dev, max(1, args.steps // 10))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
+
+
+def bench_batched(ctx, dev, steps: int) -> dict:
+    import numpy as np
+    import torch
+
+    from paper_2206_02200_amd import gridshift, synth
+
+    specs = synth.batch_specs()
+    X, off, hs = synth.batch_rgb_torch(specs, dev)
+    n = int(off[-1])
+    r = gridshift.fit_batched(X, off, hs, 100, ctx=ctx)  # warm-up (allocations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = gridshift.fit_batched(X, off, hs, 100, ctx=ctx)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    rounds = [i["n_iter"] for i in r.infos]
+    cells0 = sum(i["n_cells0"] for i in r.infos)
+    k = int(r.k_offsets[-1])
+    b_alg = n * (3 * 4 + 12) + 2 * cells0 * (16 + 8 * 3) + k * (8 * 3 + 8)
+    return {
+        "value": n / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "steps": steps,
+        "workload": "256 Voronoi images, H 240..1080, W 320..1920, 5..60 regions, sigma 4..12, RGB f32, "
+                    "h in {12,16,24}, max_iter=100, one batched call",
+        "n": n, "B": len(specs), "cells0": cells0, "clusters": k, "rounds_max": max(rounds),
+        "rounds_mean": float(np.mean(rounds)), "capped": int(sum(1 for i in r.infos if i["flags"] & 4)),
+        "hbm_GBps_alg": b_alg / (ms * 1e-3) / 1e9,
+    }
+
+
+def bench_fwd_bwd(dev, steps: int) -> dict:
+    import torch
+
+    from paper_2206_02200_amd import gridshift, synth
+
+    B = 64
+    X, off = synth.diff_batch_torch(B, dev)
+    n = int(off[-1])
+    gctx = gridshift.Context(0)
+    x = X.clone().requires_grad_(True)
+
+    def step():
+        x.grad = None
+        loss = gridshift.point_mode_loss(x, 16.0, 100, off, gctx)
+        loss.sum().backward()
+        return loss
+
+    loss = step()  # warm-up (allocations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    # points read twice (fit, loss) plus the backward's read of x, labels and cell map and its f64 write
+    b_alg = n * (5 * 4 + 12) + n * (5 * 4 + 4) + n * (4 + 5 * 4 + 4 + 8 * 5)
+    out = {
+        "value": n / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "steps": steps,
+        "workload": "64 Voronoi images 512x512, 30 regions, ramps, sigma 6, (x,y,L,a,b) f32, h=16, "
+                    "point-to-mode loss forward + backward (trajectory recorded every round)",
+        "n": n, "B": B, "loss_mean": float(loss.detach().mean()), "hbm_GBps_alg": b_alg / (ms * 1e-3) / 1e9,
+    }
+    gctx.close()
+    return out
 
 
 if __name__ == "__main__":

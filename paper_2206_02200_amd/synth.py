@@ -13,8 +13,10 @@ Those datasets are not available here, so these generators stand in for them:
   sigma uniform in [1, 3], Dirichlet(1) weights, multinomial counts, points
   shuffled by a seeded permutation.
 
-All randomness is numpy PCG64 from an explicit seed.  This module holds no
-GridShift arithmetic; both the oracle side and the GPU side read its output.
+All randomness comes from explicit seeds: numpy PCG64, plus a seeded torch
+generator for the pixel noise of the device-side variants used for the large
+batched workloads.  This module holds no GridShift arithmetic; both the oracle
+side and the GPU side read its output.
 """
 from __future__ import annotations
 
@@ -197,3 +199,79 @@ def separated_blobs(k: int, d: int, per: int, h: float, seed: int, spacing: floa
     x = centres[truth] + sigma_frac * h * z
     perm = rng.permutation(k * per)
     return x[perm], truth[perm]
+
+
+# --------------------------------------------------------------------------
+# device-side generation of the large batched workloads (same recipe; the
+# region parameters come from numpy PCG64, the pixel noise from a seeded
+# torch generator on the device)
+# --------------------------------------------------------------------------
+def voronoi_rgb_torch(H: int, W: int, regions: int, sigma: float, ramp: float, seed: int, device):
+    """[H*W, 3] float64 RGB in raster order, computed with torch on `device`."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    sx = torch.tensor(rng.uniform(0.0, W, size=regions), dtype=torch.float64, device=device)
+    sy = torch.tensor(rng.uniform(0.0, H, size=regions), dtype=torch.float64, device=device)
+    mu = torch.tensor(rng.uniform(0.0, 255.0, size=(regions, 3)), dtype=torch.float64, device=device)
+    G = torch.tensor(rng.uniform(-ramp, ramp, size=(regions, 3, 2)) if ramp > 0 else np.zeros((regions, 3, 2)),
+                     dtype=torch.float64, device=device)
+    ys = torch.arange(H, dtype=torch.float64, device=device)[:, None]
+    xs = torch.arange(W, dtype=torch.float64, device=device)[None, :]
+    best = torch.full((H, W), float("inf"), dtype=torch.float64, device=device)
+    lab = torch.zeros((H, W), dtype=torch.int64, device=device)
+    for r in range(regions):  # ties go to the lowest region index
+        dist = (xs - sx[r]) ** 2 + (ys - sy[r]) ** 2
+        closer = dist < best
+        best = torch.where(closer, dist, best)
+        lab = torch.where(closer, torch.full_like(lab, r), lab)
+    lab = lab.reshape(-1)
+    X = xs.expand(H, W).reshape(-1)
+    Y = ys.expand(H, W).reshape(-1)
+    u = (X - sx[lab]) / W
+    v = (Y - sy[lab]) / H
+    col = mu[lab] + G[lab, :, 0] * u[:, None] + G[lab, :, 1] * v[:, None]
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    col = col + sigma * torch.randn((H * W, 3), dtype=torch.float64, device=device, generator=gen)
+    return col.clamp(0.0, 255.0)
+
+
+def srgb_to_lab_torch(rgb):
+    """torch version of srgb_to_lab (float64)."""
+    import torch
+
+    c = rgb / 255.0
+    lin = torch.where(c <= 0.04045, c / 12.92, ((c + 0.055) / 1.055) ** 2.4)
+    M = torch.tensor(_SRGB_TO_XYZ, dtype=torch.float64, device=rgb.device)
+    xyz = lin @ M.T
+    t = xyz / torch.tensor(_WHITE_D65, dtype=torch.float64, device=rgb.device)
+    f = torch.where(t > _LAB_EPS, torch.pow(t.clamp_min(0.0), 1.0 / 3.0), (_LAB_KAPPA * t + 16.0) / 116.0)
+    L = 116.0 * f[:, 1] - 16.0
+    a = 500.0 * (f[:, 0] - f[:, 1])
+    b = 200.0 * (f[:, 1] - f[:, 2])
+    return torch.stack([L, a, b], dim=1)
+
+
+def batch_rgb_torch(specs: list[BatchSpec], device):
+    """Concatenated float32 RGB points of a batch, row offsets and bandwidths."""
+    import torch
+
+    xs = [voronoi_rgb_torch(s.H, s.W, s.regions, s.sigma, 0.0, s.seed, device).to(torch.float32) for s in specs]
+    off = np.concatenate([[0], np.cumsum([s.H * s.W for s in specs])]).astype(np.int64)
+    return torch.cat(xs, dim=0), off, np.array([s.h for s in specs])
+
+
+def diff_batch_torch(B: int, device, H: int = 512, W: int = 512, regions: int = 30, sigma: float = 6.0):
+    """B images of (x, y, L, a, b) float32 features with s = 1, concatenated."""
+    import torch
+
+    out = []
+    X = torch.arange(W, dtype=torch.float64, device=device)[None, :].expand(H, W).reshape(-1)
+    Y = torch.arange(H, dtype=torch.float64, device=device)[:, None].expand(H, W).reshape(-1)
+    for b in range(B):
+        rgb = voronoi_rgb_torch(H, W, regions, sigma, 64.0, 5000 + b, device)
+        lab = srgb_to_lab_torch(rgb)
+        out.append(torch.cat([X[:, None], Y[:, None], lab], dim=1).to(torch.float32))
+    off = np.arange(B + 1, dtype=np.int64) * (H * W)
+    return torch.cat(out, dim=0), off
