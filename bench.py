@@ -15,8 +15,8 @@ carries, under "forms", the other two forms of the workload family:
            320..1920, 5..60 regions, noise 4..12), RGB float32, per-image
            h in {12, 16, 24}, one gs_fit_batched call;
   fwd_bwd  64 Voronoi images of 512x512, (x, y, L, a, b) float32, h = 16:
-           the point-to-mode loss and its gradient (fit with the trajectory
-           recorded, loss, backward).
+           the point-to-mode loss and its gradient (fit with checkpoints
+           every 8 tail rounds, loss, backward with segment recomputation).
 
   python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--forms plain,batched,fwd_bwd]
 """
@@ -35,6 +35,31 @@ if ROOT not in sys.path:
 
 METRIC = "points/sec + HBM GB/s: GridShift 1080p d=5 plain vs batched vs fwd+bwd"
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (profiles/<kernel>_traffic_plain_1080p_d5.txt), or None
+    when there is none or the kernel's sources changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_plain_1080p_d5.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            kv[k] = v
+    h = hashlib.sha256()
+    for src in kv.get("sources", "").split(","):
+        f = os.path.join(ROOT, "paper_2206_02200_amd", src)
+        if not src or not os.path.exists(f):
+            return None
+        h.update(open(f, "rb").read())
+    if h.hexdigest() != kv.get("sources_sha256"):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def cpu_model() -> str:
@@ -81,6 +106,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="plain,batched,fwd_bwd")
+    ap.add_argument("--calibration-copy-mb", type=int, default=0,
+                    help="run an elementwise copy of this many MiB (read + write) before the fits, untimed: "
+                         "the reference kernel that scales hardware byte counters taken on this command")
     args = ap.parse_args()
     forms = set(args.forms.split(","))
     if args.gpus != 1:
@@ -95,6 +123,13 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibration_copy_mb > 0:
+        src = torch.ones(args.calibration_copy_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     w = synth.image_xylab_f32()
     n, d = w.x.shape
     x = torch.from_numpy(w.x).to(dev)
@@ -168,7 +203,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": measured_traffic(dominant),
             "avg_launch_us": avg_ms * 1e3,
             "alg_bytes_per_launch": bytes_per_launch,
         },
@@ -230,7 +265,7 @@ def bench_fwd_bwd(dev, steps: int) -> dict:
 
     def step():
         x.grad = None
-        loss = gridshift.point_mode_loss(x, 16.0, 100, off, gctx)
+        loss = gridshift.point_mode_loss(x, 16.0, 100, off, gctx, ckpt_every=8)
         loss.sum().backward()
         return loss
 
@@ -246,7 +281,7 @@ def bench_fwd_bwd(dev, steps: int) -> dict:
     out = {
         "value": n / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "steps": steps,
         "workload": "64 Voronoi images 512x512, 30 regions, ramps, sigma 6, (x,y,L,a,b) f32, h=16, "
-                    "point-to-mode loss forward + backward (trajectory recorded every round)",
+                    "point-to-mode loss forward + backward (tail checkpoints every 8 rounds, recomputed in the backward)",
         "n": n, "B": B, "loss_mean": float(loss.detach().mean()), "hbm_GBps_alg": b_alg / (ms * 1e-3) / 1e9,
     }
     gctx.close()

@@ -146,14 +146,23 @@ gs_status gs_copy_keys(gs_context* ctx, int64_t* keys, void* stream);
  * coordinate.  gs_context_set_tape(ctx, 1) makes later fits record that
  * trajectory in the context (device memory: the initial cells, and per round
  * the cell keys, counts, weights and merge maps); the calls below then act on
- * the context's last fit.  Reverse mode, in binary64 in a fixed order:
+ * the context's last fit.
+ * gs_context_set_tape(ctx, k) with k > 1 records the device-wide rounds (the
+ * rounds run while some instance has more than 1024 cells, a few at most) the
+ * same way, but of the remaining rounds keeps only checkpoints: the cell
+ * table (keys, counts, sums) at the start of every k-th of them.  The backward
+ * calls then recompute the per-round record one k-round segment at a time,
+ * last segment first, from its checkpoint, bitwise as the fit ran it, so the
+ * gradients are identical to those of a fully recorded fit.  0 records
+ * nothing; k < 0 is GS_ERR_INVALID_ARG.  Reverse mode, in binary64 in a fixed
+ * order:
  *   Sbar_c = grad_mode_c / C_c for the final cells;
  *   for every round, last first:  q_j = (C_j * Sbar_{g(j)}) / W_j  and
  *   Sbar_k = left fold, over the round's active cells j with Chebyshev key
  *   distance <= 1 from k, in ascending key, of q_j;
  *   grad_point_i = Sbar_{initial cell of i}.
  */
-gs_status gs_context_set_tape(gs_context* ctx, int32_t on);
+gs_status gs_context_set_tape(gs_context* ctx, int32_t ckpt_every);
 
 /* grad_modes device double [sum K][d] (the concatenated cluster rows of
  * gs_copy_modes); grad_points device double [N][d], overwritten.  Returns

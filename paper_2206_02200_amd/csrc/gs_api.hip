@@ -64,8 +64,14 @@ struct gs_context {
     DBuf counters, look, tilectr, shist, sdbase, sctr, slook;
     gs::SortScratch sort;
     uint32_t scan_epoch = 0;
+    uint64_t tile_base = 0;  // value of the scan tile counter before the next scan
+    // pinned staging: downloads (every one waits for its stream) and a bump
+    // area for uploads, reused only once a wait on up_stream has drained them
     void* pinned = nullptr;
     size_t pinned_cap = 0;
+    char* up = nullptr;
+    size_t up_cap = 0, up_used = 0;
+    hipStream_t up_stream = nullptr;
     // result of the last fit
     bool has_result = false;
     int B = 0, d = 0, cur_tab = 0;
@@ -75,6 +81,10 @@ struct gs_context {
     Profiler prof;
     // differentiable form: trajectory tape of the last fit
     bool tape_on = false, tape_valid = false;
+    int ckpt_every = 0;  // 0 or 1: every tail round recorded; k > 1: tail checkpoints every k rounds
+    int ckpt_used = 0;   // the setting the last fit was recorded with
+    DBuf ck_key, ck_cnt, ck_sum, ck_m;
+    int ck_nslots = 0;
     DBuf sums0, inst0, wt_key, wt_cnt, wt_inst, wt_W, wt_g, wt_app;
     DBuf tt_key, tt_cnt, tt_W, tt_g, tt_m;
     DBuf sbA, sbB, qbuf, gmodes, modes_i, counts_i, frows, lossc, ltab;
@@ -215,12 +225,52 @@ gs_status pinned_ensure(gs_context* c, size_t bytes) {
     return GS_OK;
 }
 
+// Wait for stream s; uploads staged on it are then complete.
+gs_status stream_wait(gs_context* c, hipStream_t s) {
+    GS_HIP(hipStreamSynchronize(s));
+    if (c->up_stream == s) c->up_used = 0;
+    return GS_OK;
+}
+
 // Copy device -> host through pinned memory and wait for the stream.
 gs_status d2h(gs_context* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
     GS_TRY(pinned_ensure(c, bytes));
     GS_HIP(hipMemcpyAsync(c->pinned, src, bytes, hipMemcpyDeviceToHost, s));
-    GS_HIP(hipStreamSynchronize(s));
+    GS_TRY(stream_wait(c, s));
     std::memcpy(dst, c->pinned, bytes);
+    return GS_OK;
+}
+
+// Host -> device copy staged in the upload area; returns without waiting
+// (the staged bytes stay untouched until a wait has drained the copy).
+gs_status h2d(gs_context* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (c->up_used > 0 && c->up_stream != s) {
+        GS_HIP(hipStreamSynchronize(c->up_stream));
+        c->up_used = 0;
+    }
+    if (c->up_used + need > c->up_cap) {
+        if (c->up_used > 0) GS_TRY(stream_wait(c, s));
+        c->up_used = 0;
+        if (need > c->up_cap) {
+            if (c->up) (void)hipHostFree(c->up);
+            c->up = nullptr;
+            c->up_cap = 0;
+            const size_t want = std::max<size_t>(need, size_t(1) << 16);
+            void* p = nullptr;
+            if (hipHostMalloc(&p, want) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(GS_ERR_ALLOC, "hipHostMalloc failed");
+            }
+            c->up = static_cast<char*>(p);
+            c->up_cap = want;
+        }
+    }
+    char* stage = c->up + c->up_used;
+    std::memcpy(stage, src, bytes);
+    GS_HIP(hipMemcpyAsync(dst, stage, bytes, hipMemcpyHostToDevice, s));
+    c->up_used += need;
+    c->up_stream = s;
     return GS_OK;
 }
 
@@ -230,19 +280,9 @@ struct Xfer {
     size_t bytes;
 };
 
-// Several host -> device copies through one staging pass and one wait.
+// Several host -> device copies, none waited for.
 gs_status h2d_batch(gs_context* c, const std::vector<Xfer>& xs, hipStream_t s) {
-    size_t total = 0;
-    for (const Xfer& x : xs) total += (x.bytes + 255) & ~size_t(255);
-    GS_TRY(pinned_ensure(c, total));
-    GS_HIP(hipStreamSynchronize(s));
-    size_t off = 0;
-    for (const Xfer& x : xs) {
-        std::memcpy(static_cast<char*>(c->pinned) + off, x.host, x.bytes);
-        GS_HIP(hipMemcpyAsync(x.dev, static_cast<char*>(c->pinned) + off, x.bytes, hipMemcpyHostToDevice, s));
-        off += (x.bytes + 255) & ~size_t(255);
-    }
-    GS_HIP(hipStreamSynchronize(s));
+    for (const Xfer& x : xs) GS_TRY(h2d(c, x.dev, x.host, x.bytes, s));
     return GS_OK;
 }
 
@@ -256,22 +296,12 @@ gs_status d2h_batch(gs_context* c, const std::vector<Xfer>& xs, hipStream_t s) {
         GS_HIP(hipMemcpyAsync(static_cast<char*>(c->pinned) + off, x.host, x.bytes, hipMemcpyDeviceToHost, s));
         off += (x.bytes + 255) & ~size_t(255);
     }
-    GS_HIP(hipStreamSynchronize(s));
+    GS_TRY(stream_wait(c, s));
     off = 0;
     for (const Xfer& x : xs) {
         std::memcpy(x.dev, static_cast<char*>(c->pinned) + off, x.bytes);
         off += (x.bytes + 255) & ~size_t(255);
     }
-    return GS_OK;
-}
-
-gs_status h2d(gs_context* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
-    GS_TRY(pinned_ensure(c, bytes));
-    // the previous use of the staging buffer has completed (every d2h waits)
-    GS_HIP(hipStreamSynchronize(s));
-    std::memcpy(c->pinned, src, bytes);
-    GS_HIP(hipMemcpyAsync(dst, c->pinned, bytes, hipMemcpyHostToDevice, s));
-    GS_HIP(hipStreamSynchronize(s));
     return GS_OK;
 }
 
@@ -290,6 +320,9 @@ __global__ void k_iota32(uint32_t* __restrict__ p, int64_t n) {
 }
 
 // Look-back storage of the tile scans: tiles status words, cleared on growth.
+// Tiles take their index from a counter that is never reset per scan: every
+// block of a scan increments it once, so the host knows its value before the
+// next scan (tile_base) and clears it only when it nears overflow.
 gs_status scan_prepare(gs_context* c, int64_t n_bound, hipStream_t s, uint32_t* epoch_out) {
     const int64_t tiles = std::max<int64_t>(1, (n_bound + gs::kScanTile - 1) / gs::kScanTile);
     if (c->look.cap < size_t(tiles) * 8) {
@@ -297,26 +330,37 @@ gs_status scan_prepare(gs_context* c, int64_t n_bound, hipStream_t s, uint32_t* 
         k_fill_u64<<<blocks_for(c->look.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->look), c->look.cap / 8, 0);
         c->scan_epoch = 0;
     }
-    GS_TRY(ensure(c->tilectr, 64));
+    if (c->tilectr.cap == 0 || c->tile_base + uint64_t(tiles) >= 0x7fffffffull) {
+        GS_TRY(ensure(c->tilectr, 64));
+        k_fill_u32<<<1, 64, 0, s>>>(P<uint32_t>(c->tilectr), 16, 0);
+        c->tile_base = 0;
+    }
     if (c->scan_epoch >= 0xffffu) {
         k_fill_u64<<<blocks_for(c->look.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->look), c->look.cap / 8, 0);
         c->scan_epoch = 0;
     }
     *epoch_out = ++c->scan_epoch;
-    k_fill_u32<<<1, 64, 0, s>>>(P<uint32_t>(c->tilectr), 16, 0);
     return GS_OK;
 }
 
+// n_dev: the length on the device, or nullptr when it is n_bound itself.
 template <class Op>
 gs_status run_scan(gs_context* c, Op op, const int64_t* n_dev, int64_t n_bound, int64_t* total_dev, hipStream_t s,
                    const char* name, double nbytes) {
     uint32_t epoch = 0;
     GS_TRY(scan_prepare(c, n_bound, s, &epoch));
     const int64_t tiles = std::max<int64_t>(1, (n_bound + gs::kScanTile - 1) / gs::kScanTile);
+    const uint32_t base = uint32_t(c->tile_base);
+    c->tile_base += uint64_t(tiles);
     PROF_LAUNCH(name, nbytes,
-                gs::k_scan<Op><<<unsigned(tiles), gs::kScanThreads, 0, s>>>(op, n_dev, P<uint64_t>(c->look),
-                                                                            P<uint32_t>(c->tilectr), epoch, total_dev));
-    GS_HIP(hipGetLastError());
+                gs::k_scan<Op><<<unsigned(tiles), gs::kScanThreads, 0, s>>>(op, n_dev, n_bound, P<uint64_t>(c->look),
+                                                                            P<uint32_t>(c->tilectr), base, epoch,
+                                                                            total_dev));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        c->tile_base = 0x7fffffffull;  // the counter is unknown now: clear it before the next scan
+        return fail(GS_ERR_DEVICE, std::string("scan launch failed: ") + hipGetErrorString(e));
+    }
     return GS_OK;
 }
 
@@ -391,15 +435,16 @@ gs_status launch_shift(gs_context* c, int d, gs::CellTable t, int64_t m, const g
 }
 
 gs_status launch_tail(gs_context* c, int d, int B, gs::CellTable t, const gs::InstParam* prm, gs::InstState* st, uint32_t* tmap,
-                      int max_iter, const gs::TailTape& tape, hipStream_t s, double nbytes) {
-    const int tk = prof_begin(c, s, "tail");
+                      int max_iter, const gs::TailTape& tape, const gs::TailCkpt& ck, int replay_r0, hipStream_t s,
+                      double nbytes) {
+    const int tk = prof_begin(c, s, replay_r0 >= 0 ? "tail_replay" : "tail");
     switch (d) {
-        case 1: gs::k_tail<1><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape); break;
-        case 2: gs::k_tail<2><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape); break;
-        case 3: gs::k_tail<3><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape); break;
-        case 4: gs::k_tail<4><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape); break;
-        case 5: gs::k_tail<5><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape); break;
-        case 6: gs::k_tail<6><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape); break;
+        case 1: gs::k_tail<1><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0); break;
+        case 2: gs::k_tail<2><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0); break;
+        case 3: gs::k_tail<3><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0); break;
+        case 4: gs::k_tail<4><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0); break;
+        case 5: gs::k_tail<5><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0); break;
+        case 6: gs::k_tail<6><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0); break;
         default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
     }
     prof_end(c, s, tk, nbytes);
@@ -448,6 +493,39 @@ gs_status build_params(gs_context* c, int B, int d, const int64_t* offsets, cons
     return GS_OK;
 }
 
+// Device view of the per-round tail tape, `rounds` rounds per instance.
+gs_status tail_tape(gs_context* c, int rounds, int B, gs::TailTape* tape) {
+    const size_t per = size_t(rounds) * gs::kTailCells;
+    GS_TRY(ensure(c->tt_key, per * B * 8));
+    GS_TRY(ensure(c->tt_cnt, per * B * 4));
+    GS_TRY(ensure(c->tt_W, per * B * 4));
+    GS_TRY(ensure(c->tt_g, per * B * 4));
+    GS_TRY(ensure(c->tt_m, size_t(rounds) * B * 4));
+    tape->key = P<uint64_t>(c->tt_key);
+    tape->cnt = P<int32_t>(c->tt_cnt);
+    tape->W = P<int32_t>(c->tt_W);
+    tape->g = P<uint32_t>(c->tt_g);
+    tape->m = P<int32_t>(c->tt_m);
+    tape->stride = int64_t(per);
+    tape->max_rounds = rounds;
+    return GS_OK;
+}
+
+// Device view of the tail checkpoints (ns slots per instance).
+gs::TailCkpt ckpt_view(gs_context* c, int ns, int B, int every) {
+    gs::TailCkpt ck;
+    ck.key = P<uint64_t>(c->ck_key);
+    ck.cnt = P<int32_t>(c->ck_cnt);
+    ck.sum = P<double>(c->ck_sum);
+    ck.m = P<int32_t>(c->ck_m);
+    ck.stride = int64_t(ns) * gs::kTailCells;
+    ck.total = ck.stride * B;
+    ck.nslots = ns;
+    ck.every = every;
+    c->ck_nslots = ns;
+    return ck;
+}
+
 template <typename T, typename K>
 gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const int64_t* offsets, int max_iter,
                     int bits, int32_t* labels, hipStream_t s) {
@@ -482,8 +560,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     c->sort.prof_end = sort_prof_end;
 
     const int np = gs::sort_passes(bits);
-    k_fill_u32<<<blocks_for(gs::kSortMaxPasses * 256, 256), 256, 0, s>>>(c->sort.hist, gs::kSortMaxPasses * 256, 0);
-    {
+    {  // the digit histograms were cleared by k_init_state
         if (c->ntiles > 0)
             PROF_LAUNCH("make_keys", N * (double(d) * sizeof(T) + sizeof(K)),
                         gs::k_make_keys<T, K><<<unsigned(c->ntiles), gs::kBoxThreads, 0, s>>>(
@@ -500,10 +577,9 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     GS_TRY(ensure(c->tstart[0], size_t(N) * 4));
     GS_TRY(ensure(c->tfirst[0], size_t(N) * 4));
     {
-        k_set_i64<<<1, 1, 0, s>>>(ctr + 3, N);
         gs::HeadsOp<K> op{skeys, perm, P<uint64_t>(c->tkey[0]), P<uint32_t>(c->tstart[0]), P<uint32_t>(c->tfirst[0]),
                           P<uint32_t>(c->cell0)};
-        GS_TRY(run_scan(c, op, ctr + 3, N, ctr + 0, s, "scan_heads", N * (sizeof(K) + 8.0)));
+        GS_TRY(run_scan(c, op, nullptr, N, ctr + 0, s, "scan_heads", N * (sizeof(K) + 8.0)));
     }
     int64_t m0 = 0;
     GS_TRY(d2h(c, &m0, ctr + 0, sizeof(int64_t), s));
@@ -526,12 +602,9 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     gs::CellTable T0 = table(c, 0);
     PROF_LAUNCH("cell_setup", m0 * 20.0,
                 gs::k_cell_setup<<<blocks_for(c->capM, 256), 256, 0, s>>>(ctr + 0, N, T0, 0, row_off, B, nullptr,
-                                                                           st));
+                                                                           st, true));
     GS_HIP(hipGetLastError());
     GS_TRY(segsum(c, d, gs::SrcPoints<T>{x, ld, perm}, T0, m0, N, s, 4.0 + double(d) * sizeof(T)));
-    gs::k_clear_ranges<<<blocks_for(B, 256), 256, 0, s>>>(st, B);
-    gs::k_inst_ranges<<<blocks_for(c->capM, 256), 256, 0, s>>>(T0.inst, ctr + 0, st);
-    GS_HIP(hipGetLastError());
     if (c->tape_on && m0 > 0) {  // the initial cells, for the adjoint and the loss
         GS_TRY(ensure(c->sums0, size_t(m0) * d * 8));
         GS_TRY(ensure(c->inst0, size_t(m0) * 4));
@@ -607,31 +680,29 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         gs::k_decide<<<blocks_for(B, 256), 256, 0, s>>>(st, B, max_iter);
         PROF_LAUNCH("merge_prep", M * (8.0 * 3 + 16.0 * d + sizeof(K)),
                     gs::k_merge_prep<K><<<blocks_for(M, 256), 256, 0, s>>>(TT, M, st, st, P<double>(c->pbuf),
-                                                                            P<uint64_t>(c->kappa), P<K>(c->ckA), d));
+                                                                            P<uint64_t>(c->kappa), P<K>(c->ckA), d,
+                                                                            np, c->sort.hist));
         GS_HIP(hipGetLastError());
         K* mk = nullptr;
         uint32_t* mperm = nullptr;
         GS_HIP(gs::radix_sort<K>(P<K>(c->ckA), P<K>(c->ckB), P<uint32_t>(c->cvA), P<uint32_t>(c->cvB), M, bits,
-                                 false, c->sort, s, &mk, &mperm));
-        k_set_i64<<<1, 1, 0, s>>>(ctr + 3, M);
+                                 true, c->sort, s, &mk, &mperm));
         gs::HeadsOp<K> op{mk, mperm, U.key, U.start, U.first, P<uint32_t>(c->gmap)};
-        GS_TRY(run_scan(c, op, ctr + 3, M, ctr + 0, s, "scan_heads", M * (sizeof(K) + 8.0)));
+        GS_TRY(run_scan(c, op, nullptr, M, ctr + 0, s, "scan_heads", M * (sizeof(K) + 8.0)));
         if (c->tape_on)
             GS_HIP(hipMemcpyAsync(P<uint32_t>(c->wt_g) + woff, c->gmap.p, M * 4, hipMemcpyDeviceToDevice, s));
         PROF_LAUNCH("cell_setup", M * 24.0,
-                    gs::k_cell_setup<<<blocks_for(M, 256), 256, 0, s>>>(ctr + 0, M, U, 1, row_off, B, TT.inst, st));
+                    gs::k_cell_setup<<<blocks_for(M, 256), 256, 0, s>>>(ctr + 0, M, U, 1, row_off, B, TT.inst, st,
+                                                                         true));
         GS_HIP(hipGetLastError());
         gs::SrcMerge src{P<double>(c->pbuf), TT.sum, TT.cnt, TT.inst, st, mperm, c->capM};
         GS_TRY(segsum(c, d, src, U, M, M, s, 4.0 + 4.0 + 8.0 + 8.0 * d));
-        PROF_LAUNCH("compose", m0 * 12.0,
-                    gs::k_compose<<<blocks_for(m0, 256), 256, 0, s>>>(P<uint32_t>(c->cur), m0, P<uint32_t>(c->gmap)));
-        gs::k_round_end<<<blocks_for(B, 256), 256, 0, s>>>(st, B, apprec);
-        gs::k_clear_ranges<<<blocks_for(B, 256), 256, 0, s>>>(st, B);
-        gs::k_inst_ranges<<<blocks_for(M, 256), 256, 0, s>>>(U.inst, ctr + 0, st);
+        PROF_LAUNCH("round_end", m0 * 12.0,
+                    gs::k_round_end<<<blocks_for(std::max<int64_t>(m0, B), 256), 256, 0, s>>>(
+                        P<uint32_t>(c->cur), m0, P<uint32_t>(c->gmap), st, B, apprec));
         GS_HIP(hipGetLastError());
         cur = 1 - cur;
-        GS_TRY(d2h(c, &M, ctr + 0, sizeof(int64_t), s));
-        GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
+        GS_TRY(d2h_batch(c, {{&M, ctr + 0, sizeof(int64_t)}, {c->st.data(), st, sizeof(gs::InstState) * B}}, s));
         for (int b = 0; b < B; ++b)
             if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");
     }
@@ -639,22 +710,22 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     // ---- remaining rounds: one LDS-resident workgroup per instance
     gs::CellTable TC = table(c, cur);
     gs::TailTape tape;
-    if (c->tape_on && max_iter > 0) {
-        const size_t per = size_t(max_iter) * gs::kTailCells;
-        GS_TRY(ensure(c->tt_key, per * B * 8));
-        GS_TRY(ensure(c->tt_cnt, per * B * 4));
-        GS_TRY(ensure(c->tt_W, per * B * 4));
-        GS_TRY(ensure(c->tt_g, per * B * 4));
-        GS_TRY(ensure(c->tt_m, size_t(max_iter) * B * 4));
-        tape.key = P<uint64_t>(c->tt_key);
-        tape.cnt = P<int32_t>(c->tt_cnt);
-        tape.W = P<int32_t>(c->tt_W);
-        tape.g = P<uint32_t>(c->tt_g);
-        tape.m = P<int32_t>(c->tt_m);
-        tape.stride = int64_t(per);
-        tape.max_rounds = max_iter;
+    gs::TailCkpt ck;
+    c->ckpt_used = c->ckpt_every;
+    if (c->tape_on && max_iter > 0 && c->ckpt_every > 1) {
+        // checkpoints only: the table every ckpt_every rounds
+        const int ns = max_iter / c->ckpt_every + 1;
+        const size_t per = size_t(ns) * gs::kTailCells;
+        GS_TRY(ensure(c->ck_key, per * B * 8));
+        GS_TRY(ensure(c->ck_cnt, per * B * 4));
+        GS_TRY(ensure(c->ck_sum, per * B * d * 8));
+        GS_TRY(ensure(c->ck_m, size_t(ns) * B * 4));
+        ck = ckpt_view(c, ns, B, c->ckpt_every);
+    } else if (c->tape_on && max_iter > 0) {
+        GS_TRY(tail_tape(c, max_iter, B, &tape));
     }
-    GS_TRY(launch_tail(c, d, B, TC, prm, st, P<uint32_t>(c->tmap), max_iter, tape, s, 2.0 * M * (16.0 + 8.0 * d)));
+    GS_TRY(launch_tail(c, d, B, TC, prm, st, P<uint32_t>(c->tmap), max_iter, tape, ck, -1, s,
+                       2.0 * M * (16.0 + 8.0 * d)));
     if (N > 0) {
         PROF_LAUNCH("labels", N * 8.0,
                     gs::k_labels<<<blocks_for(N, 256), 256, 0, s>>>(
@@ -685,18 +756,20 @@ gs_status upload_koff(gs_context* c, hipStream_t s, std::vector<int64_t>& koff) 
     return GS_OK;
 }
 
-gs_status launch_tail_adj(gs_context* c, int d, const gs::TailTape& tape, double* sbar, hipStream_t s) {
+gs_status launch_tail_adj(gs_context* c, int d, const gs::TailTape& tape, const gs::TailCkpt& ck, int seg_r0,
+                          double* sbar, hipStream_t s) {
     const gs::InstParam* prm = P<gs::InstParam>(c->param);
     const gs::InstState* st = P<gs::InstState>(c->state);
     const int B = c->B;
+    const int64_t cap = c->capM;
     const int tk = prof_begin(c, s, "tail_adj");
     switch (d) {
-        case 1: gs::k_tail_adj<1><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, c->capM); break;
-        case 2: gs::k_tail_adj<2><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, c->capM); break;
-        case 3: gs::k_tail_adj<3><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, c->capM); break;
-        case 4: gs::k_tail_adj<4><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, c->capM); break;
-        case 5: gs::k_tail_adj<5><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, c->capM); break;
-        case 6: gs::k_tail_adj<6><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, c->capM); break;
+        case 1: gs::k_tail_adj<1><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0); break;
+        case 2: gs::k_tail_adj<2><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0); break;
+        case 3: gs::k_tail_adj<3><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0); break;
+        case 4: gs::k_tail_adj<4><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0); break;
+        case 5: gs::k_tail_adj<5><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0); break;
+        case 6: gs::k_tail_adj<6><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0); break;
         default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
     }
     prof_end(c, s, tk, 0.0);
@@ -744,7 +817,20 @@ gs_status adjoint_core(gs_context* c, const double* gm, hipStream_t s, double** 
                     gs::k_adj_final<<<blocks_for(rows, 256), 256, 0, s>>>(TC, P<gs::InstState>(c->state),
                                                                           P<int64_t>(c->koff), B, rows, d, gm, sa));
     gs::TailTape tape;
-    if (c->tail_rounds > 0) {
+    if (c->tail_rounds > 0 && c->ckpt_used > 1) {
+        // segments of ckpt_used tail rounds, last first: recompute the
+        // segment's tape from its checkpoint, then reverse its rounds
+        int most = 0;
+        for (int b = 0; b < B; ++b) most = std::max(most, c->st[b].t - c->st[b].t_tail0);
+        const int k = c->ckpt_used;
+        GS_TRY(tail_tape(c, k, B, &tape));
+        const gs::TailCkpt ck = ckpt_view(c, c->ck_nslots, B, k);
+        for (int r0 = most > 0 ? ((most - 1) / k) * k : -1; r0 >= 0; r0 -= k) {
+            GS_TRY(launch_tail(c, d, B, TC, P<gs::InstParam>(c->param), P<gs::InstState>(c->state), nullptr,
+                               c->tail_rounds, tape, ck, r0, s, 0.0));
+            GS_TRY(launch_tail_adj(c, d, tape, ck, r0, sa, s));
+        }
+    } else if (c->tail_rounds > 0) {
         tape.key = P<uint64_t>(c->tt_key);
         tape.cnt = P<int32_t>(c->tt_cnt);
         tape.W = P<int32_t>(c->tt_W);
@@ -752,7 +838,7 @@ gs_status adjoint_core(gs_context* c, const double* gm, hipStream_t s, double** 
         tape.m = P<int32_t>(c->tt_m);
         tape.stride = int64_t(c->tail_rounds) * gs::kTailCells;
         tape.max_rounds = c->tail_rounds;
-        GS_TRY(launch_tail_adj(c, d, tape, sa, s));
+        GS_TRY(launch_tail_adj(c, d, tape, gs::TailCkpt{}, 0, sa, s));
     }
     for (int r = int(c->w_off.size()) - 1; r >= 0; --r) {
         const int64_t off = c->w_off[r], M = c->w_M[r];
@@ -843,9 +929,9 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
                       {c->tiles.p, tiles.data(), sizeof(gs::RowTile) * tiles.size()},
                       {c->tileoff.p, tile_off.data(), sizeof(int64_t) * (B + 1)}},
                      s));
-    gs::k_init_state<<<blocks_for(std::max(B, 8), 256), 256, 0, s>>>(P<gs::InstState>(c->state), B,
-                                                                      P<int64_t>(c->bbox), d,
-                                                                      P<int64_t>(c->counters));
+    GS_TRY(ensure(c->shist, gs::kSortMaxPasses * 256 * 4));
+    gs::k_init_state<<<blocks_for(std::max(B, gs::kSortMaxPasses * 256), 256), 256, 0, s>>>(
+        P<gs::InstState>(c->state), B, P<int64_t>(c->bbox), d, P<int64_t>(c->counters), P<uint32_t>(c->shist));
     GS_HIP(hipGetLastError());
 
     std::vector<int64_t> box(size_t(B) * gs::kMaxDim * 2, 0);
@@ -976,11 +1062,10 @@ static gs_status loss_bwd(gs_context* c, const T* x, const int32_t* labels, cons
                                     P<uint32_t>(c->xvB), m0, bits, false, c->sort, s, &sk, &sperm));
     gs::CellTable X = table(c, 1 - c->cur_tab);  // the idle ping-pong table holds the groups
     int64_t* ctr = P<int64_t>(c->counters);
-    k_set_i64<<<1, 1, 0, s>>>(ctr + 3, m0);
     gs::HeadsOp<uint32_t> op{sk, sperm, X.key, X.start, X.first, P<uint32_t>(c->frows)};
-    GS_TRY(run_scan(c, op, ctr + 3, m0, ctr + 0, s, "scan_heads", m0 * 12.0));
+    GS_TRY(run_scan(c, op, nullptr, m0, ctr + 0, s, "scan_heads", m0 * 12.0));
     gs::k_cell_setup<<<blocks_for(rows, 256), 256, 0, s>>>(ctr + 0, m0, X, 0, P<int64_t>(c->rowoff), B, nullptr,
-                                                           P<gs::InstState>(c->state));
+                                                           P<gs::InstState>(c->state), false);
     GS_HIP(hipGetLastError());
     GS_TRY(segsum(c, d, gs::SrcInit{P<double>(c->sums0), sperm, m0}, X, rows, m0, s, 4.0 + 8.0 * d));
     GS_TRY(ensure(c->gmodes, size_t(std::max<int64_t>(rows, 1)) * d * 8));
@@ -1034,11 +1119,14 @@ void gs_context_destroy(gs_context* c) {
         for (DBuf* b : tb)
             if (b->p) (void)hipFree(b->p);
     }
+    if (c->up_used > 0) (void)hipStreamSynchronize(c->up_stream);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->up) (void)hipHostFree(c->up);
     for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
     DBuf* tb2[] = {&c->sums0, &c->inst0, &c->wt_key, &c->wt_cnt, &c->wt_inst, &c->wt_W, &c->wt_g, &c->wt_app,
                    &c->tt_key, &c->tt_cnt, &c->tt_W, &c->tt_g, &c->tt_m, &c->sbA, &c->sbB, &c->qbuf, &c->gmodes,
-                   &c->modes_i, &c->counts_i, &c->frows, &c->lossc, &c->ltab, &c->xkA, &c->xkB, &c->xvA, &c->xvB};
+                   &c->modes_i, &c->counts_i, &c->frows, &c->lossc, &c->ltab, &c->xkA, &c->xkB, &c->xvA, &c->xvB,
+                   &c->ck_key, &c->ck_cnt, &c->ck_sum, &c->ck_m};
     for (DBuf* b : tb2)
         if (b->p) (void)hipFree(b->p);
     delete c;
@@ -1087,9 +1175,11 @@ gs_status gs_profile_entry(const gs_context* ctx, int32_t i, const char** name, 
     return GS_OK;
 }
 
-gs_status gs_context_set_tape(gs_context* ctx, int32_t on) {
+gs_status gs_context_set_tape(gs_context* ctx, int32_t ckpt_every) {
     if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
-    ctx->tape_on = on != 0;
+    if (ckpt_every < 0) return fail(GS_ERR_INVALID_ARG, "the checkpoint interval must be >= 0");
+    ctx->tape_on = ckpt_every != 0;
+    ctx->ckpt_every = ckpt_every;
     return GS_OK;
 }
 

@@ -46,8 +46,9 @@ __device__ __forceinline__ double cell_floor(double v, double h) { return floor(
 // state initialisation
 // ===========================================================================
 __global__ void k_init_state(InstState* __restrict__ st, int B, int64_t* __restrict__ bbox, int d,
-                             int64_t* __restrict__ counters) {
+                             int64_t* __restrict__ counters, uint32_t* __restrict__ sort_hist) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < kSortMaxPasses * 256) sort_hist[b] = 0;
     if (b < B) {
         InstState z = {};
         z.active = 1;
@@ -289,18 +290,19 @@ struct ExclOp {
 // n_ptr: device count of positions (read once per block); total: device
 // result (sum of all values).  Tiles take their index from tile_ctr.
 template <class Op>
-__global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __restrict__ n_ptr,
+__global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __restrict__ n_ptr, int64_t n_val,
                                                        uint64_t* __restrict__ look, uint32_t* __restrict__ tile_ctr,
-                                                       uint32_t epoch, int64_t* __restrict__ total) {
+                                                       uint32_t tile_base, uint32_t epoch,
+                                                       int64_t* __restrict__ total) {
     constexpr int W = kScanThreads / kWave;
     __shared__ int64_t s_tile;
     __shared__ uint64_t wtot[W];
     __shared__ uint64_t s_excl;
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u) - tile_base;
     __syncthreads();
     const int64_t tile = s_tile;
-    const int64_t n = *n_ptr;
+    const int64_t n = n_ptr ? *n_ptr : n_val;
     const int64_t t0 = tile * kScanTile;
     if (t0 >= n && tile > 0) return;
 
@@ -365,9 +367,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __r
 // ===========================================================================
 // mode 0 (binning): instance from the member's row; mode 1 (merge): from the
 // member cell's instance, and flag instances whose round merged cells.
+// With `ranges` it also records each instance's row range [cs, ce) of the
+// new table (the ranges of instances without cells were cleared beforehand).
 __global__ void k_cell_setup(const int64_t* __restrict__ m_ptr, int64_t npos, CellTable t, int mode,
                              const int64_t* __restrict__ row_off, int B, const int32_t* __restrict__ old_inst,
-                             InstState* __restrict__ st) {
+                             InstState* __restrict__ st, bool ranges) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t m = *m_ptr;
     bool merged = false;
@@ -378,13 +382,23 @@ __global__ void k_cell_setup(const int64_t* __restrict__ m_ptr, int64_t npos, Ce
         const uint32_t len = s1 - s0;
         t.len[c] = len;
         t.nch[c] = (len + kChunk - 1) / kChunk;
+        int bp = -1;  // instance of the previous cell
         if (mode == 0) {
             b = inst_of_row(row_off, B, int64_t(t.first[c]));
+            if (c > 0) bp = inst_of_row(row_off, B, int64_t(t.first[c - 1]));
         } else {
             b = old_inst[t.first[c]];
+            if (c > 0) bp = old_inst[t.first[c - 1]];
             merged = len > 1 && st[b].apply;
         }
         t.inst[c] = b;
+        if (ranges) {
+            if (bp != b) {
+                st[b].cs = c;
+                if (bp >= 0) st[bp].ce = c;
+            }
+            if (c == m - 1) st[b].ce = m;
+        }
     }
     if (mode == 1) wave_flag_or(&st[b].changed, merged);
 }
@@ -557,27 +571,6 @@ __global__ __launch_bounds__(kSegThreads) void k_segsum_levels(CellTable t, cons
 }
 
 // ===========================================================================
-// instance ranges in a cell table
-// ===========================================================================
-__global__ void k_clear_ranges(InstState* __restrict__ st, int B) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) {
-        st[b].cs = 0;
-        st[b].ce = 0;
-    }
-}
-
-__global__ void k_inst_ranges(const int32_t* __restrict__ inst, const int64_t* __restrict__ m_ptr,
-                              InstState* __restrict__ st) {
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t m = *m_ptr;
-    if (c >= m) return;
-    const int b = inst[c];
-    if (c == 0 || inst[c - 1] != b) st[b].cs = c;
-    if (c == m - 1 || inst[c + 1] != b) st[b].ce = c + 1;
-}
-
-// ===========================================================================
 // wide rounds
 // ===========================================================================
 constexpr uint64_t kEmpty = ~0ull;
@@ -632,7 +625,7 @@ __device__ __forceinline__ int64_t hash_find(const uint64_t* __restrict__ hk, co
 // lane k folds dimension k left to right and lane D adds the integer weight.
 // p = N / W and the landing key floor(p/h) follow.
 constexpr int kShiftWaves = 4;
-constexpr int kSlabMax = 2048;  // largest dimension-0 extent with a slab table in the tail
+constexpr int kSlabMax = 4096;  // most columns of a tail's column table
 
 __host__ __device__ constexpr int pow3(int d) { return d == 0 ? 1 : 3 * pow3(d - 1); }
 
@@ -744,40 +737,64 @@ __global__ void k_decide(InstState* __restrict__ st, int B, int max_iter) {
         }
     }
     s.any_nb = 0;
+    s.cs = 0;  // the merge's cell setup records the new table's ranges
+    s.ce = 0;
     st[b] = s;
 }
 
-// Landing keys for the merge sort; stationarity of applying instances.
+// Landing keys for the merge sort, with their radix digit histograms;
+// stationarity of applying instances.
 template <typename K>
-__global__ void k_merge_prep(CellTable t, int64_t m, const InstState* __restrict__ stc, InstState* __restrict__ st,
-                             const double* __restrict__ pbuf, const uint64_t* __restrict__ kappa, K* __restrict__ skey,
-                             int d) {
+__global__ __launch_bounds__(256) void k_merge_prep(CellTable t, int64_t m, const InstState* __restrict__ stc,
+                                                    InstState* __restrict__ st, const double* __restrict__ pbuf,
+                                                    const uint64_t* __restrict__ kappa, K* __restrict__ skey, int d,
+                                                    int npasses, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t hl[kSortMaxPasses * 256];
+    const int tid = threadIdx.x, lane = lane_id();
+    for (int i = tid; i < npasses * 256; i += 256) hl[i] = 0;
+    __syncthreads();
     const int64_t j0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const bool valid = j0 < m;
     const int64_t j = valid ? j0 : m - 1;  // idle lanes shadow the last cell and raise nothing
     const int b = t.inst[j];
     const uint64_t key = t.key[j];
-    if (!stc[b].apply) {
-        if (valid) skey[j] = K(key);
-        wave_flag_or(&st[b].changed, false);
-        return;
+    K out = K(key);
+    bool chg = false;
+    if (stc[b].apply) {
+        const uint64_t kap = kappa[j];
+        out = K(kap);
+        chg = valid && kap != key;
+        const double C = double(t.cnt[j]);
+        for (int k = 0; k < d; ++k) chg = chg || dbits(C * pbuf[k * t.cap + j]) != dbits(t.sum[k * t.cap + j]);
     }
-    const uint64_t kap = kappa[j];
-    if (valid) skey[j] = K(kap);
-    bool chg = valid && kap != key;
-    const double C = double(t.cnt[j]);
-    for (int k = 0; k < d; ++k) chg = chg || dbits(C * pbuf[k * t.cap + j]) != dbits(t.sum[k * t.cap + j]);
     wave_flag_or(&st[b].changed, chg);
+    if (valid) skey[j] = out;
+    const uint64_t act = __ballot(valid);
+    if (act) {
+        const int lead = __ffsll((unsigned long long)act) - 1;
+        for (int p = 0; p < npasses; ++p) {
+            const uint32_t dgt = uint32_t(out >> (8 * p)) & 255u;
+            const uint32_t d0 = __shfl(dgt, lead, kWave);
+            if (__ballot(valid && dgt == d0) == act) {
+                if (lane == lead) atomicAdd(&hl[p * 256 + d0], uint32_t(__popcll(act)));
+            } else if (valid) {
+                atomicAdd(&hl[p * 256 + dgt], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < npasses * 256; i += 256)
+        if (hl[i]) atomicAdd(&hist[i], hl[i]);
 }
 
-__global__ void k_compose(uint32_t* __restrict__ cur, int64_t m0, const uint32_t* __restrict__ g) {
+// End of a wide round: initial cell -> current cell maps (threads < m0) and
+// the per-instance round count and stationarity (threads < B).
+__global__ void k_round_end(uint32_t* __restrict__ cur, int64_t m0, const uint32_t* __restrict__ g,
+                            InstState* __restrict__ st, int B, int32_t* __restrict__ applied) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c < m0) cur[c] = g[cur[c]];
-}
-
-__global__ void k_round_end(InstState* __restrict__ st, int B, int32_t* __restrict__ applied) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    const int b = int(c);
+    if (c >= B) return;
     InstState s = st[b];
     if (applied) applied[b] = s.apply;
     if (s.apply) {
@@ -795,10 +812,115 @@ __global__ void k_round_end(InstState* __restrict__ st, int B, int32_t* __restri
 // ===========================================================================
 // tail: one workgroup per instance, whole cell table in LDS
 // ===========================================================================
+// Candidate neighbours of a tail cell.  The table is sorted by key (dimension
+// 0 most significant), so the cells whose first one or two coordinates are
+// within +-1 of a cell's own form at most three ascending index ranges.  A
+// column table in LDS gives them directly: col[v] = first cell whose column
+// (c0, or c0 * E1 + c1) is >= v, for v in [0, ncol].  Without one (too many
+// columns) a binary search gives the range of dimension-0 coordinates.
+struct TailCols {
+    int mode;  // 2: columns of (c0, c1); 1: of c0; 0: no table
+    int E0, E1, ncol;
+    int first_test;  // first dimension the candidates still have to be tested in
+};
+
+template <int D>
+__device__ inline TailCols tail_cols(int64_t E0, int64_t E1) {
+    TailCols c;
+    c.E0 = int(E0);
+    c.E1 = D >= 2 ? int(E1) : 1;
+    if (D >= 2 && E0 * E1 <= kSlabMax) {
+        c.mode = 2;
+        c.ncol = int(E0 * E1);
+        c.first_test = 2;
+    } else if (E0 <= kSlabMax) {
+        c.mode = 1;
+        c.ncol = int(E0);
+        c.first_test = 1;
+    } else {
+        c.mode = 0;
+        c.ncol = 0;
+        c.first_test = 1;
+    }
+    return c;
+}
+
+__device__ inline int tail_col(const TailCols& c, const int32_t* crd0, const int32_t* crd1, int i) {
+    return c.mode == 2 ? crd0[i] * c.E1 + crd1[i] : crd0[i];
+}
+
+// Every thread of the workgroup calls this; a barrier must follow.
+__device__ inline void tail_cols_build(const TailCols& c, const int32_t* crd0, const int32_t* crd1, int m, int tid,
+                                       uint16_t* col) {
+    if (c.mode == 0 || tid >= m) return;
+    const int hi = tail_col(c, crd0, crd1, tid);
+    const int lo = tid == 0 ? 0 : tail_col(c, crd0, crd1, tid - 1) + 1;
+    for (int v = lo; v <= hi; ++v) col[v] = uint16_t(tid);
+    if (tid == m - 1)
+        for (int v = hi + 1; v <= c.ncol; ++v) col[v] = uint16_t(m);
+}
+
+struct TailWindow {
+    int a[3], n[3];  // ranges [a[u], a[u] + n[u]), ascending and disjoint
+};
+
+__device__ inline TailWindow tail_window(const TailCols& c, const int32_t* crd0, const int32_t* crd1, int m, int i,
+                                         const uint16_t* col) {
+    TailWindow w;
+    const int c0 = crd0[i];
+    if (c.mode == 2) {
+        const int c1 = crd1[i];
+        const int lo1 = c1 - 1 < 0 ? 0 : c1 - 1;
+        const int hi1 = c1 + 2 > c.E1 ? c.E1 : c1 + 2;
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int a0 = c0 - 1 + u;
+            if (a0 < 0 || a0 >= c.E0) {
+                w.a[u] = 0;
+                w.n[u] = 0;
+            } else {
+                w.a[u] = col[a0 * c.E1 + lo1];
+                w.n[u] = int(col[a0 * c.E1 + hi1]) - w.a[u];
+            }
+        }
+        return w;
+    }
+    int a, z;  // cells with dimension-0 coordinate in [c0 - 1, c0 + 1]
+    if (c.mode == 1) {
+        a = col[c0 - 1 < 0 ? 0 : c0 - 1];
+        z = col[c0 + 2 > c.E0 ? c.E0 : c0 + 2];
+    } else {
+        a = 0;
+        z = m;
+        while (a < z) {
+            const int mid = (a + z) >> 1;
+            if (crd0[mid] < c0 - 1) a = mid + 1; else z = mid;
+        }
+        z = a;
+        while (z < m && crd0[z] <= c0 + 1) ++z;
+    }
+    w.a[0] = a;
+    w.n[0] = z - a;
+    w.a[1] = w.a[2] = 0;
+    w.n[1] = w.n[2] = 0;
+    return w;
+}
+
+// Index of the e-th candidate of a window (e < n[0] + n[1] + n[2]).
+__device__ inline int tail_cand(const TailWindow& w, int e) {
+    const int n01 = w.n[0] + w.n[1];
+    return e < w.n[0] ? w.a[0] + e : (e < n01 ? w.a[1] + e - w.n[0] : w.a[2] + e - n01);
+}
+
+// With ck.every > 0 the forward also saves the table at the start of every
+// ck.every-th tail round.  With replay_r0 >= 0 the kernel instead recomputes
+// tail rounds [replay_r0, replay_r0 + ck.every) of a finished fit from the
+// checkpoint at replay_r0, writing only their tape (rounds numbered from
+// replay_r0); the fit's outputs and state are left untouched.
 template <int D>
 __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstParam* __restrict__ param,
                                                        InstState* __restrict__ st, uint32_t* __restrict__ tmap,
-                                                       int max_iter, TailTape tape) {
+                                                       int max_iter, TailTape tape, TailCkpt ck, int replay_r0) {
     constexpr int MT = kTailCells;
     constexpr int NW = kTailThreads / kWave;
     __shared__ uint64_t lkey[MT];     // local packed key (key - base), ascending
@@ -814,16 +936,22 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
     __shared__ uint16_t hstart[MT + 1];
     __shared__ int32_t wsum[NW];
     __shared__ int32_t s_maxsz;
-    __shared__ uint16_t slab[kSlabMax + 1];  // slab[c]: first cell with dimension-0 coordinate >= c
-    __shared__ uint16_t rank_of[MT];         // old cell -> sorted position
+    __shared__ uint16_t col[kSlabMax + 1];  // column table of the current cells
+    __shared__ uint16_t rank_of[MT];        // old cell -> sorted position
     __shared__ int32_t s_flag[2][3];         // per round parity: any neighbour, bad key, changed
 
     const int b = blockIdx.x;
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     InstState* S = st + b;
+    const bool replay = replay_r0 >= 0;
     const int64_t cs = S->cs, ce = S->ce;
-    const int m_entry = int(ce - cs);
-    if (!S->active) {
+    int m_entry = int(ce - cs);
+    int seg_rounds = 0;  // replay: rounds of the segment this instance ran
+    if (replay) {
+        seg_rounds = min(ck.every, S->t - S->t_tail0 - replay_r0);
+        if (seg_rounds <= 0) return;
+        m_entry = ck.m[int64_t(b) * ck.nslots + replay_r0 / ck.every];
+    } else if (!S->active) {
         for (int e = tid; e < m_entry; e += kTailThreads) tmap[cs + e] = uint32_t(e);
         if (tid == 0) {
             S->K = m_entry;
@@ -843,40 +971,51 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
     }
 
     if (tid < m_entry) {
-        const int64_t c = cs + tid;
-        const uint64_t lk = t.key[c] - P.base;
-        lkey[tid] = lk;
-        cnt[tid] = int32_t(t.cnt[c]);
+        uint64_t lk;
+        if (replay) {
+            const int64_t e = int64_t(b) * ck.stride + int64_t(replay_r0 / ck.every) * kTailCells + tid;
+            lk = ck.key[e];
+            cnt[tid] = ck.cnt[e];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            sm[k][tid] = t.sum[k * t.cap + c];
-            crd[k][tid] = int32_t((lk / stride[k]) % uint64_t(E[k]));
+            for (int k = 0; k < D; ++k) sm[k][tid] = ck.sum[k * ck.total + e];
+        } else {
+            const int64_t c = cs + tid;
+            lk = t.key[c] - P.base;
+            cnt[tid] = int32_t(t.cnt[c]);
+#pragma unroll
+            for (int k = 0; k < D; ++k) sm[k][tid] = t.sum[k * t.cap + c];
         }
+        lkey[tid] = lk;
+#pragma unroll
+        for (int k = 0; k < D; ++k) crd[k][tid] = int32_t((lk / stride[k]) % uint64_t(E[k]));
         lmap[tid] = uint16_t(tid);
     }
     __syncthreads();
 
     int m = m_entry;
-    int tt = S->t;
+    int tt = replay ? S->t_tail0 + replay_r0 : S->t;
     const int t_entry = tt;
-    if (tid == 0) S->t_tail0 = t_entry;
+    if (tid == 0 && !replay) S->t_tail0 = t_entry;
     uint32_t flags = S->flags;
     int err = 0;
     const uint64_t lt = lanemask_lt();
-    const int E0 = int(E[0]);
-    const bool use_slab = E0 <= kSlabMax;
+    const TailCols cols = tail_cols<D>(E[0], E[D >= 2 ? 1 : 0]);
     const bool fast_rank = P.span <= (1ull << 53);  // (key << 10 | index) fits in 63 bits
     if (tid < 6) (&s_flag[0][0])[tid] = 0;
     for (int round = 0;; ++round) {
+        if (replay && round == seg_rounds) break;
         int32_t* flg = s_flag[round & 1];
-        // ---- dimension-0 slab starts of the current table
-        if (use_slab && tid < m) {
-            const int hi = crd[0][tid];
-            const int lo = tid == 0 ? 0 : crd[0][tid - 1] + 1;
-            for (int c = lo; c <= hi; ++c) slab[c] = uint16_t(tid);
-            if (tid == m - 1)
-                for (int c = hi + 1; c <= E0; ++c) slab[c] = uint16_t(m);
+        if (!replay && ck.every > 0 && round % ck.every == 0 && tid < m) {  // checkpoint of the table
+            const int slot = round / ck.every;
+            const int64_t e = int64_t(b) * ck.stride + int64_t(slot) * kTailCells + tid;
+            ck.key[e] = lkey[tid];
+            ck.cnt[e] = cnt[tid];
+#pragma unroll
+            for (int k = 0; k < D; ++k) ck.sum[k * ck.total + e] = sm[k][tid];
+            if (tid == 0) ck.m[int64_t(b) * ck.nslots + slot] = m;
         }
+        // ---- column table of the current cells
+        tail_cols_build(cols, crd[0], crd[D >= 2 ? 1 : 0], m, tid, col);
         __syncthreads();
         // every thread has finished reading the other parity's flags
         if (tid < 3) s_flag[(round + 1) & 1][tid] = 0;
@@ -887,41 +1026,30 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         uint64_t kj = 0;
         int32_t Wj = 0;
         if (tid < m) {
-            const int32_t c0 = crd[0][tid];
-            int a, z;  // cells with dimension-0 coordinate in [c0 - 1, c0 + 1]
-            if (use_slab) {
-                a = slab[c0 - 1 < 0 ? 0 : c0 - 1];
-                z = slab[c0 + 2 > E0 ? E0 : c0 + 2];
-            } else {
-                a = 0;
-                z = m;
-                while (a < z) {
-                    const int mid = (a + z) >> 1;
-                    if (crd[0][mid] < c0 - 1) a = mid + 1; else z = mid;
-                }
-                z = a;
-                while (z < m && crd[0][z] <= c0 + 1) ++z;
-            }
+            const TailWindow win = tail_window(cols, crd[0], crd[D >= 2 ? 1 : 0], m, tid, col);
+            const int ncand = win.n[0] + win.n[1] + win.n[2];
             int32_t me[D];
 #pragma unroll
             for (int dd = 1; dd < D; ++dd) me[dd] = crd[dd][tid];
-            // Straight-line fold: a non-neighbour adds -0.0, the exact additive
-            // identity, and the fold starts from -0.0, so the result is
-            // bitwise the left fold over the neighbours alone.
+            // Straight-line fold over the candidates in ascending index: a
+            // non-neighbour adds -0.0, the exact additive identity, and the
+            // fold starts from -0.0, so the result is bitwise the left fold
+            // over the neighbours alone.
             int64_t W = 0;
 #pragma unroll
             for (int dd = 0; dd < D; ++dd) p[dd] = -0.0;
             int nbs = 0;
-            for (int k0 = a; k0 < z; k0 += 4) {
+            for (int k0 = 0; k0 < ncand; k0 += 4) {
                 int okm[4];
                 int kk[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    kk[u] = (k0 + u < z) ? k0 + u : k0;
-                    okm[u] = (k0 + u < z) ? 1 : 0;
+                    okm[u] = (k0 + u < ncand) ? 1 : 0;
+                    kk[u] = okm[u] ? tail_cand(win, k0 + u) : tid;
                 }
 #pragma unroll
                 for (int dd = 1; dd < D; ++dd) {
+                    if (dd < cols.first_test) continue;
 #pragma unroll
                     for (int u = 0; u < 4; ++u) okm[u] &= (uint32_t(crd[dd][kk[u]] - me[dd] + 1) <= 2u) ? 1 : 0;
                 }
@@ -1121,6 +1249,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         }
     }
     __syncthreads();
+    if (replay) return;
     if (err) {
         if (tid == 0) S->err = err;
         return;
@@ -1159,10 +1288,15 @@ __global__ void k_adj_final(CellTable t, const InstState* __restrict__ st, const
 // cells -> Sbar of the cells the tail started from.  For round t (reversed):
 // q_j = (C_j * Sbar_{g(j)}) / W_j, then Sbar_k = left fold in ascending key
 // of q_j over the round's cells j with Chebyshev key distance <= 1.
+// With ck.every > 0 the tape holds only the segment of tail rounds
+// [seg_r0, seg_r0 + ck.every) (recomputed from its checkpoint) and the kernel
+// reverses just those rounds; sbar then holds, per instance, the Sbar of the
+// cells at the segment's end on entry and at its start on exit.
 template <int D>
 __global__ __launch_bounds__(kTailThreads) void k_tail_adj(const InstParam* __restrict__ param,
                                                            const InstState* __restrict__ st, TailTape tape,
-                                                           double* __restrict__ sbar, int64_t cap) {
+                                                           double* __restrict__ sbar, int64_t cap, TailCkpt ck,
+                                                           int seg_r0) {
     constexpr int MT = kTailCells;
     __shared__ int32_t crd[D][MT];
     __shared__ int32_t cnt[MT];
@@ -1170,12 +1304,19 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_adj(const InstParam* __re
     __shared__ uint16_t gt[MT];
     __shared__ double A[D][MT];
     __shared__ double Q[D][MT];
-    __shared__ uint16_t slab[kSlabMax + 1];
+    __shared__ uint16_t col[kSlabMax + 1];
     const int b = blockIdx.x;
     const int tid = threadIdx.x;
     const InstState S = st[b];
-    const int rounds = S.t - S.t_tail0;
-    if (rounds <= 0) return;  // nothing ran in the tail: Sbar is already that of its entry cells
+    const int all_rounds = S.t - S.t_tail0;
+    int rounds = all_rounds;
+    int mnext = int(S.K);
+    if (ck.every > 0) {
+        rounds = min(ck.every, all_rounds - seg_r0);
+        if (rounds > 0 && seg_r0 + rounds < all_rounds)  // cells at the start of the next segment
+            mnext = ck.m[int64_t(b) * ck.nslots + seg_r0 / ck.every + 1];
+    }
+    if (rounds <= 0) return;  // no tail round here: Sbar is already that of the segment's start
     const InstParam& P = param[b];
     int64_t E[D];
     uint64_t stride[D];
@@ -1184,9 +1325,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_adj(const InstParam* __re
         E[k] = P.E[k];
         stride[k] = P.stride[k];
     }
-    const int E0 = int(E[0]);
-    const bool use_slab = E0 <= kSlabMax;
-    int mnext = int(S.K);
+    const TailCols cols = tail_cols<D>(E[0], E[D >= 2 ? 1 : 0]);
     if (tid < mnext)
 #pragma unroll
         for (int k = 0; k < D; ++k) A[k][tid] = sbar[k * cap + S.cs + tid];
@@ -1209,45 +1348,27 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_adj(const InstParam* __re
             for (int k = 0; k < D; ++k) Q[k][tid] = (double(C) * A[k][g]) / double(W);
         }
         __syncthreads();
-        if (use_slab && tid < m) {
-            const int hi = crd[0][tid];
-            const int lo = tid == 0 ? 0 : crd[0][tid - 1] + 1;
-            for (int c = lo; c <= hi; ++c) slab[c] = uint16_t(tid);
-            if (tid == m - 1)
-                for (int c = hi + 1; c <= E0; ++c) slab[c] = uint16_t(m);
-        }
+        tail_cols_build(cols, crd[0], crd[D >= 2 ? 1 : 0], m, tid, col);
         __syncthreads();
         if (tid < m) {
-            const int32_t c0 = crd[0][tid];
-            int a, z;
-            if (use_slab) {
-                a = slab[c0 - 1 < 0 ? 0 : c0 - 1];
-                z = slab[c0 + 2 > E0 ? E0 : c0 + 2];
-            } else {
-                a = 0;
-                z = m;
-                while (a < z) {
-                    const int mid = (a + z) >> 1;
-                    if (crd[0][mid] < c0 - 1) a = mid + 1; else z = mid;
-                }
-                z = a;
-                while (z < m && crd[0][z] <= c0 + 1) ++z;
-            }
+            const TailWindow win = tail_window(cols, crd[0], crd[D >= 2 ? 1 : 0], m, tid, col);
+            const int ncand = win.n[0] + win.n[1] + win.n[2];
             int32_t me[D];
 #pragma unroll
             for (int dd = 1; dd < D; ++dd) me[dd] = crd[dd][tid];
             double acc[D];
 #pragma unroll
             for (int dd = 0; dd < D; ++dd) acc[dd] = -0.0;
-            for (int k0 = a; k0 < z; k0 += 4) {
+            for (int k0 = 0; k0 < ncand; k0 += 4) {
                 int okm[4], kk[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    kk[u] = (k0 + u < z) ? k0 + u : k0;
-                    okm[u] = (k0 + u < z) ? 1 : 0;
+                    okm[u] = (k0 + u < ncand) ? 1 : 0;
+                    kk[u] = okm[u] ? tail_cand(win, k0 + u) : tid;
                 }
 #pragma unroll
                 for (int dd = 1; dd < D; ++dd) {
+                    if (dd < cols.first_test) continue;
 #pragma unroll
                     for (int u = 0; u < 4; ++u) okm[u] &= (uint32_t(crd[dd][kk[u]] - me[dd] + 1) <= 2u) ? 1 : 0;
                 }

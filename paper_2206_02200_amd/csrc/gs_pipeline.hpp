@@ -40,4 +40,19 @@ struct TailTape {
     int32_t max_rounds = 0;
 };
 
+// Checkpoints of the tail (differentiable form with recomputation): slot s of
+// instance b holds the cell table at the start of tail round s * every, in
+// entries [b * stride + s * kTailCells, ...); a k-round segment of the tape
+// is recomputed from its slot during the backward pass.
+struct TailCkpt {
+    uint64_t* key = nullptr;  // local packed key
+    int32_t* cnt = nullptr;   // counts
+    double* sum = nullptr;    // sums, [d][total]
+    int32_t* m = nullptr;     // [B][nslots] cells in each slot
+    int64_t stride = 0;       // entries per instance (nslots * kTailCells)
+    int64_t total = 0;        // B * stride
+    int32_t nslots = 0;
+    int32_t every = 0;        // 0: no checkpoints
+};
+
 }  // namespace gs

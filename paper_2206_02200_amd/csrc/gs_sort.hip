@@ -29,7 +29,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const K* __restrict_
 }
 
 // Exclusive scan of each pass's histogram; also resets the tile counters.
-__global__ __launch_bounds__(256) void k_sort_bases(const uint32_t* __restrict__ hist, uint32_t* __restrict__ dbase,
+// Exclusive digit bases of every pass; the histograms are left zeroed for the
+// next sort that accumulates into them.
+__global__ __launch_bounds__(256) void k_sort_bases(uint32_t* __restrict__ hist, uint32_t* __restrict__ dbase,
                                                     uint32_t* __restrict__ ctr, int npasses) {
     __shared__ uint32_t s[256];
     const int t = threadIdx.x;
@@ -44,6 +46,7 @@ __global__ __launch_bounds__(256) void k_sort_bases(const uint32_t* __restrict__
             __syncthreads();
         }
         dbase[p * 256 + t] = s[t] - hist[p * 256 + t];
+        hist[p * 256 + t] = 0;
         __syncthreads();
     }
 }

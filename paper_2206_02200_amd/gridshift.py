@@ -122,9 +122,13 @@ class Context:
             _check(lib.gs_context_create(ctypes.byref(h)))
         self.handle = h
 
-    def set_tape(self, on: bool = True):
-        """Record the trajectory of later fits (needed by the backward calls)."""
-        _check(_lib.gs_context_set_tape(self.handle, 1 if on else 0))
+    def set_tape(self, on: bool | int = True):
+        """Record the trajectory of later fits (needed by the backward calls).
+
+        True or 1 records every round; an integer k > 1 saves the tail's cell
+        table every k rounds instead and recomputes each k-round segment
+        during the backward pass; False or 0 records nothing."""
+        _check(_lib.gs_context_set_tape(self.handle, int(on)))
 
     def profile(self, prefix: str | None = ""):
         """Time later fits' kernels whose name starts with ``prefix`` (None: off)."""
@@ -318,9 +322,9 @@ class GridShiftModes(torch.autograd.Function):
     fit before the backward pass."""
 
     @staticmethod
-    def forward(actx, x, h, max_iter=100, offsets=None, ctx=None):
+    def forward(actx, x, h, max_iter=100, offsets=None, ctx=None, ckpt_every=1):
         gctx = ctx or Context(x.device.index)
-        gctx.set_tape(True)
+        gctx.set_tape(ckpt_every)
         labels, modes, counts, koff, infos = _fit_any(x, offsets, h, max_iter, gctx)
         actx.gctx = gctx
         actx.shape = tuple(x.shape)
@@ -332,7 +336,7 @@ class GridShiftModes(torch.autograd.Function):
     def backward(actx, g_modes, g_labels, g_counts):
         n, d = actx.shape
         grad = backward_modes(actx.gctx, g_modes, n, d)
-        return grad.to(actx.x_dtype), None, None, None, None
+        return grad.to(actx.x_dtype), None, None, None, None, None
 
 
 class PointModeLoss(torch.autograd.Function):
@@ -343,9 +347,9 @@ class PointModeLoss(torch.autograd.Function):
     direct term 2 (x_i - mode) plus the adjoint of the modes)."""
 
     @staticmethod
-    def forward(actx, x, h, max_iter=100, offsets=None, ctx=None):
+    def forward(actx, x, h, max_iter=100, offsets=None, ctx=None, ckpt_every=1):
         gctx = ctx or Context(x.device.index)
-        gctx.set_tape(True)
+        gctx.set_tape(ckpt_every)
         labels, modes, counts, koff, infos = _fit_any(x, offsets, h, max_iter, gctx)
         B = 1 if offsets is None else len(offsets) - 1
         loss = point_mode_loss_values(gctx, x, labels, B)
@@ -358,14 +362,16 @@ class PointModeLoss(torch.autograd.Function):
     def backward(actx, g_loss):
         x, labels = actx.saved_tensors
         grad = point_mode_loss_grad(actx.gctx, x, labels, g_loss)
-        return grad.to(actx.x_dtype), None, None, None, None
+        return grad.to(actx.x_dtype), None, None, None, None, None
 
 
-def point_mode_loss(x, h, max_iter=100, offsets=None, ctx=None):
-    """Differentiable point-to-mode loss (per instance, float64)."""
-    return PointModeLoss.apply(x, h, max_iter, offsets, ctx)
+def point_mode_loss(x, h, max_iter=100, offsets=None, ctx=None, ckpt_every=1):
+    """Differentiable point-to-mode loss (per instance, float64).  ckpt_every
+    > 1 keeps tail checkpoints every that many rounds instead of the whole
+    trajectory (same gradient, recomputed segment by segment)."""
+    return PointModeLoss.apply(x, h, max_iter, offsets, ctx, ckpt_every)
 
 
-def gridshift_modes(x, h, max_iter=100, offsets=None, ctx=None):
+def gridshift_modes(x, h, max_iter=100, offsets=None, ctx=None, ckpt_every=1):
     """Differentiable modes (float64) with labels and counts."""
-    return GridShiftModes.apply(x, h, max_iter, offsets, ctx)
+    return GridShiftModes.apply(x, h, max_iter, offsets, ctx, ckpt_every)

@@ -204,3 +204,66 @@ def test_backward_needs_a_recorded_fit():
     with pytest.raises(gridshift.GridShiftError) as e:
         gridshift.backward_modes(ctx, torch.ones_like(r.modes), 100, 2)
     assert e.value.code == 7
+
+
+# ---------------------------------------------------------------------------
+# checkpointed tail: segments recomputed in the backward pass
+# ---------------------------------------------------------------------------
+def _grads(x, off, hs, tape_mode, mubar_seed=6, max_iter=100):
+    X = torch.from_numpy(x).to(DEV)
+    ctx = gridshift.Context(0)
+    ctx.set_tape(tape_mode)
+    if off is None:
+        r = gridshift.fit(X, hs, max_iter, ctx=ctx)
+        K, labels, B = r.modes.shape[0], r.labels, 1
+    else:
+        r = gridshift.fit_batched(X, off, hs, max_iter, ctx=ctx)
+        K, labels, B = r.modes.shape[0], r.labels, len(off) - 1
+    mubar = np.random.default_rng(mubar_seed).standard_normal(size=(K, x.shape[1]))
+    g = gridshift.backward_modes(ctx, torch.from_numpy(mubar).to(DEV), x.shape[0], x.shape[1]).cpu().numpy()
+    gl = torch.linspace(0.5, 2.0, B, dtype=torch.float64, device=DEV)
+    gL = gridshift.point_mode_loss_grad(ctx, X, labels, gl).cpu().numpy()
+    ctx.close()
+    return g, gL, mubar
+
+
+@pytest.mark.parametrize("k", [2, 3, 8, 1000])
+def test_checkpointed_backward_equals_full_tape(k):
+    x = _blobs(770, 20000, 3)
+    g1, gL1, mubar = _grads(x, None, 2.0, 1)
+    gk, gLk, _ = _grads(x, None, 2.0, k)
+    np.testing.assert_array_equal(_bits(gk), _bits(g1))
+    np.testing.assert_array_equal(_bits(gLk), _bits(gL1))
+    res, tape = gs_oracle.fit_tape(x, 2.0)
+    _say(f"ckpt k={k}: rounds={res.n_iter}")
+    assert res.n_iter >= 3
+    np.testing.assert_array_equal(_bits(gk), _bits(tape.point_adjoint(mubar)))
+
+
+def test_checkpointed_backward_batched_wide_and_capped():
+    sizes = [120000, 0, 1, 5000, 800, 3000]
+    xs = [_blobs(780 + i, s, 3, k=30 if s > 100000 else 8, scale=8.0 if s > 100000 else 5.0,
+                 spread=20.0 if s > 100000 else 12.0) for i, s in enumerate(sizes)]
+    hs = [1.0, 1.0, 1.0, 2.0, 3.0, 1.5]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x = np.concatenate(xs, axis=0).astype(np.float32)
+    for mi in [100, 7]:
+        g1, gL1, _ = _grads(x, off, hs, 1, max_iter=mi)
+        for k in [2, 5, 8]:
+            _say(f"batched ckpt k={k} max_iter={mi}")
+            gk, gLk, _ = _grads(x, off, hs, k, max_iter=mi)
+            np.testing.assert_array_equal(_bits(gk), _bits(g1))
+            np.testing.assert_array_equal(_bits(gLk), _bits(gL1))
+
+
+def test_checkpointed_autograd_and_invalid_interval():
+    x = torch.from_numpy(_blobs(790, 20000, 5).astype(np.float32)).to(DEV)
+    xa = x.clone().requires_grad_(True)
+    gridshift.point_mode_loss(xa, 3.0).sum().backward()
+    xb = x.clone().requires_grad_(True)
+    gridshift.point_mode_loss(xb, 3.0, ckpt_every=8).sum().backward()
+    assert torch.equal(xa.grad, xb.grad)
+    ctx = gridshift.Context(0)
+    with pytest.raises(gridshift.GridShiftError) as e:
+        ctx.set_tape(-1)
+    assert e.value.code == 1
