@@ -188,6 +188,37 @@ gs_status gs_point_mode_loss_backward(gs_context* ctx, const void* points, const
                                       const double* grad_loss, double* grad_points, void* stream);
 
 /*
+ * Launch configuration of a context.  Every choice runs the same binary64
+ * operations in the same order, so labels, counts, sums and modes never
+ * depend on it; only the speed does.
+ *   GS_CFG_MERGE_SMALL  1 (default): the merge of a round run while some
+ *                       instance has more than 1024 cells, when the table
+ *                       holds at most 8192 cells and keys fit 32 bits, is done
+ *                       by one 1024-thread workgroup; 0: by device-wide
+ *                       kernels (radix sort, scans, segmented sums).
+ *   GS_CFG_TILE_CHUNKS  1..64 (default 4): chunks of staged point rows (24 KiB
+ *                       of coordinates each) per workgroup of the point-level
+ *                       binning kernels.
+ * Unknown keys and out-of-range values are GS_ERR_INVALID_ARG.
+ */
+enum { GS_CFG_MERGE_SMALL = 0, GS_CFG_TILE_CHUNKS = 1 };
+gs_status gs_context_set_config(gs_context* ctx, int32_t key, int32_t value);
+gs_status gs_context_get_config(const gs_context* ctx, int32_t key, int32_t* value);
+
+/*
+ * Autotuner: fits the given input (the arguments of gs_fit_batched; B = 1 and
+ * offsets {0, n} for one point set) once per candidate configuration
+ * (GS_CFG_MERGE_SMALL in {1, 0} x GS_CFG_TILE_CHUNKS in {1, 2, 4, 8}), one
+ * warm-up run and `reps` timed runs each (host wall time of the whole call,
+ * best of the reps), and keeps the fastest configuration in the context.  The
+ * labels of the timed fits go to a buffer the context owns; the context's
+ * last result is that of the last timed fit (identical for every
+ * configuration).  On error the previous configuration is kept.
+ */
+gs_status gs_autotune(gs_context* ctx, const void* points, gs_dtype dtype, int32_t d, int64_t ld, int32_t B,
+                      const int64_t* offsets, const double* h, int32_t max_iter, int32_t reps, void* stream);
+
+/*
  * Kernel timing (instrumentation, not part of the method).  When enabled,
  * every kernel launch of later fits whose name starts with `prefix` is
  * bracketed by HIP events on the launch stream; the elapsed times, launch

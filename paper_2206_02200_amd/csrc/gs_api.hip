@@ -1,6 +1,7 @@
 // Host side of the GridShift library: context, buffers, the fit pipelines and
 // the C ABI declared in include/gridshift.h.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -50,6 +51,13 @@ struct Profiler {
 
 }  // namespace
 
+// Launch choices; every choice runs the same binary64 operations in the same
+// order, so results never depend on them (only the speed does).
+struct gs_config {
+    int merge_small = 1;  // merge rounds of at most kMergeMax cells in one workgroup
+    int tile_chunks = 4;  // staged chunks of point rows per point tile
+};
+
 struct gs_context {
     int device = 0;
     // point level
@@ -65,6 +73,8 @@ struct gs_context {
     gs::SortScratch sort;
     uint32_t scan_epoch = 0;
     uint64_t tile_base = 0;  // value of the scan tile counter before the next scan
+    gs_config cfg;           // launch choices (results do not depend on them)
+    DBuf tune_labels;        // labels of the autotuner's timed fits
     // pinned staging: downloads (every one waits for its stream) and a bump
     // area for uploads, reused only once a wait on up_stream has drained them
     void* pinned = nullptr;
@@ -380,11 +390,14 @@ gs::CellTable table(gs_context* c, int i) {
 }
 
 // Canonical sums R of every cell's members (cells [0, m) of t, m on device).
+// With have_choff the chunk offsets and the task count (counters[1]) are
+// already on the device.
 template <int D, class Src>
 gs_status segsum_d(gs_context* c, Src src, gs::CellTable t, int64_t m_bound, int64_t npos, hipStream_t s,
-                   double member_bytes) {
+                   double member_bytes, bool have_choff = false) {
     int64_t* ctr = P<int64_t>(c->counters);
-    GS_TRY(run_scan(c, gs::ExclOp{t.nch, t.choff}, ctr + 0, m_bound, ctr + 1, s, "scan_chunks", 8.0 * m_bound));
+    if (!have_choff)
+        GS_TRY(run_scan(c, gs::ExclOp{t.nch, t.choff}, ctr + 0, m_bound, ctr + 1, s, "scan_chunks", 8.0 * m_bound));
     const int64_t tasks_bound = npos / gs::kChunk + m_bound + 1;
     GS_TRY(ensure(c->part, size_t(tasks_bound) * D * sizeof(double)));
     GS_TRY(ensure(c->partc, size_t(tasks_bound) * sizeof(int64_t)));
@@ -402,14 +415,14 @@ gs_status segsum_d(gs_context* c, Src src, gs::CellTable t, int64_t m_bound, int
 
 template <class Src>
 gs_status segsum(gs_context* c, int d, Src src, gs::CellTable t, int64_t m_bound, int64_t npos, hipStream_t s,
-                 double member_bytes) {
+                 double member_bytes, bool have_choff = false) {
     switch (d) {
-        case 1: return segsum_d<1>(c, src, t, m_bound, npos, s, member_bytes);
-        case 2: return segsum_d<2>(c, src, t, m_bound, npos, s, member_bytes);
-        case 3: return segsum_d<3>(c, src, t, m_bound, npos, s, member_bytes);
-        case 4: return segsum_d<4>(c, src, t, m_bound, npos, s, member_bytes);
-        case 5: return segsum_d<5>(c, src, t, m_bound, npos, s, member_bytes);
-        case 6: return segsum_d<6>(c, src, t, m_bound, npos, s, member_bytes);
+        case 1: return segsum_d<1>(c, src, t, m_bound, npos, s, member_bytes, have_choff);
+        case 2: return segsum_d<2>(c, src, t, m_bound, npos, s, member_bytes, have_choff);
+        case 3: return segsum_d<3>(c, src, t, m_bound, npos, s, member_bytes, have_choff);
+        case 4: return segsum_d<4>(c, src, t, m_bound, npos, s, member_bytes, have_choff);
+        case 5: return segsum_d<5>(c, src, t, m_bound, npos, s, member_bytes, have_choff);
+        case 6: return segsum_d<6>(c, src, t, m_bound, npos, s, member_bytes, have_choff);
     }
     return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
 }
@@ -541,7 +554,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     GS_TRY(ensure(c->vA, size_t(N) * 4));
     GS_TRY(ensure(c->vB, size_t(N) * 4));
     GS_TRY(ensure(c->cell0, size_t(N) * 4));
-    GS_TRY(ensure(c->shist, gs::kSortMaxPasses * 256 * 4));
+    GS_TRY(ensure(c->shist, gs::kHistCopies * gs::kHistStride * 4));
     GS_TRY(ensure(c->sdbase, gs::kSortMaxPasses * 256 * 4));
     GS_TRY(ensure(c->sctr, 64));
     const int64_t sort_tiles = gs::sort_look_tiles(N);
@@ -560,11 +573,18 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     c->sort.prof_end = sort_prof_end;
 
     const int np = gs::sort_passes(bits);
-    {  // the digit histograms were cleared by k_init_state
-        if (c->ntiles > 0)
-            PROF_LAUNCH("make_keys", N * (double(d) * sizeof(T) + sizeof(K)),
-                        gs::k_make_keys<T, K><<<unsigned(c->ntiles), gs::kBoxThreads, 0, s>>>(
-                            x, ld, d, P<gs::RowTile>(c->tiles), prm, P<K>(c->kA), np, c->sort.hist));
+    if (c->ntiles > 0) {  // the digit histograms were cleared by k_init_state
+        const unsigned g = unsigned(c->ntiles);
+        const gs::RowTile* tl = P<gs::RowTile>(c->tiles);
+        const int tk = prof_begin(c, s, "make_keys");
+        switch (d) {
+#define GS_MK(D) \
+    case D: gs::k_make_keys<T, K, D><<<g, gs::kBoxThreads, 0, s>>>(x, ld, tl, prm, P<K>(c->kA), np, c->sort.hist); break;
+            GS_MK(1) GS_MK(2) GS_MK(3) GS_MK(4) GS_MK(5) GS_MK(6)
+#undef GS_MK
+            default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+        }
+        prof_end(c, s, tk, N * (double(d) * sizeof(T) + sizeof(K)));
         GS_HIP(hipGetLastError());
     }
     K* skeys = nullptr;
@@ -678,6 +698,36 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         GS_TRY(launch_shift(c, d, TT, M, prm, st, P<uint64_t>(c->hk), P<uint32_t>(c->hv), logcap, P<double>(c->pbuf),
                             P<uint64_t>(c->kappa), Wrec, s));
         gs::k_decide<<<blocks_for(B, 256), 256, 0, s>>>(st, B, max_iter);
+        if (sizeof(K) == 4 && M <= gs::kMergeMax && c->cfg.merge_small) {
+            // the whole merge and the round's bookkeeping in one workgroup
+            uint32_t* gt = c->tape_on ? P<uint32_t>(c->wt_g) + woff : nullptr;
+            const int tk = prof_begin(c, s, "merge_small");
+            switch (d) {
+#define GS_MS(D)                                                                                                   \
+    case D:                                                                                                        \
+        gs::k_merge_small<D><<<1, gs::kMergeThreads, 0, s>>>(TT, M, U, st, P<double>(c->pbuf),                     \
+                                                             P<uint64_t>(c->kappa), np, P<uint32_t>(c->gmap),      \
+                                                             P<uint32_t>(c->cvA), P<uint32_t>(c->cur), m0, gt,     \
+                                                             ctr);                                                 \
+        break;
+                GS_MS(1) GS_MS(2) GS_MS(3) GS_MS(4) GS_MS(5) GS_MS(6)
+#undef GS_MS
+                default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+            }
+            prof_end(c, s, tk, M * (8.0 * 3 + 16.0 * d + 8.0) + m0 * 8.0);
+            GS_HIP(hipGetLastError());
+            gs::SrcMerge src{P<double>(c->pbuf), TT.sum, TT.cnt, TT.inst, st, P<uint32_t>(c->cvA), c->capM};
+            GS_TRY(segsum(c, d, src, U, M, M, s, 4.0 + 4.0 + 8.0 + 8.0 * d, true));
+            PROF_LAUNCH("round_end", B * 48.0,
+                        gs::k_round_end<<<blocks_for(B, 256), 256, 0, s>>>(P<uint32_t>(c->cur), 0,
+                                                                            P<uint32_t>(c->gmap), st, B, apprec));
+            GS_HIP(hipGetLastError());
+            cur = 1 - cur;
+            GS_TRY(d2h_batch(c, {{&M, ctr + 0, sizeof(int64_t)}, {c->st.data(), st, sizeof(gs::InstState) * B}}, s));
+            for (int b = 0; b < B; ++b)
+                if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");
+            continue;
+        }
         PROF_LAUNCH("merge_prep", M * (8.0 * 3 + 16.0 * d + sizeof(K)),
                     gs::k_merge_prep<K><<<blocks_for(M, 256), 256, 0, s>>>(TT, M, st, st, P<double>(c->pbuf),
                                                                             P<uint64_t>(c->kappa), P<K>(c->ckA), d,
@@ -911,12 +961,13 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
     GS_TRY(ensure(c->hs, sizeof(double) * B));
     GS_TRY(ensure(c->bbox, sizeof(int64_t) * B * gs::kMaxDim * 2));
     GS_TRY(ensure(c->counters, 8 * sizeof(int64_t)));
-    // row tiles of at most kTileRows rows, each inside one instance
+    // row tiles of tile_chunks staged chunks of rows, each inside one instance
+    const int trows = c->cfg.tile_chunks * gs::chunk_rows(d, dtype == GS_F32 ? 4 : 8);
     std::vector<gs::RowTile> tiles;
     std::vector<int64_t> tile_off(B + 1, 0);
     for (int b = 0; b < B; ++b) {
-        for (int64_t r = offsets[b]; r < offsets[b + 1]; r += gs::kTileRows)
-            tiles.push_back({r, std::min<int64_t>(r + gs::kTileRows, offsets[b + 1]), b, 0});
+        for (int64_t r = offsets[b]; r < offsets[b + 1]; r += trows)
+            tiles.push_back({r, std::min<int64_t>(r + trows, offsets[b + 1]), b, 0});
         tile_off[b + 1] = int64_t(tiles.size());
     }
     c->ntiles = int64_t(tiles.size());
@@ -929,8 +980,8 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
                       {c->tiles.p, tiles.data(), sizeof(gs::RowTile) * tiles.size()},
                       {c->tileoff.p, tile_off.data(), sizeof(int64_t) * (B + 1)}},
                      s));
-    GS_TRY(ensure(c->shist, gs::kSortMaxPasses * 256 * 4));
-    gs::k_init_state<<<blocks_for(std::max(B, gs::kSortMaxPasses * 256), 256), 256, 0, s>>>(
+    GS_TRY(ensure(c->shist, gs::kHistCopies * gs::kHistStride * 4));
+    gs::k_init_state<<<blocks_for(std::max(B, gs::kHistCopies * gs::kHistStride), 256), 256, 0, s>>>(
         P<gs::InstState>(c->state), B, P<int64_t>(c->bbox), d, P<int64_t>(c->counters), P<uint32_t>(c->shist));
     GS_HIP(hipGetLastError());
 
@@ -938,16 +989,22 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
     if (N > 0) {
         const unsigned g = unsigned(tiles.size());
         const double xb = double(N) * d * (dtype == GS_F32 ? 4.0 : 8.0);
-        if (dtype == GS_F32)
-            PROF_LAUNCH("bbox", xb,
-                        gs::k_bbox_tiles<float><<<g, gs::kBoxThreads, 0, s>>>(
-                            static_cast<const float*>(points), ld, d, P<gs::RowTile>(c->tiles), P<double>(c->hs),
-                            P<int64_t>(c->bpart), P<int64_t>(c->counters)));
-        else
-            PROF_LAUNCH("bbox", xb,
-                        gs::k_bbox_tiles<double><<<g, gs::kBoxThreads, 0, s>>>(
-                            static_cast<const double*>(points), ld, d, P<gs::RowTile>(c->tiles), P<double>(c->hs),
-                            P<int64_t>(c->bpart), P<int64_t>(c->counters)));
+        const gs::RowTile* tl = P<gs::RowTile>(c->tiles);
+        const double* hsd = P<double>(c->hs);
+        int64_t* bp = P<int64_t>(c->bpart);
+        int64_t* cn = P<int64_t>(c->counters);
+        const float* xf = static_cast<const float*>(points);
+        const double* xd = static_cast<const double*>(points);
+        const int tk = prof_begin(c, s, "bbox");
+        switch (d * 2 + (dtype == GS_F32 ? 0 : 1)) {
+#define GS_BB(D)                                                                                               \
+    case 2 * D: gs::k_bbox_tiles<float, D><<<g, gs::kBoxThreads, 0, s>>>(xf, ld, tl, hsd, bp, cn); break;     \
+    case 2 * D + 1: gs::k_bbox_tiles<double, D><<<g, gs::kBoxThreads, 0, s>>>(xd, ld, tl, hsd, bp, cn); break;
+            GS_BB(1) GS_BB(2) GS_BB(3) GS_BB(4) GS_BB(5) GS_BB(6)
+#undef GS_BB
+            default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+        }
+        prof_end(c, s, tk, xb);
         PROF_LAUNCH("bbox_reduce", tiles.size() * 96.0,
                     gs::k_bbox_reduce<<<B, 256, 0, s>>>(P<int64_t>(c->bpart), P<int64_t>(c->tileoff),
                                                         P<int64_t>(c->bbox)));
@@ -1126,7 +1183,7 @@ void gs_context_destroy(gs_context* c) {
     DBuf* tb2[] = {&c->sums0, &c->inst0, &c->wt_key, &c->wt_cnt, &c->wt_inst, &c->wt_W, &c->wt_g, &c->wt_app,
                    &c->tt_key, &c->tt_cnt, &c->tt_W, &c->tt_g, &c->tt_m, &c->sbA, &c->sbB, &c->qbuf, &c->gmodes,
                    &c->modes_i, &c->counts_i, &c->frows, &c->lossc, &c->ltab, &c->xkA, &c->xkB, &c->xvA, &c->xvB,
-                   &c->ck_key, &c->ck_cnt, &c->ck_sum, &c->ck_m};
+                   &c->ck_key, &c->ck_cnt, &c->ck_sum, &c->ck_m, &c->tune_labels};
     for (DBuf* b : tb2)
         if (b->p) (void)hipFree(b->p);
     delete c;
@@ -1145,6 +1202,74 @@ gs_status gs_fit_batched(gs_context* ctx, const void* points, gs_dtype dtype, in
                          void* stream) {
     return fit_impl(ctx, points, dtype, d, ld, B, offsets, h, max_iter, labels, info,
                     static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_context_set_config(gs_context* ctx, int32_t key, int32_t value) {
+    if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
+    switch (key) {
+        case GS_CFG_MERGE_SMALL:
+            if (value != 0 && value != 1) return fail(GS_ERR_INVALID_ARG, "GS_CFG_MERGE_SMALL takes 0 or 1");
+            ctx->cfg.merge_small = value;
+            return GS_OK;
+        case GS_CFG_TILE_CHUNKS:
+            if (value < 1 || value > 64) return fail(GS_ERR_INVALID_ARG, "GS_CFG_TILE_CHUNKS takes 1..64");
+            ctx->cfg.tile_chunks = value;
+            return GS_OK;
+    }
+    return fail(GS_ERR_INVALID_ARG, "unknown configuration key");
+}
+
+gs_status gs_context_get_config(const gs_context* ctx, int32_t key, int32_t* value) {
+    if (!ctx || !value) return fail(GS_ERR_INVALID_ARG, "null argument");
+    switch (key) {
+        case GS_CFG_MERGE_SMALL: *value = ctx->cfg.merge_small; return GS_OK;
+        case GS_CFG_TILE_CHUNKS: *value = ctx->cfg.tile_chunks; return GS_OK;
+    }
+    return fail(GS_ERR_INVALID_ARG, "unknown configuration key");
+}
+
+gs_status gs_autotune(gs_context* ctx, const void* points, gs_dtype dtype, int32_t d, int64_t ld, int32_t B,
+                      const int64_t* offsets, const double* h, int32_t max_iter, int32_t reps, void* stream) {
+    if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
+    if (B < 1 || !offsets || !h || reps < 1) return fail(GS_ERR_INVALID_ARG, "B, offsets, h and reps are required");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t N = offsets[B];
+    if (N < 0) return fail(GS_ERR_INVALID_ARG, "offsets must be non-decreasing from 0");
+    GS_HIP(hipSetDevice(ctx->device));
+    GS_TRY(ensure(ctx->tune_labels, size_t(std::max<int64_t>(N, 1)) * 4));
+    std::vector<gs_info> info(B);
+    const bool prof = ctx->prof.on;
+    ctx->prof.on = false;
+    const gs_config keep = ctx->cfg;
+    gs_config best = keep;
+    double best_ms = 0.0;
+    bool first = true;
+    gs_status rc = GS_OK;
+    for (int ms = 1; ms >= 0 && rc == GS_OK; --ms) {
+        for (int tc : {1, 2, 4, 8}) {
+            ctx->cfg.merge_small = ms;
+            ctx->cfg.tile_chunks = tc;
+            double t_min = 0.0;
+            for (int r = 0; r <= reps; ++r) {  // the first run is a warm-up
+                const auto t0 = std::chrono::steady_clock::now();
+                rc = fit_impl(ctx, points, dtype, d, ld, B, offsets, h, max_iter, P<int32_t>(ctx->tune_labels),
+                              info.data(), s);
+                const auto t1 = std::chrono::steady_clock::now();
+                if (rc != GS_OK) break;
+                const double t = std::chrono::duration<double, std::milli>(t1 - t0).count();
+                if (r == 1 || (r > 1 && t < t_min)) t_min = t;
+            }
+            if (rc != GS_OK) break;
+            if (first || t_min < best_ms) {
+                best_ms = t_min;
+                best = ctx->cfg;
+                first = false;
+            }
+        }
+    }
+    ctx->prof.on = prof;
+    ctx->cfg = rc == GS_OK ? best : keep;
+    return rc;
 }
 
 gs_status gs_profile_enable(gs_context* ctx, const char* prefix) {

@@ -48,7 +48,7 @@ __device__ __forceinline__ double cell_floor(double v, double h) { return floor(
 __global__ void k_init_state(InstState* __restrict__ st, int B, int64_t* __restrict__ bbox, int d,
                              int64_t* __restrict__ counters, uint32_t* __restrict__ sort_hist) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < kSortMaxPasses * 256) sort_hist[b] = 0;
+    if (b < kHistCopies * kHistStride) sort_hist[b] = 0;
     if (b < B) {
         InstState z = {};
         z.active = 1;
@@ -62,14 +62,24 @@ __global__ void k_init_state(InstState* __restrict__ st, int B, int64_t* __restr
 }
 
 // ===========================================================================
-// bbox: per instance and dimension, min/max of floor(fl(x/h))
+// point-tile staging
 // ===========================================================================
-// Rows are cut into tiles of kTileRows that never straddle two instances;
-// each block reduces one tile to a partial box, then one block per instance
-// reduces its tiles' partials.
+// Rows are cut into tiles that never straddle two instances.  A block walks
+// its tile in chunks of at most kStageBytes of coordinates: it copies a chunk
+// into LDS with consecutive lanes reading consecutive dwords (whole cache
+// lines per wave instruction), issues the next chunk's loads, and meanwhile
+// each thread reads whole rows of the current chunk back from LDS.
 constexpr int kBoxThreads = 256;
-constexpr int kTileRows = 2048;
-constexpr int kRowsPerThread = kTileRows / kBoxThreads;  // 8
+constexpr int kStageBytes = 24576;
+constexpr int kMaxChunkRows = 2048;
+
+// Rows per chunk for d coordinates of `elem` bytes: a multiple of the block
+// size, at most kMaxChunkRows, with rows * d * elem <= kStageBytes.
+__host__ __device__ constexpr int chunk_rows(int d, int elem) {
+    return (kStageBytes / (d * elem)) / kBoxThreads * kBoxThreads > kMaxChunkRows
+               ? kMaxChunkRows
+               : (kStageBytes / (d * elem)) / kBoxThreads * kBoxThreads;
+}
 
 struct RowTile {
     int64_t r0, r1;  // rows [r0, r1) of one instance
@@ -77,53 +87,105 @@ struct RowTile {
     int32_t pad;
 };
 
-template <typename T>
-__global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict__ x, int64_t ld, int d,
+template <typename T, int D>
+struct Stager {
+    static constexpr int R = chunk_rows(D, int(sizeof(T)));
+    static constexpr int DW = R * D * int(sizeof(T)) / 4;           // dwords of a full chunk
+    static constexpr int PER = (DW + kBoxThreads - 1) / kBoxThreads;  // dwords per thread
+    uint32_t v[PER];
+    // Issue the loads of rows [r0, r0 + rows) (contiguous rows only).
+    __device__ __forceinline__ void load(const T* __restrict__ x, int64_t ld, int64_t r0, int rows) {
+        if (ld != D) return;
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(x + r0 * D);
+        const int ndw = rows * D * int(sizeof(T)) / 4;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = int(threadIdx.x) + i * kBoxThreads;
+            v[i] = e < ndw ? src[e] : 0u;
+        }
+    }
+    // Rows [r0, r0 + rows) into lds as rows * D consecutive elements.
+    __device__ __forceinline__ void store(const T* __restrict__ x, int64_t ld, int64_t r0, int rows, T* lds) {
+        if (ld == D) {
+            uint32_t* dst = reinterpret_cast<uint32_t*>(lds);
+            const int ndw = rows * D * int(sizeof(T)) / 4;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int e = int(threadIdx.x) + i * kBoxThreads;
+                if (e < ndw) dst[e] = v[i];
+            }
+        } else {
+            for (int e = int(threadIdx.x); e < rows * D; e += kBoxThreads) {
+                const int r = e / D, k = e - r * D;
+                lds[e] = x[(r0 + r) * ld + k];
+            }
+        }
+    }
+};
+
+// ===========================================================================
+// bbox: per instance and dimension, min/max of floor(fl(x/h))
+// ===========================================================================
+// Each block reduces one tile to a partial box, then one block per instance
+// reduces its tiles' partials.
+template <typename T, int D>
+__global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict__ x, int64_t ld,
                                                             const RowTile* __restrict__ tiles,
                                                             const double* __restrict__ hs,
                                                             int64_t* __restrict__ part,  // [tiles][kMaxDim][2]
                                                             int64_t* __restrict__ counters) {
-    __shared__ int64_t red[kBoxThreads / kWave][2 * kMaxDim];
+    using S = Stager<T, D>;
+    constexpr int R = S::R;
+    constexpr int RPT = R / kBoxThreads;
+    __shared__ T stage[R * D];
+    __shared__ int64_t red[kBoxThreads / kWave][2 * D];
     const RowTile tl = tiles[blockIdx.x];
     const double h = hs[tl.inst];
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-    int64_t mn[kMaxDim], mx[kMaxDim];
+    int64_t mn[D], mx[D];
 #pragma unroll
-    for (int k = 0; k < kMaxDim; ++k) {
+    for (int k = 0; k < D; ++k) {
         mn[k] = INT64_MAX;
         mx[k] = INT64_MIN;
     }
     int err = 0;
-    double v[kRowsPerThread][kMaxDim];
+    S sg;
+    int64_t c0 = tl.r0;
+    int crows = int(tl.r1 - c0 < R ? tl.r1 - c0 : R);
+    sg.load(x, ld, c0, crows);
+    while (crows > 0) {
+        sg.store(x, ld, c0, crows, stage);
+        __syncthreads();
+        const int64_t n0 = c0 + crows;
+        const int nrows = int(tl.r1 - n0 < R ? tl.r1 - n0 : R);
+        if (nrows > 0) sg.load(x, ld, n0, nrows);  // in flight while this chunk is reduced
 #pragma unroll
-    for (int i = 0; i < kRowsPerThread; ++i) {
-        const int64_t r = tl.r0 + tid + int64_t(i) * kBoxThreads;
+        for (int i = 0; i < RPT; ++i) {
+            const int r = tid + i * kBoxThreads;
+            if (r >= crows) continue;
 #pragma unroll
-        for (int k = 0; k < kMaxDim; ++k) v[i][k] = (r < tl.r1 && k < d) ? load_coord(x, r, ld, k) : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < kRowsPerThread; ++i) {
-        const int64_t r = tl.r0 + tid + int64_t(i) * kBoxThreads;
-        if (r >= tl.r1) continue;
-#pragma unroll
-        for (int k = 0; k < kMaxDim; ++k) {
-            if (k >= d) continue;
-            if (!isfinite(v[i][k])) {
-                err |= 1;
-                continue;
+            for (int k = 0; k < D; ++k) {
+                const double v = double(stage[r * D + k]);
+                if (!isfinite(v)) {
+                    err |= 1;
+                    continue;
+                }
+                const double q = cell_floor(v, h);
+                if (!(q > -4503599627370496.0 && q < 4503599627370496.0)) {  // |q| < 2^52
+                    err |= 2;
+                    continue;
+                }
+                const int64_t qi = int64_t(q);
+                mn[k] = qi < mn[k] ? qi : mn[k];
+                mx[k] = qi > mx[k] ? qi : mx[k];
             }
-            const double q = cell_floor(v[i][k], h);
-            if (!(q > -4503599627370496.0 && q < 4503599627370496.0)) {  // |q| < 2^52
-                err |= 2;
-                continue;
-            }
-            const int64_t qi = int64_t(q);
-            mn[k] = qi < mn[k] ? qi : mn[k];
-            mx[k] = qi > mx[k] ? qi : mx[k];
         }
+        __syncthreads();  // every row read before the next chunk is stored
+        c0 = n0;
+        crows = nrows;
     }
 #pragma unroll
-    for (int k = 0; k < kMaxDim; ++k) {
+    for (int k = 0; k < D; ++k) {
         for (int off = 32; off >= 1; off >>= 1) {
             const int64_t a = __shfl_xor(mn[k], off, kWave);
             const int64_t c = __shfl_xor(mx[k], off, kWave);
@@ -145,10 +207,11 @@ __global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict_
     if (tid < 2 * kMaxDim) {
         const bool isMin = (tid & 1) == 0;
         int64_t a = isMin ? INT64_MAX : INT64_MIN;
-        for (int ww = 0; ww < kBoxThreads / kWave; ++ww) {
-            const int64_t c = red[ww][tid];
-            a = isMin ? (c < a ? c : a) : (c > a ? c : a);
-        }
+        if (tid < 2 * D)
+            for (int ww = 0; ww < kBoxThreads / kWave; ++ww) {
+                const int64_t c = red[ww][tid];
+                a = isMin ? (c < a ? c : a) : (c > a ? c : a);
+            }
         part[int64_t(blockIdx.x) * 2 * kMaxDim + tid] = a;
     }
 }
@@ -190,64 +253,71 @@ __global__ __launch_bounds__(256) void k_bbox_reduce(const int64_t* __restrict__
 // ===========================================================================
 // packed keys + radix digit histograms
 // ===========================================================================
-template <typename T, typename K>
-__global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__ x, int64_t ld, int d,
+template <typename T, typename K, int D>
+__global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__ x, int64_t ld,
                                                            const RowTile* __restrict__ tiles,
                                                            const InstParam* __restrict__ param,
                                                            K* __restrict__ keys, int npasses,
                                                            uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[kSortMaxPasses * 256];
+    using S = Stager<T, D>;
+    constexpr int R = S::R;
+    constexpr int RPT = R / kBoxThreads;
+    __shared__ T stage[R * D];
+    __shared__ uint32_t hl[kSortMaxPasses * 256];
     __shared__ InstParam sp;
     const RowTile tl = tiles[blockIdx.x];
-    const int tid = threadIdx.x;
-    for (int i = tid; i < npasses * 256; i += kBoxThreads) h[i] = 0;
+    const int tid = threadIdx.x, lane = lane_id();
+    for (int i = tid; i < npasses * 256; i += kBoxThreads) hl[i] = 0;
     if (tid == 0) sp = param[tl.inst];
-    __syncthreads();
-    const double hh = sp.h;
-    double v[kRowsPerThread][kMaxDim];
+    S sg;
+    int64_t c0 = tl.r0;
+    int crows = int(tl.r1 - c0 < R ? tl.r1 - c0 : R);
+    sg.load(x, ld, c0, crows);
+    while (crows > 0) {
+        sg.store(x, ld, c0, crows, stage);
+        __syncthreads();
+        const int64_t n0 = c0 + crows;
+        const int nrows = int(tl.r1 - n0 < R ? tl.r1 - n0 : R);
+        if (nrows > 0) sg.load(x, ld, n0, nrows);  // in flight while this chunk is keyed
+        const double hh = sp.h;
+        K kv[RPT];
 #pragma unroll
-    for (int i = 0; i < kRowsPerThread; ++i) {
-        const int64_t r = tl.r0 + tid + int64_t(i) * kBoxThreads;
+        for (int i = 0; i < RPT; ++i) {
+            const int r = tid + i * kBoxThreads;
+            uint64_t key = sp.base;
 #pragma unroll
-        for (int k = 0; k < kMaxDim; ++k) v[i][k] = (r < tl.r1 && k < d) ? load_coord(x, r, ld, k) : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < kRowsPerThread; ++i) {
-        const int64_t r = tl.r0 + tid + int64_t(i) * kBoxThreads;
-        if (r >= tl.r1) continue;
-        uint64_t key = sp.base;
-#pragma unroll
-        for (int k = 0; k < kMaxDim; ++k) {
-            if (k >= d) continue;
-            const double q = cell_floor(v[i][k], hh);
-            key += uint64_t(int64_t(q) - sp.lo[k]) * sp.stride[k];
+            for (int k = 0; k < D; ++k) {
+                const double q = cell_floor(double(stage[(r < crows ? r : 0) * D + k]), hh);
+                key += uint64_t(int64_t(q) - sp.lo[k]) * sp.stride[k];
+            }
+            kv[i] = K(key);
+            if (r < crows) keys[c0 + r] = kv[i];
         }
-        keys[r] = K(key);
-    }
-    // digit histograms: one LDS atomic per wave when all its lanes share the
-    // digit (neighbouring points usually share a cell), else one per lane
-    const int lane = lane_id();
+        // digit histograms: one LDS atomic per wave when all its lanes share
+        // the digit (neighbouring points usually share a cell), else one per lane
 #pragma unroll
-    for (int i = 0; i < kRowsPerThread; ++i) {
-        const int64_t r = tl.r0 + tid + int64_t(i) * kBoxThreads;
-        const bool valid = r < tl.r1;
-        const K key = valid ? keys[r] : K(0);
-        const uint64_t act = __ballot(valid);
-        if (!act) continue;
-        const int lead = __ffsll((unsigned long long)act) - 1;
-        for (int p = 0; p < npasses; ++p) {
-            const uint32_t dgt = uint32_t(key >> (8 * p)) & 255u;
-            const uint32_t d0 = __shfl(dgt, lead, kWave);
-            if (__ballot(valid && dgt == d0) == act) {
-                if (lane == lead) atomicAdd(&h[p * 256 + d0], uint32_t(__popcll(act)));
-            } else if (valid) {
-                atomicAdd(&h[p * 256 + dgt], 1u);
+        for (int i = 0; i < RPT; ++i) {
+            const bool valid = tid + i * kBoxThreads < crows;
+            const uint64_t act = __ballot(valid);
+            if (!act) continue;
+            const int lead = __ffsll((unsigned long long)act) - 1;
+            for (int p = 0; p < npasses; ++p) {
+                const uint32_t dgt = uint32_t(kv[i] >> (8 * p)) & 255u;
+                const uint32_t d0 = __shfl(dgt, lead, kWave);
+                if (__ballot(valid && dgt == d0) == act) {
+                    if (lane == lead) atomicAdd(&hl[p * 256 + d0], uint32_t(__popcll(act)));
+                } else if (valid) {
+                    atomicAdd(&hl[p * 256 + dgt], 1u);
+                }
             }
         }
+        __syncthreads();  // every row read before the next chunk is stored
+        c0 = n0;
+        crows = nrows;
     }
-    __syncthreads();
+    uint32_t* hc = hist + (blockIdx.x % kHistCopies) * kHistStride;
     for (int i = tid; i < npasses * 256; i += kBoxThreads)
-        if (h[i]) atomicAdd(&hist[i], h[i]);
+        if (hl[i]) atomicAdd(&hc[i], hl[i]);
 }
 
 // ===========================================================================
@@ -266,6 +336,7 @@ struct HeadsOp {
     uint32_t* cell_start;    // [m]
     uint32_t* cell_first;    // [m] member at the start of the run
     uint32_t* member_cell;   // [n] member index -> cell id
+    static constexpr bool kBinary = true;  // values are 0 or 1
     __device__ uint32_t value(int64_t p) const { return (p == 0 || key[p] != key[p - 1]) ? 1u : 0u; }
     __device__ void emit(int64_t p, uint64_t excl, uint32_t v) const {
         const uint64_t cid = excl + v - 1;
@@ -283,6 +354,7 @@ struct HeadsOp {
 struct ExclOp {
     const uint32_t* in;
     uint32_t* out;
+    static constexpr bool kBinary = false;
     __device__ uint32_t value(int64_t p) const { return in[p]; }
     __device__ void emit(int64_t p, uint64_t excl, uint32_t) const { out[p] = uint32_t(excl); }
 };
@@ -315,16 +387,26 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __r
         const int64_t p = t0 + int64_t(w) * (kWave * kScanItems) + i * kWave + lane;
         v[i] = p < n ? op.value(p) : 0u;
     }
+    if constexpr (Op::kBinary) {  // 0/1 values: prefix counts from ballots
+        const uint64_t le = lanemask_lt() | (1ull << lane);
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        uint64_t xs = v[i];
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const uint64_t y = __shfl_up(xs, off, kWave);
-            if (lane >= off) xs += y;
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint64_t bal = __ballot(v[i] != 0);
+            incl[i] = run + uint64_t(__popcll(bal & le));
+            run += uint64_t(__popcll(bal));
         }
-        incl[i] = run + xs;
-        run += __shfl(xs, kWave - 1, kWave);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            uint64_t xs = v[i];
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const uint64_t y = __shfl_up(xs, off, kWave);
+                if (lane >= off) xs += y;
+            }
+            incl[i] = run + xs;
+            run += __shfl(xs, kWave - 1, kWave);
+        }
     }
     if (lane == 0) wtot[w] = run;
     __syncthreads();
@@ -625,7 +707,7 @@ __device__ __forceinline__ int64_t hash_find(const uint64_t* __restrict__ hk, co
 // lane k folds dimension k left to right and lane D adds the integer weight.
 // p = N / W and the landing key floor(p/h) follow.
 constexpr int kShiftWaves = 4;
-constexpr int kSlabMax = 4096;  // most columns of a tail's column table
+constexpr int kSlabMax = 4096;       // most columns of a tail's column table
 
 __host__ __device__ constexpr int pow3(int d) { return d == 0 ? 1 : 3 * pow3(d - 1); }
 
@@ -783,8 +865,9 @@ __global__ __launch_bounds__(256) void k_merge_prep(CellTable t, int64_t m, cons
         }
     }
     __syncthreads();
+    uint32_t* hc = hist + (blockIdx.x % kHistCopies) * kHistStride;
     for (int i = tid; i < npasses * 256; i += 256)
-        if (hl[i]) atomicAdd(&hist[i], hl[i]);
+        if (hl[i]) atomicAdd(&hc[i], hl[i]);
 }
 
 // End of a wide round: initial cell -> current cell maps (threads < m0) and
@@ -807,6 +890,233 @@ __global__ void k_round_end(uint32_t* __restrict__ cur, int64_t m0, const uint32
     s.apply = 0;
     s.changed = 0;
     st[b] = s;
+}
+
+// ===========================================================================
+// merge of a small table in one workgroup
+// ===========================================================================
+// For a round whose table holds at most kMergeMax cells (32-bit keys), one
+// 1024-thread workgroup does what the device-wide path does with
+// k_merge_prep, the radix sort, the heads scan, k_cell_setup and the
+// chunk-offset scan: sort keys (landing key of cells of applying instances,
+// own key otherwise), a stable LSD radix sort of (key, cell) in LDS, run heads
+// -> new cells, their member ranges and chunk offsets, the merge map and its
+// composition with the initial cells' map.  The canonical sums of the new
+// cells are then computed by k_segsum_chunks / k_segsum_levels over the
+// sorted member order it writes to `mperm`, and k_round_end (instances only)
+// closes the round.
+constexpr int kMergeThreads = 1024;
+constexpr int kMergeMax = 8192;
+constexpr int kMergeIPT = kMergeMax / kMergeThreads;  // 8
+
+// Exclusive block-wide scan of one value per thread (kMergeThreads threads);
+// returns this thread's exclusive prefix and, through *total, the sum.
+__device__ __forceinline__ uint32_t merge_block_scan(uint32_t v, uint32_t* wtot, uint32_t* total) {
+    constexpr int NW = kMergeThreads / kWave;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    uint32_t incl = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += y;
+    }
+    if (lane == kWave - 1) wtot[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) {
+        const uint32_t c = wtot[ww];
+        before += ww < w ? c : 0u;
+        all += c;
+    }
+    *total = all;
+    __syncthreads();  // wtot may be reused after this
+    return before + incl - v;
+}
+
+template <int D>
+__global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int64_t m, CellTable u,
+                                                               InstState* __restrict__ st,
+                                                               const double* __restrict__ pbuf,
+                                                               const uint64_t* __restrict__ kappa, int npasses,
+                                                               uint32_t* __restrict__ gmap,
+                                                               uint32_t* __restrict__ mperm,
+                                                               uint32_t* __restrict__ cur, int64_t m0,
+                                                               uint32_t* __restrict__ gtape,
+                                                               int64_t* __restrict__ counters) {
+    constexpr int NW = kMergeThreads / kWave;
+    __shared__ uint32_t kbuf[2][kMergeMax];
+    __shared__ uint16_t vbuf[2][kMergeMax];
+    __shared__ uint32_t wcnt[NW][256];
+    __shared__ uint16_t hs[kMergeMax + 1];  // first sorted position of every new cell
+    __shared__ uint16_t gm[kMergeMax];      // merge map (old cell -> new cell)
+    __shared__ uint32_t wtot[NW];
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    const int mm = int(m);
+
+    // ---- sort keys and stationarity of applying instances
+#pragma unroll
+    for (int i = 0; i < kMergeIPT; ++i) {
+        const int j0 = tid + i * kMergeThreads;
+        const bool valid = j0 < mm;
+        const int j = valid ? j0 : mm - 1;  // idle lanes shadow the last cell and raise nothing
+        const int b = t.inst[j];
+        const uint64_t key = t.key[j];
+        uint64_t out = key;
+        bool chg = false;
+        if (st[b].apply) {
+            const uint64_t kap = kappa[j];
+            out = kap;
+            chg = valid && kap != key;
+            const double C = double(t.cnt[j]);
+#pragma unroll
+            for (int k = 0; k < D; ++k) chg = chg || dbits(C * pbuf[k * t.cap + j]) != dbits(t.sum[k * t.cap + j]);
+        }
+        wave_flag_or(&st[b].changed, chg);
+        if (valid) {
+            kbuf[0][j] = uint32_t(out);
+            vbuf[0][j] = uint16_t(j);
+        }
+    }
+
+    // ---- stable LSD radix sort of (key, cell) in LDS
+    int src = 0;
+    for (int p = 0; p < npasses; ++p) {
+        const int shift = 8 * p;
+        for (int i = tid; i < NW * 256; i += kMergeThreads) (&wcnt[0][0])[i] = 0;
+        __syncthreads();
+        // wave w ranks positions [w * 64 * IPT, (w + 1) * 64 * IPT); slot i
+        // covers 64 consecutive positions, so (slot, lane) order is input order
+        uint32_t kk[kMergeIPT];
+        uint16_t vv[kMergeIPT];
+        uint32_t rk[kMergeIPT];
+#pragma unroll
+        for (int i = 0; i < kMergeIPT; ++i) {
+            const int pos = w * (kWave * kMergeIPT) + i * kWave + lane;
+            const bool valid = pos < mm;
+            kk[i] = valid ? kbuf[src][pos] : 0u;
+            vv[i] = valid ? vbuf[src][pos] : uint16_t(0);
+            const uint32_t dgt = (kk[i] >> shift) & 255u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int bb = 0; bb < 8; ++bb) {
+                const bool bit = (dgt >> bb) & 1u;
+                const uint64_t bal = __ballot(bit);
+                peers &= bit ? bal : ~bal;
+            }
+            uint32_t prior = 0;
+            if (valid) prior = wcnt[w][dgt];
+            rk[i] = prior + uint32_t(__popcll(peers & lt));
+            if (valid && lane == 63 - __clzll(peers)) wcnt[w][dgt] = prior + uint32_t(__popcll(peers));
+        }
+        __syncthreads();
+        // digit d (thread d): exclusive over the waves, then over the digits
+        uint32_t run = 0;
+        if (tid < 256) {
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) {
+                const uint32_t c = wcnt[ww][tid];
+                wcnt[ww][tid] = run;
+                run += c;
+            }
+        }
+        uint32_t total = 0;
+        const uint32_t base = merge_block_scan(tid < 256 ? run : 0u, wtot, &total);
+        if (tid < 256) {
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) wcnt[ww][tid] += base;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kMergeIPT; ++i) {
+            const int pos = w * (kWave * kMergeIPT) + i * kWave + lane;
+            if (pos < mm) {
+                const uint32_t dgt = (kk[i] >> shift) & 255u;
+                const uint32_t dst = wcnt[w][dgt] + rk[i];
+                kbuf[src ^ 1][dst] = kk[i];
+                vbuf[src ^ 1][dst] = vv[i];
+            }
+        }
+        __syncthreads();
+        src ^= 1;
+    }
+    const uint32_t* sk = kbuf[src];
+    const uint16_t* sv = vbuf[src];
+
+    // ---- run heads -> new cells (thread t owns positions [t * IPT, (t + 1) * IPT))
+    int nh = 0;
+    bool hf[kMergeIPT];
+#pragma unroll
+    for (int i = 0; i < kMergeIPT; ++i) {
+        const int p = tid * kMergeIPT + i;
+        hf[i] = p < mm && (p == 0 || sk[p] != sk[p - 1]);
+        nh += hf[i] ? 1 : 0;
+    }
+    uint32_t mnew_u = 0;
+    int cid = int(merge_block_scan(uint32_t(nh), wtot, &mnew_u)) - 1;
+    const int mnew = int(mnew_u);
+#pragma unroll
+    for (int i = 0; i < kMergeIPT; ++i) {
+        const int p = tid * kMergeIPT + i;
+        if (p < mm) {
+            if (hf[i]) {
+                ++cid;
+                hs[cid] = uint16_t(p);
+                u.key[cid] = uint64_t(sk[p]);
+            }
+            const int j = sv[p];
+            mperm[p] = uint32_t(j);
+            gm[j] = uint16_t(cid);
+            gmap[j] = uint32_t(cid);
+            if (gtape) gtape[j] = uint32_t(cid);
+        }
+    }
+    if (tid == 0) hs[mnew] = uint16_t(mm);
+    __syncthreads();
+
+    // ---- new cells: members, chunks, instance ranges, merged groups
+    // (thread t owns new cells [t * IPT, (t + 1) * IPT))
+    uint32_t nchunks = 0;
+#pragma unroll
+    for (int i = 0; i < kMergeIPT; ++i) {
+        const int c = tid * kMergeIPT + i;
+        if (c < mnew) nchunks += (uint32_t(hs[c + 1] - hs[c]) + kChunk - 1) / kChunk;
+    }
+    uint32_t tasks = 0;
+    uint32_t choff = merge_block_scan(nchunks, wtot, &tasks);
+#pragma unroll
+    for (int i = 0; i < kMergeIPT; ++i) {
+        const int c = tid * kMergeIPT + i;
+        if (c >= mnew) continue;
+        const int p0 = hs[c];
+        const uint32_t len = uint32_t(hs[c + 1]) - uint32_t(p0);
+        const uint32_t nch = (len + kChunk - 1) / kChunk;
+        const int j0 = sv[p0];
+        const int b = t.inst[j0];
+        u.start[c] = uint32_t(p0);
+        u.len[c] = len;
+        u.first[c] = uint32_t(j0);
+        u.nch[c] = nch;
+        u.choff[c] = choff;
+        u.inst[c] = b;
+        choff += nch;
+        const int bp = c > 0 ? t.inst[sv[hs[c - 1]]] : -1;
+        if (bp != b) {
+            st[b].cs = c;
+            if (bp >= 0) st[bp].ce = c;
+        }
+        if (c == mnew - 1) st[b].ce = mnew;
+        if (len > 1 && st[b].apply) atomicOr(&st[b].changed, 1);
+    }
+
+    // ---- initial cell -> current cell (the per-instance round end follows
+    // the sums, which still read which instances apply the round)
+    for (int64_t c = tid; c < m0; c += kMergeThreads) cur[c] = gm[cur[c]];
+    if (tid == 0) {
+        counters[0] = mnew;   // new cells
+        counters[1] = tasks;  // chunk tasks of their sums
+    }
 }
 
 // ===========================================================================
@@ -849,15 +1159,19 @@ __device__ inline int tail_col(const TailCols& c, const int32_t* crd0, const int
     return c.mode == 2 ? crd0[i] * c.E1 + crd1[i] : crd0[i];
 }
 
-// Every thread of the workgroup calls this; a barrier must follow.
+// Every thread of the workgroup calls this; a barrier must follow.  Entry v
+// is a binary search over the m cells' columns (ascending with the cells).
 __device__ inline void tail_cols_build(const TailCols& c, const int32_t* crd0, const int32_t* crd1, int m, int tid,
                                        uint16_t* col) {
-    if (c.mode == 0 || tid >= m) return;
-    const int hi = tail_col(c, crd0, crd1, tid);
-    const int lo = tid == 0 ? 0 : tail_col(c, crd0, crd1, tid - 1) + 1;
-    for (int v = lo; v <= hi; ++v) col[v] = uint16_t(tid);
-    if (tid == m - 1)
-        for (int v = hi + 1; v <= c.ncol; ++v) col[v] = uint16_t(m);
+    if (c.mode == 0) return;
+    for (int v = tid; v <= c.ncol; v += kTailThreads) {
+        int lo = 0, hi = m;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (tail_col(c, crd0, crd1, mid) < v) lo = mid + 1; else hi = mid;
+        }
+        col[v] = uint16_t(lo);
+    }
 }
 
 struct TailWindow {

@@ -24,20 +24,26 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const K* __restrict_
     for (int64_t i = int64_t(blockIdx.x) * kSortThreads + threadIdx.x; i < n; i += stride)
         sort_hist_add<K>(h, keys[i], npasses);
     __syncthreads();
+    uint32_t* hc = hist + (blockIdx.x % kHistCopies) * kHistStride;
     for (int i = threadIdx.x; i < npasses * 256; i += kSortThreads)
-        if (h[i]) atomicAdd(&hist[i], h[i]);
+        if (h[i]) atomicAdd(&hc[i], h[i]);
 }
 
-// Exclusive scan of each pass's histogram; also resets the tile counters.
-// Exclusive digit bases of every pass; the histograms are left zeroed for the
-// next sort that accumulates into them.
+// Exclusive digit bases of every pass from the histogram copies, which are
+// left zeroed for the next sort that accumulates into them; also resets the
+// tile counters.
 __global__ __launch_bounds__(256) void k_sort_bases(uint32_t* __restrict__ hist, uint32_t* __restrict__ dbase,
                                                     uint32_t* __restrict__ ctr, int npasses) {
     __shared__ uint32_t s[256];
     const int t = threadIdx.x;
     if (t < kSortMaxPasses) ctr[t] = 0;
     for (int p = 0; p < npasses; ++p) {
-        s[t] = hist[p * 256 + t];
+        uint32_t tot = 0;
+        for (int c = 0; c < kHistCopies; ++c) {
+            tot += hist[c * kHistStride + p * 256 + t];
+            hist[c * kHistStride + p * 256 + t] = 0;
+        }
+        s[t] = tot;
         __syncthreads();
         for (int off = 1; off < 256; off <<= 1) {
             const uint32_t v = t >= off ? s[t - off] : 0u;
@@ -45,8 +51,7 @@ __global__ __launch_bounds__(256) void k_sort_bases(uint32_t* __restrict__ hist,
             s[t] += v;
             __syncthreads();
         }
-        dbase[p * 256 + t] = s[t] - hist[p * 256 + t];
-        hist[p * 256 + t] = 0;
+        dbase[p * 256 + t] = s[t] - tot;
         __syncthreads();
     }
 }
@@ -66,6 +71,8 @@ __global__ void k_clear_u64(uint64_t* __restrict__ p, int64_t n) {
     if (i < n) p[i] = 0;
 }
 
+constexpr int kSortLookWindow = 32;
+
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                             K* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -73,8 +80,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict_
                                                             uint64_t* __restrict__ look, uint32_t* __restrict__ ctr,
                                                             uint32_t epoch) {
     constexpr int W = kSortThreads / kWave;
+    static_assert(kSortThreads == 256, "one thread per digit");
     __shared__ uint32_t wcnt[W][256];    // per-wave digit counts, then their exclusive scan over waves
     __shared__ uint32_t doff[256];       // tile-local exclusive digit offsets
+    __shared__ uint32_t wsum[W];         // per-wave totals of the digit scan
     __shared__ uint32_t gbase[256];      // global position of the tile's first key of each digit
     __shared__ K skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
@@ -131,43 +140,36 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict_
     __syncthreads();
 
     // Scan the per-wave counts over waves (digit = thread) and publish the
-    // tile total for the look-back.
-    {
-        const int dgt = tid;
-        uint32_t run = 0;
+    // tile total for the look-back at once, so that later tiles can use it.
+    uint32_t run = 0;  // this tile's count of digit tid
+    uint64_t* st = look + tile * 256 + tid;
 #pragma unroll
-        for (int ww = 0; ww < W; ++ww) {
-            const uint32_t c = wcnt[ww][dgt];
-            wcnt[ww][dgt] = run;
-            run += c;
-        }
-        uint64_t* st = look + tile * 256 + dgt;
-        if (tile == 0) {
-            lb_store(st, lb_pack(epoch, kFlagPrefix, run));
-            gbase[dgt] = dbase[dgt];
-        } else {
-            lb_store(st, lb_pack(epoch, kFlagAgg, run));
-            const uint64_t excl = lb_exclusive<8>(look + dgt, tile, 256, epoch);
-            lb_store(st, lb_pack(epoch, kFlagPrefix, excl + run));
-            gbase[dgt] = dbase[dgt] + uint32_t(excl);
-        }
-        doff[dgt] = run;  // inclusive scan over digits follows
+    for (int ww = 0; ww < W; ++ww) {
+        const uint32_t c = wcnt[ww][tid];
+        wcnt[ww][tid] = run;
+        run += c;
     }
-    __syncthreads();
-    // tile-local exclusive scan over the 256 digit totals
+    lb_store(st, lb_pack(epoch, tile == 0 ? kFlagPrefix : kFlagAgg, run));
+    // tile-local exclusive scan over the 256 digit totals (digit = thread):
+    // within each wave by shuffles, then across the waves' totals
     {
-        const uint32_t mine = doff[tid];
-        for (int off = 1; off < 256; off <<= 1) {
-            const uint32_t v = tid >= off ? doff[tid - off] : 0u;
-            __syncthreads();
-            doff[tid] += v;
-            __syncthreads();
+        uint32_t incl = run;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += y;
         }
-        doff[tid] -= mine;
+        if (lane == kWave - 1) wsum[w] = incl;
+        __syncthreads();
+        uint32_t before = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) before += ww < w ? wsum[ww] : 0u;
+        doff[tid] = before + incl - run;
     }
     __syncthreads();
 
-    // Reorder the tile by digit in LDS.
+    // Reorder the tile by digit in LDS (local offsets only), which leaves the
+    // items' registers free for a wide look-back.
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const int64_t pos = t0 + int64_t(w) * (kWave * kSortItems) + i * kWave + lane;
@@ -177,6 +179,15 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict_
             skey[lp] = key[i];
             sval[lp] = val[i];
         }
+    }
+    // Exclusive prefix of digit tid over all earlier tiles (decoupled
+    // look-back, 32 predecessors per round trip), then this tile's prefix.
+    if (tile == 0) {
+        gbase[tid] = dbase[tid];
+    } else {
+        const uint64_t excl = lb_exclusive<kSortLookWindow>(look + tid, tile, 256, epoch);
+        lb_store(st, lb_pack(epoch, kFlagPrefix, excl + run));
+        gbase[tid] = dbase[tid] + uint32_t(excl);
     }
     __syncthreads();
 
@@ -205,7 +216,7 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
     const int64_t tiles = sort_look_tiles(n);
     if (tiles > sc.look_tiles) return hipErrorInvalidValue;
     if (!hist_ready) {
-        k_clear_u32<<<dim3(kSortMaxPasses), dim3(256), 0, s>>>(sc.hist, kSortMaxPasses * 256);
+        k_clear_u32<<<dim3(kSortMaxPasses * kHistCopies), dim3(256), 0, s>>>(sc.hist, kHistCopies * kHistStride);
         int64_t blocks = (n + kSortThreads * 16 - 1) / (kSortThreads * 16);
         if (blocks > 2048) blocks = 2048;
         const int tk = sc.prof_begin ? sc.prof_begin(sc.prof_ctx, s, "sort_hist") : -1;

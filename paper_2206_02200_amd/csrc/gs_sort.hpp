@@ -10,6 +10,8 @@ constexpr int kSortThreads = 256;                        // 4 waves
 constexpr int kSortItems = 16;                           // keys per thread
 constexpr int kSortTile = kSortThreads * kSortItems;     // 4096 keys per tile
 constexpr int kSortMaxPasses = 8;                        // 8-bit digits, up to 64 bits
+constexpr int kHistCopies = 16;                          // histogram copies that producers spread atomics over
+constexpr int kHistStride = kSortMaxPasses * 256;        // entries of one copy
 
 // Optional timing hooks: begin returns a token (or -1), end closes it with the
 // algorithmic bytes the launch had to move.
@@ -17,7 +19,7 @@ typedef int (*ProfBeginFn)(void* ctx, hipStream_t s, const char* name);
 typedef void (*ProfEndFn)(void* ctx, hipStream_t s, int token, double bytes);
 
 struct SortScratch {
-    uint32_t* hist = nullptr;   // [kSortMaxPasses][256] digit histograms
+    uint32_t* hist = nullptr;   // [kHistCopies][kSortMaxPasses][256] digit histograms (summed over copies)
     uint32_t* dbase = nullptr;  // [kSortMaxPasses][256] exclusive digit bases
     uint32_t* ctr = nullptr;    // [kSortMaxPasses] tile counters
     uint64_t* look = nullptr;   // [tiles][256] look-back status words

@@ -33,7 +33,10 @@ EXPORTED = [
     "gs_fit", "gs_fit_batched", "gs_copy_modes", "gs_copy_keys",
     "gs_profile_enable", "gs_profile_reset", "gs_profile_count", "gs_profile_entry",
     "gs_context_set_tape", "gs_backward", "gs_point_mode_loss", "gs_point_mode_loss_backward",
+    "gs_context_set_config", "gs_context_get_config", "gs_autotune",
 ]
+CFG_MERGE_SMALL, CFG_TILE_CHUNKS = 0, 1
+CONFIG_KEYS = {"merge_small": CFG_MERGE_SMALL, "tile_chunks": CFG_TILE_CHUNKS}
 
 
 class GridShiftError(RuntimeError):
@@ -102,6 +105,12 @@ def load_library(path: str = LIB_PATH):
         lib.gs_point_mode_loss.restype = ctypes.c_int
         lib.gs_point_mode_loss_backward.argtypes = [V, V, V, V, V, V]
         lib.gs_point_mode_loss_backward.restype = ctypes.c_int
+        lib.gs_context_set_config.argtypes = [V, I32, I32]
+        lib.gs_context_set_config.restype = ctypes.c_int
+        lib.gs_context_get_config.argtypes = [V, I32, ctypes.POINTER(I32)]
+        lib.gs_context_get_config.restype = ctypes.c_int
+        lib.gs_autotune.argtypes = [V, V, ctypes.c_int, I32, I64, I32, V, V, I32, I32, V]
+        lib.gs_autotune.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -129,6 +138,31 @@ class Context:
         table every k rounds instead and recomputes each k-round segment
         during the backward pass; False or 0 records nothing."""
         _check(_lib.gs_context_set_tape(self.handle, int(on)))
+
+    def set_config(self, **kv):
+        """Launch choices (merge_small=0/1, tile_chunks=1..64); results never depend on them."""
+        for k, v in kv.items():
+            _check(_lib.gs_context_set_config(self.handle, CONFIG_KEYS[k], int(v)))
+
+    def config(self) -> dict:
+        out = {}
+        for k, key in CONFIG_KEYS.items():
+            v = ctypes.c_int32()
+            _check(_lib.gs_context_get_config(self.handle, key, ctypes.byref(v)))
+            out[k] = v.value
+        return out
+
+    def autotune(self, x: torch.Tensor, h, max_iter: int = 100, offsets=None, reps: int = 3, stream=None) -> dict:
+        """Time every candidate configuration on this input and keep the fastest."""
+        x, dt, ld = _points(x)
+        n, d = x.shape
+        off = np.ascontiguousarray(np.asarray([0, n] if offsets is None else offsets, dtype=np.int64))
+        B = off.size - 1
+        hs = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (B,)))
+        _check(_lib.gs_autotune(self.handle, ctypes.c_void_p(x.data_ptr()), dt, d, ld, B,
+                                off.ctypes.data_as(ctypes.c_void_p), hs.ctypes.data_as(ctypes.c_void_p),
+                                int(max_iter), int(reps), _stream_ptr(stream)))
+        return self.config()
 
     def profile(self, prefix: str | None = ""):
         """Time later fits' kernels whose name starts with ``prefix`` (None: off)."""
