@@ -199,16 +199,22 @@ gs_status gs_point_mode_loss_backward(gs_context* ctx, const void* points, const
  *   GS_CFG_TILE_CHUNKS  1..64 (default 4): chunks of staged point rows (24 KiB
  *                       of coordinates each) per workgroup of the point-level
  *                       binning kernels.
+ *   GS_CFG_DENSE_TABLE  1 (default): the device-wide rounds find neighbour
+ *                       cells through a table over the whole packed key range
+ *                       (8 bytes per key, kept in the context) when that range
+ *                       is at most 2^27 keys; 0: through an open-addressing
+ *                       hash rebuilt every round.
  * Unknown keys and out-of-range values are GS_ERR_INVALID_ARG.
  */
-enum { GS_CFG_MERGE_SMALL = 0, GS_CFG_TILE_CHUNKS = 1 };
+enum { GS_CFG_MERGE_SMALL = 0, GS_CFG_TILE_CHUNKS = 1, GS_CFG_DENSE_TABLE = 2 };
 gs_status gs_context_set_config(gs_context* ctx, int32_t key, int32_t value);
 gs_status gs_context_get_config(const gs_context* ctx, int32_t key, int32_t* value);
 
 /*
  * Autotuner: fits the given input (the arguments of gs_fit_batched; B = 1 and
  * offsets {0, n} for one point set) once per candidate configuration
- * (GS_CFG_MERGE_SMALL in {1, 0} x GS_CFG_TILE_CHUNKS in {1, 2, 4, 8}), one
+ * (GS_CFG_MERGE_SMALL in {1, 0} x GS_CFG_DENSE_TABLE in {1, 0} x
+ * GS_CFG_TILE_CHUNKS in {1, 2, 4, 8}), one
  * warm-up run and `reps` timed runs each (host wall time of the whole call,
  * best of the reps), and keeps the fastest configuration in the context.  The
  * labels of the timed fits go to a buffer the context owns; the context's

@@ -56,6 +56,7 @@ struct Profiler {
 struct gs_config {
     int merge_small = 1;  // merge rounds of at most kMergeMax cells in one workgroup
     int tile_chunks = 4;  // staged chunks of point rows per point tile
+    int dense_table = 1;  // neighbour lookups through a dense key table when the key range allows
 };
 
 struct gs_context {
@@ -66,7 +67,7 @@ struct gs_context {
     DBuf tkey[2], tcnt[2], tsum[2], tinst[2], tstart[2], tlen[2], tfirst[2], tnch[2], tchoff[2];
     DBuf kappa, pbuf, gmap, cur, tmap, part, partc, hk, hv, ckA, ckB, cvA, cvB;
     // instances
-    DBuf param, state, rowoff, hs, bbox, koff, tiles, tileoff, bpart;
+    DBuf param, state, rowoff, hs, bbox, koff, tiles;
     int64_t ntiles = 0;
     // scans and sorts
     DBuf counters, look, tilectr, shist, sdbase, sctr, slook;
@@ -75,6 +76,9 @@ struct gs_context {
     uint64_t tile_base = 0;  // value of the scan tile counter before the next scan
     gs_config cfg;           // launch choices (results do not depend on them)
     DBuf tune_labels;        // labels of the autotuner's timed fits
+    DBuf dk;                 // dense key -> cell table of the device-wide rounds
+    uint32_t dk_epoch = 0;
+    int64_t key_span = 0;    // packed key range of the current fit
     // pinned staging: downloads (every one waits for its stream) and a bump
     // area for uploads, reused only once a wait on up_stream has drained them
     void* pinned = nullptr;
@@ -427,19 +431,19 @@ gs_status segsum(gs_context* c, int d, Src src, gs::CellTable t, int64_t m_bound
     return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
 }
 
+template <class Lookup>
 gs_status launch_shift(gs_context* c, int d, gs::CellTable t, int64_t m, const gs::InstParam* prm, gs::InstState* st,
-                       const uint64_t* hk, const uint32_t* hv, int logcap, double* pbuf, uint64_t* kappa,
-                       int32_t* Wout, hipStream_t s) {
+                       Lookup lk, double* pbuf, uint64_t* kappa, int32_t* Wout, hipStream_t s) {
     const unsigned g = blocks_for(m, gs::kShiftWaves);  // one wave per cell
     // reads every cell row once, writes p and the landing key
     const int tk = prof_begin(c, s, "shift");
     switch (d) {
-        case 1: gs::k_shift<1><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa, Wout); break;
-        case 2: gs::k_shift<2><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa, Wout); break;
-        case 3: gs::k_shift<3><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa, Wout); break;
-        case 4: gs::k_shift<4><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa, Wout); break;
-        case 5: gs::k_shift<5><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa, Wout); break;
-        case 6: gs::k_shift<6><<<g, 256, 0, s>>>(t, m, prm, st, hk, hv, logcap, pbuf, kappa, Wout); break;
+        case 1: gs::k_shift<1, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout); break;
+        case 2: gs::k_shift<2, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout); break;
+        case 3: gs::k_shift<3, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout); break;
+        case 4: gs::k_shift<4, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout); break;
+        case 5: gs::k_shift<5, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout); break;
+        case 6: gs::k_shift<6, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout); break;
         default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
     }
     prof_end(c, s, tk, double(m) * (8.0 + 8.0 + 4.0 + 8.0 * d) + double(m) * (8.0 * d + 8.0));
@@ -449,15 +453,15 @@ gs_status launch_shift(gs_context* c, int d, gs::CellTable t, int64_t m, const g
 
 gs_status launch_tail(gs_context* c, int d, int B, gs::CellTable t, const gs::InstParam* prm, gs::InstState* st, uint32_t* tmap,
                       int max_iter, const gs::TailTape& tape, const gs::TailCkpt& ck, int replay_r0, hipStream_t s,
-                      double nbytes) {
+                      double nbytes, const int64_t* gate = nullptr) {
     const int tk = prof_begin(c, s, replay_r0 >= 0 ? "tail_replay" : "tail");
     switch (d) {
-        case 1: gs::k_tail<1><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0); break;
-        case 2: gs::k_tail<2><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0); break;
-        case 3: gs::k_tail<3><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0); break;
-        case 4: gs::k_tail<4><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0); break;
-        case 5: gs::k_tail<5><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0); break;
-        case 6: gs::k_tail<6><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0); break;
+#define GS_TL(D)                                                                                                  \
+    case D:                                                                                                       \
+        gs::k_tail<D><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0, gate);      \
+        break;
+        GS_TL(1) GS_TL(2) GS_TL(3) GS_TL(4) GS_TL(5) GS_TL(6)
+#undef GS_TL
         default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
     }
     prof_end(c, s, tk, nbytes);
@@ -503,6 +507,7 @@ gs_status build_params(gs_context* c, int B, int d, const int64_t* offsets, cons
         if (total >= kLimit) return fail(GS_ERR_KEY_RANGE, "the instances' key boxes exceed 2^62 cells in total");
     }
     *bits_out = total <= 1 ? 0 : 64 - __builtin_clzll(total - 1);
+    c->key_span = int64_t(total);
     return GS_OK;
 }
 
@@ -636,15 +641,52 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     c->wt_used = 0;
 
     c->st.assign(B, gs::InstState{});
-    GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
+    if (B == 1) {  // one instance: it holds all m0 cells and is active unless empty
+        c->st[0].active = N > 0;
+        c->st[0].cs = 0;
+        c->st[0].ce = m0;
+    } else {
+        GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
+    }
     std::vector<int64_t> m0_of(B);
     for (int b = 0; b < B; ++b) m0_of[b] = c->st[b].ce - c->st[b].cs;
+
+    // ---- remaining rounds: one LDS-resident workgroup per instance, then labels
+    auto tail_and_labels = [&](int cur_tab, int nwide, int64_t Mnow, const int64_t* gate) -> gs_status {
+        gs::CellTable TC = table(c, cur_tab);
+        gs::TailTape tape;
+        gs::TailCkpt ck;
+        c->ckpt_used = c->ckpt_every;
+        if (c->tape_on && max_iter > 0 && c->ckpt_every > 1) {
+            // checkpoints only: the table every ckpt_every rounds
+            const int ns = max_iter / c->ckpt_every + 1;
+            const size_t per = size_t(ns) * gs::kTailCells;
+            GS_TRY(ensure(c->ck_key, per * B * 8));
+            GS_TRY(ensure(c->ck_cnt, per * B * 4));
+            GS_TRY(ensure(c->ck_sum, per * B * d * 8));
+            GS_TRY(ensure(c->ck_m, size_t(ns) * B * 4));
+            ck = ckpt_view(c, ns, B, c->ckpt_every);
+        } else if (c->tape_on && max_iter > 0) {
+            GS_TRY(tail_tape(c, max_iter, B, &tape));
+        }
+        GS_TRY(launch_tail(c, d, B, TC, prm, st, P<uint32_t>(c->tmap), max_iter, tape, ck, -1, s,
+                           2.0 * Mnow * (16.0 + 8.0 * d), gate));
+        if (N > 0) {
+            PROF_LAUNCH("labels", N * 8.0,
+                        gs::k_labels<<<unsigned(std::min<int64_t>(gs::kLabelBlocks, blocks_for(N, 256))), 256, 0, s>>>(
+                            P<uint32_t>(c->cell0), nwide ? P<uint32_t>(c->cur) : nullptr, P<uint32_t>(c->tmap), labels, N,
+                            gate));
+            GS_HIP(hipGetLastError());
+        }
+        return GS_OK;
+    };
 
     // ---- wide rounds while some active instance has more cells than a tail holds
     GS_TRY(ensure(c->tmap, size_t(c->capM) * 4));
     int cur = 0;
     int64_t M = m0;
     int wide = 0;
+    bool tail_done = false;
     for (;;) {
         bool need = false;
         for (int b = 0; b < B; ++b)
@@ -663,16 +705,34 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         }
         ++wide;
         gs::CellTable TT = table(c, cur), U = table(c, 1 - cur);
+        // neighbour lookup structure of the round's table
+        const bool dense = c->cfg.dense_table && c->key_span <= gs::kDenseMax;
         int logcap = 1;
-        while ((int64_t(1) << logcap) < 2 * M) ++logcap;
-        const int64_t hcap = int64_t(1) << logcap;
-        GS_TRY(ensure(c->hk, size_t(hcap) * 8));
-        GS_TRY(ensure(c->hv, size_t(hcap) * 4));
-        PROF_LAUNCH("hash_clear", hcap * 8.0,
-                    gs::k_hash_clear<<<blocks_for(hcap, 256), 256, 0, s>>>(P<uint64_t>(c->hk), hcap));
-        PROF_LAUNCH("hash_insert", M * 20.0,
-                    gs::k_hash_insert<<<blocks_for(M, 256), 256, 0, s>>>(TT.key, M, P<uint64_t>(c->hk),
-                                                                          P<uint32_t>(c->hv), logcap));
+        if (dense) {
+            if (c->dk.cap < size_t(c->key_span) * 8) {
+                GS_TRY(ensure(c->dk, size_t(c->key_span) * 8));
+                k_fill_u64<<<blocks_for(c->dk.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->dk), c->dk.cap / 8, 0);
+                c->dk_epoch = 0;
+            }
+            if (c->dk_epoch == 0xffffffffu) {
+                k_fill_u64<<<blocks_for(c->dk.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->dk), c->dk.cap / 8, 0);
+                c->dk_epoch = 0;
+            }
+            ++c->dk_epoch;
+            PROF_LAUNCH("dense_insert", M * 16.0,
+                        gs::k_dense_insert<<<blocks_for(M, 256), 256, 0, s>>>(TT.key, M, P<uint64_t>(c->dk),
+                                                                               c->dk_epoch));
+        } else {
+            while ((int64_t(1) << logcap) < 2 * M) ++logcap;
+            const int64_t hcap = int64_t(1) << logcap;
+            GS_TRY(ensure(c->hk, size_t(hcap) * 8));
+            GS_TRY(ensure(c->hv, size_t(hcap) * 4));
+            PROF_LAUNCH("hash_clear", hcap * 8.0,
+                        gs::k_hash_clear<<<blocks_for(hcap, 256), 256, 0, s>>>(P<uint64_t>(c->hk), hcap));
+            PROF_LAUNCH("hash_insert", M * 20.0,
+                        gs::k_hash_insert<<<blocks_for(M, 256), 256, 0, s>>>(TT.key, M, P<uint64_t>(c->hk),
+                                                                              P<uint32_t>(c->hv), logcap));
+        }
         GS_HIP(hipGetLastError());
         int32_t* Wrec = nullptr;
         int32_t* apprec = nullptr;
@@ -695,17 +755,22 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
             c->w_M.push_back(M);
             c->wt_used = woff + M;
         }
-        GS_TRY(launch_shift(c, d, TT, M, prm, st, P<uint64_t>(c->hk), P<uint32_t>(c->hv), logcap, P<double>(c->pbuf),
-                            P<uint64_t>(c->kappa), Wrec, s));
+        if (dense)
+            GS_TRY(launch_shift(c, d, TT, M, prm, st, gs::DenseLookup{P<uint64_t>(c->dk), c->dk_epoch},
+                                P<double>(c->pbuf), P<uint64_t>(c->kappa), Wrec, s));
+        else
+            GS_TRY(launch_shift(c, d, TT, M, prm, st,
+                                gs::HashLookup{P<uint64_t>(c->hk), P<uint32_t>(c->hv), logcap}, P<double>(c->pbuf),
+                                P<uint64_t>(c->kappa), Wrec, s));
         gs::k_decide<<<blocks_for(B, 256), 256, 0, s>>>(st, B, max_iter);
-        if (sizeof(K) == 4 && M <= gs::kMergeMax && c->cfg.merge_small) {
+        if (sizeof(K) == 4 && M <= gs::kMergeMax && B <= gs::kMergeMaxInst && c->cfg.merge_small) {
             // the whole merge and the round's bookkeeping in one workgroup
             uint32_t* gt = c->tape_on ? P<uint32_t>(c->wt_g) + woff : nullptr;
             const int tk = prof_begin(c, s, "merge_small");
             switch (d) {
 #define GS_MS(D)                                                                                                   \
     case D:                                                                                                        \
-        gs::k_merge_small<D><<<1, gs::kMergeThreads, 0, s>>>(TT, M, U, st, P<double>(c->pbuf),                     \
+        gs::k_merge_small<D><<<1, gs::kMergeThreads, 0, s>>>(TT, M, U, st, B, P<double>(c->pbuf),                  \
                                                              P<uint64_t>(c->kappa), np, P<uint32_t>(c->gmap),      \
                                                              P<uint32_t>(c->cvA), P<uint32_t>(c->cur), m0, gt,     \
                                                              ctr);                                                 \
@@ -722,12 +787,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
                         gs::k_round_end<<<blocks_for(B, 256), 256, 0, s>>>(P<uint32_t>(c->cur), 0,
                                                                             P<uint32_t>(c->gmap), st, B, apprec));
             GS_HIP(hipGetLastError());
-            cur = 1 - cur;
-            GS_TRY(d2h_batch(c, {{&M, ctr + 0, sizeof(int64_t)}, {c->st.data(), st, sizeof(gs::InstState) * B}}, s));
-            for (int b = 0; b < B; ++b)
-                if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");
-            continue;
-        }
+        } else {
         PROF_LAUNCH("merge_prep", M * (8.0 * 3 + 16.0 * d + sizeof(K)),
                     gs::k_merge_prep<K><<<blocks_for(M, 256), 256, 0, s>>>(TT, M, st, st, P<double>(c->pbuf),
                                                                             P<uint64_t>(c->kappa), P<K>(c->ckA), d,
@@ -751,38 +811,31 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
                     gs::k_round_end<<<blocks_for(std::max<int64_t>(m0, B), 256), 256, 0, s>>>(
                         P<uint32_t>(c->cur), m0, P<uint32_t>(c->gmap), st, B, apprec));
         GS_HIP(hipGetLastError());
+        }
         cur = 1 - cur;
-        GS_TRY(d2h_batch(c, {{&M, ctr + 0, sizeof(int64_t)}, {c->st.data(), st, sizeof(gs::InstState) * B}}, s));
+        // the tail and the labels right away, unless some instance still needs
+        // a device-wide round (then the tail changes nothing and the loop goes on)
+        gs::k_tail_gate<<<1, 256, 0, s>>>(st, B, ctr + 4);
+        GS_HIP(hipGetLastError());
+        GS_TRY(tail_and_labels(cur, wide, M, ctr + 4));
+        int64_t gate = 0;
+        GS_TRY(d2h_batch(c,
+                         {{&M, ctr + 0, sizeof(int64_t)},
+                          {c->st.data(), st, sizeof(gs::InstState) * B},
+                          {&gate, ctr + 4, sizeof(int64_t)}},
+                         s));
         for (int b = 0; b < B; ++b)
             if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");
+        if (!gate) {
+            tail_done = true;
+            break;
+        }
     }
 
-    // ---- remaining rounds: one LDS-resident workgroup per instance
-    gs::CellTable TC = table(c, cur);
-    gs::TailTape tape;
-    gs::TailCkpt ck;
-    c->ckpt_used = c->ckpt_every;
-    if (c->tape_on && max_iter > 0 && c->ckpt_every > 1) {
-        // checkpoints only: the table every ckpt_every rounds
-        const int ns = max_iter / c->ckpt_every + 1;
-        const size_t per = size_t(ns) * gs::kTailCells;
-        GS_TRY(ensure(c->ck_key, per * B * 8));
-        GS_TRY(ensure(c->ck_cnt, per * B * 4));
-        GS_TRY(ensure(c->ck_sum, per * B * d * 8));
-        GS_TRY(ensure(c->ck_m, size_t(ns) * B * 4));
-        ck = ckpt_view(c, ns, B, c->ckpt_every);
-    } else if (c->tape_on && max_iter > 0) {
-        GS_TRY(tail_tape(c, max_iter, B, &tape));
+    if (!tail_done) {
+        GS_TRY(tail_and_labels(cur, wide, M, nullptr));
+        GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
     }
-    GS_TRY(launch_tail(c, d, B, TC, prm, st, P<uint32_t>(c->tmap), max_iter, tape, ck, -1, s,
-                       2.0 * M * (16.0 + 8.0 * d)));
-    if (N > 0) {
-        PROF_LAUNCH("labels", N * 8.0,
-                    gs::k_labels<<<blocks_for(N, 256), 256, 0, s>>>(
-                        P<uint32_t>(c->cell0), wide ? P<uint32_t>(c->cur) : nullptr, P<uint32_t>(c->tmap), labels, N));
-        GS_HIP(hipGetLastError());
-    }
-    GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
     for (int b = 0; b < B; ++b) {
         if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");
         c->st[b].m0 = m0_of[b];
@@ -964,21 +1017,16 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
     // row tiles of tile_chunks staged chunks of rows, each inside one instance
     const int trows = c->cfg.tile_chunks * gs::chunk_rows(d, dtype == GS_F32 ? 4 : 8);
     std::vector<gs::RowTile> tiles;
-    std::vector<int64_t> tile_off(B + 1, 0);
     for (int b = 0; b < B; ++b) {
         for (int64_t r = offsets[b]; r < offsets[b + 1]; r += trows)
             tiles.push_back({r, std::min<int64_t>(r + trows, offsets[b + 1]), b, 0});
-        tile_off[b + 1] = int64_t(tiles.size());
     }
     c->ntiles = int64_t(tiles.size());
     GS_TRY(ensure(c->tiles, sizeof(gs::RowTile) * std::max<size_t>(tiles.size(), 1)));
-    GS_TRY(ensure(c->tileoff, sizeof(int64_t) * (B + 1)));
-    GS_TRY(ensure(c->bpart, sizeof(int64_t) * 2 * gs::kMaxDim * std::max<size_t>(tiles.size(), 1)));
     GS_TRY(h2d_batch(c,
                      {{c->rowoff.p, offsets, sizeof(int64_t) * (B + 1)},
                       {c->hs.p, h, sizeof(double) * B},
-                      {c->tiles.p, tiles.data(), sizeof(gs::RowTile) * tiles.size()},
-                      {c->tileoff.p, tile_off.data(), sizeof(int64_t) * (B + 1)}},
+                      {c->tiles.p, tiles.data(), sizeof(gs::RowTile) * tiles.size()}},
                      s));
     GS_TRY(ensure(c->shist, gs::kHistCopies * gs::kHistStride * 4));
     gs::k_init_state<<<blocks_for(std::max(B, gs::kHistCopies * gs::kHistStride), 256), 256, 0, s>>>(
@@ -991,7 +1039,7 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
         const double xb = double(N) * d * (dtype == GS_F32 ? 4.0 : 8.0);
         const gs::RowTile* tl = P<gs::RowTile>(c->tiles);
         const double* hsd = P<double>(c->hs);
-        int64_t* bp = P<int64_t>(c->bpart);
+        int64_t* bp = P<int64_t>(c->bbox);
         int64_t* cn = P<int64_t>(c->counters);
         const float* xf = static_cast<const float*>(points);
         const double* xd = static_cast<const double*>(points);
@@ -1005,9 +1053,6 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
             default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
         }
         prof_end(c, s, tk, xb);
-        PROF_LAUNCH("bbox_reduce", tiles.size() * 96.0,
-                    gs::k_bbox_reduce<<<B, 256, 0, s>>>(P<int64_t>(c->bpart), P<int64_t>(c->tileoff),
-                                                        P<int64_t>(c->bbox)));
         GS_HIP(hipGetLastError());
         int64_t errbits = 0;
         GS_TRY(d2h_batch(c, {{box.data(), c->bbox.p, box.size() * sizeof(int64_t)},
@@ -1166,7 +1211,7 @@ void gs_context_destroy(gs_context* c) {
     (void)hipSetDevice(c->device);
     DBuf* all[] = {&c->kA, &c->kB, &c->vA, &c->vB, &c->cell0, &c->kappa, &c->pbuf, &c->gmap, &c->cur, &c->tmap,
                    &c->part, &c->partc, &c->hk, &c->hv, &c->ckA, &c->ckB, &c->cvA, &c->cvB, &c->param, &c->state,
-                   &c->rowoff, &c->hs, &c->bbox, &c->koff, &c->tiles, &c->tileoff, &c->bpart, &c->counters, &c->look, &c->tilectr, &c->shist,
+                   &c->rowoff, &c->hs, &c->bbox, &c->koff, &c->tiles, &c->counters, &c->look, &c->tilectr, &c->shist,
                    &c->sdbase, &c->sctr, &c->slook};
     for (DBuf* b : all)
         if (b->p) (void)hipFree(b->p);
@@ -1183,7 +1228,7 @@ void gs_context_destroy(gs_context* c) {
     DBuf* tb2[] = {&c->sums0, &c->inst0, &c->wt_key, &c->wt_cnt, &c->wt_inst, &c->wt_W, &c->wt_g, &c->wt_app,
                    &c->tt_key, &c->tt_cnt, &c->tt_W, &c->tt_g, &c->tt_m, &c->sbA, &c->sbB, &c->qbuf, &c->gmodes,
                    &c->modes_i, &c->counts_i, &c->frows, &c->lossc, &c->ltab, &c->xkA, &c->xkB, &c->xvA, &c->xvB,
-                   &c->ck_key, &c->ck_cnt, &c->ck_sum, &c->ck_m, &c->tune_labels};
+                   &c->ck_key, &c->ck_cnt, &c->ck_sum, &c->ck_m, &c->tune_labels, &c->dk};
     for (DBuf* b : tb2)
         if (b->p) (void)hipFree(b->p);
     delete c;
@@ -1215,6 +1260,10 @@ gs_status gs_context_set_config(gs_context* ctx, int32_t key, int32_t value) {
             if (value < 1 || value > 64) return fail(GS_ERR_INVALID_ARG, "GS_CFG_TILE_CHUNKS takes 1..64");
             ctx->cfg.tile_chunks = value;
             return GS_OK;
+        case GS_CFG_DENSE_TABLE:
+            if (value != 0 && value != 1) return fail(GS_ERR_INVALID_ARG, "GS_CFG_DENSE_TABLE takes 0 or 1");
+            ctx->cfg.dense_table = value;
+            return GS_OK;
     }
     return fail(GS_ERR_INVALID_ARG, "unknown configuration key");
 }
@@ -1224,6 +1273,7 @@ gs_status gs_context_get_config(const gs_context* ctx, int32_t key, int32_t* val
     switch (key) {
         case GS_CFG_MERGE_SMALL: *value = ctx->cfg.merge_small; return GS_OK;
         case GS_CFG_TILE_CHUNKS: *value = ctx->cfg.tile_chunks; return GS_OK;
+        case GS_CFG_DENSE_TABLE: *value = ctx->cfg.dense_table; return GS_OK;
     }
     return fail(GS_ERR_INVALID_ARG, "unknown configuration key");
 }
@@ -1245,10 +1295,12 @@ gs_status gs_autotune(gs_context* ctx, const void* points, gs_dtype dtype, int32
     double best_ms = 0.0;
     bool first = true;
     gs_status rc = GS_OK;
-    for (int ms = 1; ms >= 0 && rc == GS_OK; --ms) {
-        for (int tc : {1, 2, 4, 8}) {
-            ctx->cfg.merge_small = ms;
-            ctx->cfg.tile_chunks = tc;
+    for (int cand = 0; cand < 16 && rc == GS_OK; ++cand) {
+        {
+            const int tcs[4] = {1, 2, 4, 8};
+            ctx->cfg.merge_small = 1 - (cand >> 3);
+            ctx->cfg.dense_table = 1 - ((cand >> 2) & 1);
+            ctx->cfg.tile_chunks = tcs[cand & 3];
             double t_min = 0.0;
             for (int r = 0; r <= reps; ++r) {  // the first run is a warm-up
                 const auto t0 = std::chrono::steady_clock::now();

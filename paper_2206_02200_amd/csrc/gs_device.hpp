@@ -89,6 +89,8 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
 // The caller has already published its own aggregate.  Tile 0 returns 0.
 // kWin predecessors are read per round trip; their words are consumed
 // nearest first until an inclusive prefix is found.
+constexpr int kLookSleep = 2;  // back-off (s_sleep units of 64 clocks) before polling an unpublished tile again
+
 template <int kWin>
 __device__ __forceinline__ uint64_t lb_exclusive(const uint64_t* status, int64_t tile, int64_t stride,
                                                  uint32_t epoch) {
@@ -115,6 +117,7 @@ __device__ __forceinline__ uint64_t lb_exclusive(const uint64_t* status, int64_t
         }
         if (done) break;
         p -= used;  // unpublished predecessor: read again from there
+        if (kLookSleep > 0 && used < kWin) __builtin_amdgcn_s_sleep(kLookSleep);
     }
     return excl;
 }

@@ -126,13 +126,13 @@ struct Stager {
 // ===========================================================================
 // bbox: per instance and dimension, min/max of floor(fl(x/h))
 // ===========================================================================
-// Each block reduces one tile to a partial box, then one block per instance
-// reduces its tiles' partials.
+// Each block reduces one tile and merges the result into its instance's box
+// [B][kMaxDim][2] (initialised to INT64_MAX / INT64_MIN) with atomic min/max.
 template <typename T, int D>
 __global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict__ x, int64_t ld,
                                                             const RowTile* __restrict__ tiles,
                                                             const double* __restrict__ hs,
-                                                            int64_t* __restrict__ part,  // [tiles][kMaxDim][2]
+                                                            int64_t* __restrict__ bbox,
                                                             int64_t* __restrict__ counters) {
     using S = Stager<T, D>;
     constexpr int R = S::R;
@@ -204,49 +204,16 @@ __global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict_
         if (lane == 0) atomicOr((unsigned long long*)&counters[2], (unsigned long long)e);
     }
     __syncthreads();
-    if (tid < 2 * kMaxDim) {
+    if (tid < 2 * D) {
         const bool isMin = (tid & 1) == 0;
         int64_t a = isMin ? INT64_MAX : INT64_MIN;
-        if (tid < 2 * D)
-            for (int ww = 0; ww < kBoxThreads / kWave; ++ww) {
-                const int64_t c = red[ww][tid];
-                a = isMin ? (c < a ? c : a) : (c > a ? c : a);
-            }
-        part[int64_t(blockIdx.x) * 2 * kMaxDim + tid] = a;
-    }
-}
-
-// One block per instance: reduce the partial boxes of its tiles.
-__global__ __launch_bounds__(256) void k_bbox_reduce(const int64_t* __restrict__ part,
-                                                     const int64_t* __restrict__ tile_off, int64_t* __restrict__ bbox) {
-    __shared__ int64_t red[4][2 * kMaxDim];
-    const int b = blockIdx.x;
-    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-    const int64_t t0 = tile_off[b], t1 = tile_off[b + 1];
-    int64_t acc[2 * kMaxDim];
-#pragma unroll
-    for (int i = 0; i < 2 * kMaxDim; ++i) acc[i] = (i & 1) ? INT64_MIN : INT64_MAX;
-    for (int64_t t = t0 + tid; t < t1; t += 256) {
-#pragma unroll
-        for (int i = 0; i < 2 * kMaxDim; ++i) {
-            const int64_t c = part[t * 2 * kMaxDim + i];
-            acc[i] = (i & 1) ? (c > acc[i] ? c : acc[i]) : (c < acc[i] ? c : acc[i]);
+        for (int ww = 0; ww < kBoxThreads / kWave; ++ww) {
+            const int64_t c = red[ww][tid];
+            a = isMin ? (c < a ? c : a) : (c > a ? c : a);
         }
-    }
-#pragma unroll
-    for (int i = 0; i < 2 * kMaxDim; ++i) {
-        for (int off = 32; off >= 1; off >>= 1) {
-            const int64_t c = __shfl_xor(acc[i], off, kWave);
-            acc[i] = (i & 1) ? (c > acc[i] ? c : acc[i]) : (c < acc[i] ? c : acc[i]);
-        }
-        if (lane == 0) red[w][i] = acc[i];
-    }
-    __syncthreads();
-    if (tid < 2 * kMaxDim) {
-        int64_t a = red[0][tid];
-        for (int ww = 1; ww < 4; ++ww) a = (tid & 1) ? (red[ww][tid] > a ? red[ww][tid] : a)
-                                                     : (red[ww][tid] < a ? red[ww][tid] : a);
-        bbox[int64_t(b) * 2 * kMaxDim + tid] = a;
+        int64_t* dst = bbox + int64_t(tl.inst) * 2 * kMaxDim + tid;
+        if (isMin) __hip_atomic_fetch_min(dst, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else __hip_atomic_fetch_max(dst, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -700,6 +667,32 @@ __device__ __forceinline__ int64_t hash_find(const uint64_t* __restrict__ hk, co
     }
 }
 
+// Neighbour lookup through the open-addressing hash.
+struct HashLookup {
+    const uint64_t* hk;
+    const uint32_t* hv;
+    int logcap;
+    __device__ __forceinline__ int64_t find(uint64_t k) const { return hash_find(hk, hv, k, logcap); }
+};
+
+// Neighbour lookup through a dense table over the whole packed key range:
+// entry k holds (epoch << 32) | cell for the keys of the current table and
+// older epochs elsewhere, so it is never cleared between rounds.
+struct DenseLookup {
+    const uint64_t* dk;
+    uint32_t epoch;
+    __device__ __forceinline__ int64_t find(uint64_t k) const {
+        const uint64_t e = dk[k];
+        return uint32_t(e >> 32) == epoch ? int64_t(uint32_t(e)) : -1;
+    }
+};
+
+__global__ void k_dense_insert(const uint64_t* __restrict__ key, int64_t m, uint64_t* __restrict__ dk,
+                               uint32_t epoch) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j < m) dk[key[j]] = (uint64_t(epoch) << 32) | uint64_t(j);
+}
+
 // Shift of every cell of an active instance (Eq. 1-2, parallel form Eq. 6).
 // One wave per cell: the lanes probe the 3^D neighbour keys j+v in parallel,
 // v enumerated lexicographically (dimension 0 most significant, which is
@@ -707,16 +700,16 @@ __device__ __forceinline__ int64_t hash_find(const uint64_t* __restrict__ hk, co
 // lane k folds dimension k left to right and lane D adds the integer weight.
 // p = N / W and the landing key floor(p/h) follow.
 constexpr int kShiftWaves = 4;
+constexpr int64_t kDenseMax = int64_t(1) << 27;  // largest key range with a dense lookup table (1 GiB)
 constexpr int kSlabMax = 4096;       // most columns of a tail's column table
+
 
 __host__ __device__ constexpr int pow3(int d) { return d == 0 ? 1 : 3 * pow3(d - 1); }
 
-template <int D>
+template <int D, class Lookup>
 __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int64_t m,
                                                                const InstParam* __restrict__ param,
-                                                               InstState* __restrict__ st,
-                                                               const uint64_t* __restrict__ hk,
-                                                               const uint32_t* __restrict__ hv, int logcap,
+                                                               InstState* __restrict__ st, Lookup lk,
                                                                double* __restrict__ pbuf,
                                                                uint64_t* __restrict__ kappa,
                                                                int32_t* __restrict__ Wout) {
@@ -750,7 +743,7 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
                 inside = inside && c >= 0 && c < P.E[k];
                 nk += uint64_t(int64_t(v)) * P.stride[k];
             }
-            if (inside) idx = hash_find(hk, hv, nk, logcap);
+            if (inside) idx = lk.find(nk);
         }
         const uint64_t bal = __ballot(idx >= 0);
         if (idx >= 0) list[w][nfound + __popcll(bal & lt)] = int32_t(idx);
@@ -907,6 +900,7 @@ __global__ void k_round_end(uint32_t* __restrict__ cur, int64_t m0, const uint32
 // closes the round.
 constexpr int kMergeThreads = 1024;
 constexpr int kMergeMax = 8192;
+constexpr int kMergeMaxInst = 8192;  // instances whose change flags it keeps in LDS
 constexpr int kMergeIPT = kMergeMax / kMergeThreads;  // 8
 
 // Exclusive block-wide scan of one value per thread (kMergeThreads threads);
@@ -936,7 +930,7 @@ __device__ __forceinline__ uint32_t merge_block_scan(uint32_t v, uint32_t* wtot,
 
 template <int D>
 __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int64_t m, CellTable u,
-                                                               InstState* __restrict__ st,
+                                                               InstState* __restrict__ st, int B,
                                                                const double* __restrict__ pbuf,
                                                                const uint64_t* __restrict__ kappa, int npasses,
                                                                uint32_t* __restrict__ gmap,
@@ -951,30 +945,44 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
     __shared__ uint16_t hs[kMergeMax + 1];  // first sorted position of every new cell
     __shared__ uint16_t gm[kMergeMax];      // merge map (old cell -> new cell)
     __shared__ uint32_t wtot[NW];
+    __shared__ uint32_t chmask[kMergeMaxInst / 32];  // instances whose round changed the state
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     const uint64_t lt = lanemask_lt();
     const int mm = int(m);
+    for (int i = tid; i < kMergeMaxInst / 32; i += kMergeThreads) chmask[i] = 0;
 
-    // ---- sort keys and stationarity of applying instances
+    // ---- sort keys and stationarity of applying instances (all loads of a
+    // thread are issued before any use)
+    {
+        int bi[kMergeIPT];
+        uint64_t key[kMergeIPT], kap[kMergeIPT];
+        int64_t cnt[kMergeIPT];
+        int ap[kMergeIPT];
 #pragma unroll
-    for (int i = 0; i < kMergeIPT; ++i) {
-        const int j0 = tid + i * kMergeThreads;
-        const bool valid = j0 < mm;
-        const int j = valid ? j0 : mm - 1;  // idle lanes shadow the last cell and raise nothing
-        const int b = t.inst[j];
-        const uint64_t key = t.key[j];
-        uint64_t out = key;
-        bool chg = false;
-        if (st[b].apply) {
-            const uint64_t kap = kappa[j];
-            out = kap;
-            chg = valid && kap != key;
-            const double C = double(t.cnt[j]);
-#pragma unroll
-            for (int k = 0; k < D; ++k) chg = chg || dbits(C * pbuf[k * t.cap + j]) != dbits(t.sum[k * t.cap + j]);
+        for (int i = 0; i < kMergeIPT; ++i) {
+            const int j = min(tid + i * kMergeThreads, mm - 1);
+            bi[i] = t.inst[j];
+            key[i] = t.key[j];
+            kap[i] = kappa[j];  // read for every cell, used for applying instances only
+            cnt[i] = t.cnt[j];
         }
-        wave_flag_or(&st[b].changed, chg);
-        if (valid) {
+#pragma unroll
+        for (int i = 0; i < kMergeIPT; ++i) ap[i] = st[bi[i]].apply;
+        __syncthreads();  // chmask cleared
+#pragma unroll
+        for (int i = 0; i < kMergeIPT; ++i) {
+            const int j = tid + i * kMergeThreads;
+            if (j >= mm) continue;
+            uint64_t out = key[i];
+            if (ap[i]) {
+                out = kap[i];
+                bool chg = kap[i] != key[i];
+                const double C = double(cnt[i]);
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    chg = chg || dbits(C * pbuf[k * t.cap + j]) != dbits(t.sum[k * t.cap + j]);
+                if (chg) atomicOr(&chmask[bi[i] >> 5], 1u << (bi[i] & 31));
+            }
             kbuf[0][j] = uint32_t(out);
             vbuf[0][j] = uint16_t(j);
         }
@@ -1078,10 +1086,19 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
     // ---- new cells: members, chunks, instance ranges, merged groups
     // (thread t owns new cells [t * IPT, (t + 1) * IPT))
     uint32_t nchunks = 0;
+    int bc[kMergeIPT + 1];  // instance of the cells tid * IPT - 1 .. tid * IPT + IPT - 1
+    int apc[kMergeIPT];
+    {
+        const int c0 = tid * kMergeIPT;
+        bc[0] = (c0 > 0 && c0 - 1 < mnew) ? t.inst[sv[hs[c0 - 1]]] : -1;
 #pragma unroll
-    for (int i = 0; i < kMergeIPT; ++i) {
-        const int c = tid * kMergeIPT + i;
-        if (c < mnew) nchunks += (uint32_t(hs[c + 1] - hs[c]) + kChunk - 1) / kChunk;
+        for (int i = 0; i < kMergeIPT; ++i) {
+            const int c = c0 + i;
+            bc[i + 1] = c < mnew ? t.inst[sv[hs[c]]] : -1;
+            if (c < mnew) nchunks += (uint32_t(hs[c + 1] - hs[c]) + kChunk - 1) / kChunk;
+        }
+#pragma unroll
+        for (int i = 0; i < kMergeIPT; ++i) apc[i] = bc[i + 1] >= 0 ? st[bc[i + 1]].apply : 0;
     }
     uint32_t tasks = 0;
     uint32_t choff = merge_block_scan(nchunks, wtot, &tasks);
@@ -1092,27 +1109,40 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
         const int p0 = hs[c];
         const uint32_t len = uint32_t(hs[c + 1]) - uint32_t(p0);
         const uint32_t nch = (len + kChunk - 1) / kChunk;
-        const int j0 = sv[p0];
-        const int b = t.inst[j0];
+        const int b = bc[i + 1], bp = bc[i];
         u.start[c] = uint32_t(p0);
         u.len[c] = len;
-        u.first[c] = uint32_t(j0);
+        u.first[c] = uint32_t(sv[p0]);
         u.nch[c] = nch;
         u.choff[c] = choff;
         u.inst[c] = b;
         choff += nch;
-        const int bp = c > 0 ? t.inst[sv[hs[c - 1]]] : -1;
         if (bp != b) {
             st[b].cs = c;
             if (bp >= 0) st[bp].ce = c;
         }
         if (c == mnew - 1) st[b].ce = mnew;
-        if (len > 1 && st[b].apply) atomicOr(&st[b].changed, 1);
+        if (len > 1 && apc[i]) atomicOr(&chmask[b >> 5], 1u << (b & 31));
     }
+    __syncthreads();
+    for (int b = tid; b < B; b += kMergeThreads)
+        if ((chmask[b >> 5] >> (b & 31)) & 1u) st[b].changed = 1;
 
     // ---- initial cell -> current cell (the per-instance round end follows
     // the sums, which still read which instances apply the round)
-    for (int64_t c = tid; c < m0; c += kMergeThreads) cur[c] = gm[cur[c]];
+    for (int64_t c0 = tid; c0 < m0; c0 += 4 * kMergeThreads) {
+        uint32_t v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t c = c0 + int64_t(i) * kMergeThreads;
+            v[i] = c < m0 ? cur[c] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t c = c0 + int64_t(i) * kMergeThreads;
+            if (c < m0) cur[c] = gm[v[i]];
+        }
+    }
     if (tid == 0) {
         counters[0] = mnew;   // new cells
         counters[1] = tasks;  // chunk tasks of their sums
@@ -1231,10 +1261,24 @@ __device__ inline int tail_cand(const TailWindow& w, int e) {
 // tail rounds [replay_r0, replay_r0 + ck.every) of a finished fit from the
 // checkpoint at replay_r0, writing only their tape (rounds numbered from
 // replay_r0); the fit's outputs and state are left untouched.
+// Whether some active instance still holds more cells than a tail workgroup
+// (the tail launched right after a device-wide round checks it first).
+__global__ void k_tail_gate(const InstState* __restrict__ st, int B, int64_t* __restrict__ gate) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < B; b += blockDim.x)
+        if (st[b].active && st[b].ce - st[b].cs > kTailCells) any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) *gate = any;
+}
+
+// With `gate` set and nonzero the kernel returns at once, changing nothing.
 template <int D>
 __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstParam* __restrict__ param,
                                                        InstState* __restrict__ st, uint32_t* __restrict__ tmap,
-                                                       int max_iter, TailTape tape, TailCkpt ck, int replay_r0) {
+                                                       int max_iter, TailTape tape, TailCkpt ck, int replay_r0,
+                                                       const int64_t* __restrict__ gate) {
     constexpr int MT = kTailCells;
     constexpr int NW = kTailThreads / kWave;
     __shared__ uint64_t lkey[MT];     // local packed key (key - base), ascending
@@ -1254,6 +1298,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
     __shared__ uint16_t rank_of[MT];        // old cell -> sorted position
     __shared__ int32_t s_flag[2][3];         // per round parity: any neighbour, bad key, changed
 
+    if (gate && *gate) return;
     const int b = blockIdx.x;
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     InstState* S = st + b;
@@ -1275,13 +1320,18 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
     }
     const InstParam& P = param[b];
     const double h = P.h;
-    int64_t lo[D], E[D];
-    uint64_t stride[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        lo[k] = P.lo[k];
-        E[k] = P.E[k];
-        stride[k] = P.stride[k];
+    // packing of the instance's keys, read from LDS where used (kept out of
+    // registers, which the rounds need)
+    __shared__ int64_t s_lo[D];
+    __shared__ uint64_t s_stride[D];
+    __shared__ double s_lod[D], s_Ed[D];
+    __shared__ int64_t s_E01[2];
+    if (tid < D) {
+        s_lo[tid] = P.lo[tid];
+        s_stride[tid] = P.stride[tid];
+        s_lod[tid] = double(P.lo[tid]);
+        s_Ed[tid] = double(P.E[tid]);
+        if (tid < 2) s_E01[tid] = P.E[tid < D ? tid : 0];
     }
 
     if (tid < m_entry) {
@@ -1301,7 +1351,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         }
         lkey[tid] = lk;
 #pragma unroll
-        for (int k = 0; k < D; ++k) crd[k][tid] = int32_t((lk / stride[k]) % uint64_t(E[k]));
+        for (int k = 0; k < D; ++k) crd[k][tid] = int32_t((lk / P.stride[k]) % uint64_t(P.E[k]));
         lmap[tid] = uint16_t(tid);
     }
     __syncthreads();
@@ -1313,7 +1363,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
     uint32_t flags = S->flags;
     int err = 0;
     const uint64_t lt = lanemask_lt();
-    const TailCols cols = tail_cols<D>(E[0], E[D >= 2 ? 1 : 0]);
+    const TailCols cols = tail_cols<D>(s_E01[0], D >= 2 ? s_E01[1] : 1);
     const bool fast_rank = P.span <= (1ull << 53);  // (key << 10 | index) fits in 63 bits
     if (tid < 6) (&s_flag[0][0])[tid] = 0;
     for (int round = 0;; ++round) {
@@ -1353,11 +1403,12 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
 #pragma unroll
             for (int dd = 0; dd < D; ++dd) p[dd] = -0.0;
             int nbs = 0;
-            for (int k0 = 0; k0 < ncand; k0 += 4) {
-                int okm[4];
-                int kk[4];
+            constexpr int U = D >= 5 ? 2 : 4;  // candidates per step (register budget of 1024 threads)
+            for (int k0 = 0; k0 < ncand; k0 += U) {
+                int okm[U];
+                int kk[U];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < U; ++u) {
                     okm[u] = (k0 + u < ncand) ? 1 : 0;
                     kk[u] = okm[u] ? tail_cand(win, k0 + u) : tid;
                 }
@@ -1365,10 +1416,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
                 for (int dd = 1; dd < D; ++dd) {
                     if (dd < cols.first_test) continue;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) okm[u] &= (uint32_t(crd[dd][kk[u]] - me[dd] + 1) <= 2u) ? 1 : 0;
+                    for (int u = 0; u < U; ++u) okm[u] &= (uint32_t(crd[dd][kk[u]] - me[dd] + 1) <= 2u) ? 1 : 0;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < U; ++u) {
                     const int k = kk[u];
                     const bool ok = okm[u] != 0;
                     W += ok ? int64_t(cnt[k]) : 0;
@@ -1383,10 +1434,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
             for (int dd = 0; dd < D; ++dd) {
                 p[dd] = p[dd] / double(W);
                 const double qq = cell_floor(p[dd], h);
-                const double rel = qq - double(lo[dd]);
-                if (!(rel >= 0.0 && rel < double(E[dd]))) bad = true;
-                q[dd] = int32_t(int64_t(qq) - lo[dd]);
-                kj += uint64_t(int64_t(qq) - lo[dd]) * stride[dd];
+                const double rel = qq - s_lod[dd];
+                if (!(rel >= 0.0 && rel < s_Ed[dd])) bad = true;
+                q[dd] = int32_t(int64_t(qq) - s_lo[dd]);
+                kj += uint64_t(int64_t(qq) - s_lo[dd]) * s_stride[dd];
             }
         }
         if (__ballot(nb) && lane == 0) atomicOr(&flg[0], 1);
@@ -1869,13 +1920,31 @@ __global__ void k_loss_mubar(const double* __restrict__ X, int64_t xcap, const i
 // ===========================================================================
 // outputs
 // ===========================================================================
-__global__ void k_labels(const uint32_t* __restrict__ cell0, const uint32_t* __restrict__ cur,
-                         const uint32_t* __restrict__ tmap, int32_t* __restrict__ labels, int64_t n) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t c0 = cell0[i];
-    const uint32_t c = cur ? cur[c0] : c0;
-    labels[i] = int32_t(tmap[c]);
+// Grid-stride over the points, four per thread per step; returns at once when
+// `gate` is set and nonzero (the tail did not run).
+constexpr int kLabelBlocks = 2048;
+__global__ __launch_bounds__(256) void k_labels(const uint32_t* __restrict__ cell0, const uint32_t* __restrict__ cur,
+                                                const uint32_t* __restrict__ tmap, int32_t* __restrict__ labels,
+                                                int64_t n, const int64_t* __restrict__ gate) {
+    if (gate && *gate) return;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += 4 * stride) {
+        uint32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u * stride;
+            c[u] = i < n ? cell0[i] : 0u;
+        }
+        if (cur) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) c[u] = cur[c[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i < n) labels[i] = int32_t(tmap[c[u]]);
+        }
+    }
 }
 
 // Row r of the concatenated output belongs to instance b with

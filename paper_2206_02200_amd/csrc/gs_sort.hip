@@ -71,7 +71,7 @@ __global__ void k_clear_u64(uint64_t* __restrict__ p, int64_t n) {
     if (i < n) p[i] = 0;
 }
 
-constexpr int kSortLookWindow = 32;
+constexpr int kSortLookWindow = 4;
 
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict__ kin, const uint32_t* __restrict__ vin,

@@ -35,8 +35,8 @@ EXPORTED = [
     "gs_context_set_tape", "gs_backward", "gs_point_mode_loss", "gs_point_mode_loss_backward",
     "gs_context_set_config", "gs_context_get_config", "gs_autotune",
 ]
-CFG_MERGE_SMALL, CFG_TILE_CHUNKS = 0, 1
-CONFIG_KEYS = {"merge_small": CFG_MERGE_SMALL, "tile_chunks": CFG_TILE_CHUNKS}
+CFG_MERGE_SMALL, CFG_TILE_CHUNKS, CFG_DENSE_TABLE = 0, 1, 2
+CONFIG_KEYS = {"merge_small": CFG_MERGE_SMALL, "tile_chunks": CFG_TILE_CHUNKS, "dense_table": CFG_DENSE_TABLE}
 
 
 class GridShiftError(RuntimeError):
@@ -140,7 +140,7 @@ class Context:
         _check(_lib.gs_context_set_tape(self.handle, int(on)))
 
     def set_config(self, **kv):
-        """Launch choices (merge_small=0/1, tile_chunks=1..64); results never depend on them."""
+        """Launch choices (merge_small=0/1, tile_chunks=1..64, dense_table=0/1); results never depend on them."""
         for k, v in kv.items():
             _check(_lib.gs_context_set_config(self.handle, CONFIG_KEYS[k], int(v)))
 

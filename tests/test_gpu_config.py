@@ -22,7 +22,7 @@ from oracle import gs_oracle  # noqa: E402
 from paper_2206_02200_amd import gridshift  # noqa: E402
 
 DEV = torch.device("cuda:0")
-CONFIGS = [dict(merge_small=ms, tile_chunks=tc) for ms in (1, 0) for tc in (1, 3, 4, 8)]
+CONFIGS = [dict(merge_small=ms, tile_chunks=tc, dense_table=dt) for ms in (1, 0) for dt in (1, 0) for tc in (1, 3, 8)]
 
 
 def _say(*a):
@@ -76,8 +76,8 @@ def test_batched_under_both_merge_paths():
     X = torch.from_numpy(np.concatenate(xs, axis=0)).to(DEV)
     ref = [gs_oracle.fit(v, h, 100) for v, h in zip(xs, hs)]
     ctx = gridshift.Context(0)
-    for ms in (1, 0):
-        ctx.set_config(merge_small=ms)
+    for ms, dt in ((1, 1), (0, 0), (1, 0)):
+        ctx.set_config(merge_small=ms, dense_table=dt)
         br = gridshift.fit_batched(X, off, hs, 100, ctx=ctx, with_sums=True)
         sums = br.sums.cpu().numpy()
         for b, o in enumerate(ref):
@@ -110,7 +110,7 @@ def test_autotune_keeps_a_candidate_and_results():
     ctx = gridshift.Context(0)
     cfg = ctx.autotune(xt, h, 100, reps=2)
     _say(f"autotuned configuration: {cfg}")
-    assert cfg["merge_small"] in (0, 1) and cfg["tile_chunks"] in (1, 2, 4, 8)
+    assert cfg["merge_small"] in (0, 1) and cfg["dense_table"] in (0, 1) and cfg["tile_chunks"] in (1, 2, 4, 8)
     o = gs_oracle.fit(x, h, 100)
     r = gridshift.fit(xt, h, 100, ctx=ctx)
     np.testing.assert_array_equal(r.labels.cpu().numpy(), o.labels)
@@ -119,10 +119,10 @@ def test_autotune_keeps_a_candidate_and_results():
 
 def test_configuration_errors():
     ctx = gridshift.Context(0)
-    for kv in (dict(merge_small=2), dict(tile_chunks=0), dict(tile_chunks=65)):
+    for kv in (dict(merge_small=2), dict(tile_chunks=0), dict(tile_chunks=65), dict(dense_table=-1)):
         with pytest.raises(gridshift.GridShiftError) as e:
             ctx.set_config(**kv)
         assert e.value.code == 1
     assert gridshift._lib.gs_context_set_config(ctx.handle, 7, 1) == 1  # unknown key
-    assert ctx.config() == {"merge_small": 1, "tile_chunks": 4}
+    assert ctx.config() == {"merge_small": 1, "tile_chunks": 4, "dense_table": 1}
     ctx.close()
