@@ -106,6 +106,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="plain,batched,fwd_bwd")
+    ap.add_argument("--form-only", choices=["batched", "fwd_bwd"], default=None,
+                    help="time only this form (--steps timed calls after one warm-up) and print its JSON object; "
+                         "for profiling a form on its own")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="run an elementwise copy of this many MiB (read + write) before the fits, untimed: "
                          "the reference kernel that scales hardware byte counters taken on this command")
@@ -123,6 +126,12 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.form_only:
+        if args.form_only == "batched":
+            print(json.dumps(bench_batched(gridshift.Context(0), dev, args.steps)), flush=True)
+        else:
+            print(json.dumps(bench_fwd_bwd(dev, args.steps)), flush=True)
+        return 0
     if args.calibration_copy_mb > 0:
         src = torch.ones(args.calibration_copy_mb << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
