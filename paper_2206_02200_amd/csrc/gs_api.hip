@@ -67,10 +67,20 @@ struct gs_context {
     DBuf tkey[2], tcnt[2], tsum[2], tinst[2], tstart[2], tlen[2], tfirst[2], tnch[2], tchoff[2];
     DBuf kappa, pbuf, gmap, cur, tmap, part, partc, hk, hv, ckA, ckB, cvA, cvB;
     // instances
-    DBuf param, state, rowoff, hs, bbox, koff, tiles;
+    // Control block: one allocation holding, in this order, the boxes, the
+    // counters, the instance states, the cluster row offsets, the row
+    // offsets, the bandwidths, the row tiles and the packing parameters; the
+    // views below point into it.  Its
+    // part before the parameters is uploaded in one copy at the start of a
+    // fit, and boxes + counters and counters + states are read back in one
+    // copy each.
+    DBuf ctl;
+    DBuf param, state, koff, rowoff, hs, bbox, counters, tiles;  // views into ctl (never allocated or freed)
+    std::vector<char> ctl_img;                             // host image of the uploaded part
+    bool hist_dirty = true;                                // sort histograms may hold stale counts
     int64_t ntiles = 0;
     // scans and sorts
-    DBuf counters, look, tilectr, shist, sdbase, sctr, slook;
+    DBuf look, tilectr, shist, sctr, slook;
     gs::SortScratch sort;
     uint32_t scan_epoch = 0;
     uint64_t tile_base = 0;  // value of the scan tile counter before the next scan
@@ -300,6 +310,20 @@ gs_status h2d_batch(gs_context* c, const std::vector<Xfer>& xs, hipStream_t s) {
     return GS_OK;
 }
 
+// The counters and the instance states (adjacent in the control block) in
+// one copy, with one wait.
+gs_status read_counters_states(gs_context* c, int64_t* ctrs, hipStream_t s) {
+    const char* a = static_cast<const char*>(c->counters.p);
+    const char* z = static_cast<const char*>(c->state.p) + c->state.cap;
+    const size_t off = static_cast<const char*>(c->state.p) - a;
+    std::vector<char>& tmp = c->ctl_img;
+    tmp.resize(size_t(z - a));
+    GS_TRY(d2h(c, tmp.data(), a, tmp.size(), s));
+    std::memcpy(ctrs, tmp.data(), 8 * sizeof(int64_t));
+    std::memcpy(c->st.data(), tmp.data() + off, c->state.cap);
+    return GS_OK;
+}
+
 // Several device -> host copies with one wait.
 gs_status d2h_batch(gs_context* c, const std::vector<Xfer>& xs, hipStream_t s) {
     size_t total = 0;
@@ -431,6 +455,26 @@ gs_status segsum(gs_context* c, int d, Src src, gs::CellTable t, int64_t m_bound
     return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
 }
 
+// Ready the dense key table for one more table (allocated and cleared on
+// first use or growth, cleared again before the epochs wrap) and hand out a
+// new epoch for its entries (c->dk_epoch is the last one handed out, so an
+// epoch reserved for a table that never got its round is never reused).
+// Stream-ordered: a clear here comes after every lookup of the rounds before.
+gs_status dense_reserve(gs_context* c, hipStream_t s, uint32_t* next) {
+    if (c->dk.cap < size_t(c->key_span) * 8) {
+        GS_TRY(ensure(c->dk, size_t(c->key_span) * 8));
+        k_fill_u64<<<blocks_for(c->dk.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->dk), c->dk.cap / 8, 0);
+        c->dk_epoch = 0;
+    }
+    if (c->dk_epoch == 0xffffffffu) {
+        k_fill_u64<<<blocks_for(c->dk.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->dk), c->dk.cap / 8, 0);
+        c->dk_epoch = 0;
+    }
+    *next = ++c->dk_epoch;
+    GS_HIP(hipGetLastError());
+    return GS_OK;
+}
+
 template <class Lookup>
 gs_status launch_shift(gs_context* c, int d, gs::CellTable t, int64_t m, const gs::InstParam* prm, gs::InstState* st,
                        Lookup lk, double* pbuf, uint64_t* kappa, int32_t* Wout, hipStream_t s) {
@@ -559,9 +603,11 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     GS_TRY(ensure(c->vA, size_t(N) * 4));
     GS_TRY(ensure(c->vB, size_t(N) * 4));
     GS_TRY(ensure(c->cell0, size_t(N) * 4));
-    GS_TRY(ensure(c->shist, gs::kHistCopies * gs::kHistStride * 4));
-    GS_TRY(ensure(c->sdbase, gs::kSortMaxPasses * 256 * 4));
-    GS_TRY(ensure(c->sctr, 64));
+    {
+        void* old = c->sctr.p;
+        GS_TRY(ensure(c->sctr, 64));
+        if (c->sctr.p != old) c->sort.tile_base = 0x7fffffffull;  // new counter: cleared before its first use
+    }
     const int64_t sort_tiles = gs::sort_look_tiles(N);
     if (c->slook.cap < size_t(sort_tiles) * 256 * 8) {
         GS_TRY(ensure(c->slook, size_t(sort_tiles) * 256 * 8));
@@ -569,7 +615,6 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         c->sort.epoch = 0;
     }
     c->sort.hist = P<uint32_t>(c->shist);
-    c->sort.dbase = P<uint32_t>(c->sdbase);
     c->sort.ctr = P<uint32_t>(c->sctr);
     c->sort.look = P<uint64_t>(c->slook);
     c->sort.look_tiles = int64_t(c->slook.cap / (256 * 8));
@@ -578,13 +623,13 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     c->sort.prof_end = sort_prof_end;
 
     const int np = gs::sort_passes(bits);
-    if (c->ntiles > 0) {  // the digit histograms were cleared by k_init_state
+    if (c->ntiles > 0) {  // the current histogram buffer is zero (cleared by the previous sort)
         const unsigned g = unsigned(c->ntiles);
         const gs::RowTile* tl = P<gs::RowTile>(c->tiles);
         const int tk = prof_begin(c, s, "make_keys");
         switch (d) {
 #define GS_MK(D) \
-    case D: gs::k_make_keys<T, K, D><<<g, gs::kBoxThreads, 0, s>>>(x, ld, tl, prm, P<K>(c->kA), np, c->sort.hist); break;
+    case D: gs::k_make_keys<T, K, D><<<g, gs::kBoxThreads, 0, s>>>(x, ld, tl, prm, P<K>(c->kA), np, c->sort.cur_hist()); break;
             GS_MK(1) GS_MK(2) GS_MK(3) GS_MK(4) GS_MK(5) GS_MK(6)
 #undef GS_MK
             default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
@@ -625,10 +670,31 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         GS_TRY(ensure(c->tchoff[i], size_t(c->capM) * 4));
     }
     gs::CellTable T0 = table(c, 0);
-    PROF_LAUNCH("cell_setup", m0 * 20.0,
-                gs::k_cell_setup<<<blocks_for(c->capM, 256), 256, 0, s>>>(ctr + 0, N, T0, 0, row_off, B, nullptr,
-                                                                           st, true));
-    GS_HIP(hipGetLastError());
+    // cell rows; when a device-wide round follows (some instance may hold
+    // more cells than a tail workgroup), the same pass starts the map initial
+    // cell -> current cell and fills the dense key table for it
+    const bool wide_next = m0 > gs::kTailCells;
+    const bool dense = c->cfg.dense_table && c->key_span <= gs::kDenseMax;
+    bool dk_pre = false;  // the next round's table is already in the dense table, under epoch dk_pre_epoch
+    uint32_t dk_pre_epoch = 0;
+    {
+        uint32_t* cur0 = nullptr;
+        uint64_t* dk0 = nullptr;
+        if (wide_next) {
+            GS_TRY(ensure(c->cur, size_t(c->capM) * 4));
+            cur0 = P<uint32_t>(c->cur);
+            if (dense) {
+                GS_TRY(dense_reserve(c, s, &dk_pre_epoch));
+                dk0 = P<uint64_t>(c->dk);
+                dk_pre = true;
+            }
+        }
+        PROF_LAUNCH("cell_setup", m0 * (20.0 + (wide_next ? 12.0 : 0.0)),
+                    gs::k_cell_setup<<<blocks_for(c->capM, 256), 256, 0, s>>>(ctr + 0, N, T0, 0, row_off, B,
+                                                                               nullptr, st, true, cur0, dk0,
+                                                                               dk_pre_epoch));
+        GS_HIP(hipGetLastError());
+    }
     GS_TRY(segsum(c, d, gs::SrcPoints<T>{x, ld, perm}, T0, m0, N, s, 4.0 + double(d) * sizeof(T)));
     if (c->tape_on && m0 > 0) {  // the initial cells, for the adjoint and the loss
         GS_TRY(ensure(c->sums0, size_t(m0) * d * 8));
@@ -675,7 +741,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
             PROF_LAUNCH("labels", N * 8.0,
                         gs::k_labels<<<unsigned(std::min<int64_t>(gs::kLabelBlocks, blocks_for(N, 256))), 256, 0, s>>>(
                             P<uint32_t>(c->cell0), nwide ? P<uint32_t>(c->cur) : nullptr, P<uint32_t>(c->tmap), labels, N,
-                            gate));
+                            gate, st, B, P<int64_t>(c->koff)));
             GS_HIP(hipGetLastError());
         }
         return GS_OK;
@@ -694,7 +760,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         if (!need) break;
         if (wide == 0) {
             GS_TRY(ensure(c->cur, size_t(c->capM) * 4));
-            k_iota32<<<blocks_for(m0, 256), 256, 0, s>>>(P<uint32_t>(c->cur), m0);
+            if (!wide_next) k_iota32<<<blocks_for(m0, 256), 256, 0, s>>>(P<uint32_t>(c->cur), m0);
             GS_TRY(ensure(c->kappa, size_t(c->capM) * 8));
             GS_TRY(ensure(c->pbuf, size_t(c->capM) * d * 8));
             GS_TRY(ensure(c->gmap, size_t(c->capM) * 4));
@@ -705,23 +771,20 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         }
         ++wide;
         gs::CellTable TT = table(c, cur), U = table(c, 1 - cur);
-        // neighbour lookup structure of the round's table
-        const bool dense = c->cfg.dense_table && c->key_span <= gs::kDenseMax;
+        // neighbour lookup structure of the round's table (the first round's
+        // dense entries were written with the cell rows)
         int logcap = 1;
+        uint32_t tab_epoch = 0;  // epoch of this round's table in the dense table
         if (dense) {
-            if (c->dk.cap < size_t(c->key_span) * 8) {
-                GS_TRY(ensure(c->dk, size_t(c->key_span) * 8));
-                k_fill_u64<<<blocks_for(c->dk.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->dk), c->dk.cap / 8, 0);
-                c->dk_epoch = 0;
+            if (dk_pre) {
+                tab_epoch = dk_pre_epoch;
+            } else {
+                GS_TRY(dense_reserve(c, s, &tab_epoch));
+                PROF_LAUNCH("dense_insert", M * 16.0,
+                            gs::k_dense_insert<<<blocks_for(M, 256), 256, 0, s>>>(TT.key, M, P<uint64_t>(c->dk),
+                                                                                   tab_epoch));
             }
-            if (c->dk_epoch == 0xffffffffu) {
-                k_fill_u64<<<blocks_for(c->dk.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->dk), c->dk.cap / 8, 0);
-                c->dk_epoch = 0;
-            }
-            ++c->dk_epoch;
-            PROF_LAUNCH("dense_insert", M * 16.0,
-                        gs::k_dense_insert<<<blocks_for(M, 256), 256, 0, s>>>(TT.key, M, P<uint64_t>(c->dk),
-                                                                               c->dk_epoch));
+            dk_pre = false;
         } else {
             while ((int64_t(1) << logcap) < 2 * M) ++logcap;
             const int64_t hcap = int64_t(1) << logcap;
@@ -756,15 +819,21 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
             c->wt_used = woff + M;
         }
         if (dense)
-            GS_TRY(launch_shift(c, d, TT, M, prm, st, gs::DenseLookup{P<uint64_t>(c->dk), c->dk_epoch},
+            GS_TRY(launch_shift(c, d, TT, M, prm, st, gs::DenseLookup{P<uint64_t>(c->dk), tab_epoch},
                                 P<double>(c->pbuf), P<uint64_t>(c->kappa), Wrec, s));
         else
             GS_TRY(launch_shift(c, d, TT, M, prm, st,
                                 gs::HashLookup{P<uint64_t>(c->hk), P<uint32_t>(c->hv), logcap}, P<double>(c->pbuf),
                                 P<uint64_t>(c->kappa), Wrec, s));
-        gs::k_decide<<<blocks_for(B, 256), 256, 0, s>>>(st, B, max_iter);
+        bool gated = false;  // the round's last kernel already wrote the tail gate
+        uint64_t* dk_next = nullptr;  // the merge also enters the new table in the dense table
+        if (dense) {
+            GS_TRY(dense_reserve(c, s, &dk_pre_epoch));
+            dk_next = P<uint64_t>(c->dk);
+            dk_pre = true;
+        }
         if (sizeof(K) == 4 && M <= gs::kMergeMax && B <= gs::kMergeMaxInst && c->cfg.merge_small) {
-            // the whole merge and the round's bookkeeping in one workgroup
+            // the round's decisions, the whole merge and its bookkeeping in one workgroup
             uint32_t* gt = c->tape_on ? P<uint32_t>(c->wt_g) + woff : nullptr;
             const int tk = prof_begin(c, s, "merge_small");
             switch (d) {
@@ -773,7 +842,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         gs::k_merge_small<D><<<1, gs::kMergeThreads, 0, s>>>(TT, M, U, st, B, P<double>(c->pbuf),                  \
                                                              P<uint64_t>(c->kappa), np, P<uint32_t>(c->gmap),      \
                                                              P<uint32_t>(c->cvA), P<uint32_t>(c->cur), m0, gt,     \
-                                                             ctr);                                                 \
+                                                             ctr, max_iter, dk_next, dk_pre_epoch);                \
         break;
                 GS_MS(1) GS_MS(2) GS_MS(3) GS_MS(4) GS_MS(5) GS_MS(6)
 #undef GS_MS
@@ -783,15 +852,18 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
             GS_HIP(hipGetLastError());
             gs::SrcMerge src{P<double>(c->pbuf), TT.sum, TT.cnt, TT.inst, st, P<uint32_t>(c->cvA), c->capM};
             GS_TRY(segsum(c, d, src, U, M, M, s, 4.0 + 4.0 + 8.0 + 8.0 * d, true));
+            gated = B <= 256;  // one block: it also writes the tail gate
             PROF_LAUNCH("round_end", B * 48.0,
                         gs::k_round_end<<<blocks_for(B, 256), 256, 0, s>>>(P<uint32_t>(c->cur), 0,
-                                                                            P<uint32_t>(c->gmap), st, B, apprec));
+                                                                            P<uint32_t>(c->gmap), st, B, apprec,
+                                                                            gated ? ctr + 4 : nullptr));
             GS_HIP(hipGetLastError());
         } else {
+        gs::k_decide<<<blocks_for(B, 256), 256, 0, s>>>(st, B, max_iter);
         PROF_LAUNCH("merge_prep", M * (8.0 * 3 + 16.0 * d + sizeof(K)),
                     gs::k_merge_prep<K><<<blocks_for(M, 256), 256, 0, s>>>(TT, M, st, st, P<double>(c->pbuf),
                                                                             P<uint64_t>(c->kappa), P<K>(c->ckA), d,
-                                                                            np, c->sort.hist));
+                                                                            np, c->sort.cur_hist()));
         GS_HIP(hipGetLastError());
         K* mk = nullptr;
         uint32_t* mperm = nullptr;
@@ -803,27 +875,27 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
             GS_HIP(hipMemcpyAsync(P<uint32_t>(c->wt_g) + woff, c->gmap.p, M * 4, hipMemcpyDeviceToDevice, s));
         PROF_LAUNCH("cell_setup", M * 24.0,
                     gs::k_cell_setup<<<blocks_for(M, 256), 256, 0, s>>>(ctr + 0, M, U, 1, row_off, B, TT.inst, st,
-                                                                         true));
+                                                                         true, nullptr, dk_next, dk_pre_epoch));
         GS_HIP(hipGetLastError());
         gs::SrcMerge src{P<double>(c->pbuf), TT.sum, TT.cnt, TT.inst, st, mperm, c->capM};
         GS_TRY(segsum(c, d, src, U, M, M, s, 4.0 + 4.0 + 8.0 + 8.0 * d));
         PROF_LAUNCH("round_end", m0 * 12.0,
                     gs::k_round_end<<<blocks_for(std::max<int64_t>(m0, B), 256), 256, 0, s>>>(
-                        P<uint32_t>(c->cur), m0, P<uint32_t>(c->gmap), st, B, apprec));
+                        P<uint32_t>(c->cur), m0, P<uint32_t>(c->gmap), st, B, apprec, nullptr));
         GS_HIP(hipGetLastError());
         }
         cur = 1 - cur;
         // the tail and the labels right away, unless some instance still needs
         // a device-wide round (then the tail changes nothing and the loop goes on)
-        gs::k_tail_gate<<<1, 256, 0, s>>>(st, B, ctr + 4);
-        GS_HIP(hipGetLastError());
+        if (!gated) {
+            gs::k_tail_gate<<<1, 256, 0, s>>>(st, B, ctr + 4);
+            GS_HIP(hipGetLastError());
+        }
         GS_TRY(tail_and_labels(cur, wide, M, ctr + 4));
-        int64_t gate = 0;
-        GS_TRY(d2h_batch(c,
-                         {{&M, ctr + 0, sizeof(int64_t)},
-                          {c->st.data(), st, sizeof(gs::InstState) * B},
-                          {&gate, ctr + 4, sizeof(int64_t)}},
-                         s));
+        int64_t ctrs[8];
+        GS_TRY(read_counters_states(c, ctrs, s));
+        M = ctrs[0];
+        const int64_t gate = ctrs[4];
         for (int b = 0; b < B; ++b)
             if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");
         if (!gate) {
@@ -851,11 +923,11 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
 // ---------------------------------------------------------------------------
 // differentiable form
 // ---------------------------------------------------------------------------
-gs_status upload_koff(gs_context* c, hipStream_t s, std::vector<int64_t>& koff) {
+// Host copy of the cluster row offsets (the fit left the same values in
+// c->koff on the device).
+gs_status host_koff(gs_context* c, hipStream_t, std::vector<int64_t>& koff) {
     koff.assign(c->B + 1, 0);
     for (int b = 0; b < c->B; ++b) koff[b + 1] = koff[b] + c->st[b].K;
-    GS_TRY(ensure(c->koff, sizeof(int64_t) * (c->B + 1)));
-    GS_TRY(h2d(c, c->koff.p, koff.data(), sizeof(int64_t) * (c->B + 1), s));
     return GS_OK;
 }
 
@@ -906,7 +978,7 @@ gs_status launch_adj_stencil(gs_context* c, int d, const uint64_t* key, const in
 gs_status adjoint_core(gs_context* c, const double* gm, hipStream_t s, double** sbar0_out) {
     const int d = c->d, B = c->B;
     std::vector<int64_t> koff;
-    GS_TRY(upload_koff(c, s, koff));
+    GS_TRY(host_koff(c, s, koff));
     const int64_t rows = koff[B];
     const size_t cellbytes = size_t(c->capM) * d * 8;
     GS_TRY(ensure(c->sbA, cellbytes));
@@ -1008,12 +1080,6 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
     GS_HIP(hipSetDevice(c->device));
     prof_flush(c, false);  // drop records of an earlier failed call
 
-    GS_TRY(ensure(c->param, sizeof(gs::InstParam) * B));
-    GS_TRY(ensure(c->state, sizeof(gs::InstState) * B));
-    GS_TRY(ensure(c->rowoff, sizeof(int64_t) * (B + 1)));
-    GS_TRY(ensure(c->hs, sizeof(double) * B));
-    GS_TRY(ensure(c->bbox, sizeof(int64_t) * B * gs::kMaxDim * 2));
-    GS_TRY(ensure(c->counters, 8 * sizeof(int64_t)));
     // row tiles of tile_chunks staged chunks of rows, each inside one instance
     const int trows = c->cfg.tile_chunks * gs::chunk_rows(d, dtype == GS_F32 ? 4 : 8);
     std::vector<gs::RowTile> tiles;
@@ -1022,16 +1088,57 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
             tiles.push_back({r, std::min<int64_t>(r + trows, offsets[b + 1]), b, 0});
     }
     c->ntiles = int64_t(tiles.size());
-    GS_TRY(ensure(c->tiles, sizeof(gs::RowTile) * std::max<size_t>(tiles.size(), 1)));
-    GS_TRY(h2d_batch(c,
-                     {{c->rowoff.p, offsets, sizeof(int64_t) * (B + 1)},
-                      {c->hs.p, h, sizeof(double) * B},
-                      {c->tiles.p, tiles.data(), sizeof(gs::RowTile) * tiles.size()}},
-                     s));
-    GS_TRY(ensure(c->shist, gs::kHistCopies * gs::kHistStride * 4));
-    gs::k_init_state<<<blocks_for(std::max(B, gs::kHistCopies * gs::kHistStride), 256), 256, 0, s>>>(
-        P<gs::InstState>(c->state), B, P<int64_t>(c->bbox), d, P<int64_t>(c->counters), P<uint32_t>(c->shist));
-    GS_HIP(hipGetLastError());
+    // control block layout (256-byte aligned parts)
+    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const int nbc = B >= 64 ? 1 : 16;  // box copies per instance (fewer atomics per address)
+    const size_t box_bytes = sizeof(int64_t) * size_t(B) * nbc * gs::kMaxDim * 2;
+    const size_t o_ctr = al(box_bytes);
+    const size_t o_state = al(o_ctr + 8 * sizeof(int64_t));
+    const size_t o_koff = al(o_state + sizeof(gs::InstState) * B);
+    const size_t o_rowoff = al(o_koff + sizeof(int64_t) * (B + 1));
+    const size_t o_hs = al(o_rowoff + sizeof(int64_t) * (B + 1));
+    const size_t o_tiles = al(o_hs + sizeof(double) * B);
+    const size_t up_end = o_tiles + sizeof(gs::RowTile) * tiles.size();
+    const size_t o_param = al(up_end);
+    GS_TRY(ensure(c->ctl, o_param + sizeof(gs::InstParam) * B));
+    char* base = static_cast<char*>(c->ctl.p);
+    c->bbox = DBuf{base, box_bytes};
+    c->counters = DBuf{base + o_ctr, 8 * sizeof(int64_t)};
+    c->state = DBuf{base + o_state, sizeof(gs::InstState) * B};
+    c->koff = DBuf{base + o_koff, sizeof(int64_t) * (B + 1)};  // written by the labels kernel (zero if no points)
+    c->rowoff = DBuf{base + o_rowoff, sizeof(int64_t) * (B + 1)};
+    c->hs = DBuf{base + o_hs, sizeof(double) * B};
+    c->tiles = DBuf{base + o_tiles, sizeof(gs::RowTile) * tiles.size()};
+    c->param = DBuf{base + o_param, sizeof(gs::InstParam) * B};
+    // initial boxes (empty), counters (zero) and states (active), offsets,
+    // bandwidths and tiles: one upload
+    std::vector<char>& img = c->ctl_img;
+    img.assign(up_end, 0);
+    {
+        int64_t* bx = reinterpret_cast<int64_t*>(img.data());
+        for (size_t i = 0; i < box_bytes / 8; i += 2) {
+            bx[i] = INT64_MAX;
+            bx[i + 1] = INT64_MIN;
+        }
+        gs::InstState z{};
+        z.active = 1;
+        for (int b = 0; b < B; ++b) std::memcpy(img.data() + o_state + sizeof(z) * b, &z, sizeof(z));
+        std::memcpy(img.data() + o_rowoff, offsets, sizeof(int64_t) * (B + 1));
+        std::memcpy(img.data() + o_hs, h, sizeof(double) * B);
+        if (!tiles.empty()) std::memcpy(img.data() + o_tiles, tiles.data(), sizeof(gs::RowTile) * tiles.size());
+    }
+    GS_TRY(h2d(c, base, img.data(), up_end, s));
+    {
+        void* old = c->shist.p;
+        GS_TRY(ensure(c->shist, gs::kHistEntries * 4));
+        if (c->shist.p != old) c->hist_dirty = true;
+    }
+    if (c->hist_dirty) {  // each sort clears the buffer the next producer uses; only a new or failed use needs this
+        k_fill_u32<<<blocks_for(gs::kHistEntries, 256), 256, 0, s>>>(
+            P<uint32_t>(c->shist), gs::kHistEntries, 0u);
+        GS_HIP(hipGetLastError());
+        c->hist_dirty = false;
+    }
 
     std::vector<int64_t> box(size_t(B) * gs::kMaxDim * 2, 0);
     if (N > 0) {
@@ -1046,18 +1153,33 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
         const int tk = prof_begin(c, s, "bbox");
         switch (d * 2 + (dtype == GS_F32 ? 0 : 1)) {
 #define GS_BB(D)                                                                                               \
-    case 2 * D: gs::k_bbox_tiles<float, D><<<g, gs::kBoxThreads, 0, s>>>(xf, ld, tl, hsd, bp, cn); break;     \
-    case 2 * D + 1: gs::k_bbox_tiles<double, D><<<g, gs::kBoxThreads, 0, s>>>(xd, ld, tl, hsd, bp, cn); break;
+    case 2 * D: gs::k_bbox_tiles<float, D><<<g, gs::kBoxThreads, 0, s>>>(xf, ld, tl, hsd, bp, nbc, cn); break; \
+    case 2 * D + 1:                                                                                            \
+        gs::k_bbox_tiles<double, D><<<g, gs::kBoxThreads, 0, s>>>(xd, ld, tl, hsd, bp, nbc, cn);               \
+        break;
             GS_BB(1) GS_BB(2) GS_BB(3) GS_BB(4) GS_BB(5) GS_BB(6)
 #undef GS_BB
             default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
         }
         prof_end(c, s, tk, xb);
         GS_HIP(hipGetLastError());
+        // boxes and counters in one copy (counter 2 holds the error bits)
+        std::vector<char> rb(o_ctr + 3 * sizeof(int64_t));
+        GS_TRY(d2h(c, rb.data(), base, rb.size(), s));
+        const int64_t* bc = reinterpret_cast<const int64_t*>(rb.data());
+        for (int b = 0; b < B; ++b)
+            for (int k = 0; k < gs::kMaxDim; ++k) {
+                int64_t mn = INT64_MAX, mx = INT64_MIN;
+                for (int q = 0; q < nbc; ++q) {
+                    const int64_t* e = bc + ((int64_t(b) * nbc + q) * gs::kMaxDim + k) * 2;
+                    mn = std::min(mn, e[0]);
+                    mx = std::max(mx, e[1]);
+                }
+                box[(int64_t(b) * gs::kMaxDim + k) * 2 + 0] = mn;
+                box[(int64_t(b) * gs::kMaxDim + k) * 2 + 1] = mx;
+            }
         int64_t errbits = 0;
-        GS_TRY(d2h_batch(c, {{box.data(), c->bbox.p, box.size() * sizeof(int64_t)},
-                             {&errbits, P<int64_t>(c->counters) + 2, sizeof(int64_t)}},
-                         s));
+        std::memcpy(&errbits, rb.data() + o_ctr + 2 * sizeof(int64_t), sizeof(int64_t));
         if (errbits & 1) return fail(GS_ERR_NONFINITE, "a coordinate is NaN or infinite");
         if (errbits & 2) return fail(GS_ERR_KEY_RANGE, "|floor(x/h)| >= 2^52");
     }
@@ -1079,6 +1201,7 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
     }
     if (rc != GS_OK) {
         (void)hipStreamSynchronize(s);
+        c->hist_dirty = true;
         prof_flush(c, false);
         return rc;
     }
@@ -1108,7 +1231,7 @@ template <typename T>
 static gs_status loss_fwd(gs_context* c, const T* x, const int32_t* labels, double* loss, hipStream_t s) {
     const int B = c->B;
     std::vector<int64_t> koff;
-    GS_TRY(upload_koff(c, s, koff));
+    GS_TRY(host_koff(c, s, koff));
     GS_TRY(cluster_modes(c, s, koff[B]));
     // one "cell" per instance, whose members are its points in index order
     std::vector<uint32_t> host(4 * size_t(B));
@@ -1141,7 +1264,7 @@ static gs_status loss_bwd(gs_context* c, const T* x, const int32_t* labels, cons
                           hipStream_t s) {
     const int B = c->B, d = c->d;
     std::vector<int64_t> koff;
-    GS_TRY(upload_koff(c, s, koff));
+    GS_TRY(host_koff(c, s, koff));
     const int64_t rows = koff[B];
     GS_TRY(cluster_modes(c, s, rows));
     const int64_t m0 = c->m0;
@@ -1167,7 +1290,7 @@ static gs_status loss_bwd(gs_context* c, const T* x, const int32_t* labels, cons
     gs::HeadsOp<uint32_t> op{sk, sperm, X.key, X.start, X.first, P<uint32_t>(c->frows)};
     GS_TRY(run_scan(c, op, nullptr, m0, ctr + 0, s, "scan_heads", m0 * 12.0));
     gs::k_cell_setup<<<blocks_for(rows, 256), 256, 0, s>>>(ctr + 0, m0, X, 0, P<int64_t>(c->rowoff), B, nullptr,
-                                                           P<gs::InstState>(c->state), false);
+                                                           P<gs::InstState>(c->state), false, nullptr, nullptr, 0);
     GS_HIP(hipGetLastError());
     GS_TRY(segsum(c, d, gs::SrcInit{P<double>(c->sums0), sperm, m0}, X, rows, m0, s, 4.0 + 8.0 * d));
     GS_TRY(ensure(c->gmodes, size_t(std::max<int64_t>(rows, 1)) * d * 8));
@@ -1210,9 +1333,9 @@ void gs_context_destroy(gs_context* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     DBuf* all[] = {&c->kA, &c->kB, &c->vA, &c->vB, &c->cell0, &c->kappa, &c->pbuf, &c->gmap, &c->cur, &c->tmap,
-                   &c->part, &c->partc, &c->hk, &c->hv, &c->ckA, &c->ckB, &c->cvA, &c->cvB, &c->param, &c->state,
-                   &c->rowoff, &c->hs, &c->bbox, &c->koff, &c->tiles, &c->counters, &c->look, &c->tilectr, &c->shist,
-                   &c->sdbase, &c->sctr, &c->slook};
+                   &c->part, &c->partc, &c->hk, &c->hv, &c->ckA, &c->ckB, &c->cvA, &c->cvB, &c->ctl,
+                   &c->look, &c->tilectr, &c->shist,
+                   &c->sctr, &c->slook};
     for (DBuf* b : all)
         if (b->p) (void)hipFree(b->p);
     for (int i = 0; i < 2; ++i) {
@@ -1406,11 +1529,10 @@ static gs_status prepare_copy(gs_context* c, hipStream_t s, int64_t* rows) {
     if (!c) return fail(GS_ERR_INVALID_ARG, "null context");
     if (!c->has_result) return fail(GS_ERR_STATE, "the context holds no fit result");
     GS_HIP(hipSetDevice(c->device));
-    std::vector<int64_t> koff(c->B + 1, 0);
-    for (int b = 0; b < c->B; ++b) koff[b + 1] = koff[b] + c->st[b].K;
-    GS_TRY(ensure(c->koff, sizeof(int64_t) * (c->B + 1)));
-    GS_TRY(h2d(c, c->koff.p, koff.data(), sizeof(int64_t) * (c->B + 1), s));
-    *rows = koff[c->B];
+    int64_t rows_total = 0;  // the cluster row offsets are on the device since the fit
+    for (int b = 0; b < c->B; ++b) rows_total += c->st[b].K;
+    (void)s;
+    *rows = rows_total;
     return GS_OK;
 }
 

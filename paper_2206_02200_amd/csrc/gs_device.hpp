@@ -151,6 +151,75 @@ __device__ __forceinline__ uint64_t lb_exclusive_wave(const uint64_t* status, in
     return excl;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves (row
+// shifts by 1, 2, 4, 8 within each 16-lane row, then the row-15 and row-31
+// broadcasts into the later rows), no LDS traffic.  Lanes whose DPP source
+// lies outside the row, or whose row the mask leaves out, add 0.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+    x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x111, 0xf, 0xf, false));  // row_shr:1
+    x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x112, 0xf, 0xf, false));  // row_shr:2
+    x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x114, 0xf, 0xf, false));  // row_shr:4
+    x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x118, 0xf, 0xf, false));  // row_shr:8
+    x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x142, 0xa, 0xf, false));  // row_bcast:15 -> rows 1, 3
+    x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x143, 0xc, 0xf, false));  // row_bcast:31 -> rows 2, 3
+    return x;
+}
+
+// Value of lane (lane ^ S) for a compile-time S: DPP moves for S = 1, 2
+// (quad permutations), 4 (row shifts left / right by 4, picked by lane bit
+// 2) and 8 (row rotation by 8); a cross-lane permute otherwise.
+template <int S>
+__device__ __forceinline__ uint32_t lane_xor_u32(uint32_t x) {
+    if constexpr (S == 1) {
+        return uint32_t(__builtin_amdgcn_update_dpp(int(x), int(x), 0xB1, 0xf, 0xf, false));  // quad_perm 1,0,3,2
+    } else if constexpr (S == 2) {
+        return uint32_t(__builtin_amdgcn_update_dpp(int(x), int(x), 0x4E, 0xf, 0xf, false));  // quad_perm 2,3,0,1
+    } else if constexpr (S == 4) {
+        const uint32_t up = uint32_t(__builtin_amdgcn_update_dpp(int(x), int(x), 0x104, 0xf, 0xf, false));  // row_shl:4
+        const uint32_t dn = uint32_t(__builtin_amdgcn_update_dpp(int(x), int(x), 0x114, 0xf, 0xf, false));  // row_shr:4
+        return (__lane_id() & 4) ? dn : up;
+    } else if constexpr (S == 8) {
+        return uint32_t(__builtin_amdgcn_update_dpp(int(x), int(x), 0x128, 0xf, 0xf, false));  // row_ror:8
+    } else {
+        return uint32_t(__shfl_xor(int(x), S, 64));
+    }
+}
+
+template <int S>
+__device__ __forceinline__ uint64_t lane_xor_u64(uint64_t x) {
+    const uint32_t lo = lane_xor_u32<S>(uint32_t(x));
+    const uint32_t hi = lane_xor_u32<S>(uint32_t(x >> 32));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+// One bitonic compare-exchange step (partner lane ^ STRIDE) of the ascending
+// sort of 64 values over the lanes, within blocks of SIZE.
+template <int SIZE, int STRIDE>
+__device__ __forceinline__ uint64_t bitonic_step_u64(uint64_t v) {
+    const uint64_t o = lane_xor_u64<STRIDE>(v);
+    const int lane = __lane_id();
+    const bool keep_min = ((lane & STRIDE) == 0) == ((lane & SIZE) == 0);
+    return keep_min ? (o < v ? o : v) : (o > v ? o : v);
+}
+
+template <int SIZE, int STRIDE>
+__device__ __forceinline__ uint64_t bitonic_merge_u64(uint64_t v) {
+    v = bitonic_step_u64<SIZE, STRIDE>(v);
+    if constexpr (STRIDE > 1) v = bitonic_merge_u64<SIZE, STRIDE / 2>(v);
+    return v;
+}
+
+// Ascending sort of one value per lane over the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t v) {
+    v = bitonic_merge_u64<2, 1>(v);
+    v = bitonic_merge_u64<4, 2>(v);
+    v = bitonic_merge_u64<8, 4>(v);
+    v = bitonic_merge_u64<16, 8>(v);
+    v = bitonic_merge_u64<32, 16>(v);
+    v = bitonic_merge_u64<64, 32>(v);
+    return v;
+}
+
 // Raise *flag (set it to 1) for every lane with `pred`, with one atomic per
 // distinct flag address in the wave (skipped when the flag is already set):
 // many lanes raising one flag at once would serialise on that address.

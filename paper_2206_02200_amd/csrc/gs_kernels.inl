@@ -43,25 +43,6 @@ __device__ __forceinline__ uint64_t dbits(double v) { return __double_as_longlon
 __device__ __forceinline__ double cell_floor(double v, double h) { return floor(v / h); }
 
 // ===========================================================================
-// state initialisation
-// ===========================================================================
-__global__ void k_init_state(InstState* __restrict__ st, int B, int64_t* __restrict__ bbox, int d,
-                             int64_t* __restrict__ counters, uint32_t* __restrict__ sort_hist) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < kHistCopies * kHistStride) sort_hist[b] = 0;
-    if (b < B) {
-        InstState z = {};
-        z.active = 1;
-        st[b] = z;
-        for (int k = 0; k < d; ++k) {
-            bbox[(int64_t(b) * kMaxDim + k) * 2 + 0] = INT64_MAX;
-            bbox[(int64_t(b) * kMaxDim + k) * 2 + 1] = INT64_MIN;
-        }
-    }
-    if (b < 8) counters[b] = 0;
-}
-
-// ===========================================================================
 // point-tile staging
 // ===========================================================================
 // Rows are cut into tiles that never straddle two instances.  A block walks
@@ -126,13 +107,15 @@ struct Stager {
 // ===========================================================================
 // bbox: per instance and dimension, min/max of floor(fl(x/h))
 // ===========================================================================
-// Each block reduces one tile and merges the result into its instance's box
-// [B][kMaxDim][2] (initialised to INT64_MAX / INT64_MIN) with atomic min/max.
+// Each block reduces one tile and merges the result into one of `ncopies`
+// copies of its instance's box, [B][ncopies][kMaxDim][2] (initialised to
+// INT64_MAX / INT64_MIN), with atomic min/max; spreading the blocks over
+// copies keeps atomics on one address few (the host combines the copies).
 template <typename T, int D>
 __global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict__ x, int64_t ld,
                                                             const RowTile* __restrict__ tiles,
                                                             const double* __restrict__ hs,
-                                                            int64_t* __restrict__ bbox,
+                                                            int64_t* __restrict__ bbox, int ncopies,
                                                             int64_t* __restrict__ counters) {
     using S = Stager<T, D>;
     constexpr int R = S::R;
@@ -211,7 +194,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict_
             const int64_t c = red[ww][tid];
             a = isMin ? (c < a ? c : a) : (c > a ? c : a);
         }
-        int64_t* dst = bbox + int64_t(tl.inst) * 2 * kMaxDim + tid;
+        int64_t* dst = bbox + (int64_t(tl.inst) * ncopies + int(blockIdx.x) % ncopies) * 2 * kMaxDim + tid;
         if (isMin) __hip_atomic_fetch_min(dst, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         else __hip_atomic_fetch_max(dst, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -288,10 +271,14 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__
 }
 
 // ===========================================================================
-// one-pass look-back scan over positions (tile = 4096, wave-striped slots)
+// one-pass look-back scan over positions (tile = 8192, wave-striped slots)
 // ===========================================================================
-constexpr int kScanThreads = 256;
+constexpr int kScanThreads = 512;
 constexpr int kScanItems = kScanTile / kScanThreads;  // 16
+
+// Scan operations: load(p) reads everything position p needs (the kernel
+// issues every load of a thread before any store), value() is its value
+// (< 2^32, and a tile's sum stays below 2^32), emit() writes its results.
 
 // Run heads of a sorted key array: emits the cell table rows and the map
 // member -> cell.
@@ -304,16 +291,27 @@ struct HeadsOp {
     uint32_t* cell_first;    // [m] member at the start of the run
     uint32_t* member_cell;   // [n] member index -> cell id
     static constexpr bool kBinary = true;  // values are 0 or 1
-    __device__ uint32_t value(int64_t p) const { return (p == 0 || key[p] != key[p - 1]) ? 1u : 0u; }
-    __device__ void emit(int64_t p, uint64_t excl, uint32_t v) const {
-        const uint64_t cid = excl + v - 1;
-        const uint32_t mem = perm[p];
-        if (v) {
-            cell_key[cid] = uint64_t(key[p]);
+    struct Item {
+        K key;
+        uint32_t mem;
+        uint32_t head;
+    };
+    __device__ Item load(int64_t p) const {
+        Item it;
+        it.key = key[p];
+        it.head = (p == 0 || it.key != key[p - 1]) ? 1u : 0u;
+        it.mem = perm[p];
+        return it;
+    }
+    __device__ static uint32_t value(const Item& it) { return it.head; }
+    __device__ void emit(int64_t p, uint64_t excl, const Item& it) const {
+        const uint64_t cid = excl + it.head - 1;
+        if (it.head) {
+            cell_key[cid] = uint64_t(it.key);
             cell_start[cid] = uint32_t(p);
-            cell_first[cid] = mem;
+            cell_first[cid] = it.mem;
         }
-        member_cell[mem] = uint32_t(cid);
+        member_cell[it.mem] = uint32_t(cid);
     }
 };
 
@@ -322,8 +320,12 @@ struct ExclOp {
     const uint32_t* in;
     uint32_t* out;
     static constexpr bool kBinary = false;
-    __device__ uint32_t value(int64_t p) const { return in[p]; }
-    __device__ void emit(int64_t p, uint64_t excl, uint32_t) const { out[p] = uint32_t(excl); }
+    struct Item {
+        uint32_t v;
+    };
+    __device__ Item load(int64_t p) const { return Item{in[p]}; }
+    __device__ static uint32_t value(const Item& it) { return it.v; }
+    __device__ void emit(int64_t p, uint64_t excl, const Item&) const { out[p] = uint32_t(excl); }
 };
 
 // n_ptr: device count of positions (read once per block); total: device
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __r
                                                        int64_t* __restrict__ total) {
     constexpr int W = kScanThreads / kWave;
     __shared__ int64_t s_tile;
-    __shared__ uint64_t wtot[W];
+    __shared__ uint32_t wtot[W];
     __shared__ uint64_t s_excl;
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u) - tile_base;
@@ -345,34 +347,35 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __r
     const int64_t t0 = tile * kScanTile;
     if (t0 >= n && tile > 0) return;
 
+    typename Op::Item it[kScanItems];
     uint32_t v[kScanItems];
-    uint64_t incl[kScanItems];
-    uint64_t run = 0;
-    // all values first, so that their loads overlap
+    uint32_t incl[kScanItems];  // tile-local inclusive sums
+    uint32_t run = 0;
+    // all loads first, so that their latency overlaps
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t p = t0 + int64_t(w) * (kWave * kScanItems) + i * kWave + lane;
-        v[i] = p < n ? op.value(p) : 0u;
+        if (p < n) it[i] = op.load(p);
+    }
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t p = t0 + int64_t(w) * (kWave * kScanItems) + i * kWave + lane;
+        v[i] = p < n ? Op::value(it[i]) : 0u;
     }
     if constexpr (Op::kBinary) {  // 0/1 values: prefix counts from ballots
         const uint64_t le = lanemask_lt() | (1ull << lane);
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
             const uint64_t bal = __ballot(v[i] != 0);
-            incl[i] = run + uint64_t(__popcll(bal & le));
-            run += uint64_t(__popcll(bal));
+            incl[i] = run + uint32_t(__popcll(bal & le));
+            run += uint32_t(__popcll(bal));
         }
     } else {
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
-            uint64_t xs = v[i];
-#pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const uint64_t y = __shfl_up(xs, off, kWave);
-                if (lane >= off) xs += y;
-            }
+            const uint32_t xs = wave_incl_scan_u32(v[i]);
             incl[i] = run + xs;
-            run += __shfl(xs, kWave - 1, kWave);
+            run += uint32_t(__builtin_amdgcn_readlane(int(xs), kWave - 1));
         }
     }
     if (lane == 0) wtot[w] = run;
@@ -395,9 +398,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __r
     }
     __syncthreads();
     if (tid == 0) {
-        uint64_t acc = 0;
+        uint32_t acc = 0;
         for (int ww = 0; ww < W; ++ww) {
-            const uint64_t c = wtot[ww];
+            const uint32_t c = wtot[ww];
             wtot[ww] = acc;
             acc += c;
         }
@@ -407,7 +410,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __r
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t p = t0 + int64_t(w) * (kWave * kScanItems) + i * kWave + lane;
-        if (p < n) op.emit(p, base + incl[i] - v[i], v[i]);
+        if (p < n) op.emit(p, base + incl[i] - v[i], it[i]);
     }
 }
 
@@ -418,9 +421,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __r
 // member cell's instance, and flag instances whose round merged cells.
 // With `ranges` it also records each instance's row range [cs, ce) of the
 // new table (the ranges of instances without cells were cleared beforehand).
+// With `cur` / `dk` (a device-wide round follows the binning) it also starts
+// the map initial cell -> current cell (identity) and enters the cells in
+// the dense key table under `epoch`.
 __global__ void k_cell_setup(const int64_t* __restrict__ m_ptr, int64_t npos, CellTable t, int mode,
                              const int64_t* __restrict__ row_off, int B, const int32_t* __restrict__ old_inst,
-                             InstState* __restrict__ st, bool ranges) {
+                             InstState* __restrict__ st, bool ranges, uint32_t* __restrict__ cur,
+                             uint64_t* __restrict__ dk, uint32_t epoch) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t m = *m_ptr;
     bool merged = false;
@@ -441,6 +448,8 @@ __global__ void k_cell_setup(const int64_t* __restrict__ m_ptr, int64_t npos, Ce
             merged = len > 1 && st[b].apply;
         }
         t.inst[c] = b;
+        if (cur) cur[c] = uint32_t(c);
+        if (dk) dk[t.key[c]] = (uint64_t(epoch) << 32) | uint64_t(c);
         if (ranges) {
             if (bp != b) {
                 st[b].cs = c;
@@ -794,10 +803,8 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
 
 // Stop test of the round (Section 2.1 (v)): decides whether each instance
 // applies the shift and merge computed by k_shift.
-__global__ void k_decide(InstState* __restrict__ st, int B, int max_iter) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    InstState s = st[b];
+__device__ inline void decide_state(InstState* __restrict__ sp, int max_iter) {
+    InstState s = *sp;
     s.apply = 0;
     s.changed = 0;
     if (s.active) {
@@ -814,7 +821,12 @@ __global__ void k_decide(InstState* __restrict__ st, int B, int max_iter) {
     s.any_nb = 0;
     s.cs = 0;  // the merge's cell setup records the new table's ranges
     s.ce = 0;
-    st[b] = s;
+    *sp = s;
+}
+
+__global__ void k_decide(InstState* __restrict__ st, int B, int max_iter) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) decide_state(st + b, max_iter);
 }
 
 // Landing keys for the merge sort, with their radix digit histograms;
@@ -865,24 +877,37 @@ __global__ __launch_bounds__(256) void k_merge_prep(CellTable t, int64_t m, cons
 
 // End of a wide round: initial cell -> current cell maps (threads < m0) and
 // the per-instance round count and stationarity (threads < B).
+// With `gate` (a single block holding every instance) it also writes
+// whether some active instance still holds more cells than a tail workgroup.
 __global__ void k_round_end(uint32_t* __restrict__ cur, int64_t m0, const uint32_t* __restrict__ g,
-                            InstState* __restrict__ st, int B, int32_t* __restrict__ applied) {
+                            InstState* __restrict__ st, int B, int32_t* __restrict__ applied,
+                            int64_t* __restrict__ gate) {
+    __shared__ int any;
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gate && threadIdx.x == 0) any = 0;
     if (c < m0) cur[c] = g[cur[c]];
     const int b = int(c);
-    if (c >= B) return;
-    InstState s = st[b];
-    if (applied) applied[b] = s.apply;
-    if (s.apply) {
-        s.t += 1;
-        if (!s.changed) {
-            s.flags |= 2u;  // stationary
-            s.active = 0;
+    bool big = false;
+    if (c < B) {
+        InstState s = st[b];
+        if (applied) applied[b] = s.apply;
+        if (s.apply) {
+            s.t += 1;
+            if (!s.changed) {
+                s.flags |= 2u;  // stationary
+                s.active = 0;
+            }
         }
+        s.apply = 0;
+        s.changed = 0;
+        st[b] = s;
+        big = s.active && s.ce - s.cs > kTailCells;
     }
-    s.apply = 0;
-    s.changed = 0;
-    st[b] = s;
+    if (!gate) return;
+    __syncthreads();
+    if (big) any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) *gate = any;
 }
 
 // ===========================================================================
@@ -908,12 +933,7 @@ constexpr int kMergeIPT = kMergeMax / kMergeThreads;  // 8
 __device__ __forceinline__ uint32_t merge_block_scan(uint32_t v, uint32_t* wtot, uint32_t* total) {
     constexpr int NW = kMergeThreads / kWave;
     const int w = threadIdx.x / kWave, lane = lane_id();
-    uint32_t incl = v;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t y = __shfl_up(incl, off, kWave);
-        if (lane >= off) incl += y;
-    }
+    const uint32_t incl = wave_incl_scan_u32(v);
     if (lane == kWave - 1) wtot[w] = incl;
     __syncthreads();
     uint32_t before = 0, all = 0;
@@ -937,7 +957,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
                                                                uint32_t* __restrict__ mperm,
                                                                uint32_t* __restrict__ cur, int64_t m0,
                                                                uint32_t* __restrict__ gtape,
-                                                               int64_t* __restrict__ counters) {
+                                                               int64_t* __restrict__ counters, int max_iter,
+                                                               uint64_t* __restrict__ dk, uint32_t dk_epoch) {
     constexpr int NW = kMergeThreads / kWave;
     __shared__ uint32_t kbuf[2][kMergeMax];
     __shared__ uint16_t vbuf[2][kMergeMax];
@@ -950,6 +971,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
     const uint64_t lt = lanemask_lt();
     const int mm = int(m);
     for (int i = tid; i < kMergeMaxInst / 32; i += kMergeThreads) chmask[i] = 0;
+    // the round's decision per instance (converged, capped or applying)
+    for (int b = tid; b < B; b += kMergeThreads) decide_state(st + b, max_iter);
+    __syncthreads();
 
     // ---- sort keys and stationarity of applying instances (all loads of a
     // thread are issued before any use)
@@ -1072,6 +1096,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
                 ++cid;
                 hs[cid] = uint16_t(p);
                 u.key[cid] = uint64_t(sk[p]);
+                if (dk) dk[sk[p]] = (uint64_t(dk_epoch) << 32) | uint64_t(cid);
             }
             const int j = sv[p];
             mperm[p] = uint32_t(j);
@@ -1477,17 +1502,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
             // run (binary search in LDS)
             const int nruns = (m + kWave - 1) / kWave;
             uint64_t v = tid < m ? ((kj << 10) | uint64_t(tid)) : ~0ull;
-            if (w < nruns) {
-#pragma unroll
-                for (int size = 2; size <= kWave; size <<= 1) {
-#pragma unroll
-                    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                        const uint64_t o = __shfl_xor((unsigned long long)v, stride, kWave);
-                        const bool keep_min = ((lane & stride) == 0) == ((lane & size) == 0);
-                        v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
-                    }
-                }
-            }
+            if (w < nruns) v = wave_sort_u64(v);
             skey[tid] = v;
             __syncthreads();
             if (w < nruns) {
@@ -1925,8 +1940,31 @@ __global__ void k_loss_mubar(const double* __restrict__ X, int64_t xcap, const i
 constexpr int kLabelBlocks = 2048;
 __global__ __launch_bounds__(256) void k_labels(const uint32_t* __restrict__ cell0, const uint32_t* __restrict__ cur,
                                                 const uint32_t* __restrict__ tmap, int32_t* __restrict__ labels,
-                                                int64_t n, const int64_t* __restrict__ gate) {
+                                                int64_t n, const int64_t* __restrict__ gate,
+                                                const InstState* __restrict__ st, int B, int64_t* __restrict__ koff) {
     if (gate && *gate) return;
+    if (koff && blockIdx.x == 0) {  // first output row of every instance's clusters
+        __shared__ int64_t wt[4];
+        const int w = int(threadIdx.x) / kWave, lane = lane_id();
+        int64_t carry = 0;
+        for (int b0 = 0; b0 < B; b0 += 256) {
+            const int b = b0 + int(threadIdx.x);
+            int64_t x = b < B ? st[b].K : 0;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int64_t y = __shfl_up(x, off, kWave);
+                if (lane >= off) x += y;
+            }
+            if (lane == kWave - 1) wt[w] = x;
+            __syncthreads();
+            int64_t before = carry;
+            for (int ww = 0; ww < w; ++ww) before += wt[ww];
+            if (b < B) koff[b + 1] = before + x;
+            carry += wt[0] + wt[1] + wt[2] + wt[3];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) koff[0] = 0;
+    }
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += 4 * stride) {
         uint32_t c[4];

@@ -12,7 +12,7 @@ namespace gs {
 constexpr int kTailCells = 1024;    // cells one tail workgroup holds in LDS
 constexpr int kTailThreads = 1024;  // one cell per thread
 constexpr int kChunk = 256;         // leaves of one wave's sum subtree (64 lanes x 4)
-constexpr int kScanTile = 4096;     // positions per look-back scan tile
+constexpr int kScanTile = 8192;     // positions per look-back scan tile
 
 // Device pointers of one cell table (struct of arrays with capacity cap).
 struct CellTable {

@@ -1,14 +1,17 @@
 // Stable LSD radix sort of (key, index) pairs, one read and one write of the
 // pairs per 8-bit digit (a single-pass "onesweep" scheme):
 //   * all digit histograms come from one up-front pass (or from the key
-//     producer, which fuses it);
-//   * every pass ranks its 4096-key tile in LDS with wave64 ballots, stably
+//     producer, which fuses it); every tile derives its pass's digit bases
+//     from them, and the first pass clears the other of two histogram
+//     buffers for the next sort;
+//   * every pass ranks its 8192-key tile in LDS with wave64 ballots, stably
 //     (positions ascend with the input order), publishes the tile's digit
 //     counts and finds the counts of all earlier tiles by decoupled look-back;
 //   * the tile is reordered by digit in LDS and written out in digit runs, so
 //     consecutive lanes store consecutive addresses.
-// Tiles take their index from an atomic counter, so a tile only ever waits on
-// tiles that started before it: the look-back always terminates.
+// Tiles take their index from an atomic counter (never reset: the host keeps
+// its value before each launch), so a tile only ever waits on tiles that
+// started before it: the look-back always terminates.
 #include "gs_device.hpp"
 #include "gs_sort.hpp"
 
@@ -29,33 +32,6 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const K* __restrict_
         if (h[i]) atomicAdd(&hc[i], h[i]);
 }
 
-// Exclusive digit bases of every pass from the histogram copies, which are
-// left zeroed for the next sort that accumulates into them; also resets the
-// tile counters.
-__global__ __launch_bounds__(256) void k_sort_bases(uint32_t* __restrict__ hist, uint32_t* __restrict__ dbase,
-                                                    uint32_t* __restrict__ ctr, int npasses) {
-    __shared__ uint32_t s[256];
-    const int t = threadIdx.x;
-    if (t < kSortMaxPasses) ctr[t] = 0;
-    for (int p = 0; p < npasses; ++p) {
-        uint32_t tot = 0;
-        for (int c = 0; c < kHistCopies; ++c) {
-            tot += hist[c * kHistStride + p * 256 + t];
-            hist[c * kHistStride + p * 256 + t] = 0;
-        }
-        s[t] = tot;
-        __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {
-            const uint32_t v = t >= off ? s[t - off] : 0u;
-            __syncthreads();
-            s[t] += v;
-            __syncthreads();
-        }
-        dbase[p * 256 + t] = s[t] - tot;
-        __syncthreads();
-    }
-}
-
 __global__ void k_iota(uint32_t* __restrict__ v, int64_t n) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) v[i] = uint32_t(i);
@@ -74,16 +50,18 @@ __global__ void k_clear_u64(uint64_t* __restrict__ p, int64_t n) {
 constexpr int kSortLookWindow = 4;
 
 template <typename K>
-__global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+__global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                             K* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                            int64_t n, int shift, const uint32_t* __restrict__ dbase,
+                                                            int64_t n, int shift, const uint32_t* __restrict__ hist,
+                                                            uint32_t* __restrict__ clear, int64_t ntiles,
                                                             uint64_t* __restrict__ look, uint32_t* __restrict__ ctr,
-                                                            uint32_t epoch) {
-    constexpr int W = kSortThreads / kWave;
-    static_assert(kSortThreads == 256, "one thread per digit");
+                                                            uint32_t tile_base, uint32_t epoch) {
+    constexpr int W = kPassThreads / kWave;
+    static_assert(kPassThreads >= 256 && kPassThreads % 256 == 0, "threads 0..255 own one digit each");
     __shared__ uint32_t wcnt[W][256];    // per-wave digit counts, then their exclusive scan over waves
     __shared__ uint32_t doff[256];       // tile-local exclusive digit offsets
-    __shared__ uint32_t wsum[W];         // per-wave totals of the digit scan
+    __shared__ uint32_t wsum[4];         // per-wave totals of the digit scan (waves 0..3)
+    __shared__ uint32_t hsum[4];         // per-wave totals of the histogram scan (waves 0..3)
     __shared__ uint32_t gbase[256];      // global position of the tile's first key of each digit
     __shared__ K skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
@@ -92,11 +70,24 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict_
     const int tid = threadIdx.x;
     const int w = tid / kWave;
     const int lane = lane_id();
-    if (tid == 0) s_tile = atomicAdd(ctr, 1u);
-    for (int i = tid; i < W * 256; i += kSortThreads) (&wcnt[0][0])[i] = 0;
+    if (tid == 0) s_tile = int64_t(atomicAdd(ctr, 1u) - tile_base);
+    for (int i = tid; i < W * 256; i += kPassThreads) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t tile = s_tile;
     const int64_t t0 = tile * kSortTile;
+    // the pass's count of digit tid over all keys (its histogram copies),
+    // loaded now and scanned over the digits after the ranking
+    uint32_t dtot = 0;
+    if (tid < 256) {
+#pragma unroll
+        for (int c = 0; c < kHistCopies; ++c) dtot += hist[c * kHistStride + tid];
+    }
+    if (clear) {  // this tile's slice of the other histogram buffer
+        const int64_t total = int64_t(kHistCopies) * kHistStride;
+        const int64_t per = (total + ntiles - 1) / ntiles;
+        const int64_t z1 = (tile + 1) * per < total ? (tile + 1) * per : total;
+        for (int64_t i = tile * per + tid; i < z1; i += kPassThreads) clear[i] = 0;
+    }
 
     // Load: wave w owns keys [w*64*ITEMS, (w+1)*64*ITEMS) of the tile, slot i
     // covers 64 consecutive keys, so (slot, lane) order is input order.
@@ -141,30 +132,39 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict_
 
     // Scan the per-wave counts over waves (digit = thread) and publish the
     // tile total for the look-back at once, so that later tiles can use it.
+    const bool dig = tid < 256;
     uint32_t run = 0;  // this tile's count of digit tid
     uint64_t* st = look + tile * 256 + tid;
+    if (dig) {
 #pragma unroll
-    for (int ww = 0; ww < W; ++ww) {
-        const uint32_t c = wcnt[ww][tid];
-        wcnt[ww][tid] = run;
-        run += c;
-    }
-    lb_store(st, lb_pack(epoch, tile == 0 ? kFlagPrefix : kFlagAgg, run));
-    // tile-local exclusive scan over the 256 digit totals (digit = thread):
-    // within each wave by shuffles, then across the waves' totals
-    {
-        uint32_t incl = run;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += y;
+        for (int ww = 0; ww < W; ++ww) {
+            const uint32_t c = wcnt[ww][tid];
+            wcnt[ww][tid] = run;
+            run += c;
         }
-        if (lane == kWave - 1) wsum[w] = incl;
+        lb_store(st, lb_pack(epoch, tile == 0 ? kFlagPrefix : kFlagAgg, run));
+    }
+    // tile-local exclusive scan over the 256 digit totals and global one over
+    // the pass's digit counts (digit = thread): within each of waves 0..3 by
+    // shuffles, then across their totals
+    uint32_t dbase = 0;  // keys of all smaller digits in the whole pass
+    {
+        const uint32_t incl = wave_incl_scan_u32(run), hincl = wave_incl_scan_u32(dtot);
+        if (dig && lane == kWave - 1) {
+            wsum[w] = incl;
+            hsum[w] = hincl;
+        }
         __syncthreads();
-        uint32_t before = 0;
+        if (dig) {
+            uint32_t before = 0, hbefore = 0;
 #pragma unroll
-        for (int ww = 0; ww < W; ++ww) before += ww < w ? wsum[ww] : 0u;
-        doff[tid] = before + incl - run;
+            for (int ww = 0; ww < 4; ++ww) {
+                before += ww < w ? wsum[ww] : 0u;
+                hbefore += ww < w ? hsum[ww] : 0u;
+            }
+            doff[tid] = before + incl - run;
+            dbase = hbefore + hincl - dtot;
+        }
     }
     __syncthreads();
 
@@ -181,19 +181,21 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict_
         }
     }
     // Exclusive prefix of digit tid over all earlier tiles (decoupled
-    // look-back, 32 predecessors per round trip), then this tile's prefix.
-    if (tile == 0) {
-        gbase[tid] = dbase[tid];
-    } else {
-        const uint64_t excl = lb_exclusive<kSortLookWindow>(look + tid, tile, 256, epoch);
-        lb_store(st, lb_pack(epoch, kFlagPrefix, excl + run));
-        gbase[tid] = dbase[tid] + uint32_t(excl);
+    // look-back, kSortLookWindow predecessors per round trip), then this tile's prefix.
+    if (dig) {
+        if (tile == 0) {
+            gbase[tid] = dbase;
+        } else {
+            const uint64_t excl = lb_exclusive<kSortLookWindow>(look + tid, tile, 256, epoch);
+            lb_store(st, lb_pack(epoch, kFlagPrefix, excl + run));
+            gbase[tid] = dbase + uint32_t(excl);
+        }
     }
     __syncthreads();
 
     // Write out: entry j of the reordered tile goes to gbase[digit] + (j - doff[digit]).
     const int64_t cnt = (n - t0) < kSortTile ? (n - t0) : kSortTile;
-    for (int j = tid; j < cnt; j += kSortThreads) {
+    for (int j = tid; j < cnt; j += kPassThreads) {
         const K k = skey[j];
         const uint32_t dgt = uint32_t(k >> shift) & 255u;
         const uint32_t g = gbase[dgt] + (uint32_t(j) - doff[dgt]);
@@ -215,15 +217,16 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
     }
     const int64_t tiles = sort_look_tiles(n);
     if (tiles > sc.look_tiles) return hipErrorInvalidValue;
+    uint32_t* hcur = sc.hist + int64_t(sc.parity) * kHistCopies * kHistStride;
+    uint32_t* hother = sc.hist + int64_t(sc.parity ^ 1) * kHistCopies * kHistStride;
     if (!hist_ready) {
-        k_clear_u32<<<dim3(kSortMaxPasses * kHistCopies), dim3(256), 0, s>>>(sc.hist, kHistCopies * kHistStride);
+        k_clear_u32<<<dim3(kSortMaxPasses * kHistCopies), dim3(256), 0, s>>>(hcur, kHistCopies * kHistStride);
         int64_t blocks = (n + kSortThreads * 16 - 1) / (kSortThreads * 16);
         if (blocks > 2048) blocks = 2048;
         const int tk = sc.prof_begin ? sc.prof_begin(sc.prof_ctx, s, "sort_hist") : -1;
-        k_sort_hist<K><<<dim3(unsigned(blocks)), dim3(kSortThreads), 0, s>>>(kA, n, np, sc.hist);
+        k_sort_hist<K><<<dim3(unsigned(blocks)), dim3(kSortThreads), 0, s>>>(kA, n, np, hcur);
         if (sc.prof_end) sc.prof_end(sc.prof_ctx, s, tk, double(n) * sizeof(K));
     }
-    k_sort_bases<<<1, 256, 0, s>>>(sc.hist, sc.dbase, sc.ctr, np);
     K* ki = kA;
     K* ko = kB;
     uint32_t* vi = nullptr;
@@ -234,11 +237,16 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
                 sc.look, sc.look_tiles * 256);
             sc.epoch = 0;
         }
+        if (sc.tile_base + uint64_t(tiles) >= 0x7fffffffull) {  // first use, or the counter nears overflow
+            k_clear_u32<<<dim3(1), dim3(64), 0, s>>>(sc.ctr, 1);
+            sc.tile_base = 0;
+        }
         const uint32_t ep = ++sc.epoch;
+        const uint32_t base = uint32_t(sc.tile_base);
+        sc.tile_base += uint64_t(tiles);
         const int tk = sc.prof_begin ? sc.prof_begin(sc.prof_ctx, s, "sort_pass") : -1;
-        k_sort_pass<K><<<dim3(unsigned(tiles)), dim3(kSortThreads), 0, s>>>(ki, vi, ko, vo, n, 8 * p,
-                                                                            sc.dbase + p * 256, sc.look,
-                                                                            sc.ctr + p, ep);
+        k_sort_pass<K><<<dim3(unsigned(tiles)), dim3(kPassThreads), 0, s>>>(
+            ki, vi, ko, vo, n, 8 * p, hcur + p * 256, p == 0 ? hother : nullptr, tiles, sc.look, sc.ctr, base, ep);
         // reads keys (and values after the first pass), writes keys and values
         if (sc.prof_end)
             sc.prof_end(sc.prof_ctx, s, tk, double(n) * (sizeof(K) + (p ? 4 : 0) + sizeof(K) + 4));
@@ -248,9 +256,12 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
         vi = vo;
         vo = (vo == vA) ? vB : vA;
     }
+    sc.parity ^= 1;  // the next producer accumulates into the buffer cleared above
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) sc.tile_base = 0x7fffffffull;  // counter state unknown: clear it before the next use
     *kout = ki;
     *vout = vi;
-    return hipGetLastError();
+    return e;
 }
 
 template hipError_t radix_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, int, bool,

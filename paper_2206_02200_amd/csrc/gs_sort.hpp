@@ -6,12 +6,14 @@
 
 namespace gs {
 
-constexpr int kSortThreads = 256;                        // 4 waves
+constexpr int kSortThreads = 256;                        // histogram kernel block
+constexpr int kPassThreads = 512;                        // one sort-pass tile: 8 waves
 constexpr int kSortItems = 16;                           // keys per thread
-constexpr int kSortTile = kSortThreads * kSortItems;     // 4096 keys per tile
+constexpr int kSortTile = kPassThreads * kSortItems;     // 8192 keys per tile
 constexpr int kSortMaxPasses = 8;                        // 8-bit digits, up to 64 bits
 constexpr int kHistCopies = 16;                          // histogram copies that producers spread atomics over
 constexpr int kHistStride = kSortMaxPasses * 256;        // entries of one copy
+constexpr int64_t kHistEntries = 2 * kHistCopies * kHistStride;  // both histogram buffers
 
 // Optional timing hooks: begin returns a token (or -1), end closes it with the
 // algorithmic bytes the launch had to move.
@@ -19,9 +21,14 @@ typedef int (*ProfBeginFn)(void* ctx, hipStream_t s, const char* name);
 typedef void (*ProfEndFn)(void* ctx, hipStream_t s, int token, double bytes);
 
 struct SortScratch {
-    uint32_t* hist = nullptr;   // [kHistCopies][kSortMaxPasses][256] digit histograms (summed over copies)
-    uint32_t* dbase = nullptr;  // [kSortMaxPasses][256] exclusive digit bases
-    uint32_t* ctr = nullptr;    // [kSortMaxPasses] tile counters
+    // [2][kHistCopies][kSortMaxPasses][256] digit histograms (summed over the
+    // copies), two buffers: producers accumulate into buffer `parity`, which
+    // is zero beforehand; a sort reads it and clears the other one
+    uint32_t* hist = nullptr;
+    int parity = 0;
+    uint32_t* cur_hist() const { return hist + int64_t(parity) * kHistCopies * kHistStride; }
+    uint32_t* ctr = nullptr;    // tile ticket counter
+    uint64_t tile_base = 0x7fffffffull;  // its value before the next pass (>= 2^31 - 1: clear it first)
     uint64_t* look = nullptr;   // [tiles][256] look-back status words
     int64_t look_tiles = 0;     // capacity of `look` in tiles
     uint32_t epoch = 0;         // last epoch used in `look`
@@ -37,8 +44,8 @@ inline int64_t sort_look_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTi
 
 // Sort n pairs by the low `bits` bits of the key, stably.  The keys are in
 // kA; the values are implicitly 0..n-1.  kB, vA, vB are ping-pong buffers of
-// n entries.  If `hist_ready`, sc.hist already holds the digit histograms of
-// kA for every pass (computed by the key producer).  On return *kout/*vout
+// n entries.  If `hist_ready`, histogram buffer sc.parity already holds the
+// digit histograms of kA for every pass (computed by the key producer).  On return *kout/*vout
 // point at the sorted keys and the permutation (inside kA/kB, vA/vB).
 template <typename K>
 hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int bits, bool hist_ready,

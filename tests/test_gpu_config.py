@@ -126,3 +126,19 @@ def test_configuration_errors():
     assert gridshift._lib.gs_context_set_config(ctx.handle, 7, 1) == 1  # unknown key
     assert ctx.config() == {"merge_small": 1, "tile_chunks": 4, "dense_table": 1}
     ctx.close()
+
+
+def test_context_reuse_across_inputs():
+    # One context fits several different inputs in a row; state a fit leaves
+    # behind (dense-table epochs, histogram buffers, tile counters) must never
+    # leak into the next one.
+    seq = [CASES[0], CASES[2], CASES[1], CASES[0]]
+    ctx = gridshift.Context(0)
+    for name, x, h, dtype in seq:
+        x = x.astype(dtype)
+        o = gs_oracle.fit(x.astype(np.float64), h, 100)
+        r = gridshift.fit(torch.from_numpy(x).to(DEV), h, 100, ctx=ctx, with_sums=True)
+        assert (r.info["n_clusters"], r.info["n_iter"], r.info["flags"]) == (o.K, o.n_iter, o.flags), name
+        np.testing.assert_array_equal(r.labels.cpu().numpy(), o.labels, err_msg=name)
+        np.testing.assert_array_equal(_bits(r.sums.cpu().numpy()), _bits(o.sums), err_msg=name)
+    ctx.close()
