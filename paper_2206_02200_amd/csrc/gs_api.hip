@@ -625,11 +625,15 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     const int np = gs::sort_passes(bits);
     if (c->ntiles > 0) {  // the current histogram buffer is zero (cleared by the previous sort)
         const unsigned g = unsigned(c->ntiles);
+        const unsigned ksplit = 1;
         const gs::RowTile* tl = P<gs::RowTile>(c->tiles);
         const int tk = prof_begin(c, s, "make_keys");
         switch (d) {
 #define GS_MK(D) \
-    case D: gs::k_make_keys<T, K, D><<<g, gs::kBoxThreads, 0, s>>>(x, ld, tl, prm, P<K>(c->kA), np, c->sort.cur_hist()); break;
+    case D:                                                                                                    \
+        gs::k_make_keys<T, K, D><<<g * ksplit, gs::kBoxThreads, 0, s>>>(x, ld, tl, prm, P<K>(c->kA), np,        \
+                                                                        c->sort.cur_hist(), ksplit);            \
+        break;
             GS_MK(1) GS_MK(2) GS_MK(3) GS_MK(4) GS_MK(5) GS_MK(6)
 #undef GS_MK
             default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
@@ -1143,6 +1147,7 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
     std::vector<int64_t> box(size_t(B) * gs::kMaxDim * 2, 0);
     if (N > 0) {
         const unsigned g = unsigned(tiles.size());
+        const unsigned bsplit = 1;
         const double xb = double(N) * d * (dtype == GS_F32 ? 4.0 : 8.0);
         const gs::RowTile* tl = P<gs::RowTile>(c->tiles);
         const double* hsd = P<double>(c->hs);
@@ -1153,9 +1158,11 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
         const int tk = prof_begin(c, s, "bbox");
         switch (d * 2 + (dtype == GS_F32 ? 0 : 1)) {
 #define GS_BB(D)                                                                                               \
-    case 2 * D: gs::k_bbox_tiles<float, D><<<g, gs::kBoxThreads, 0, s>>>(xf, ld, tl, hsd, bp, nbc, cn); break; \
+    case 2 * D:                                                                                                \
+        gs::k_bbox_tiles<float, D><<<g * bsplit, gs::kBoxThreads, 0, s>>>(xf, ld, tl, hsd, bp, nbc, cn, bsplit); \
+        break;                                                                                                 \
     case 2 * D + 1:                                                                                            \
-        gs::k_bbox_tiles<double, D><<<g, gs::kBoxThreads, 0, s>>>(xd, ld, tl, hsd, bp, nbc, cn);               \
+        gs::k_bbox_tiles<double, D><<<g * bsplit, gs::kBoxThreads, 0, s>>>(xd, ld, tl, hsd, bp, nbc, cn, bsplit); \
         break;
             GS_BB(1) GS_BB(2) GS_BB(3) GS_BB(4) GS_BB(5) GS_BB(6)
 #undef GS_BB

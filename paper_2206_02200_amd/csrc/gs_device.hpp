@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace gs {
@@ -39,6 +40,9 @@ struct InstState {
     int64_t K;        // clusters at exit
     int64_t m0;       // cells after binning
 };
+// the shift reads any_nb and changed with one 64-bit load
+static_assert(offsetof(InstState, any_nb) % 8 == 0 && offsetof(InstState, changed) == offsetof(InstState, any_nb) + 4,
+              "any_nb and changed share one aligned 64-bit word");
 
 // ---------------------------------------------------------------------------
 // wave helpers
@@ -50,19 +54,48 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// Perfect binary tree over the 64 lane values (lane l holds leaf l): after the
-// loop lane 0 holds ((v0+v1)+(v2+v3))+... with the pairing of R.  Missing
-// leaves must hold -0.0, the exact additive identity.
+// Lane l + S of the same 16-lane row (DPP row_shl:S, S = 1, 2, 4 or 8) for a
+// 64-bit value; lanes whose source lies past the row end keep their own.
+template <int S>
+__device__ __forceinline__ uint64_t row_down_u64(uint64_t x) {
+    const int lo = int(uint32_t(x)), hi = int(uint32_t(x >> 32));
+    const uint32_t nlo = uint32_t(__builtin_amdgcn_update_dpp(lo, lo, 0x100 + S, 0xf, 0xf, false));
+    const uint32_t nhi = uint32_t(__builtin_amdgcn_update_dpp(hi, hi, 0x100 + S, 0xf, 0xf, false));
+    return (uint64_t(nhi) << 32) | nlo;
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x)), l));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x >> 32)), l));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+// Perfect binary tree over the 64 lane values (lane l holds leaf l), with the
+// pairing of R: pairs (l, l + 1), then pairs of pairs, ... each level adding
+// the left block's value to the right block's in that order (DPP row shifts
+// within each 16-lane row, then the four row totals read out as
+// (r0 + r1) + (r2 + r3)).  Missing leaves must hold -0.0, the exact additive
+// identity.  Every lane returns the total.
 __device__ __forceinline__ double wave_tree_sum(double v) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) v = v + __shfl_down(v, off, kWave);
-    return v;
+    v = v + __longlong_as_double((long long)row_down_u64<1>(uint64_t(__double_as_longlong(v))));
+    v = v + __longlong_as_double((long long)row_down_u64<2>(uint64_t(__double_as_longlong(v))));
+    v = v + __longlong_as_double((long long)row_down_u64<4>(uint64_t(__double_as_longlong(v))));
+    v = v + __longlong_as_double((long long)row_down_u64<8>(uint64_t(__double_as_longlong(v))));
+    const uint64_t bv = uint64_t(__double_as_longlong(v));
+    const double r0 = __longlong_as_double((long long)readlane_u64(bv, 0));
+    const double r1 = __longlong_as_double((long long)readlane_u64(bv, 16));
+    const double r2 = __longlong_as_double((long long)readlane_u64(bv, 32));
+    const double r3 = __longlong_as_double((long long)readlane_u64(bv, 48));
+    return (r0 + r1) + (r2 + r3);
 }
 
 __device__ __forceinline__ int64_t wave_tree_sum_i64(int64_t v) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) v = v + __shfl_down(v, off, kWave);
-    return v;
+    v = v + int64_t(row_down_u64<1>(uint64_t(v)));
+    v = v + int64_t(row_down_u64<2>(uint64_t(v)));
+    v = v + int64_t(row_down_u64<4>(uint64_t(v)));
+    v = v + int64_t(row_down_u64<8>(uint64_t(v)));
+    return (int64_t(readlane_u64(uint64_t(v), 0)) + int64_t(readlane_u64(uint64_t(v), 16))) +
+           (int64_t(readlane_u64(uint64_t(v), 32)) + int64_t(readlane_u64(uint64_t(v), 48)));
 }
 
 // ---------------------------------------------------------------------------

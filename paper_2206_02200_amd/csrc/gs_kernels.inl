@@ -68,6 +68,22 @@ struct RowTile {
     int32_t pad;
 };
 
+// Rows of part `blockIdx.x % split` of tile `blockIdx.x / split`: the tile's
+// chunks of R rows shared out evenly over `split` workgroups.
+__device__ inline RowTile tile_part(const RowTile* __restrict__ tiles, int split, int R) {
+    RowTile tl = tiles[blockIdx.x / split];
+    if (split > 1) {
+        const int part = int(blockIdx.x % split);
+        const int64_t nc = (tl.r1 - tl.r0 + R - 1) / R;
+        const int64_t c0 = nc * part / split, c1 = nc * (part + 1) / split;
+        const int64_t r1 = tl.r0 + c1 * R;
+        tl.r0 += c0 * R;
+        tl.r1 = r1 < tl.r1 ? r1 : tl.r1;
+        if (tl.r0 > tl.r1) tl.r0 = tl.r1;
+    }
+    return tl;
+}
+
 template <typename T, int D>
 struct Stager {
     static constexpr int R = chunk_rows(D, int(sizeof(T)));
@@ -116,20 +132,23 @@ __global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict_
                                                             const RowTile* __restrict__ tiles,
                                                             const double* __restrict__ hs,
                                                             int64_t* __restrict__ bbox, int ncopies,
-                                                            int64_t* __restrict__ counters) {
+                                                            int64_t* __restrict__ counters, int split) {
     using S = Stager<T, D>;
     constexpr int R = S::R;
     constexpr int RPT = R / kBoxThreads;
     __shared__ T stage[R * D];
     __shared__ int64_t red[kBoxThreads / kWave][2 * D];
-    const RowTile tl = tiles[blockIdx.x];
+    const RowTile tl = tile_part(tiles, split, R);
+    if (tl.r0 >= tl.r1) return;
     const double h = hs[tl.inst];
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-    int64_t mn[D], mx[D];
+    // running min / max of the cell coordinates as doubles: they are integers
+    // below 2^52 in magnitude (checked), so binary64 min/max are exact
+    double mnd[D], mxd[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        mn[k] = INT64_MAX;
-        mx[k] = INT64_MIN;
+        mnd[k] = 4503599627370496.0;
+        mxd[k] = -4503599627370496.0;
     }
     int err = 0;
     S sg;
@@ -158,14 +177,19 @@ __global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict_
                     err |= 2;
                     continue;
                 }
-                const int64_t qi = int64_t(q);
-                mn[k] = qi < mn[k] ? qi : mn[k];
-                mx[k] = qi > mx[k] ? qi : mx[k];
+                mnd[k] = fmin(mnd[k], q);
+                mxd[k] = fmax(mxd[k], q);
             }
         }
         __syncthreads();  // every row read before the next chunk is stored
         c0 = n0;
         crows = nrows;
+    }
+    int64_t mn[D], mx[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        mn[k] = mnd[k] <= mxd[k] ? int64_t(mnd[k]) : INT64_MAX;  // no finite row: empty box
+        mx[k] = mnd[k] <= mxd[k] ? int64_t(mxd[k]) : INT64_MIN;
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -208,14 +232,15 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__
                                                            const RowTile* __restrict__ tiles,
                                                            const InstParam* __restrict__ param,
                                                            K* __restrict__ keys, int npasses,
-                                                           uint32_t* __restrict__ hist) {
+                                                           uint32_t* __restrict__ hist, int split) {
     using S = Stager<T, D>;
     constexpr int R = S::R;
     constexpr int RPT = R / kBoxThreads;
     __shared__ T stage[R * D];
     __shared__ uint32_t hl[kSortMaxPasses * 256];
     __shared__ InstParam sp;
-    const RowTile tl = tiles[blockIdx.x];
+    const RowTile tl = tile_part(tiles, split, R);
+    if (tl.r0 >= tl.r1) return;
     const int tid = threadIdx.x, lane = lane_id();
     for (int i = tid; i < npasses * 256; i += kBoxThreads) hl[i] = 0;
     if (tid == 0) sp = param[tl.inst];
@@ -234,13 +259,25 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
             const int r = tid + i * kBoxThreads;
-            uint64_t key = sp.base;
+            if constexpr (sizeof(K) == 4) {
+                // the whole key is below 2^32, so is every term: 32-bit
+                // arithmetic, with q - lo exact in binary64 and below 2^32
+                uint32_t key = uint32_t(sp.base);
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const double q = cell_floor(double(stage[(r < crows ? r : 0) * D + k]), hh);
-                key += uint64_t(int64_t(q) - sp.lo[k]) * sp.stride[k];
+                for (int k = 0; k < D; ++k) {
+                    const double q = cell_floor(double(stage[(r < crows ? r : 0) * D + k]), hh);
+                    key += uint32_t(q - double(sp.lo[k])) * uint32_t(sp.stride[k]);
+                }
+                kv[i] = K(key);
+            } else {
+                uint64_t key = sp.base;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double q = cell_floor(double(stage[(r < crows ? r : 0) * D + k]), hh);
+                    key += uint64_t(int64_t(q) - sp.lo[k]) * sp.stride[k];
+                }
+                kv[i] = K(key);
             }
-            kv[i] = K(key);
             if (r < crows) keys[c0 + r] = kv[i];
         }
         // digit histograms: one LDS atomic per wave when all its lanes share
@@ -731,6 +768,9 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
     if (!st[b].active) return;
     const InstParam& P = param[b];
     const uint64_t key = t.key[j];
+    // the cell's own count and sum, for the stationarity test at the end
+    const int64_t own_cnt = t.cnt[j];
+    const double own_sum = lane < D ? t.sum[int64_t(lane) * t.cap + j] : 0.0;
     const uint64_t local = key - P.base;
     int64_t crd[D];
 #pragma unroll
@@ -780,11 +820,13 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
         for (int q = 0; q < nfound; ++q) W += t.cnt[list[w][q]];
     }
     W = __shfl(W, D, kWave);
-    bool bad = false;
+    bool bad = false, chg = false;
     uint64_t term = 0;
     if (lane < D) {
         const double p = acc / double(W);
         pbuf[int64_t(lane) * t.cap + j] = p;
+        // stationarity: the cell's merge value C_j * p_j against its sum
+        chg = dbits(double(own_cnt) * p) != dbits(own_sum);
         const double q = cell_floor(p, P.h);
         const double rel = q - double(P.lo[lane]);
         bad = !(rel >= 0.0 && rel < double(P.E[lane]));
@@ -792,11 +834,19 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
     }
 #pragma unroll
     for (int off = 1; off < 8; off <<= 1) term += __shfl_xor((unsigned long long)term, off, kWave);
+    const bool moved = __ballot(chg) != 0 || P.base + term != key;  // wave-uniform
     if (lane == 0) {
         kappa[j] = P.base + term;
         if (Wout) Wout[j] = int32_t(W);
-        if (nfound > 1 && __hip_atomic_load(&st[b].any_nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-            atomicOr(&st[b].any_nb, 1);
+        // instance flags: some cell has a neighbour; the round changes the
+        // table (used only if the instance applies it).  One coherent read of
+        // both, and an atomic only while a flag is still clear.
+        if (nfound > 1 || moved) {
+            const uint64_t both = __hip_atomic_load(reinterpret_cast<uint64_t*>(&st[b].any_nb), __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+            if (nfound > 1 && uint32_t(both) == 0) atomicOr(&st[b].any_nb, 1);
+            if (moved && uint32_t(both >> 32) == 0) atomicOr(&st[b].changed, 1);
+        }
     }
     if (__ballot(bad) && lane == 0) atomicOr(&st[b].err, 3);  // GS_ERR_KEY_RANGE
 }
@@ -805,8 +855,7 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
 // applies the shift and merge computed by k_shift.
 __device__ inline void decide_state(InstState* __restrict__ sp, int max_iter) {
     InstState s = *sp;
-    s.apply = 0;
-    s.changed = 0;
+    s.apply = 0;  // (changed was raised by this round's shift; the round end clears it)
     if (s.active) {
         if (!s.any_nb) {
             s.flags |= 1u;  // converged
@@ -846,15 +895,7 @@ __global__ __launch_bounds__(256) void k_merge_prep(CellTable t, int64_t m, cons
     const int b = t.inst[j];
     const uint64_t key = t.key[j];
     K out = K(key);
-    bool chg = false;
-    if (stc[b].apply) {
-        const uint64_t kap = kappa[j];
-        out = K(kap);
-        chg = valid && kap != key;
-        const double C = double(t.cnt[j]);
-        for (int k = 0; k < d; ++k) chg = chg || dbits(C * pbuf[k * t.cap + j]) != dbits(t.sum[k * t.cap + j]);
-    }
-    wave_flag_or(&st[b].changed, chg);
+    if (stc[b].apply) out = K(kappa[j]);
     if (valid) skey[j] = out;
     const uint64_t act = __ballot(valid);
     if (act) {
@@ -975,12 +1016,13 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
     for (int b = tid; b < B; b += kMergeThreads) decide_state(st + b, max_iter);
     __syncthreads();
 
-    // ---- sort keys and stationarity of applying instances (all loads of a
-    // thread are issued before any use)
+    // ---- sort keys: landing key for cells of applying instances, own key
+    // otherwise (the shift already flagged instances whose cells moved or
+    // whose merge values differ from their sums); all loads of a thread are
+    // issued before any use
     {
         int bi[kMergeIPT];
         uint64_t key[kMergeIPT], kap[kMergeIPT];
-        int64_t cnt[kMergeIPT];
         int ap[kMergeIPT];
 #pragma unroll
         for (int i = 0; i < kMergeIPT; ++i) {
@@ -988,7 +1030,6 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
             bi[i] = t.inst[j];
             key[i] = t.key[j];
             kap[i] = kappa[j];  // read for every cell, used for applying instances only
-            cnt[i] = t.cnt[j];
         }
 #pragma unroll
         for (int i = 0; i < kMergeIPT; ++i) ap[i] = st[bi[i]].apply;
@@ -997,17 +1038,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
         for (int i = 0; i < kMergeIPT; ++i) {
             const int j = tid + i * kMergeThreads;
             if (j >= mm) continue;
-            uint64_t out = key[i];
-            if (ap[i]) {
-                out = kap[i];
-                bool chg = kap[i] != key[i];
-                const double C = double(cnt[i]);
-#pragma unroll
-                for (int k = 0; k < D; ++k)
-                    chg = chg || dbits(C * pbuf[k * t.cap + j]) != dbits(t.sum[k * t.cap + j]);
-                if (chg) atomicOr(&chmask[bi[i] >> 5], 1u << (bi[i] & 31));
-            }
-            kbuf[0][j] = uint32_t(out);
+            kbuf[0][j] = uint32_t(ap[i] ? kap[i] : key[i]);
             vbuf[0][j] = uint16_t(j);
         }
     }
@@ -1026,6 +1057,12 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
 #pragma unroll
         for (int i = 0; i < kMergeIPT; ++i) {
             const int pos = w * (kWave * kMergeIPT) + i * kWave + lane;
+            if (w * (kWave * kMergeIPT) + i * kWave >= mm) {  // the whole slot is past the end
+                kk[i] = 0u;
+                vv[i] = 0;
+                rk[i] = 0u;
+                continue;
+            }
             const bool valid = pos < mm;
             kk[i] = valid ? kbuf[src][pos] : 0u;
             vv[i] = valid ? vbuf[src][pos] : uint16_t(0);
@@ -1410,7 +1447,9 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         if (tid < 3) s_flag[(round + 1) & 1][tid] = 0;
         // ---- shift (one cell per thread)
         bool nb = false, bad = false;
+        bool chg = false;  // stationarity: landing key or merge value differs from the cell's own
         double p[D];
+        double val[D];
         int32_t q[D];
         uint64_t kj = 0;
         int32_t Wj = 0;
@@ -1464,6 +1503,14 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
                 q[dd] = int32_t(int64_t(qq) - s_lo[dd]);
                 kj += uint64_t(int64_t(qq) - s_lo[dd]) * s_stride[dd];
             }
+            // merge values and stationarity (own cell only: nothing writes it
+            // before the scatter below)
+            chg = kj != lkey[tid];
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) {
+                val[dd] = double(cnt[tid]) * p[dd];
+                chg = chg || dbits(val[dd]) != dbits(sm[dd][tid]);
+            }
         }
         if (__ballot(nb) && lane == 0) atomicOr(&flg[0], 1);
         if (__ballot(bad) && lane == 0) atomicOr(&flg[1], 1);
@@ -1480,19 +1527,11 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
             err = 3;
             break;
         }
-        // ---- merge values, stationarity, landing keys
-        bool chg = false;
-        double val[D];
-        if (tid < m) {
-            chg = kj != lkey[tid];
-#pragma unroll
-            for (int dd = 0; dd < D; ++dd) {
-                val[dd] = double(cnt[tid]) * p[dd];
-                chg = chg || dbits(val[dd]) != dbits(sm[dd][tid]);
-            }
-            kap[tid] = kj;
+        // ---- landing keys (read by the linear rank only)
+        if (!fast_rank) {
+            if (tid < m) kap[tid] = kj;
+            __syncthreads();
         }
-        __syncthreads();
         // ---- stable rank by (landing key, old index)
         int rank = 0;
         if (fast_rank) {
@@ -1503,8 +1542,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
             const int nruns = (m + kWave - 1) / kWave;
             uint64_t v = tid < m ? ((kj << 10) | uint64_t(tid)) : ~0ull;
             if (w < nruns) v = wave_sort_u64(v);
-            skey[tid] = v;
-            __syncthreads();
+            if (nruns > 1) {  // other waves' runs are read below
+                skey[tid] = v;
+                __syncthreads();
+            }
             if (w < nruns) {
                 int r = lane;
                 for (int rr = 0; rr < nruns; ++rr) {
