@@ -16,9 +16,12 @@ carries, under "forms", the other two forms of the workload family:
            h in {12, 16, 24}, one gs_fit_batched call;
   fwd_bwd  64 Voronoi images of 512x512, (x, y, L, a, b) float32, h = 16:
            the point-to-mode loss and its gradient (fit with checkpoints
-           every 8 tail rounds, loss, backward with segment recomputation).
+           every 8 tail rounds, loss, backward with segment recomputation);
+  gmm      Gaussian mixtures of 10^7 float32 points, 50 components, h = 4,
+           d = 2..6: the cost of the 3^d neighbour gather per dimension.
+The plain form also reports its time per phase (binning, rounds, labels).
 
-  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--forms plain,batched,fwd_bwd]
+  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--forms plain,batched,fwd_bwd,gmm]
 """
 from __future__ import annotations
 
@@ -105,7 +108,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,batched,fwd_bwd")
+    ap.add_argument("--forms", default="plain,batched,fwd_bwd,gmm")
     ap.add_argument("--form-only", choices=["batched", "fwd_bwd"], default=None,
                     help="time only this form (--steps timed calls after one warm-up) and print its JSON object; "
                          "for profiling a form on its own")
@@ -217,11 +220,14 @@ def main() -> int:
             "alg_bytes_per_launch": bytes_per_launch,
         },
         "kernels_ms_per_step": {kk: vv["ms"] / 3 for kk, vv in sorted(full.items(), key=lambda t: -t[1]["ms"])},
+        "phases_ms_per_step": phase_split(full, 3),
     }
     out["forms"] = {"plain": {"value": value, "unit": "points/s", "ms_per_step": ms_per_step,
                               "hbm_GBps_alg": out["hbm_GBps_step_alg"]}}
     if "batched" in forms:
         out["forms"]["batched"] = bench_batched(ctx, dev, max(1, args.steps // 10))
+    if "gmm" in forms:
+        out["forms"]["gmm"] = bench_gmm(dev, max(1, args.steps // 4))
     if "fwd_bwd" in forms:
         out["forms"]["fwd_bwd"] = bench_fwd_bwd(dev, max(1, args.steps // 10))
     if not args.no_cpu_baseline:
@@ -229,6 +235,62 @@ def main() -> int:
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
+
+
+# Kernels of the binning phase of a plain fit (its single device-wide merge
+# runs in one workgroup, so every sort pass and heads scan belongs to the
+# binning); the labels kernel is its own phase; everything else is rounds.
+BIN_KERNELS = ("bbox", "make_keys", "sort_pass", "scan_heads", "bin_cell_setup", "bin_scan_chunks",
+               "bin_segsum_chunks", "bin_segsum_levels")
+
+
+def phase_split(table: dict, fits: int) -> dict:
+    out = {"binning": 0.0, "rounds": 0.0, "labels": 0.0}
+    for name, v in table.items():
+        ph = "binning" if name in BIN_KERNELS else ("labels" if name == "labels" else "rounds")
+        out[ph] += v["ms"] / fits
+    return out
+
+
+def bench_gmm(dev, steps: int) -> dict:
+    import torch
+
+    from paper_2206_02200_amd import gridshift, synth
+
+    ctx = gridshift.Context(0)
+    res = {}
+    for d in range(2, 7):
+        w = synth.gmm_f32(10_000_000, d, seed=40 + d)
+        x = torch.from_numpy(w.x).to(dev)
+        n = w.x.shape[0]
+        r = gridshift.fit(x, w.h, w.max_iter, ctx=ctx)  # warm-up (allocations)
+        torch.cuda.synchronize()
+        ctx.profile("shift")
+        ctx.profile_reset()
+        gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
+        torch.cuda.synchronize()
+        sh = ctx.profile_table().get("shift", {"ms": 0.0, "launches": 0})
+        ctx.profile(None)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        info = r.info
+        m0, k = info["n_cells0"], info["n_clusters"]
+        b_alg = n * (d * 4 + 12) + 2 * m0 * (16 + 8 * d) + k * (8 * d + 8)
+        res[f"d{d}"] = {
+            "value": n / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "steps": steps,
+            "hbm_GBps_alg": b_alg / (ms * 1e-3) / 1e9, "cells0": m0, "clusters": k, "rounds": info["n_iter"],
+            "shift_ms_per_fit": sh["ms"], "shift_launches": sh["launches"],
+            # every cell of a device-wide round probes its 3^d neighbour keys
+            "first_round_probes": m0 * 3 ** d,
+        }
+        del x
+    ctx.close()
+    res["workload"] = ("Gaussian mixture, 50 isotropic components, means U[0,100]^d, sigma U[1,3], "
+                       "Dirichlet(1) weights, n=1e7 f32, h=4, max_iter=100")
+    return res
 
 
 def bench_batched(ctx, dev, steps: int) -> dict:

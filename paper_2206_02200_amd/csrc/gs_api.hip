@@ -422,19 +422,20 @@ gs::CellTable table(gs_context* c, int i) {
 // already on the device.
 template <int D, class Src>
 gs_status segsum_d(gs_context* c, Src src, gs::CellTable t, int64_t m_bound, int64_t npos, hipStream_t s,
-                   double member_bytes, bool have_choff = false) {
+                   double member_bytes, bool have_choff, bool bin) {
     int64_t* ctr = P<int64_t>(c->counters);
     if (!have_choff)
-        GS_TRY(run_scan(c, gs::ExclOp{t.nch, t.choff}, ctr + 0, m_bound, ctr + 1, s, "scan_chunks", 8.0 * m_bound));
+        GS_TRY(run_scan(c, gs::ExclOp{t.nch, t.choff}, ctr + 0, m_bound, ctr + 1, s,
+                        bin ? "bin_scan_chunks" : "scan_chunks", 8.0 * m_bound));
     const int64_t tasks_bound = npos / gs::kChunk + m_bound + 1;
     GS_TRY(ensure(c->part, size_t(tasks_bound) * D * sizeof(double)));
     GS_TRY(ensure(c->partc, size_t(tasks_bound) * sizeof(int64_t)));
     // members are read once (index + value); every cell row is written once
-    PROF_LAUNCH("segsum_chunks", npos * member_bytes + m_bound * (8.0 * D + 8.0),
+    PROF_LAUNCH(bin ? "bin_segsum_chunks" : "segsum_chunks", npos * member_bytes + m_bound * (8.0 * D + 8.0),
                 gs::k_segsum_chunks<D, Src><<<blocks_for(tasks_bound * gs::kWave, gs::kSegThreads), gs::kSegThreads,
                                               0, s>>>(src, t, ctr + 0, ctr + 1, P<double>(c->part),
                                                       P<int64_t>(c->partc), tasks_bound));
-    PROF_LAUNCH("segsum_levels", 0.0,
+    PROF_LAUNCH(bin ? "bin_segsum_levels" : "segsum_levels", 0.0,
                 gs::k_segsum_levels<D><<<blocks_for(m_bound * gs::kWave, gs::kSegThreads), gs::kSegThreads, 0, s>>>(
                     t, ctr + 0, P<double>(c->part), P<int64_t>(c->partc), tasks_bound));
     GS_HIP(hipGetLastError());
@@ -443,14 +444,14 @@ gs_status segsum_d(gs_context* c, Src src, gs::CellTable t, int64_t m_bound, int
 
 template <class Src>
 gs_status segsum(gs_context* c, int d, Src src, gs::CellTable t, int64_t m_bound, int64_t npos, hipStream_t s,
-                 double member_bytes, bool have_choff = false) {
+                 double member_bytes, bool have_choff = false, bool bin = false) {
     switch (d) {
-        case 1: return segsum_d<1>(c, src, t, m_bound, npos, s, member_bytes, have_choff);
-        case 2: return segsum_d<2>(c, src, t, m_bound, npos, s, member_bytes, have_choff);
-        case 3: return segsum_d<3>(c, src, t, m_bound, npos, s, member_bytes, have_choff);
-        case 4: return segsum_d<4>(c, src, t, m_bound, npos, s, member_bytes, have_choff);
-        case 5: return segsum_d<5>(c, src, t, m_bound, npos, s, member_bytes, have_choff);
-        case 6: return segsum_d<6>(c, src, t, m_bound, npos, s, member_bytes, have_choff);
+        case 1: return segsum_d<1>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin);
+        case 2: return segsum_d<2>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin);
+        case 3: return segsum_d<3>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin);
+        case 4: return segsum_d<4>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin);
+        case 5: return segsum_d<5>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin);
+        case 6: return segsum_d<6>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin);
     }
     return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
 }
@@ -693,13 +694,13 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
                 dk_pre = true;
             }
         }
-        PROF_LAUNCH("cell_setup", m0 * (20.0 + (wide_next ? 12.0 : 0.0)),
+        PROF_LAUNCH("bin_cell_setup", m0 * (20.0 + (wide_next ? 12.0 : 0.0)),
                     gs::k_cell_setup<<<blocks_for(c->capM, 256), 256, 0, s>>>(ctr + 0, N, T0, 0, row_off, B,
                                                                                nullptr, st, true, cur0, dk0,
                                                                                dk_pre_epoch));
         GS_HIP(hipGetLastError());
     }
-    GS_TRY(segsum(c, d, gs::SrcPoints<T>{x, ld, perm}, T0, m0, N, s, 4.0 + double(d) * sizeof(T)));
+    GS_TRY(segsum(c, d, gs::SrcPoints<T>{x, ld, perm}, T0, m0, N, s, 4.0 + double(d) * sizeof(T), false, true));
     if (c->tape_on && m0 > 0) {  // the initial cells, for the adjoint and the loss
         GS_TRY(ensure(c->sums0, size_t(m0) * d * 8));
         GS_TRY(ensure(c->inst0, size_t(m0) * 4));
@@ -1263,7 +1264,7 @@ static gs_status loss_fwd(gs_context* c, const T* x, const int32_t* labels, doub
     int64_t* ctr = P<int64_t>(c->counters);
     k_set_i64<<<1, 1, 0, s>>>(ctr + 0, B);
     gs::SrcLoss<T> src{x, c->ld, labels, P<double>(c->modes_i), P<int64_t>(c->rowoff), P<int64_t>(c->koff), B, c->d};
-    return segsum_d<1>(c, src, t, B, c->N, s, 4.0 + 4.0 + c->d * double(sizeof(T)));
+    return segsum_d<1>(c, src, t, B, c->N, s, 4.0 + 4.0 + c->d * double(sizeof(T)), false, false);
 }
 
 template <typename T>

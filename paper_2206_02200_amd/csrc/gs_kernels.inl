@@ -539,7 +539,9 @@ struct SrcMerge {
 constexpr int kSegThreads = 256;
 
 // One wave per chunk task: the R subtree of 256 members aligned at the
-// cell's first member.  Lane l holds members 4l..4l+3 of the chunk.
+// cell's first member.  Lane l holds members l, 64 + l, 128 + l and 192 + l
+// of the chunk (consecutive lanes read consecutive members); the subtree is
+// the four 64-leaf trees over the lanes, combined as (t0 + t1) + (t2 + t3).
 template <int D, class Src>
 __global__ __launch_bounds__(kSegThreads) void k_segsum_chunks(Src src, CellTable t, const int64_t* __restrict__ m_ptr,
                                                                const int64_t* __restrict__ tasks_ptr,
@@ -566,7 +568,7 @@ __global__ __launch_bounds__(kSegThreads) void k_segsum_chunks(Src src, CellTabl
         int64_t ca[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int64_t r = 4 * lane + i;
+            const int64_t r = i * kWave + lane;
             if (r < cnt) {
                 ca[i] = src.load(p0 + r, a[i], D);
             } else {
@@ -575,13 +577,24 @@ __global__ __launch_bounds__(kSegThreads) void k_segsum_chunks(Src src, CellTabl
                 for (int k = 0; k < D; ++k) a[i][k] = -0.0;
             }
         }
+        double sl[4][D];
+        int64_t cs[4];
 #pragma unroll
-        for (int k = 0; k < D; ++k) acc[k] = (a[0][k] + a[1][k]) + (a[2][k] + a[3][k]);
-        cacc = (ca[0] + ca[1]) + (ca[2] + ca[3]);
+        for (int i = 0; i < 4; ++i) {
+            if (i * kWave < cnt) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) sl[i][k] = wave_tree_sum(a[i][k]);
+                cs[i] = wave_tree_sum_i64(ca[i]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < D; ++k) sl[i][k] = -0.0;
+                cs[i] = 0;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = (sl[0][k] + sl[1][k]) + (sl[2][k] + sl[3][k]);
+        cacc = (cs[0] + cs[1]) + (cs[2] + cs[3]);
     }
-#pragma unroll
-    for (int k = 0; k < D; ++k) acc[k] = wave_tree_sum(acc[k]);
-    cacc = wave_tree_sum_i64(cacc);
     if (lane == 0) {
         if (t.nch[c] == 1) {
 #pragma unroll
