@@ -1120,10 +1120,10 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
     std::vector<char>& img = c->ctl_img;
     img.assign(up_end, 0);
     {
-        int64_t* bx = reinterpret_cast<int64_t*>(img.data());
+        uint64_t* bx = reinterpret_cast<uint64_t*>(img.data());
         for (size_t i = 0; i < box_bytes / 8; i += 2) {
-            bx[i] = INT64_MAX;
-            bx[i + 1] = INT64_MIN;
+            bx[i] = ~0ull;  // min image (the largest)
+            bx[i + 1] = 0;  // max image (the smallest)
         }
         gs::InstState z{};
         z.active = 1;
@@ -1151,8 +1151,7 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
         const unsigned bsplit = 1;
         const double xb = double(N) * d * (dtype == GS_F32 ? 4.0 : 8.0);
         const gs::RowTile* tl = P<gs::RowTile>(c->tiles);
-        const double* hsd = P<double>(c->hs);
-        int64_t* bp = P<int64_t>(c->bbox);
+        uint64_t* bp = P<uint64_t>(c->bbox);
         int64_t* cn = P<int64_t>(c->counters);
         const float* xf = static_cast<const float*>(points);
         const double* xd = static_cast<const double*>(points);
@@ -1160,10 +1159,10 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
         switch (d * 2 + (dtype == GS_F32 ? 0 : 1)) {
 #define GS_BB(D)                                                                                               \
     case 2 * D:                                                                                                \
-        gs::k_bbox_tiles<float, D><<<g * bsplit, gs::kBoxThreads, 0, s>>>(xf, ld, tl, hsd, bp, nbc, cn, bsplit); \
+        gs::k_bbox_tiles<float, D><<<g * bsplit, gs::kBoxThreads, 0, s>>>(xf, ld, tl, bp, nbc, cn, bsplit);       \
         break;                                                                                                 \
     case 2 * D + 1:                                                                                            \
-        gs::k_bbox_tiles<double, D><<<g * bsplit, gs::kBoxThreads, 0, s>>>(xd, ld, tl, hsd, bp, nbc, cn, bsplit); \
+        gs::k_bbox_tiles<double, D><<<g * bsplit, gs::kBoxThreads, 0, s>>>(xd, ld, tl, bp, nbc, cn, bsplit);      \
         break;
             GS_BB(1) GS_BB(2) GS_BB(3) GS_BB(4) GS_BB(5) GS_BB(6)
 #undef GS_BB
@@ -1174,22 +1173,37 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
         // boxes and counters in one copy (counter 2 holds the error bits)
         std::vector<char> rb(o_ctr + 3 * sizeof(int64_t));
         GS_TRY(d2h(c, rb.data(), base, rb.size(), s));
-        const int64_t* bc = reinterpret_cast<const int64_t*>(rb.data());
-        for (int b = 0; b < B; ++b)
-            for (int k = 0; k < gs::kMaxDim; ++k) {
-                int64_t mn = INT64_MAX, mx = INT64_MIN;
-                for (int q = 0; q < nbc; ++q) {
-                    const int64_t* e = bc + ((int64_t(b) * nbc + q) * gs::kMaxDim + k) * 2;
-                    mn = std::min(mn, e[0]);
-                    mx = std::max(mx, e[1]);
-                }
-                box[(int64_t(b) * gs::kMaxDim + k) * 2 + 0] = mn;
-                box[(int64_t(b) * gs::kMaxDim + k) * 2 + 1] = mx;
-            }
         int64_t errbits = 0;
         std::memcpy(&errbits, rb.data() + o_ctr + 2 * sizeof(int64_t), sizeof(int64_t));
         if (errbits & 1) return fail(GS_ERR_NONFINITE, "a coordinate is NaN or infinite");
-        if (errbits & 2) return fail(GS_ERR_KEY_RANGE, "|floor(x/h)| >= 2^52");
+        // extremes of the coordinates (order-preserving images, combined over
+        // the copies) -> cell coordinates floor(fl(v / h)) of the extremes,
+        // which bound every point's by monotonicity
+        const uint64_t* bc = reinterpret_cast<const uint64_t*>(rb.data());
+        auto decode = [](uint64_t u) {
+            const uint64_t bits = (u >> 63) ? (u & ~(1ull << 63)) : ~u;
+            double v;
+            std::memcpy(&v, &bits, sizeof(v));
+            return v;
+        };
+        for (int b = 0; b < B; ++b) {
+            if (offsets[b + 1] == offsets[b]) continue;  // empty instance: no box
+            for (int k = 0; k < d; ++k) {
+                uint64_t mn = ~0ull, mx = 0;
+                for (int q = 0; q < nbc; ++q) {
+                    const uint64_t* e = bc + ((int64_t(b) * nbc + q) * gs::kMaxDim + k) * 2;
+                    mn = std::min(mn, e[0]);
+                    mx = std::max(mx, e[1]);
+                }
+                const double qlo = std::floor(decode(mn) / h[b]);
+                const double qhi = std::floor(decode(mx) / h[b]);
+                const double lim = 4503599627370496.0;  // 2^52
+                if (!(qlo > -lim && qlo < lim && qhi > -lim && qhi < lim))
+                    return fail(GS_ERR_KEY_RANGE, "|floor(x/h)| >= 2^52");
+                box[(int64_t(b) * gs::kMaxDim + k) * 2 + 0] = int64_t(qlo);
+                box[(int64_t(b) * gs::kMaxDim + k) * 2 + 1] = int64_t(qhi);
+            }
+        }
     }
     int bits = 0;
     GS_TRY(build_params(c, B, d, offsets, h, box, &bits));

@@ -121,34 +121,41 @@ struct Stager {
 };
 
 // ===========================================================================
-// bbox: per instance and dimension, min/max of floor(fl(x/h))
+// bbox: per instance and dimension, min/max of the coordinates
 // ===========================================================================
-// Each block reduces one tile and merges the result into one of `ncopies`
-// copies of its instance's box, [B][ncopies][kMaxDim][2] (initialised to
-// INT64_MAX / INT64_MIN), with atomic min/max; spreading the blocks over
-// copies keeps atomics on one address few (the host combines the copies).
+// floor(fl(v / h)) is non-decreasing in v (h > 0; division and floor are
+// monotone), so the box of the cell coordinates is [floor(fl(min/h)),
+// floor(fl(max/h))]: the device reduces the raw coordinates only, the host
+// divides the two extremes.  Each block reduces one tile and merges the
+// result into one of `ncopies` copies of its instance's box,
+// [B][ncopies][kMaxDim][2], as order-preserving 64-bit images of the
+// binary64 values (initialised to all ones / zero) with atomic min/max;
+// spreading the blocks over copies keeps atomics on one address few (the
+// host combines the copies).  Non-finite coordinates set bit 0 of
+// counters[2] and are left out of the box.
+__device__ __forceinline__ uint64_t ordered_bits(double v) {
+    const uint64_t u = uint64_t(__double_as_longlong(v));
+    return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+
 template <typename T, int D>
 __global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict__ x, int64_t ld,
                                                             const RowTile* __restrict__ tiles,
-                                                            const double* __restrict__ hs,
-                                                            int64_t* __restrict__ bbox, int ncopies,
+                                                            uint64_t* __restrict__ bbox, int ncopies,
                                                             int64_t* __restrict__ counters, int split) {
     using S = Stager<T, D>;
     constexpr int R = S::R;
     constexpr int RPT = R / kBoxThreads;
     __shared__ T stage[R * D];
-    __shared__ int64_t red[kBoxThreads / kWave][2 * D];
+    __shared__ uint64_t red[kBoxThreads / kWave][2 * D];
     const RowTile tl = tile_part(tiles, split, R);
     if (tl.r0 >= tl.r1) return;
-    const double h = hs[tl.inst];
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-    // running min / max of the cell coordinates as doubles: they are integers
-    // below 2^52 in magnitude (checked), so binary64 min/max are exact
-    double mnd[D], mxd[D];
+    T mn[D], mx[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        mnd[k] = 4503599627370496.0;
-        mxd[k] = -4503599627370496.0;
+        mn[k] = T(INFINITY);
+        mx[k] = T(-INFINITY);
     }
     int err = 0;
     S sg;
@@ -167,58 +174,45 @@ __global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict_
             if (r >= crows) continue;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                const double v = double(stage[r * D + k]);
+                const T v = stage[r * D + k];
                 if (!isfinite(v)) {
-                    err |= 1;
+                    err = 1;
                     continue;
                 }
-                const double q = cell_floor(v, h);
-                if (!(q > -4503599627370496.0 && q < 4503599627370496.0)) {  // |q| < 2^52
-                    err |= 2;
-                    continue;
-                }
-                mnd[k] = fmin(mnd[k], q);
-                mxd[k] = fmax(mxd[k], q);
+                mn[k] = fmin(mn[k], v);
+                mx[k] = fmax(mx[k], v);
             }
         }
         __syncthreads();  // every row read before the next chunk is stored
         c0 = n0;
         crows = nrows;
     }
-    int64_t mn[D], mx[D];
+    uint64_t kmn[D], kmx[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        mn[k] = mnd[k] <= mxd[k] ? int64_t(mnd[k]) : INT64_MAX;  // no finite row: empty box
-        mx[k] = mnd[k] <= mxd[k] ? int64_t(mxd[k]) : INT64_MIN;
-    }
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
+        kmn[k] = ordered_bits(double(mn[k]));
+        kmx[k] = ordered_bits(double(mx[k]));
         for (int off = 32; off >= 1; off >>= 1) {
-            const int64_t a = __shfl_xor(mn[k], off, kWave);
-            const int64_t c = __shfl_xor(mx[k], off, kWave);
-            mn[k] = a < mn[k] ? a : mn[k];
-            mx[k] = c > mx[k] ? c : mx[k];
+            const uint64_t a = __shfl_xor((unsigned long long)kmn[k], off, kWave);
+            const uint64_t c = __shfl_xor((unsigned long long)kmx[k], off, kWave);
+            kmn[k] = a < kmn[k] ? a : kmn[k];
+            kmx[k] = c > kmx[k] ? c : kmx[k];
         }
         if (lane == 0) {
-            red[w][2 * k] = mn[k];
-            red[w][2 * k + 1] = mx[k];
+            red[w][2 * k] = kmn[k];
+            red[w][2 * k + 1] = kmx[k];
         }
     }
-    const uint64_t eb = __ballot(err != 0);
-    if (eb) {
-        int e = err;
-        for (int off = 32; off >= 1; off >>= 1) e |= __shfl_xor(e, off, kWave);
-        if (lane == 0) atomicOr((unsigned long long*)&counters[2], (unsigned long long)e);
-    }
+    if (__ballot(err != 0) && lane == 0) atomicOr((unsigned long long*)&counters[2], 1ull);
     __syncthreads();
     if (tid < 2 * D) {
         const bool isMin = (tid & 1) == 0;
-        int64_t a = isMin ? INT64_MAX : INT64_MIN;
+        uint64_t a = isMin ? ~0ull : 0ull;
         for (int ww = 0; ww < kBoxThreads / kWave; ++ww) {
-            const int64_t c = red[ww][tid];
+            const uint64_t c = red[ww][tid];
             a = isMin ? (c < a ? c : a) : (c > a ? c : a);
         }
-        int64_t* dst = bbox + (int64_t(tl.inst) * ncopies + int(blockIdx.x) % ncopies) * 2 * kMaxDim + tid;
+        uint64_t* dst = bbox + (int64_t(tl.inst) * ncopies + int(blockIdx.x) % ncopies) * 2 * kMaxDim + tid;
         if (isMin) __hip_atomic_fetch_min(dst, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         else __hip_atomic_fetch_max(dst, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }

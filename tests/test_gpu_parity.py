@@ -163,6 +163,21 @@ def test_strided_rows():
     np.testing.assert_array_equal(_bits(r.sums.cpu().numpy()), _bits(o.sums))
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_signed_coordinates_and_cell_edges(dtype):
+    # The key box comes from the extreme coordinates of every dimension;
+    # coordinates of both signs, signed zeros, values exactly on cell edges
+    # and one dimension where every point sits in one cell must all give the
+    # oracle's cells.
+    rng = np.random.default_rng(3100)
+    x = np.concatenate([_blobs(3101, 3000, 3, k=6, scale=4.0, spread=10.0) - 30.0,
+                        rng.integers(-12, 13, size=(400, 3)).astype(np.float64) * 2.5,
+                        np.array([[-0.0, 0.0, -0.0], [0.0, -0.0, 0.0]])], axis=0)
+    x[:, 2] = np.where(x[:, 2] > 0, 0.75, 0.25) + 0.0 * x[:, 2]
+    x = x.astype(dtype)
+    assert_parity(x, 2.5, 100, f"signed {np.dtype(dtype).name}")
+
+
 def test_errors():
     with pytest.raises(gridshift.GridShiftError) as e:
         _gpu(np.array([[np.nan, 1.0]]), 1.0)
