@@ -957,20 +957,18 @@ gs_status launch_tail_adj(gs_context* c, int d, const gs::TailTape& tape, const 
     return GS_OK;
 }
 
+template <class Lookup>
 gs_status launch_adj_stencil(gs_context* c, int d, const uint64_t* key, const int32_t* inst, const int32_t* applied,
-                             int64_t m, const uint64_t* hk, const uint32_t* hv, int logcap, const double* q,
-                             double* out, hipStream_t s) {
+                             int64_t m, Lookup lk, const double* q, double* out, hipStream_t s) {
     const gs::InstParam* prm = P<gs::InstParam>(c->param);
     const unsigned g = blocks_for(m, gs::kShiftWaves);
     const int64_t cap = c->capM;
     const int tk = prof_begin(c, s, "adj_stencil");
     switch (d) {
-        case 1: gs::k_adj_stencil<1><<<g, 256, 0, s>>>(key, inst, applied, m, prm, hk, hv, logcap, q, out, cap); break;
-        case 2: gs::k_adj_stencil<2><<<g, 256, 0, s>>>(key, inst, applied, m, prm, hk, hv, logcap, q, out, cap); break;
-        case 3: gs::k_adj_stencil<3><<<g, 256, 0, s>>>(key, inst, applied, m, prm, hk, hv, logcap, q, out, cap); break;
-        case 4: gs::k_adj_stencil<4><<<g, 256, 0, s>>>(key, inst, applied, m, prm, hk, hv, logcap, q, out, cap); break;
-        case 5: gs::k_adj_stencil<5><<<g, 256, 0, s>>>(key, inst, applied, m, prm, hk, hv, logcap, q, out, cap); break;
-        case 6: gs::k_adj_stencil<6><<<g, 256, 0, s>>>(key, inst, applied, m, prm, hk, hv, logcap, q, out, cap); break;
+#define GS_AS(D)                                                                                                \
+    case D: gs::k_adj_stencil<D, Lookup><<<g, 256, 0, s>>>(key, inst, applied, m, prm, lk, q, out, cap); break;
+        GS_AS(1) GS_AS(2) GS_AS(3) GS_AS(4) GS_AS(5) GS_AS(6)
+#undef GS_AS
         default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
     }
     prof_end(c, s, tk, double(m) * (8.0 + 8.0 * d) * 2);
@@ -1027,17 +1025,28 @@ gs_status adjoint_core(gs_context* c, const double* gm, hipStream_t s, double** 
                     gs::k_adj_q<<<blocks_for(M, 256), 256, 0, s>>>(
                         P<int32_t>(c->wt_inst) + off, P<int64_t>(c->wt_cnt) + off, P<int32_t>(c->wt_W) + off,
                         P<uint32_t>(c->wt_g) + off, applied, M, d, sa, P<double>(c->qbuf), c->capM));
-        int logcap = 1;
-        while ((int64_t(1) << logcap) < 2 * M) ++logcap;
-        const int64_t hcap = int64_t(1) << logcap;
-        GS_TRY(ensure(c->hk, size_t(hcap) * 8));
-        GS_TRY(ensure(c->hv, size_t(hcap) * 4));
-        gs::k_hash_clear<<<blocks_for(hcap, 256), 256, 0, s>>>(P<uint64_t>(c->hk), hcap);
-        gs::k_hash_insert<<<blocks_for(M, 256), 256, 0, s>>>(P<uint64_t>(c->wt_key) + off, M, P<uint64_t>(c->hk),
-                                                              P<uint32_t>(c->hv), logcap);
-        GS_HIP(hipGetLastError());
-        GS_TRY(launch_adj_stencil(c, d, P<uint64_t>(c->wt_key) + off, P<int32_t>(c->wt_inst) + off, applied, M,
-                                  P<uint64_t>(c->hk), P<uint32_t>(c->hv), logcap, P<double>(c->qbuf), sb, s));
+        const uint64_t* rkey = P<uint64_t>(c->wt_key) + off;
+        if (c->cfg.dense_table && c->key_span <= gs::kDenseMax) {  // the round's table in the dense key table
+            uint32_t ep = 0;
+            GS_TRY(dense_reserve(c, s, &ep));
+            gs::k_dense_insert<<<blocks_for(M, 256), 256, 0, s>>>(rkey, M, P<uint64_t>(c->dk), ep);
+            GS_HIP(hipGetLastError());
+            GS_TRY(launch_adj_stencil(c, d, rkey, P<int32_t>(c->wt_inst) + off, applied, M,
+                                      gs::DenseLookup{P<uint64_t>(c->dk), ep}, P<double>(c->qbuf), sb, s));
+        } else {
+            int logcap = 1;
+            while ((int64_t(1) << logcap) < 2 * M) ++logcap;
+            const int64_t hcap = int64_t(1) << logcap;
+            GS_TRY(ensure(c->hk, size_t(hcap) * 8));
+            GS_TRY(ensure(c->hv, size_t(hcap) * 4));
+            gs::k_hash_clear<<<blocks_for(hcap, 256), 256, 0, s>>>(P<uint64_t>(c->hk), hcap);
+            gs::k_hash_insert<<<blocks_for(M, 256), 256, 0, s>>>(rkey, M, P<uint64_t>(c->hk), P<uint32_t>(c->hv),
+                                                                  logcap);
+            GS_HIP(hipGetLastError());
+            GS_TRY(launch_adj_stencil(c, d, rkey, P<int32_t>(c->wt_inst) + off, applied, M,
+                                      gs::HashLookup{P<uint64_t>(c->hk), P<uint32_t>(c->hv), logcap},
+                                      P<double>(c->qbuf), sb, s));
+        }
         std::swap(sa, sb);
     }
     *sbar0_out = sa;

@@ -783,10 +783,14 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
 #pragma unroll
     for (int k = 0; k < D; ++k) crd[k] = int64_t((local / P.stride[k]) % uint64_t(P.E[k]));
     const uint64_t lt = lanemask_lt();
-    int nfound = 0;
-    for (int r0 = 0; r0 < NOFF; r0 += kWave) {
-        const int r = r0 + lane;
-        int64_t idx = -1;
+    // every probe of the cell first (independent loads, all in flight), then
+    // the found cells compacted in probe order
+    constexpr int NIT = (NOFF + kWave - 1) / kWave;
+    int64_t idx[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int r = it * kWave + lane;
+        idx[it] = -1;
         if (r < NOFF) {
             int rr = r;
             bool inside = true;
@@ -799,32 +803,39 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
                 inside = inside && c >= 0 && c < P.E[k];
                 nk += uint64_t(int64_t(v)) * P.stride[k];
             }
-            if (inside) idx = lk.find(nk);
+            if (inside) idx[it] = lk.find(nk);
         }
-        const uint64_t bal = __ballot(idx >= 0);
-        if (idx >= 0) list[w][nfound + __popcll(bal & lt)] = int32_t(idx);
+    }
+    int nfound = 0;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const uint64_t bal = __ballot(idx[it] >= 0);
+        if (idx[it] >= 0) list[w][nfound + __popcll(bal & lt)] = int32_t(idx[it]);
         nfound += __popcll(bal);
     }
     __builtin_amdgcn_wave_barrier();
+    // lane k < D folds dimension k left to right over the found cells (its
+    // loads issued 16 at a time); lane D adds the counts
     double acc = 0.0;
     int64_t W = 0;
     if (lane < D) {
         const double* col = t.sum + int64_t(lane) * t.cap;
-        int q = 0;
-        for (; q + 4 <= nfound; q += 4) {
-            const double s0 = col[list[w][q]], s1 = col[list[w][q + 1]];
-            const double s2 = col[list[w][q + 2]], s3 = col[list[w][q + 3]];
-            acc = (q == 0) ? s0 : acc + s0;
-            acc = acc + s1;
-            acc = acc + s2;
-            acc = acc + s3;
-        }
-        for (; q < nfound; ++q) {
-            const double s0 = col[list[w][q]];
-            acc = (q == 0) ? s0 : acc + s0;
+        for (int q0 = 0; q0 < nfound; q0 += 16) {
+            double sv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) sv[u] = q0 + u < nfound ? col[list[w][q0 + u]] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (q0 + u < nfound) acc = (q0 + u == 0) ? sv[u] : acc + sv[u];
         }
     } else if (lane == D) {
-        for (int q = 0; q < nfound; ++q) W += t.cnt[list[w][q]];
+        for (int q0 = 0; q0 < nfound; q0 += 16) {
+            int64_t cv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) cv[u] = q0 + u < nfound ? t.cnt[list[w][q0 + u]] : 0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) W += cv[u];
+        }
     }
     W = __shfl(W, D, kWave);
     bool bad = false, chg = false;
@@ -1837,13 +1848,11 @@ __global__ void k_adj_q(const int32_t* __restrict__ inst, const int64_t* __restr
 
 // Wide round r, reversed: Sbar_k = fold over the 3^D neighbour keys (ascending)
 // of q; one wave per cell, the probes in parallel as in k_shift.
-template <int D>
+template <int D, class Lookup>
 __global__ __launch_bounds__(kShiftWaves * kWave) void k_adj_stencil(const uint64_t* __restrict__ key,
                                                                      const int32_t* __restrict__ inst,
                                                                      const int32_t* __restrict__ applied, int64_t m,
-                                                                     const InstParam* __restrict__ param,
-                                                                     const uint64_t* __restrict__ hk,
-                                                                     const uint32_t* __restrict__ hv, int logcap,
+                                                                     const InstParam* __restrict__ param, Lookup lk,
                                                                      const double* __restrict__ q,
                                                                      double* __restrict__ out, int64_t cap) {
     constexpr int NOFF = pow3(D);
@@ -1863,10 +1872,14 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_adj_stencil(const uint6
 #pragma unroll
     for (int k = 0; k < D; ++k) crd[k] = int64_t((local / P.stride[k]) % uint64_t(P.E[k]));
     const uint64_t lt = lanemask_lt();
-    int nfound = 0;
-    for (int r0 = 0; r0 < NOFF; r0 += kWave) {
-        const int r = r0 + lane;
-        int64_t idx = -1;
+    // every probe first (independent loads), then the found cells compacted
+    // in probe order, as in k_shift
+    constexpr int NIT = (NOFF + kWave - 1) / kWave;
+    int64_t idx[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int r = it * kWave + lane;
+        idx[it] = -1;
         if (r < NOFF) {
             int rr = r;
             bool inside = true;
@@ -1879,17 +1892,28 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_adj_stencil(const uint6
                 inside = inside && c >= 0 && c < P.E[k];
                 nk += uint64_t(int64_t(v)) * P.stride[k];
             }
-            if (inside) idx = hash_find(hk, hv, nk, logcap);
+            if (inside) idx[it] = lk.find(nk);
         }
-        const uint64_t bal = __ballot(idx >= 0);
-        if (idx >= 0) list[w][nfound + __popcll(bal & lt)] = int32_t(idx);
+    }
+    int nfound = 0;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const uint64_t bal = __ballot(idx[it] >= 0);
+        if (idx[it] >= 0) list[w][nfound + __popcll(bal & lt)] = int32_t(idx[it]);
         nfound += __popcll(bal);
     }
     __builtin_amdgcn_wave_barrier();
-    if (lane < D) {
+    if (lane < D) {  // left fold from -0.0, loads issued 16 at a time
         const double* col = q + int64_t(lane) * cap;
         double acc = -0.0;
-        for (int e = 0; e < nfound; ++e) acc = acc + col[list[w][e]];
+        for (int e0 = 0; e0 < nfound; e0 += 16) {
+            double sv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) sv[u] = e0 + u < nfound ? col[list[w][e0 + u]] : -0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (e0 + u < nfound) acc = acc + sv[u];
+        }
         out[int64_t(lane) * cap + j] = acc;
     }
 }
