@@ -111,6 +111,10 @@ struct gs_context {
     int ck_nslots = 0;
     DBuf sums0, inst0, wt_key, wt_cnt, wt_inst, wt_W, wt_g, wt_app;
     DBuf tt_key, tt_cnt, tt_W, tt_g, tt_m;
+    // backward with checkpoints: a second stream recomputes the next (earlier)
+    // tape segment while the current one is reversed (two tape buffers)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_start = nullptr, ev_rep[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
     DBuf sbA, sbB, qbuf, gmodes, modes_i, counts_i, frows, lossc, ltab;
     DBuf xkA, xkB, xvA, xvB;
     std::vector<int64_t> w_off, w_M;
@@ -574,6 +578,37 @@ gs_status tail_tape(gs_context* c, int rounds, int B, gs::TailTape* tape) {
     return GS_OK;
 }
 
+// Two device tapes of `rounds` rounds per instance (one allocation each
+// buffer, the second half for tp[1]).
+gs_status tail_tape_pair(gs_context* c, int rounds, int B, gs::TailTape* tp) {
+    const size_t per = size_t(rounds) * gs::kTailCells, half = per * B;
+    GS_TRY(ensure(c->tt_key, 2 * half * 8));
+    GS_TRY(ensure(c->tt_cnt, 2 * half * 4));
+    GS_TRY(ensure(c->tt_W, 2 * half * 4));
+    GS_TRY(ensure(c->tt_g, 2 * half * 4));
+    GS_TRY(ensure(c->tt_m, 2 * size_t(rounds) * B * 4));
+    for (int q = 0; q < 2; ++q) {
+        tp[q].key = P<uint64_t>(c->tt_key) + q * half;
+        tp[q].cnt = P<int32_t>(c->tt_cnt) + q * half;
+        tp[q].W = P<int32_t>(c->tt_W) + q * half;
+        tp[q].g = P<uint32_t>(c->tt_g) + q * half;
+        tp[q].m = P<int32_t>(c->tt_m) + q * size_t(rounds) * B;
+        tp[q].stride = int64_t(per);
+        tp[q].max_rounds = rounds;
+    }
+    return GS_OK;
+}
+
+// The context's second stream and its events (created on first use, default
+// priority, non-blocking).
+gs_status aux_stream(gs_context* c) {
+    if (c->aux) return GS_OK;
+    GS_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    hipEvent_t* evs[] = {&c->ev_start, &c->ev_rep[0], &c->ev_rep[1], &c->ev_adj[0], &c->ev_adj[1]};
+    for (hipEvent_t* e : evs) GS_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    return GS_OK;
+}
+
 // Device view of the tail checkpoints (ns slots per instance).
 gs::TailCkpt ckpt_view(gs_context* c, int ns, int B, int every) {
     gs::TailCkpt ck;
@@ -845,7 +880,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
 #define GS_MS(D)                                                                                                   \
     case D:                                                                                                        \
         gs::k_merge_small<D><<<1, gs::kMergeThreads, 0, s>>>(TT, M, U, st, B, P<double>(c->pbuf),                  \
-                                                             P<uint64_t>(c->kappa), np, P<uint32_t>(c->gmap),      \
+                                                             P<uint64_t>(c->kappa), np, bits, P<uint32_t>(c->gmap), \
                                                              P<uint32_t>(c->cvA), P<uint32_t>(c->cur), m0, gt,     \
                                                              ctr, max_iter, dk_next, dk_pre_epoch);                \
         break;
@@ -1000,13 +1035,27 @@ gs_status adjoint_core(gs_context* c, const double* gm, hipStream_t s, double** 
         // segment's tape from its checkpoint, then reverse its rounds
         int most = 0;
         for (int b = 0; b < B; ++b) most = std::max(most, c->st[b].t - c->st[b].t_tail0);
+        // Segment i is recomputed on the second stream into tape buffer i % 2
+        // while segment i - 1 is reversed on s; a buffer is refilled only
+        // after the reversal that read it.
         const int k = c->ckpt_used;
-        GS_TRY(tail_tape(c, k, B, &tape));
+        gs::TailTape tp[2];
+        GS_TRY(tail_tape_pair(c, k, B, tp));
+        GS_TRY(aux_stream(c));
         const gs::TailCkpt ck = ckpt_view(c, c->ck_nslots, B, k);
-        for (int r0 = most > 0 ? ((most - 1) / k) * k : -1; r0 >= 0; r0 -= k) {
+        hipStream_t s2 = c->aux;
+        GS_HIP(hipEventRecord(c->ev_start, s));
+        GS_HIP(hipStreamWaitEvent(s2, c->ev_start, 0));
+        int i = 0;
+        for (int r0 = most > 0 ? ((most - 1) / k) * k : -1; r0 >= 0; r0 -= k, ++i) {
+            const int q = i & 1;
+            if (i >= 2) GS_HIP(hipStreamWaitEvent(s2, c->ev_adj[q], 0));
             GS_TRY(launch_tail(c, d, B, TC, P<gs::InstParam>(c->param), P<gs::InstState>(c->state), nullptr,
-                               c->tail_rounds, tape, ck, r0, s, 0.0));
-            GS_TRY(launch_tail_adj(c, d, tape, ck, r0, sa, s));
+                               c->tail_rounds, tp[q], ck, r0, s2, 0.0));
+            GS_HIP(hipEventRecord(c->ev_rep[q], s2));
+            GS_HIP(hipStreamWaitEvent(s, c->ev_rep[q], 0));
+            GS_TRY(launch_tail_adj(c, d, tp[q], ck, r0, sa, s));
+            GS_HIP(hipEventRecord(c->ev_adj[q], s));
         }
     } else if (c->tail_rounds > 0) {
         tape.key = P<uint64_t>(c->tt_key);
@@ -1379,6 +1428,13 @@ void gs_context_destroy(gs_context* c) {
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->up) (void)hipHostFree(c->up);
     for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
+    if (c->aux) {
+        (void)hipStreamSynchronize(c->aux);
+        (void)hipStreamDestroy(c->aux);
+        hipEvent_t evs[] = {c->ev_start, c->ev_rep[0], c->ev_rep[1], c->ev_adj[0], c->ev_adj[1]};
+        for (hipEvent_t e : evs)
+            if (e) (void)hipEventDestroy(e);
+    }
     DBuf* tb2[] = {&c->sums0, &c->inst0, &c->wt_key, &c->wt_cnt, &c->wt_inst, &c->wt_W, &c->wt_g, &c->wt_app,
                    &c->tt_key, &c->tt_cnt, &c->tt_W, &c->tt_g, &c->tt_m, &c->sbA, &c->sbB, &c->qbuf, &c->gmodes,
                    &c->modes_i, &c->counts_i, &c->frows, &c->lossc, &c->ltab, &c->xkA, &c->xkB, &c->xvA, &c->xvB,

@@ -1012,6 +1012,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
                                                                InstState* __restrict__ st, int B,
                                                                const double* __restrict__ pbuf,
                                                                const uint64_t* __restrict__ kappa, int npasses,
+                                                               int kbits,
                                                                uint32_t* __restrict__ gmap,
                                                                uint32_t* __restrict__ mperm,
                                                                uint32_t* __restrict__ cur, int64_t m0,
@@ -1065,6 +1066,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
     int src = 0;
     for (int p = 0; p < npasses; ++p) {
         const int shift = 8 * p;
+        const int nbits = kbits - shift < 8 ? kbits - shift : 8;  // the last digit may be narrower
         for (int i = tid; i < NW * 256; i += kMergeThreads) (&wcnt[0][0])[i] = 0;
         __syncthreads();
         // wave w ranks positions [w * 64 * IPT, (w + 1) * 64 * IPT); slot i
@@ -1088,6 +1090,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
             uint64_t peers = __ballot(valid);
 #pragma unroll
             for (int bb = 0; bb < 8; ++bb) {
+                if (bb >= nbits) break;
                 const bool bit = (dgt >> bb) & 1u;
                 const uint64_t bal = __ballot(bit);
                 peers &= bit ? bal : ~bal;

@@ -52,7 +52,8 @@ constexpr int kSortLookWindow = 4;
 template <typename K>
 __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                             K* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                            int64_t n, int shift, const uint32_t* __restrict__ hist,
+                                                            int64_t n, int shift, int nbits,
+                                                            const uint32_t* __restrict__ hist,
                                                             uint32_t* __restrict__ clear, int64_t ntiles,
                                                             uint64_t* __restrict__ look, uint32_t* __restrict__ ctr,
                                                             uint32_t tile_base, uint32_t epoch) {
@@ -119,6 +120,7 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
+            if (b >= nbits) break;  // digits of the last pass may be narrower (higher bits are zero)
             const bool bit = (dgt >> b) & 1u;
             const uint64_t bal = __ballot(bit);
             peers &= bit ? bal : ~bal;
@@ -246,7 +248,8 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
         sc.tile_base += uint64_t(tiles);
         const int tk = sc.prof_begin ? sc.prof_begin(sc.prof_ctx, s, "sort_pass") : -1;
         k_sort_pass<K><<<dim3(unsigned(tiles)), dim3(kPassThreads), 0, s>>>(
-            ki, vi, ko, vo, n, 8 * p, hcur + p * 256, p == 0 ? hother : nullptr, tiles, sc.look, sc.ctr, base, ep);
+            ki, vi, ko, vo, n, 8 * p, bits - 8 * p < 8 ? bits - 8 * p : 8, hcur + p * 256, p == 0 ? hother : nullptr,
+            tiles, sc.look, sc.ctr, base, ep);
         // reads keys (and values after the first pass), writes keys and values
         if (sc.prof_end)
             sc.prof_end(sc.prof_ctx, s, tk, double(n) * (sizeof(K) + (p ? 4 : 0) + sizeof(K) + 4));
