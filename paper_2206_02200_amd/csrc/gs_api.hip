@@ -114,6 +114,11 @@ struct gs_context {
     // backward with checkpoints: a second stream recomputes the next (earlier)
     // tape segment while the current one is reversed (two tape buffers)
     hipStream_t aux = nullptr;
+    // host memory mapped for the device: [counters 8][states B], written by
+    // the kernel that ends a step the host waits for (no copy back)
+    int64_t* hmap = nullptr;      // host view
+    int64_t* hmap_dev = nullptr;  // device view
+    size_t hmap_cap = 0;
     hipEvent_t ev_start = nullptr, ev_rep[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
     DBuf sbA, sbB, qbuf, gmodes, modes_i, counts_i, frows, lossc, ltab;
     DBuf xkA, xkB, xvA, xvB;
@@ -314,17 +319,37 @@ gs_status h2d_batch(gs_context* c, const std::vector<Xfer>& xs, hipStream_t s) {
     return GS_OK;
 }
 
-// The counters and the instance states (adjacent in the control block) in
-// one copy, with one wait.
-gs_status read_counters_states(gs_context* c, int64_t* ctrs, hipStream_t s) {
-    const char* a = static_cast<const char*>(c->counters.p);
-    const char* z = static_cast<const char*>(c->state.p) + c->state.cap;
-    const size_t off = static_cast<const char*>(c->state.p) - a;
-    std::vector<char>& tmp = c->ctl_img;
-    tmp.resize(size_t(z - a));
-    GS_TRY(d2h(c, tmp.data(), a, tmp.size(), s));
-    std::memcpy(ctrs, tmp.data(), 8 * sizeof(int64_t));
-    std::memcpy(c->st.data(), tmp.data() + off, c->state.cap);
+// Host memory mapped for the device, for `B` published states.
+gs_status hmap_ensure(gs_context* c, int B) {
+    const size_t bytes = 8 * sizeof(int64_t) + sizeof(gs::InstState) * size_t(B);
+    if (c->hmap_cap >= bytes) return GS_OK;
+    if (c->hmap) (void)hipHostFree(c->hmap);
+    c->hmap = nullptr;
+    c->hmap_dev = nullptr;
+    c->hmap_cap = 0;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocMapped) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ERR_ALLOC, "hipHostMalloc (mapped) failed");
+    }
+    void* dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, p, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(p);
+        return fail(GS_ERR_ALLOC, "hipHostGetDevicePointer failed");
+    }
+    c->hmap = static_cast<int64_t*>(p);
+    c->hmap_dev = static_cast<int64_t*>(dp);
+    c->hmap_cap = bytes;
+    return GS_OK;
+}
+
+// Wait for the stream, then read the counters and states a kernel published
+// into the mapped host memory.
+gs_status read_published(gs_context* c, int64_t* ctrs, hipStream_t s) {
+    GS_TRY(stream_wait(c, s));
+    std::memcpy(ctrs, c->hmap, 8 * sizeof(int64_t));
+    std::memcpy(c->st.data(), c->hmap + 8, c->state.cap);
     return GS_OK;
 }
 
@@ -388,7 +413,7 @@ gs_status scan_prepare(gs_context* c, int64_t n_bound, hipStream_t s, uint32_t* 
 // n_dev: the length on the device, or nullptr when it is n_bound itself.
 template <class Op>
 gs_status run_scan(gs_context* c, Op op, const int64_t* n_dev, int64_t n_bound, int64_t* total_dev, hipStream_t s,
-                   const char* name, double nbytes) {
+                   const char* name, double nbytes, int64_t* total_host = nullptr) {
     uint32_t epoch = 0;
     GS_TRY(scan_prepare(c, n_bound, s, &epoch));
     const int64_t tiles = std::max<int64_t>(1, (n_bound + gs::kScanTile - 1) / gs::kScanTile);
@@ -397,7 +422,7 @@ gs_status run_scan(gs_context* c, Op op, const int64_t* n_dev, int64_t n_bound, 
     PROF_LAUNCH(name, nbytes,
                 gs::k_scan<Op><<<unsigned(tiles), gs::kScanThreads, 0, s>>>(op, n_dev, n_bound, P<uint64_t>(c->look),
                                                                             P<uint32_t>(c->tilectr), base, epoch,
-                                                                            total_dev));
+                                                                            total_dev, total_host));
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         c->tile_base = 0x7fffffffull;  // the counter is unknown now: clear it before the next scan
@@ -689,10 +714,10 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     {
         gs::HeadsOp<K> op{skeys, perm, P<uint64_t>(c->tkey[0]), P<uint32_t>(c->tstart[0]), P<uint32_t>(c->tfirst[0]),
                           P<uint32_t>(c->cell0)};
-        GS_TRY(run_scan(c, op, nullptr, N, ctr + 0, s, "scan_heads", N * (sizeof(K) + 8.0)));
+        GS_TRY(run_scan(c, op, nullptr, N, ctr + 0, s, "scan_heads", N * (sizeof(K) + 8.0), c->hmap_dev));
     }
-    int64_t m0 = 0;
-    GS_TRY(d2h(c, &m0, ctr + 0, sizeof(int64_t), s));
+    GS_TRY(stream_wait(c, s));
+    const int64_t m0 = c->hmap[0];  // the cell count, published by the scan's last tile
 
     // ---- cell tables with capacity m0
     c->capM = std::max<int64_t>(m0, 1);
@@ -781,7 +806,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
             PROF_LAUNCH("labels", N * 8.0,
                         gs::k_labels<<<unsigned(std::min<int64_t>(gs::kLabelBlocks, blocks_for(N, 256))), 256, 0, s>>>(
                             P<uint32_t>(c->cell0), nwide ? P<uint32_t>(c->cur) : nullptr, P<uint32_t>(c->tmap), labels, N,
-                            gate, st, B, P<int64_t>(c->koff)));
+                            gate, st, B, P<int64_t>(c->koff), ctr, c->hmap_dev));
             GS_HIP(hipGetLastError());
         }
         return GS_OK;
@@ -896,7 +921,8 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
             PROF_LAUNCH("round_end", B * 48.0,
                         gs::k_round_end<<<blocks_for(B, 256), 256, 0, s>>>(P<uint32_t>(c->cur), 0,
                                                                             P<uint32_t>(c->gmap), st, B, apprec,
-                                                                            gated ? ctr + 4 : nullptr));
+                                                                            gated ? ctr + 4 : nullptr, ctr,
+                                                                            c->hmap_dev));
             GS_HIP(hipGetLastError());
         } else {
         gs::k_decide<<<blocks_for(B, 256), 256, 0, s>>>(st, B, max_iter);
@@ -921,19 +947,21 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         GS_TRY(segsum(c, d, src, U, M, M, s, 4.0 + 4.0 + 8.0 + 8.0 * d));
         PROF_LAUNCH("round_end", m0 * 12.0,
                     gs::k_round_end<<<blocks_for(std::max<int64_t>(m0, B), 256), 256, 0, s>>>(
-                        P<uint32_t>(c->cur), m0, P<uint32_t>(c->gmap), st, B, apprec, nullptr));
+                        P<uint32_t>(c->cur), m0, P<uint32_t>(c->gmap), st, B, apprec, nullptr, nullptr, nullptr));
         GS_HIP(hipGetLastError());
         }
         cur = 1 - cur;
         // the tail and the labels right away, unless some instance still needs
         // a device-wide round (then the tail changes nothing and the loop goes on)
         if (!gated) {
-            gs::k_tail_gate<<<1, 256, 0, s>>>(st, B, ctr + 4);
+            gs::k_tail_gate<<<1, 256, 0, s>>>(st, B, ctr + 4, ctr, c->hmap_dev);
             GS_HIP(hipGetLastError());
         }
         GS_TRY(tail_and_labels(cur, wide, M, ctr + 4));
+        // the gate's kernel published the round's counters and states; the
+        // labels kernel, when the tail ran, the tail's
         int64_t ctrs[8];
-        GS_TRY(read_counters_states(c, ctrs, s));
+        GS_TRY(read_published(c, ctrs, s));
         M = ctrs[0];
         const int64_t gate = ctrs[4];
         for (int b = 0; b < B; ++b)
@@ -946,7 +974,12 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
 
     if (!tail_done) {
         GS_TRY(tail_and_labels(cur, wide, M, nullptr));
-        GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
+        if (N > 0) {  // published by the labels kernel
+            int64_t ctrs[8];
+            GS_TRY(read_published(c, ctrs, s));
+        } else {
+            GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
+        }
     }
     for (int b = 0; b < B; ++b) {
         if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");
@@ -1191,6 +1224,7 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
         if (!tiles.empty()) std::memcpy(img.data() + o_tiles, tiles.data(), sizeof(gs::RowTile) * tiles.size());
     }
     GS_TRY(h2d(c, base, img.data(), up_end, s));
+    GS_TRY(hmap_ensure(c, B));
     {
         void* old = c->shist.p;
         GS_TRY(ensure(c->shist, gs::kHistEntries * 4));
@@ -1427,6 +1461,7 @@ void gs_context_destroy(gs_context* c) {
     if (c->up_used > 0) (void)hipStreamSynchronize(c->up_stream);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->up) (void)hipHostFree(c->up);
+    if (c->hmap) (void)hipHostFree(c->hmap);
     for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
     if (c->aux) {
         (void)hipStreamSynchronize(c->aux);

@@ -365,7 +365,7 @@ template <class Op>
 __global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __restrict__ n_ptr, int64_t n_val,
                                                        uint64_t* __restrict__ look, uint32_t* __restrict__ tile_ctr,
                                                        uint32_t tile_base, uint32_t epoch,
-                                                       int64_t* __restrict__ total) {
+                                                       int64_t* __restrict__ total, int64_t* __restrict__ total_host) {
     constexpr int W = kScanThreads / kWave;
     __shared__ int64_t s_tile;
     __shared__ uint32_t wtot[W];
@@ -424,7 +424,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Op op, const int64_t* __r
         }
         if (lane == 0) {
             s_excl = excl;
-            if (t0 + kScanTile >= n) *total = int64_t(excl + tot);
+            if (t0 + kScanTile >= n) {
+                *total = int64_t(excl + tot);
+                if (total_host) *total_host = int64_t(excl + tot);
+            }
         }
     }
     __syncthreads();
@@ -934,13 +937,27 @@ __global__ __launch_bounds__(256) void k_merge_prep(CellTable t, int64_t m, cons
         if (hl[i]) atomicAdd(&hc[i], hl[i]);
 }
 
+// One block copies the 8 counters and the B instance states into host
+// memory mapped for the device (host [counters 8][states B]), which the host
+// reads after its next wait on the stream instead of copying them back.
+// Every thread of the block calls this after a barrier that orders the
+// counter and state writes it publishes.
+__device__ inline void publish_host(const int64_t* __restrict__ ctr, const InstState* __restrict__ st, int B,
+                                    int64_t* __restrict__ host) {
+    constexpr int SW = int(sizeof(InstState) / sizeof(int64_t));
+    static_assert(sizeof(InstState) % sizeof(int64_t) == 0, "states are copied in 64-bit words");
+    const int64_t* sw = reinterpret_cast<const int64_t*>(st);
+    for (int i = threadIdx.x; i < 8 + SW * B; i += blockDim.x) host[i] = i < 8 ? ctr[i] : sw[i - 8];
+}
+
 // End of a wide round: initial cell -> current cell maps (threads < m0) and
 // the per-instance round count and stationarity (threads < B).
 // With `gate` (a single block holding every instance) it also writes
 // whether some active instance still holds more cells than a tail workgroup.
 __global__ void k_round_end(uint32_t* __restrict__ cur, int64_t m0, const uint32_t* __restrict__ g,
                             InstState* __restrict__ st, int B, int32_t* __restrict__ applied,
-                            int64_t* __restrict__ gate) {
+                            int64_t* __restrict__ gate, const int64_t* __restrict__ ctr,
+                            int64_t* __restrict__ host) {
     __shared__ int any;
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gate && threadIdx.x == 0) any = 0;
@@ -967,6 +984,10 @@ __global__ void k_round_end(uint32_t* __restrict__ cur, int64_t m0, const uint32
     if (big) any = 1;
     __syncthreads();
     if (threadIdx.x == 0) *gate = any;
+    if (host) {
+        __syncthreads();
+        publish_host(ctr, st, B, host);
+    }
 }
 
 // ===========================================================================
@@ -1346,7 +1367,8 @@ __device__ inline int tail_cand(const TailWindow& w, int e) {
 // replay_r0); the fit's outputs and state are left untouched.
 // Whether some active instance still holds more cells than a tail workgroup
 // (the tail launched right after a device-wide round checks it first).
-__global__ void k_tail_gate(const InstState* __restrict__ st, int B, int64_t* __restrict__ gate) {
+__global__ void k_tail_gate(const InstState* __restrict__ st, int B, int64_t* __restrict__ gate,
+                            const int64_t* __restrict__ ctr, int64_t* __restrict__ host) {
     __shared__ int any;
     if (threadIdx.x == 0) any = 0;
     __syncthreads();
@@ -1354,6 +1376,10 @@ __global__ void k_tail_gate(const InstState* __restrict__ st, int B, int64_t* __
         if (st[b].active && st[b].ce - st[b].cs > kTailCells) any = 1;
     __syncthreads();
     if (threadIdx.x == 0) *gate = any;
+    if (host) {
+        __syncthreads();
+        publish_host(ctr, st, B, host);
+    }
 }
 
 // With `gate` set and nonzero the kernel returns at once, changing nothing.
@@ -2016,7 +2042,8 @@ constexpr int kLabelBlocks = 2048;
 __global__ __launch_bounds__(256) void k_labels(const uint32_t* __restrict__ cell0, const uint32_t* __restrict__ cur,
                                                 const uint32_t* __restrict__ tmap, int32_t* __restrict__ labels,
                                                 int64_t n, const int64_t* __restrict__ gate,
-                                                const InstState* __restrict__ st, int B, int64_t* __restrict__ koff) {
+                                                const InstState* __restrict__ st, int B, int64_t* __restrict__ koff,
+                                                const int64_t* __restrict__ ctr, int64_t* __restrict__ host) {
     if (gate && *gate) return;
     if (koff && blockIdx.x == 0) {  // first output row of every instance's clusters
         __shared__ int64_t wt[4];
@@ -2040,6 +2067,7 @@ __global__ __launch_bounds__(256) void k_labels(const uint32_t* __restrict__ cel
         }
         if (threadIdx.x == 0) koff[0] = 0;
     }
+    if (host && blockIdx.x == 0) publish_host(ctr, st, B, host);  // the tail's final states
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += 4 * stride) {
         uint32_t c[4];
