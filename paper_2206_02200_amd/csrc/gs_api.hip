@@ -485,6 +485,21 @@ gs_status segsum(gs_context* c, int d, Src src, gs::CellTable t, int64_t m_bound
     return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
 }
 
+// Look-back storage of the radix sort for n keys of `bits` bits (grown and
+// cleared when too small).
+gs_status sort_look_ensure(gs_context* c, int64_t n, int bits, hipStream_t s) {
+    const int64_t words = gs::sort_look_words(n, bits);
+    if (c->slook.cap < size_t(words) * 8) {
+        GS_TRY(ensure(c->slook, size_t(words) * 8));
+        k_fill_u64<<<blocks_for(c->slook.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->slook), c->slook.cap / 8, 0);
+        GS_HIP(hipGetLastError());
+        c->sort.epoch = 0;
+    }
+    c->sort.look = P<uint64_t>(c->slook);
+    c->sort.look_words = int64_t(c->slook.cap / 8);
+    return GS_OK;
+}
+
 // Ready the dense key table for one more table (allocated and cleared on
 // first use or growth, cleared again before the epochs wrap) and hand out a
 // new epoch for its entries (c->dk_epoch is the last one handed out, so an
@@ -669,21 +684,15 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         GS_TRY(ensure(c->sctr, 64));
         if (c->sctr.p != old) c->sort.tile_base = 0x7fffffffull;  // new counter: cleared before its first use
     }
-    const int64_t sort_tiles = gs::sort_look_tiles(N);
-    if (c->slook.cap < size_t(sort_tiles) * 256 * 8) {
-        GS_TRY(ensure(c->slook, size_t(sort_tiles) * 256 * 8));
-        k_fill_u64<<<blocks_for(c->slook.cap / 8, 256), 256, 0, s>>>(P<uint64_t>(c->slook), c->slook.cap / 8, 0);
-        c->sort.epoch = 0;
-    }
+    GS_TRY(sort_look_ensure(c, N, bits, s));
     c->sort.hist = P<uint32_t>(c->shist);
     c->sort.ctr = P<uint32_t>(c->sctr);
-    c->sort.look = P<uint64_t>(c->slook);
-    c->sort.look_tiles = int64_t(c->slook.cap / (256 * 8));
     c->sort.prof_ctx = c;
     c->sort.prof_begin = sort_prof_begin;
     c->sort.prof_end = sort_prof_end;
 
-    const int np = gs::sort_passes(bits);
+    const gs::SortPlan plan = gs::sort_plan(bits);
+    const int np = plan.passes;
     if (c->ntiles > 0) {  // the current histogram buffer is zero (cleared by the previous sort)
         const unsigned g = unsigned(c->ntiles);
         const unsigned ksplit = 1;
@@ -693,7 +702,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
 #define GS_MK(D) \
     case D:                                                                                                    \
         gs::k_make_keys<T, K, D><<<g * ksplit, gs::kBoxThreads, 0, s>>>(x, ld, tl, prm, P<K>(c->kA), np,        \
-                                                                        c->sort.cur_hist(), ksplit);            \
+                                                                        plan.digit, c->sort.cur_hist(), ksplit); \
         break;
             GS_MK(1) GS_MK(2) GS_MK(3) GS_MK(4) GS_MK(5) GS_MK(6)
 #undef GS_MK
@@ -905,7 +914,8 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
 #define GS_MS(D)                                                                                                   \
     case D:                                                                                                        \
         gs::k_merge_small<D><<<1, gs::kMergeThreads, 0, s>>>(TT, M, U, st, B, P<double>(c->pbuf),                  \
-                                                             P<uint64_t>(c->kappa), np, bits, P<uint32_t>(c->gmap), \
+                                                             P<uint64_t>(c->kappa), (bits + 7) / 8, bits,          \
+                                                             P<uint32_t>(c->gmap),                                 \
                                                              P<uint32_t>(c->cvA), P<uint32_t>(c->cur), m0, gt,     \
                                                              ctr, max_iter, dk_next, dk_pre_epoch);                \
         break;
@@ -929,7 +939,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         PROF_LAUNCH("merge_prep", M * (8.0 * 3 + 16.0 * d + sizeof(K)),
                     gs::k_merge_prep<K><<<blocks_for(M, 256), 256, 0, s>>>(TT, M, st, st, P<double>(c->pbuf),
                                                                             P<uint64_t>(c->kappa), P<K>(c->ckA), d,
-                                                                            np, c->sort.cur_hist()));
+                                                                            np, plan.digit, c->sort.cur_hist()));
         GS_HIP(hipGetLastError());
         K* mk = nullptr;
         uint32_t* mperm = nullptr;
@@ -1395,6 +1405,7 @@ static gs_status loss_bwd(gs_context* c, const T* x, const int32_t* labels, cons
     GS_HIP(hipGetLastError());
     int bits = 0;
     while ((int64_t(1) << bits) < rows) ++bits;
+    GS_TRY(sort_look_ensure(c, m0, bits, s));
     uint32_t* sk = nullptr;
     uint32_t* sperm = nullptr;
     GS_HIP(gs::radix_sort<uint32_t>(P<uint32_t>(c->xkA), P<uint32_t>(c->xkB), P<uint32_t>(c->xvA),

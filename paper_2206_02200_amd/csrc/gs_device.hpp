@@ -155,6 +155,62 @@ __device__ __forceinline__ uint64_t lb_exclusive(const uint64_t* status, int64_t
     return excl;
 }
 
+// lb_exclusive for N adjacent status columns at once (status + j for column
+// j): each column keeps its own position and stops at its own inclusive
+// prefix, and every round trip reads the next kWin words of every column
+// still walking.
+template <int kWin, int N>
+__device__ __forceinline__ void lb_exclusive_cols(const uint64_t* status, int64_t tile, int64_t stride,
+                                                  uint32_t epoch, uint64_t* excl) {
+    const uint32_t ep = epoch & 0xffffu;
+    int64_t p[N];
+    bool done[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        excl[j] = 0;
+        p[j] = tile - 1;
+        done[j] = p[j] < 0;
+    }
+    for (;;) {
+        bool all = true;
+#pragma unroll
+        for (int j = 0; j < N; ++j) all = all && done[j];
+        if (all) break;
+        uint64_t w[N][kWin];
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int i = 0; i < kWin; ++i)
+                w[j][i] = (!done[j] && p[j] - i >= 0) ? lb_load(status + (p[j] - i) * stride + j) : 0ull;
+        bool stalled = false;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            if (done[j]) continue;
+            int used = 0;
+            bool fin = false;
+#pragma unroll
+            for (int i = 0; i < kWin; ++i) {
+                if (fin || used != i) continue;
+                if (p[j] - i < 0) {
+                    fin = true;
+                    continue;
+                }
+                if (lb_epoch(w[j][i]) != ep || lb_flag(w[j][i]) == 0) continue;  // not published yet
+                excl[j] += lb_value(w[j][i]);
+                ++used;
+                if (lb_flag(w[j][i]) == kFlagPrefix) fin = true;
+            }
+            if (fin) {
+                done[j] = true;
+            } else {
+                p[j] -= used;
+                stalled = stalled || used < kWin;
+            }
+        }
+        if (kLookSleep > 0 && stalled) __builtin_amdgcn_s_sleep(kLookSleep);
+    }
+}
+
 // Look-back by a whole wave for one status word per tile: lane l reads
 // predecessor p - l, so 64 predecessors cost one round trip.  Every lane
 // returns the exclusive prefix.

@@ -225,18 +225,20 @@ template <typename T, typename K, int D>
 __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__ x, int64_t ld,
                                                            const RowTile* __restrict__ tiles,
                                                            const InstParam* __restrict__ param,
-                                                           K* __restrict__ keys, int npasses,
+                                                           K* __restrict__ keys, int npasses, int digit,
                                                            uint32_t* __restrict__ hist, int split) {
     using S = Stager<T, D>;
     constexpr int R = S::R;
     constexpr int RPT = R / kBoxThreads;
     __shared__ T stage[R * D];
-    __shared__ uint32_t hl[kSortMaxPasses * 256];
+    __shared__ uint32_t hl[kHistLds];  // pass p, digit v at (p << digit) + v
     __shared__ InstParam sp;
     const RowTile tl = tile_part(tiles, split, R);
     if (tl.r0 >= tl.r1) return;
     const int tid = threadIdx.x, lane = lane_id();
-    for (int i = tid; i < npasses * 256; i += kBoxThreads) hl[i] = 0;
+    const int nh = npasses << digit;
+    const uint32_t dmask = (1u << digit) - 1u;
+    for (int i = tid; i < nh; i += kBoxThreads) hl[i] = 0;
     if (tid == 0) sp = param[tl.inst];
     S sg;
     int64_t c0 = tl.r0;
@@ -283,12 +285,12 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__
             if (!act) continue;
             const int lead = __ffsll((unsigned long long)act) - 1;
             for (int p = 0; p < npasses; ++p) {
-                const uint32_t dgt = uint32_t(kv[i] >> (8 * p)) & 255u;
+                const uint32_t dgt = uint32_t(kv[i] >> (digit * p)) & dmask;
                 const uint32_t d0 = __shfl(dgt, lead, kWave);
                 if (__ballot(valid && dgt == d0) == act) {
-                    if (lane == lead) atomicAdd(&hl[p * 256 + d0], uint32_t(__popcll(act)));
+                    if (lane == lead) atomicAdd(&hl[(p << digit) + d0], uint32_t(__popcll(act)));
                 } else if (valid) {
-                    atomicAdd(&hl[p * 256 + dgt], 1u);
+                    atomicAdd(&hl[(p << digit) + dgt], 1u);
                 }
             }
         }
@@ -297,8 +299,8 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__
         crows = nrows;
     }
     uint32_t* hc = hist + (blockIdx.x % kHistCopies) * kHistStride;
-    for (int i = tid; i < npasses * 256; i += kBoxThreads)
-        if (hl[i]) atomicAdd(&hc[i], hl[i]);
+    for (int i = tid; i < nh; i += kBoxThreads)
+        if (hl[i]) atomicAdd(&hc[hist_index(i, digit)], hl[i]);
 }
 
 // ===========================================================================
@@ -905,10 +907,12 @@ template <typename K>
 __global__ __launch_bounds__(256) void k_merge_prep(CellTable t, int64_t m, const InstState* __restrict__ stc,
                                                     InstState* __restrict__ st, const double* __restrict__ pbuf,
                                                     const uint64_t* __restrict__ kappa, K* __restrict__ skey, int d,
-                                                    int npasses, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t hl[kSortMaxPasses * 256];
+                                                    int npasses, int digit, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t hl[kHistLds];  // pass p, digit v at (p << digit) + v
     const int tid = threadIdx.x, lane = lane_id();
-    for (int i = tid; i < npasses * 256; i += 256) hl[i] = 0;
+    const int nh = npasses << digit;
+    const uint32_t dmask = (1u << digit) - 1u;
+    for (int i = tid; i < nh; i += 256) hl[i] = 0;
     __syncthreads();
     const int64_t j0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const bool valid = j0 < m;
@@ -922,19 +926,19 @@ __global__ __launch_bounds__(256) void k_merge_prep(CellTable t, int64_t m, cons
     if (act) {
         const int lead = __ffsll((unsigned long long)act) - 1;
         for (int p = 0; p < npasses; ++p) {
-            const uint32_t dgt = uint32_t(out >> (8 * p)) & 255u;
+            const uint32_t dgt = uint32_t(out >> (digit * p)) & dmask;
             const uint32_t d0 = __shfl(dgt, lead, kWave);
             if (__ballot(valid && dgt == d0) == act) {
-                if (lane == lead) atomicAdd(&hl[p * 256 + d0], uint32_t(__popcll(act)));
+                if (lane == lead) atomicAdd(&hl[(p << digit) + d0], uint32_t(__popcll(act)));
             } else if (valid) {
-                atomicAdd(&hl[p * 256 + dgt], 1u);
+                atomicAdd(&hl[(p << digit) + dgt], 1u);
             }
         }
     }
     __syncthreads();
     uint32_t* hc = hist + (blockIdx.x % kHistCopies) * kHistStride;
-    for (int i = tid; i < npasses * 256; i += 256)
-        if (hl[i]) atomicAdd(&hc[i], hl[i]);
+    for (int i = tid; i < nh; i += 256)
+        if (hl[i]) atomicAdd(&hc[hist_index(i, digit)], hl[i]);
 }
 
 // One block copies the 8 counters and the B instance states into host

@@ -1,5 +1,5 @@
 // Stable LSD radix sort of (key, index) pairs, one read and one write of the
-// pairs per 8-bit digit (a single-pass "onesweep" scheme):
+// pairs per digit of 8 or 10 bits (a single-pass "onesweep" scheme):
 //   * all digit histograms come from one up-front pass (or from the key
 //     producer, which fuses it); every tile derives its pass's digit bases
 //     from them, and the first pass clears the other of two histogram
@@ -19,17 +19,18 @@ namespace gs {
 
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const K* __restrict__ keys, int64_t n, int npasses,
-                                                            uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[kSortMaxPasses * 256];
-    for (int i = threadIdx.x; i < npasses * 256; i += kSortThreads) h[i] = 0;
+                                                            int digit, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[kHistLds];
+    const int nh = npasses << digit;
+    for (int i = threadIdx.x; i < nh; i += kSortThreads) h[i] = 0;
     __syncthreads();
     const int64_t stride = int64_t(gridDim.x) * kSortThreads;
     for (int64_t i = int64_t(blockIdx.x) * kSortThreads + threadIdx.x; i < n; i += stride)
-        sort_hist_add<K>(h, keys[i], npasses);
+        sort_hist_add<K>(h, keys[i], npasses, digit);
     __syncthreads();
     uint32_t* hc = hist + (blockIdx.x % kHistCopies) * kHistStride;
-    for (int i = threadIdx.x; i < npasses * 256; i += kSortThreads)
-        if (h[i]) atomicAdd(&hc[i], h[i]);
+    for (int i = threadIdx.x; i < nh; i += kSortThreads)
+        if (h[i]) atomicAdd(&hc[hist_index(i, digit)], h[i]);
 }
 
 __global__ void k_iota(uint32_t* __restrict__ v, int64_t n) {
@@ -49,7 +50,10 @@ __global__ void k_clear_u64(uint64_t* __restrict__ p, int64_t n) {
 
 constexpr int kSortLookWindow = 4;
 
-template <typename K>
+// One pass over digit (key >> shift) of DIG bits (the last pass ranks only
+// its nbits significant bits).  Threads t < RADIX / DPT own digits
+// t * DPT .. t * DPT + DPT - 1.
+template <typename K, int DIG>
 __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                             K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                             int64_t n, int shift, int nbits,
@@ -58,12 +62,16 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
                                                             uint64_t* __restrict__ look, uint32_t* __restrict__ ctr,
                                                             uint32_t tile_base, uint32_t epoch) {
     constexpr int W = kPassThreads / kWave;
-    static_assert(kPassThreads >= 256 && kPassThreads % 256 == 0, "threads 0..255 own one digit each");
-    __shared__ uint32_t wcnt[W][256];    // per-wave digit counts, then their exclusive scan over waves
-    __shared__ uint32_t doff[256];       // tile-local exclusive digit offsets
-    __shared__ uint32_t wsum[4];         // per-wave totals of the digit scan (waves 0..3)
-    __shared__ uint32_t hsum[4];         // per-wave totals of the histogram scan (waves 0..3)
-    __shared__ uint32_t gbase[256];      // global position of the tile's first key of each digit
+    constexpr int RADIX = 1 << DIG;
+    constexpr int DPT = RADIX > kPassThreads ? RADIX / kPassThreads : 1;  // digits per owning thread
+    constexpr int OWN = RADIX / DPT;                                      // owning threads
+    constexpr int OW = OWN / kWave;                                       // owning waves
+    static_assert(OWN <= kPassThreads && OWN % kWave == 0, "digits are owned by whole waves");
+    __shared__ uint32_t wcnt[W][RADIX];  // per-wave digit counts, then their exclusive scan over waves
+    __shared__ uint32_t doff[RADIX];     // tile-local exclusive digit offsets
+    __shared__ uint32_t wsum[OW];        // per-wave totals of the digit scan (owning waves)
+    __shared__ uint32_t hsum[OW];        // per-wave totals of the histogram scan (owning waves)
+    __shared__ uint32_t gbase[RADIX];    // global position of the tile's first key of each digit
     __shared__ K skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
     __shared__ int64_t s_tile;
@@ -72,16 +80,22 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
     const int w = tid / kWave;
     const int lane = lane_id();
     if (tid == 0) s_tile = int64_t(atomicAdd(ctr, 1u) - tile_base);
-    for (int i = tid; i < W * 256; i += kPassThreads) (&wcnt[0][0])[i] = 0;
+    for (int i = tid; i < W * RADIX; i += kPassThreads) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t tile = s_tile;
     const int64_t t0 = tile * kSortTile;
-    // the pass's count of digit tid over all keys (its histogram copies),
-    // loaded now and scanned over the digits after the ranking
-    uint32_t dtot = 0;
-    if (tid < 256) {
+    const bool dig = tid < OWN;
+    const int d0 = tid * DPT;  // first digit of this thread
+    // the pass's count of each owned digit over all keys (its histogram
+    // copies), loaded now and scanned over the digits after the ranking
+    uint32_t dtot[DPT];
 #pragma unroll
-        for (int c = 0; c < kHistCopies; ++c) dtot += hist[c * kHistStride + tid];
+    for (int j = 0; j < DPT; ++j) dtot[j] = 0;
+    if (dig) {
+#pragma unroll
+        for (int c = 0; c < kHistCopies; ++c)
+#pragma unroll
+            for (int j = 0; j < DPT; ++j) dtot[j] += hist[c * kHistStride + d0 + j];
     }
     if (clear) {  // this tile's slice of the other histogram buffer
         const int64_t total = int64_t(kHistCopies) * kHistStride;
@@ -116,10 +130,10 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const bool valid = wbase + i * kWave < n;
-        const uint32_t dgt = uint32_t(key[i] >> shift) & 255u;
+        const uint32_t dgt = uint32_t(key[i] >> shift) & uint32_t(RADIX - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < DIG; ++b) {
             if (b >= nbits) break;  // digits of the last pass may be narrower (higher bits are zero)
             const bool bit = (dgt >> b) & 1u;
             const uint64_t bal = __ballot(bit);
@@ -132,26 +146,38 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
     }
     __syncthreads();
 
-    // Scan the per-wave counts over waves (digit = thread) and publish the
-    // tile total for the look-back at once, so that later tiles can use it.
-    const bool dig = tid < 256;
-    uint32_t run = 0;  // this tile's count of digit tid
-    uint64_t* st = look + tile * 256 + tid;
+    // Scan the per-wave counts over waves (per owned digit) and publish the
+    // tile totals for the look-back at once, so that later tiles can use them.
+    uint32_t run[DPT];  // this tile's count of each owned digit
+    uint64_t* st = look + tile * RADIX + d0;
     if (dig) {
 #pragma unroll
-        for (int ww = 0; ww < W; ++ww) {
-            const uint32_t c = wcnt[ww][tid];
-            wcnt[ww][tid] = run;
-            run += c;
+        for (int j = 0; j < DPT; ++j) {
+            run[j] = 0;
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww) {
+                const uint32_t c = wcnt[ww][d0 + j];
+                wcnt[ww][d0 + j] = run[j];
+                run[j] += c;
+            }
+            lb_store(st + j, lb_pack(epoch, tile == 0 ? kFlagPrefix : kFlagAgg, run[j]));
         }
-        lb_store(st, lb_pack(epoch, tile == 0 ? kFlagPrefix : kFlagAgg, run));
+    } else {
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) run[j] = 0;
     }
-    // tile-local exclusive scan over the 256 digit totals and global one over
-    // the pass's digit counts (digit = thread): within each of waves 0..3 by
-    // shuffles, then across their totals
-    uint32_t dbase = 0;  // keys of all smaller digits in the whole pass
+    // tile-local exclusive scan over the digit totals and global one over the
+    // pass's digit counts: within the thread over its digits, then a DPP scan
+    // over the owning waves' lanes, then across those waves' totals
+    uint32_t dbase[DPT];  // keys of all smaller digits in the whole pass
     {
-        const uint32_t incl = wave_incl_scan_u32(run), hincl = wave_incl_scan_u32(dtot);
+        uint32_t tsum = 0, hts = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            tsum += run[j];
+            hts += dtot[j];
+        }
+        const uint32_t incl = wave_incl_scan_u32(tsum), hincl = wave_incl_scan_u32(hts);
         if (dig && lane == kWave - 1) {
             wsum[w] = incl;
             hsum[w] = hincl;
@@ -160,12 +186,18 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
         if (dig) {
             uint32_t before = 0, hbefore = 0;
 #pragma unroll
-            for (int ww = 0; ww < 4; ++ww) {
+            for (int ww = 0; ww < OW; ++ww) {
                 before += ww < w ? wsum[ww] : 0u;
                 hbefore += ww < w ? hsum[ww] : 0u;
             }
-            doff[tid] = before + incl - run;
-            dbase = hbefore + hincl - dtot;
+            uint32_t a = before + incl - tsum, ha = hbefore + hincl - hts;
+#pragma unroll
+            for (int j = 0; j < DPT; ++j) {
+                doff[d0 + j] = a;
+                dbase[j] = ha;
+                a += run[j];
+                ha += dtot[j];
+            }
         }
     }
     __syncthreads();
@@ -176,21 +208,27 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
     for (int i = 0; i < kSortItems; ++i) {
         const int64_t pos = t0 + int64_t(w) * (kWave * kSortItems) + i * kWave + lane;
         if (pos < n) {
-            const uint32_t dgt = uint32_t(key[i] >> shift) & 255u;
+            const uint32_t dgt = uint32_t(key[i] >> shift) & uint32_t(RADIX - 1);
             const uint32_t lp = doff[dgt] + wcnt[w][dgt] + rank[i];
             skey[lp] = key[i];
             sval[lp] = val[i];
         }
     }
-    // Exclusive prefix of digit tid over all earlier tiles (decoupled
-    // look-back, kSortLookWindow predecessors per round trip), then this tile's prefix.
+    // Exclusive prefix of each owned digit over all earlier tiles (decoupled
+    // look-back, kSortLookWindow predecessors per round trip), then this
+    // tile's prefix.
     if (dig) {
         if (tile == 0) {
-            gbase[tid] = dbase;
+#pragma unroll
+            for (int j = 0; j < DPT; ++j) gbase[d0 + j] = dbase[j];
         } else {
-            const uint64_t excl = lb_exclusive<kSortLookWindow>(look + tid, tile, 256, epoch);
-            lb_store(st, lb_pack(epoch, kFlagPrefix, excl + run));
-            gbase[tid] = dbase + uint32_t(excl);
+            uint64_t excl[DPT];
+            lb_exclusive_cols<kSortLookWindow, DPT>(look + d0, tile, RADIX, epoch, excl);
+#pragma unroll
+            for (int j = 0; j < DPT; ++j) {
+                lb_store(st + j, lb_pack(epoch, kFlagPrefix, excl[j] + run[j]));
+                gbase[d0 + j] = dbase[j] + uint32_t(excl[j]);
+            }
         }
     }
     __syncthreads();
@@ -199,7 +237,7 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
     const int64_t cnt = (n - t0) < kSortTile ? (n - t0) : kSortTile;
     for (int j = tid; j < cnt; j += kPassThreads) {
         const K k = skey[j];
-        const uint32_t dgt = uint32_t(k >> shift) & 255u;
+        const uint32_t dgt = uint32_t(k >> shift) & uint32_t(RADIX - 1);
         const uint32_t g = gbase[dgt] + (uint32_t(j) - doff[dgt]);
         kout[g] = k;
         vout[g] = sval[j];
@@ -209,7 +247,8 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
 template <typename K>
 hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int bits, bool hist_ready,
                       SortScratch& sc, hipStream_t s, K** kout, uint32_t** vout) {
-    const int np = sort_passes(bits);
+    const SortPlan plan = sort_plan(bits);
+    const int np = plan.passes, dg = plan.digit;
     *kout = kA;
     *vout = vA;
     if (n <= 0) return hipSuccess;
@@ -218,15 +257,16 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
         return hipGetLastError();
     }
     const int64_t tiles = sort_look_tiles(n);
-    if (tiles > sc.look_tiles) return hipErrorInvalidValue;
+    if (tiles * (int64_t(1) << dg) > sc.look_words) return hipErrorInvalidValue;
     uint32_t* hcur = sc.hist + int64_t(sc.parity) * kHistCopies * kHistStride;
     uint32_t* hother = sc.hist + int64_t(sc.parity ^ 1) * kHistCopies * kHistStride;
     if (!hist_ready) {
-        k_clear_u32<<<dim3(kSortMaxPasses * kHistCopies), dim3(256), 0, s>>>(hcur, kHistCopies * kHistStride);
+        k_clear_u32<<<dim3(unsigned((kHistCopies * kHistStride + 255) / 256)), dim3(256), 0, s>>>(
+            hcur, kHistCopies * kHistStride);
         int64_t blocks = (n + kSortThreads * 16 - 1) / (kSortThreads * 16);
         if (blocks > 2048) blocks = 2048;
         const int tk = sc.prof_begin ? sc.prof_begin(sc.prof_ctx, s, "sort_hist") : -1;
-        k_sort_hist<K><<<dim3(unsigned(blocks)), dim3(kSortThreads), 0, s>>>(kA, n, np, hcur);
+        k_sort_hist<K><<<dim3(unsigned(blocks)), dim3(kSortThreads), 0, s>>>(kA, n, np, dg, hcur);
         if (sc.prof_end) sc.prof_end(sc.prof_ctx, s, tk, double(n) * sizeof(K));
     }
     K* ki = kA;
@@ -235,8 +275,7 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
     uint32_t* vo = vA;
     for (int p = 0; p < np; ++p) {
         if (sc.epoch >= 0xffffu) {  // epochs wrap: clear the status words once
-            k_clear_u64<<<dim3(unsigned((sc.look_tiles * 256 + 255) / 256)), dim3(256), 0, s>>>(
-                sc.look, sc.look_tiles * 256);
+            k_clear_u64<<<dim3(unsigned((sc.look_words + 255) / 256)), dim3(256), 0, s>>>(sc.look, sc.look_words);
             sc.epoch = 0;
         }
         if (sc.tile_base + uint64_t(tiles) >= 0x7fffffffull) {  // first use, or the counter nears overflow
@@ -247,9 +286,15 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
         const uint32_t base = uint32_t(sc.tile_base);
         sc.tile_base += uint64_t(tiles);
         const int tk = sc.prof_begin ? sc.prof_begin(sc.prof_ctx, s, "sort_pass") : -1;
-        k_sort_pass<K><<<dim3(unsigned(tiles)), dim3(kPassThreads), 0, s>>>(
-            ki, vi, ko, vo, n, 8 * p, bits - 8 * p < 8 ? bits - 8 * p : 8, hcur + p * 256, p == 0 ? hother : nullptr,
-            tiles, sc.look, sc.ctr, base, ep);
+        const int nb = bits - dg * p < dg ? bits - dg * p : dg;
+        if (dg == 10)
+            k_sort_pass<K, 10><<<dim3(unsigned(tiles)), dim3(kPassThreads), 0, s>>>(
+                ki, vi, ko, vo, n, dg * p, nb, hcur + p * kRadixMax, p == 0 ? hother : nullptr, tiles, sc.look, sc.ctr,
+                base, ep);
+        else
+            k_sort_pass<K, 8><<<dim3(unsigned(tiles)), dim3(kPassThreads), 0, s>>>(
+                ki, vi, ko, vo, n, dg * p, nb, hcur + p * kRadixMax, p == 0 ? hother : nullptr, tiles, sc.look, sc.ctr,
+                base, ep);
         // reads keys (and values after the first pass), writes keys and values
         if (sc.prof_end)
             sc.prof_end(sc.prof_ctx, s, tk, double(n) * (sizeof(K) + (p ? 4 : 0) + sizeof(K) + 4));
