@@ -15,6 +15,10 @@
  *     and of the supplement's update of r_j: every active cell j moves to the
  *     count-weighted mean of the centroids of the active cells j+v,
  *     v in {-1,0,1}^d (itself included), all read from the same iteration.
+ *     gso_fit_rule also offers the sequential form of Eq. 5 (Section 2.2):
+ *     the cells are visited one after another and a visited cell's new
+ *     centroid replaces its old one for the cells visited after it, in
+ *     ascending key or colour by colour (gso_colour_order).
  *   - Section 2.1 (iii): the moved cell gets the key floor(p_j / h).
  *   - Section 2.1 (iv), Eq. 3-4: cells that land on one key merge; counts add,
  *     the centroid is the count-weighted mean, the point sets are united.
@@ -263,6 +267,81 @@ void gso_shift(const int64_t* keys, const int64_t* counts, const double* sums, i
 }
 
 /* ---------------------------------------------------------------------- */
+/* Step 3, sequential form (Eq. 5, Section 2.2; Algorithm 1 writes S'(j)   */
+/* in place while looping over the keys).                                  */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * The cells are visited one at a time, in the order order[0], order[1], ...
+ * (a permutation of 0..m-1).  Visiting j computes W_j and the left fold N_j
+ * in ascending neighbour key exactly as gso_shift does, except that a
+ * neighbour k already visited in this sweep contributes C_k times its new
+ * centroid, fl(C_k * p_k), in place of its sum S_k: the centroids are
+ * updated in place and later cells read the updated value, while the
+ * weights C stay those of the round's table.  p_j = N_j / W_j.
+ * Returns GSO_ERR_ALLOC or GSO_OK.
+ */
+int gso_shift_seq(const int64_t* keys, const int64_t* counts, const double* sums, int64_t m, int32_t d,
+                  const int64_t* order, double* p, int64_t* weights)
+{
+    int64_t n_off = 1, v[16], q[16];
+    for (int k = 0; k < d; k++)
+        n_off *= 3;
+    double* cur = malloc(sizeof(double) * (m > 0 ? m : 1) * d); /* C_k * centroid_k */
+    if (!cur)
+        return GSO_ERR_ALLOC;
+    memcpy(cur, sums, sizeof(double) * m * d);
+    for (int64_t r0 = 0; r0 < m; r0++) {
+        const int64_t j = order[r0];
+        int64_t W = 0;
+        int first = 1;
+        double* pj = p + j * d;
+        for (int64_t r = 0; r < n_off; r++) {
+            offset_of(r, d, v);
+            for (int k = 0; k < d; k++)
+                q[k] = keys[j * d + k] + v[k];
+            int64_t nb = find_cell(keys, m, d, q);
+            if (nb < 0)
+                continue;
+            W += counts[nb];
+            for (int k = 0; k < d; k++)
+                pj[k] = first ? cur[nb * d + k] : pj[k] + cur[nb * d + k];
+            first = 0;
+        }
+        for (int k = 0; k < d; k++) {
+            pj[k] = pj[k] / (double)W;
+            cur[j * d + k] = (double)counts[j] * pj[k];
+        }
+        if (weights)
+            weights[j] = W;
+    }
+    free(cur);
+    return GSO_OK;
+}
+
+/*
+ * Colour of a cell: bit (d-1-k) is the parity of its integer coordinate k
+ * (dimension 0 most significant).  Two distinct cells of one colour differ
+ * by an even, hence non-zero by at least 2, amount in some coordinate, so
+ * they are never neighbours: visiting the cells colour by colour, ascending
+ * colour and ascending key within a colour, is a sequential sweep whose
+ * cells of one colour could be visited in any order, or all at once.
+ * order [m] receives that visiting order of the (key-sorted) cells.
+ */
+void gso_colour_order(const int64_t* keys, int64_t m, int32_t d, int64_t* order)
+{
+    int64_t r = 0;
+    for (int64_t c = 0; c < ((int64_t)1 << d); c++)
+        for (int64_t j = 0; j < m; j++) {
+            int64_t cj = 0;
+            for (int k = 0; k < d; k++)
+                cj = (cj << 1) | (((keys[j * d + k] % 2) + 2) % 2);
+            if (cj == c)
+                order[r++] = j;
+        }
+}
+
+/* ---------------------------------------------------------------------- */
 /* Step 4: relocation and merge (Section 2.1 (iii)-(iv), Eq. 3-4).         */
 /* ---------------------------------------------------------------------- */
 
@@ -414,11 +493,16 @@ void gso_tape_free(gso_tape* tp)
 /* The whole fit.                                                         */
 /* ---------------------------------------------------------------------- */
 
-static int fit_impl(const double* x, int64_t n, int32_t d, double h, int32_t max_iter, int32_t* labels,
-                    double* modes, int64_t* counts, double* sums, int64_t* keys_out, int64_t* m_hist,
-                    int64_t* K_out, int32_t* n_iter_out, uint32_t* flags_out, gso_tape* tp)
+/* Update rules of a round's shift. */
+enum { GSO_RULE_PARALLEL = 0, GSO_RULE_SEQ_KEY = 1, GSO_RULE_SEQ_COLOUR = 2 };
+
+static int fit_impl(const double* x, int64_t n, int32_t d, double h, int32_t max_iter, int32_t rule,
+                    int32_t* labels, double* modes, int64_t* counts, double* sums, int64_t* keys_out,
+                    int64_t* m_hist, int64_t* K_out, int32_t* n_iter_out, uint32_t* flags_out, gso_tape* tp)
 {
     if (n < 0 || d < 1 || d > 16 || max_iter < 0 || !(h > 0.0) || !isfinite(h))
+        return GSO_ERR_INVALID_ARG;
+    if (rule < GSO_RULE_PARALLEL || rule > GSO_RULE_SEQ_COLOUR || (tp && rule != GSO_RULE_PARALLEL))
         return GSO_ERR_INVALID_ARG;
     *K_out = 0;
     *n_iter_out = 0;
@@ -443,7 +527,7 @@ static int fit_impl(const double* x, int64_t n, int32_t d, double h, int32_t max
     int64_t* ckey = malloc(sizeof(int64_t) * n * d);
     int64_t* ccnt = malloc(sizeof(int64_t) * n);
     double* csum = malloc(sizeof(double) * n * d);
-    int64_t *cur = NULL, *g = NULL, *nkey = NULL, *ncnt = NULL, *W = NULL;
+    int64_t *cur = NULL, *g = NULL, *nkey = NULL, *ncnt = NULL, *W = NULL, *order = NULL;
     double *p = NULL, *nsum = NULL;
     if (!cell0 || !ckey || !ccnt || !csum) {
         rc = GSO_ERR_ALLOC;
@@ -460,7 +544,8 @@ static int fit_impl(const double* x, int64_t n, int32_t d, double h, int32_t max
     W = malloc(sizeof(int64_t) * m0);
     p = malloc(sizeof(double) * m0 * d);
     nsum = malloc(sizeof(double) * m0 * d);
-    if (!cur || !g || !nkey || !ncnt || !W || !p || !nsum) {
+    order = malloc(sizeof(int64_t) * m0);
+    if (!cur || !g || !nkey || !ncnt || !W || !p || !nsum || !order) {
         rc = GSO_ERR_ALLOC;
         goto done;
     }
@@ -493,7 +578,17 @@ static int fit_impl(const double* x, int64_t n, int32_t d, double h, int32_t max
             flags |= GSO_CAPPED;
             break;
         }
-        gso_shift(ckey, ccnt, csum, m, d, p, W);
+        if (rule == GSO_RULE_PARALLEL) {
+            gso_shift(ckey, ccnt, csum, m, d, p, W);
+        } else {
+            if (rule == GSO_RULE_SEQ_KEY)
+                for (int64_t c = 0; c < m; c++)
+                    order[c] = c;
+            else
+                gso_colour_order(ckey, m, d, order);
+            if ((rc = gso_shift_seq(ckey, ccnt, csum, m, d, order, p, W)) != GSO_OK)
+                goto done;
+        }
         int64_t nm = 0;
         if ((rc = gso_merge(ccnt, p, m, d, h, nkey, ncnt, nsum, g, &nm)) != GSO_OK)
             goto done;
@@ -553,6 +648,7 @@ done:
     free(W);
     free(p);
     free(nsum);
+    free(order);
     return rc;
 }
 
@@ -577,7 +673,24 @@ int gso_fit(const double* x, int64_t n, int32_t d, double h, int32_t max_iter,
             int32_t* labels, double* modes, int64_t* counts, double* sums, int64_t* keys_out,
             int64_t* m_hist, int64_t* K_out, int32_t* n_iter_out, uint32_t* flags_out)
 {
-    return fit_impl(x, n, d, h, max_iter, labels, modes, counts, sums, keys_out, m_hist, K_out, n_iter_out,
+    return fit_impl(x, n, d, h, max_iter, GSO_RULE_PARALLEL, labels, modes, counts, sums, keys_out, m_hist, K_out,
+                    n_iter_out, flags_out, NULL);
+}
+
+/*
+ * gso_fit with a choice of update rule for the shift of every round:
+ *   0  parallel (Eq. 6): every cell reads the round's table (gso_shift);
+ *   1  sequential (Eq. 5), the cells visited in ascending key;
+ *   2  sequential (Eq. 5), the cells visited colour by colour
+ *      (gso_colour_order), the sweep a device can run one colour at a time.
+ * Relocation, merge (the merge values are fl(C_j * p_j) in every rule) and
+ * the stopping tests are those of gso_fit.
+ */
+int gso_fit_rule(const double* x, int64_t n, int32_t d, double h, int32_t max_iter, int32_t rule,
+                 int32_t* labels, double* modes, int64_t* counts, double* sums, int64_t* keys_out,
+                 int64_t* m_hist, int64_t* K_out, int32_t* n_iter_out, uint32_t* flags_out)
+{
+    return fit_impl(x, n, d, h, max_iter, rule, labels, modes, counts, sums, keys_out, m_hist, K_out, n_iter_out,
                     flags_out, NULL);
 }
 
@@ -591,8 +704,8 @@ int gso_fit_tape(const double* x, int64_t n, int32_t d, double h, int32_t max_it
     *tape_out = NULL;
     if (!tp)
         return GSO_ERR_ALLOC;
-    int rc = fit_impl(x, n, d, h, max_iter, labels, modes, counts, sums, keys_out, m_hist, K_out, n_iter_out,
-                      flags_out, tp);
+    int rc = fit_impl(x, n, d, h, max_iter, GSO_RULE_PARALLEL, labels, modes, counts, sums, keys_out, m_hist, K_out,
+                      n_iter_out, flags_out, tp);
     if (rc != GSO_OK) {
         gso_tape_free(tp);
         return rc;

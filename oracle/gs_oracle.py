@@ -104,6 +104,15 @@ def _load():
         P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
         P, P, P, P, P, P, P, P, P,
     ]
+    lib.gso_fit_rule.restype = ctypes.c_int
+    lib.gso_fit_rule.argtypes = [
+        P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+        P, P, P, P, P, P, P, P, P,
+    ]
+    lib.gso_shift_seq.restype = ctypes.c_int
+    lib.gso_shift_seq.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, P, P, P]
+    lib.gso_colour_order.restype = None
+    lib.gso_colour_order.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P]
     _lib = lib
     return lib
 
@@ -132,8 +141,18 @@ class OracleResult:
     flags: int
 
 
-def fit(x, h: float, max_iter: int = 100) -> OracleResult:
-    """Run GridShift on points ``x`` ([n, d]; float32 is widened exactly)."""
+# update rules of the shift (gso_fit_rule)
+RULES = {"parallel": 0, "sequential_key": 1, "sequential": 2}
+
+
+def fit(x, h: float, max_iter: int = 100, rule: str = "parallel") -> OracleResult:
+    """Run GridShift on points ``x`` ([n, d]; float32 is widened exactly).
+
+    ``rule``: "parallel" (Eq. 6, every cell reads the round's table),
+    "sequential" (Eq. 5, cells visited colour by colour: ascending colour,
+    the colour's bit d-1-k being the parity of integer coordinate k, then
+    ascending key) or "sequential_key" (Eq. 5, cells visited in ascending
+    key)."""
     x = np.asarray(x)
     if x.ndim != 2:
         raise ValueError("x must be [n, d]")
@@ -149,8 +168,10 @@ def fit(x, h: float, max_iter: int = 100) -> OracleResult:
     K = ctypes.c_int64(0)
     T = ctypes.c_int32(0)
     flags = ctypes.c_uint32(0)
-    rc = _load().gso_fit(
-        _ptr(xd), n, d, float(h), int(max_iter),
+    if rule not in RULES:
+        raise ValueError(f"unknown rule {rule!r}")
+    rc = _load().gso_fit_rule(
+        _ptr(xd), n, d, float(h), int(max_iter), RULES[rule],
         _ptr(labels), _ptr(modes), _ptr(counts), _ptr(sums), _ptr(keys), _ptr(m_hist),
         ctypes.byref(K), ctypes.byref(T), ctypes.byref(flags),
     )
@@ -208,6 +229,35 @@ def shift(table: CellTable) -> tuple[np.ndarray, np.ndarray]:
     p = np.empty((max(m, 1), d), np.float64)
     W = np.empty(max(m, 1), np.int64)
     _load().gso_shift(_ptr(keys), _ptr(counts), _ptr(sums), m, d, _ptr(p), _ptr(W))
+    return p[:m].copy(), W[:m].copy()
+
+
+def colour_order(table: CellTable) -> np.ndarray:
+    """Visiting order of the sequential sweep used on the device: ascending
+    colour (bit d-1-k = parity of integer coordinate k), then ascending key."""
+    keys = np.ascontiguousarray(table.keys, dtype=np.int64)
+    m, d = keys.shape
+    order = np.empty(max(m, 1), np.int64)
+    _load().gso_colour_order(_ptr(keys), m, d, _ptr(order))
+    return order[:m].copy()
+
+
+def shift_sequential(table: CellTable, order) -> tuple[np.ndarray, np.ndarray]:
+    """Eq. 5 (sequential form): cells visited in ``order`` (a permutation of
+    the table's rows); a visited cell's fl(C * p) replaces its sum for the
+    cells visited after it.  Returns (p [m, d], W [m])."""
+    keys = np.ascontiguousarray(table.keys, dtype=np.int64)
+    counts = np.ascontiguousarray(table.counts, dtype=np.int64)
+    sums = np.ascontiguousarray(table.sums, dtype=np.float64)
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    m, d = keys.shape
+    if sorted(order.tolist()) != list(range(m)):
+        raise ValueError("order must be a permutation of the table's rows")
+    p = np.empty((max(m, 1), d), np.float64)
+    W = np.empty(max(m, 1), np.int64)
+    rc = _load().gso_shift_seq(_ptr(keys), _ptr(counts), _ptr(sums), m, d, _ptr(order), _ptr(p), _ptr(W))
+    if rc != 0:
+        raise OracleError(rc)
     return p[:m].copy(), W[:m].copy()
 
 

@@ -8,7 +8,13 @@ floating-point rounding:
 * the neighbour relation is the supplement's cell distance
   M(z, x; h) = max_k |floor(x_k/h) - floor(z_k/h)| <= 1, evaluated over all
   pairs of active cells (no 3^d offset enumeration);
-* the shift is the exact count-weighted mean of Eq. 1-2, parallel form Eq. 6;
+* the shift is the exact count-weighted mean of Eq. 1-2, parallel form Eq. 6,
+  or (``rule``) the sequential form of Eq. 5, written on centroids: the cells
+  are visited one after another and the centroid of a visited cell is
+  replaced by its new value for the cells visited after it, the weights
+  staying the counts of the round ("sequential_key": ascending key;
+  "sequential": ascending colour, the colour being the tuple of coordinate
+  parities with dimension 0 first, then ascending key);
 * merges use the exact weighted mean of Eq. 3-4;
 * stopping follows Section 2.1 (v) / Theorem 2, capped at max_iter, with the
   same early exit on an unchanged state.
@@ -26,7 +32,13 @@ def _cheb_adjacent(a, b):
     return max(abs(x - y) for x, y in zip(a, b)) <= 1
 
 
-def exact_fit(x, h, max_iter=100):
+def _visit_order(ks, rule):
+    if rule == "sequential_key":
+        return list(ks)
+    return sorted(ks, key=lambda k: (tuple(v % 2 for v in k), k))
+
+
+def exact_fit(x, h, max_iter=100, rule="parallel"):
     hq = Fraction(h)
     pts = [[Fraction(float(v)) for v in row] for row in x]
     n = len(pts)
@@ -67,12 +79,23 @@ def exact_fit(x, h, max_iter=100):
         if t == max_iter:
             flags |= 4
             break
+        # new centroid of every cell
+        newc = {}
+        if rule == "parallel":
+            for j in ks:
+                nb = [k for k in ks if _cheb_adjacent(j, k)]
+                W = sum(cells[k][0] for k in nb)
+                newc[j] = [sum(cells[k][1][dd] for k in nb) / W for dd in range(d)]
+        else:
+            cent = {k: [s / cells[k][0] for s in cells[k][1]] for k in ks}
+            for j in _visit_order(ks, rule):
+                nb = [k for k in ks if _cheb_adjacent(j, k)]
+                W = sum(cells[k][0] for k in nb)
+                cent[j] = [sum(cells[k][0] * cent[k][dd] for k in nb) / W for dd in range(d)]
+                newc[j] = cent[j]
         moved = {}
         for j in ks:
-            nb = [k for k in ks if _cheb_adjacent(j, k)]
-            W = sum(cells[k][0] for k in nb)
-            N = [sum(cells[k][1][dd] for k in nb) for dd in range(d)]
-            p = [v / W for v in N]
+            p = newc[j]
             kap = key(p)
             C = cells[j][0]
             if kap not in moved:

@@ -50,6 +50,6 @@ def test_worked_examples_agree_with_exact(oracle):
     for e in ex_all["examples"]:
         if "labels" not in e:
             continue
-        ex = exact_fit(np.array(e["x"]), e["h"])
+        ex = exact_fit(np.array(e["x"]), e["h"], rule=e.get("rule", "parallel"))
         assert ex["labels"] == e["labels"] and ex["counts"] == e["counts"]
         assert ex["n_iter"] == e["n_iter"]

@@ -1,7 +1,8 @@
 """Oracle vs hand-worked examples (tests/golden/worked_examples.json).
 
 Each example follows Section 2.1 (i)-(v), Eq. 1-4 and the parallel update of
-Eq. 6; the expected values were derived by hand, operation by operation.
+Eq. 6, or, where it names a rule, the sequential update of Eq. 5; the expected
+values were derived by hand, operation by operation.
 """
 import json
 import os
@@ -21,7 +22,7 @@ def _bits(a):
 def test_round_by_round_states(oracle, ex):
     x = np.array(ex["x"], dtype=np.float64)
     for t, state in enumerate(ex["states"]):
-        r = oracle.fit(x, ex["h"], max_iter=t)
+        r = oracle.fit(x, ex["h"], max_iter=t, rule=ex.get("rule", "parallel"))
         keys = [s[0] for s in state]
         counts = [s[1] for s in state]
         sums = [s[2] for s in state]
@@ -34,7 +35,7 @@ def test_round_by_round_states(oracle, ex):
 @pytest.mark.parametrize("ex", [e for e in EXAMPLES if "labels" in e], ids=lambda e: e["name"])
 def test_final_outputs(oracle, ex):
     x = np.array(ex["x"], dtype=np.float64)
-    r = oracle.fit(x, ex["h"], max_iter=100)
+    r = oracle.fit(x, ex["h"], max_iter=100, rule=ex.get("rule", "parallel"))
     assert r.n_iter == ex["n_iter"]
     assert r.flags == ex["flags"]
     assert r.labels.tolist() == ex["labels"]
