@@ -21,7 +21,7 @@ carries, under "forms", the other two forms of the workload family:
            d = 2..6: the cost of the 3^d neighbour gather per dimension.
 The plain form also reports its time per phase (binning, rounds, labels).
 
-  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--forms plain,batched,fwd_bwd,gmm]
+  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--forms plain,batched,fwd_bwd,gmm,sequential]
 """
 from __future__ import annotations
 
@@ -108,7 +108,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,batched,fwd_bwd,gmm")
+    ap.add_argument("--forms", default="plain,batched,fwd_bwd,gmm,sequential")
     ap.add_argument("--form-only", choices=["batched", "fwd_bwd"], default=None,
                     help="time only this form (--steps timed calls after one warm-up) and print its JSON object; "
                          "for profiling a form on its own")
@@ -226,6 +226,8 @@ def main() -> int:
                               "hbm_GBps_alg": out["hbm_GBps_step_alg"]}}
     if "batched" in forms:
         out["forms"]["batched"] = bench_batched(ctx, dev, max(1, args.steps // 10))
+    if "sequential" in forms:
+        out["forms"]["sequential"] = bench_sequential(x, w, max(1, args.steps // 2))
     if "gmm" in forms:
         out["forms"]["gmm"] = bench_gmm(dev, max(1, args.steps // 4))
     if "fwd_bwd" in forms:
@@ -249,6 +251,30 @@ def phase_split(table: dict, fits: int) -> dict:
     for name, v in table.items():
         ph = "binning" if name in BIN_KERNELS else ("labels" if name == "labels" else "rounds")
         out[ph] += v["ms"] / fits
+    return out
+
+
+def bench_sequential(x, w, steps: int) -> dict:
+    """The same 1080p fit with the sequential update of Eq. 5 (swept colour by
+    colour): throughput, and the rounds and clusters it takes."""
+    import torch
+
+    from paper_2206_02200_amd import gridshift
+
+    ctx = gridshift.Context(0)
+    ctx.set_update("sequential")
+    r = gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    n = x.shape[0]
+    out = {"value": n / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "steps": steps,
+           "rounds": r.info["n_iter"], "clusters": r.info["n_clusters"], "flags": r.info["flags"],
+           "workload": "plain 1920x1080 (0.25x, 0.25y, L, a, b) f32, d=5, h=16, update of Eq. 5 by colours"}
+    ctx.close()
     return out
 
 

@@ -7,7 +7,8 @@
  * round (Section 2.1 (ii)-(iv), Eq. 1-4, in the parallel form of Eq. 6) moves
  * every active cell to the count-weighted mean of the active cells among its
  * 3^d neighbours, re-bins the moved cells and merges the cells that land on
- * the same key.  The rounds stop when no active cell has an active neighbour
+ * the same key (gs_context_set_update selects the sequential form of Eq. 5
+ * instead).  The rounds stop when no active cell has an active neighbour
  * (Section 2.1 (v), Theorem 2), after max_iter rounds, or when a round leaves
  * the state bitwise unchanged.  Labels are then propagated back to the points.
  *
@@ -63,7 +64,7 @@ typedef enum {
     GS_ERR_KEY_RANGE = 3,   /* cell keys do not fit the packed 62-bit key space */
     GS_ERR_ALLOC = 4,       /* device allocation failed */
     GS_ERR_DEVICE = 5,      /* a HIP runtime error */
-    GS_ERR_UNSUPPORTED = 6, /* d outside 1..6 */
+    GS_ERR_UNSUPPORTED = 6, /* d outside 1..6; a recorded fit with the sequential update */
     GS_ERR_STATE = 7        /* no fit result in the context */
 } gs_status;
 
@@ -137,6 +138,28 @@ gs_status gs_copy_modes(gs_context* ctx, double* modes, int64_t* counts, double*
 
 /* Integer cell keys floor(.) of the last fit's clusters: device int64 [sum K][d]. */
 gs_status gs_copy_keys(gs_context* ctx, int64_t* keys, void* stream);
+
+/*
+ * Update rule of the shift of every round.
+ *   GS_UPDATE_PARALLEL (default): Eq. 6, every cell moves to the mean over the
+ *     round's table.
+ *   GS_UPDATE_SEQUENTIAL: Eq. 5 (Section 2.2; Algorithm 1 overwrites S'(j) while
+ *     it loops over the cells): the cells move one after another, and a cell
+ *     that has moved contributes C_k * p_k (its count times its new centroid,
+ *     fl(C_k * p_k) in binary64) instead of its sum S_k to the cells that move
+ *     after it; the weights stay the counts of the round's table.  The visiting
+ *     order is colour by colour: the colour of a cell has bit d-1-k equal to
+ *     the parity of its integer coordinate k; colours ascend, and cells of one
+ *     colour (never neighbours of each other) move together, so the order
+ *     among them does not matter.  Relocation, merge and stopping are those of
+ *     the parallel rule.
+ * The rule applies to later fits of the context.  A fit with the sequential
+ * rule while a trajectory is being recorded (gs_context_set_tape) returns
+ * GS_ERR_UNSUPPORTED.  Other values are GS_ERR_INVALID_ARG.
+ */
+enum { GS_UPDATE_PARALLEL = 0, GS_UPDATE_SEQUENTIAL = 1 };
+gs_status gs_context_set_update(gs_context* ctx, int32_t rule);
+gs_status gs_context_get_update(const gs_context* ctx, int32_t* rule);
 
 /*
  * Differentiable form.  With the discrete trajectory of a fit held fixed

@@ -61,6 +61,7 @@ struct gs_config {
 
 struct gs_context {
     int device = 0;
+    int rule = GS_UPDATE_PARALLEL;  // update rule of the shift (gs_context_set_update)
     // point level
     DBuf kA, kB, vA, vB, cell0;
     // cell tables (ping-pong) and per-round scratch
@@ -524,19 +525,23 @@ template <class Lookup>
 gs_status launch_shift(gs_context* c, int d, gs::CellTable t, int64_t m, const gs::InstParam* prm, gs::InstState* st,
                        Lookup lk, double* pbuf, uint64_t* kappa, int32_t* Wout, hipStream_t s) {
     const unsigned g = blocks_for(m, gs::kShiftWaves);  // one wave per cell
-    // reads every cell row once, writes p and the landing key
-    const int tk = prof_begin(c, s, "shift");
-    switch (d) {
-        case 1: gs::k_shift<1, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout); break;
-        case 2: gs::k_shift<2, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout); break;
-        case 3: gs::k_shift<3, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout); break;
-        case 4: gs::k_shift<4, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout); break;
-        case 5: gs::k_shift<5, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout); break;
-        case 6: gs::k_shift<6, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout); break;
-        default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+    // the parallel form in one launch; the sequential form one launch per
+    // colour, ascending (each moves the cells of its colour)
+    const int ncol = c->rule == GS_UPDATE_SEQUENTIAL ? 1 << d : 1;
+    for (int col = 0; col < ncol; ++col) {
+        const int colour = c->rule == GS_UPDATE_SEQUENTIAL ? col : -1;
+        // reads every cell row once, writes p and the landing key
+        const int tk = prof_begin(c, s, "shift");
+        switch (d) {
+#define GS_SH(D)                                                                                                  \
+    case D: gs::k_shift<D, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout, colour); break;
+            GS_SH(1) GS_SH(2) GS_SH(3) GS_SH(4) GS_SH(5) GS_SH(6)
+#undef GS_SH
+            default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+        }
+        prof_end(c, s, tk, (double(m) * (8.0 + 8.0 + 4.0 + 8.0 * d) + double(m) * (8.0 * d + 8.0)) / ncol);
+        GS_HIP(hipGetLastError());
     }
-    prof_end(c, s, tk, double(m) * (8.0 + 8.0 + 4.0 + 8.0 * d) + double(m) * (8.0 * d + 8.0));
-    GS_HIP(hipGetLastError());
     return GS_OK;
 }
 
@@ -547,7 +552,12 @@ gs_status launch_tail(gs_context* c, int d, int B, gs::CellTable t, const gs::In
     switch (d) {
 #define GS_TL(D)                                                                                                  \
     case D:                                                                                                       \
-        gs::k_tail<D><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0, gate);      \
+        if (c->rule == GS_UPDATE_SEQUENTIAL)                                                                      \
+            gs::k_tail<D, true><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0,   \
+                                                               gate);                                             \
+        else                                                                                                      \
+            gs::k_tail<D, false><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0,  \
+                                                                gate);                                            \
         break;
         GS_TL(1) GS_TL(2) GS_TL(3) GS_TL(4) GS_TL(5) GS_TL(6)
 #undef GS_TL
@@ -1175,6 +1185,8 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
     if (dtype != GS_F32 && dtype != GS_F64) return fail(GS_ERR_INVALID_ARG, "dtype must be GS_F32 or GS_F64");
     if (ld < d) return fail(GS_ERR_INVALID_ARG, "ld must be >= d");
     if (max_iter < 0) return fail(GS_ERR_INVALID_ARG, "max_iter must be >= 0");
+    if (c->tape_on && c->rule != GS_UPDATE_PARALLEL)
+        return fail(GS_ERR_UNSUPPORTED, "the trajectory is recorded for the parallel update only");
     if (offsets[0] != 0) return fail(GS_ERR_INVALID_ARG, "offsets[0] must be 0");
     for (int b = 0; b < B; ++b) {
         if (offsets[b + 1] < offsets[b]) return fail(GS_ERR_INVALID_ARG, "offsets must be non-decreasing");
@@ -1605,6 +1617,20 @@ gs_status gs_profile_entry(const gs_context* ctx, int32_t i, const char** name, 
     if (total_ms) *total_ms = ctx->prof.ms[i];
     if (launches) *launches = ctx->prof.launches[i];
     if (bytes) *bytes = ctx->prof.bytes[i];
+    return GS_OK;
+}
+
+gs_status gs_context_set_update(gs_context* ctx, int32_t rule) {
+    if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
+    if (rule != GS_UPDATE_PARALLEL && rule != GS_UPDATE_SEQUENTIAL)
+        return fail(GS_ERR_INVALID_ARG, "rule must be GS_UPDATE_PARALLEL or GS_UPDATE_SEQUENTIAL");
+    ctx->rule = rule;
+    return GS_OK;
+}
+
+gs_status gs_context_get_update(const gs_context* ctx, int32_t* rule) {
+    if (!ctx || !rule) return fail(GS_ERR_INVALID_ARG, "null context or output");
+    *rule = ctx->rule;
     return GS_OK;
 }
 

@@ -770,9 +770,9 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
                                                                InstState* __restrict__ st, Lookup lk,
                                                                double* __restrict__ pbuf,
                                                                uint64_t* __restrict__ kappa,
-                                                               int32_t* __restrict__ Wout) {
+                                                               int32_t* __restrict__ Wout, int colour) {
     constexpr int NOFF = pow3(D);
-    __shared__ int32_t list[kShiftWaves][NOFF];
+    __shared__ uint32_t list[kShiftWaves][NOFF];
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int64_t j = int64_t(blockIdx.x) * kShiftWaves + w;
     if (j >= m) return;  // wave-uniform
@@ -787,19 +787,32 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
     int64_t crd[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) crd[k] = int64_t((local / P.stride[k]) % uint64_t(P.E[k]));
+    // Sequential form (Eq. 5), run colour by colour: a launch moves only the
+    // cells of colour `colour` (bit D-1-k = parity of integer coordinate k);
+    // cells of one colour are never neighbours.  Neighbours of a lower colour
+    // were moved by earlier launches and contribute fl(C_k * p_k).
+    int own_col = 0;
+    if (colour >= 0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) own_col = (own_col << 1) | int((crd[k] + P.lo[k]) & 1);
+        if (own_col != colour) return;  // wave-uniform
+    }
     const uint64_t lt = lanemask_lt();
     // every probe of the cell first (independent loads, all in flight), then
     // the found cells compacted in probe order
     constexpr int NIT = (NOFF + kWave - 1) / kWave;
     int64_t idx[NIT];
+    bool upd[NIT];  // the neighbour was moved earlier in this sweep
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int r = it * kWave + lane;
         idx[it] = -1;
+        upd[it] = false;
         if (r < NOFF) {
             int rr = r;
             bool inside = true;
             uint64_t nk = key;
+            int flip = 0;  // colour bits in which the neighbour differs
 #pragma unroll
             for (int k = D - 1; k >= 0; --k) {
                 const int v = rr % 3 - 1;
@@ -807,7 +820,9 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
                 const int64_t c = crd[k] + v;
                 inside = inside && c >= 0 && c < P.E[k];
                 nk += uint64_t(int64_t(v)) * P.stride[k];
+                flip |= (v != 0 ? 1 : 0) << (D - 1 - k);
             }
+            upd[it] = colour >= 0 && (own_col ^ flip) < own_col;
             if (inside) idx[it] = lk.find(nk);
         }
     }
@@ -815,7 +830,7 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const uint64_t bal = __ballot(idx[it] >= 0);
-        if (idx[it] >= 0) list[w][nfound + __popcll(bal & lt)] = int32_t(idx[it]);
+        if (idx[it] >= 0) list[w][nfound + __popcll(bal & lt)] = uint32_t(idx[it]) | (upd[it] ? 0x80000000u : 0u);
         nfound += __popcll(bal);
     }
     __builtin_amdgcn_wave_barrier();
@@ -825,10 +840,15 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
     int64_t W = 0;
     if (lane < D) {
         const double* col = t.sum + int64_t(lane) * t.cap;
+        const double* pcol = pbuf + int64_t(lane) * t.cap;
         for (int q0 = 0; q0 < nfound; q0 += 16) {
             double sv[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) sv[u] = q0 + u < nfound ? col[list[w][q0 + u]] : 0.0;
+            for (int u = 0; u < 16; ++u) {
+                const uint32_t e = q0 + u < nfound ? list[w][q0 + u] : 0u;
+                const uint32_t k = e & 0x7fffffffu;
+                sv[u] = q0 + u >= nfound ? 0.0 : (e >> 31) ? double(t.cnt[k]) * pcol[k] : col[k];
+            }
 #pragma unroll
             for (int u = 0; u < 16; ++u)
                 if (q0 + u < nfound) acc = (q0 + u == 0) ? sv[u] : acc + sv[u];
@@ -837,7 +857,7 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
         for (int q0 = 0; q0 < nfound; q0 += 16) {
             int64_t cv[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) cv[u] = q0 + u < nfound ? t.cnt[list[w][q0 + u]] : 0;
+            for (int u = 0; u < 16; ++u) cv[u] = q0 + u < nfound ? t.cnt[list[w][q0 + u] & 0x7fffffffu] : 0;
 #pragma unroll
             for (int u = 0; u < 16; ++u) W += cv[u];
         }
@@ -1387,7 +1407,12 @@ __global__ void k_tail_gate(const InstState* __restrict__ st, int B, int64_t* __
 }
 
 // With `gate` set and nonzero the kernel returns at once, changing nothing.
-template <int D>
+// SEQ runs the sequential form of Eq. 5 colour by colour (bit D-1-k of a
+// cell's colour = parity of its integer coordinate k; cells of one colour are
+// never neighbours): the cells of a colour move together, each then writes
+// fl(C_j * p_j) over its sum for the colours after it, and a round that stops
+// puts the sums back.  SEQ fits record no tape or checkpoints.
+template <int D, bool SEQ>
 __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstParam* __restrict__ param,
                                                        InstState* __restrict__ st, uint32_t* __restrict__ tmap,
                                                        int max_iter, TailTape tape, TailCkpt ck, int replay_r0,
@@ -1410,6 +1435,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
     __shared__ uint16_t col[kSlabMax + 1];  // column table of the current cells
     __shared__ uint16_t rank_of[MT];        // old cell -> sorted position
     __shared__ int32_t s_flag[2][3];         // per round parity: any neighbour, bad key, changed
+    __shared__ unsigned long long s_cols[2];  // per round parity: colours present (sequential form)
 
     if (gate && *gate) return;
     const int b = blockIdx.x;
@@ -1446,6 +1472,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         s_Ed[tid] = double(P.E[tid]);
         if (tid < 2) s_E01[tid] = P.E[tid < D ? tid : 0];
     }
+    if (tid < 2) s_cols[tid] = 0;
 
     if (tid < m_entry) {
         uint64_t lk;
@@ -1479,6 +1506,11 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
     const TailCols cols = tail_cols<D>(s_E01[0], D >= 2 ? s_E01[1] : 1);
     const bool fast_rank = P.span <= (1ull << 53);  // (key << 10 | index) fits in 63 bits
     if (tid < 6) (&s_flag[0][0])[tid] = 0;
+    int lo_par = 0;  // parities of the box origin, as colour bits
+    if constexpr (SEQ) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) lo_par = (lo_par << 1) | int(P.lo[k] & 1);
+    }
     for (int round = 0;; ++round) {
         if (replay && round == seg_rounds) break;
         int32_t* flg = s_flag[round & 1];
@@ -1493,18 +1525,36 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         }
         // ---- column table of the current cells
         tail_cols_build(cols, crd[0], crd[D >= 2 ? 1 : 0], m, tid, col);
+        int my_col = 0;
+        if constexpr (SEQ) {
+            if (tid < m) {
+                int rp = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) rp = (rp << 1) | (crd[k][tid] & 1);
+                my_col = rp ^ lo_par;
+                atomicOr(&s_cols[round & 1], 1ull << my_col);
+            }
+        }
         __syncthreads();
         // every thread has finished reading the other parity's flags
         if (tid < 3) s_flag[(round + 1) & 1][tid] = 0;
+        uint64_t present = 1;  // colours to visit; the parallel form visits once
+        if constexpr (SEQ) {
+            present = s_cols[round & 1];
+            if (tid == 0) s_cols[(round + 1) & 1] = 0;
+        }
         // ---- shift (one cell per thread)
         bool nb = false, bad = false;
         bool chg = false;  // stationarity: landing key or merge value differs from the cell's own
         double p[D];
         double val[D];
+        double orig[SEQ ? D : 1];  // the cell's sums before the sweep overwrote them
         int32_t q[D];
         uint64_t kj = 0;
         int32_t Wj = 0;
-        if (tid < m) {
+        for (int cc = 0; cc < (SEQ ? (1 << D) : 1); ++cc) {
+        if (SEQ && !((present >> cc) & 1)) continue;  // block-uniform
+        if (tid < m && (!SEQ || my_col == cc)) {
             const TailWindow win = tail_window(cols, crd[0], crd[D >= 2 ? 1 : 0], m, tid, col);
             const int ncand = win.n[0] + win.n[1] + win.n[2];
             int32_t me[D];
@@ -1537,10 +1587,13 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
                 for (int u = 0; u < U; ++u) {
                     const int k = kk[u];
                     const bool ok = okm[u] != 0;
+                    // the sequential sweep reads sums only of neighbours (a
+                    // cell of this colour may be rewriting its own meanwhile)
+                    const int ks = SEQ ? (ok ? k : tid) : k;
                     W += ok ? int64_t(cnt[k]) : 0;
                     nbs += ok ? 1 : 0;
 #pragma unroll
-                    for (int dd = 0; dd < D; ++dd) p[dd] = p[dd] + (ok ? sm[dd][k] : -0.0);
+                    for (int dd = 0; dd < D; ++dd) p[dd] = p[dd] + (ok ? sm[dd][ks] : -0.0);
                 }
             }
             nb = nbs > 1;  // the cell itself is always among the candidates
@@ -1562,10 +1615,23 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
                 val[dd] = double(cnt[tid]) * p[dd];
                 chg = chg || dbits(val[dd]) != dbits(sm[dd][tid]);
             }
+            if constexpr (SEQ) {  // the cells moving after this one read C_j * p_j
+#pragma unroll
+                for (int dd = 0; dd < D; ++dd) {
+                    orig[dd] = sm[dd][tid];
+                    sm[dd][tid] = val[dd];
+                }
+            }
+        }
+        if constexpr (SEQ) __syncthreads();
         }
         if (__ballot(nb) && lane == 0) atomicOr(&flg[0], 1);
         if (__ballot(bad) && lane == 0) atomicOr(&flg[1], 1);
         __syncthreads();
+        if (SEQ && (!flg[0] || tt >= max_iter) && tid < m) {  // the round is not applied
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) sm[dd][tid] = orig[dd];
+        }
         if (!flg[0]) {
             flags |= 1u;
             break;

@@ -34,9 +34,11 @@ EXPORTED = [
     "gs_profile_enable", "gs_profile_reset", "gs_profile_count", "gs_profile_entry",
     "gs_context_set_tape", "gs_backward", "gs_point_mode_loss", "gs_point_mode_loss_backward",
     "gs_context_set_config", "gs_context_get_config", "gs_autotune",
+    "gs_context_set_update", "gs_context_get_update",
 ]
 CFG_MERGE_SMALL, CFG_TILE_CHUNKS, CFG_DENSE_TABLE = 0, 1, 2
 CONFIG_KEYS = {"merge_small": CFG_MERGE_SMALL, "tile_chunks": CFG_TILE_CHUNKS, "dense_table": CFG_DENSE_TABLE}
+UPDATE_RULES = {"parallel": 0, "sequential": 1}  # gs_context_set_update
 
 
 class GridShiftError(RuntimeError):
@@ -105,6 +107,10 @@ def load_library(path: str = LIB_PATH):
         lib.gs_point_mode_loss.restype = ctypes.c_int
         lib.gs_point_mode_loss_backward.argtypes = [V, V, V, V, V, V]
         lib.gs_point_mode_loss_backward.restype = ctypes.c_int
+        lib.gs_context_set_update.argtypes = [V, I32]
+        lib.gs_context_set_update.restype = ctypes.c_int
+        lib.gs_context_get_update.argtypes = [V, ctypes.POINTER(I32)]
+        lib.gs_context_get_update.restype = ctypes.c_int
         lib.gs_context_set_config.argtypes = [V, I32, I32]
         lib.gs_context_set_config.restype = ctypes.c_int
         lib.gs_context_get_config.argtypes = [V, I32, ctypes.POINTER(I32)]
@@ -138,6 +144,19 @@ class Context:
         table every k rounds instead and recomputes each k-round segment
         during the backward pass; False or 0 records nothing."""
         _check(_lib.gs_context_set_tape(self.handle, int(on)))
+
+    def set_update(self, rule: str = "parallel"):
+        """Update rule of later fits: "parallel" (Eq. 6, the default) or
+        "sequential" (Eq. 5, cells moved colour by colour, each colour reading
+        the centroids the earlier colours just moved)."""
+        if rule not in UPDATE_RULES:
+            raise ValueError(f"unknown update rule {rule!r}")
+        _check(_lib.gs_context_set_update(self.handle, UPDATE_RULES[rule]))
+
+    def update_rule(self) -> str:
+        v = ctypes.c_int32()
+        _check(_lib.gs_context_get_update(self.handle, ctypes.byref(v)))
+        return {i: k for k, i in UPDATE_RULES.items()}[v.value]
 
     def set_config(self, **kv):
         """Launch choices (merge_small=0/1, tile_chunks=1..64, dense_table=0/1); results never depend on them."""

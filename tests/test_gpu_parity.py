@@ -34,11 +34,21 @@ def _bits(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64)).view(np.uint64)
 
 
-def _gpu(x_np, h, max_iter=100, dtype=None):
+_CTX = {}
+
+
+def _ctx(rule):
+    if rule not in _CTX:
+        _CTX[rule] = gridshift.Context(0)
+        _CTX[rule].set_update(rule)
+    return _CTX[rule]
+
+
+def _gpu(x_np, h, max_iter=100, dtype=None, rule="parallel"):
     x = torch.from_numpy(np.ascontiguousarray(x_np)).to(DEV)
     if dtype is not None:
         x = x.to(dtype)
-    r = gridshift.fit(x, h, max_iter, with_sums=True, with_keys=True)
+    r = gridshift.fit(x, h, max_iter, with_sums=True, with_keys=True, ctx=_ctx(rule))
     torch.cuda.synchronize()
     return r
 
@@ -71,16 +81,21 @@ def _blobs(seed, n, d, k=8, scale=5.0, spread=12.0):
 # ---------------------------------------------------------------------------
 # worked examples
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("ex", GOLDEN, ids=[e["name"] for e in GOLDEN])
+# the device runs the parallel rule and the colour-ordered sequential rule
+ON_DEVICE = [e for e in GOLDEN if e.get("rule", "parallel") in ("parallel", "sequential")]
+
+
+@pytest.mark.parametrize("ex", ON_DEVICE, ids=[e["name"] for e in ON_DEVICE])
 def test_worked_examples_round_by_round(ex):
     x = np.array(ex["x"], dtype=np.float64)
+    rule = ex.get("rule", "parallel")
     for t, state in enumerate(ex["states"]):
-        g = _gpu(x, ex["h"], max_iter=t)
+        g = _gpu(x, ex["h"], max_iter=t, rule=rule)
         assert g.keys.cpu().numpy().tolist() == [s[0] for s in state], f"round {t}"
         assert g.counts.cpu().numpy().tolist() == [s[1] for s in state], f"round {t}"
         np.testing.assert_array_equal(_bits(g.sums.cpu().numpy()), _bits([s[2] for s in state]))
     if "labels" in ex:
-        g = _gpu(x, ex["h"])
+        g = _gpu(x, ex["h"], rule=rule)
         assert g.labels.cpu().numpy().tolist() == ex["labels"]
         np.testing.assert_array_equal(_bits(g.modes.cpu().numpy()), _bits(ex["modes"]))
         assert g.info["n_iter"] == ex["n_iter"] and g.info["flags"] == ex["flags"]

@@ -1,0 +1,163 @@
+"""GPU parity of the sequential update (Eq. 5, swept colour by colour) against
+the FP64 oracle's "sequential" rule.
+
+Bar, as for the parallel rule: labels, counts, K, round count, flags and keys
+bit-exact, cell sums and modes bit-exact.  The cases cover the tail workgroup
+(few cells), the device-wide rounds (one shift launch per colour), rounds that
+stop or hit the cap after the sweep has run (the sums must be put back),
+coordinates of both signs (the colour is the parity of the integer
+coordinate, not of the offset inside the key box), and the batched form.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import gs_oracle  # noqa: E402
+from paper_2206_02200_amd import gridshift, synth  # noqa: E402
+
+DEV = torch.device("cuda:0")
+_CTX = {}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _bits(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64)).view(np.uint64)
+
+
+def _ctx(rule="sequential"):
+    if rule not in _CTX:
+        _CTX[rule] = gridshift.Context(0)
+        _CTX[rule].set_update(rule)
+    return _CTX[rule]
+
+
+def assert_seq_parity(x_np, h, max_iter=100, what=""):
+    _say(f"sequential case {what}: n={x_np.shape[0]} d={x_np.shape[1]} dtype={x_np.dtype} h={h} max_iter={max_iter}")
+    x = torch.from_numpy(np.ascontiguousarray(x_np)).to(DEV)
+    g = gridshift.fit(x, h, max_iter, with_sums=True, with_keys=True, ctx=_ctx())
+    torch.cuda.synchronize()
+    o = gs_oracle.fit(x_np.astype(np.float64), h, max_iter, rule="sequential")
+    info = g.info
+    assert info["n_clusters"] == o.K, what
+    assert info["n_iter"] == o.n_iter, what
+    assert info["flags"] == o.flags, what
+    np.testing.assert_array_equal(g.labels.cpu().numpy(), o.labels, err_msg=what)
+    np.testing.assert_array_equal(g.counts.cpu().numpy(), o.counts, err_msg=what)
+    np.testing.assert_array_equal(g.keys.cpu().numpy(), o.keys, err_msg=what)
+    np.testing.assert_array_equal(_bits(g.sums.cpu().numpy()), _bits(o.sums), err_msg=what)
+    np.testing.assert_array_equal(_bits(g.modes.cpu().numpy()), _bits(o.modes), err_msg=what)
+    return g, o
+
+
+def _blobs(seed, n, d, k=8, scale=5.0, spread=12.0, shift=0.0):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0, spread * scale, size=(k, d)) - shift
+    lab = rng.integers(0, k, size=n)
+    return c[lab] + scale * 0.8 * rng.standard_normal(size=(n, d))
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("n", [37, 4097, 20011])
+def test_sequential_blobs_f64(d, n):
+    x = _blobs(5000 + 7 * d + n, n, d)
+    assert_seq_parity(x, 4.0, 100, f"blobs f64 d={d} n={n}")
+
+
+@pytest.mark.parametrize("d", [2, 3, 5])
+def test_sequential_blobs_f32_signed(d):
+    # centres on both sides of zero: odd and even box origins
+    x = _blobs(5100 + d, 30000, d, shift=25.0).astype(np.float32)
+    assert_seq_parity(x, 3.0, 100, f"signed blobs f32 d={d}")
+
+
+@pytest.mark.parametrize("t", [0, 1, 2, 3, 5])
+def test_sequential_state_after_each_round(t):
+    x = _blobs(5201, 8000, 3)
+    assert_seq_parity(x, 2.5, t, f"max_iter={t}")
+
+
+def test_sequential_wide_rounds():
+    x = _blobs(5202, 150000, 3, k=30, scale=8.0, spread=20.0, shift=40.0)
+    g, o = assert_seq_parity(x, 1.0, 100, "wide rounds")
+    assert o.m_hist[0] > 4096
+
+
+def test_sequential_wide_rounds_hit_the_cap():
+    x = _blobs(5203, 60000, 2, k=20, scale=6.0, spread=30.0)
+    assert_seq_parity(x, 0.5, 2, "wide rounds capped")
+
+
+def test_sequential_1080p_xylab_f32_full_size():
+    w = synth.image_xylab_f32()
+    assert_seq_parity(w.x, w.h, w.max_iter, w.name + " sequential")
+
+
+def test_sequential_gmm_d4_f32():
+    w = synth.gmm_f32(200000, 4, seed=45)
+    assert_seq_parity(w.x, w.h, w.max_iter, w.name + " sequential")
+
+
+def test_sequential_identical_points_and_empty():
+    assert_seq_parity(np.full((1000, 3), -2.5), 1.0, 100, "identical")
+    x = torch.empty((0, 2), dtype=torch.float64, device=DEV)
+    r = gridshift.fit(x, 1.0, 100, ctx=_ctx())
+    assert r.info["n_clusters"] == 0 and r.labels.numel() == 0
+
+
+def test_sequential_batched_equals_oracle():
+    rng = np.random.default_rng(78)
+    sizes = [0, 1, 500, 12000, 3, 150000, 2048]
+    xs = [_blobs(5300 + i, s, 3, k=20, scale=6.0, spread=20.0, shift=30.0 * (i % 2)) for i, s in enumerate(sizes)]
+    hs = [float(rng.choice([1.0, 1.5, 2.0])) for _ in sizes]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    X = torch.from_numpy(np.concatenate(xs, axis=0)).to(DEV)
+    br = gridshift.fit_batched(X, off, hs, 100, with_sums=True, ctx=_ctx())
+    labels = br.labels.cpu().numpy()
+    sums = br.sums.cpu().numpy()
+    counts = br.counts.cpu().numpy()
+    for b, (x, h) in enumerate(zip(xs, hs)):
+        _say(f"sequential batched instance {b}: n={len(x)} h={h}")
+        o = gs_oracle.fit(x, h, 100, rule="sequential")
+        ko = slice(br.k_offsets[b], br.k_offsets[b + 1])
+        assert br.infos[b]["n_clusters"] == o.K
+        assert br.infos[b]["n_iter"] == o.n_iter and br.infos[b]["flags"] == o.flags
+        np.testing.assert_array_equal(labels[off[b]:off[b + 1]], o.labels)
+        np.testing.assert_array_equal(counts[ko], o.counts)
+        np.testing.assert_array_equal(_bits(sums[ko]), _bits(o.sums))
+
+
+def test_rule_is_per_context_and_reversible():
+    x_np = _blobs(5400, 20000, 3)
+    x = torch.from_numpy(x_np).to(DEV)
+    ctx = gridshift.Context(0)
+    assert ctx.update_rule() == "parallel"
+    ctx.set_update("sequential")
+    a = gridshift.fit(x, 2.0, 100, with_sums=True, ctx=ctx)
+    ctx.set_update("parallel")
+    b = gridshift.fit(x, 2.0, 100, with_sums=True, ctx=ctx)
+    o_seq = gs_oracle.fit(x_np, 2.0, 100, rule="sequential")
+    o_par = gs_oracle.fit(x_np, 2.0, 100)
+    np.testing.assert_array_equal(_bits(a.sums.cpu().numpy()), _bits(o_seq.sums))
+    np.testing.assert_array_equal(_bits(b.sums.cpu().numpy()), _bits(o_par.sums))
+    with pytest.raises(ValueError):
+        ctx.set_update("sequential_key")
+
+
+def test_recorded_fit_rejects_the_sequential_rule():
+    ctx = gridshift.Context(0)
+    ctx.set_update("sequential")
+    ctx.set_tape(True)
+    x = torch.from_numpy(_blobs(5401, 1000, 2)).to(DEV)
+    with pytest.raises(RuntimeError, match="GS_ERR_UNSUPPORTED"):
+        gridshift.fit(x, 2.0, 100, ctx=ctx)
