@@ -21,7 +21,7 @@ carries, under "forms", the other two forms of the workload family:
            d = 2..6: the cost of the 3^d neighbour gather per dimension.
 The plain form also reports its time per phase (binning, rounds, labels).
 
-  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--forms plain,batched,fwd_bwd,gmm,sequential]
+  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--forms plain,batched,fwd_bwd,gmm,sequential,hsweep]
 """
 from __future__ import annotations
 
@@ -108,7 +108,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,batched,fwd_bwd,gmm,sequential")
+    ap.add_argument("--forms", default="plain,batched,fwd_bwd,gmm,sequential,hsweep")
     ap.add_argument("--form-only", choices=["batched", "fwd_bwd"], default=None,
                     help="time only this form (--steps timed calls after one warm-up) and print its JSON object; "
                          "for profiling a form on its own")
@@ -230,6 +230,8 @@ def main() -> int:
         out["forms"]["sequential"] = bench_sequential(x, w, max(1, args.steps // 2))
     if "gmm" in forms:
         out["forms"]["gmm"] = bench_gmm(dev, max(1, args.steps // 4))
+    if "hsweep" in forms:
+        out["forms"]["hsweep"] = bench_hsweep(dev, max(1, args.steps // 4))
     if "fwd_bwd" in forms:
         out["forms"]["fwd_bwd"] = bench_fwd_bwd(dev, max(1, args.steps // 10))
     if not args.no_cpu_baseline:
@@ -274,6 +276,34 @@ def bench_sequential(x, w, steps: int) -> dict:
     out = {"value": n / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "steps": steps,
            "rounds": r.info["n_iter"], "clusters": r.info["n_clusters"], "flags": r.info["flags"],
            "workload": "plain 1920x1080 (0.25x, 0.25y, L, a, b) f32, d=5, h=16, update of Eq. 5 by colours"}
+    ctx.close()
+    return out
+
+
+def bench_hsweep(dev, steps: int) -> dict:
+    """Bandwidth sweep: 1e6 points of a clustering set scaled into [0,1]^3,
+    fitted at h = 0.02, 0.04, ..., 1.00 (50 values) in one batched pass."""
+    import torch
+
+    from paper_2206_02200_amd import gridshift, synth
+
+    n, d = 1_000_000, 3
+    x = torch.from_numpy(synth.unit_gmm_f32(n, d, seed=95)).to(dev)
+    hs = synth.hsweep_grid(50)
+    ctx = gridshift.Context(0)
+    r = gridshift.fit_hsweep(x, hs, 100, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = gridshift.fit_hsweep(x, hs, 100, ctx=ctx)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    out = {"value": n * len(hs) / (ms * 1e-3), "unit": "points/s (points x bandwidths)", "ms_per_step": ms,
+           "steps": steps, "n": n, "d": d, "bandwidths": len(hs),
+           "clusters_by_h": {f"{h:.2f}": i["n_clusters"] for h, i in zip(hs, r.infos)},
+           "rounds_by_h": {f"{h:.2f}": i["n_iter"] for h, i in zip(hs, r.infos)},
+           "workload": "1e6 points, 12-component Gaussian mixture scaled into [0,1]^3, f32, "
+                       "h = 0.02..1.00 step 0.02, one batched pass"}
     ctx.close()
     return out
 

@@ -128,6 +128,23 @@ gs_status gs_fit_batched(gs_context* ctx, const void* points, gs_dtype dtype, in
                          gs_info* info, void* stream);
 
 /*
+ * Bandwidth sweep: the same point set fitted once per bandwidth hs[0..H-1]
+ * (the tuning of Section 4.1 scans h over (0,1]), all H fits in one batched
+ * pass (gs_fit_batched over H copies of the points).  Results per bandwidth
+ * are bitwise those of gs_fit with that h.
+ *   points  device, n rows of ld elements of dtype (as gs_fit).
+ *   hs      host double [H], each finite and > 0.
+ *   labels  device int32 [H][n]: the labels of bandwidth j at j * n.
+ *   info    host gs_info [H].
+ * The context keeps the H dense copies (H * n * d elements of dtype) in its
+ * own device memory; H * n must stay below 2^31.  The cluster tables stay in
+ * the context as after gs_fit_batched (gs_copy_modes: bandwidth j's clusters
+ * after those of bandwidths 0..j-1).
+ */
+gs_status gs_fit_hsweep(gs_context* ctx, const void* points, gs_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                        int32_t H, const double* hs, int32_t max_iter, int32_t* labels, gs_info* info, void* stream);
+
+/*
  * Copy the cluster table of the last fit, instances concatenated in order
  * (instance b's K_b clusters start at row sum_{b'<b} K_b').
  *   modes   device double [sum K][d]: fl(S / C)           (may be NULL)

@@ -111,6 +111,7 @@ struct gs_context {
     DBuf ck_key, ck_cnt, ck_sum, ck_m;
     int ck_nslots = 0;
     DBuf sums0, inst0, wt_key, wt_cnt, wt_inst, wt_W, wt_g, wt_app;
+    DBuf rep;  // the replicated points of a bandwidth sweep
     DBuf tt_key, tt_cnt, tt_W, tt_g, tt_m;
     // backward with checkpoints: a second stream recomputes the next (earlier)
     // tape segment while the current one is reversed (two tape buffers)
@@ -382,6 +383,18 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 __global__ void k_set_i64(int64_t* __restrict__ p, int64_t v) { *p = v; }
+
+// The first d elements of the n rows of x (row stride ld), written densely H
+// times one after another: each element is read once and stored H times.
+template <typename T>
+__global__ void k_replicate_rows(const T* __restrict__ x, int64_t ld, int64_t n, int d, int H, T* __restrict__ out) {
+    const int64_t per = n * d;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < per; e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = e / d;
+        const T v = x[i * ld + (e - i * d)];
+        for (int j = 0; j < H; ++j) out[int64_t(j) * per + e] = v;
+    }
+}
 __global__ void k_iota32(uint32_t* __restrict__ p, int64_t n) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = uint32_t(i);
@@ -1496,7 +1509,7 @@ void gs_context_destroy(gs_context* c) {
     DBuf* tb2[] = {&c->sums0, &c->inst0, &c->wt_key, &c->wt_cnt, &c->wt_inst, &c->wt_W, &c->wt_g, &c->wt_app,
                    &c->tt_key, &c->tt_cnt, &c->tt_W, &c->tt_g, &c->tt_m, &c->sbA, &c->sbB, &c->qbuf, &c->gmodes,
                    &c->modes_i, &c->counts_i, &c->frows, &c->lossc, &c->ltab, &c->xkA, &c->xkB, &c->xvA, &c->xvB,
-                   &c->ck_key, &c->ck_cnt, &c->ck_sum, &c->ck_m, &c->tune_labels, &c->dk};
+                   &c->ck_key, &c->ck_cnt, &c->ck_sum, &c->ck_m, &c->tune_labels, &c->dk, &c->rep};
     for (DBuf* b : tb2)
         if (b->p) (void)hipFree(b->p);
     delete c;
@@ -1515,6 +1528,41 @@ gs_status gs_fit_batched(gs_context* ctx, const void* points, gs_dtype dtype, in
                          void* stream) {
     return fit_impl(ctx, points, dtype, d, ld, B, offsets, h, max_iter, labels, info,
                     static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_fit_hsweep(gs_context* ctx, const void* points, gs_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                        int32_t H, const double* hs, int32_t max_iter, int32_t* labels, gs_info* info, void* stream) {
+    if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
+    if (n < 0 || H < 1 || !hs || !info) return fail(GS_ERR_INVALID_ARG, "n >= 0, H >= 1, hs and info are required");
+    if (d < 1 || d > gs::kMaxDim) return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+    if (dtype != GS_F32 && dtype != GS_F64) return fail(GS_ERR_INVALID_ARG, "dtype must be GS_F32 or GS_F64");
+    if (ld < d) return fail(GS_ERR_INVALID_ARG, "ld must be >= d");
+    if (n > 0 && int64_t(H) * n >= (int64_t(1) << 31))
+        return fail(GS_ERR_INVALID_ARG, "H * n must stay below 2^31 points");
+    if (n > 0 && (!points || !labels)) return fail(GS_ERR_INVALID_ARG, "points and labels are required");
+    for (int j = 0; j < H; ++j)
+        if (!(hs[j] > 0.0) || !std::isfinite(hs[j])) return fail(GS_ERR_INVALID_ARG, "h must be finite and > 0");
+    gs_context* c = ctx;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GS_HIP(hipSetDevice(c->device));
+    std::vector<int64_t> off(size_t(H) + 1);
+    for (int j = 0; j <= H; ++j) off[j] = int64_t(j) * n;
+    const void* rows = nullptr;
+    if (n > 0) {
+        const size_t es = dtype == GS_F32 ? 4 : 8;
+        GS_TRY(ensure(c->rep, size_t(H) * size_t(n) * size_t(d) * es));
+        const unsigned g = unsigned(std::min<int64_t>(blocks_for(n * d, 256), 8192));
+        const int tk = prof_begin(c, s, "replicate");
+        if (dtype == GS_F32)
+            k_replicate_rows<float><<<g, 256, 0, s>>>(static_cast<const float*>(points), ld, n, d, H, P<float>(c->rep));
+        else
+            k_replicate_rows<double><<<g, 256, 0, s>>>(static_cast<const double*>(points), ld, n, d, H,
+                                                       P<double>(c->rep));
+        prof_end(c, s, tk, double(n) * d * es * (1.0 + H));
+        GS_HIP(hipGetLastError());
+        rows = c->rep.p;
+    }
+    return fit_impl(c, rows, dtype, d, d, H, off.data(), hs, max_iter, labels, info, s);
 }
 
 gs_status gs_context_set_config(gs_context* ctx, int32_t key, int32_t value) {

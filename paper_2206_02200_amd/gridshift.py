@@ -34,7 +34,7 @@ EXPORTED = [
     "gs_profile_enable", "gs_profile_reset", "gs_profile_count", "gs_profile_entry",
     "gs_context_set_tape", "gs_backward", "gs_point_mode_loss", "gs_point_mode_loss_backward",
     "gs_context_set_config", "gs_context_get_config", "gs_autotune",
-    "gs_context_set_update", "gs_context_get_update",
+    "gs_context_set_update", "gs_context_get_update", "gs_fit_hsweep",
 ]
 CFG_MERGE_SMALL, CFG_TILE_CHUNKS, CFG_DENSE_TABLE = 0, 1, 2
 CONFIG_KEYS = {"merge_small": CFG_MERGE_SMALL, "tile_chunks": CFG_TILE_CHUNKS, "dense_table": CFG_DENSE_TABLE}
@@ -86,6 +86,8 @@ def load_library(path: str = LIB_PATH):
         lib.gs_fit.restype = ctypes.c_int
         lib.gs_fit_batched.argtypes = [V, V, ctypes.c_int, I32, I64, I32, V, V, I32, V, V, V]
         lib.gs_fit_batched.restype = ctypes.c_int
+        lib.gs_fit_hsweep.argtypes = [V, V, ctypes.c_int, I64, I32, I64, I32, V, I32, V, V, V]
+        lib.gs_fit_hsweep.restype = ctypes.c_int
         lib.gs_copy_modes.argtypes = [V, V, V, V, V]
         lib.gs_copy_modes.restype = ctypes.c_int
         lib.gs_copy_keys.argtypes = [V, V, V]
@@ -320,6 +322,34 @@ def fit_batched(x: torch.Tensor, offsets, h, max_iter: int = 100, *, with_sums: 
     _check(lib.gs_copy_modes(ctx.handle, ctypes.c_void_p(modes.data_ptr()), ctypes.c_void_p(counts.data_ptr()),
                              ctypes.c_void_p(sums.data_ptr() if sums is not None else 0), sp))
     return BatchedResult(labels, modes, counts, koff, [infos[b].as_dict() for b in range(B)], sums)
+
+
+def fit_hsweep(x: torch.Tensor, hs, max_iter: int = 100, *, with_sums: bool = False,
+               ctx: Context | None = None, stream=None) -> BatchedResult:
+    """The point set ``x`` fitted once per bandwidth in ``hs``, all in one
+    batched pass; labels come back as [H, n], the cluster rows of bandwidth j
+    at k_offsets[j]..k_offsets[j+1]-1."""
+    lib = load_library()
+    x, dt, ld = _points(x)
+    n, d = x.shape
+    hv = np.ascontiguousarray(np.asarray(hs, dtype=np.float64).ravel())
+    H = hv.size
+    ctx = ctx or default_context(x.device.index)
+    sp = _stream_ptr(stream)
+    labels = torch.empty((H, n), dtype=torch.int32, device=x.device)
+    infos = (Info * H)()
+    _check(lib.gs_fit_hsweep(ctx.handle, ctypes.c_void_p(x.data_ptr()), dt, n, d, ld, H,
+                             hv.ctypes.data_as(ctypes.c_void_p), int(max_iter), ctypes.c_void_p(labels.data_ptr()),
+                             ctypes.cast(infos, ctypes.c_void_p), sp))
+    ks = np.array([infos[j].n_clusters for j in range(H)], dtype=np.int64)
+    koff = np.concatenate([[0], np.cumsum(ks)]).astype(np.int64)
+    tot = int(koff[-1])
+    modes = torch.empty((tot, d), dtype=torch.float64, device=x.device)
+    counts = torch.empty(tot, dtype=torch.int64, device=x.device)
+    sums = torch.empty((tot, d), dtype=torch.float64, device=x.device) if with_sums else None
+    _check(lib.gs_copy_modes(ctx.handle, ctypes.c_void_p(modes.data_ptr()), ctypes.c_void_p(counts.data_ptr()),
+                             ctypes.c_void_p(sums.data_ptr() if sums is not None else 0), sp))
+    return BatchedResult(labels, modes, counts, koff, [infos[j].as_dict() for j in range(H)], sums)
 
 
 # ---------------------------------------------------------------------------

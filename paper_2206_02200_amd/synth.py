@@ -124,6 +124,28 @@ def gmm_f32(n: int, d: int, seed: int, components: int = 50, h: float = 4.0) -> 
     return Workload(f"gmm{components}_n{n}_d{d}_f32", x[perm].astype(np.float32), h, 100)
 
 
+def unit_gmm_f32(n: int, d: int, seed: int, components: int = 12) -> np.ndarray:
+    """A clustering set scaled into [0,1]^d (the range the bandwidth tuning of
+    Section 4.1 scans): an isotropic Gaussian mixture (means U[0,1]^d, sigma
+    U[0.02,0.06], Dirichlet(1) weights), each coordinate mapped affinely onto
+    [0,1] by its own minimum and maximum, float32, shuffled."""
+    rng = np.random.default_rng(seed)
+    w = rng.dirichlet(np.ones(components))
+    mu = rng.uniform(0.0, 1.0, size=(components, d))
+    sig = rng.uniform(0.02, 0.06, size=components)
+    cnt = rng.multinomial(n, w)
+    comp = np.repeat(np.arange(components), cnt)
+    x = mu[comp] + sig[comp][:, None] * rng.standard_normal(size=(n, d))
+    lo, hi = x.min(axis=0), x.max(axis=0)
+    x = (x - lo) / np.where(hi > lo, hi - lo, 1.0)
+    return x[rng.permutation(n)].astype(np.float32)
+
+
+def hsweep_grid(count: int = 20) -> np.ndarray:
+    """Bandwidths 1/count, 2/count, ..., 1: an even grid over (0,1]."""
+    return np.arange(1, count + 1, dtype=np.float64) / count
+
+
 def gmm_truth(n: int, d: int, seed: int, components: int = 50) -> np.ndarray:
     """Component id of every point of gmm_f32(n, d, seed) (same draws)."""
     rng = np.random.default_rng(seed)
