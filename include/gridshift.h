@@ -145,6 +145,38 @@ gs_status gs_fit_hsweep(gs_context* ctx, const void* points, gs_dtype dtype, int
                         int32_t H, const double* hs, int32_t max_iter, int32_t* labels, gs_info* info, void* stream);
 
 /*
+ * Object tracking (Algorithm 2, Section 2.3) through a sequence of frames.
+ *   frames  device [T][H][W][dc] of dtype: the colour features (1 <= dc <= 4)
+ *           of pixel (px, py) (column, row) of frame t at
+ *           ((t * H + py) * W + px) * dc.  H * W < 2^31.
+ *   o0      host double [2]: the initial centre (x, y); l0 and w0 the initial
+ *           window's extents along x and y (all > 0).
+ * The window W(o, l, w) holds the pixels with |px - o_x| <= l/2 and
+ * |py - o_y| <= w/2 (binary64).  Initialisation: GridShift with bandwidth h
+ * (max_iter rounds, the context's update rule) on the colours of
+ * W(o0, l0, w0) of frame 0 in raster order; the n_select largest clusters
+ * (count descending, then cluster id) give the set B of colour cells
+ * floor(fl(c / h)) of their pixels.  Every later frame repeats, at most
+ * max_inner times: R = the pixels of the search window W(o, l/f, w/f) whose
+ * colour cell is in B; an empty R multiplies l and w by 1.1; otherwise the
+ * centre moves to the mean pixel position of R (exact integer sums, one
+ * division), B becomes the colour cells of R, l becomes 0.99 l if R's extent
+ * max px - min px is below l and 1.01 l otherwise (w likewise along y), and
+ * the loop ends once the centre moved by less than eta (dx*dx + dy*dy <
+ * eta*eta).  One workgroup runs the whole sequence in one launch.
+ *   windows host double [T][4]: (o_x, o_y, l, w) after every frame (frame 0:
+ *           the initial window).
+ * The context's last fit becomes the initial clustering.  Errors:
+ * GS_ERR_KEY_RANGE if a selected colour cell index is outside
+ * [-32768, 32767); GS_ERR_UNSUPPORTED if B would hold more than 2048 cells
+ * or dc is outside 1..4; GS_ERR_INVALID_ARG for bad sizes or parameters.
+ * Pixels whose colour cells cannot be packed are never in R (B holds none).
+ */
+gs_status gs_track(gs_context* ctx, const void* frames, gs_dtype dtype, int32_t T, int32_t H, int32_t W, int32_t dc,
+                   const double* o0, double l0, double w0, double f, double h, double eta, int32_t max_inner,
+                   int32_t n_select, int32_t max_iter, double* windows, void* stream);
+
+/*
  * Copy the cluster table of the last fit, instances concatenated in order
  * (instance b's K_b clusters start at row sum_{b'<b} K_b').
  *   modes   device double [sum K][d]: fl(S / C)           (may be NULL)

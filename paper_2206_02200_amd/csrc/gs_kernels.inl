@@ -2187,4 +2187,220 @@ __global__ void k_copy_keys(CellTable t, const InstState* __restrict__ st, const
     for (int k = 0; k < d; ++k) out[r * d + k] = int64_t((local / P.stride[k]) % uint64_t(P.E[k])) + P.lo[k];
 }
 
+// ===========================================================================
+// object tracking (Algorithm 2, Section 2.3)
+// ===========================================================================
+constexpr int kTrackThreads = 1024;
+constexpr int kTrackSlots = 4096;  // LDS hash of the colour cells B
+constexpr int kTrackMaxCells = 2048;
+constexpr int kTrackMaxChannels = 4;
+
+// Colour cell floor(fl(c_k / h)) of every channel, packed 16 bits per channel
+// (q + 32768); false if some channel is outside [-32768, 32767), or not finite.
+template <typename T>
+__device__ __forceinline__ bool track_cell(const T* __restrict__ c, int dc, double h, uint64_t* out) {
+    uint64_t key = 0;
+    bool ok = true;
+    for (int k = 0; k < dc; ++k) {
+        const double q = floor(double(c[k]) / h);
+        ok = ok && q >= -32768.0 && q < 32767.0;
+        key |= uint64_t(ok ? int64_t(q) + 32768 : 0) << (16 * k);
+    }
+    *out = key;
+    return ok;
+}
+
+__device__ __forceinline__ int track_hash(uint64_t key) {
+    return int((key * 0x9E3779B97F4A7C15ull) >> (64 - 12));  // 12 bits: kTrackSlots
+}
+
+// Slot of `key` in the LDS table, or -1.
+__device__ __forceinline__ int track_find(const uint64_t* tab, uint64_t key) {
+    int s = track_hash(key);
+    for (int probe = 0; probe < kTrackSlots; ++probe) {
+        const uint64_t v = tab[s];
+        if (v == key) return s;
+        if (v == ~0ull) return -1;
+        s = (s + 1) & (kTrackSlots - 1);
+    }
+    return -1;
+}
+
+// One workgroup tracks one object through frames 1..T-1 (frame t, pixel
+// (px, py): colour at ((t * H + py) * W + px) * dc).  B starts as the colour
+// cells of the window pixels (win, n0 rows of dc values, raster order) whose
+// initial cluster label is selected (sel[label] != 0).  Per frame, at most
+// max_inner times: the search window W(o, l/f, w/f) (|px - o_x| <= l'/2,
+// |py - o_y| <= w'/2); R = its pixels whose colour cell is in B; an empty R
+// widens l and w by 1.1; otherwise o moves to the mean pixel position of R
+// (exact integer sums), B shrinks to the cells R hit, l and w shrink by 0.99
+// when R's extent along them is below them and grow by 1.01 otherwise, and
+// the loop ends once the centre moved by less than eta.  windows[t] =
+// (o_x, o_y, l, w) after frame t.  err: 1 = a selected colour cell is out of
+// the packable range, 2 = B exceeds kTrackMaxCells.
+template <typename T>
+__global__ __launch_bounds__(kTrackThreads) void k_track(const T* __restrict__ frames, int nT, int H, int W, int dc,
+                                                         const T* __restrict__ win, const int32_t* __restrict__ labels,
+                                                         int64_t n0, const int32_t* __restrict__ sel, double ox0,
+                                                         double oy0, double l0, double w0, double f, double h,
+                                                         double eta, int max_inner, double* __restrict__ windows,
+                                                         int32_t* __restrict__ err) {
+    constexpr int NW = kTrackThreads / kWave;
+    __shared__ uint64_t tab[kTrackSlots];
+    __shared__ uint32_t hit[kTrackSlots];  // stamp of the last step whose R held the cell
+    __shared__ uint8_t alive[kTrackSlots];
+    __shared__ int64_t red_i[NW][3];       // count, sum px, sum py
+    __shared__ int32_t red_m[NW][4];       // min px, -max px, min py, -max py
+    __shared__ double st_d[4];             // o_x, o_y, l, w
+    __shared__ int st_flag[2];             // done, R non-empty
+    __shared__ int s_ncells, s_err;
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    for (int i = tid; i < kTrackSlots; i += kTrackThreads) {
+        tab[i] = ~0ull;
+        hit[i] = 0;
+        alive[i] = 0;
+    }
+    if (tid == 0) {
+        s_ncells = 0;
+        s_err = 0;
+        st_d[0] = ox0;
+        st_d[1] = oy0;
+        st_d[2] = l0;
+        st_d[3] = w0;
+    }
+    __syncthreads();
+    // ---- B: colour cells of the selected initial clusters
+    for (int64_t j = tid; j < n0; j += kTrackThreads) {
+        if (!sel[labels[j]]) continue;
+        uint64_t key;
+        if (!track_cell(win + j * dc, dc, h, &key)) {
+            atomicOr(&s_err, 1);
+            continue;
+        }
+        int s = track_hash(key);
+        for (int probe = 0; probe < kTrackSlots; ++probe) {
+            const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[s]), ~0ull, key);
+            if (prev == ~0ull) {
+                alive[s] = 1;
+                atomicAdd(&s_ncells, 1);
+                break;
+            }
+            if (prev == key) break;
+            s = (s + 1) & (kTrackSlots - 1);
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && s_ncells > kTrackMaxCells) s_err |= 2;
+    __syncthreads();
+    if (s_err) {
+        if (tid == 0) *err = s_err;
+        return;
+    }
+    uint32_t stamp = 0;
+    for (int t = 1; t < nT; ++t) {
+        const T* fr = frames + int64_t(t) * H * W * dc;
+        for (int it = 0; it < max_inner; ++it) {
+            ++stamp;
+            const double ox = st_d[0], oy = st_d[1];
+            const double hl = 0.5 * (st_d[2] / f), hw = 0.5 * (st_d[3] / f);
+            // bounding rows and columns (one pixel of margin), clamped to the frame
+            const int c0 = int(fmax(0.0, ceil(ox - hl) - 1.0)), c1 = int(fmin(double(W - 1), floor(ox + hl) + 1.0));
+            const int r0 = int(fmax(0.0, ceil(oy - hw) - 1.0)), r1 = int(fmin(double(H - 1), floor(oy + hw) + 1.0));
+            const int ncols = c1 >= c0 ? c1 - c0 + 1 : 0;
+            const int npix = r1 >= r0 ? (r1 - r0 + 1) * ncols : 0;  // H * W < 2^31
+            int64_t cnt = 0, sx = 0, sy = 0;
+            int32_t mnx = INT32_MAX, mxx = INT32_MIN, mny = INT32_MAX, mxy = INT32_MIN;
+            for (int e = tid; e < npix; e += kTrackThreads) {
+                const int rr = e / ncols;
+                const int py = r0 + rr, px = c0 + (e - rr * ncols);
+                if (!(fabs(double(px) - ox) <= hl && fabs(double(py) - oy) <= hw)) continue;
+                uint64_t key;
+                if (!track_cell(fr + (int64_t(py) * W + px) * dc, dc, h, &key)) continue;
+                const int s = track_find(tab, key);
+                if (s < 0 || !alive[s]) continue;
+                hit[s] = stamp;
+                ++cnt;
+                sx += px;
+                sy += py;
+                mnx = min(mnx, px);
+                mxx = max(mxx, px);
+                mny = min(mny, py);
+                mxy = max(mxy, py);
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                cnt += __shfl_xor(cnt, off, kWave);
+                sx += __shfl_xor(sx, off, kWave);
+                sy += __shfl_xor(sy, off, kWave);
+                mnx = min(mnx, __shfl_xor(mnx, off, kWave));
+                mxx = max(mxx, __shfl_xor(mxx, off, kWave));
+                mny = min(mny, __shfl_xor(mny, off, kWave));
+                mxy = max(mxy, __shfl_xor(mxy, off, kWave));
+            }
+            if (lane == 0) {
+                red_i[w][0] = cnt;
+                red_i[w][1] = sx;
+                red_i[w][2] = sy;
+                red_m[w][0] = mnx;
+                red_m[w][1] = mxx;
+                red_m[w][2] = mny;
+                red_m[w][3] = mxy;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int64_t C = 0, SX = 0, SY = 0;
+                int32_t a = INT32_MAX, bx = INT32_MIN, c = INT32_MAX, dy_ = INT32_MIN;
+                for (int ww = 0; ww < NW; ++ww) {
+                    C += red_i[ww][0];
+                    SX += red_i[ww][1];
+                    SY += red_i[ww][2];
+                    a = min(a, red_m[ww][0]);
+                    bx = max(bx, red_m[ww][1]);
+                    c = min(c, red_m[ww][2]);
+                    dy_ = max(dy_, red_m[ww][3]);
+                }
+                double l = st_d[2], wd = st_d[3];
+                int done = 0;
+                if (C == 0) {
+                    l = 1.1 * l;
+                    wd = 1.1 * wd;
+                } else {
+                    const double nx = double(SX) / double(C), ny = double(SY) / double(C);
+                    l = double(bx - a) < l ? 0.99 * l : 1.01 * l;
+                    wd = double(dy_ - c) < wd ? 0.99 * wd : 1.01 * wd;
+                    const double ddx = nx - ox, ddy = ny - oy;
+                    done = ddx * ddx + ddy * ddy < eta * eta;
+                    st_d[0] = nx;
+                    st_d[1] = ny;
+                }
+                st_d[2] = l;
+                st_d[3] = wd;
+                st_flag[0] = done;
+                st_flag[1] = C > 0;
+            }
+            __syncthreads();
+            if (st_flag[1]) {  // B becomes the cells R hit
+                for (int i = tid; i < kTrackSlots; i += kTrackThreads)
+                    if (alive[i] && hit[i] != stamp) alive[i] = 0;
+            }
+            const int done = st_flag[0];
+            __syncthreads();
+            if (done) break;
+        }
+        if (tid == 0) {
+            windows[int64_t(t) * 4 + 0] = st_d[0];
+            windows[int64_t(t) * 4 + 1] = st_d[1];
+            windows[int64_t(t) * 4 + 2] = st_d[2];
+            windows[int64_t(t) * 4 + 3] = st_d[3];
+        }
+    }
+    if (tid == 0) {
+        windows[0] = ox0;
+        windows[1] = oy0;
+        windows[2] = l0;
+        windows[3] = w0;
+        *err = 0;
+    }
+}
+
 }  // namespace gs

@@ -34,7 +34,7 @@ EXPORTED = [
     "gs_profile_enable", "gs_profile_reset", "gs_profile_count", "gs_profile_entry",
     "gs_context_set_tape", "gs_backward", "gs_point_mode_loss", "gs_point_mode_loss_backward",
     "gs_context_set_config", "gs_context_get_config", "gs_autotune",
-    "gs_context_set_update", "gs_context_get_update", "gs_fit_hsweep",
+    "gs_context_set_update", "gs_context_get_update", "gs_fit_hsweep", "gs_track",
 ]
 CFG_MERGE_SMALL, CFG_TILE_CHUNKS, CFG_DENSE_TABLE = 0, 1, 2
 CONFIG_KEYS = {"merge_small": CFG_MERGE_SMALL, "tile_chunks": CFG_TILE_CHUNKS, "dense_table": CFG_DENSE_TABLE}
@@ -88,6 +88,8 @@ def load_library(path: str = LIB_PATH):
         lib.gs_fit_batched.restype = ctypes.c_int
         lib.gs_fit_hsweep.argtypes = [V, V, ctypes.c_int, I64, I32, I64, I32, V, I32, V, V, V]
         lib.gs_fit_hsweep.restype = ctypes.c_int
+        lib.gs_track.argtypes = [V, V, ctypes.c_int, I32, I32, I32, I32, V, D, D, D, D, D, I32, I32, I32, V, V]
+        lib.gs_track.restype = ctypes.c_int
         lib.gs_copy_modes.argtypes = [V, V, V, V, V]
         lib.gs_copy_modes.restype = ctypes.c_int
         lib.gs_copy_keys.argtypes = [V, V, V]
@@ -350,6 +352,32 @@ def fit_hsweep(x: torch.Tensor, hs, max_iter: int = 100, *, with_sums: bool = Fa
     _check(lib.gs_copy_modes(ctx.handle, ctypes.c_void_p(modes.data_ptr()), ctypes.c_void_p(counts.data_ptr()),
                              ctypes.c_void_p(sums.data_ptr() if sums is not None else 0), sp))
     return BatchedResult(labels, modes, counts, koff, [infos[j].as_dict() for j in range(H)], sums)
+
+
+def track(frames: torch.Tensor, o0, l0: float, w0: float, f: float, h: float, eta: float, max_inner: int = 20,
+          n_select: int = 1, max_iter: int = 100, *, ctx: Context | None = None, stream=None) -> np.ndarray:
+    """Object tracking (Algorithm 2) through ``frames`` ([T, H, W, dc] float32
+    or float64 colour features on the GPU); returns the windows
+    (o_x, o_y, l, w) of every frame as a float64 [T, 4] array."""
+    lib = load_library()
+    if frames.dim() != 4 or not frames.is_cuda:
+        raise ValueError("frames must be a [T, H, W, dc] GPU tensor")
+    if frames.dtype == torch.float32:
+        dt = GS_F32
+    elif frames.dtype == torch.float64:
+        dt = GS_F64
+    else:
+        raise TypeError("frames must be float32 or float64")
+    frames = frames.contiguous()
+    T, H, W, dc = frames.shape
+    ctx = ctx or default_context(frames.device.index)
+    o = np.ascontiguousarray(np.asarray(o0, dtype=np.float64).ravel()[:2])
+    out = np.empty((T, 4), np.float64)
+    _check(lib.gs_track(ctx.handle, ctypes.c_void_p(frames.data_ptr()), dt, T, H, W, dc,
+                        o.ctypes.data_as(ctypes.c_void_p), float(l0), float(w0), float(f), float(h), float(eta),
+                        int(max_inner), int(n_select), int(max_iter), out.ctypes.data_as(ctypes.c_void_p),
+                        _stream_ptr(stream)))
+    return out
 
 
 # ---------------------------------------------------------------------------
