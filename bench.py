@@ -21,7 +21,7 @@ carries, under "forms", the other two forms of the workload family:
            d = 2..6: the cost of the 3^d neighbour gather per dimension.
 The plain form also reports its time per phase (binning, rounds, labels).
 
-  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--forms plain,batched,fwd_bwd,gmm,sequential,hsweep]
+  python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--forms plain,batched,fwd_bwd,gmm,sequential,hsweep,track]
 """
 from __future__ import annotations
 
@@ -108,7 +108,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,batched,fwd_bwd,gmm,sequential,hsweep")
+    ap.add_argument("--forms", default="plain,batched,fwd_bwd,gmm,sequential,hsweep,track")
     ap.add_argument("--form-only", choices=["batched", "fwd_bwd"], default=None,
                     help="time only this form (--steps timed calls after one warm-up) and print its JSON object; "
                          "for profiling a form on its own")
@@ -232,6 +232,8 @@ def main() -> int:
         out["forms"]["gmm"] = bench_gmm(dev, max(1, args.steps // 4))
     if "hsweep" in forms:
         out["forms"]["hsweep"] = bench_hsweep(dev, max(1, args.steps // 4))
+    if "track" in forms:
+        out["forms"]["track"] = bench_track(dev, max(1, args.steps // 10))
     if "fwd_bwd" in forms:
         out["forms"]["fwd_bwd"] = bench_fwd_bwd(dev, max(1, args.steps // 10))
     if not args.no_cpu_baseline:
@@ -306,6 +308,34 @@ def bench_hsweep(dev, steps: int) -> dict:
                        "h = 0.02..1.00 step 0.02, one batched pass"}
     ctx.close()
     return out
+
+
+def bench_track(dev, steps: int) -> dict:
+    """Object tracking (Algorithm 2): a 640x480 RGB float32 video of 200
+    frames, one moving disc; the whole sequence (initial GridShift + every
+    frame) per step."""
+    import numpy as np
+    import torch
+
+    from paper_2206_02200_amd import gridshift, synth
+
+    frames, centres = synth.moving_blob_video(T=200, H=480, W=640, radius=28.0, seed=7)
+    fr = torch.from_numpy(frames).to(dev)
+    ctx = gridshift.Context(0)
+    args = (fr, centres[0], 48.0, 48.0, 0.8, 16.0, 0.5, 20)
+    win = gridshift.track(*args, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        win = gridshift.track(*args, ctx=ctx)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    T = frames.shape[0]
+    ctx.close()
+    return {"value": T / (ms * 1e-3), "unit": "frames/s", "ms_per_step": ms, "steps": steps, "frames": T,
+            "max_centre_error_px": float(np.abs(win[:, :2] - centres).max()),
+            "workload": "640x480 RGB f32, 200 frames, one textured disc (radius 28) moving 2-5 px/frame; "
+                        "h=16, f=0.8, eta=0.5, max_inner=20, the largest initial cluster"}
 
 
 def bench_gmm(dev, steps: int) -> dict:
