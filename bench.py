@@ -109,7 +109,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="plain,batched,fwd_bwd,gmm,sequential,hsweep,track")
-    ap.add_argument("--form-only", choices=["batched", "fwd_bwd"], default=None,
+    ap.add_argument("--form-only", choices=["batched", "fwd_bwd", "sequential", "hsweep", "track"], default=None,
                     help="time only this form (--steps timed calls after one warm-up) and print its JSON object; "
                          "for profiling a form on its own")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
@@ -131,9 +131,17 @@ def main() -> int:
     torch.cuda.set_device(dev)
     if args.form_only:
         if args.form_only == "batched":
-            print(json.dumps(bench_batched(gridshift.Context(0), dev, args.steps)), flush=True)
+            res = bench_batched(gridshift.Context(0), dev, args.steps)
+        elif args.form_only == "sequential":
+            w = synth.image_xylab_f32()
+            res = bench_sequential(torch.from_numpy(w.x).to(dev), w, args.steps)
+        elif args.form_only == "hsweep":
+            res = bench_hsweep(dev, args.steps)
+        elif args.form_only == "track":
+            res = bench_track(dev, args.steps)
         else:
-            print(json.dumps(bench_fwd_bwd(dev, args.steps)), flush=True)
+            res = bench_fwd_bwd(dev, args.steps)
+        print(json.dumps(res), flush=True)
         return 0
     if args.calibration_copy_mb > 0:
         src = torch.ones(args.calibration_copy_mb << 18, dtype=torch.float32, device=dev)
