@@ -1407,11 +1407,11 @@ __global__ void k_tail_gate(const InstState* __restrict__ st, int B, int64_t* __
 }
 
 // With `gate` set and nonzero the kernel returns at once, changing nothing.
-// SEQ runs the sequential form of Eq. 5 colour by colour (bit D-1-k of a
-// cell's colour = parity of its integer coordinate k; cells of one colour are
-// never neighbours): the cells of a colour move together, each then writes
-// fl(C_j * p_j) over its sum for the colours after it, and a round that stops
-// puts the sums back.  SEQ fits record no tape or checkpoints.
+// SEQ runs the sequential form of Eq. 5 in the colour-by-colour order (bit
+// D-1-k of a cell's colour = parity of its integer coordinate k; cells of one
+// colour are never neighbours): a moved cell writes fl(C_j * p_j) over its sum
+// for the cells moving after it, and a round that stops puts the sums back.
+// SEQ fits record no tape or checkpoints.
 template <int D, bool SEQ>
 __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstParam* __restrict__ param,
                                                        InstState* __restrict__ st, uint32_t* __restrict__ tmap,
@@ -1435,7 +1435,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
     __shared__ uint16_t col[kSlabMax + 1];  // column table of the current cells
     __shared__ uint16_t rank_of[MT];        // old cell -> sorted position
     __shared__ int32_t s_flag[2][3];         // per round parity: any neighbour, bad key, changed
-    __shared__ unsigned long long s_cols[2];  // per round parity: colours present (sequential form)
+    __shared__ uint8_t cstate[MT];  // sequential form: colour of each cell, bit 7 once it has moved
+    __shared__ int32_t s_pend[2];   // sequential form, per step parity: some cell still waits
 
     if (gate && *gate) return;
     const int b = blockIdx.x;
@@ -1472,7 +1473,6 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         s_Ed[tid] = double(P.E[tid]);
         if (tid < 2) s_E01[tid] = P.E[tid < D ? tid : 0];
     }
-    if (tid < 2) s_cols[tid] = 0;
 
     if (tid < m_entry) {
         uint64_t lk;
@@ -1532,18 +1532,21 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
 #pragma unroll
                 for (int k = 0; k < D; ++k) rp = (rp << 1) | (crd[k][tid] & 1);
                 my_col = rp ^ lo_par;
-                atomicOr(&s_cols[round & 1], 1ull << my_col);
+                cstate[tid] = uint8_t(my_col);  // colour; bit 7 set once the cell has moved
             }
+            if (tid < 2) s_pend[tid] = 0;
         }
         __syncthreads();
         // every thread has finished reading the other parity's flags
         if (tid < 3) s_flag[(round + 1) & 1][tid] = 0;
-        uint64_t present = 1;  // colours to visit; the parallel form visits once
-        if constexpr (SEQ) {
-            present = s_cols[round & 1];
-            if (tid == 0) s_cols[(round + 1) & 1] = 0;
-        }
         // ---- shift (one cell per thread)
+        // Sequential form: instead of one step per colour, a cell moves in the
+        // first step in which all its neighbours of lower colours have moved
+        // (its neighbours of higher colours wait for it in turn), so it reads
+        // exactly the sums the colour-by-colour sweep gives it: C_k * p_k of
+        // the lower colours, the round's sums of the higher ones.  Moves are
+        // committed after a barrier; the steps number the longest chain of
+        // ascending colours among neighbours, at most 2^D.
         bool nb = false, bad = false;
         bool chg = false;  // stationarity: landing key or merge value differs from the cell's own
         double p[D];
@@ -1552,9 +1555,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         int32_t q[D];
         uint64_t kj = 0;
         int32_t Wj = 0;
-        for (int cc = 0; cc < (SEQ ? (1 << D) : 1); ++cc) {
-        if (SEQ && !((present >> cc) & 1)) continue;  // block-uniform
-        if (tid < m && (!SEQ || my_col == cc)) {
+        bool pending = tid < m;
+        for (int lvl = 0; lvl < (SEQ ? (1 << D) : 1); ++lvl) {
+        bool ready = true;
+        if (pending) {
             const TailWindow win = tail_window(cols, crd[0], crd[D >= 2 ? 1 : 0], m, tid, col);
             const int ncand = win.n[0] + win.n[1] + win.n[2];
             int32_t me[D];
@@ -1568,7 +1572,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
 #pragma unroll
             for (int dd = 0; dd < D; ++dd) p[dd] = -0.0;
             int nbs = 0;
-            constexpr int U = D >= 5 ? 2 : 4;  // candidates per step (register budget of 1024 threads)
+            constexpr int U = (D >= 5 || (SEQ && D >= 4)) ? 2 : 4;  // candidates per step (register budget of 1024 threads)
             for (int k0 = 0; k0 < ncand; k0 += U) {
                 int okm[U];
                 int kk[U];
@@ -1587,15 +1591,17 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
                 for (int u = 0; u < U; ++u) {
                     const int k = kk[u];
                     const bool ok = okm[u] != 0;
-                    // the sequential sweep reads sums only of neighbours (a
-                    // cell of this colour may be rewriting its own meanwhile)
-                    const int ks = SEQ ? (ok ? k : tid) : k;
+                    if constexpr (SEQ) {  // a neighbour of a lower colour that has not moved yet
+                        const int cs8 = cstate[k];
+                        if (ok && (cs8 & 63) < my_col && !(cs8 & 128)) ready = false;
+                    }
                     W += ok ? int64_t(cnt[k]) : 0;
                     nbs += ok ? 1 : 0;
 #pragma unroll
-                    for (int dd = 0; dd < D; ++dd) p[dd] = p[dd] + (ok ? sm[dd][ks] : -0.0);
+                    for (int dd = 0; dd < D; ++dd) p[dd] = p[dd] + (ok ? sm[dd][k] : -0.0);
                 }
             }
+            if (ready) {
             nb = nbs > 1;  // the cell itself is always among the candidates
             Wj = int32_t(W);
 #pragma unroll
@@ -1615,15 +1621,25 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
                 val[dd] = double(cnt[tid]) * p[dd];
                 chg = chg || dbits(val[dd]) != dbits(sm[dd][tid]);
             }
-            if constexpr (SEQ) {  // the cells moving after this one read C_j * p_j
+            }
+        }
+        if constexpr (SEQ) {
+            if (__ballot(pending && !ready) && lane == 0) atomicOr(&s_pend[lvl & 1], 1);
+            __syncthreads();
+            if (pending && ready) {  // commit: the cells moving later read C_j * p_j
 #pragma unroll
                 for (int dd = 0; dd < D; ++dd) {
                     orig[dd] = sm[dd][tid];
                     sm[dd][tid] = val[dd];
                 }
+                cstate[tid] = uint8_t(my_col | 128);
+                pending = false;
             }
+            const int more = s_pend[lvl & 1];
+            if (tid == 0) s_pend[(lvl + 1) & 1] = 0;
+            __syncthreads();
+            if (!more) break;
         }
-        if constexpr (SEQ) __syncthreads();
         }
         if (__ballot(nb) && lane == 0) atomicOr(&flg[0], 1);
         if (__ballot(bad) && lane == 0) atomicOr(&flg[1], 1);
