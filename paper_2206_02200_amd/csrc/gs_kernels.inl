@@ -2326,22 +2326,39 @@ __global__ __launch_bounds__(kTrackThreads) void k_track(const T* __restrict__ f
             const int npix = r1 >= r0 ? (r1 - r0 + 1) * ncols : 0;  // H * W < 2^31
             int64_t cnt = 0, sx = 0, sy = 0;
             int32_t mnx = INT32_MAX, mxx = INT32_MIN, mny = INT32_MAX, mxy = INT32_MIN;
-            for (int e = tid; e < npix; e += kTrackThreads) {
-                const int rr = e / ncols;
-                const int py = r0 + rr, px = c0 + (e - rr * ncols);
-                if (!(fabs(double(px) - ox) <= hl && fabs(double(py) - oy) <= hw)) continue;
-                uint64_t key;
-                if (!track_cell(fr + (int64_t(py) * W + px) * dc, dc, h, &key)) continue;
-                const int s = track_find(tab, key);
-                if (s < 0 || !alive[s]) continue;
-                hit[s] = stamp;
-                ++cnt;
-                sx += px;
-                sy += py;
-                mnx = min(mnx, px);
-                mxx = max(mxx, px);
-                mny = min(mny, py);
-                mxy = max(mxy, py);
+            // TP pixels per thread per pass, every colour load issued before any is used
+            constexpr int TP = 4;
+            for (int e0 = 0; e0 < npix; e0 += TP * kTrackThreads) {
+                T cv[TP][kTrackMaxChannels];
+                int pxs[TP], pys[TP];
+                bool in[TP];
+#pragma unroll
+                for (int u = 0; u < TP; ++u) {
+                    const int e = e0 + u * kTrackThreads + tid;
+                    const int rr = e / ncols;
+                    pys[u] = r0 + rr;
+                    pxs[u] = c0 + (e - rr * ncols);
+                    in[u] = e < npix && fabs(double(pxs[u]) - ox) <= hl && fabs(double(pys[u]) - oy) <= hw;
+                    const T* c = fr + (int64_t(in[u] ? pys[u] : 0) * W + (in[u] ? pxs[u] : 0)) * dc;
+#pragma unroll
+                    for (int k = 0; k < kTrackMaxChannels; ++k) cv[u][k] = k < dc ? c[k] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < TP; ++u) {
+                    uint64_t key;
+                    if (!in[u] || !track_cell(cv[u], dc, h, &key)) continue;
+                    const int s = track_find(tab, key);
+                    if (s < 0 || !alive[s]) continue;
+                    const int px = pxs[u], py = pys[u];
+                    hit[s] = stamp;
+                    ++cnt;
+                    sx += px;
+                    sy += py;
+                    mnx = min(mnx, px);
+                    mxx = max(mxx, px);
+                    mny = min(mny, py);
+                    mxy = max(mxy, py);
+                }
             }
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
