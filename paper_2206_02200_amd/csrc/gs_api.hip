@@ -62,6 +62,7 @@ struct gs_config {
 struct gs_context {
     int device = 0;
     int rule = GS_UPDATE_PARALLEL;  // update rule of the shift (gs_context_set_update)
+    int tail_tok = -1;              // profiling record of the last tail launch
     // point level
     DBuf kA, kB, vA, vB, cell0;
     // cell tables (ping-pong) and per-round scratch
@@ -215,6 +216,11 @@ void prof_end(gs_context* c, hipStream_t s, int tok, double bytes) {
     Profiler& p = c->prof;
     (void)hipEventRecord(p.ev[p.recs[tok].e1], s);
     p.recs[tok].bytes = bytes;
+}
+
+// Algorithmic bytes of a recorded launch, once the host knows them.
+void prof_set_bytes(gs_context* c, int tok, double bytes) {
+    if (tok >= 0 && size_t(tok) < c->prof.recs.size()) c->prof.recs[tok].bytes = bytes;
 }
 
 // Accumulate the recorded intervals (the stream has been synchronised).
@@ -563,6 +569,7 @@ gs_status launch_tail(gs_context* c, int d, int B, gs::CellTable t, const gs::In
                       int max_iter, const gs::TailTape& tape, const gs::TailCkpt& ck, int replay_r0, hipStream_t s,
                       double nbytes, const int64_t* gate = nullptr) {
     const int tk = prof_begin(c, s, replay_r0 >= 0 ? "tail_replay" : "tail");
+    c->tail_tok = tk;
     switch (d) {
 #define GS_TL(D)                                                                                                  \
     case D:                                                                                                       \
@@ -833,6 +840,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         } else if (c->tape_on && max_iter > 0) {
             GS_TRY(tail_tape(c, max_iter, B, &tape));
         }
+        // (bytes: an upper bound, replaced once the host knows the cell counts)
         GS_TRY(launch_tail(c, d, B, TC, prm, st, P<uint32_t>(c->tmap), max_iter, tape, ck, -1, s,
                            2.0 * Mnow * (16.0 + 8.0 * d), gate));
         if (N > 0) {
@@ -1001,6 +1009,11 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         for (int b = 0; b < B; ++b)
             if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");
         if (!gate) {
+            // the tail read the merged table (M cells) and wrote the final one
+            // and the entry map; the launch could only bound M from above
+            int64_t kfin = 0;
+            for (int b = 0; b < B; ++b) kfin += c->st[b].K;
+            prof_set_bytes(c, c->tail_tok, double(M + kfin) * (16.0 + 8.0 * d) + 4.0 * double(M));
             tail_done = true;
             break;
         }
@@ -1014,6 +1027,9 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         } else {
             GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
         }
+        int64_t kfin = 0;
+        for (int b = 0; b < B; ++b) kfin += c->st[b].K;
+        prof_set_bytes(c, c->tail_tok, double(M + kfin) * (16.0 + 8.0 * d) + 4.0 * double(M));
     }
     for (int b = 0; b < B; ++b) {
         if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");
