@@ -339,11 +339,29 @@ def bench_track(dev, steps: int) -> dict:
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     T = frames.shape[0]
+    out = {"value": T / (ms * 1e-3), "unit": "frames/s", "ms_per_step": ms, "steps": steps, "frames": T,
+           "max_centre_error_px": float(np.abs(win[:, :2] - centres).max()),
+           "workload": "640x480 RGB f32, 200 frames, one textured disc (radius 28) moving 2-5 px/frame; "
+                       "h=16, f=0.8, eta=0.5, max_inner=20, the largest initial cluster"}
+    # many objects at once: 32 discs (radius 14), one workgroup per track
+    nd = 32
+    frames, centres = synth.moving_blob_video(T=200, H=480, W=640, radius=14.0, seed=8, discs=nd)
+    fr = torch.from_numpy(frames).to(dev)
+    bargs = (fr, centres[0], np.full(nd, 24.0), np.full(nd, 24.0), 0.8, 16.0, 0.5, 20)
+    bw = gridshift.track_batched(*bargs, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bw = gridshift.track_batched(*bargs, ctx=ctx)
+    torch.cuda.synchronize()
+    bms = (time.perf_counter() - t0) * 1e3 / steps
+    err = np.abs(bw[:, :, :2] - np.transpose(centres, (1, 0, 2)))
+    out["batched"] = {"value": nd * T / (bms * 1e-3), "unit": "track-frames/s", "ms_per_step": bms, "tracks": nd,
+                      "median_centre_error_px": float(np.median(err)),
+                      "workload": "640x480 RGB f32, 200 frames, 32 textured discs (radius 14) of distinct colours, "
+                                  "one track each, one launch"}
     ctx.close()
-    return {"value": T / (ms * 1e-3), "unit": "frames/s", "ms_per_step": ms, "steps": steps, "frames": T,
-            "max_centre_error_px": float(np.abs(win[:, :2] - centres).max()),
-            "workload": "640x480 RGB f32, 200 frames, one textured disc (radius 28) moving 2-5 px/frame; "
-                        "h=16, f=0.8, eta=0.5, max_inner=20, the largest initial cluster"}
+    return out
 
 
 def bench_gmm(dev, steps: int) -> dict:

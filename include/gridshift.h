@@ -177,6 +177,20 @@ gs_status gs_track(gs_context* ctx, const void* frames, gs_dtype dtype, int32_t 
                    int32_t n_select, int32_t max_iter, double* windows, void* stream);
 
 /*
+ * Several objects tracked through the same frames at once: gs_track for
+ * each of ntracks initial windows, bitwise the same per track.  The initial
+ * windows are clustered in one batched pass and each track runs in its own
+ * workgroup of one launch.
+ *   o0      host double [ntracks][2]; l0, w0 host double [ntracks].
+ *   windows host double [ntracks][T][4].
+ * The context's last fit becomes the batched initial clustering.
+ */
+gs_status gs_track_batched(gs_context* ctx, const void* frames, gs_dtype dtype, int32_t T, int32_t H, int32_t W,
+                           int32_t dc, int32_t ntracks, const double* o0, const double* l0, const double* w0, double f,
+                           double h, double eta, int32_t max_inner, int32_t n_select, int32_t max_iter,
+                           double* windows, void* stream);
+
+/*
  * Copy the cluster table of the last fit, instances concatenated in order
  * (instance b's K_b clusters start at row sum_{b'<b} K_b').
  *   modes   device double [sum K][d]: fl(S / C)           (may be NULL)

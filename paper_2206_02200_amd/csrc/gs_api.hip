@@ -113,7 +113,7 @@ struct gs_context {
     int ck_nslots = 0;
     DBuf sums0, inst0, wt_key, wt_cnt, wt_inst, wt_W, wt_g, wt_app;
     DBuf rep;  // the replicated points of a bandwidth sweep
-    DBuf trk_win, trk_lab, trk_cnt, trk_sel, trk_out;  // tracking: initial window, labels, selection, output
+    DBuf trk_win, trk_lab, trk_cnt, trk_sel, trk_out, trk_rect, trk_init;  // tracking buffers
     DBuf tt_key, tt_cnt, tt_W, tt_g, tt_m;
     // backward with checkpoints: a second stream recomputes the next (earlier)
     // tape segment while the current one is reversed (two tape buffers)
@@ -1527,7 +1527,7 @@ void gs_context_destroy(gs_context* c) {
                    &c->tt_key, &c->tt_cnt, &c->tt_W, &c->tt_g, &c->tt_m, &c->sbA, &c->sbB, &c->qbuf, &c->gmodes,
                    &c->modes_i, &c->counts_i, &c->frows, &c->lossc, &c->ltab, &c->xkA, &c->xkB, &c->xvA, &c->xvB,
                    &c->ck_key, &c->ck_cnt, &c->ck_sum, &c->ck_m, &c->tune_labels, &c->dk, &c->rep,
-                   &c->trk_win, &c->trk_lab, &c->trk_cnt, &c->trk_sel, &c->trk_out};
+                   &c->trk_win, &c->trk_lab, &c->trk_cnt, &c->trk_sel, &c->trk_out, &c->trk_rect, &c->trk_init};
     for (DBuf* b : tb2)
         if (b->p) (void)hipFree(b->p);
     delete c;
@@ -1583,26 +1583,30 @@ gs_status gs_fit_hsweep(gs_context* ctx, const void* points, gs_dtype dtype, int
     return fit_impl(c, rows, dtype, d, d, H, off.data(), hs, max_iter, labels, info, s);
 }
 
-gs_status gs_track(gs_context* ctx, const void* frames, gs_dtype dtype, int32_t T, int32_t H, int32_t W, int32_t dc,
-                   const double* o0, double l0, double w0, double f, double h, double eta, int32_t max_inner,
-                   int32_t n_select, int32_t max_iter, double* windows, void* stream) {
+gs_status gs_track_batched(gs_context* ctx, const void* frames, gs_dtype dtype, int32_t T, int32_t H, int32_t W,
+                           int32_t dc, int32_t ntracks, const double* o0, const double* l0, const double* w0, double f,
+                           double h, double eta, int32_t max_inner, int32_t n_select, int32_t max_iter,
+                           double* windows, void* stream) {
     if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
-    if (T < 1 || H < 1 || W < 1 || int64_t(H) * W >= (int64_t(1) << 31) || !frames || !o0 || !windows)
-        return fail(GS_ERR_INVALID_ARG, "T, H, W >= 1, H * W < 2^31, frames, o0 and windows are required");
+    if (T < 1 || H < 1 || W < 1 || int64_t(H) * W >= (int64_t(1) << 31) || !frames || !o0 || !l0 || !w0 ||
+        !windows || ntracks < 1)
+        return fail(GS_ERR_INVALID_ARG, "T, H, W, ntracks >= 1, H * W < 2^31, frames, o0, l0, w0, windows required");
     if (dc < 1 || dc > gs::kTrackMaxChannels) return fail(GS_ERR_UNSUPPORTED, "dc must be in 1..4");
     if (dtype != GS_F32 && dtype != GS_F64) return fail(GS_ERR_INVALID_ARG, "dtype must be GS_F32 or GS_F64");
     auto pos_finite = [](double v) { return v > 0.0 && std::isfinite(v); };
-    if (!pos_finite(l0) || !pos_finite(w0) || !pos_finite(f) || !pos_finite(h) || !pos_finite(eta) ||
-        !std::isfinite(o0[0]) || !std::isfinite(o0[1]))
-        return fail(GS_ERR_INVALID_ARG, "l0, w0, f, h and eta must be finite and > 0, o0 finite");
+    if (!pos_finite(f) || !pos_finite(h) || !pos_finite(eta))
+        return fail(GS_ERR_INVALID_ARG, "f, h and eta must be finite and > 0");
+    for (int t = 0; t < ntracks; ++t)
+        if (!pos_finite(l0[t]) || !pos_finite(w0[t]) || !std::isfinite(o0[2 * t]) || !std::isfinite(o0[2 * t + 1]))
+            return fail(GS_ERR_INVALID_ARG, "l0, w0 must be finite and > 0, o0 finite");
     if (max_inner < 1 || n_select < 1 || max_iter < 0)
         return fail(GS_ERR_INVALID_ARG, "max_inner >= 1, n_select >= 1, max_iter >= 0");
     gs_context* c = ctx;
     hipStream_t s = static_cast<hipStream_t>(stream);
     GS_HIP(hipSetDevice(c->device));
     const size_t es = dtype == GS_F32 ? 4 : 8;
-    // the initial window of frame 0: an interval of columns and one of rows
-    // (the membership test |p - o| <= extent / 2 separates)
+    // the initial windows of frame 0: an interval of columns and one of rows
+    // each (the membership test |p - o| <= extent / 2 separates)
     auto span = [](int n, double o, double ext, int* a, int* b) {
         *a = n;
         *b = -1;
@@ -1612,60 +1616,92 @@ gs_status gs_track(gs_context* ctx, const void* frames, gs_dtype dtype, int32_t 
                 *b = std::max(*b, p);
             }
     };
-    int cx0, cx1, ry0, ry1;
-    span(W, o0[0], l0, &cx0, &cx1);
-    span(H, o0[1], w0, &ry0, &ry1);
-    const int64_t ncols = cx1 >= cx0 ? cx1 - cx0 + 1 : 0, nrows = ry1 >= ry0 ? ry1 - ry0 + 1 : 0;
-    const int64_t n0 = ncols * nrows;
-    int64_t K = 0;
-    if (n0 > 0) {
-        GS_TRY(ensure(c->trk_win, size_t(n0) * dc * es));
-        GS_TRY(ensure(c->trk_lab, size_t(n0) * 4));
-        GS_HIP(hipMemcpy2DAsync(c->trk_win.p, size_t(ncols) * dc * es,
-                                static_cast<const char*>(frames) + (size_t(ry0) * W + cx0) * dc * es,
-                                size_t(W) * dc * es, size_t(ncols) * dc * es, size_t(nrows),
-                                hipMemcpyDeviceToDevice, s));
-        // GridShift on the window's colours (Algorithm 2, initialisation)
-        gs_info info{};
-        const int64_t off[2] = {0, n0};
-        GS_TRY(fit_impl(c, c->trk_win.p, dtype, dc, dc, 1, off, &h, max_iter, P<int32_t>(c->trk_lab), &info, s));
-        K = info.n_clusters;
+    std::vector<gs::TrackRect> rects(static_cast<size_t>(ntracks));
+    std::vector<int64_t> woff(size_t(ntracks) + 1, 0);
+    for (int t = 0; t < ntracks; ++t) {
+        int cx0, cx1, ry0, ry1;
+        span(W, o0[2 * t], l0[t], &cx0, &cx1);
+        span(H, o0[2 * t + 1], w0[t], &ry0, &ry1);
+        const int ncols = cx1 >= cx0 ? cx1 - cx0 + 1 : 0, nrows = ry1 >= ry0 ? ry1 - ry0 + 1 : 0;
+        rects[t] = {std::max(cx0, 0), std::max(ry0, 0), ncols, nrows, woff[t]};
+        woff[t + 1] = woff[t] + int64_t(ncols) * nrows;
     }
-    // the n_select largest clusters (count descending, then cluster id)
-    std::vector<int32_t> sel(size_t(std::max<int64_t>(K, 1)), 0);
-    if (K > 0) {
-        GS_TRY(ensure(c->trk_cnt, size_t(K) * 8));
+    const int64_t ntot = woff[ntracks];
+    if (ntot >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "the initial windows hold 2^31 pixels or more");
+    std::vector<gs_info> infos(static_cast<size_t>(ntracks));
+    std::vector<int64_t> koff(size_t(ntracks) + 1, 0);
+    if (ntot > 0) {
+        GS_TRY(ensure(c->trk_win, size_t(ntot) * dc * es));
+        GS_TRY(ensure(c->trk_lab, size_t(ntot) * 4));
+        GS_TRY(ensure(c->trk_rect, sizeof(gs::TrackRect) * ntracks));
+        GS_TRY(h2d(c, c->trk_rect.p, rects.data(), sizeof(gs::TrackRect) * ntracks, s));
+        if (dtype == GS_F32)
+            gs::k_track_windows<float><<<ntracks, 256, 0, s>>>(static_cast<const float*>(frames), W, dc,
+                                                              P<gs::TrackRect>(c->trk_rect), P<float>(c->trk_win));
+        else
+            gs::k_track_windows<double><<<ntracks, 256, 0, s>>>(static_cast<const double*>(frames), W, dc,
+                                                               P<gs::TrackRect>(c->trk_rect), P<double>(c->trk_win));
+        GS_HIP(hipGetLastError());
+        // GridShift on every window's colours (Algorithm 2, initialisation), one batched pass
+        std::vector<double> hs(static_cast<size_t>(ntracks), h);
+        GS_TRY(fit_impl(c, c->trk_win.p, dtype, dc, dc, ntracks, woff.data(), hs.data(), max_iter,
+                        P<int32_t>(c->trk_lab), infos.data(), s));
+    }
+    for (int t = 0; t < ntracks; ++t) koff[t + 1] = koff[t] + infos[t].n_clusters;
+    const int64_t ktot = koff[ntracks];
+    // per track, the n_select largest clusters (count descending, then cluster id)
+    std::vector<int32_t> sel(size_t(std::max<int64_t>(ktot, 1)), 0);
+    if (ktot > 0) {
+        GS_TRY(ensure(c->trk_cnt, size_t(ktot) * 8));
         GS_TRY(gs_copy_modes(c, nullptr, P<int64_t>(c->trk_cnt), nullptr, s));
-        std::vector<int64_t> cnt(static_cast<size_t>(K));
-        GS_TRY(d2h(c, cnt.data(), c->trk_cnt.p, size_t(K) * 8, s));
-        std::vector<int32_t> order(static_cast<size_t>(K));
-        for (int32_t i = 0; i < K; ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; });
-        for (int32_t i = 0; i < std::min<int64_t>(n_select, K); ++i) sel[order[i]] = 1;
+        std::vector<int64_t> cnt(static_cast<size_t>(ktot));
+        GS_TRY(d2h(c, cnt.data(), c->trk_cnt.p, size_t(ktot) * 8, s));
+        for (int t = 0; t < ntracks; ++t) {
+            const int64_t k0 = koff[t], K = koff[t + 1] - k0;
+            std::vector<int32_t> order(static_cast<size_t>(K));
+            for (int32_t i = 0; i < K; ++i) order[i] = i;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int32_t a, int32_t b) { return cnt[k0 + a] > cnt[k0 + b]; });
+            for (int32_t i = 0; i < std::min<int64_t>(n_select, K); ++i) sel[k0 + order[i]] = 1;
+        }
     }
+    std::vector<gs::TrackInit> init(static_cast<size_t>(ntracks));
+    for (int t = 0; t < ntracks; ++t) init[t] = {o0[2 * t], o0[2 * t + 1], l0[t], w0[t], woff[t], woff[t + 1], koff[t]};
     GS_TRY(ensure(c->trk_sel, sel.size() * 4));
     GS_TRY(h2d(c, c->trk_sel.p, sel.data(), sel.size() * 4, s));
-    GS_TRY(ensure(c->trk_out, size_t(T) * 4 * 8 + 256));
-    int32_t* derr = reinterpret_cast<int32_t*>(static_cast<char*>(c->trk_out.p) + size_t(T) * 4 * 8);
+    GS_TRY(ensure(c->trk_init, sizeof(gs::TrackInit) * ntracks));
+    GS_TRY(h2d(c, c->trk_init.p, init.data(), sizeof(gs::TrackInit) * ntracks, s));
+    const size_t wbytes = size_t(ntracks) * T * 4 * 8;
+    GS_TRY(ensure(c->trk_out, wbytes + size_t(ntracks) * 4 + 256));
+    int32_t* derr = reinterpret_cast<int32_t*>(static_cast<char*>(c->trk_out.p) + wbytes);
     const int tk = prof_begin(c, s, "track");
     if (dtype == GS_F32)
-        gs::k_track<float><<<1, gs::kTrackThreads, 0, s>>>(
-            static_cast<const float*>(frames), T, H, W, dc, P<float>(c->trk_win), P<int32_t>(c->trk_lab), n0,
-            P<int32_t>(c->trk_sel), o0[0], o0[1], l0, w0, f, h, eta, max_inner, P<double>(c->trk_out), derr);
+        gs::k_track<float><<<ntracks, gs::kTrackThreads, 0, s>>>(
+            static_cast<const float*>(frames), T, H, W, dc, P<float>(c->trk_win), P<int32_t>(c->trk_lab),
+            P<gs::TrackInit>(c->trk_init), P<int32_t>(c->trk_sel), f, h, eta, max_inner, P<double>(c->trk_out), derr);
     else
-        gs::k_track<double><<<1, gs::kTrackThreads, 0, s>>>(
-            static_cast<const double*>(frames), T, H, W, dc, P<double>(c->trk_win), P<int32_t>(c->trk_lab), n0,
-            P<int32_t>(c->trk_sel), o0[0], o0[1], l0, w0, f, h, eta, max_inner, P<double>(c->trk_out), derr);
-    prof_end(c, s, tk, double(T) * 4 * 8);
+        gs::k_track<double><<<ntracks, gs::kTrackThreads, 0, s>>>(
+            static_cast<const double*>(frames), T, H, W, dc, P<double>(c->trk_win), P<int32_t>(c->trk_lab),
+            P<gs::TrackInit>(c->trk_init), P<int32_t>(c->trk_sel), f, h, eta, max_inner, P<double>(c->trk_out), derr);
+    prof_end(c, s, tk, double(wbytes));
     GS_HIP(hipGetLastError());
-    std::vector<char> back(size_t(T) * 4 * 8 + 4);
+    std::vector<char> back(wbytes + size_t(ntracks) * 4);
     GS_TRY(d2h(c, back.data(), c->trk_out.p, back.size(), s));
-    int32_t e = 0;
-    std::memcpy(&e, back.data() + size_t(T) * 4 * 8, 4);
-    if (e & 1) return fail(GS_ERR_KEY_RANGE, "a selected colour cell index is outside [-32768, 32767)");
-    if (e & 2) return fail(GS_ERR_UNSUPPORTED, "the selected clusters span more than 2048 colour cells");
-    std::memcpy(windows, back.data(), size_t(T) * 4 * 8);
+    for (int t = 0; t < ntracks; ++t) {
+        int32_t e = 0;
+        std::memcpy(&e, back.data() + wbytes + size_t(t) * 4, 4);
+        if (e & 1) return fail(GS_ERR_KEY_RANGE, "a selected colour cell index is outside [-32768, 32767)");
+        if (e & 2) return fail(GS_ERR_UNSUPPORTED, "the selected clusters span more than 2048 colour cells");
+    }
+    std::memcpy(windows, back.data(), wbytes);
     return GS_OK;
+}
+
+gs_status gs_track(gs_context* ctx, const void* frames, gs_dtype dtype, int32_t T, int32_t H, int32_t W, int32_t dc,
+                   const double* o0, double l0, double w0, double f, double h, double eta, int32_t max_inner,
+                   int32_t n_select, int32_t max_iter, double* windows, void* stream) {
+    return gs_track_batched(ctx, frames, dtype, T, H, W, dc, 1, o0, &l0, &w0, f, h, eta, max_inner, n_select,
+                            max_iter, windows, stream);
 }
 
 gs_status gs_context_set_config(gs_context* ctx, int32_t key, int32_t value) {

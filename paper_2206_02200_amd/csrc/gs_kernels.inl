@@ -2242,6 +2242,26 @@ __device__ __forceinline__ int track_find(const uint64_t* tab, uint64_t key) {
     return -1;
 }
 
+// Copies the initial window of every track (rows y0.., columns x0.. of frame
+// 0, ncols x nrows pixels, dc values each) densely into win at row p0 of the
+// track, in raster order; one workgroup per track.
+struct TrackRect {
+    int x0, y0, ncols, nrows;
+    int64_t p0;
+};
+template <typename T>
+__global__ void k_track_windows(const T* __restrict__ frame0, int W, int dc, const TrackRect* __restrict__ rects,
+                                T* __restrict__ win) {
+    const TrackRect r = rects[blockIdx.x];
+    const int64_t npx = int64_t(r.ncols) * r.nrows;
+    for (int64_t e = threadIdx.x; e < npx * dc; e += blockDim.x) {
+        const int64_t pix = e / dc;
+        const int k = int(e - pix * dc);
+        const int yy = r.y0 + int(pix / r.ncols), xx = r.x0 + int(pix % r.ncols);
+        win[(r.p0 + pix) * dc + k] = frame0[(int64_t(yy) * W + xx) * dc + k];
+    }
+}
+
 // One workgroup tracks one object through frames 1..T-1 (frame t, pixel
 // (px, py): colour at ((t * H + py) * W + px) * dc).  B starts as the colour
 // cells of the window pixels (win, n0 rows of dc values, raster order) whose
@@ -2254,14 +2274,32 @@ __device__ __forceinline__ int track_find(const uint64_t* tab, uint64_t key) {
 // the loop ends once the centre moved by less than eta.  windows[t] =
 // (o_x, o_y, l, w) after frame t.  err: 1 = a selected colour cell is out of
 // the packable range, 2 = B exceeds kTrackMaxCells.
+// Per track: the initial window (centre, extents), its pixels' rows in the
+// window buffer and their labels [p0, p1), and where its clusters' selection
+// flags start.
+struct TrackInit {
+    double ox, oy, l, w;
+    int64_t p0, p1, k0;
+};
+
 template <typename T>
 __global__ __launch_bounds__(kTrackThreads) void k_track(const T* __restrict__ frames, int nT, int H, int W, int dc,
-                                                         const T* __restrict__ win, const int32_t* __restrict__ labels,
-                                                         int64_t n0, const int32_t* __restrict__ sel, double ox0,
-                                                         double oy0, double l0, double w0, double f, double h,
-                                                         double eta, int max_inner, double* __restrict__ windows,
-                                                         int32_t* __restrict__ err) {
+                                                         const T* __restrict__ win_all,
+                                                         const int32_t* __restrict__ labels_all,
+                                                         const TrackInit* __restrict__ init,
+                                                         const int32_t* __restrict__ sel_all, double f, double h,
+                                                         double eta, int max_inner, double* __restrict__ windows_all,
+                                                         int32_t* __restrict__ err_all) {
     constexpr int NW = kTrackThreads / kWave;
+    // one workgroup per track
+    const TrackInit ti = init[blockIdx.x];
+    const T* __restrict__ win = win_all + ti.p0 * dc;
+    const int32_t* __restrict__ labels = labels_all + ti.p0;
+    const int32_t* __restrict__ sel = sel_all + ti.k0;
+    const int64_t n0 = ti.p1 - ti.p0;
+    const double ox0 = ti.ox, oy0 = ti.oy, l0 = ti.l, w0 = ti.w;
+    double* __restrict__ windows = windows_all + int64_t(blockIdx.x) * nT * 4;
+    int32_t* __restrict__ err = err_all + blockIdx.x;
     __shared__ uint64_t tab[kTrackSlots];
     __shared__ uint32_t hit[kTrackSlots];  // stamp of the last step whose R held the cell
     __shared__ uint8_t alive[kTrackSlots];

@@ -35,6 +35,7 @@ EXPORTED = [
     "gs_context_set_tape", "gs_backward", "gs_point_mode_loss", "gs_point_mode_loss_backward",
     "gs_context_set_config", "gs_context_get_config", "gs_autotune",
     "gs_context_set_update", "gs_context_get_update", "gs_fit_hsweep", "gs_track",
+    "gs_track_batched",
 ]
 CFG_MERGE_SMALL, CFG_TILE_CHUNKS, CFG_DENSE_TABLE = 0, 1, 2
 CONFIG_KEYS = {"merge_small": CFG_MERGE_SMALL, "tile_chunks": CFG_TILE_CHUNKS, "dense_table": CFG_DENSE_TABLE}
@@ -90,6 +91,9 @@ def load_library(path: str = LIB_PATH):
         lib.gs_fit_hsweep.restype = ctypes.c_int
         lib.gs_track.argtypes = [V, V, ctypes.c_int, I32, I32, I32, I32, V, D, D, D, D, D, I32, I32, I32, V, V]
         lib.gs_track.restype = ctypes.c_int
+        lib.gs_track_batched.argtypes = [V, V, ctypes.c_int, I32, I32, I32, I32, I32, V, V, V, D, D, D, I32, I32, I32,
+                                         V, V]
+        lib.gs_track_batched.restype = ctypes.c_int
         lib.gs_copy_modes.argtypes = [V, V, V, V, V]
         lib.gs_copy_modes.restype = ctypes.c_int
         lib.gs_copy_keys.argtypes = [V, V, V]
@@ -377,6 +381,37 @@ def track(frames: torch.Tensor, o0, l0: float, w0: float, f: float, h: float, et
                         o.ctypes.data_as(ctypes.c_void_p), float(l0), float(w0), float(f), float(h), float(eta),
                         int(max_inner), int(n_select), int(max_iter), out.ctypes.data_as(ctypes.c_void_p),
                         _stream_ptr(stream)))
+    return out
+
+
+def track_batched(frames: torch.Tensor, o0, l0, w0, f: float, h: float, eta: float, max_inner: int = 20,
+                  n_select: int = 1, max_iter: int = 100, *, ctx: Context | None = None, stream=None) -> np.ndarray:
+    """Several objects tracked through the same ``frames`` at once (one
+    workgroup per track): ``o0`` [ntracks, 2], ``l0`` and ``w0`` [ntracks];
+    returns the windows as a float64 [ntracks, T, 4] array, bitwise those of
+    ``track`` run per object."""
+    lib = load_library()
+    if frames.dim() != 4 or not frames.is_cuda:
+        raise ValueError("frames must be a [T, H, W, dc] GPU tensor")
+    if frames.dtype == torch.float32:
+        dt = GS_F32
+    elif frames.dtype == torch.float64:
+        dt = GS_F64
+    else:
+        raise TypeError("frames must be float32 or float64")
+    frames = frames.contiguous()
+    T, H, W, dc = frames.shape
+    o = np.ascontiguousarray(np.asarray(o0, dtype=np.float64).reshape(-1, 2))
+    nt = o.shape[0]
+    lv = np.ascontiguousarray(np.broadcast_to(np.asarray(l0, dtype=np.float64), (nt,)))
+    wv = np.ascontiguousarray(np.broadcast_to(np.asarray(w0, dtype=np.float64), (nt,)))
+    ctx = ctx or default_context(frames.device.index)
+    out = np.empty((nt, T, 4), np.float64)
+    _check(lib.gs_track_batched(ctx.handle, ctypes.c_void_p(frames.data_ptr()), dt, T, H, W, dc, nt,
+                                o.ctypes.data_as(ctypes.c_void_p), lv.ctypes.data_as(ctypes.c_void_p),
+                                wv.ctypes.data_as(ctypes.c_void_p), float(f), float(h), float(eta), int(max_inner),
+                                int(n_select), int(max_iter), out.ctypes.data_as(ctypes.c_void_p),
+                                _stream_ptr(stream)))
     return out
 
 

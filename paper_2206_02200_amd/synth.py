@@ -147,40 +147,49 @@ def hsweep_grid(count: int = 20) -> np.ndarray:
 
 
 def moving_blob_video(T: int = 120, H: int = 480, W: int = 640, radius: float = 28.0, seed: int = 7,
-                      sigma: float = 6.0, dtype=np.float32):
-    """A synthetic tracking sequence (stand-in for OTB100): a textured disc of
-    one colour family moving over a smooth two-colour background ramp.
+                      sigma: float = 6.0, dtype=np.float32, discs: int = 1):
+    """A synthetic tracking sequence (stand-in for OTB100): textured discs of
+    distinct colour families moving over a smooth two-colour background ramp.
 
-    The disc starts at a random point of the central half, moves with a random
-    velocity of 2-5 px per frame plus a slow sinusoidal wobble, and bounces off
-    the borders; its colour is (215, 60, 45) + N(0, sigma^2) per pixel, the
-    background a diagonal ramp between (20, 90, 160) and (60, 170, 90) plus the
-    same noise; clipped to [0, 255].  Returns (frames [T][H][W][3], centres
-    [T][2] as (x, y))."""
+    Each disc starts at a random point of the central half, moves with a
+    random velocity of 2-5 px per frame plus a slow sinusoidal wobble, and
+    bounces off the borders; the first disc's colour is (215, 60, 45), the
+    others' U[120,255] x U[0,80] x U[0,255] (red-dominant, away from the
+    background), each plus N(0, sigma^2) per pixel; the background is a
+    diagonal ramp between (20, 90, 160) and (60, 170, 90) plus the same noise;
+    clipped to [0, 255]; later discs are drawn over earlier ones.  Returns
+    (frames [T][H][W][3], centres [T][discs][2] as (x, y), squeezed to [T][2]
+    for one disc)."""
     rng = np.random.default_rng(seed)
-    cx, cy = rng.uniform(0.25 * W, 0.75 * W), rng.uniform(0.25 * H, 0.75 * H)
-    ang = rng.uniform(0, 2 * np.pi)
-    sp = rng.uniform(2.0, 5.0)
-    vx, vy = sp * np.cos(ang), sp * np.sin(ang)
+    state = []
+    for j in range(discs):
+        cx, cy = rng.uniform(0.25 * W, 0.75 * W), rng.uniform(0.25 * H, 0.75 * H)
+        ang = rng.uniform(0, 2 * np.pi)
+        sp = rng.uniform(2.0, 5.0)
+        col = np.array([215.0, 60.0, 45.0]) if j == 0 else np.array(
+            [rng.uniform(120, 255), rng.uniform(0, 80), rng.uniform(0, 255)])
+        state.append([cx, cy, sp * np.cos(ang), sp * np.sin(ang), col, rng.uniform(0, 6.28) if j else 0.0])
     yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
     t_ramp = (xx / W + yy / H) / 2.0
     bg = np.stack([20 + 40 * t_ramp, 90 + 80 * t_ramp, 160 - 70 * t_ramp], axis=-1)
     frames = np.empty((T, H, W, 3), dtype=dtype)
-    centres = np.empty((T, 2), dtype=np.float64)
+    centres = np.empty((T, discs, 2), dtype=np.float64)
     for t in range(T):
-        ox = cx + 6.0 * np.sin(0.15 * t)
-        oy = cy + 6.0 * np.cos(0.11 * t)
-        centres[t] = (ox, oy)
         img = bg + sigma * rng.standard_normal(size=(H, W, 3))
-        disc = (xx - ox) ** 2 + (yy - oy) ** 2 <= radius * radius
-        img[disc] = np.array([215.0, 60.0, 45.0]) + sigma * rng.standard_normal(size=(int(disc.sum()), 3))
+        for j, st in enumerate(state):
+            ph = 0.0 if j == 0 else st[5]
+            ox = st[0] + 6.0 * np.sin(0.15 * t + ph)
+            oy = st[1] + 6.0 * np.cos(0.11 * t + ph)
+            centres[t, j] = (ox, oy)
+            disc = (xx - ox) ** 2 + (yy - oy) ** 2 <= radius * radius
+            img[disc] = st[4] + sigma * rng.standard_normal(size=(int(disc.sum()), 3))
+            st[0], st[1] = st[0] + st[2], st[1] + st[3]
+            if not (radius < st[0] < W - radius):
+                st[2] = -st[2]
+            if not (radius < st[1] < H - radius):
+                st[3] = -st[3]
         frames[t] = np.clip(img, 0, 255).astype(dtype)
-        cx, cy = cx + vx, cy + vy
-        if not (radius < cx < W - radius):
-            vx = -vx
-        if not (radius < cy < H - radius):
-            vy = -vy
-    return frames, centres
+    return frames, (centres[:, 0] if discs == 1 else centres)
 
 
 def gmm_truth(n: int, d: int, seed: int, components: int = 50) -> np.ndarray:

@@ -84,3 +84,18 @@ def test_errors():
     big = torch.full((2, 8, 8, 3), 1e9, dtype=torch.float32, device=DEV)
     with pytest.raises(RuntimeError, match="GS_ERR_KEY_RANGE"):
         gridshift.track(big, (4.0, 4.0), 4.0, 4.0, 1.0, 1.0, 0.5)
+
+
+def test_batched_tracks_equal_single_tracks_and_oracle():
+    fr, c = synth.moving_blob_video(T=10, H=96, W=128, radius=9.0, seed=13, discs=3)
+    o0 = np.concatenate([c[0], [[-40.0, -40.0]]])  # the last window lies outside the frame: empty
+    l0 = np.array([16.0, 20.0, 14.0, 10.0])
+    w0 = np.array([16.0, 14.0, 20.0, 10.0])
+    print(f"batched track case: frames={fr.shape} tracks={len(o0)}", flush=True)
+    g = gridshift.track_batched(torch.from_numpy(fr).to(DEV), o0, l0, w0, 0.75, 16.0, 0.5, 15)
+    for t in range(len(o0)):
+        o = tr.track(fr, o0[t], l0[t], w0[t], 0.75, 16.0, 0.5, 15)
+        np.testing.assert_array_equal(g[t].view(np.uint64), o.view(np.uint64), err_msg=f"track {t}")
+        one = gridshift.track(torch.from_numpy(fr).to(DEV), o0[t], l0[t], w0[t], 0.75, 16.0, 0.5, 15)
+        np.testing.assert_array_equal(g[t].view(np.uint64), one.view(np.uint64), err_msg=f"track {t} single")
+    assert np.abs(g[:3, :, :2] - np.transpose(c, (1, 0, 2))).max() < 4.0
