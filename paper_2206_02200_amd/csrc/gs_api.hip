@@ -63,6 +63,8 @@ struct gs_context {
     int device = 0;
     int rule = GS_UPDATE_PARALLEL;  // update rule of the shift (gs_context_set_update)
     int tail_tok = -1;              // profiling record of the last tail launch
+    DBuf seq_moved, seq_waiting;    // sequential form: step stamps per cell, waiting flags per step
+    uint32_t seq_epoch = 0;
     // point level
     DBuf kA, kB, vA, vB, cell0;
     // cell tables (ping-pong) and per-round scratch
@@ -545,16 +547,31 @@ template <class Lookup>
 gs_status launch_shift(gs_context* c, int d, gs::CellTable t, int64_t m, const gs::InstParam* prm, gs::InstState* st,
                        Lookup lk, double* pbuf, uint64_t* kappa, int32_t* Wout, hipStream_t s) {
     const unsigned g = blocks_for(m, gs::kShiftWaves);  // one wave per cell
-    // the parallel form in one launch; the sequential form one launch per
-    // colour, ascending (each moves the cells of its colour)
+    // the parallel form in one launch; the sequential form in up to 2^d steps
+    // (a cell moves in the step after its lower-colour neighbours; steps after
+    // the last waiting cell return at once)
+    gs::SeqStep seq{nullptr, nullptr, 0, 0};
     const int ncol = c->rule == GS_UPDATE_SEQUENTIAL ? 1 << d : 1;
+    if (c->rule == GS_UPDATE_SEQUENTIAL) {
+        if (c->seq_moved.cap < size_t(c->capM) * 4 || c->seq_epoch >= (1u << 24) - 1) {
+            // new storage, or the epochs wrapped: start from cleared stamps
+            GS_TRY(ensure(c->seq_moved, size_t(c->capM) * 4));
+            GS_TRY(ensure(c->seq_waiting, 64 * 4));
+            k_fill_u32<<<blocks_for(c->seq_moved.cap / 4, 256), 256, 0, s>>>(P<uint32_t>(c->seq_moved),
+                                                                            c->seq_moved.cap / 4, 0u);
+            k_fill_u32<<<1, 64, 0, s>>>(P<uint32_t>(c->seq_waiting), 64, 0u);
+            GS_HIP(hipGetLastError());
+            c->seq_epoch = 0;
+        }
+        seq = {P<uint32_t>(c->seq_moved), P<uint32_t>(c->seq_waiting), ++c->seq_epoch, 0};
+    }
     for (int col = 0; col < ncol; ++col) {
-        const int colour = c->rule == GS_UPDATE_SEQUENTIAL ? col : -1;
+        seq.step = col;
         // reads every cell row once, writes p and the landing key
         const int tk = prof_begin(c, s, "shift");
         switch (d) {
 #define GS_SH(D)                                                                                                  \
-    case D: gs::k_shift<D, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout, colour); break;
+    case D: gs::k_shift<D, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout, seq); break;
             GS_SH(1) GS_SH(2) GS_SH(3) GS_SH(4) GS_SH(5) GS_SH(6)
 #undef GS_SH
             default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
@@ -1527,7 +1544,8 @@ void gs_context_destroy(gs_context* c) {
                    &c->tt_key, &c->tt_cnt, &c->tt_W, &c->tt_g, &c->tt_m, &c->sbA, &c->sbB, &c->qbuf, &c->gmodes,
                    &c->modes_i, &c->counts_i, &c->frows, &c->lossc, &c->ltab, &c->xkA, &c->xkB, &c->xvA, &c->xvB,
                    &c->ck_key, &c->ck_cnt, &c->ck_sum, &c->ck_m, &c->tune_labels, &c->dk, &c->rep,
-                   &c->trk_win, &c->trk_lab, &c->trk_cnt, &c->trk_sel, &c->trk_out, &c->trk_rect, &c->trk_init};
+                   &c->trk_win, &c->trk_lab, &c->trk_cnt, &c->trk_sel, &c->trk_out, &c->trk_rect, &c->trk_init,
+                   &c->seq_moved, &c->seq_waiting};
     for (DBuf* b : tb2)
         if (b->p) (void)hipFree(b->p);
     delete c;

@@ -764,18 +764,36 @@ constexpr int kSlabMax = 4096;       // most columns of a tail's column table
 
 __host__ __device__ constexpr int pow3(int d) { return d == 0 ? 1 : 3 * pow3(d - 1); }
 
+// One step of the sequential form's device-wide shift: moved[cell] =
+// (epoch << 8) | step of the step that moved it; waiting[step] = epoch when
+// some cell still waited after that step.  epoch is unique per round and
+// fit (24 bits), so neither array needs clearing.  moved == nullptr: the
+// parallel form.
+struct SeqStep {
+    uint32_t* moved;
+    uint32_t* waiting;
+    uint32_t epoch;
+    int step;
+};
+
 template <int D, class Lookup>
 __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int64_t m,
                                                                const InstParam* __restrict__ param,
                                                                InstState* __restrict__ st, Lookup lk,
                                                                double* __restrict__ pbuf,
                                                                uint64_t* __restrict__ kappa,
-                                                               int32_t* __restrict__ Wout, int colour) {
+                                                               int32_t* __restrict__ Wout, SeqStep seq) {
     constexpr int NOFF = pow3(D);
     __shared__ uint32_t list[kShiftWaves][NOFF];
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int64_t j = int64_t(blockIdx.x) * kShiftWaves + w;
     if (j >= m) return;  // wave-uniform
+    const bool sequential = seq.moved != nullptr;
+    if (sequential) {
+        // no cell was left waiting by the previous step: nothing to do
+        if (seq.step > 0 && seq.waiting[seq.step - 1] != seq.epoch) return;
+        if ((seq.moved[j] >> 8) == seq.epoch) return;  // moved in an earlier step
+    }
     const int b = t.inst[j];
     if (!st[b].active) return;
     const InstParam& P = param[b];
@@ -787,15 +805,15 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
     int64_t crd[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) crd[k] = int64_t((local / P.stride[k]) % uint64_t(P.E[k]));
-    // Sequential form (Eq. 5), run colour by colour: a launch moves only the
-    // cells of colour `colour` (bit D-1-k = parity of integer coordinate k);
-    // cells of one colour are never neighbours.  Neighbours of a lower colour
-    // were moved by earlier launches and contribute fl(C_k * p_k).
+    // Sequential form (Eq. 5) in the colour-by-colour order (bit D-1-k of a
+    // colour = parity of integer coordinate k; cells of one colour are never
+    // neighbours): a cell moves in the first step (launch) after all its
+    // neighbours of lower colours have moved, and reads their fl(C_k * p_k);
+    // its neighbours of higher colours wait for it, so it reads their sums.
     int own_col = 0;
-    if (colour >= 0) {
+    if (sequential) {
 #pragma unroll
         for (int k = 0; k < D; ++k) own_col = (own_col << 1) | int((crd[k] + P.lo[k]) & 1);
-        if (own_col != colour) return;  // wave-uniform
     }
     const uint64_t lt = lanemask_lt();
     // every probe of the cell first (independent loads, all in flight), then
@@ -822,8 +840,22 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
                 nk += uint64_t(int64_t(v)) * P.stride[k];
                 flip |= (v != 0 ? 1 : 0) << (D - 1 - k);
             }
-            upd[it] = colour >= 0 && (own_col ^ flip) < own_col;
+            upd[it] = sequential && (own_col ^ flip) < own_col;
             if (inside) idx[it] = lk.find(nk);
+        }
+    }
+    if (sequential) {  // wait unless every lower-colour neighbour moved in an earlier step
+        bool wait = false;
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            if (idx[it] >= 0 && upd[it]) {
+                const uint32_t mv = seq.moved[idx[it]];
+                wait = wait || (mv >> 8) != seq.epoch || int(mv & 255u) >= seq.step;
+            }
+        }
+        if (__ballot(wait)) {
+            if (lane == 0) seq.waiting[seq.step] = seq.epoch;
+            return;
         }
     }
     int nfound = 0;
@@ -880,6 +912,7 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
     const bool moved = __ballot(chg) != 0 || P.base + term != key;  // wave-uniform
     if (lane == 0) {
         kappa[j] = P.base + term;
+        if (sequential) seq.moved[j] = (seq.epoch << 8) | uint32_t(seq.step);
         if (Wout) Wout[j] = int32_t(W);
         // instance flags: some cell has a neighbour; the round changes the
         // table (used only if the instance applies it).  One coherent read of
