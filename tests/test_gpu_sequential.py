@@ -3,10 +3,11 @@ the FP64 oracle's "sequential" rule.
 
 Bar, as for the parallel rule: labels, counts, K, round count, flags and keys
 bit-exact, cell sums and modes bit-exact.  The cases cover the tail workgroup
-(few cells), the device-wide rounds (one shift launch per colour), rounds that
-stop or hit the cap after the sweep has run (the sums must be put back),
-coordinates of both signs (the colour is the parity of the integer
-coordinate, not of the offset inside the key box), and the batched form.
+(few cells), the device-wide rounds (shift launches in dependency steps), both
+merge paths and both neighbour lookups, rounds that stop or hit the cap after
+the sweep has run (the sums must be put back), coordinates of both signs (the
+colour is the parity of the integer coordinate, not of the offset inside the
+key box), and the batched form.
 """
 import sys
 
@@ -161,3 +162,18 @@ def test_recorded_fit_rejects_the_sequential_rule():
     x = torch.from_numpy(_blobs(5401, 1000, 2)).to(DEV)
     with pytest.raises(RuntimeError, match="GS_ERR_UNSUPPORTED"):
         gridshift.fit(x, 2.0, 100, ctx=ctx)
+
+
+@pytest.mark.parametrize("merge_small,dense_table", [(0, 1), (1, 0), (0, 0)])
+def test_sequential_every_launch_configuration(merge_small, dense_table):
+    # the hash lookups and the device-wide merge (radix sort) under the sequential rule
+    x_np = _blobs(5500, 150000, 3, k=30, scale=8.0, spread=20.0, shift=20.0)
+    ctx = gridshift.Context(0)
+    ctx.set_update("sequential")
+    ctx.set_config(merge_small=merge_small, dense_table=dense_table)
+    _say(f"sequential config merge_small={merge_small} dense_table={dense_table}")
+    g = gridshift.fit(torch.from_numpy(x_np).to(DEV), 1.0, 100, with_sums=True, ctx=ctx)
+    o = gs_oracle.fit(x_np, 1.0, 100, rule="sequential")
+    assert g.info["n_iter"] == o.n_iter and g.info["flags"] == o.flags
+    np.testing.assert_array_equal(g.labels.cpu().numpy(), o.labels)
+    np.testing.assert_array_equal(_bits(g.sums.cpu().numpy()), _bits(o.sums))
