@@ -33,9 +33,11 @@
  *     All device work of a call is ordered on it.  gs_fit / gs_fit_batched
  *     synchronise the stream before returning, because cluster counts and
  *     flags are returned in host memory.
- *   - The caller owns every array it passes.  The context owns its scratch
- *     device memory, which grows on demand (hipMalloc) and is reused by later
- *     calls; results of a fit stay in the context until its next fit.
+ *   - The caller owns every array it passes.  A result (gs_fit) or a context
+ *     (gs_ctx_fit) owns its scratch device memory, taken from the caller's
+ *     gs_allocator when one is given and from hipMalloc otherwise; a
+ *     context's grows on demand and is reused by later calls, and its last
+ *     fit's results stay in it until its next fit.
  *   - Errors are returned as gs_status codes; gs_last_error() gives text.  The
  *     library never aborts the process.  On error the context holds no result.
  *   - A context is used by one host thread at a time; different contexts may
@@ -83,6 +85,91 @@ typedef struct {
     uint32_t flags;     /* GS_CONVERGED | GS_STATIONARY | GS_CAPPED */
 } gs_info;
 
+/*
+ * Device memory supplied by the caller (for instance a framework's caching
+ * allocator): alloc returns `bytes` of device memory usable on `stream` (NULL
+ * on failure), free gives back a pointer alloc returned, ordered on the
+ * stream it was allocated for.  ctx is passed back unchanged.
+ */
+typedef struct {
+    void* (*alloc)(void* ctx, size_t bytes, void* stream);
+    void (*free)(void* ctx, void* p, void* stream);
+    void* ctx;
+} gs_allocator;
+
+/* One point set for gs_fit.  ckpt_every: 0 records nothing, 1 records the
+ * whole trajectory for gs_backward and the loss gradient, k > 1 records it
+ * with tail checkpoints every k rounds (see gs_context_set_tape). */
+typedef struct {
+    const void* points; /* device, n rows of ld elements of dtype (ld >= d) */
+    gs_dtype dtype;
+    int64_t n;
+    int32_t d;
+    int64_t ld;
+    double h;
+    int32_t max_iter;
+    int32_t ckpt_every;
+} gs_problem;
+
+/* The result of one fit: its cluster tables, summaries and (when recorded)
+ * trajectory, held in device memory from the fit's allocator until
+ * gs_result_free. */
+typedef struct gs_result gs_result;
+
+/*
+ * Plain fit of one point set (Section 2.1, Algorithm 1; the update of Eq. 6),
+ * with every piece of scratch and the trajectory taken from `a` (NULL:
+ * hipMalloc).  labels device int32 [n] receives the cluster of every point
+ * (0..K-1, ascending final key); *out the result, owned by the caller and
+ * released with gs_result_free.  The stream is synchronised once before the
+ * call returns (K and the flags are host-visible).  On error *out is NULL.
+ */
+gs_status gs_fit(const gs_problem* p, const gs_allocator* a, void* stream, int32_t* labels, gs_result** out);
+
+/*
+ * Batched fit of B concatenated instances (rows offsets[b]..offsets[b+1]-1
+ * of points [offsets[B]][d], bandwidth h[b]; offsets, h host), bitwise B
+ * plain fits; labels device int32 [offsets[B]] (ids local per instance).
+ */
+gs_status gs_fit_batched(const void* points, gs_dtype dtype, int32_t d, int32_t B, const int64_t* offsets,
+                         const double* h, int32_t max_iter, int32_t ckpt_every, const gs_allocator* a, void* stream,
+                         int32_t* labels, gs_result** out);
+
+/* Summary of instance `instance` (0 for a plain fit) into host *out. */
+gs_status gs_result_info(const gs_result* r, int32_t instance, gs_info* out);
+
+/* Host int64 [B+1]: instance b's clusters are rows k_offsets[b] .. k_offsets[b+1]-1. */
+gs_status gs_result_offsets(const gs_result* r, int64_t* k_offsets);
+
+/* Modes fl(S/C) device double [sum K][d] and counts device int64 [sum K]
+ * (either may be NULL), instances concatenated. */
+gs_status gs_result_copy(const gs_result* r, double* modes, int64_t* counts, void* stream);
+
+/* Adjoint of the modes (a recorded fit, ckpt_every >= 1; else GS_ERR_STATE):
+ * grad_modes device double [sum K][d], grad_points device double [N][d]
+ * (overwritten); the reverse pass is described at gs_context_set_tape. */
+gs_status gs_backward(const gs_result* r, const double* grad_modes, double* grad_points, void* stream);
+
+/* Point-to-mode loss per instance (see gs_ctx_point_mode_loss) of a recorded
+ * fit, with the labels the fit wrote (they must still hold them); loss
+ * device double [B]. */
+gs_status gs_point_mode_loss(const gs_result* r, const void* points, double* loss, void* stream);
+
+/* Gradient of sum_b grad_loss[b] * L_b (see gs_ctx_point_mode_loss_backward). */
+gs_status gs_point_mode_loss_backward(const gs_result* r, const void* points, const double* grad_loss,
+                                      double* grad_points, void* stream);
+
+/* Release a result: waits for its stream, then returns its memory to its
+ * allocator.  NULL is a no-op. */
+void gs_result_free(gs_result* r);
+
+/*
+ * Contexts.  A gs_context holds the scratch of repeated fits and the last
+ * fit's result; the gs_ctx_* calls below do what the calls above do, on a
+ * context that the caller keeps (no allocation after the first fit of a
+ * given size), plus the bandwidth sweep, tracking, launch configuration,
+ * autotuning and timing.
+ */
 typedef struct gs_context gs_context;
 
 /* ABI version (GS_ABI_VERSION). */
@@ -108,14 +195,14 @@ void gs_context_destroy(gs_context* ctx);
  *   info    host, receives the result summary.
  * The cluster table stays in the context (gs_copy_modes, gs_copy_keys).
  */
-gs_status gs_fit(gs_context* ctx, const void* points, gs_dtype dtype, int64_t n, int32_t d, int64_t ld,
-                 double h, int32_t max_iter, int32_t* labels, gs_info* info, void* stream);
+gs_status gs_ctx_fit(gs_context* ctx, const void* points, gs_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                     double h, int32_t max_iter, int32_t* labels, gs_info* info, void* stream);
 
 /*
  * Batched fit: B independent instances, concatenated, each with its own h,
  * in one pass of the pipeline (keys carry the instance as top digit; the
  * per-round tail runs one workgroup per instance in a single launch).
- * Results are bitwise those of B separate gs_fit calls.
+ * Results are bitwise those of B separate gs_ctx_fit calls.
  *   points  device [offsets[B]][ld] of dtype; instance b owns rows
  *           offsets[b] .. offsets[b+1]-1.
  *   offsets host int64 [B+1], offsets[0] = 0, non-decreasing.
@@ -123,9 +210,9 @@ gs_status gs_fit(gs_context* ctx, const void* points, gs_dtype dtype, int64_t n,
  *   labels  device int32 [offsets[B]]: per-instance cluster ids.
  *   info    host gs_info [B].
  */
-gs_status gs_fit_batched(gs_context* ctx, const void* points, gs_dtype dtype, int32_t d, int64_t ld, int32_t B,
-                         const int64_t* offsets, const double* h, int32_t max_iter, int32_t* labels,
-                         gs_info* info, void* stream);
+gs_status gs_ctx_fit_batched(gs_context* ctx, const void* points, gs_dtype dtype, int32_t d, int64_t ld, int32_t B,
+                             const int64_t* offsets, const double* h, int32_t max_iter, int32_t* labels,
+                             gs_info* info, void* stream);
 
 /*
  * Bandwidth sweep: the same point set fitted once per bandwidth hs[0..H-1]
@@ -253,7 +340,7 @@ gs_status gs_context_set_tape(gs_context* ctx, int32_t ckpt_every);
 /* grad_modes device double [sum K][d] (the concatenated cluster rows of
  * gs_copy_modes); grad_points device double [N][d], overwritten.  Returns
  * GS_ERR_STATE if the last fit was not recorded. */
-gs_status gs_backward(gs_context* ctx, const double* grad_modes, double* grad_points, void* stream);
+gs_status gs_ctx_backward(gs_context* ctx, const double* grad_modes, double* grad_points, void* stream);
 
 /*
  * Point-to-mode loss of every instance, L_b = sum over its points of
@@ -261,7 +348,8 @@ gs_status gs_backward(gs_context* ctx, const double* grad_modes, double* grad_po
  * the left fold over the coordinates.  points and labels are the arrays of
  * the recorded fit (same layout); loss device double [B].
  */
-gs_status gs_point_mode_loss(gs_context* ctx, const void* points, const int32_t* labels, double* loss, void* stream);
+gs_status gs_ctx_point_mode_loss(gs_context* ctx, const void* points, const int32_t* labels, double* loss,
+                                 void* stream);
 
 /*
  * Gradient of sum_b grad_loss[b] * L_b with respect to the points, the
@@ -270,8 +358,8 @@ gs_status gs_point_mode_loss(gs_context* ctx, const void* points, const int32_t*
  * cluster c (R over its initial cells' sums in ascending cell order).
  * grad_loss device double [B]; grad_points device double [N][d], overwritten.
  */
-gs_status gs_point_mode_loss_backward(gs_context* ctx, const void* points, const int32_t* labels,
-                                      const double* grad_loss, double* grad_points, void* stream);
+gs_status gs_ctx_point_mode_loss_backward(gs_context* ctx, const void* points, const int32_t* labels,
+                                          const double* grad_loss, double* grad_points, void* stream);
 
 /*
  * Launch configuration of a context.  Every choice runs the same binary64

@@ -29,7 +29,44 @@ gs_status fail(gs_status st, const std::string& msg) {
 struct DBuf {
     void* p = nullptr;
     size_t cap = 0;
+    const gs_allocator* al = nullptr;  // the caller's allocator that gave p (null: hipMalloc)
+    void* st = nullptr;                // and the stream it was given for
 };
+
+// Device memory of a call on a context with a caller allocator comes from
+// that allocator: the entry point opens an AllocScope, and every buffer grown
+// during the call records where its memory came from.
+thread_local const gs_allocator* t_alloc = nullptr;
+thread_local void* t_alloc_stream = nullptr;
+
+void dbuf_release(DBuf& b) {
+    if (b.p) {
+        if (b.al)
+            b.al->free(b.al->ctx, b.p, b.st);
+        else
+            (void)hipFree(b.p);
+    }
+    b.p = nullptr;
+    b.cap = 0;
+    b.al = nullptr;
+    b.st = nullptr;
+}
+
+gs_status dbuf_get(DBuf& b, size_t want) {
+    void* p = nullptr;
+    if (t_alloc) {
+        p = t_alloc->alloc(t_alloc->ctx, want, t_alloc_stream);
+        if (!p) return fail(GS_ERR_ALLOC, "the caller's allocator returned NULL for " + std::to_string(want) + " bytes");
+    } else if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GS_ERR_ALLOC, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    b.p = p;
+    b.cap = want;
+    b.al = t_alloc;
+    b.st = t_alloc_stream;
+    return GS_OK;
+}
 
 // Optional per-kernel timing with HIP events on the launch stream.  Only
 // kernels whose name starts with `filter` are timed.
@@ -62,6 +99,8 @@ struct gs_config {
 struct gs_context {
     int device = 0;
     int rule = GS_UPDATE_PARALLEL;  // update rule of the shift (gs_context_set_update)
+    gs_allocator alloc{};           // the caller's device allocator (has_alloc), else hipMalloc
+    bool has_alloc = false;
     int tail_tok = -1;              // profiling record of the last tail launch
     DBuf seq_moved, seq_waiting;    // sequential form: step stamps per cell, waiting flags per step
     uint32_t seq_epoch = 0;
@@ -134,41 +173,44 @@ struct gs_context {
     int64_t N = 0, ld = 0, m0 = 0;
 };
 
+// The caller allocator of a context, for the duration of one entry point.
+struct AllocScope {
+    const gs_allocator* pa;
+    void* ps;
+    AllocScope(const gs_context* c, void* stream) : pa(t_alloc), ps(t_alloc_stream) {
+        t_alloc = c && c->has_alloc ? &c->alloc : nullptr;
+        t_alloc_stream = c && c->has_alloc ? stream : nullptr;
+    }
+    ~AllocScope() {
+        t_alloc = pa;
+        t_alloc_stream = ps;
+    }
+};
+
 namespace {
 
 gs_status ensure(DBuf& b, size_t bytes) {
     if (bytes == 0) bytes = 8;
     if (b.cap >= bytes) return GS_OK;
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.cap = 0;
-    const size_t want = bytes + bytes / 8;
-    if (hipMalloc(&b.p, want) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(GS_ERR_ALLOC, "hipMalloc of " + std::to_string(want) + " bytes failed");
-    }
-    b.cap = want;
-    return GS_OK;
+    dbuf_release(b);
+    return dbuf_get(b, bytes + bytes / 8);
 }
 
 // Grow a buffer keeping its first `used` bytes (stream-ordered copy).
 gs_status ensure_keep(DBuf& b, size_t bytes, size_t used, hipStream_t s) {
     if (b.cap >= bytes) return GS_OK;
     const size_t want = bytes + bytes / 2;
-    void* np = nullptr;
-    if (hipMalloc(&np, want) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(GS_ERR_ALLOC, "hipMalloc of " + std::to_string(want) + " bytes failed");
-    }
+    DBuf nb;
+    if (const gs_status e = dbuf_get(nb, want); e != GS_OK) return e;
     if (b.p && used) {
-        if (hipMemcpyAsync(np, b.p, used, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        if (hipMemcpyAsync(nb.p, b.p, used, hipMemcpyDeviceToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
-            (void)hipFree(np);
+            dbuf_release(nb);
             return fail(GS_ERR_DEVICE, "tape copy failed");
         }
     }
-    if (b.p) (void)hipFree(b.p);
-    b.p = np;
+    dbuf_release(b);
+    b = nb;
     b.cap = want;
     return GS_OK;
 }
@@ -1520,13 +1562,11 @@ void gs_context_destroy(gs_context* c) {
                    &c->part, &c->partc, &c->hk, &c->hv, &c->ckA, &c->ckB, &c->cvA, &c->cvB, &c->ctl,
                    &c->look, &c->tilectr, &c->shist,
                    &c->sctr, &c->slook};
-    for (DBuf* b : all)
-        if (b->p) (void)hipFree(b->p);
+    for (DBuf* b : all) dbuf_release(*b);
     for (int i = 0; i < 2; ++i) {
         DBuf* tb[] = {&c->tkey[i], &c->tcnt[i], &c->tsum[i], &c->tinst[i], &c->tstart[i],
                       &c->tlen[i], &c->tfirst[i], &c->tnch[i], &c->tchoff[i]};
-        for (DBuf* b : tb)
-            if (b->p) (void)hipFree(b->p);
+        for (DBuf* b : tb) dbuf_release(*b);
     }
     if (c->up_used > 0) (void)hipStreamSynchronize(c->up_stream);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -1546,28 +1586,30 @@ void gs_context_destroy(gs_context* c) {
                    &c->ck_key, &c->ck_cnt, &c->ck_sum, &c->ck_m, &c->tune_labels, &c->dk, &c->rep,
                    &c->trk_win, &c->trk_lab, &c->trk_cnt, &c->trk_sel, &c->trk_out, &c->trk_rect, &c->trk_init,
                    &c->seq_moved, &c->seq_waiting};
-    for (DBuf* b : tb2)
-        if (b->p) (void)hipFree(b->p);
+    for (DBuf* b : tb2) dbuf_release(*b);
     delete c;
 }
 
-gs_status gs_fit(gs_context* ctx, const void* points, gs_dtype dtype, int64_t n, int32_t d, int64_t ld, double h,
+gs_status gs_ctx_fit(gs_context* ctx, const void* points, gs_dtype dtype, int64_t n, int32_t d, int64_t ld, double h,
                  int32_t max_iter, int32_t* labels, gs_info* info, void* stream) {
+    AllocScope as_(ctx, stream);
     if (n < 0) return fail(GS_ERR_INVALID_ARG, "n must be >= 0");
     const int64_t offsets[2] = {0, n};
     return fit_impl(ctx, points, dtype, d, ld, 1, offsets, &h, max_iter, labels, info,
                     static_cast<hipStream_t>(stream));
 }
 
-gs_status gs_fit_batched(gs_context* ctx, const void* points, gs_dtype dtype, int32_t d, int64_t ld, int32_t B,
+gs_status gs_ctx_fit_batched(gs_context* ctx, const void* points, gs_dtype dtype, int32_t d, int64_t ld, int32_t B,
                          const int64_t* offsets, const double* h, int32_t max_iter, int32_t* labels, gs_info* info,
                          void* stream) {
+    AllocScope as_(ctx, stream);
     return fit_impl(ctx, points, dtype, d, ld, B, offsets, h, max_iter, labels, info,
                     static_cast<hipStream_t>(stream));
 }
 
 gs_status gs_fit_hsweep(gs_context* ctx, const void* points, gs_dtype dtype, int64_t n, int32_t d, int64_t ld,
                         int32_t H, const double* hs, int32_t max_iter, int32_t* labels, gs_info* info, void* stream) {
+    AllocScope as_(ctx, stream);
     if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
     if (n < 0 || H < 1 || !hs || !info) return fail(GS_ERR_INVALID_ARG, "n >= 0, H >= 1, hs and info are required");
     if (d < 1 || d > gs::kMaxDim) return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
@@ -1605,6 +1647,7 @@ gs_status gs_track_batched(gs_context* ctx, const void* frames, gs_dtype dtype, 
                            int32_t dc, int32_t ntracks, const double* o0, const double* l0, const double* w0, double f,
                            double h, double eta, int32_t max_inner, int32_t n_select, int32_t max_iter,
                            double* windows, void* stream) {
+    AllocScope as_(ctx, stream);
     if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
     if (T < 1 || H < 1 || W < 1 || int64_t(H) * W >= (int64_t(1) << 31) || !frames || !o0 || !l0 || !w0 ||
         !windows || ntracks < 1)
@@ -1753,6 +1796,7 @@ gs_status gs_context_get_config(const gs_context* ctx, int32_t key, int32_t* val
 
 gs_status gs_autotune(gs_context* ctx, const void* points, gs_dtype dtype, int32_t d, int64_t ld, int32_t B,
                       const int64_t* offsets, const double* h, int32_t max_iter, int32_t reps, void* stream) {
+    AllocScope as_(ctx, stream);
     if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
     if (B < 1 || !offsets || !h || reps < 1) return fail(GS_ERR_INVALID_ARG, "B, offsets, h and reps are required");
     const hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1847,7 +1891,8 @@ gs_status gs_context_set_tape(gs_context* ctx, int32_t ckpt_every) {
     return GS_OK;
 }
 
-gs_status gs_backward(gs_context* ctx, const double* grad_modes, double* grad_points, void* stream) {
+gs_status gs_ctx_backward(gs_context* ctx, const double* grad_modes, double* grad_points, void* stream) {
+    AllocScope as_(ctx, stream);
     GS_TRY(check_tape(ctx));
     gs_context* c = ctx;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1864,7 +1909,8 @@ gs_status gs_backward(gs_context* ctx, const double* grad_modes, double* grad_po
     return GS_OK;
 }
 
-gs_status gs_point_mode_loss(gs_context* ctx, const void* points, const int32_t* labels, double* loss, void* stream) {
+gs_status gs_ctx_point_mode_loss(gs_context* ctx, const void* points, const int32_t* labels, double* loss, void* stream) {
+    AllocScope as_(ctx, stream);
     GS_TRY(check_tape(ctx));
     gs_context* c = ctx;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1875,8 +1921,9 @@ gs_status gs_point_mode_loss(gs_context* ctx, const void* points, const int32_t*
     return loss_fwd(c, static_cast<const double*>(points), labels, loss, s);
 }
 
-gs_status gs_point_mode_loss_backward(gs_context* ctx, const void* points, const int32_t* labels,
+gs_status gs_ctx_point_mode_loss_backward(gs_context* ctx, const void* points, const int32_t* labels,
                                       const double* grad_loss, double* grad_points, void* stream) {
+    AllocScope as_(ctx, stream);
     GS_TRY(check_tape(ctx));
     gs_context* c = ctx;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1901,6 +1948,7 @@ static gs_status prepare_copy(gs_context* c, hipStream_t s, int64_t* rows) {
 }
 
 gs_status gs_copy_modes(gs_context* ctx, double* modes, int64_t* counts, double* sums, void* stream) {
+    AllocScope as_(ctx, stream);
     hipStream_t s = static_cast<hipStream_t>(stream);
     int64_t rows = 0;
     GS_TRY(prepare_copy(ctx, s, &rows));
@@ -1913,6 +1961,7 @@ gs_status gs_copy_modes(gs_context* ctx, double* modes, int64_t* counts, double*
 }
 
 gs_status gs_copy_keys(gs_context* ctx, int64_t* keys, void* stream) {
+    AllocScope as_(ctx, stream);
     hipStream_t s = static_cast<hipStream_t>(stream);
     int64_t rows = 0;
     GS_TRY(prepare_copy(ctx, s, &rows));
@@ -1923,6 +1972,122 @@ gs_status gs_copy_keys(gs_context* ctx, int64_t* keys, void* stream) {
                                                           P<int64_t>(ctx->koff), ctx->B, rows, ctx->d, keys);
     GS_HIP(hipGetLastError());
     return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-fit results (each owns a context whose device memory comes from the
+// caller's allocator when one is given)
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct gs_result {
+    gs_context* ctx = nullptr;
+    void* stream = nullptr;
+    const int32_t* labels = nullptr;  // the caller's labels of the fit (for the loss)
+    std::vector<gs_info> info;
+    std::vector<int64_t> koff;
+};
+
+namespace {
+
+gs_status result_fit(const void* points, gs_dtype dtype, int32_t d, int64_t ld, int32_t B, const int64_t* offsets,
+                     const double* h, int32_t max_iter, int32_t ckpt_every, const gs_allocator* a, void* stream,
+                     int32_t* labels, gs_result** out) {
+    if (!out) return fail(GS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (a && (!a->alloc || !a->free)) return fail(GS_ERR_INVALID_ARG, "the allocator needs alloc and free");
+    if (B < 1) return fail(GS_ERR_INVALID_ARG, "B must be >= 1");
+    gs_context* c = nullptr;
+    GS_TRY(gs_context_create(&c));
+    if (a) {
+        c->alloc = *a;
+        c->has_alloc = true;
+    }
+    gs_result* r = new (std::nothrow) gs_result();
+    if (!r) {
+        gs_context_destroy(c);
+        return fail(GS_ERR_ALLOC, "out of host memory");
+    }
+    r->ctx = c;
+    r->stream = stream;
+    r->labels = labels;
+    r->info.assign(size_t(B), gs_info{});
+    gs_status rc = gs_context_set_tape(c, ckpt_every);
+    if (rc == GS_OK)
+        rc = gs_ctx_fit_batched(c, points, dtype, d, ld, B, offsets, h, max_iter, labels, r->info.data(), stream);
+    if (rc != GS_OK) {
+        const std::string msg = gs_last_error();
+        gs_result_free(r);
+        g_last_error = msg;
+        return rc;
+    }
+    r->koff.assign(size_t(B) + 1, 0);
+    for (int32_t b = 0; b < B; ++b) r->koff[b + 1] = r->koff[b] + r->info[b].n_clusters;
+    *out = r;
+    return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gs_status gs_fit(const gs_problem* p, const gs_allocator* a, void* stream, int32_t* labels, gs_result** out) {
+    if (!p) return fail(GS_ERR_INVALID_ARG, "problem is NULL");
+    if (p->n < 0) return fail(GS_ERR_INVALID_ARG, "n must be >= 0");
+    const int64_t offsets[2] = {0, p->n};
+    return result_fit(p->points, p->dtype, p->d, p->ld, 1, offsets, &p->h, p->max_iter, p->ckpt_every, a, stream,
+                      labels, out);
+}
+
+gs_status gs_fit_batched(const void* points, gs_dtype dtype, int32_t d, int32_t B, const int64_t* offsets,
+                         const double* h, int32_t max_iter, int32_t ckpt_every, const gs_allocator* a, void* stream,
+                         int32_t* labels, gs_result** out) {
+    return result_fit(points, dtype, d, d, B, offsets, h, max_iter, ckpt_every, a, stream, labels, out);
+}
+
+gs_status gs_result_info(const gs_result* r, int32_t instance, gs_info* out) {
+    if (!r || !out) return fail(GS_ERR_INVALID_ARG, "null result or output");
+    if (instance < 0 || size_t(instance) >= r->info.size()) return fail(GS_ERR_INVALID_ARG, "no such instance");
+    *out = r->info[size_t(instance)];
+    return GS_OK;
+}
+
+gs_status gs_result_offsets(const gs_result* r, int64_t* k_offsets) {
+    if (!r || !k_offsets) return fail(GS_ERR_INVALID_ARG, "null result or output");
+    std::memcpy(k_offsets, r->koff.data(), r->koff.size() * sizeof(int64_t));
+    return GS_OK;
+}
+
+gs_status gs_result_copy(const gs_result* r, double* modes, int64_t* counts, void* stream) {
+    if (!r) return fail(GS_ERR_INVALID_ARG, "null result");
+    return gs_copy_modes(r->ctx, modes, counts, nullptr, stream);
+}
+
+gs_status gs_backward(const gs_result* r, const double* grad_modes, double* grad_points, void* stream) {
+    if (!r) return fail(GS_ERR_INVALID_ARG, "null result");
+    return gs_ctx_backward(r->ctx, grad_modes, grad_points, stream);
+}
+
+gs_status gs_point_mode_loss(const gs_result* r, const void* points, double* loss, void* stream) {
+    if (!r) return fail(GS_ERR_INVALID_ARG, "null result");
+    return gs_ctx_point_mode_loss(r->ctx, points, r->labels, loss, stream);
+}
+
+gs_status gs_point_mode_loss_backward(const gs_result* r, const void* points, const double* grad_loss,
+                                      double* grad_points, void* stream) {
+    if (!r) return fail(GS_ERR_INVALID_ARG, "null result");
+    return gs_ctx_point_mode_loss_backward(r->ctx, points, r->labels, grad_loss, grad_points, stream);
+}
+
+void gs_result_free(gs_result* r) {
+    if (!r) return;
+    if (r->ctx) {
+        // stream-ordered: the result's work on its stream ends before its memory goes back
+        (void)hipSetDevice(r->ctx->device);
+        (void)hipStreamSynchronize(static_cast<hipStream_t>(r->stream));
+        gs_context_destroy(r->ctx);
+    }
+    delete r;
 }
 
 }  // extern "C"

@@ -30,9 +30,11 @@ STATUS = {
 }
 EXPORTED = [
     "gs_abi_version", "gs_last_error", "gs_context_create", "gs_context_destroy",
-    "gs_fit", "gs_fit_batched", "gs_copy_modes", "gs_copy_keys",
+    "gs_ctx_fit", "gs_ctx_fit_batched", "gs_copy_modes", "gs_copy_keys",
+    "gs_fit", "gs_fit_batched", "gs_result_info", "gs_result_offsets", "gs_result_copy", "gs_backward",
+    "gs_point_mode_loss", "gs_point_mode_loss_backward", "gs_result_free",
     "gs_profile_enable", "gs_profile_reset", "gs_profile_count", "gs_profile_entry",
-    "gs_context_set_tape", "gs_backward", "gs_point_mode_loss", "gs_point_mode_loss_backward",
+    "gs_context_set_tape", "gs_ctx_backward", "gs_ctx_point_mode_loss", "gs_ctx_point_mode_loss_backward",
     "gs_context_set_config", "gs_context_get_config", "gs_autotune",
     "gs_context_set_update", "gs_context_get_update", "gs_fit_hsweep", "gs_track",
     "gs_track_batched",
@@ -46,6 +48,44 @@ class GridShiftError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
         self.code = code
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    """gs_allocator"""
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class Problem(ctypes.Structure):
+    """gs_problem"""
+    _fields_ = [("points", ctypes.c_void_p), ("dtype", ctypes.c_int), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("ld", ctypes.c_int64), ("h", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("ckpt_every", ctypes.c_int32)]
+
+
+# device memory of results from torch's caching allocator (counted, for tests)
+ALLOC_STATS = {"allocs": 0, "frees": 0, "bytes": 0}
+
+
+def _torch_alloc(ctx, nbytes, stream):
+    try:
+        p = torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:  # out of memory: the library reports GS_ERR_ALLOC
+        return None
+    ALLOC_STATS["allocs"] += 1
+    ALLOC_STATS["bytes"] += int(nbytes)
+    return p
+
+
+def _torch_free(ctx, p, stream):
+    torch.cuda.caching_allocator_delete(int(p))
+    ALLOC_STATS["frees"] += 1
+
+
+TORCH_ALLOCATOR = Allocator(_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free), None)
 
 
 class Info(ctypes.Structure):
@@ -83,10 +123,29 @@ def load_library(path: str = LIB_PATH):
         lib.gs_context_create.restype = ctypes.c_int
         lib.gs_context_destroy.argtypes = [V]
         lib.gs_context_destroy.restype = None
-        lib.gs_fit.argtypes = [V, V, ctypes.c_int, I64, I32, I64, D, I32, V, ctypes.POINTER(Info), V]
+        lib.gs_fit.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Allocator), V, V, ctypes.POINTER(V)]
         lib.gs_fit.restype = ctypes.c_int
-        lib.gs_fit_batched.argtypes = [V, V, ctypes.c_int, I32, I64, I32, V, V, I32, V, V, V]
+        lib.gs_fit_batched.argtypes = [V, ctypes.c_int, I32, I32, V, V, I32, I32, ctypes.POINTER(Allocator), V, V,
+                                       ctypes.POINTER(V)]
         lib.gs_fit_batched.restype = ctypes.c_int
+        lib.gs_result_info.argtypes = [V, I32, ctypes.POINTER(Info)]
+        lib.gs_result_info.restype = ctypes.c_int
+        lib.gs_result_offsets.argtypes = [V, V]
+        lib.gs_result_offsets.restype = ctypes.c_int
+        lib.gs_result_copy.argtypes = [V, V, V, V]
+        lib.gs_result_copy.restype = ctypes.c_int
+        lib.gs_backward.argtypes = [V, V, V, V]
+        lib.gs_backward.restype = ctypes.c_int
+        lib.gs_point_mode_loss.argtypes = [V, V, V, V]
+        lib.gs_point_mode_loss.restype = ctypes.c_int
+        lib.gs_point_mode_loss_backward.argtypes = [V, V, V, V, V]
+        lib.gs_point_mode_loss_backward.restype = ctypes.c_int
+        lib.gs_result_free.argtypes = [V]
+        lib.gs_result_free.restype = None
+        lib.gs_ctx_fit.argtypes = [V, V, ctypes.c_int, I64, I32, I64, D, I32, V, ctypes.POINTER(Info), V]
+        lib.gs_ctx_fit.restype = ctypes.c_int
+        lib.gs_ctx_fit_batched.argtypes = [V, V, ctypes.c_int, I32, I64, I32, V, V, I32, V, V, V]
+        lib.gs_ctx_fit_batched.restype = ctypes.c_int
         lib.gs_fit_hsweep.argtypes = [V, V, ctypes.c_int, I64, I32, I64, I32, V, I32, V, V, V]
         lib.gs_fit_hsweep.restype = ctypes.c_int
         lib.gs_track.argtypes = [V, V, ctypes.c_int, I32, I32, I32, I32, V, D, D, D, D, D, I32, I32, I32, V, V]
@@ -109,12 +168,12 @@ def load_library(path: str = LIB_PATH):
         lib.gs_profile_entry.restype = ctypes.c_int
         lib.gs_context_set_tape.argtypes = [V, I32]
         lib.gs_context_set_tape.restype = ctypes.c_int
-        lib.gs_backward.argtypes = [V, V, V, V]
-        lib.gs_backward.restype = ctypes.c_int
-        lib.gs_point_mode_loss.argtypes = [V, V, V, V, V]
-        lib.gs_point_mode_loss.restype = ctypes.c_int
-        lib.gs_point_mode_loss_backward.argtypes = [V, V, V, V, V, V]
-        lib.gs_point_mode_loss_backward.restype = ctypes.c_int
+        lib.gs_ctx_backward.argtypes = [V, V, V, V]
+        lib.gs_ctx_backward.restype = ctypes.c_int
+        lib.gs_ctx_point_mode_loss.argtypes = [V, V, V, V, V]
+        lib.gs_ctx_point_mode_loss.restype = ctypes.c_int
+        lib.gs_ctx_point_mode_loss_backward.argtypes = [V, V, V, V, V, V]
+        lib.gs_ctx_point_mode_loss_backward.restype = ctypes.c_int
         lib.gs_context_set_update.argtypes = [V, I32]
         lib.gs_context_set_update.restype = ctypes.c_int
         lib.gs_context_get_update.argtypes = [V, ctypes.POINTER(I32)]
@@ -275,7 +334,7 @@ def fit(x: torch.Tensor, h: float, max_iter: int = 100, *, with_sums: bool = Fal
     sp = _stream_ptr(stream)
     labels = torch.empty(n, dtype=torch.int32, device=x.device)
     info = Info()
-    _check(lib.gs_fit(ctx.handle, ctypes.c_void_p(x.data_ptr()), dt, n, d, ld, float(h), int(max_iter),
+    _check(lib.gs_ctx_fit(ctx.handle, ctypes.c_void_p(x.data_ptr()), dt, n, d, ld, float(h), int(max_iter),
                       ctypes.c_void_p(labels.data_ptr()), ctypes.byref(info), sp))
     K = info.n_clusters
     modes = torch.empty((K, d), dtype=torch.float64, device=x.device)
@@ -316,7 +375,7 @@ def fit_batched(x: torch.Tensor, offsets, h, max_iter: int = 100, *, with_sums: 
     sp = _stream_ptr(stream)
     labels = torch.empty(x.shape[0], dtype=torch.int32, device=x.device)
     infos = (Info * B)()
-    _check(lib.gs_fit_batched(ctx.handle, ctypes.c_void_p(x.data_ptr()), dt, d, ld, B,
+    _check(lib.gs_ctx_fit_batched(ctx.handle, ctypes.c_void_p(x.data_ptr()), dt, d, ld, B,
                               off.ctypes.data_as(ctypes.c_void_p), hs.ctypes.data_as(ctypes.c_void_p), int(max_iter),
                               ctypes.c_void_p(labels.data_ptr()), ctypes.cast(infos, ctypes.c_void_p), sp))
     ks = np.array([infos[b].n_clusters for b in range(B)], dtype=np.int64)
@@ -415,6 +474,98 @@ def track_batched(frames: torch.Tensor, o0, l0, w0, f: float, h: float, eta: flo
     return out
 
 
+class Result:
+    """A gs_result: one fit's (or one batched fit's) cluster tables and, when
+    recorded, its trajectory; its device memory comes from torch's caching
+    allocator (or hipMalloc with ``allocator=None``) until ``close``."""
+
+    def __init__(self, handle, B: int, d: int, labels: torch.Tensor, stream):
+        self.handle, self.B, self.d, self.labels, self._stream = handle, B, d, labels, stream
+
+    def info(self, b: int = 0) -> dict:
+        out = Info()
+        _check(_lib.gs_result_info(self.handle, int(b), ctypes.byref(out)))
+        return out.as_dict()
+
+    def offsets(self) -> np.ndarray:
+        k = np.empty(self.B + 1, np.int64)
+        _check(_lib.gs_result_offsets(self.handle, k.ctypes.data_as(ctypes.c_void_p)))
+        return k
+
+    def copy(self):
+        """(modes float64 [sum K, d], counts int64 [sum K])"""
+        tot = int(self.offsets()[-1])
+        dev = self.labels.device
+        modes = torch.empty((tot, self.d), dtype=torch.float64, device=dev)
+        counts = torch.empty(tot, dtype=torch.int64, device=dev)
+        _check(_lib.gs_result_copy(self.handle, _vp(modes), _vp(counts), self._stream))
+        return modes, counts
+
+    def backward(self, grad_modes: torch.Tensor) -> torch.Tensor:
+        g = grad_modes.to(torch.float64).contiguous()
+        out = torch.empty((self.labels.numel(), self.d), dtype=torch.float64, device=g.device)
+        _check(_lib.gs_backward(self.handle, _vp(g), _vp(out), self._stream))
+        return out
+
+    def loss(self, x: torch.Tensor) -> torch.Tensor:
+        out = torch.empty(self.B, dtype=torch.float64, device=x.device)
+        _check(_lib.gs_point_mode_loss(self.handle, _vp(x.contiguous()), _vp(out), self._stream))
+        return out
+
+    def loss_backward(self, x: torch.Tensor, grad_loss: torch.Tensor) -> torch.Tensor:
+        gl = grad_loss.to(torch.float64).contiguous()
+        out = torch.empty((self.labels.numel(), self.d), dtype=torch.float64, device=x.device)
+        _check(_lib.gs_point_mode_loss_backward(self.handle, _vp(x.contiguous()), _vp(gl), _vp(out), self._stream))
+        return out
+
+    def close(self):
+        if self.handle:
+            _lib.gs_result_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fit_result(x: torch.Tensor, h: float, max_iter: int = 100, ckpt_every: int = 0, *, allocator="torch",
+               stream=None) -> Result:
+    """gs_fit: one point set, its result object owning the fit's memory."""
+    lib = load_library()
+    x, dt, ld = _points(x)
+    n, d = x.shape
+    labels = torch.empty(n, dtype=torch.int32, device=x.device)
+    p = Problem(ctypes.c_void_p(x.data_ptr()), dt, n, d, ld, float(h), int(max_iter), int(ckpt_every))
+    out = ctypes.c_void_p()
+    al = ctypes.byref(TORCH_ALLOCATOR) if allocator == "torch" else None
+    sp = _stream_ptr(stream)
+    _check(lib.gs_fit(ctypes.byref(p), al, sp, ctypes.c_void_p(labels.data_ptr()), ctypes.byref(out)))
+    return Result(out, 1, d, labels, sp)
+
+
+def fit_batched_result(x: torch.Tensor, offsets, h, max_iter: int = 100, ckpt_every: int = 0, *,
+                       allocator="torch", stream=None) -> Result:
+    """gs_fit_batched: B concatenated dense point sets, one result object."""
+    lib = load_library()
+    x, dt, ld = _points(x)
+    d = x.shape[1]
+    if ld != d:
+        raise ValueError("gs_fit_batched takes dense rows")
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    B = off.size - 1
+    hs = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (B,)))
+    labels = torch.empty(x.shape[0], dtype=torch.int32, device=x.device)
+    out = ctypes.c_void_p()
+    al = ctypes.byref(TORCH_ALLOCATOR) if allocator == "torch" else None
+    sp = _stream_ptr(stream)
+    _check(lib.gs_fit_batched(ctypes.c_void_p(x.data_ptr()), dt, d, B, off.ctypes.data_as(ctypes.c_void_p),
+                              hs.ctypes.data_as(ctypes.c_void_p), int(max_iter), int(ckpt_every), al, sp,
+                              ctypes.c_void_p(labels.data_ptr()), ctypes.byref(out)))
+    return Result(out, B, d, labels, sp)
+
+
 # ---------------------------------------------------------------------------
 # differentiable form
 # ---------------------------------------------------------------------------
@@ -427,7 +578,7 @@ def backward_modes(ctx: Context, grad_modes: torch.Tensor, n: int, d: int, strea
     context's last (recorded) fit; float64 [n, d]."""
     g = grad_modes.to(torch.float64).contiguous()
     out = torch.empty((n, d), dtype=torch.float64, device=g.device)
-    _check(_lib.gs_backward(ctx.handle, _vp(g), _vp(out), _stream_ptr(stream)))
+    _check(_lib.gs_ctx_backward(ctx.handle, _vp(g), _vp(out), _stream_ptr(stream)))
     return out
 
 
@@ -435,7 +586,7 @@ def point_mode_loss_values(ctx: Context, x: torch.Tensor, labels: torch.Tensor, 
     """Per-instance loss sum_i ||x_i - mode(label_i)||^2 of the last recorded fit."""
     x, _, _ = _points(x)
     loss = torch.empty(B, dtype=torch.float64, device=x.device)
-    _check(_lib.gs_point_mode_loss(ctx.handle, _vp(x), _vp(labels), _vp(loss), _stream_ptr(stream)))
+    _check(_lib.gs_ctx_point_mode_loss(ctx.handle, _vp(x), _vp(labels), _vp(loss), _stream_ptr(stream)))
     return loss
 
 
@@ -445,7 +596,7 @@ def point_mode_loss_grad(ctx: Context, x: torch.Tensor, labels: torch.Tensor, gr
     x, _, _ = _points(x)
     gl = grad_loss.to(torch.float64).contiguous()
     out = torch.empty(x.shape, dtype=torch.float64, device=x.device)
-    _check(_lib.gs_point_mode_loss_backward(ctx.handle, _vp(x), _vp(labels), _vp(gl), _vp(out),
+    _check(_lib.gs_ctx_point_mode_loss_backward(ctx.handle, _vp(x), _vp(labels), _vp(gl), _vp(out),
                                             _stream_ptr(stream)))
     return out
 

@@ -1,0 +1,106 @@
+"""The per-fit result API (gs_fit / gs_fit_batched -> gs_result) through the C
+ABI, with the device memory taken from torch's caching allocator: bitwise
+the same labels, modes, counts, summaries, adjoint and loss as the context
+calls, every allocation returned on gs_result_free, and the errors."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2206_02200_amd import gridshift, synth  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _bits(t):
+    return np.ascontiguousarray(t.detach().cpu().numpy().astype(np.float64)).view(np.uint64)
+
+
+def _blobs(seed, n, d, k=8, scale=5.0, spread=12.0):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0, spread * scale, size=(k, d))
+    return c[rng.integers(0, k, size=n)] + scale * 0.8 * rng.standard_normal(size=(n, d))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("allocator", ["torch", None])
+def test_plain_result_equals_context_fit(allocator):
+    _say(f"result api plain, allocator={allocator}")
+    w = synth.image_rgb_f64()
+    x = torch.from_numpy(w.x).to(DEV)
+    before = dict(gridshift.ALLOC_STATS)
+    r = gridshift.fit_result(x, w.h, w.max_iter, allocator=allocator)
+    c = gridshift.fit(x, w.h, w.max_iter)
+    info = r.info(0)
+    assert info == c.info
+    assert r.offsets().tolist() == [0, c.info["n_clusters"]]
+    modes, counts = r.copy()
+    np.testing.assert_array_equal(r.labels.cpu().numpy(), c.labels.cpu().numpy())
+    np.testing.assert_array_equal(_bits(modes), _bits(c.modes))
+    np.testing.assert_array_equal(counts.cpu().numpy(), c.counts.cpu().numpy())
+    used = gridshift.ALLOC_STATS["allocs"] - before["allocs"]
+    r.close()
+    torch.cuda.synchronize()
+    if allocator == "torch":
+        assert used > 0
+        assert gridshift.ALLOC_STATS["frees"] - before["frees"] == used
+    else:
+        assert used == 0
+
+
+def test_batched_result_equals_context_fit():
+    _say("result api batched")
+    sizes = [0, 300, 12000, 5, 40000]
+    xs = [_blobs(6000 + i, s, 3) for i, s in enumerate(sizes)]
+    hs = [2.0, 3.0, 1.5, 2.0, 2.5]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    X = torch.from_numpy(np.concatenate(xs, axis=0)).to(DEV)
+    r = gridshift.fit_batched_result(X, off, hs, 100)
+    c = gridshift.fit_batched(X, off, hs, 100)
+    assert [r.info(b) for b in range(len(sizes))] == c.infos
+    assert r.offsets().tolist() == c.k_offsets.tolist()
+    modes, counts = r.copy()
+    np.testing.assert_array_equal(r.labels.cpu().numpy(), c.labels.cpu().numpy())
+    np.testing.assert_array_equal(_bits(modes), _bits(c.modes))
+    with pytest.raises(RuntimeError, match="GS_ERR_INVALID_ARG"):
+        r.info(len(sizes))
+    r.close()
+
+
+@pytest.mark.parametrize("ckpt", [1, 8])
+def test_result_adjoint_and_loss_equal_context(ckpt):
+    _say(f"result api adjoint, ckpt_every={ckpt}")
+    x_np = _blobs(6100, 30000, 5, k=6, scale=4.0)
+    x = torch.from_numpy(x_np).to(DEV)
+    r = gridshift.fit_result(x, 3.0, 100, ckpt_every=ckpt)
+    ctx = gridshift.Context(0)
+    ctx.set_tape(ckpt)
+    c = gridshift.fit(x, 3.0, 100, ctx=ctx)
+    rng = np.random.default_rng(1)
+    gm = torch.from_numpy(rng.standard_normal(size=(c.info["n_clusters"], 5))).to(DEV)
+    np.testing.assert_array_equal(_bits(r.backward(gm)), _bits(gridshift.backward_modes(ctx, gm, 30000, 5)))
+    loss_r = r.loss(x)
+    loss_c = gridshift.point_mode_loss_values(ctx, x, c.labels, 1)
+    np.testing.assert_array_equal(_bits(loss_r), _bits(loss_c))
+    gl = torch.tensor([0.75], dtype=torch.float64, device=DEV)
+    np.testing.assert_array_equal(_bits(r.loss_backward(x, gl)),
+                                  _bits(gridshift.point_mode_loss_grad(ctx, x, c.labels, gl)))
+    r.close()
+
+
+def test_unrecorded_result_has_no_adjoint():
+    x = torch.from_numpy(_blobs(6200, 2000, 2)).to(DEV)
+    r = gridshift.fit_result(x, 2.0, 100)
+    with pytest.raises(RuntimeError, match="GS_ERR_STATE"):
+        r.backward(torch.zeros((r.info()["n_clusters"], 2), dtype=torch.float64, device=DEV))
+    r.close()

@@ -19,7 +19,9 @@ def _declared():
 
 def test_header_declares_entry_points():
     names = _declared()
-    for n in ("gs_fit", "gs_fit_batched", "gs_copy_modes", "gs_copy_keys", "gs_context_create",
+    for n in ("gs_fit", "gs_fit_batched", "gs_result_info", "gs_result_offsets", "gs_result_copy", "gs_backward",
+              "gs_point_mode_loss", "gs_point_mode_loss_backward", "gs_result_free", "gs_ctx_fit",
+              "gs_ctx_fit_batched", "gs_copy_modes", "gs_copy_keys", "gs_context_create",
               "gs_context_destroy", "gs_last_error", "gs_abi_version"):
         assert n in names
 
