@@ -159,8 +159,8 @@ gs_status gs_point_mode_loss(const gs_result* r, const void* points, double* los
 gs_status gs_point_mode_loss_backward(const gs_result* r, const void* points, const double* grad_loss,
                                       double* grad_points, void* stream);
 
-/* Release a result: waits for its stream, then returns its memory to its
- * allocator.  NULL is a no-op. */
+/* Release a result: waits for the stream its fit ran on (which must still
+ * exist), then returns its memory to its allocator.  NULL is a no-op. */
 void gs_result_free(gs_result* r);
 
 /*
