@@ -1597,10 +1597,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
             int32_t me[D];
 #pragma unroll
             for (int dd = 1; dd < D; ++dd) me[dd] = crd[dd][tid];
-            // Straight-line fold over the candidates in ascending index: a
-            // non-neighbour adds -0.0, the exact additive identity, and the
-            // fold starts from -0.0, so the result is bitwise the left fold
-            // over the neighbours alone.
+            // Left fold over the neighbours among the candidates, in
+            // ascending index, starting from -0.0 (the exact additive
+            // identity); non-neighbours' rows are not read (fewer LDS bank
+            // conflicts in the large rounds).
             int64_t W = 0;
 #pragma unroll
             for (int dd = 0; dd < D; ++dd) p[dd] = -0.0;
@@ -1628,10 +1628,12 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
                         const int cs8 = cstate[k];
                         if (ok && (cs8 & 63) < my_col && !(cs8 & 128)) ready = false;
                     }
-                    W += ok ? int64_t(cnt[k]) : 0;
-                    nbs += ok ? 1 : 0;
+                    if (ok) {  // only neighbours' rows are read (a non-neighbour would add -0.0)
+                        W += int64_t(cnt[k]);
+                        nbs += 1;
 #pragma unroll
-                    for (int dd = 0; dd < D; ++dd) p[dd] = p[dd] + (ok ? sm[dd][k] : -0.0);
+                        for (int dd = 0; dd < D; ++dd) p[dd] = p[dd] + sm[dd][k];
+                    }
                 }
             }
             if (ready) {
