@@ -40,13 +40,12 @@ METRIC = "points/sec + HBM GB/s: GridShift 1080p d=5 plain vs batched vs fwd+bwd
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary (profiles/<kernel>_traffic_plain_1080p_d5.txt), or None
-    when there is none or the kernel's sources changed since it was taken."""
+def _profile_values(name: str):
+    """key=value lines of a committed rocprofv3 summary under profiles/, or None
+    when there is none or the sources it names changed since it was taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_plain_1080p_d5.txt")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -62,7 +61,24 @@ def measured_traffic(kernel: str):
         h.update(open(f, "rb").read())
     if h.hexdigest() != kv.get("sources_sha256"):
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return kv
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the FETCH_SIZE / WRITE_SIZE summary
+    (profiles/<kernel>_traffic_plain_1080p_d5.txt), or None."""
+    kv = _profile_values(f"{kernel}_traffic_plain_1080p_d5.txt")
+    return None if kv is None else float(kv["traffic_bytes_per_launch"])
+
+
+def measured_counters(kernel: str):
+    """LDS and L2-atomic counters per launch of `kernel` from the summary
+    profiles/lds_atomic_counters_plain_1080p_d5.txt, or None."""
+    kv = _profile_values("lds_atomic_counters_plain_1080p_d5.txt")
+    if kv is None or f"{kernel}.lds_insts" not in kv:
+        return None
+    fields = ("lds_insts", "lds_active_cycles", "lds_bank_conflict_cycles", "lds_conflict_ratio", "l2_atomics")
+    return {f: float(kv[f"{kernel}.{f}"]) for f in fields}
 
 
 def cpu_model() -> str:
@@ -224,6 +240,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": measured_traffic(dominant),
+            "counters": measured_counters(dominant),
             "avg_launch_us": avg_ms * 1e3,
             "alg_bytes_per_launch": bytes_per_launch,
         },
