@@ -132,6 +132,7 @@ struct gs_context {
     DBuf dk;                 // dense key -> cell table of the device-wide rounds
     uint32_t dk_epoch = 0;
     int64_t key_span = 0;    // packed key range of the current fit
+    bool wide_crd = false;   // some key-box extent is 2^31 or more: the tail keeps 64-bit coordinates
     // pinned staging: downloads (every one waits for its stream) and a bump
     // area for uploads, reused only once a wait on up_stream has drained them
     void* pinned = nullptr;
@@ -630,17 +631,24 @@ gs_status launch_tail(gs_context* c, int d, int B, gs::CellTable t, const gs::In
     const int tk = prof_begin(c, s, replay_r0 >= 0 ? "tail_replay" : "tail");
     c->tail_tok = tk;
     switch (d) {
+#define GS_TL2(D, CT)                                                                                             \
+    if (c->rule == GS_UPDATE_SEQUENTIAL)                                                                          \
+        gs::k_tail<D, true, CT><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0,   \
+                                                               gate);                                             \
+    else                                                                                                          \
+        gs::k_tail<D, false, CT><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0,  \
+                                                                gate);
 #define GS_TL(D)                                                                                                  \
     case D:                                                                                                       \
-        if (c->rule == GS_UPDATE_SEQUENTIAL)                                                                      \
-            gs::k_tail<D, true><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0,   \
-                                                               gate);                                             \
-        else                                                                                                      \
-            gs::k_tail<D, false><<<B, gs::kTailThreads, 0, s>>>(t, prm, st, tmap, max_iter, tape, ck, replay_r0,  \
-                                                                gate);                                            \
+        if (c->wide_crd) {                                                                                        \
+            GS_TL2(D, int64_t)                                                                                    \
+        } else {                                                                                                  \
+            GS_TL2(D, int32_t)                                                                                    \
+        }                                                                                                         \
         break;
         GS_TL(1) GS_TL(2) GS_TL(3) GS_TL(4) GS_TL(5) GS_TL(6)
 #undef GS_TL
+#undef GS_TL2
         default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
     }
     prof_end(c, s, tk, nbytes);
@@ -654,6 +662,7 @@ gs_status build_params(gs_context* c, int B, int d, const int64_t* offsets, cons
     c->prm.assign(B, gs::InstParam{});
     const uint64_t kLimit = 1ull << 62;
     uint64_t total = 0;
+    c->wide_crd = false;
     for (int b = 0; b < B; ++b) {
         gs::InstParam& p = c->prm[b];
         p.h = h[b];
@@ -675,6 +684,7 @@ gs_status build_params(gs_context* c, int B, int d, const int64_t* offsets, cons
             const int64_t mx = box[(int64_t(b) * gs::kMaxDim + k) * 2 + 1];
             p.lo[k] = mn - 1;
             p.E[k] = mx - mn + 3;
+            if (p.E[k] >= (int64_t(1) << 31)) c->wide_crd = true;
             span *= (long double)p.E[k];
         }
         if (span >= (long double)kLimit)
@@ -1121,12 +1131,15 @@ gs_status launch_tail_adj(gs_context* c, int d, const gs::TailTape& tape, const 
     const int64_t cap = c->capM;
     const int tk = prof_begin(c, s, "tail_adj");
     switch (d) {
-        case 1: gs::k_tail_adj<1><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0); break;
-        case 2: gs::k_tail_adj<2><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0); break;
-        case 3: gs::k_tail_adj<3><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0); break;
-        case 4: gs::k_tail_adj<4><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0); break;
-        case 5: gs::k_tail_adj<5><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0); break;
-        case 6: gs::k_tail_adj<6><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0); break;
+#define GS_TA(D)                                                                                                  \
+    case D:                                                                                                       \
+        if (c->wide_crd)                                                                                          \
+            gs::k_tail_adj<D, int64_t><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0);      \
+        else                                                                                                      \
+            gs::k_tail_adj<D, int32_t><<<B, gs::kTailThreads, 0, s>>>(prm, st, tape, sbar, cap, ck, seg_r0);      \
+        break;
+        GS_TA(1) GS_TA(2) GS_TA(3) GS_TA(4) GS_TA(5) GS_TA(6)
+#undef GS_TA
         default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
     }
     prof_end(c, s, tk, 0.0);

@@ -1319,6 +1319,13 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
 // column table in LDS gives them directly: col[v] = first cell whose column
 // (c0, or c0 * E1 + c1) is >= v, for v in [0, ncol].  Without one (too many
 // columns) a binary search gives the range of dimension-0 coordinates.
+// Coordinates of tail cells relative to the box origin: 32-bit while every
+// extent of the instances' key boxes is below 2^31, else 64-bit (the neighbour
+// test |a - b| <= 1 is (a - b + 1) <= 2 in the unsigned type of the same width).
+template <typename CT> struct CoordUnsigned;
+template <> struct CoordUnsigned<int32_t> { using type = uint32_t; };
+template <> struct CoordUnsigned<int64_t> { using type = uint64_t; };
+
 struct TailCols {
     int mode;  // 2: columns of (c0, c1); 1: of c0; 0: no table
     int E0, E1, ncol;
@@ -1346,13 +1353,15 @@ __device__ inline TailCols tail_cols(int64_t E0, int64_t E1) {
     return c;
 }
 
-__device__ inline int tail_col(const TailCols& c, const int32_t* crd0, const int32_t* crd1, int i) {
-    return c.mode == 2 ? crd0[i] * c.E1 + crd1[i] : crd0[i];
+template <typename CT>
+__device__ inline int tail_col(const TailCols& c, const CT* crd0, const CT* crd1, int i) {
+    return c.mode == 2 ? int(crd0[i]) * c.E1 + int(crd1[i]) : int(crd0[i]);
 }
 
 // Every thread of the workgroup calls this; a barrier must follow.  Entry v
 // is a binary search over the m cells' columns (ascending with the cells).
-__device__ inline void tail_cols_build(const TailCols& c, const int32_t* crd0, const int32_t* crd1, int m, int tid,
+template <typename CT>
+__device__ inline void tail_cols_build(const TailCols& c, const CT* crd0, const CT* crd1, int m, int tid,
                                        uint16_t* col) {
     if (c.mode == 0) return;
     for (int v = tid; v <= c.ncol; v += kTailThreads) {
@@ -1369,17 +1378,18 @@ struct TailWindow {
     int a[3], n[3];  // ranges [a[u], a[u] + n[u]), ascending and disjoint
 };
 
-__device__ inline TailWindow tail_window(const TailCols& c, const int32_t* crd0, const int32_t* crd1, int m, int i,
+template <typename CT>
+__device__ inline TailWindow tail_window(const TailCols& c, const CT* crd0, const CT* crd1, int m, int i,
                                          const uint16_t* col) {
     TailWindow w;
-    const int c0 = crd0[i];
+    const CT c0 = crd0[i];
     if (c.mode == 2) {
-        const int c1 = crd1[i];
+        const int c1 = int(crd1[i]);
         const int lo1 = c1 - 1 < 0 ? 0 : c1 - 1;
         const int hi1 = c1 + 2 > c.E1 ? c.E1 : c1 + 2;
 #pragma unroll
         for (int u = 0; u < 3; ++u) {
-            const int a0 = c0 - 1 + u;
+            const int a0 = int(c0) - 1 + u;
             if (a0 < 0 || a0 >= c.E0) {
                 w.a[u] = 0;
                 w.n[u] = 0;
@@ -1392,8 +1402,9 @@ __device__ inline TailWindow tail_window(const TailCols& c, const int32_t* crd0,
     }
     int a, z;  // cells with dimension-0 coordinate in [c0 - 1, c0 + 1]
     if (c.mode == 1) {
-        a = col[c0 - 1 < 0 ? 0 : c0 - 1];
-        z = col[c0 + 2 > c.E0 ? c.E0 : c0 + 2];
+        const int c0i = int(c0);
+        a = col[c0i - 1 < 0 ? 0 : c0i - 1];
+        z = col[c0i + 2 > c.E0 ? c.E0 : c0i + 2];
     } else {
         a = 0;
         z = m;
@@ -1445,15 +1456,16 @@ __global__ void k_tail_gate(const InstState* __restrict__ st, int B, int64_t* __
 // colour are never neighbours): a moved cell writes fl(C_j * p_j) over its sum
 // for the cells moving after it, and a round that stops puts the sums back.
 // SEQ fits record no tape or checkpoints.
-template <int D, bool SEQ>
+template <int D, bool SEQ, typename CT>
 __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstParam* __restrict__ param,
                                                        InstState* __restrict__ st, uint32_t* __restrict__ tmap,
                                                        int max_iter, TailTape tape, TailCkpt ck, int replay_r0,
                                                        const int64_t* __restrict__ gate) {
     constexpr int MT = kTailCells;
     constexpr int NW = kTailThreads / kWave;
+    using UCT = typename CoordUnsigned<CT>::type;
     __shared__ uint64_t lkey[MT];     // local packed key (key - base), ascending
-    __shared__ int32_t crd[D][MT];    // unpacked coordinates relative to lo
+    __shared__ CT crd[D][MT];         // unpacked coordinates relative to lo
     __shared__ int32_t cnt[MT];       // counts
     __shared__ double sm[D][MT];      // sums; reused as the sorted merge values
     __shared__ uint64_t kap[MT];      // landing keys
@@ -1524,7 +1536,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         }
         lkey[tid] = lk;
 #pragma unroll
-        for (int k = 0; k < D; ++k) crd[k][tid] = int32_t((lk / P.stride[k]) % uint64_t(P.E[k]));
+        for (int k = 0; k < D; ++k) crd[k][tid] = CT((lk / P.stride[k]) % uint64_t(P.E[k]));
         lmap[tid] = uint16_t(tid);
     }
     __syncthreads();
@@ -1563,7 +1575,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
             if (tid < m) {
                 int rp = 0;
 #pragma unroll
-                for (int k = 0; k < D; ++k) rp = (rp << 1) | (crd[k][tid] & 1);
+                for (int k = 0; k < D; ++k) rp = (rp << 1) | int(crd[k][tid] & 1);
                 my_col = rp ^ lo_par;
                 cstate[tid] = uint8_t(my_col);  // colour; bit 7 set once the cell has moved
             }
@@ -1585,7 +1597,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         double p[D];
         double val[D];
         double orig[SEQ ? D : 1];  // the cell's sums before the sweep overwrote them
-        int32_t q[D];
+        CT q[D];
         uint64_t kj = 0;
         int32_t Wj = 0;
         bool pending = tid < m;
@@ -1594,7 +1606,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         if (pending) {
             const TailWindow win = tail_window(cols, crd[0], crd[D >= 2 ? 1 : 0], m, tid, col);
             const int ncand = win.n[0] + win.n[1] + win.n[2];
-            int32_t me[D];
+            CT me[D];
 #pragma unroll
             for (int dd = 1; dd < D; ++dd) me[dd] = crd[dd][tid];
             // Left fold over the neighbours among the candidates, in
@@ -1618,7 +1630,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
                 for (int dd = 1; dd < D; ++dd) {
                     if (dd < cols.first_test) continue;
 #pragma unroll
-                    for (int u = 0; u < U; ++u) okm[u] &= (uint32_t(crd[dd][kk[u]] - me[dd] + 1) <= 2u) ? 1 : 0;
+                    for (int u = 0; u < U; ++u) okm[u] &= (UCT(crd[dd][kk[u]] - me[dd] + 1) <= UCT(2)) ? 1 : 0;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -1645,7 +1657,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
                 const double qq = cell_floor(p[dd], h);
                 const double rel = qq - s_lod[dd];
                 if (!(rel >= 0.0 && rel < s_Ed[dd])) bad = true;
-                q[dd] = int32_t(int64_t(qq) - s_lo[dd]);
+                q[dd] = CT(int64_t(qq) - s_lo[dd]);
                 kj += uint64_t(int64_t(qq) - s_lo[dd]) * s_stride[dd];
             }
             // merge values and stationarity (own cell only: nothing writes it
@@ -1794,7 +1806,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         uint64_t nk = 0;
         int32_t nc = 0;
         double ns[D];
-        int32_t nq[D];
+        CT nq[D];
         if (head) {
             nk = skey[tid];
             nc = scnt[tid];
@@ -1881,16 +1893,14 @@ __global__ void k_adj_final(CellTable t, const InstState* __restrict__ st, const
 // [seg_r0, seg_r0 + ck.every) (recomputed from its checkpoint) and the kernel
 // reverses just those rounds; sbar then holds, per instance, the Sbar of the
 // cells at the segment's end on entry and at its start on exit.
-template <int D>
+template <int D, typename CT>
 __global__ __launch_bounds__(kTailThreads) void k_tail_adj(const InstParam* __restrict__ param,
                                                            const InstState* __restrict__ st, TailTape tape,
                                                            double* __restrict__ sbar, int64_t cap, TailCkpt ck,
                                                            int seg_r0) {
     constexpr int MT = kTailCells;
-    __shared__ int32_t crd[D][MT];
-    __shared__ int32_t cnt[MT];
-    __shared__ int32_t Wt[MT];
-    __shared__ uint16_t gt[MT];
+    using UCT = typename CoordUnsigned<CT>::type;
+    __shared__ CT crd[D][MT];
     __shared__ double A[D][MT];
     __shared__ double Q[D][MT];
     __shared__ uint16_t col[kSlabMax + 1];
@@ -1926,13 +1936,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_adj(const InstParam* __re
         if (tid < m) {
             const uint64_t lk = tape.key[e0 + tid];
 #pragma unroll
-            for (int k = 0; k < D; ++k) crd[k][tid] = int32_t((lk / stride[k]) % uint64_t(E[k]));
+            for (int k = 0; k < D; ++k) crd[k][tid] = CT((lk / stride[k]) % uint64_t(E[k]));
             const int32_t C = tape.cnt[e0 + tid];
             const int32_t W = tape.W[e0 + tid];
             const uint32_t g = tape.g[e0 + tid];
-            cnt[tid] = C;
-            Wt[tid] = W;
-            gt[tid] = uint16_t(g);
 #pragma unroll
             for (int k = 0; k < D; ++k) Q[k][tid] = (double(C) * A[k][g]) / double(W);
         }
@@ -1942,7 +1949,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_adj(const InstParam* __re
         if (tid < m) {
             const TailWindow win = tail_window(cols, crd[0], crd[D >= 2 ? 1 : 0], m, tid, col);
             const int ncand = win.n[0] + win.n[1] + win.n[2];
-            int32_t me[D];
+            CT me[D];
 #pragma unroll
             for (int dd = 1; dd < D; ++dd) me[dd] = crd[dd][tid];
             double acc[D];
@@ -1959,7 +1966,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_adj(const InstParam* __re
                 for (int dd = 1; dd < D; ++dd) {
                     if (dd < cols.first_test) continue;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) okm[u] &= (uint32_t(crd[dd][kk[u]] - me[dd] + 1) <= 2u) ? 1 : 0;
+                    for (int u = 0; u < 4; ++u) okm[u] &= (UCT(crd[dd][kk[u]] - me[dd] + 1) <= UCT(2)) ? 1 : 0;
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {

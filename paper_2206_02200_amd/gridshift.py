@@ -479,8 +479,18 @@ class Result:
     recorded, its trajectory; its device memory comes from torch's caching
     allocator (or hipMalloc with ``allocator=None``) until ``close``."""
 
-    def __init__(self, handle, B: int, d: int, labels: torch.Tensor, stream):
+    def __init__(self, handle, B: int, d: int, labels: torch.Tensor, stream, dtype: int, ld: int):
         self.handle, self.B, self.d, self.labels, self._stream = handle, B, d, labels, stream
+        # the loss calls read the points with the fit's row stride and type
+        self._dtype, self._ld = dtype, ld
+
+    def _same_points(self, x: torch.Tensor) -> torch.Tensor:
+        x, dt, ld = _points(x)
+        if dt != self._dtype or ld != self._ld or x.shape != (self.labels.numel(), self.d):
+            raise ValueError(f"the loss needs the points in the fit's layout: [{self.labels.numel()}, {self.d}] "
+                             f"rows of stride {self._ld}, dtype code {self._dtype} (got {tuple(x.shape)}, "
+                             f"stride {ld}, dtype code {dt})")
+        return x
 
     def info(self, b: int = 0) -> dict:
         out = Info()
@@ -508,14 +518,16 @@ class Result:
         return out
 
     def loss(self, x: torch.Tensor) -> torch.Tensor:
+        x = self._same_points(x)
         out = torch.empty(self.B, dtype=torch.float64, device=x.device)
-        _check(_lib.gs_point_mode_loss(self.handle, _vp(x.contiguous()), _vp(out), self._stream))
+        _check(_lib.gs_point_mode_loss(self.handle, _vp(x), _vp(out), self._stream))
         return out
 
     def loss_backward(self, x: torch.Tensor, grad_loss: torch.Tensor) -> torch.Tensor:
+        x = self._same_points(x)
         gl = grad_loss.to(torch.float64).contiguous()
         out = torch.empty((self.labels.numel(), self.d), dtype=torch.float64, device=x.device)
-        _check(_lib.gs_point_mode_loss_backward(self.handle, _vp(x.contiguous()), _vp(gl), _vp(out), self._stream))
+        _check(_lib.gs_point_mode_loss_backward(self.handle, _vp(x), _vp(gl), _vp(out), self._stream))
         return out
 
     def close(self):
@@ -542,7 +554,7 @@ def fit_result(x: torch.Tensor, h: float, max_iter: int = 100, ckpt_every: int =
     al = ctypes.byref(TORCH_ALLOCATOR) if allocator == "torch" else None
     sp = _stream_ptr(stream)
     _check(lib.gs_fit(ctypes.byref(p), al, sp, ctypes.c_void_p(labels.data_ptr()), ctypes.byref(out)))
-    return Result(out, 1, d, labels, sp)
+    return Result(out, 1, d, labels, sp, dt, ld)
 
 
 def fit_batched_result(x: torch.Tensor, offsets, h, max_iter: int = 100, ckpt_every: int = 0, *,
@@ -563,7 +575,7 @@ def fit_batched_result(x: torch.Tensor, offsets, h, max_iter: int = 100, ckpt_ev
     _check(lib.gs_fit_batched(ctypes.c_void_p(x.data_ptr()), dt, d, B, off.ctypes.data_as(ctypes.c_void_p),
                               hs.ctypes.data_as(ctypes.c_void_p), int(max_iter), int(ckpt_every), al, sp,
                               ctypes.c_void_p(labels.data_ptr()), ctypes.byref(out)))
-    return Result(out, B, d, labels, sp)
+    return Result(out, B, d, labels, sp, dt, ld)
 
 
 # ---------------------------------------------------------------------------

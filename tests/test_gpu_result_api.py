@@ -104,3 +104,25 @@ def test_unrecorded_result_has_no_adjoint():
     with pytest.raises(RuntimeError, match="GS_ERR_STATE"):
         r.backward(torch.zeros((r.info()["n_clusters"], 2), dtype=torch.float64, device=DEV))
     r.close()
+
+
+def test_result_loss_with_column_sliced_points():
+    # points as a column slice of a wider tensor (row stride 5, d = 3): the
+    # loss and its gradient read the rows with the fit's stride, bitwise as a
+    # fit of the dense copy
+    _say("result api loss, column-sliced points")
+    wide = torch.from_numpy(_blobs(6300, 20000, 5, k=6, scale=4.0)).to(DEV)
+    view = wide[:, :3]
+    dense = view.contiguous()
+    r = gridshift.fit_result(view, 3.0, 100, ckpt_every=1)
+    q = gridshift.fit_result(dense, 3.0, 100, ckpt_every=1)
+    assert r.info() == q.info()
+    np.testing.assert_array_equal(_bits(r.loss(view)), _bits(q.loss(dense)))
+    gl = torch.tensor([1.25], dtype=torch.float64, device=DEV)
+    np.testing.assert_array_equal(_bits(r.loss_backward(view, gl)), _bits(q.loss_backward(dense, gl)))
+    with pytest.raises(ValueError, match="layout"):
+        r.loss(dense)  # same values, another row stride
+    with pytest.raises(ValueError, match="layout"):
+        q.loss(view.to(torch.float32))
+    r.close()
+    q.close()

@@ -48,8 +48,8 @@ def test_worked_examples_agree_with_exact(oracle):
 
     ex_all = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))
     for e in ex_all["examples"]:
-        if "labels" not in e:
-            continue
+        if "labels" not in e or e.get("rounding_decides"):
+            continue  # (a fixed point only in binary64: exact means would move it)
         ex = exact_fit(np.array(e["x"]), e["h"], rule=e.get("rule", "parallel"))
         assert ex["labels"] == e["labels"] and ex["counts"] == e["counts"]
         assert ex["n_iter"] == e["n_iter"]

@@ -158,3 +158,27 @@ def test_errors(oracle):
     with pytest.raises(oracle.OracleError) as e:
         oracle.fit(np.array([[1e300]]), 1e-300)
     assert e.value.code == 3
+
+
+def test_key_range_edge(oracle):
+    # The oracle keeps keys as int64 and accepts |floor(x/h)| < 2^62: the last
+    # binary64 value below 2^62 is accepted, 2^62 itself (either sign) is not.
+    below = 2.0**62 - 1024.0  # spacing of binary64 just below 2^62 is 1024
+    for v in (below, -below):
+        r = oracle.fit(np.array([[v], [0.5]]), 1.0)
+        assert r.K == 2 and r.flags == oracle.CONVERGED
+        assert sorted(r.keys.ravel().tolist()) == sorted([int(v), 0])
+    for v in (2.0**62, -(2.0**62)):
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.fit(np.array([[v], [0.5]]), 1.0)
+        assert e.value.code == 3
+
+
+def test_far_apart_cells_are_not_neighbours(oracle):
+    # Cells 2^32 apart (a distance that wraps to 0 in 32 bits) are not
+    # neighbours (Section 2.1 (v)): two clusters, no round.
+    r = oracle.fit(np.array([[0.5], [2.0**32 + 0.5]]), 1.0)
+    assert (r.K, r.n_iter, r.flags) == (2, 0, oracle.CONVERGED)
+    x = np.array([[0.5, 0.5], [0.5, 2.0**32 + 0.5], [1.5, 2.0**32 + 1.5]])
+    r = oracle.fit(x, 1.0)
+    assert (r.K, r.n_iter) == (2, 1) and r.labels.tolist() == [0, 1, 1]
