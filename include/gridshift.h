@@ -164,6 +164,38 @@ gs_status gs_point_mode_loss_backward(const gs_result* r, const void* points, co
 void gs_result_free(gs_result* r);
 
 /*
+ * Plain fit for callers that cannot allocate (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): gs_fit without a
+ * result object and without any device allocation.  The fit's scratch comes
+ * from a fixed array of GS_NOALLOC_SCRATCH_BYTES of device memory that the
+ * library holds on every GPU it runs on until the process ends; no hipMalloc,
+ * hipHostMalloc, hipFree or caller allocator is called (host bookkeeping
+ * uses ordinary heap memory).
+ *   p            as for gs_fit; p->n <= GS_NOALLOC_MAX_POINTS (larger sets
+ *                return GS_ERR_INVALID_ARG before any device work) and
+ *                p->ckpt_every must be 0 (else GS_ERR_UNSUPPORTED).
+ *   labels       device int32 [n], as for gs_fit.
+ *   modes        device double [max_clusters][d]: fl(S / C) of clusters 0..K-1.
+ *   counts       device int64 [max_clusters]: C of clusters 0..K-1.
+ *   max_clusters rows the caller gave modes and counts (K <= n always); if
+ *                K exceeds it the call returns GS_ERR_INVALID_ARG with *info
+ *                filled and labels written, modes and counts untouched.
+ *   info         host, the summary (as gs_result_info).
+ * Results are bitwise those of gs_fit.  The stream is synchronised before
+ * the call returns.  Every call on one GPU uses that GPU's one scratch array
+ * and overwrites what the previous call left there: calls that overlap on
+ * one GPU (other host threads, or other streams whose work has not ended)
+ * race, and must be serialised by the caller.  The worst case (n points,
+ * every point its own cell, d = 6, binary64) fits the array for every
+ * n <= GS_NOALLOC_MAX_POINTS; a fit that would still exceed it returns
+ * GS_ERR_ALLOC.
+ */
+#define GS_NOALLOC_MAX_POINTS 131072
+#define GS_NOALLOC_SCRATCH_BYTES (64u << 20)
+gs_status gs_fit_noalloc(const gs_problem* p, void* stream, int32_t* labels, double* modes, int64_t* counts,
+                         int64_t max_clusters, gs_info* info);
+
+/*
  * Contexts.  A gs_context holds the scratch of repeated fits and the last
  * fit's result; the gs_ctx_* calls below do what the calls above do, on a
  * context that the caller keeps (no allocation after the first fit of a

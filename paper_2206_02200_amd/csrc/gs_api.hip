@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -165,6 +166,11 @@ struct gs_context {
     int64_t* hmap = nullptr;      // host view
     int64_t* hmap_dev = nullptr;  // device view
     size_t hmap_cap = 0;
+    // a context over fixed memory (gs_fit_noalloc): the staging areas and the
+    // published block are never reallocated, and the published block is
+    // device memory that the host copies back after each wait
+    bool fixed_host = false;
+    bool hmap_on_device = false;
     hipEvent_t ev_start = nullptr, ev_rep[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
     DBuf sbA, sbB, qbuf, gmodes, modes_i, counts_i, frows, lossc, ltab;
     DBuf xkA, xkB, xvA, xvB;
@@ -301,6 +307,8 @@ void sort_prof_end(void* ctx, hipStream_t s, int tok, double bytes) {
 
 gs_status pinned_ensure(gs_context* c, size_t bytes) {
     if (c->pinned_cap >= bytes) return GS_OK;
+    if (c->fixed_host)
+        return fail(GS_ERR_INVALID_ARG, "a download of " + std::to_string(bytes) + " bytes exceeds the fixed staging");
     if (c->pinned) (void)hipHostFree(c->pinned);
     c->pinned = nullptr;
     c->pinned_cap = 0;
@@ -340,6 +348,9 @@ gs_status h2d(gs_context* c, void* dst, const void* src, size_t bytes, hipStream
         if (c->up_used > 0) GS_TRY(stream_wait(c, s));
         c->up_used = 0;
         if (need > c->up_cap) {
+            if (c->fixed_host)
+                return fail(GS_ERR_INVALID_ARG,
+                            "an upload of " + std::to_string(bytes) + " bytes exceeds the fixed staging");
             if (c->up) (void)hipHostFree(c->up);
             c->up = nullptr;
             c->up_cap = 0;
@@ -377,6 +388,7 @@ gs_status h2d_batch(gs_context* c, const std::vector<Xfer>& xs, hipStream_t s) {
 gs_status hmap_ensure(gs_context* c, int B) {
     const size_t bytes = 8 * sizeof(int64_t) + sizeof(gs::InstState) * size_t(B);
     if (c->hmap_cap >= bytes) return GS_OK;
+    if (c->fixed_host) return fail(GS_ERR_INVALID_ARG, "the fixed published block is too small for the instances");
     if (c->hmap) (void)hipHostFree(c->hmap);
     c->hmap = nullptr;
     c->hmap_dev = nullptr;
@@ -398,10 +410,17 @@ gs_status hmap_ensure(gs_context* c, int B) {
     return GS_OK;
 }
 
+// Wait for the stream; afterwards the first `bytes` of the published block
+// are readable at c->hmap (copied back when the block is device memory).
+gs_status published_pull(gs_context* c, size_t bytes, hipStream_t s) {
+    if (c->hmap_on_device) GS_HIP(hipMemcpyAsync(c->hmap, c->hmap_dev, bytes, hipMemcpyDeviceToHost, s));
+    return stream_wait(c, s);
+}
+
 // Wait for the stream, then read the counters and states a kernel published
 // into the mapped host memory.
 gs_status read_published(gs_context* c, int64_t* ctrs, hipStream_t s) {
-    GS_TRY(stream_wait(c, s));
+    GS_TRY(published_pull(c, 8 * sizeof(int64_t) + c->state.cap, s));
     std::memcpy(ctrs, c->hmap, 8 * sizeof(int64_t));
     std::memcpy(c->st.data(), c->hmap + 8, c->state.cap);
     return GS_OK;
@@ -825,7 +844,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
                           P<uint32_t>(c->cell0)};
         GS_TRY(run_scan(c, op, nullptr, N, ctr + 0, s, "scan_heads", N * (sizeof(K) + 8.0), c->hmap_dev));
     }
-    GS_TRY(stream_wait(c, s));
+    GS_TRY(published_pull(c, sizeof(int64_t), s));
     const int64_t m0 = c->hmap[0];  // the cell count, published by the scan's last tile
 
     // ---- cell tables with capacity m0
@@ -2101,6 +2120,133 @@ void gs_result_free(gs_result* r) {
         gs_context_destroy(r->ctx);
     }
     delete r;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// plain fit without allocation: every device buffer of the fit is carved out
+// of one fixed array of device memory
+// ---------------------------------------------------------------------------
+// The fixed array.  Host code never uses its name as an address: each device
+// has its own copy, whose address hipGetSymbolAddress gives (fixed_setup).
+static __device__ __align__(256) unsigned char scratch[GS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr size_t kFixedPublished = 4096;  // head of the array: counters and states the kernels publish
+constexpr size_t kFixedStage = 16384;     // host staging per device and direction
+constexpr int kFixedDevices = 16;
+
+struct FixedDevice {
+    bool ready = false;
+    void* scratch = nullptr;  // this device's copy of `scratch`
+    alignas(256) char down[kFixedStage];
+    alignas(256) char up[kFixedStage];
+    alignas(256) int64_t published[kFixedPublished / sizeof(int64_t)];
+};
+FixedDevice g_fixed[kFixedDevices];
+std::mutex g_fixed_mu;
+
+// Once per device, with that device current: the device address of its copy
+// of the array.
+gs_status fixed_setup(int dev, FixedDevice** out) {
+    if (dev < 0 || dev >= kFixedDevices)
+        return fail(GS_ERR_UNSUPPORTED, "gs_fit_noalloc supports devices 0.." + std::to_string(kFixedDevices - 1));
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    FixedDevice& fd = g_fixed[dev];
+    if (!fd.ready) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(GS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        fd.scratch = ptr;
+        fd.ready = true;
+    }
+    *out = &fd;
+    return GS_OK;
+}
+
+// Bump allocation over the array (after its published head); nothing is
+// given back before the call ends, and the next call starts again at 0.
+struct Bump {
+    char* base;
+    size_t cap, used, failed;
+};
+void* bump_alloc(void* ctx, size_t bytes, void*) {
+    Bump* b = static_cast<Bump*>(ctx);
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (need > b->cap - b->used) {
+        b->failed = bytes;
+        return nullptr;
+    }
+    void* p = b->base + b->used;
+    b->used += need;
+    return p;
+}
+void bump_free(void*, void*, void*) {}
+
+}  // namespace
+
+extern "C" {
+
+gs_status gs_fit_noalloc(const gs_problem* p, void* stream, int32_t* labels, double* modes, int64_t* counts,
+                         int64_t max_clusters, gs_info* info) {
+    if (!p || !info) return fail(GS_ERR_INVALID_ARG, "problem and info are required");
+    if (p->n < 0) return fail(GS_ERR_INVALID_ARG, "n must be >= 0");
+    if (p->n > GS_NOALLOC_MAX_POINTS)
+        return fail(GS_ERR_INVALID_ARG, "gs_fit_noalloc takes at most " + std::to_string(GS_NOALLOC_MAX_POINTS) +
+                                            " points (its fixed scratch is " +
+                                            std::to_string(GS_NOALLOC_SCRATCH_BYTES >> 20) + " MiB); got " +
+                                            std::to_string(p->n));
+    if (p->ckpt_every != 0) return fail(GS_ERR_UNSUPPORTED, "gs_fit_noalloc records no trajectory (ckpt_every 0)");
+    if (max_clusters < 0) return fail(GS_ERR_INVALID_ARG, "max_clusters must be >= 0");
+    int dev = 0;
+    GS_HIP(hipGetDevice(&dev));
+    FixedDevice* fd = nullptr;
+    GS_TRY(fixed_setup(dev, &fd));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    // a fresh context each call (epochs, tickets and look-back storage start
+    // cleared, as in a new context), its device memory from the array
+    Bump bump{static_cast<char*>(fd->scratch) + kFixedPublished, size_t(GS_NOALLOC_SCRATCH_BYTES) - kFixedPublished,
+              0, 0};
+    gs_context c;
+    c.device = dev;
+    c.alloc = gs_allocator{bump_alloc, bump_free, &bump};
+    c.has_alloc = true;
+    c.cfg.dense_table = 0;  // neighbour lookups through the per-round hash (the dense table can reach 1 GiB)
+    c.fixed_host = true;
+    c.pinned = fd->down;
+    c.pinned_cap = sizeof(fd->down);
+    c.up = fd->up;
+    c.up_cap = sizeof(fd->up);
+    c.hmap = fd->published;
+    c.hmap_dev = static_cast<int64_t*>(fd->scratch);
+    c.hmap_cap = kFixedPublished;
+    c.hmap_on_device = true;
+    AllocScope as_(&c, stream);
+    const int64_t offsets[2] = {0, p->n};
+    gs_status rc = fit_impl(&c, p->points, p->dtype, p->d, p->ld, 1, offsets, &p->h, p->max_iter, labels, info, s);
+    if (rc == GS_ERR_ALLOC)
+        return fail(GS_ERR_ALLOC, "gs_fit_noalloc: the fit needs more than the fixed " +
+                                      std::to_string(GS_NOALLOC_SCRATCH_BYTES >> 20) + " MiB of scratch (" +
+                                      std::to_string(bump.used) + " bytes in use, " + std::to_string(bump.failed) +
+                                      " more asked for)");
+    if (rc != GS_OK) return rc;
+    const int64_t K = info->n_clusters;
+    if (K > max_clusters)
+        return fail(GS_ERR_INVALID_ARG, "the fit found " + std::to_string(K) + " clusters; modes and counts hold " +
+                                            std::to_string(max_clusters));
+    if (K > 0) {
+        if (!modes && !counts) return GS_OK;
+        gs::k_copy_modes<<<blocks_for(K, 256), 256, 0, s>>>(table(&c, c.cur_tab), P<gs::InstState>(c.state),
+                                                            P<int64_t>(c.koff), 1, K, c.d, modes, counts, nullptr);
+        GS_HIP(hipGetLastError());
+    }
+    // the next call reuses the array: this call's work ends first
+    GS_HIP(hipStreamSynchronize(s));
+    return GS_OK;
 }
 
 }  // extern "C"

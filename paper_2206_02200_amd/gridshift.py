@@ -37,7 +37,7 @@ EXPORTED = [
     "gs_context_set_tape", "gs_ctx_backward", "gs_ctx_point_mode_loss", "gs_ctx_point_mode_loss_backward",
     "gs_context_set_config", "gs_context_get_config", "gs_autotune",
     "gs_context_set_update", "gs_context_get_update", "gs_fit_hsweep", "gs_track",
-    "gs_track_batched",
+    "gs_track_batched", "gs_fit_noalloc",
 ]
 CFG_MERGE_SMALL, CFG_TILE_CHUNKS, CFG_DENSE_TABLE = 0, 1, 2
 CONFIG_KEYS = {"merge_small": CFG_MERGE_SMALL, "tile_chunks": CFG_TILE_CHUNKS, "dense_table": CFG_DENSE_TABLE}
@@ -141,6 +141,8 @@ def load_library(path: str = LIB_PATH):
         lib.gs_point_mode_loss_backward.argtypes = [V, V, V, V, V]
         lib.gs_point_mode_loss_backward.restype = ctypes.c_int
         lib.gs_result_free.argtypes = [V]
+        lib.gs_fit_noalloc.restype = ctypes.c_int
+        lib.gs_fit_noalloc.argtypes = [ctypes.POINTER(Problem), V, V, V, V, I64, ctypes.POINTER(Info)]
         lib.gs_result_free.restype = None
         lib.gs_ctx_fit.argtypes = [V, V, ctypes.c_int, I64, I32, I64, D, I32, V, ctypes.POINTER(Info), V]
         lib.gs_ctx_fit.restype = ctypes.c_int
@@ -576,6 +578,34 @@ def fit_batched_result(x: torch.Tensor, offsets, h, max_iter: int = 100, ckpt_ev
                               hs.ctypes.data_as(ctypes.c_void_p), int(max_iter), int(ckpt_every), al, sp,
                               ctypes.c_void_p(labels.data_ptr()), ctypes.byref(out)))
     return Result(out, B, d, labels, sp, dt, ld)
+
+
+NOALLOC_MAX_POINTS = 131072  # GS_NOALLOC_MAX_POINTS
+
+
+def fit_noalloc(x: torch.Tensor, h: float, max_iter: int = 100, *, labels: torch.Tensor | None = None,
+                modes: torch.Tensor | None = None, counts: torch.Tensor | None = None, stream=None) -> FitResult:
+    """gs_fit_noalloc: a plain fit whose device scratch is the library's fixed
+    array (no allocation inside the call).  The output tensors may be passed
+    in (labels int32 [n], modes float64 [k, d], counts int64 [k]); missing ones
+    are created here, with room for n clusters.  Returns views of the K rows."""
+    lib = load_library()
+    x, dt, ld = _points(x)
+    n, d = x.shape
+    dev = x.device
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+    if modes is None:
+        modes = torch.empty((max(n, 1), d), dtype=torch.float64, device=dev)
+    if counts is None:
+        counts = torch.empty(modes.shape[0], dtype=torch.int64, device=dev)
+    kcap = min(modes.shape[0], counts.shape[0])
+    p = Problem(ctypes.c_void_p(x.data_ptr()), dt, n, d, ld, float(h), int(max_iter), 0)
+    info = Info()
+    _check(lib.gs_fit_noalloc(ctypes.byref(p), _stream_ptr(stream), _vp(labels), _vp(modes), _vp(counts), kcap,
+                              ctypes.byref(info)))
+    K = info.n_clusters
+    return FitResult(labels, modes[:K], counts[:K], info.as_dict())
 
 
 # ---------------------------------------------------------------------------
