@@ -21,7 +21,13 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gs_oracle.c")
-LIB_PATH = os.path.join(_HERE, "liboracle_gs.so")
+# GS_ORACLE_SANITIZE=1 selects an AddressSanitizer + UndefinedBehaviorSanitizer
+# build (liboracle_gs_san.so); the process must then preload the sanitizer
+# runtimes (oracle/run_sanitized_tests.sh does).
+SANITIZE = os.environ.get("GS_ORACLE_SANITIZE", "") not in ("", "0")
+LIB_PATH = os.path.join(_HERE, "liboracle_gs_san.so" if SANITIZE else "liboracle_gs.so")
+SANITIZE_FLAGS = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"]
 
 CONVERGED = 1
 STATIONARY = 2
@@ -41,16 +47,20 @@ class OracleError(RuntimeError):
         self.code = code
 
 
-def build() -> str:
-    """Compile the oracle with gcc (binary64 SSE2 arithmetic, no contraction)."""
+def build(sanitize: bool | None = None) -> str:
+    """Compile the oracle with gcc (binary64 SSE2 arithmetic, no contraction);
+    with sanitize (default: GS_ORACLE_SANITIZE) the ASan + UBSan build."""
+    san = SANITIZE if sanitize is None else sanitize
+    path = os.path.join(_HERE, "liboracle_gs_san.so" if san else "liboracle_gs.so")
     cmd = [
         "gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
         "-fno-strict-aliasing", "-shared", "-fPIC", "-Wall", "-Wextra",
-        "-o", LIB_PATH + ".tmp", _SRC, "-lm",
+        *(SANITIZE_FLAGS if san else []),
+        "-o", path + ".tmp", _SRC, "-lm",
     ]
     subprocess.run(cmd, check=True)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+    os.replace(path + ".tmp", path)
+    return path
 
 
 _lib = None
