@@ -64,21 +64,81 @@ def _profile_values(name: str):
     return kv
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, workload: str = "plain_1080p_d5"):
     """HBM bytes per launch of `kernel` from the FETCH_SIZE / WRITE_SIZE summary
-    (profiles/<kernel>_traffic_plain_1080p_d5.txt), or None."""
-    kv = _profile_values(f"{kernel}_traffic_plain_1080p_d5.txt")
+    profiles/<kernel>_traffic_<workload>.txt, or None."""
+    kv = _profile_values(f"{kernel}_traffic_{workload}.txt")
     return None if kv is None else float(kv["traffic_bytes_per_launch"])
 
 
-def measured_counters(kernel: str):
+def measured_counters(kernel: str, workload: str = "plain_1080p_d5"):
     """LDS and L2-atomic counters per launch of `kernel` from the summary
-    profiles/lds_atomic_counters_plain_1080p_d5.txt, or None."""
-    kv = _profile_values("lds_atomic_counters_plain_1080p_d5.txt")
+    profiles/lds_atomic_counters_<workload>.txt, or None."""
+    kv = _profile_values(f"lds_atomic_counters_{workload}.txt")
     if kv is None or f"{kernel}.lds_insts" not in kv:
         return None
     fields = ("lds_insts", "lds_active_cycles", "lds_bank_conflict_cycles", "lds_conflict_ratio", "l2_atomics")
     return {f: float(kv[f"{kernel}.{f}"]) for f in fields}
+
+
+def host_cores() -> int:
+    """Host threads the instance-parallel oracle runs use: the CPUs this
+    process may run on, at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def form_roofline(ctx, run, reps: int, workload: str) -> dict:
+    """Every kernel of `reps` untimed runs of a form timed with HIP events on
+    its launch stream; the roofline object of the one with the largest total
+    time (its algorithmic bytes per launch over its average launch time)."""
+    import torch
+
+    ctx.profile("")
+    ctx.profile_reset()
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    table = ctx.profile_table()
+    ctx.profile(None)
+    dom = max(table, key=lambda k: table[k]["ms"])
+    e = table[dom]
+    avg_ms = e["ms"] / e["launches"]
+    bpl = e["bytes"] / e["launches"]
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
+    return {
+        "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(dom, workload),
+        "counters": measured_counters(dom, workload), "avg_launch_us": avg_ms * 1e3,
+        "alg_bytes_per_launch": bpl, "launches_per_step": e["launches"] / reps,
+        "kernels_ms_per_step": {k: v["ms"] / reps for k, v in sorted(table.items(), key=lambda t: -t[1]["ms"])},
+    }
+
+
+def oracle_instances(xs, hs, max_iter: int, cores: int, seconds: float):
+    """The FP64 oracle on independent instances, one host thread per core
+    (the oracle itself is single-threaded C; ctypes releases the GIL around
+    it).  Runs instances in order until `seconds` have passed; returns
+    (instances done, points done, wall seconds)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import gs_oracle
+
+    gs_oracle.ensure_loaded()
+    done = pts = 0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as pool:
+        i = 0
+        while i < len(xs) and (time.perf_counter() - t0) < seconds:
+            chunk = list(range(i, min(len(xs), i + cores)))
+            list(pool.map(lambda j: gs_oracle.fit(xs[j], float(hs[j]), max_iter), chunk))
+            done += len(chunk)
+            pts += sum(len(xs[j]) for j in chunk)
+            i += len(chunk)
+    return done, pts, time.perf_counter() - t0
 
 
 def cpu_model() -> str:
@@ -123,9 +183,12 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip every oracle timing (the headline baseline and those of the forms)")
+    ap.add_argument("--form-cpu-seconds", type=float, default=8.0,
+                    help="bound of each form's oracle timing (instances are started until it has passed)")
     ap.add_argument("--forms", default="plain,batched,fwd_bwd,gmm,sequential,hsweep,track")
-    ap.add_argument("--form-only", choices=["batched", "fwd_bwd", "sequential", "hsweep", "track"], default=None,
+    ap.add_argument("--form-only", choices=["batched", "fwd_bwd", "gmm", "sequential", "hsweep", "track"], default=None,
                     help="time only this form (--steps timed calls after one warm-up) and print its JSON object; "
                          "for profiling a form on its own")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
@@ -147,7 +210,7 @@ def main() -> int:
     torch.cuda.set_device(dev)
     if args.form_only:
         if args.form_only == "batched":
-            res = bench_batched(gridshift.Context(0), dev, args.steps)
+            res = bench_batched(gridshift.Context(0), dev, args.steps, 0.0)
         elif args.form_only == "sequential":
             w = synth.image_xylab_f32()
             res = bench_sequential(torch.from_numpy(w.x).to(dev), w, args.steps)
@@ -155,8 +218,10 @@ def main() -> int:
             res = bench_hsweep(dev, args.steps)
         elif args.form_only == "track":
             res = bench_track(dev, args.steps)
+        elif args.form_only == "gmm":
+            res = bench_gmm(dev, args.steps, 0.0)
         else:
-            res = bench_fwd_bwd(dev, args.steps)
+            res = bench_fwd_bwd(dev, args.steps, 0.0)
         print(json.dumps(res), flush=True)
         return 0
     if args.calibration_copy_mb > 0:
@@ -249,18 +314,20 @@ def main() -> int:
     }
     out["forms"] = {"plain": {"value": value, "unit": "points/s", "ms_per_step": ms_per_step,
                               "hbm_GBps_alg": out["hbm_GBps_step_alg"]}}
+    cpu_s = 0.0 if args.no_cpu_baseline else args.form_cpu_seconds
+    out["forms"]["plain"]["result_api"] = bench_result_api(x, w, args.steps, ms_per_step)
     if "batched" in forms:
-        out["forms"]["batched"] = bench_batched(ctx, dev, max(1, args.steps // 10))
+        out["forms"]["batched"] = bench_batched(ctx, dev, max(1, args.steps // 10), cpu_s)
     if "sequential" in forms:
         out["forms"]["sequential"] = bench_sequential(x, w, max(1, args.steps // 2))
     if "gmm" in forms:
-        out["forms"]["gmm"] = bench_gmm(dev, max(1, args.steps // 4))
+        out["forms"]["gmm"] = bench_gmm(dev, max(1, args.steps // 4), cpu_s)
     if "hsweep" in forms:
         out["forms"]["hsweep"] = bench_hsweep(dev, max(1, args.steps // 4))
     if "track" in forms:
         out["forms"]["track"] = bench_track(dev, max(1, args.steps // 10))
     if "fwd_bwd" in forms:
-        out["forms"]["fwd_bwd"] = bench_fwd_bwd(dev, max(1, args.steps // 10))
+        out["forms"]["fwd_bwd"] = bench_fwd_bwd(dev, max(1, args.steps // 10), cpu_s)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -381,7 +448,11 @@ def bench_track(dev, steps: int) -> dict:
     return out
 
 
-def bench_gmm(dev, steps: int) -> dict:
+def bench_gmm(dev, steps: int, cpu_seconds: float) -> dict:
+    """Gaussian mixtures of 1e7 float32 points, d = 2..6: the 3^d neighbour
+    probes of the device-wide rounds, as probes/s of the shift kernel, and
+    the dominant kernel per d."""
+    import numpy as np
     import torch
 
     from paper_2206_02200_amd import gridshift, synth
@@ -394,12 +465,6 @@ def bench_gmm(dev, steps: int) -> dict:
         n = w.x.shape[0]
         r = gridshift.fit(x, w.h, w.max_iter, ctx=ctx)  # warm-up (allocations)
         torch.cuda.synchronize()
-        ctx.profile("shift")
-        ctx.profile_reset()
-        gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
-        torch.cuda.synchronize()
-        sh = ctx.profile_table().get("shift", {"ms": 0.0, "launches": 0})
-        ctx.profile(None)
         t0 = time.perf_counter()
         for _ in range(steps):
             r = gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
@@ -408,13 +473,42 @@ def bench_gmm(dev, steps: int) -> dict:
         info = r.info
         m0, k = info["n_cells0"], info["n_clusters"]
         b_alg = n * (d * 4 + 12) + 2 * m0 * (16 + 8 * d) + k * (8 * d + 8)
-        res[f"d{d}"] = {
+        roof = form_roofline(ctx, lambda: gridshift.fit(x, w.h, w.max_iter, ctx=ctx), 2, f"gmm_1e7_d{d}")
+        sh_ms = roof["kernels_ms_per_step"].get("shift", 0.0)
+        # the shift's algorithmic bytes are (28 + 16d) per cell of its round:
+        # the cells it moved, each probing its 3^d neighbour keys
+        ctx.profile("shift")
+        ctx.profile_reset()
+        gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
+        torch.cuda.synchronize()
+        sh = ctx.profile_table().get("shift", {"ms": 0.0, "launches": 0, "bytes": 0.0})
+        ctx.profile(None)
+        shift_cells = sh["bytes"] / (28.0 + 16.0 * d)
+        probes = shift_cells * 3 ** d
+        ent = {
             "value": n / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "steps": steps,
             "hbm_GBps_alg": b_alg / (ms * 1e-3) / 1e9, "cells0": m0, "clusters": k, "rounds": info["n_iter"],
-            "shift_ms_per_fit": sh["ms"], "shift_launches": sh["launches"],
-            # every cell of a device-wide round probes its 3^d neighbour keys
-            "first_round_probes": m0 * 3 ** d,
+            "shift_ms_per_fit": sh["ms"], "shift_launches": sh["launches"], "shift_cells": shift_cells,
+            "neighbour_probes": probes, "probes_per_s": probes / (sh["ms"] * 1e-3) if sh["ms"] > 0 else None,
+            "shift_ms_per_fit_profiled_run": sh_ms, "roofline": roof,
         }
+        if cpu_seconds > 0:
+            # the oracle (one thread) on a prefix of the same i.i.d. points
+            from oracle import gs_oracle
+
+            npre = 1_000_000
+            xs = w.x[:npre].astype(np.float64)
+            runs, t0 = 0, time.perf_counter()
+            while True:
+                gs_oracle.fit(xs, w.h, w.max_iter)
+                runs += 1
+                if time.perf_counter() - t0 >= cpu_seconds / 5:
+                    break
+            el = time.perf_counter() - t0
+            ent["cpu_baseline"] = {"value": runs * npre / el, "unit": "points/s", "cores": 1, "kind": "oracle",
+                                   "sample": f"{runs} fits of the first {npre} points of the same mixture "
+                                             f"in {el:.1f} s (single thread)"}
+        res[f"d{d}"] = ent
         del x
     ctx.close()
     res["workload"] = ("Gaussian mixture, 50 isotropic components, means U[0,100]^d, sigma U[1,3], "
@@ -422,7 +516,7 @@ def bench_gmm(dev, steps: int) -> dict:
     return res
 
 
-def bench_batched(ctx, dev, steps: int) -> dict:
+def bench_batched(ctx, dev, steps: int, cpu_seconds: float) -> dict:
     import numpy as np
     import torch
 
@@ -449,7 +543,7 @@ def bench_batched(ctx, dev, steps: int) -> dict:
     cells0 = sum(i["n_cells0"] for i in r.infos)
     k = int(r.k_offsets[-1])
     b_alg = n * (3 * 4 + 12) + 2 * cells0 * (16 + 8 * 3) + k * (8 * 3 + 8)
-    return {
+    out = {
         "value": n / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "steps": steps,
         "workload": "256 Voronoi images, H 240..1080, W 320..1920, 5..60 regions, sigma 4..12, RGB f32, "
                     "h in {12,16,24}, max_iter=100, one batched call, launch configuration autotuned on the batch",
@@ -457,10 +551,22 @@ def bench_batched(ctx, dev, steps: int) -> dict:
         "rounds_mean": float(np.mean(rounds)), "capped": int(sum(1 for i in r.infos if i["flags"] & 4)),
         "hbm_GBps_alg": b_alg / (ms * 1e-3) / 1e9,
         "launch_config": cfg, "autotune_s": t_tune,
+        "roofline": form_roofline(ctx, lambda: gridshift.fit_batched(X, off, hs, 100, ctx=ctx), 1,
+                                  "batched_256_images"),
     }
+    if cpu_seconds > 0:
+        # the oracle on the same bytes, instance-parallel over the host cores
+        Xh = X.cpu().numpy()
+        xs = [Xh[off[b]:off[b + 1]] for b in range(len(specs))]
+        cores = host_cores()
+        done, pts, el = oracle_instances(xs, hs, 100, cores, cpu_seconds)
+        out["cpu_baseline"] = {"value": pts / el, "unit": "points/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{done} of the {len(specs)} images ({pts} points) in {el:.1f} s, "
+                                         f"one image per thread on {cores} threads ({cpu_model()})"}
+    return out
 
 
-def bench_fwd_bwd(dev, steps: int) -> dict:
+def bench_fwd_bwd(dev, steps: int, cpu_seconds: float) -> dict:
     import torch
 
     from paper_2206_02200_amd import gridshift, synth
@@ -491,9 +597,58 @@ def bench_fwd_bwd(dev, steps: int) -> dict:
         "workload": "64 Voronoi images 512x512, 30 regions, ramps, sigma 6, (x,y,L,a,b) f32, h=16, "
                     "point-to-mode loss forward + backward (tail checkpoints every 8 rounds, recomputed in the backward)",
         "n": n, "B": B, "loss_mean": float(loss.detach().mean()), "hbm_GBps_alg": b_alg / (ms * 1e-3) / 1e9,
+        "roofline": form_roofline(gctx, step, 1, "fwd_bwd_64x512"),
     }
+    if cpu_seconds > 0:
+        # the oracle's loss and gradient (fit with the trajectory, the loss, the
+        # adjoint), instance-parallel over the host cores
+        from concurrent.futures import ThreadPoolExecutor
+
+        from oracle import gs_oracle
+
+        Xh = X.cpu().numpy()
+        cores = host_cores()
+        gs_oracle.ensure_loaded()
+        done = pts = 0
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=cores) as pool:
+            while done < B and time.perf_counter() - t0 < cpu_seconds:
+                chunk = list(range(done, min(B, done + cores)))
+                list(pool.map(lambda j: gs_oracle.loss_and_grad(Xh[off[j]:off[j + 1]], 16.0, 100), chunk))
+                done += len(chunk)
+                pts += sum(int(off[j + 1] - off[j]) for j in chunk)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": pts / el, "unit": "points/s", "cores": cores, "kind": "oracle",
+                               "sample": f"loss + gradient of {done} of the {B} images ({pts} points) in "
+                                         f"{el:.1f} s, one image per thread on {cores} threads ({cpu_model()})"}
     gctx.close()
     return out
+
+
+def bench_result_api(x, w, steps: int, ctx_ms: float) -> dict:
+    """The boundary call itself: gs_fit with torch's caching allocator (a new
+    result per fit), the mode copy and gs_result_free, per step, beside the
+    same fit on a kept context."""
+    import torch
+
+    from paper_2206_02200_amd import gridshift
+
+    def step():
+        r = gridshift.fit_result(x, w.h, w.max_iter, allocator="torch")
+        r.copy()
+        r.close()
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"ms_per_step": ms, "value": x.shape[0] / (ms * 1e-3), "unit": "points/s", "steps": steps,
+            "vs_context_fit": ms / ctx_ms,
+            "workload": "the plain workload through gs_fit + gs_result_copy + gs_result_free, device memory "
+                        "from torch's caching allocator"}
 
 
 if __name__ == "__main__":

@@ -89,9 +89,10 @@ static int cmp_keyvec(const int64_t* a, const int64_t* b, int d)
     return 0;
 }
 
-/* qsort context: the oracle is single-threaded and not re-entrant. */
-static const int64_t* g_sort_keys;
-static int g_sort_d;
+/* qsort context, one per host thread: each call is single-threaded, and
+ * independent calls may run on different threads at once. */
+static _Thread_local const int64_t* g_sort_keys;
+static _Thread_local int g_sort_d;
 
 /* Order row indices by (key vector, index): a stable grouping by key. */
 static int cmp_rows_by_key_then_index(const void* A, const void* B)

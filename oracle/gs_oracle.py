@@ -127,6 +127,12 @@ def _load():
     return lib
 
 
+def ensure_loaded() -> None:
+    """Load (building if needed) the oracle library now, e.g. before several
+    host threads start calling it."""
+    _load()
+
+
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 

@@ -783,6 +783,16 @@ gs::TailCkpt ckpt_view(gs_context* c, int ns, int B, int every) {
     return ck;
 }
 
+// Algorithmic bytes of a tail launch (known once its states are back): every
+// shift+merge round reads and writes its cell table (key, count and d sums:
+// 16 + 8d bytes a cell), the exit test reads the final table once more, and
+// the map of the M entering cells is written once.
+double tail_alg_bytes(const gs_context* c, int B, int d, int64_t M) {
+    double cells = 0.0;
+    for (int b = 0; b < B; ++b) cells += 2.0 * double(c->st[b].tail_cells) + double(c->st[b].K);
+    return cells * (16.0 + 8.0 * d) + 4.0 * double(M);
+}
+
 template <typename T, typename K>
 gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const int64_t* offsets, int max_iter,
                     int bits, int32_t* labels, hipStream_t s) {
@@ -1097,11 +1107,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         for (int b = 0; b < B; ++b)
             if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");
         if (!gate) {
-            // the tail read the merged table (M cells) and wrote the final one
-            // and the entry map; the launch could only bound M from above
-            int64_t kfin = 0;
-            for (int b = 0; b < B; ++b) kfin += c->st[b].K;
-            prof_set_bytes(c, c->tail_tok, double(M + kfin) * (16.0 + 8.0 * d) + 4.0 * double(M));
+            prof_set_bytes(c, c->tail_tok, tail_alg_bytes(c, B, d, M));
             tail_done = true;
             break;
         }
@@ -1115,9 +1121,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         } else {
             GS_TRY(d2h(c, c->st.data(), st, sizeof(gs::InstState) * B, s));
         }
-        int64_t kfin = 0;
-        for (int b = 0; b < B; ++b) kfin += c->st[b].K;
-        prof_set_bytes(c, c->tail_tok, double(M + kfin) * (16.0 + 8.0 * d) + 4.0 * double(M));
+        prof_set_bytes(c, c->tail_tok, tail_alg_bytes(c, B, d, M));
     }
     for (int b = 0; b < B; ++b) {
         if (c->st[b].err) return fail(GS_ERR_KEY_RANGE, "a moved cell left its instance's key box");

@@ -39,6 +39,7 @@ struct InstState {
     int64_t cs, ce;   // cell range [cs, ce) in the current cell table
     int64_t K;        // clusters at exit
     int64_t m0;       // cells after binning
+    int64_t tail_cells;  // sum over the tail's shift+merge rounds of the table size entering each
 };
 // the shift reads any_nb and changed with one 64-bit load
 static_assert(offsetof(InstState, any_nb) % 8 == 0 && offsetof(InstState, changed) == offsetof(InstState, any_nb) + 4,

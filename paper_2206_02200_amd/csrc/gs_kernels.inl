@@ -1542,6 +1542,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
     __syncthreads();
 
     int m = m_entry;
+    int64_t msum = 0;  // table sizes of the rounds run here (thread 0)
     int tt = replay ? S->t_tail0 + replay_r0 : S->t;
     const int t_entry = tt;
     if (tid == 0 && !replay) S->t_tail0 = t_entry;
@@ -1707,6 +1708,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
             err = 3;
             break;
         }
+        msum += m;
         // ---- landing keys (read by the linear rank only)
         if (!fast_rank) {
             if (tid < m) kap[tid] = kj;
@@ -1868,6 +1870,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         S->flags = flags;
         S->K = m;
         S->active = 0;
+        S->tail_cells = msum;
     }
 }
 

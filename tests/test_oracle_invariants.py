@@ -182,3 +182,20 @@ def test_far_apart_cells_are_not_neighbours(oracle):
     x = np.array([[0.5, 0.5], [0.5, 2.0**32 + 0.5], [1.5, 2.0**32 + 1.5]])
     r = oracle.fit(x, 1.0)
     assert (r.K, r.n_iter) == (2, 1) and r.labels.tolist() == [0, 1, 1]
+
+
+def test_independent_calls_on_several_threads_match_sequential(oracle):
+    # the benchmark runs the oracle one instance per host thread: calls must
+    # not share state (bitwise the same results as one after another)
+    from concurrent.futures import ThreadPoolExecutor
+
+    rng = np.random.default_rng(11)
+    xs = [rng.uniform(0, 200, size=(int(rng.integers(500, 20000)), 3)) for _ in range(16)]
+    seq = [oracle.fit(x, 12.0, 100) for x in xs]
+    oracle.ensure_loaded()
+    with ThreadPoolExecutor(8) as pool:
+        par = list(pool.map(lambda x: oracle.fit(x, 12.0, 100), xs))
+    for a, b in zip(seq, par):
+        assert (a.K, a.n_iter, a.flags) == (b.K, b.n_iter, b.flags)
+        np.testing.assert_array_equal(a.labels, b.labels)
+        np.testing.assert_array_equal(a.sums.view(np.uint64), b.sums.view(np.uint64))
