@@ -119,7 +119,8 @@ typedef struct gs_result gs_result;
 /*
  * Plain fit of one point set (Section 2.1, Algorithm 1; the update of Eq. 6),
  * with every piece of scratch and the trajectory taken from `a` (NULL:
- * hipMalloc).  labels device int32 [n] receives the cluster of every point
+ * hipMalloc; with an allocator, in a few large chunks, each at least as
+ * large as all before it, asked for the fit's stream).  labels device int32 [n] receives the cluster of every point
  * (0..K-1, ascending final key); *out the result, owned by the caller and
  * released with gs_result_free.  The stream is synchronised once before the
  * call returns (K and the flags are host-visible).  On error *out is NULL.
@@ -159,8 +160,13 @@ gs_status gs_point_mode_loss(const gs_result* r, const void* points, double* los
 gs_status gs_point_mode_loss_backward(const gs_result* r, const void* points, const double* grad_loss,
                                       double* grad_points, void* stream);
 
-/* Release a result: waits for the stream its fit ran on (which must still
- * exist), then returns its memory to its allocator.  NULL is a no-op. */
+/* Release a result without waiting on the host: the stream its fit ran on
+ * (which must still exist) first waits for every other stream a result call
+ * used, then the result's device memory goes back to its allocator for that
+ * stream (a stream-ordered caching allocator hands it out again only to work
+ * queued after it; memory from hipMalloc goes back with hipFree, which waits
+ * for the device).  A result call on another stream than the fit's first
+ * makes that stream wait for the fit's.  NULL is a no-op. */
 void gs_result_free(gs_result* r);
 
 /*

@@ -32,6 +32,20 @@ struct DBuf {
     size_t cap = 0;
     const gs_allocator* al = nullptr;  // the caller's allocator that gave p (null: hipMalloc)
     void* st = nullptr;                // and the stream it was given for
+    bool arena = false;                // carved from an arena chunk (given back with the arena)
+};
+
+// Device memory of a result: a few large chunks from the caller's allocator,
+// each new one at least as large as all before it, carved in order; nothing
+// is given back before the result is released (then every chunk at once).
+struct Arena {
+    struct Chunk {
+        char* p;
+        size_t cap, used;
+        void* stream;  // the stream it was allocated for
+    };
+    std::vector<Chunk> chunks;
+    size_t total = 0;
 };
 
 // Device memory of a call on a context with a caller allocator comes from
@@ -39,9 +53,30 @@ struct DBuf {
 // during the call records where its memory came from.
 thread_local const gs_allocator* t_alloc = nullptr;
 thread_local void* t_alloc_stream = nullptr;
+thread_local Arena* t_arena = nullptr;
+
+constexpr size_t kArenaMinChunk = size_t(32) << 20;
+
+void* arena_get(Arena& a, size_t bytes) {
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (!a.chunks.empty()) {
+        Arena::Chunk& c = a.chunks.back();
+        if (c.cap - c.used >= need) {
+            void* p = c.p + c.used;
+            c.used += need;
+            return p;
+        }
+    }
+    const size_t want = std::max(need, std::max(kArenaMinChunk, a.total));
+    void* p = t_alloc->alloc(t_alloc->ctx, want, t_alloc_stream);
+    if (!p) return nullptr;
+    a.chunks.push_back({static_cast<char*>(p), want, need, t_alloc_stream});
+    a.total += want;
+    return p;
+}
 
 void dbuf_release(DBuf& b) {
-    if (b.p) {
+    if (b.p && !b.arena) {
         if (b.al)
             b.al->free(b.al->ctx, b.p, b.st);
         else
@@ -51,10 +86,23 @@ void dbuf_release(DBuf& b) {
     b.cap = 0;
     b.al = nullptr;
     b.st = nullptr;
+    b.arena = false;
 }
 
 gs_status dbuf_get(DBuf& b, size_t want) {
     void* p = nullptr;
+    if (t_alloc && t_arena) {
+        p = arena_get(*t_arena, want);
+        if (!p)
+            return fail(GS_ERR_ALLOC, "the caller's allocator returned NULL (" + std::to_string(want) +
+                                          " more bytes of device memory wanted)");
+        b.p = p;
+        b.cap = want;
+        b.al = nullptr;
+        b.st = nullptr;
+        b.arena = true;
+        return GS_OK;
+    }
     if (t_alloc) {
         p = t_alloc->alloc(t_alloc->ctx, want, t_alloc_stream);
         if (!p) return fail(GS_ERR_ALLOC, "the caller's allocator returned NULL for " + std::to_string(want) + " bytes");
@@ -102,6 +150,11 @@ struct gs_context {
     int rule = GS_UPDATE_PARALLEL;  // update rule of the shift (gs_context_set_update)
     gs_allocator alloc{};           // the caller's device allocator (has_alloc), else hipMalloc
     bool has_alloc = false;
+    bool use_arena = false;         // with has_alloc: buffers carved from `arena` (results)
+    Arena arena;
+    bool stage_pooled = false;      // the host staging below returns to the per-device pool
+    void* own_stream = nullptr;     // with has_alloc: allocate for this stream whatever the call's stream
+    bool has_own_stream = false;
     int tail_tok = -1;              // profiling record of the last tail launch
     DBuf seq_moved, seq_waiting;    // sequential form: step stamps per cell, waiting flags per step
     uint32_t seq_epoch = 0;
@@ -184,13 +237,16 @@ struct gs_context {
 struct AllocScope {
     const gs_allocator* pa;
     void* ps;
-    AllocScope(const gs_context* c, void* stream) : pa(t_alloc), ps(t_alloc_stream) {
+    Arena* pr;
+    AllocScope(gs_context* c, void* stream) : pa(t_alloc), ps(t_alloc_stream), pr(t_arena) {
         t_alloc = c && c->has_alloc ? &c->alloc : nullptr;
-        t_alloc_stream = c && c->has_alloc ? stream : nullptr;
+        t_alloc_stream = c && c->has_alloc ? (c->has_own_stream ? c->own_stream : stream) : nullptr;
+        t_arena = c && c->has_alloc && c->use_arena ? &c->arena : nullptr;
     }
     ~AllocScope() {
         t_alloc = pa;
         t_alloc_stream = ps;
+        t_arena = pr;
     }
 };
 
@@ -1573,6 +1629,89 @@ static gs_status loss_bwd(gs_context* c, const T* x, const int32_t* labels, cons
 
 }  // namespace
 
+namespace {
+
+// Host staging of results (pinned download and upload areas, the mapped
+// block kernels publish into), kept per device across results: a result takes
+// a set when it is created and gives it back when it is released, behind an
+// event on the stream of its last upload (its staged bytes stay untouched
+// until that copy has run).
+struct HostStage {
+    int device;
+    void* pinned;
+    size_t pinned_cap;
+    char* up;
+    size_t up_cap;
+    int64_t* hmap;
+    int64_t* hmap_dev;
+    size_t hmap_cap;
+    hipEvent_t done;  // recorded on release when an upload may still be in flight (else null)
+};
+std::mutex g_stage_mu;
+std::vector<HostStage> g_stage_pool;
+constexpr size_t kStagePoolMax = 16;
+
+void stage_acquire(gs_context* c) {
+    HostStage h{};
+    bool found = false;
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        for (size_t i = g_stage_pool.size(); i-- > 0;) {
+            if (g_stage_pool[i].device == c->device) {
+                h = g_stage_pool[i];
+                g_stage_pool.erase(g_stage_pool.begin() + i);
+                found = true;
+                break;
+            }
+        }
+    }
+    c->stage_pooled = true;
+    if (!found) return;  // the context allocates its staging on first use
+    if (h.done) {
+        (void)hipEventSynchronize(h.done);
+        (void)hipEventDestroy(h.done);
+    }
+    c->pinned = h.pinned;
+    c->pinned_cap = h.pinned_cap;
+    c->up = h.up;
+    c->up_cap = h.up_cap;
+    c->hmap = h.hmap;
+    c->hmap_dev = h.hmap_dev;
+    c->hmap_cap = h.hmap_cap;
+}
+
+void stage_release(gs_context* c) {
+    HostStage h{c->device, c->pinned, c->pinned_cap, c->up, c->up_cap, c->hmap, c->hmap_dev, c->hmap_cap, nullptr};
+    if (c->up_used > 0 && hipEventCreateWithFlags(&h.done, hipEventDisableTiming) == hipSuccess &&
+        hipEventRecord(h.done, c->up_stream) != hipSuccess) {
+        (void)hipEventDestroy(h.done);
+        h.done = nullptr;
+        (void)hipStreamSynchronize(c->up_stream);
+    }
+    c->pinned = nullptr;
+    c->up = nullptr;
+    c->hmap = nullptr;
+    c->hmap_dev = nullptr;
+    c->pinned_cap = c->up_cap = c->hmap_cap = c->up_used = 0;
+    if (!h.pinned && !h.up && !h.hmap) return;
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        if (g_stage_pool.size() < kStagePoolMax) {
+            g_stage_pool.push_back(h);
+            return;
+        }
+    }
+    if (h.done) {
+        (void)hipEventSynchronize(h.done);
+        (void)hipEventDestroy(h.done);
+    }
+    if (h.pinned) (void)hipHostFree(h.pinned);
+    if (h.up) (void)hipHostFree(h.up);
+    if (h.hmap) (void)hipHostFree(h.hmap);
+}
+
+}  // namespace
+
 extern "C" {
 
 int32_t gs_abi_version(void) { return GS_ABI_VERSION; }
@@ -1594,6 +1733,13 @@ gs_status gs_context_create(gs_context** out) {
 void gs_context_destroy(gs_context* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    if (c->aux) {  // the second stream's work (checkpoint replays) ends first
+        (void)hipStreamSynchronize(c->aux);
+        (void)hipStreamDestroy(c->aux);
+        hipEvent_t evs[] = {c->ev_start, c->ev_rep[0], c->ev_rep[1], c->ev_adj[0], c->ev_adj[1]};
+        for (hipEvent_t e : evs)
+            if (e) (void)hipEventDestroy(e);
+    }
     DBuf* all[] = {&c->kA, &c->kB, &c->vA, &c->vB, &c->cell0, &c->kappa, &c->pbuf, &c->gmap, &c->cur, &c->tmap,
                    &c->part, &c->partc, &c->hk, &c->hv, &c->ckA, &c->ckB, &c->cvA, &c->cvB, &c->ctl,
                    &c->look, &c->tilectr, &c->shist,
@@ -1604,18 +1750,6 @@ void gs_context_destroy(gs_context* c) {
                       &c->tlen[i], &c->tfirst[i], &c->tnch[i], &c->tchoff[i]};
         for (DBuf* b : tb) dbuf_release(*b);
     }
-    if (c->up_used > 0) (void)hipStreamSynchronize(c->up_stream);
-    if (c->pinned) (void)hipHostFree(c->pinned);
-    if (c->up) (void)hipHostFree(c->up);
-    if (c->hmap) (void)hipHostFree(c->hmap);
-    for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
-    if (c->aux) {
-        (void)hipStreamSynchronize(c->aux);
-        (void)hipStreamDestroy(c->aux);
-        hipEvent_t evs[] = {c->ev_start, c->ev_rep[0], c->ev_rep[1], c->ev_adj[0], c->ev_adj[1]};
-        for (hipEvent_t e : evs)
-            if (e) (void)hipEventDestroy(e);
-    }
     DBuf* tb2[] = {&c->sums0, &c->inst0, &c->wt_key, &c->wt_cnt, &c->wt_inst, &c->wt_W, &c->wt_g, &c->wt_app,
                    &c->tt_key, &c->tt_cnt, &c->tt_W, &c->tt_g, &c->tt_m, &c->sbA, &c->sbB, &c->qbuf, &c->gmodes,
                    &c->modes_i, &c->counts_i, &c->frows, &c->lossc, &c->ltab, &c->xkA, &c->xkB, &c->xvA, &c->xvB,
@@ -1623,6 +1757,18 @@ void gs_context_destroy(gs_context* c) {
                    &c->trk_win, &c->trk_lab, &c->trk_cnt, &c->trk_sel, &c->trk_out, &c->trk_rect, &c->trk_init,
                    &c->seq_moved, &c->seq_waiting};
     for (DBuf* b : tb2) dbuf_release(*b);
+    // arena chunks go back on the stream each was allocated for
+    for (const Arena::Chunk& ch : c->arena.chunks) c->alloc.free(c->alloc.ctx, ch.p, ch.stream);
+    c->arena.chunks.clear();
+    if (c->stage_pooled) {
+        stage_release(c);
+    } else {
+        if (c->up_used > 0) (void)hipStreamSynchronize(c->up_stream);
+        if (c->pinned) (void)hipHostFree(c->pinned);
+        if (c->up) (void)hipHostFree(c->up);
+        if (c->hmap) (void)hipHostFree(c->hmap);
+    }
+    for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -2022,9 +2168,42 @@ struct gs_result {
     const int32_t* labels = nullptr;  // the caller's labels of the fit (for the loss)
     std::vector<gs_info> info;
     std::vector<int64_t> koff;
+    // Calls on another stream than the fit's: that stream first waits for the
+    // fit stream (memory the result allocates is handed out for the fit
+    // stream), and an event recorded after the call lets the release wait
+    // for it.
+    mutable hipEvent_t fit_ev = nullptr;
+    mutable std::vector<std::pair<void*, hipEvent_t>> side;
 };
 
 namespace {
+
+gs_status side_begin(const gs_result* r, void* stream) {
+    if (stream == r->stream) return GS_OK;
+    GS_HIP(hipSetDevice(r->ctx->device));
+    if (!r->fit_ev) GS_HIP(hipEventCreateWithFlags(&r->fit_ev, hipEventDisableTiming));
+    GS_HIP(hipEventRecord(r->fit_ev, static_cast<hipStream_t>(r->stream)));
+    GS_HIP(hipStreamWaitEvent(static_cast<hipStream_t>(stream), r->fit_ev, 0));
+    return GS_OK;
+}
+
+// After a call on `stream` (whatever its status: kernels may have been queued).
+gs_status side_end(const gs_result* r, void* stream, gs_status rc) {
+    if (stream == r->stream) return rc;
+    hipEvent_t ev = nullptr;
+    for (auto& pr : r->side)
+        if (pr.first == stream) ev = pr.second;
+    if (!ev) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+            return rc;
+        }
+        r->side.emplace_back(stream, ev);
+    }
+    if (hipEventRecord(ev, static_cast<hipStream_t>(stream)) != hipSuccess)
+        (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    return rc;
+}
 
 gs_status result_fit(const void* points, gs_dtype dtype, int32_t d, int64_t ld, int32_t B, const int64_t* offsets,
                      const double* h, int32_t max_iter, int32_t ckpt_every, const gs_allocator* a, void* stream,
@@ -2038,7 +2217,11 @@ gs_status result_fit(const void* points, gs_dtype dtype, int32_t d, int64_t ld, 
     if (a) {
         c->alloc = *a;
         c->has_alloc = true;
+        c->use_arena = true;
+        c->own_stream = stream;
+        c->has_own_stream = true;
     }
+    stage_acquire(c);
     gs_result* r = new (std::nothrow) gs_result();
     if (!r) {
         gs_context_destroy(c);
@@ -2096,32 +2279,46 @@ gs_status gs_result_offsets(const gs_result* r, int64_t* k_offsets) {
 
 gs_status gs_result_copy(const gs_result* r, double* modes, int64_t* counts, void* stream) {
     if (!r) return fail(GS_ERR_INVALID_ARG, "null result");
-    return gs_copy_modes(r->ctx, modes, counts, nullptr, stream);
+    GS_TRY(side_begin(r, stream));
+    return side_end(r, stream, gs_copy_modes(r->ctx, modes, counts, nullptr, stream));
 }
 
 gs_status gs_backward(const gs_result* r, const double* grad_modes, double* grad_points, void* stream) {
     if (!r) return fail(GS_ERR_INVALID_ARG, "null result");
-    return gs_ctx_backward(r->ctx, grad_modes, grad_points, stream);
+    GS_TRY(side_begin(r, stream));
+    return side_end(r, stream, gs_ctx_backward(r->ctx, grad_modes, grad_points, stream));
 }
 
 gs_status gs_point_mode_loss(const gs_result* r, const void* points, double* loss, void* stream) {
     if (!r) return fail(GS_ERR_INVALID_ARG, "null result");
-    return gs_ctx_point_mode_loss(r->ctx, points, r->labels, loss, stream);
+    GS_TRY(side_begin(r, stream));
+    return side_end(r, stream, gs_ctx_point_mode_loss(r->ctx, points, r->labels, loss, stream));
 }
 
 gs_status gs_point_mode_loss_backward(const gs_result* r, const void* points, const double* grad_loss,
                                       double* grad_points, void* stream) {
     if (!r) return fail(GS_ERR_INVALID_ARG, "null result");
-    return gs_ctx_point_mode_loss_backward(r->ctx, points, r->labels, grad_loss, grad_points, stream);
+    GS_TRY(side_begin(r, stream));
+    return side_end(r, stream,
+                    gs_ctx_point_mode_loss_backward(r->ctx, points, r->labels, grad_loss, grad_points, stream));
 }
 
 void gs_result_free(gs_result* r) {
     if (!r) return;
     if (r->ctx) {
-        // stream-ordered: the result's work on its stream ends before its memory goes back
+        // Stream-ordered, without waiting on the host: the fit stream waits
+        // for every other stream a result call used, then the memory goes
+        // back to the caller's allocator for the fit stream (a caching
+        // allocator hands it out again only to work ordered after that), and
+        // the host staging to the per-device pool behind an event.  Memory
+        // from hipMalloc (no allocator) is given back with hipFree, which
+        // waits for the device.
+        hipStream_t s = static_cast<hipStream_t>(r->stream);
         (void)hipSetDevice(r->ctx->device);
-        (void)hipStreamSynchronize(static_cast<hipStream_t>(r->stream));
+        for (auto& pr : r->side) (void)hipStreamWaitEvent(s, pr.second, 0);
         gs_context_destroy(r->ctx);
+        for (auto& pr : r->side) (void)hipEventDestroy(pr.second);
+        if (r->fit_ev) (void)hipEventDestroy(r->fit_ev);
     }
     delete r;
 }

@@ -2,6 +2,7 @@
 ABI, with the device memory taken from torch's caching allocator: bitwise
 the same labels, modes, counts, summaries, adjoint and loss as the context
 calls, every allocation returned on gs_result_free, and the errors."""
+import ctypes
 import sys
 
 import numpy as np
@@ -126,3 +127,76 @@ def test_result_loss_with_column_sliced_points():
         q.loss(view.to(torch.float32))
     r.close()
     q.close()
+
+
+@pytest.mark.parametrize("ckpt", [0, 8])
+def test_allocation_failure_returns_every_allocation(ckpt):
+    # the caller's allocator fails at its k-th call, for every k a clean fit
+    # reaches: gs_fit returns GS_ERR_ALLOC, no result, and every allocation
+    # it made has been given back
+    _say(f"result api allocation failure, ckpt_every={ckpt}")
+    x = torch.from_numpy(_blobs(6400, 30000, 3, k=6, scale=4.0)).to(DEV)
+    lib = gridshift.load_library()
+    st = {"calls": 0, "fail_at": None, "live": set()}
+
+    def alloc(ctx, nbytes, stream):
+        st["calls"] += 1
+        if st["fail_at"] is not None and st["calls"] == st["fail_at"]:
+            return None
+        p = torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        st["live"].add(p)
+        return p
+
+    def free(ctx, p, stream):
+        st["live"].remove(int(p))
+        torch.cuda.caching_allocator_delete(int(p))
+
+    al = gridshift.Allocator(gridshift._ALLOC_FN(alloc), gridshift._FREE_FN(free), None)
+    labels = torch.empty(x.shape[0], dtype=torch.int32, device=DEV)
+    p = gridshift.Problem(x.data_ptr(), gridshift.GS_F64, x.shape[0], 3, 3, 3.0, 100, ckpt)
+    sp = gridshift._stream_ptr(None)
+    out = ctypes.c_void_p()
+    assert lib.gs_fit(ctypes.byref(p), ctypes.byref(al), sp, labels.data_ptr(), ctypes.byref(out)) == 0
+    n_calls = st["calls"]
+    assert n_calls >= 1 and st["live"]
+    lib.gs_result_free(out)
+    assert not st["live"]
+    for k in range(1, n_calls + 1):
+        st.update(calls=0, fail_at=k)
+        out = ctypes.c_void_p()
+        rc = lib.gs_fit(ctypes.byref(p), ctypes.byref(al), sp, labels.data_ptr(), ctypes.byref(out))
+        assert gridshift.STATUS[rc] == "GS_ERR_ALLOC", (k, rc)
+        assert not out.value
+        assert not st["live"], k
+    torch.cuda.synchronize()
+
+
+def test_result_calls_on_another_stream():
+    # copies, loss and adjoint queued on a second stream, then the result
+    # released without waiting: the same bits as on the fit's stream
+    _say("result api, calls on a second stream")
+    x = torch.from_numpy(_blobs(6500, 30000, 5, k=6, scale=4.0)).to(DEV)
+    r = gridshift.fit_result(x, 3.0, 100, ckpt_every=8)
+    modes_a, counts_a = r.copy()
+    gm = torch.from_numpy(np.random.default_rng(2).standard_normal(size=(r.info()["n_clusters"], 5))).to(DEV)
+    grad_a = r.backward(gm)
+    loss_a = r.loss(x)
+    s2 = torch.cuda.Stream()
+    sp2 = ctypes.c_void_p(s2.cuda_stream)
+    lib = gridshift.load_library()
+    with torch.cuda.stream(s2):
+        tot = int(r.offsets()[-1])
+        modes_b = torch.empty((tot, 5), dtype=torch.float64, device=DEV)
+        counts_b = torch.empty(tot, dtype=torch.int64, device=DEV)
+        grad_b = torch.empty((x.shape[0], 5), dtype=torch.float64, device=DEV)
+        loss_b = torch.empty(1, dtype=torch.float64, device=DEV)
+        g2 = gm.clone()
+        assert lib.gs_result_copy(r.handle, modes_b.data_ptr(), counts_b.data_ptr(), sp2) == 0
+        assert lib.gs_backward(r.handle, g2.data_ptr(), grad_b.data_ptr(), sp2) == 0
+        assert lib.gs_point_mode_loss(r.handle, x.data_ptr(), loss_b.data_ptr(), sp2) == 0
+    r.close()
+    s2.synchronize()
+    np.testing.assert_array_equal(_bits(modes_b), _bits(modes_a))
+    np.testing.assert_array_equal(counts_b.cpu().numpy(), counts_a.cpu().numpy())
+    np.testing.assert_array_equal(_bits(grad_b), _bits(grad_a))
+    np.testing.assert_array_equal(_bits(loss_b), _bits(loss_a))
