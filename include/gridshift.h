@@ -255,16 +255,18 @@ gs_status gs_ctx_fit_batched(gs_context* ctx, const void* points, gs_dtype dtype
 /*
  * Bandwidth sweep: the same point set fitted once per bandwidth hs[0..H-1]
  * (the tuning of Section 4.1 scans h over (0,1]), all H fits in one batched
- * pass (gs_fit_batched over H copies of the points).  Results per bandwidth
- * are bitwise those of gs_fit with that h.
+ * pass in which bandwidth j is instance j.  The points are not copied: the
+ * box of the coordinates is reduced once, every staged row is keyed for all
+ * H bandwidths in one read, and the cell sums read each member from the
+ * shared rows.  Results per bandwidth are bitwise those of gs_fit with that h.
  *   points  device, n rows of ld elements of dtype (as gs_fit).
  *   hs      host double [H], each finite and > 0.
  *   labels  device int32 [H][n]: the labels of bandwidth j at j * n.
  *   info    host gs_info [H].
- * The context keeps the H dense copies (H * n * d elements of dtype) in its
- * own device memory; H * n must stay below 2^31.  The cluster tables stay in
- * the context as after gs_fit_batched (gs_copy_modes: bandwidth j's clusters
- * after those of bandwidths 0..j-1).
+ * H * n must stay below 2^31.  A context recording the trajectory
+ * (gs_context_set_tape) returns GS_ERR_UNSUPPORTED.  The cluster tables stay
+ * in the context as after gs_fit_batched (gs_copy_modes: bandwidth j's
+ * clusters after those of bandwidths 0..j-1).
  */
 gs_status gs_fit_hsweep(gs_context* ctx, const void* points, gs_dtype dtype, int64_t n, int32_t d, int64_t ld,
                         int32_t H, const double* hs, int32_t max_iter, int32_t* labels, gs_info* info, void* stream);
@@ -416,9 +418,13 @@ gs_status gs_ctx_point_mode_loss_backward(gs_context* ctx, const void* points, c
  *                       (8 bytes per key, kept in the context) when that range
  *                       is at most 2^27 keys; 0: through an open-addressing
  *                       hash rebuilt every round.
+ *   GS_CFG_SORT_DIGIT10 0 (default): the radix sorts use 8-bit digits; 1:
+ *                       10-bit digits where that saves a pass (measured
+ *                       slower per pass than the pass it saves on the
+ *                       workloads here).
  * Unknown keys and out-of-range values are GS_ERR_INVALID_ARG.
  */
-enum { GS_CFG_MERGE_SMALL = 0, GS_CFG_TILE_CHUNKS = 1, GS_CFG_DENSE_TABLE = 2 };
+enum { GS_CFG_MERGE_SMALL = 0, GS_CFG_TILE_CHUNKS = 1, GS_CFG_DENSE_TABLE = 2, GS_CFG_SORT_DIGIT10 = 3 };
 gs_status gs_context_set_config(gs_context* ctx, int32_t key, int32_t value);
 gs_status gs_context_get_config(const gs_context* ctx, int32_t key, int32_t* value);
 
@@ -426,12 +432,20 @@ gs_status gs_context_get_config(const gs_context* ctx, int32_t key, int32_t* val
  * Autotuner: fits the given input (the arguments of gs_fit_batched; B = 1 and
  * offsets {0, n} for one point set) once per candidate configuration
  * (GS_CFG_MERGE_SMALL in {1, 0} x GS_CFG_DENSE_TABLE in {1, 0} x
- * GS_CFG_TILE_CHUNKS in {1, 2, 4, 8}), one
+ * GS_CFG_TILE_CHUNKS in {1, 2, 4, 8} x GS_CFG_SORT_DIGIT10 in {1, 0}), one
  * warm-up run and `reps` timed runs each (host wall time of the whole call,
- * best of the reps), and keeps the fastest configuration in the context.  The
- * labels of the timed fits go to a buffer the context owns; the context's
- * last result is that of the last timed fit (identical for every
- * configuration).  On error the previous configuration is kept.
+ * best of the reps), and keeps the fastest configuration in the context.
+ * Every candidate's labels, cluster counts and cluster sums are compared bit
+ * for bit with the first candidate's on the device; a difference is
+ * GS_ERR_DEVICE (it would be a defect of the library).  The choice is kept
+ * per shape (device, d, dtype, and B and the point count rounded down to
+ * powers of two) for the rest of the process, and appended to the file the
+ * environment variable GRIDSHIFT_TUNE_CACHE names, if set, which later
+ * processes read: a shape met before takes its configuration without any
+ * fit.  The labels of the timed fits go to a buffer the context owns; after
+ * a tuning run the context's last result is that of the last timed fit
+ * (identical for every configuration), after a cache hit it is unchanged.
+ * On error the previous configuration is kept.
  */
 gs_status gs_autotune(gs_context* ctx, const void* points, gs_dtype dtype, int32_t d, int64_t ld, int32_t B,
                       const int64_t* offsets, const double* h, int32_t max_iter, int32_t reps, void* stream);

@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -143,6 +145,7 @@ struct gs_config {
     int merge_small = 1;  // merge rounds of at most kMergeMax cells in one workgroup
     int tile_chunks = 4;  // staged chunks of point rows per point tile
     int dense_table = 1;  // neighbour lookups through a dense key table when the key range allows
+    int sort_digit10 = 0;  // radix sorts use 10-bit digits where that saves a pass (else 8-bit)
 };
 
 struct gs_context {
@@ -183,6 +186,8 @@ struct gs_context {
     uint64_t tile_base = 0;  // value of the scan tile counter before the next scan
     gs_config cfg;           // launch choices (results do not depend on them)
     DBuf tune_labels;        // labels of the autotuner's timed fits
+    DBuf tune_ref, tune_tab; // the first candidate's labels; cluster tables compared across candidates
+    bool tune_hit = false;   // the last gs_autotune took its choice from the cache
     DBuf dk;                 // dense key -> cell table of the device-wide rounds
     uint32_t dk_epoch = 0;
     int64_t key_span = 0;    // packed key range of the current fit
@@ -208,7 +213,7 @@ struct gs_context {
     DBuf ck_key, ck_cnt, ck_sum, ck_m;
     int ck_nslots = 0;
     DBuf sums0, inst0, wt_key, wt_cnt, wt_inst, wt_W, wt_g, wt_app;
-    DBuf rep;  // the replicated points of a bandwidth sweep
+    int64_t sweep_n = 0;  // during a bandwidth sweep: the instances share the first n rows of the points
     DBuf trk_win, trk_lab, trk_cnt, trk_sel, trk_out, trk_rect, trk_init;  // tracking buffers
     DBuf tt_key, tt_cnt, tt_W, tt_g, tt_m;
     // backward with checkpoints: a second stream recomputes the next (earlier)
@@ -510,18 +515,14 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 __global__ void k_set_i64(int64_t* __restrict__ p, int64_t v) { *p = v; }
-
-// The first d elements of the n rows of x (row stride ld), written densely H
-// times one after another: each element is read once and stored H times.
-template <typename T>
-__global__ void k_replicate_rows(const T* __restrict__ x, int64_t ld, int64_t n, int d, int H, T* __restrict__ out) {
-    const int64_t per = n * d;
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < per; e += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t i = e / d;
-        const T v = x[i * ld + (e - i * d)];
-        for (int j = 0; j < H; ++j) out[int64_t(j) * per + e] = v;
-    }
+// Count of positions where two word arrays differ (added to *diff).
+__global__ void k_count_diff_u32(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, int64_t n,
+                                 int64_t* __restrict__ diff) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool ne = i < n && a[i] != b[i];
+    if (__ballot(ne) && gs::lane_id() == 0) atomicAdd(reinterpret_cast<unsigned long long*>(diff), 1ull);
 }
+
 __global__ void k_iota32(uint32_t* __restrict__ p, int64_t n) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = uint32_t(i);
@@ -876,7 +877,8 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     c->sort.prof_begin = sort_prof_begin;
     c->sort.prof_end = sort_prof_end;
 
-    const gs::SortPlan plan = gs::sort_plan(bits);
+    c->sort.allow10 = c->cfg.sort_digit10 != 0;
+    const gs::SortPlan plan = gs::sort_plan(bits, c->sort.allow10);
     const int np = plan.passes;
     if (c->ntiles > 0) {  // the current histogram buffer is zero (cleared by the previous sort)
         const unsigned g = unsigned(c->ntiles);
@@ -886,14 +888,21 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         switch (d) {
 #define GS_MK(D) \
     case D:                                                                                                    \
-        gs::k_make_keys<T, K, D><<<g * ksplit, gs::kBoxThreads, 0, s>>>(x, ld, tl, prm, P<K>(c->kA), np,        \
-                                                                        plan.digit, c->sort.cur_hist(), ksplit); \
+        if (c->sweep_n > 0)                                                                                    \
+            gs::k_make_keys_sweep<T, K, D><<<g, gs::kBoxThreads, 0, s>>>(x, ld, tl, prm, B, c->sweep_n,         \
+                                                                         P<K>(c->kA), np, plan.digit,          \
+                                                                         c->sort.cur_hist());                  \
+        else                                                                                                   \
+            gs::k_make_keys<T, K, D><<<g * ksplit, gs::kBoxThreads, 0, s>>>(x, ld, tl, prm, P<K>(c->kA), np,    \
+                                                                            plan.digit, c->sort.cur_hist(),    \
+                                                                            ksplit);                           \
         break;
             GS_MK(1) GS_MK(2) GS_MK(3) GS_MK(4) GS_MK(5) GS_MK(6)
 #undef GS_MK
             default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
         }
-        prof_end(c, s, tk, N * (double(d) * sizeof(T) + sizeof(K)));
+        // points read once (once in all for a sweep), a key written per position
+        prof_end(c, s, tk, (c->sweep_n > 0 ? double(c->sweep_n) : double(N)) * d * sizeof(T) + N * double(sizeof(K)));
         GS_HIP(hipGetLastError());
     }
     K* skeys = nullptr;
@@ -954,7 +963,8 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
                                                                                dk_pre_epoch));
         GS_HIP(hipGetLastError());
     }
-    GS_TRY(segsum(c, d, gs::SrcPoints<T>{x, ld, perm}, T0, m0, N, s, 4.0 + double(d) * sizeof(T), false, true));
+    GS_TRY(segsum(c, d, gs::SrcPoints<T>{x, ld, perm, uint32_t(c->sweep_n)}, T0, m0, N, s,
+                  4.0 + double(d) * sizeof(T), false, true));
     if (c->tape_on && m0 > 0) {  // the initial cells, for the adjoint and the loss
         GS_TRY(ensure(c->sums0, size_t(m0) * d * 8));
         GS_TRY(ensure(c->inst0, size_t(m0) * 4));
@@ -1381,8 +1391,9 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
 
     // row tiles of tile_chunks staged chunks of rows, each inside one instance
     const int trows = c->cfg.tile_chunks * gs::chunk_rows(d, dtype == GS_F32 ? 4 : 8);
+    // (a bandwidth sweep tiles its shared rows once, as instance 0)
     std::vector<gs::RowTile> tiles;
-    for (int b = 0; b < B; ++b) {
+    for (int b = 0; b < (c->sweep_n > 0 ? 1 : B); ++b) {
         for (int64_t r = offsets[b]; r < offsets[b + 1]; r += trows)
             tiles.push_back({r, std::min<int64_t>(r + trows, offsets[b + 1]), b, 0});
     }
@@ -1483,10 +1494,11 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
         };
         for (int b = 0; b < B; ++b) {
             if (offsets[b + 1] == offsets[b]) continue;  // empty instance: no box
+            const int64_t ib = c->sweep_n > 0 ? 0 : b;  // a sweep's instances share instance 0's coordinates
             for (int k = 0; k < d; ++k) {
                 uint64_t mn = ~0ull, mx = 0;
                 for (int q = 0; q < nbc; ++q) {
-                    const uint64_t* e = bc + ((int64_t(b) * nbc + q) * gs::kMaxDim + k) * 2;
+                    const uint64_t* e = bc + ((ib * nbc + q) * gs::kMaxDim + k) * 2;
                     mn = std::min(mn, e[0]);
                     mx = std::max(mx, e[1]);
                 }
@@ -1631,6 +1643,91 @@ static gs_status loss_bwd(gs_context* c, const T* x, const int32_t* labels, cons
 
 namespace {
 
+// ---- autotuner: candidates, and the choices kept per input shape
+constexpr int kTuneCandidates = 32;
+
+gs_config tune_candidate(int cand) {
+    const int tcs[4] = {1, 2, 4, 8};
+    gs_config c;
+    c.merge_small = 1 - ((cand >> 3) & 1);
+    c.dense_table = 1 - ((cand >> 2) & 1);
+    c.tile_chunks = tcs[cand & 3];
+    c.sort_digit10 = (cand >> 4) & 1;
+    return c;
+}
+
+// A shape: device, d, dtype, and the instance and point counts rounded down
+// to powers of two.
+struct TuneKey {
+    int device, d, dtype, logB, logN;
+    bool operator==(const TuneKey& o) const {
+        return device == o.device && d == o.d && dtype == o.dtype && logB == o.logB && logN == o.logN;
+    }
+};
+
+int floor_log2(int64_t v) { return v <= 1 ? 0 : 63 - __builtin_clzll(uint64_t(v)); }
+
+TuneKey tune_key(int device, int d, int dtype, int B, int64_t N) {
+    return TuneKey{device, d, dtype, floor_log2(B), floor_log2(N)};
+}
+
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, gs_config>> g_tune;
+bool g_tune_loaded = false;
+
+// The cache file (environment GRIDSHIFT_TUNE_CACHE): one line per shape,
+// "device d dtype logB logN merge_small dense_table tile_chunks sort_digit10 ms".
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("GRIDSHIFT_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof(line), f)) {
+        TuneKey k{};
+        gs_config c;
+        double ms = 0.0;
+        if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %lf", &k.device, &k.d, &k.dtype, &k.logB, &k.logN,
+                        &c.merge_small, &c.dense_table, &c.tile_chunks, &c.sort_digit10, &ms) != 10)
+            continue;
+        if ((c.merge_small | c.dense_table | c.sort_digit10) & ~1 || c.tile_chunks < 1 || c.tile_chunks > 64) continue;
+        bool have = false;
+        for (auto& e : g_tune)
+            if (e.first == k) {
+                e.second = c;
+                have = true;
+            }
+        if (!have) g_tune.emplace_back(k, c);
+    }
+    std::fclose(f);
+}
+
+bool tune_lookup(const TuneKey& k, gs_config* out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    for (const auto& e : g_tune)
+        if (e.first == k) {
+            *out = e.second;
+            return true;
+        }
+    return false;
+}
+
+void tune_store(const TuneKey& k, const gs_config& c, double ms) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tune.emplace_back(k, c);
+    const char* path = std::getenv("GRIDSHIFT_TUNE_CACHE");
+    if (!path || !*path) return;
+    if (FILE* f = std::fopen(path, "a")) {
+        std::fprintf(f, "%d %d %d %d %d %d %d %d %d %.4f\n", k.device, k.d, k.dtype, k.logB, k.logN, c.merge_small,
+                     c.dense_table, c.tile_chunks, c.sort_digit10, ms);
+        std::fclose(f);
+    }
+}
+
 // Host staging of results (pinned download and upload areas, the mapped
 // block kernels publish into), kept per device across results: a result takes
 // a set when it is created and gives it back when it is released, behind an
@@ -1753,7 +1850,7 @@ void gs_context_destroy(gs_context* c) {
     DBuf* tb2[] = {&c->sums0, &c->inst0, &c->wt_key, &c->wt_cnt, &c->wt_inst, &c->wt_W, &c->wt_g, &c->wt_app,
                    &c->tt_key, &c->tt_cnt, &c->tt_W, &c->tt_g, &c->tt_m, &c->sbA, &c->sbB, &c->qbuf, &c->gmodes,
                    &c->modes_i, &c->counts_i, &c->frows, &c->lossc, &c->ltab, &c->xkA, &c->xkB, &c->xvA, &c->xvB,
-                   &c->ck_key, &c->ck_cnt, &c->ck_sum, &c->ck_m, &c->tune_labels, &c->dk, &c->rep,
+                   &c->ck_key, &c->ck_cnt, &c->ck_sum, &c->ck_m, &c->tune_labels, &c->tune_ref, &c->tune_tab, &c->dk,
                    &c->trk_win, &c->trk_lab, &c->trk_cnt, &c->trk_sel, &c->trk_out, &c->trk_rect, &c->trk_init,
                    &c->seq_moved, &c->seq_waiting};
     for (DBuf* b : tb2) dbuf_release(*b);
@@ -1802,27 +1899,17 @@ gs_status gs_fit_hsweep(gs_context* ctx, const void* points, gs_dtype dtype, int
     if (n > 0 && (!points || !labels)) return fail(GS_ERR_INVALID_ARG, "points and labels are required");
     for (int j = 0; j < H; ++j)
         if (!(hs[j] > 0.0) || !std::isfinite(hs[j])) return fail(GS_ERR_INVALID_ARG, "h must be finite and > 0");
+    if (ctx->tape_on) return fail(GS_ERR_UNSUPPORTED, "a bandwidth sweep records no trajectory");
     gs_context* c = ctx;
     hipStream_t s = static_cast<hipStream_t>(stream);
     GS_HIP(hipSetDevice(c->device));
     std::vector<int64_t> off(size_t(H) + 1);
     for (int j = 0; j <= H; ++j) off[j] = int64_t(j) * n;
-    const void* rows = nullptr;
-    if (n > 0) {
-        const size_t es = dtype == GS_F32 ? 4 : 8;
-        GS_TRY(ensure(c->rep, size_t(H) * size_t(n) * size_t(d) * es));
-        const unsigned g = unsigned(std::min<int64_t>(blocks_for(n * d, 256), 8192));
-        const int tk = prof_begin(c, s, "replicate");
-        if (dtype == GS_F32)
-            k_replicate_rows<float><<<g, 256, 0, s>>>(static_cast<const float*>(points), ld, n, d, H, P<float>(c->rep));
-        else
-            k_replicate_rows<double><<<g, 256, 0, s>>>(static_cast<const double*>(points), ld, n, d, H,
-                                                       P<double>(c->rep));
-        prof_end(c, s, tk, double(n) * d * es * (1.0 + H));
-        GS_HIP(hipGetLastError());
-        rows = c->rep.p;
-    }
-    return fit_impl(c, rows, dtype, d, d, H, off.data(), hs, max_iter, labels, info, s);
+    // every instance reads the caller's n rows: position j * n + i is row i
+    c->sweep_n = n;
+    const gs_status rc = fit_impl(c, points, dtype, d, ld, H, off.data(), hs, max_iter, labels, info, s);
+    c->sweep_n = 0;
+    return rc;
 }
 
 gs_status gs_track_batched(gs_context* ctx, const void* frames, gs_dtype dtype, int32_t T, int32_t H, int32_t W,
@@ -1962,6 +2049,10 @@ gs_status gs_context_set_config(gs_context* ctx, int32_t key, int32_t value) {
             if (value != 0 && value != 1) return fail(GS_ERR_INVALID_ARG, "GS_CFG_DENSE_TABLE takes 0 or 1");
             ctx->cfg.dense_table = value;
             return GS_OK;
+        case GS_CFG_SORT_DIGIT10:
+            if (value != 0 && value != 1) return fail(GS_ERR_INVALID_ARG, "GS_CFG_SORT_DIGIT10 takes 0 or 1");
+            ctx->cfg.sort_digit10 = value;
+            return GS_OK;
     }
     return fail(GS_ERR_INVALID_ARG, "unknown configuration key");
 }
@@ -1972,6 +2063,7 @@ gs_status gs_context_get_config(const gs_context* ctx, int32_t key, int32_t* val
         case GS_CFG_MERGE_SMALL: *value = ctx->cfg.merge_small; return GS_OK;
         case GS_CFG_TILE_CHUNKS: *value = ctx->cfg.tile_chunks; return GS_OK;
         case GS_CFG_DENSE_TABLE: *value = ctx->cfg.dense_table; return GS_OK;
+        case GS_CFG_SORT_DIGIT10: *value = ctx->cfg.sort_digit10; return GS_OK;
     }
     return fail(GS_ERR_INVALID_ARG, "unknown configuration key");
 }
@@ -1985,8 +2077,17 @@ gs_status gs_autotune(gs_context* ctx, const void* points, gs_dtype dtype, int32
     const int64_t N = offsets[B];
     if (N < 0) return fail(GS_ERR_INVALID_ARG, "offsets must be non-decreasing from 0");
     GS_HIP(hipSetDevice(ctx->device));
+    const TuneKey key = tune_key(ctx->device, d, dtype, B, N);
+    gs_config cached;
+    if (tune_lookup(key, &cached)) {
+        ctx->cfg = cached;
+        ctx->tune_hit = true;
+        return GS_OK;
+    }
+    ctx->tune_hit = false;
     GS_TRY(ensure(ctx->tune_labels, size_t(std::max<int64_t>(N, 1)) * 4));
-    std::vector<gs_info> info(B);
+    GS_TRY(ensure(ctx->tune_ref, size_t(std::max<int64_t>(N, 1)) * 4));
+    std::vector<gs_info> info(B), info0(B);
     const bool prof = ctx->prof.on;
     ctx->prof.on = false;
     const gs_config keep = ctx->cfg;
@@ -1994,32 +2095,74 @@ gs_status gs_autotune(gs_context* ctx, const void* points, gs_dtype dtype, int32
     double best_ms = 0.0;
     bool first = true;
     gs_status rc = GS_OK;
-    for (int cand = 0; cand < 16 && rc == GS_OK; ++cand) {
-        {
-            const int tcs[4] = {1, 2, 4, 8};
-            ctx->cfg.merge_small = 1 - (cand >> 3);
-            ctx->cfg.dense_table = 1 - ((cand >> 2) & 1);
-            ctx->cfg.tile_chunks = tcs[cand & 3];
-            double t_min = 0.0;
-            for (int r = 0; r <= reps; ++r) {  // the first run is a warm-up
-                const auto t0 = std::chrono::steady_clock::now();
-                rc = fit_impl(ctx, points, dtype, d, ld, B, offsets, h, max_iter, P<int32_t>(ctx->tune_labels),
-                              info.data(), s);
-                const auto t1 = std::chrono::steady_clock::now();
-                if (rc != GS_OK) break;
-                const double t = std::chrono::duration<double, std::milli>(t1 - t0).count();
-                if (r == 1 || (r > 1 && t < t_min)) t_min = t;
-            }
+    int64_t rows0 = 0;
+    int64_t* ctr = nullptr;
+    for (int cand = 0; cand < kTuneCandidates && rc == GS_OK; ++cand) {
+        ctx->cfg = tune_candidate(cand);
+        double t_min = 0.0;
+        for (int r = 0; r <= reps; ++r) {  // the first run is a warm-up
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = fit_impl(ctx, points, dtype, d, ld, B, offsets, h, max_iter, P<int32_t>(ctx->tune_labels),
+                          info.data(), s);
+            const auto t1 = std::chrono::steady_clock::now();
             if (rc != GS_OK) break;
-            if (first || t_min < best_ms) {
-                best_ms = t_min;
-                best = ctx->cfg;
-                first = false;
-            }
+            const double t = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            if (r == 1 || (r > 1 && t < t_min)) t_min = t;
+        }
+        if (rc != GS_OK) break;
+        // every candidate runs the same binary64 operations in the same
+        // order: its labels, counts and sums must equal the first's bit for bit
+        int64_t rows = 0;
+        for (int b = 0; b < B; ++b) rows += info[b].n_clusters;
+        const size_t tab = size_t(std::max<int64_t>(rows, 1)) * (size_t(d) + 1) * 8;
+        if (cand == 0) {
+            info0 = info;
+            rows0 = rows;
+            GS_TRY(ensure(ctx->tune_tab, 2 * tab + 64));
+            ctr = reinterpret_cast<int64_t*>(static_cast<char*>(ctx->tune_tab.p) + 2 * tab);
+            if (N > 0)
+                GS_HIP(hipMemcpyAsync(ctx->tune_ref.p, ctx->tune_labels.p, size_t(N) * 4, hipMemcpyDeviceToDevice, s));
+        }
+        bool same = rows == rows0;
+        for (int b = 0; b < B && same; ++b)
+            same = info[b].n_clusters == info0[b].n_clusters && info[b].n_iter == info0[b].n_iter &&
+                   info[b].flags == info0[b].flags && info[b].n_cells0 == info0[b].n_cells0;
+        if (same && rows > 0) {
+            // the cluster table, dense: sums then counts (cand 0 into the first half)
+            char* dst = static_cast<char*>(ctx->tune_tab.p) + (cand == 0 ? 0 : tab);
+            gs::k_copy_modes<<<blocks_for(rows, 256), 256, 0, s>>>(
+                table(ctx, ctx->cur_tab), P<gs::InstState>(ctx->state), P<int64_t>(ctx->koff), B, rows, d, nullptr,
+                reinterpret_cast<int64_t*>(dst + size_t(rows) * d * 8), reinterpret_cast<double*>(dst));
+            GS_HIP(hipGetLastError());
+        }
+        if (same && cand > 0) {
+            k_fill_u64<<<1, 64, 0, s>>>(reinterpret_cast<uint64_t*>(ctr), 1, 0);
+            if (N > 0)
+                k_count_diff_u32<<<blocks_for(N, 256), 256, 0, s>>>(P<uint32_t>(ctx->tune_labels),
+                                                                    P<uint32_t>(ctx->tune_ref), N, ctr);
+            if (rows > 0)
+                k_count_diff_u32<<<blocks_for(int64_t(tab / 4), 256), 256, 0, s>>>(
+                    reinterpret_cast<const uint32_t*>(static_cast<char*>(ctx->tune_tab.p) + tab),
+                    reinterpret_cast<const uint32_t*>(ctx->tune_tab.p), int64_t(tab / 4), ctr);
+            GS_HIP(hipGetLastError());
+            int64_t diff = 0;
+            GS_TRY(d2h(ctx, &diff, ctr, sizeof(diff), s));
+            same = diff == 0;
+        }
+        if (!same) {
+            rc = fail(GS_ERR_DEVICE, "autotune: launch configuration " + std::to_string(cand) +
+                                         " gave results that differ from configuration 0");
+            break;
+        }
+        if (first || t_min < best_ms) {
+            best_ms = t_min;
+            best = ctx->cfg;
+            first = false;
         }
     }
     ctx->prof.on = prof;
     ctx->cfg = rc == GS_OK ? best : keep;
+    if (rc == GS_OK) tune_store(key, best, best_ms);
     return rc;
 }
 

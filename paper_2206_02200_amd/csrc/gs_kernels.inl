@@ -303,6 +303,89 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__
         if (hl[i]) atomicAdd(&hc[hist_index(i, digit)], hl[i]);
 }
 
+// Keys of a bandwidth sweep: H instances that share one point set of n rows
+// (instance j owns positions j * n .. j * n + n - 1, its keys with bandwidth
+// param[j].h).  The tiles cover the n source rows once; every staged row is
+// keyed for all H instances, so the points are read once.
+template <typename T, typename K, int D>
+__global__ __launch_bounds__(kBoxThreads) void k_make_keys_sweep(const T* __restrict__ x, int64_t ld,
+                                                                 const RowTile* __restrict__ tiles,
+                                                                 const InstParam* __restrict__ param, int H,
+                                                                 int64_t n, K* __restrict__ keys, int npasses,
+                                                                 int digit, uint32_t* __restrict__ hist) {
+    using S = Stager<T, D>;
+    constexpr int R = S::R;
+    constexpr int RPT = R / kBoxThreads;
+    __shared__ T stage[R * D];
+    __shared__ uint32_t hl[kHistLds];  // pass p, digit v at (p << digit) + v
+    const RowTile tl = tiles[blockIdx.x];
+    if (tl.r0 >= tl.r1) return;
+    const int tid = threadIdx.x, lane = lane_id();
+    const int nh = npasses << digit;
+    const uint32_t dmask = (1u << digit) - 1u;
+    for (int i = tid; i < nh; i += kBoxThreads) hl[i] = 0;
+    S sg;
+    int64_t c0 = tl.r0;
+    int crows = int(tl.r1 - c0 < R ? tl.r1 - c0 : R);
+    sg.load(x, ld, c0, crows);
+    while (crows > 0) {
+        sg.store(x, ld, c0, crows, stage);
+        __syncthreads();
+        const int64_t n0 = c0 + crows;
+        const int nrows = int(tl.r1 - n0 < R ? tl.r1 - n0 : R);
+        if (nrows > 0) sg.load(x, ld, n0, nrows);  // in flight while this chunk is keyed
+        for (int j = 0; j < H; ++j) {
+            const InstParam& sp = param[j];
+            const double hh = sp.h;
+            K kv[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = tid + i * kBoxThreads;
+                if constexpr (sizeof(K) == 4) {
+                    uint32_t key = uint32_t(sp.base);
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const double q = cell_floor(double(stage[(r < crows ? r : 0) * D + k]), hh);
+                        key += uint32_t(q - double(sp.lo[k])) * uint32_t(sp.stride[k]);
+                    }
+                    kv[i] = K(key);
+                } else {
+                    uint64_t key = sp.base;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const double q = cell_floor(double(stage[(r < crows ? r : 0) * D + k]), hh);
+                        key += uint64_t(int64_t(q) - sp.lo[k]) * sp.stride[k];
+                    }
+                    kv[i] = K(key);
+                }
+                if (r < crows) keys[int64_t(j) * n + c0 + r] = kv[i];
+            }
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const bool valid = tid + i * kBoxThreads < crows;
+                const uint64_t act = __ballot(valid);
+                if (!act) continue;
+                const int lead = __ffsll((unsigned long long)act) - 1;
+                for (int p = 0; p < npasses; ++p) {
+                    const uint32_t dgt = uint32_t(kv[i] >> (digit * p)) & dmask;
+                    const uint32_t d0 = __shfl(dgt, lead, kWave);
+                    if (__ballot(valid && dgt == d0) == act) {
+                        if (lane == lead) atomicAdd(&hl[(p << digit) + d0], uint32_t(__popcll(act)));
+                    } else if (valid) {
+                        atomicAdd(&hl[(p << digit) + dgt], 1u);
+                    }
+                }
+            }
+        }
+        __syncthreads();  // every row read before the next chunk is stored
+        c0 = n0;
+        crows = nrows;
+    }
+    uint32_t* hc = hist + (blockIdx.x % kHistCopies) * kHistStride;
+    for (int i = tid; i < nh; i += kBoxThreads)
+        if (hl[i]) atomicAdd(&hc[hist_index(i, digit)], hl[i]);
+}
+
 // ===========================================================================
 // one-pass look-back scan over positions (tile = 8192, wave-striped slots)
 // ===========================================================================
@@ -506,8 +589,9 @@ struct SrcPoints {
     const T* x;
     int64_t ld;
     const uint32_t* perm;
+    uint32_t src_n = 0;  // > 0: positions are instances of n shared rows (a bandwidth sweep): row = position mod n
     __device__ int64_t load(int64_t p, double* v, int d) const {
-        const int64_t r = perm[p];
+        const int64_t r = src_n ? int64_t(perm[p] % src_n) : int64_t(perm[p]);
         for (int k = 0; k < d; ++k) v[k] = load_coord(x, r, ld, k);
         return 1;
     }

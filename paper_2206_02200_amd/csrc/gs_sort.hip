@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
 template <typename K>
 hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int bits, bool hist_ready,
                       SortScratch& sc, hipStream_t s, K** kout, uint32_t** vout) {
-    const SortPlan plan = sort_plan(bits);
+    const SortPlan plan = sort_plan(bits, sc.allow10);
     const int np = plan.passes, dg = plan.digit;
     *kout = kA;
     *vout = vA;

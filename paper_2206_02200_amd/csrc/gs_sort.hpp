@@ -17,16 +17,16 @@ constexpr int kHistStride = kSortMaxPasses * kRadixMax;  // entries of one copy 
 constexpr int64_t kHistEntries = 2 * kHistCopies * kHistStride;  // both histogram buffers
 constexpr int kHistLds = 4096;                           // LDS histogram of a producer: passes x digits
 
-// Digits of a sort: 10-bit digits where that saves a pass (at most 4 of
-// them, e.g. 17..20-bit or 25..30-bit keys), else 8-bit digits.
+// Digits of a sort: with allow10, 10-bit digits where that saves a pass (at
+// most 4 of them, e.g. 17..20-bit or 25..30-bit keys), else 8-bit digits.
 struct SortPlan {
     int passes;
     int digit;  // bits per digit (8 or 10); the last digit holds the remaining bits
 };
-inline SortPlan sort_plan(int bits) {
+inline SortPlan sort_plan(int bits, bool allow10 = true) {
     if (bits <= 0) return {0, 8};
     const int p8 = (bits + 7) / 8, p10 = (bits + 9) / 10;
-    if (p10 < p8 && p10 <= 4) return {p10, 10};
+    if (allow10 && p10 < p8 && p10 <= 4) return {p10, 10};
     return {p8, 8};
 }
 
@@ -47,6 +47,7 @@ struct SortScratch {
     uint64_t* look = nullptr;   // [tiles][radix] look-back status words
     int64_t look_words = 0;     // capacity of `look` in words
     uint32_t epoch = 0;         // last epoch used in `look`
+    bool allow10 = true;        // sort_plan's choice of 10-bit digits
     void* prof_ctx = nullptr;
     ProfBeginFn prof_begin = nullptr;
     ProfEndFn prof_end = nullptr;
@@ -60,7 +61,7 @@ inline int64_t sort_look_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTi
 // Look-back words a sort of n keys by `bits`-bit keys needs (one per tile
 // and digit value).
 inline int64_t sort_look_words(int64_t n, int bits) {
-    return sort_look_tiles(n) * (int64_t(1) << sort_plan(bits).digit);
+    return sort_look_tiles(n) * (int64_t(1) << sort_plan(bits, true).digit);  // the wider of the two plans
 }
 
 // Sort n pairs by the low `bits` bits of the key, stably.  The keys are in

@@ -39,8 +39,9 @@ EXPORTED = [
     "gs_context_set_update", "gs_context_get_update", "gs_fit_hsweep", "gs_track",
     "gs_track_batched", "gs_fit_noalloc",
 ]
-CFG_MERGE_SMALL, CFG_TILE_CHUNKS, CFG_DENSE_TABLE = 0, 1, 2
-CONFIG_KEYS = {"merge_small": CFG_MERGE_SMALL, "tile_chunks": CFG_TILE_CHUNKS, "dense_table": CFG_DENSE_TABLE}
+CFG_MERGE_SMALL, CFG_TILE_CHUNKS, CFG_DENSE_TABLE, CFG_SORT_DIGIT10 = 0, 1, 2, 3
+CONFIG_KEYS = {"merge_small": CFG_MERGE_SMALL, "tile_chunks": CFG_TILE_CHUNKS, "dense_table": CFG_DENSE_TABLE,
+               "sort_digit10": CFG_SORT_DIGIT10}
 UPDATE_RULES = {"parallel": 0, "sequential": 1}  # gs_context_set_update
 
 
@@ -228,7 +229,8 @@ class Context:
         return {i: k for k, i in UPDATE_RULES.items()}[v.value]
 
     def set_config(self, **kv):
-        """Launch choices (merge_small=0/1, tile_chunks=1..64, dense_table=0/1); results never depend on them."""
+        """Launch choices (merge_small=0/1, tile_chunks=1..64, dense_table=0/1, sort_digit10=0/1); results
+        never depend on them."""
         for k, v in kv.items():
             _check(_lib.gs_context_set_config(self.handle, CONFIG_KEYS[k], int(v)))
 

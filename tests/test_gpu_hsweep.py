@@ -85,3 +85,20 @@ def test_sweep_single_h_and_empty():
     assert r.labels.shape == (2, 0) and all(i["n_clusters"] == 0 for i in r.infos)
     with pytest.raises(RuntimeError):
         gridshift.fit_hsweep(torch.from_numpy(x).to(DEV), [0.1, -1.0], 100)
+
+
+def test_sweep_64_bit_keys():
+    # d = 6 and h = 0.01 over the unit cube: about 103^6 keys per bandwidth,
+    # so the sweep's keys are 64-bit
+    x = synth.unit_gmm_f32(3000, 6, seed=95)
+    _check_sweep(x, [0.01, 0.02, 0.6], what="d=6 64-bit keys")
+
+
+def test_sweep_refuses_a_recording_context():
+    x = torch.from_numpy(synth.unit_gmm_f32(2000, 3, seed=96)).to(DEV)
+    ctx = gridshift.Context(0)
+    ctx.set_tape(True)
+    with pytest.raises(gridshift.GridShiftError) as e:
+        gridshift.fit_hsweep(x, [0.1, 0.2], 100, ctx=ctx)
+    assert e.value.code == 6  # GS_ERR_UNSUPPORTED
+    ctx.close()
