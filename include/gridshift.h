@@ -422,9 +422,17 @@ gs_status gs_ctx_point_mode_loss_backward(gs_context* ctx, const void* points, c
  *                       10-bit digits where that saves a pass (measured
  *                       slower per pass than the pass it saves on the
  *                       workloads here).
+ *   GS_CFG_SORT_TILE    8192 (default) or 4096: keys per workgroup tile of a
+ *                       radix-sort pass.
  * Unknown keys and out-of-range values are GS_ERR_INVALID_ARG.
  */
-enum { GS_CFG_MERGE_SMALL = 0, GS_CFG_TILE_CHUNKS = 1, GS_CFG_DENSE_TABLE = 2, GS_CFG_SORT_DIGIT10 = 3 };
+enum {
+    GS_CFG_MERGE_SMALL = 0,
+    GS_CFG_TILE_CHUNKS = 1,
+    GS_CFG_DENSE_TABLE = 2,
+    GS_CFG_SORT_DIGIT10 = 3,
+    GS_CFG_SORT_TILE = 4
+};
 gs_status gs_context_set_config(gs_context* ctx, int32_t key, int32_t value);
 gs_status gs_context_get_config(const gs_context* ctx, int32_t key, int32_t* value);
 
@@ -460,7 +468,8 @@ gs_status gs_autotune(gs_context* ctx, const void* points, gs_dtype dtype, int32
  */
 gs_status gs_profile_enable(gs_context* ctx, const char* prefix);
 gs_status gs_profile_reset(gs_context* ctx);
-/* Number of kernel names with accumulated timings. */
+/* Number of kernel names with accumulated timings (launches not yet
+ * accumulated are waited for and added first). */
 int32_t gs_profile_count(const gs_context* ctx);
 /* Entry i: *name stays valid until gs_profile_reset / gs_context_destroy. */
 gs_status gs_profile_entry(const gs_context* ctx, int32_t i, const char** name, double* total_ms, int64_t* launches,

@@ -146,6 +146,7 @@ struct gs_config {
     int tile_chunks = 4;  // staged chunks of point rows per point tile
     int dense_table = 1;  // neighbour lookups through a dense key table when the key range allows
     int sort_digit10 = 0;  // radix sorts use 10-bit digits where that saves a pass (else 8-bit)
+    int sort_tile = 8192;  // keys per radix-sort pass tile (8192 or 4096)
 };
 
 struct gs_context {
@@ -335,9 +336,10 @@ void prof_set_bytes(gs_context* c, int tok, double bytes) {
     if (tok >= 0 && size_t(tok) < c->prof.recs.size()) c->prof.recs[tok].bytes = bytes;
 }
 
-// Accumulate the recorded intervals (the stream has been synchronised).
+// Accumulate the recorded intervals (waiting for the last of them first).
 void prof_flush(gs_context* c, bool keep) {
     Profiler& p = c->prof;
+    if (keep && !p.recs.empty()) (void)hipEventSynchronize(p.ev[p.recs.back().e1]);
     if (keep) {
         for (const Profiler::Rec& r : p.recs) {
             float ms = 0.f;
@@ -878,6 +880,7 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     c->sort.prof_end = sort_prof_end;
 
     c->sort.allow10 = c->cfg.sort_digit10 != 0;
+    c->sort.tile_keys = c->cfg.sort_tile;
     const gs::SortPlan plan = gs::sort_plan(bits, c->sort.allow10);
     const int np = plan.passes;
     if (c->ntiles > 0) {  // the current histogram buffer is zero (cleared by the previous sort)
@@ -1387,7 +1390,7 @@ gs_status fit_impl(gs_context* c, const void* points, gs_dtype dtype, int d, int
     if (N >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "at most 2^31 - 1 points");
     if (N > 0 && (!points || !labels)) return fail(GS_ERR_INVALID_ARG, "points and labels are required");
     GS_HIP(hipSetDevice(c->device));
-    prof_flush(c, false);  // drop records of an earlier failed call
+    prof_flush(c, true);  // records of the calls since the last fit (backward, loss)
 
     // row tiles of tile_chunks staged chunks of rows, each inside one instance
     const int trows = c->cfg.tile_chunks * gs::chunk_rows(d, dtype == GS_F32 ? 4 : 8);
@@ -1644,7 +1647,7 @@ static gs_status loss_bwd(gs_context* c, const T* x, const int32_t* labels, cons
 namespace {
 
 // ---- autotuner: candidates, and the choices kept per input shape
-constexpr int kTuneCandidates = 32;
+constexpr int kTuneCandidates = 64;
 
 gs_config tune_candidate(int cand) {
     const int tcs[4] = {1, 2, 4, 8};
@@ -1653,6 +1656,7 @@ gs_config tune_candidate(int cand) {
     c.dense_table = 1 - ((cand >> 2) & 1);
     c.tile_chunks = tcs[cand & 3];
     c.sort_digit10 = (cand >> 4) & 1;
+    c.sort_tile = (cand >> 5) & 1 ? 4096 : 8192;
     return c;
 }
 
@@ -1676,7 +1680,7 @@ std::vector<std::pair<TuneKey, gs_config>> g_tune;
 bool g_tune_loaded = false;
 
 // The cache file (environment GRIDSHIFT_TUNE_CACHE): one line per shape,
-// "device d dtype logB logN merge_small dense_table tile_chunks sort_digit10 ms".
+// "device d dtype logB logN merge_small dense_table tile_chunks sort_digit10 sort_tile ms".
 void tune_load_locked() {
     if (g_tune_loaded) return;
     g_tune_loaded = true;
@@ -1689,10 +1693,12 @@ void tune_load_locked() {
         TuneKey k{};
         gs_config c;
         double ms = 0.0;
-        if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %lf", &k.device, &k.d, &k.dtype, &k.logB, &k.logN,
-                        &c.merge_small, &c.dense_table, &c.tile_chunks, &c.sort_digit10, &ms) != 10)
+        if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %lf", &k.device, &k.d, &k.dtype, &k.logB, &k.logN,
+                        &c.merge_small, &c.dense_table, &c.tile_chunks, &c.sort_digit10, &c.sort_tile, &ms) != 11)
             continue;
-        if ((c.merge_small | c.dense_table | c.sort_digit10) & ~1 || c.tile_chunks < 1 || c.tile_chunks > 64) continue;
+        if ((c.merge_small | c.dense_table | c.sort_digit10) & ~1 || c.tile_chunks < 1 || c.tile_chunks > 64 ||
+            (c.sort_tile != 8192 && c.sort_tile != 4096))
+            continue;
         bool have = false;
         for (auto& e : g_tune)
             if (e.first == k) {
@@ -1722,8 +1728,8 @@ void tune_store(const TuneKey& k, const gs_config& c, double ms) {
     const char* path = std::getenv("GRIDSHIFT_TUNE_CACHE");
     if (!path || !*path) return;
     if (FILE* f = std::fopen(path, "a")) {
-        std::fprintf(f, "%d %d %d %d %d %d %d %d %d %.4f\n", k.device, k.d, k.dtype, k.logB, k.logN, c.merge_small,
-                     c.dense_table, c.tile_chunks, c.sort_digit10, ms);
+        std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %.4f\n", k.device, k.d, k.dtype, k.logB, k.logN,
+                     c.merge_small, c.dense_table, c.tile_chunks, c.sort_digit10, c.sort_tile, ms);
         std::fclose(f);
     }
 }
@@ -2053,6 +2059,10 @@ gs_status gs_context_set_config(gs_context* ctx, int32_t key, int32_t value) {
             if (value != 0 && value != 1) return fail(GS_ERR_INVALID_ARG, "GS_CFG_SORT_DIGIT10 takes 0 or 1");
             ctx->cfg.sort_digit10 = value;
             return GS_OK;
+        case GS_CFG_SORT_TILE:
+            if (value != 8192 && value != 4096) return fail(GS_ERR_INVALID_ARG, "GS_CFG_SORT_TILE takes 8192 or 4096");
+            ctx->cfg.sort_tile = value;
+            return GS_OK;
     }
     return fail(GS_ERR_INVALID_ARG, "unknown configuration key");
 }
@@ -2064,6 +2074,7 @@ gs_status gs_context_get_config(const gs_context* ctx, int32_t key, int32_t* val
         case GS_CFG_TILE_CHUNKS: *value = ctx->cfg.tile_chunks; return GS_OK;
         case GS_CFG_DENSE_TABLE: *value = ctx->cfg.dense_table; return GS_OK;
         case GS_CFG_SORT_DIGIT10: *value = ctx->cfg.sort_digit10; return GS_OK;
+        case GS_CFG_SORT_TILE: *value = ctx->cfg.sort_tile; return GS_OK;
     }
     return fail(GS_ERR_INVALID_ARG, "unknown configuration key");
 }
@@ -2175,6 +2186,7 @@ gs_status gs_profile_enable(gs_context* ctx, const char* prefix) {
 
 gs_status gs_profile_reset(gs_context* ctx) {
     if (!ctx) return fail(GS_ERR_INVALID_ARG, "null context");
+    prof_flush(ctx, false);  // launches recorded before the reset are not counted
     ctx->prof.names.clear();
     ctx->prof.ms.clear();
     ctx->prof.bytes.clear();
@@ -2182,7 +2194,12 @@ gs_status gs_profile_reset(gs_context* ctx) {
     return GS_OK;
 }
 
-int32_t gs_profile_count(const gs_context* ctx) { return ctx ? int32_t(ctx->prof.names.size()) : 0; }
+int32_t gs_profile_count(const gs_context* ctx) {
+    if (!ctx) return 0;
+    // launches since the last fit (backward, loss) are accumulated first
+    prof_flush(const_cast<gs_context*>(ctx), true);
+    return int32_t(ctx->prof.names.size());
+}
 
 gs_status gs_profile_entry(const gs_context* ctx, int32_t i, const char** name, double* total_ms, int64_t* launches,
                            double* bytes) {

@@ -4,7 +4,7 @@
 //     producer, which fuses it); every tile derives its pass's digit bases
 //     from them, and the first pass clears the other of two histogram
 //     buffers for the next sort;
-//   * every pass ranks its 8192-key tile in LDS with wave64 ballots, stably
+//   * every pass ranks its tile (8192 keys, or 4096) in LDS with wave64 ballots, stably
 //     (positions ascend with the input order), publishes the tile's digit
 //     counts and finds the counts of all earlier tiles by decoupled look-back;
 //   * the tile is reordered by digit in LDS and written out in digit runs, so
@@ -53,7 +53,7 @@ constexpr int kSortLookWindow = 4;
 // One pass over digit (key >> shift) of DIG bits (the last pass ranks only
 // its nbits significant bits).  Threads t < RADIX / DPT own digits
 // t * DPT .. t * DPT + DPT - 1.
-template <typename K, int DIG>
+template <typename K, int DIG, int ITEMS>
 __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                             K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                             int64_t n, int shift, int nbits,
@@ -62,6 +62,7 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
                                                             uint64_t* __restrict__ look, uint32_t* __restrict__ ctr,
                                                             uint32_t tile_base, uint32_t epoch) {
     constexpr int W = kPassThreads / kWave;
+    constexpr int TILE = kPassThreads * ITEMS;
     constexpr int RADIX = 1 << DIG;
     constexpr int DPT = RADIX > kPassThreads ? RADIX / kPassThreads : 1;  // digits per owning thread
     constexpr int OWN = RADIX / DPT;                                      // owning threads
@@ -72,8 +73,8 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
     __shared__ uint32_t wsum[OW];        // per-wave totals of the digit scan (owning waves)
     __shared__ uint32_t hsum[OW];        // per-wave totals of the histogram scan (owning waves)
     __shared__ uint32_t gbase[RADIX];    // global position of the tile's first key of each digit
-    __shared__ K skey[kSortTile];
-    __shared__ uint32_t sval[kSortTile];
+    __shared__ K skey[TILE];
+    __shared__ uint32_t sval[TILE];
     __shared__ int64_t s_tile;
 
     const int tid = threadIdx.x;
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
     for (int i = tid; i < W * RADIX; i += kPassThreads) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t tile = s_tile;
-    const int64_t t0 = tile * kSortTile;
+    const int64_t t0 = tile * TILE;
     const bool dig = tid < OWN;
     const int d0 = tid * DPT;  // first digit of this thread
     // the pass's count of each owned digit over all keys (its histogram
@@ -106,29 +107,29 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
 
     // Load: wave w owns keys [w*64*ITEMS, (w+1)*64*ITEMS) of the tile, slot i
     // covers 64 consecutive keys, so (slot, lane) order is input order.
-    K key[kSortItems];
-    uint32_t val[kSortItems];
-    uint32_t rank[kSortItems];
+    K key[ITEMS];
+    uint32_t val[ITEMS];
+    uint32_t rank[ITEMS];
     const uint64_t lt = lanemask_lt();
-    const int64_t wbase = t0 + int64_t(w) * (kWave * kSortItems) + lane;
+    const int64_t wbase = t0 + int64_t(w) * (kWave * ITEMS) + lane;
     // all loads first, so that the 16 slots' memory latency overlaps
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const int64_t pos = wbase + i * kWave;
         key[i] = pos < n ? kin[pos] : K(0);
     }
     if (vin) {
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
+        for (int i = 0; i < ITEMS; ++i) {
             const int64_t pos = wbase + i * kWave;
             val[i] = pos < n ? vin[pos] : 0u;
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) val[i] = uint32_t(wbase + i * kWave);
+        for (int i = 0; i < ITEMS; ++i) val[i] = uint32_t(wbase + i * kWave);
     }
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const bool valid = wbase + i * kWave < n;
         const uint32_t dgt = uint32_t(key[i] >> shift) & uint32_t(RADIX - 1);
         uint64_t peers = __ballot(valid);
@@ -205,8 +206,8 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
     // Reorder the tile by digit in LDS (local offsets only), which leaves the
     // items' registers free for a wide look-back.
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        const int64_t pos = t0 + int64_t(w) * (kWave * kSortItems) + i * kWave + lane;
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t pos = t0 + int64_t(w) * (kWave * ITEMS) + i * kWave + lane;
         if (pos < n) {
             const uint32_t dgt = uint32_t(key[i] >> shift) & uint32_t(RADIX - 1);
             const uint32_t lp = doff[dgt] + wcnt[w][dgt] + rank[i];
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
     __syncthreads();
 
     // Write out: entry j of the reordered tile goes to gbase[digit] + (j - doff[digit]).
-    const int64_t cnt = (n - t0) < kSortTile ? (n - t0) : kSortTile;
+    const int64_t cnt = (n - t0) < TILE ? (n - t0) : TILE;
     for (int j = tid; j < cnt; j += kPassThreads) {
         const K k = skey[j];
         const uint32_t dgt = uint32_t(k >> shift) & uint32_t(RADIX - 1);
@@ -256,7 +257,8 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
         k_iota<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, s>>>(vA, n);
         return hipGetLastError();
     }
-    const int64_t tiles = sort_look_tiles(n);
+    const int items = sc.tile_keys == kSortTile / 2 ? kSortItems / 2 : kSortItems;
+    const int64_t tiles = (n + int64_t(kPassThreads) * items - 1) / (int64_t(kPassThreads) * items);
     if (tiles * (int64_t(1) << dg) > sc.look_words) return hipErrorInvalidValue;
     uint32_t* hcur = sc.hist + int64_t(sc.parity) * kHistCopies * kHistStride;
     uint32_t* hother = sc.hist + int64_t(sc.parity ^ 1) * kHistCopies * kHistStride;
@@ -287,14 +289,16 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
         sc.tile_base += uint64_t(tiles);
         const int tk = sc.prof_begin ? sc.prof_begin(sc.prof_ctx, s, "sort_pass") : -1;
         const int nb = bits - dg * p < dg ? bits - dg * p : dg;
-        if (dg == 10)
-            k_sort_pass<K, 10><<<dim3(unsigned(tiles)), dim3(kPassThreads), 0, s>>>(
-                ki, vi, ko, vo, n, dg * p, nb, hcur + p * kRadixMax, p == 0 ? hother : nullptr, tiles, sc.look, sc.ctr,
-                base, ep);
-        else
-            k_sort_pass<K, 8><<<dim3(unsigned(tiles)), dim3(kPassThreads), 0, s>>>(
-                ki, vi, ko, vo, n, dg * p, nb, hcur + p * kRadixMax, p == 0 ? hother : nullptr, tiles, sc.look, sc.ctr,
-                base, ep);
+#define GS_PASS(DG, IT)                                                                                        \
+    k_sort_pass<K, DG, IT><<<dim3(unsigned(tiles)), dim3(kPassThreads), 0, s>>>(                                \
+        ki, vi, ko, vo, n, dg * p, nb, hcur + p * kRadixMax, p == 0 ? hother : nullptr, tiles, sc.look, sc.ctr, \
+        base, ep)
+        if (dg == 10) {
+            if (items == kSortItems) GS_PASS(10, kSortItems); else GS_PASS(10, kSortItems / 2);
+        } else {
+            if (items == kSortItems) GS_PASS(8, kSortItems); else GS_PASS(8, kSortItems / 2);
+        }
+#undef GS_PASS
         // reads keys (and values after the first pass), writes keys and values
         if (sc.prof_end)
             sc.prof_end(sc.prof_ctx, s, tk, double(n) * (sizeof(K) + (p ? 4 : 0) + sizeof(K) + 4));

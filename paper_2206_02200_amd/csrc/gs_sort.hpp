@@ -48,6 +48,7 @@ struct SortScratch {
     int64_t look_words = 0;     // capacity of `look` in words
     uint32_t epoch = 0;         // last epoch used in `look`
     bool allow10 = true;        // sort_plan's choice of 10-bit digits
+    int tile_keys = kSortTile;  // keys per pass tile: kSortTile or kSortTile / 2
     void* prof_ctx = nullptr;
     ProfBeginFn prof_begin = nullptr;
     ProfEndFn prof_end = nullptr;
@@ -55,8 +56,8 @@ struct SortScratch {
 
 inline int sort_passes(int bits) { return sort_plan(bits).passes; }
 
-// Tiles of a pass over n keys.
-inline int64_t sort_look_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+// Tiles of a pass over n keys (with the smaller of the two tile sizes).
+inline int64_t sort_look_tiles(int64_t n) { return (n + kSortTile / 2 - 1) / (kSortTile / 2); }
 
 // Look-back words a sort of n keys by `bits`-bit keys needs (one per tile
 // and digit value).

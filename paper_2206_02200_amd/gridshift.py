@@ -39,9 +39,9 @@ EXPORTED = [
     "gs_context_set_update", "gs_context_get_update", "gs_fit_hsweep", "gs_track",
     "gs_track_batched", "gs_fit_noalloc",
 ]
-CFG_MERGE_SMALL, CFG_TILE_CHUNKS, CFG_DENSE_TABLE, CFG_SORT_DIGIT10 = 0, 1, 2, 3
+CFG_MERGE_SMALL, CFG_TILE_CHUNKS, CFG_DENSE_TABLE, CFG_SORT_DIGIT10, CFG_SORT_TILE = 0, 1, 2, 3, 4
 CONFIG_KEYS = {"merge_small": CFG_MERGE_SMALL, "tile_chunks": CFG_TILE_CHUNKS, "dense_table": CFG_DENSE_TABLE,
-               "sort_digit10": CFG_SORT_DIGIT10}
+               "sort_digit10": CFG_SORT_DIGIT10, "sort_tile": CFG_SORT_TILE}
 UPDATE_RULES = {"parallel": 0, "sequential": 1}  # gs_context_set_update
 
 

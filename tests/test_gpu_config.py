@@ -22,8 +22,8 @@ from oracle import gs_oracle  # noqa: E402
 from paper_2206_02200_amd import gridshift  # noqa: E402
 
 DEV = torch.device("cuda:0")
-CONFIGS = [dict(merge_small=ms, tile_chunks=tc, dense_table=dt, sort_digit10=sd)
-           for ms in (1, 0) for dt in (1, 0) for tc in (1, 3, 8) for sd in (1, 0)]
+CONFIGS = [dict(merge_small=ms, tile_chunks=tc, dense_table=dt, sort_digit10=sd, sort_tile=st)
+           for ms in (1, 0) for dt in (1, 0) for tc in (1, 8) for sd in (1, 0) for st in (8192, 4096)]
 
 
 def _say(*a):
@@ -77,8 +77,8 @@ def test_batched_under_both_merge_paths():
     X = torch.from_numpy(np.concatenate(xs, axis=0)).to(DEV)
     ref = [gs_oracle.fit(v, h, 100) for v, h in zip(xs, hs)]
     ctx = gridshift.Context(0)
-    for ms, dt, sd in ((1, 1, 1), (0, 0, 1), (1, 0, 0), (0, 1, 0)):
-        ctx.set_config(merge_small=ms, dense_table=dt, sort_digit10=sd)
+    for ms, dt, sd, st in ((1, 1, 1, 8192), (0, 0, 1, 4096), (1, 0, 0, 4096), (0, 1, 0, 8192)):
+        ctx.set_config(merge_small=ms, dense_table=dt, sort_digit10=sd, sort_tile=st)
         br = gridshift.fit_batched(X, off, hs, 100, ctx=ctx, with_sums=True)
         sums = br.sums.cpu().numpy()
         for b, o in enumerate(ref):
@@ -112,7 +112,7 @@ def test_autotune_keeps_a_candidate_and_results():
     cfg = ctx.autotune(xt, h, 100, reps=2)
     _say(f"autotuned configuration: {cfg}")
     assert cfg["merge_small"] in (0, 1) and cfg["dense_table"] in (0, 1) and cfg["tile_chunks"] in (1, 2, 4, 8)
-    assert cfg["sort_digit10"] in (0, 1)
+    assert cfg["sort_digit10"] in (0, 1) and cfg["sort_tile"] in (8192, 4096)
     o = gs_oracle.fit(x, h, 100)
     r = gridshift.fit(xt, h, 100, ctx=ctx)
     np.testing.assert_array_equal(r.labels.cpu().numpy(), o.labels)
@@ -140,10 +140,10 @@ def test_autotune_choice_is_kept_per_shape(tmp_path, monkeypatch):
     assert cfg2 == cfg1
     assert (t2 - t1) < 0.2 * (t1 - t0)
     lines = [ln.split() for ln in path.read_text().splitlines()]
-    # device d dtype logB logN merge_small dense_table tile_chunks sort_digit10 ms
+    # device d dtype logB logN merge_small dense_table tile_chunks sort_digit10 sort_tile ms
     mine = [ln for ln in lines if ln[1] == "5" and ln[2] == "1" and ln[3] == "0" and ln[4] == str(30000 .bit_length() - 1)]
-    assert mine and [int(v) for v in mine[-1][5:9]] == [cfg1[k] for k in ("merge_small", "dense_table", "tile_chunks",
-                                                                           "sort_digit10")]
+    assert mine and [int(v) for v in mine[-1][5:10]] == [cfg1[k] for k in ("merge_small", "dense_table", "tile_chunks",
+                                                                            "sort_digit10", "sort_tile")]
     c1.close()
     c2.close()
 
@@ -151,12 +151,13 @@ def test_autotune_choice_is_kept_per_shape(tmp_path, monkeypatch):
 def test_configuration_errors():
     ctx = gridshift.Context(0)
     for kv in (dict(merge_small=2), dict(tile_chunks=0), dict(tile_chunks=65), dict(dense_table=-1),
-               dict(sort_digit10=2)):
+               dict(sort_digit10=2), dict(sort_tile=2048)):
         with pytest.raises(gridshift.GridShiftError) as e:
             ctx.set_config(**kv)
         assert e.value.code == 1
     assert gridshift._lib.gs_context_set_config(ctx.handle, 7, 1) == 1  # unknown key
-    assert ctx.config() == {"merge_small": 1, "tile_chunks": 4, "dense_table": 1, "sort_digit10": 0}
+    assert ctx.config() == {"merge_small": 1, "tile_chunks": 4, "dense_table": 1, "sort_digit10": 0,
+                            "sort_tile": 8192}
     ctx.close()
 
 
