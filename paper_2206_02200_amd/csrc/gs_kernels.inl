@@ -1717,19 +1717,42 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
 #pragma unroll
                     for (int u = 0; u < U; ++u) okm[u] &= (UCT(crd[dd][kk[u]] - me[dd] + 1) <= UCT(2)) ? 1 : 0;
                 }
+                if constexpr (SEQ) {
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int k = kk[u];
-                    const bool ok = okm[u] != 0;
-                    if constexpr (SEQ) {  // a neighbour of a lower colour that has not moved yet
+                    for (int u = 0; u < U; ++u) {
+                        const int k = kk[u];
+                        const bool ok = okm[u] != 0;
+                        // a neighbour of a lower colour that has not moved yet
                         const int cs8 = cstate[k];
                         if (ok && (cs8 & 63) < my_col && !(cs8 & 128)) ready = false;
-                    }
-                    if (ok) {  // only neighbours' rows are read (a non-neighbour would add -0.0)
-                        W += int64_t(cnt[k]);
-                        nbs += 1;
+                        if (ok) {  // only neighbours' rows are read (a non-neighbour would add -0.0)
+                            W += int64_t(cnt[k]);
+                            nbs += 1;
 #pragma unroll
-                        for (int dd = 0; dd < D; ++dd) p[dd] = p[dd] + sm[dd][k];
+                            for (int dd = 0; dd < D; ++dd) p[dd] = p[dd] + sm[dd][k];
+                        }
+                    }
+                } else {
+                    // every candidate's count and sums loaded at once (rows of
+                    // candidates outside the table are the cell's own), then
+                    // added where the candidate is a neighbour: a non-neighbour
+                    // adds -0.0, the exact additive identity, so the fold's
+                    // bits are those of the neighbours alone
+                    int32_t cv[U];
+                    double sv[U][D];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        cv[u] = cnt[kk[u]];
+#pragma unroll
+                        for (int dd = 0; dd < D; ++dd) sv[u][dd] = sm[dd][kk[u]];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const bool ok = okm[u] != 0;
+                        W += ok ? int64_t(cv[u]) : int64_t(0);
+                        nbs += ok ? 1 : 0;
+#pragma unroll
+                        for (int dd = 0; dd < D; ++dd) p[dd] = p[dd] + (ok ? sv[u][dd] : -0.0);
                     }
                 }
             }
