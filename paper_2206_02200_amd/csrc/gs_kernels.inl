@@ -1898,18 +1898,30 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(CellTable t, const InstPa
         }
         __syncthreads();
         const int maxsz = s_maxsz;
-        for (int s = 1; s < maxsz; s <<= 1) {
+        {
+            int rel = 0, sz = 0;  // place in the group, group size
             if (tid < m) {
                 const int g0 = hstart[gid];
-                const int rel = tid - g0;
-                const int sz = int(hstart[gid + 1]) - g0;
-                if ((rel & (2 * s - 1)) == 0 && rel + s < sz) {
-#pragma unroll
-                    for (int dd = 0; dd < D; ++dd) sm[dd][tid] = sm[dd][tid] + sm[dd][tid + s];
-                    scnt[tid] = scnt[tid] + scnt[tid + s];
-                }
+                rel = tid - g0;
+                sz = int(hstart[gid + 1]) - g0;
             }
-            __syncthreads();
+            for (int s = 1; s < maxsz; s <<= 1) {
+                if (tid < m && (rel & (2 * s - 1)) == 0 && rel + s < sz) {
+                    // both operands of every coordinate read before any write
+                    // (the LDS reads then overlap)
+                    double a[D], o[D];
+#pragma unroll
+                    for (int dd = 0; dd < D; ++dd) {
+                        a[dd] = sm[dd][tid];
+                        o[dd] = sm[dd][tid + s];
+                    }
+                    const int32_t ca = scnt[tid], co = scnt[tid + s];
+#pragma unroll
+                    for (int dd = 0; dd < D; ++dd) sm[dd][tid] = a[dd] + o[dd];
+                    scnt[tid] = ca + co;
+                }
+                __syncthreads();
+            }
         }
         // ---- new table
         uint64_t nk = 0;
