@@ -191,6 +191,10 @@ def main() -> int:
     ap.add_argument("--form-only", choices=["batched", "fwd_bwd", "gmm", "sequential", "hsweep", "track"], default=None,
                     help="time only this form (--steps timed calls after one warm-up) and print its JSON object; "
                          "for profiling a form on its own")
+    ap.add_argument("--gmm-d", default="2,3,4,5,6", help="dimensions of the Gaussian-mixture form")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched form: keep the default launch configuration (for counter runs, where the "
+                         "tuner's fits would multiply the dispatches)")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="run an elementwise copy of this many MiB (read + write) before the fits, untimed: "
                          "the reference kernel that scales hardware byte counters taken on this command")
@@ -208,9 +212,17 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibration_copy_mb > 0:
+        src = torch.ones(args.calibration_copy_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+    gmm_dims = [int(v) for v in args.gmm_d.split(",")]
     if args.form_only:
         if args.form_only == "batched":
-            res = bench_batched(gridshift.Context(0), dev, args.steps, 0.0)
+            res = bench_batched(gridshift.Context(0), dev, args.steps, 0.0, not args.no_autotune)
         elif args.form_only == "sequential":
             w = synth.image_xylab_f32()
             res = bench_sequential(torch.from_numpy(w.x).to(dev), w, args.steps)
@@ -219,18 +231,11 @@ def main() -> int:
         elif args.form_only == "track":
             res = bench_track(dev, args.steps)
         elif args.form_only == "gmm":
-            res = bench_gmm(dev, args.steps, 0.0)
+            res = bench_gmm(dev, args.steps, 0.0, gmm_dims)
         else:
             res = bench_fwd_bwd(dev, args.steps, 0.0)
         print(json.dumps(res), flush=True)
         return 0
-    if args.calibration_copy_mb > 0:
-        src = torch.ones(args.calibration_copy_mb << 18, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.neg(src, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
     w = synth.image_xylab_f32()
     n, d = w.x.shape
     x = torch.from_numpy(w.x).to(dev)
@@ -317,11 +322,11 @@ def main() -> int:
     cpu_s = 0.0 if args.no_cpu_baseline else args.form_cpu_seconds
     out["forms"]["plain"]["result_api"] = bench_result_api(x, w, args.steps, ms_per_step)
     if "batched" in forms:
-        out["forms"]["batched"] = bench_batched(ctx, dev, max(1, args.steps // 10), cpu_s)
+        out["forms"]["batched"] = bench_batched(ctx, dev, max(1, args.steps // 10), cpu_s, not args.no_autotune)
     if "sequential" in forms:
         out["forms"]["sequential"] = bench_sequential(x, w, max(1, args.steps // 2))
     if "gmm" in forms:
-        out["forms"]["gmm"] = bench_gmm(dev, max(1, args.steps // 4), cpu_s)
+        out["forms"]["gmm"] = bench_gmm(dev, max(1, args.steps // 4), cpu_s, gmm_dims)
     if "hsweep" in forms:
         out["forms"]["hsweep"] = bench_hsweep(dev, max(1, args.steps // 4))
     if "track" in forms:
@@ -448,7 +453,7 @@ def bench_track(dev, steps: int) -> dict:
     return out
 
 
-def bench_gmm(dev, steps: int, cpu_seconds: float) -> dict:
+def bench_gmm(dev, steps: int, cpu_seconds: float, dims=(2, 3, 4, 5, 6)) -> dict:
     """Gaussian mixtures of 1e7 float32 points, d = 2..6: the 3^d neighbour
     probes of the device-wide rounds, as probes/s of the shift kernel, and
     the dominant kernel per d."""
@@ -459,7 +464,7 @@ def bench_gmm(dev, steps: int, cpu_seconds: float) -> dict:
 
     ctx = gridshift.Context(0)
     res = {}
-    for d in range(2, 7):
+    for d in dims:
         w = synth.gmm_f32(10_000_000, d, seed=40 + d)
         x = torch.from_numpy(w.x).to(dev)
         n = w.x.shape[0]
@@ -516,7 +521,7 @@ def bench_gmm(dev, steps: int, cpu_seconds: float) -> dict:
     return res
 
 
-def bench_batched(ctx, dev, steps: int, cpu_seconds: float) -> dict:
+def bench_batched(ctx, dev, steps: int, cpu_seconds: float, tune: bool = True) -> dict:
     import numpy as np
     import torch
 
@@ -528,14 +533,17 @@ def bench_batched(ctx, dev, steps: int, cpu_seconds: float) -> dict:
     r = gridshift.fit_batched(X, off, hs, 100, ctx=ctx)  # warm-up (allocations)
     torch.cuda.synchronize()
     # the launch configuration: every candidate timed on this batch, the fastest kept
-    t_tune = time.perf_counter()
-    cfg = ctx.autotune(X, hs, 100, offsets=off, reps=1)
-    torch.cuda.synchronize()
-    t_tune = time.perf_counter() - t_tune
-    # the same shape again: the choice comes from the cache, no fit runs
-    t_cached = time.perf_counter()
-    ctx.autotune(X, hs, 100, offsets=off, reps=1)
-    t_cached = time.perf_counter() - t_cached
+    t_tune = t_cached = None
+    cfg = ctx.config()
+    if tune:
+        t_tune = time.perf_counter()
+        cfg = ctx.autotune(X, hs, 100, offsets=off, reps=1)
+        torch.cuda.synchronize()
+        t_tune = time.perf_counter() - t_tune
+        # the same shape again: the choice comes from the cache, no fit runs
+        t_cached = time.perf_counter()
+        ctx.autotune(X, hs, 100, offsets=off, reps=1)
+        t_cached = time.perf_counter() - t_cached
     r = gridshift.fit_batched(X, off, hs, 100, ctx=ctx)  # warm-up of the chosen configuration
     torch.cuda.synchronize()
     t0 = time.perf_counter()
