@@ -221,6 +221,36 @@ __global__ __launch_bounds__(kBoxThreads) void k_bbox_tiles(const T* __restrict_
 // ===========================================================================
 // packed keys + radix digit histograms
 // ===========================================================================
+// Adds one key per valid lane to the LDS digit histograms of `npasses`
+// passes.  Neighbouring points usually share a cell, so lanes are grouped in
+// runs of consecutive lanes with the same digit: the first lane of a run adds
+// the run's length (one LDS atomic per run instead of one per lane).
+template <typename K>
+__device__ __forceinline__ void wave_digit_hist(uint32_t* hl, K key, bool valid, int npasses, int digit) {
+    const uint64_t act = __ballot(valid);
+    if (!act) return;
+    const int lane = lane_id();
+    const uint32_t dmask = (1u << digit) - 1u;
+    K prev;
+    if constexpr (sizeof(K) == 4) {
+        prev = K(__shfl_up(uint32_t(key), 1, kWave));
+    } else {
+        const uint32_t lo = __shfl_up(uint32_t(key), 1, kWave), hi = __shfl_up(uint32_t(key >> 32), 1, kWave);
+        prev = K((uint64_t(hi) << 32) | lo);
+    }
+    const bool prev_valid = lane > 0 && ((act >> (lane - 1)) & 1ull);
+    const uint64_t above = ~((2ull << lane) - 1ull);  // lanes after this one (none for lane 63)
+    for (int p = 0; p < npasses; ++p) {
+        const uint32_t dgt = uint32_t(key >> (digit * p)) & dmask;
+        const bool head = valid && (!prev_valid || (uint32_t(prev >> (digit * p)) & dmask) != dgt);
+        const uint64_t brk = __ballot(head || !valid) & above;  // a run ends where another starts
+        if (head) {
+            const int end = brk ? __ffsll((unsigned long long)brk) - 1 : kWave;
+            atomicAdd(&hl[(p << digit) + dgt], uint32_t(end - lane));
+        }
+    }
+}
+
 template <typename T, typename K, int D>
 __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__ x, int64_t ld,
                                                            const RowTile* __restrict__ tiles,
@@ -235,9 +265,8 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__
     __shared__ InstParam sp;
     const RowTile tl = tile_part(tiles, split, R);
     if (tl.r0 >= tl.r1) return;
-    const int tid = threadIdx.x, lane = lane_id();
+    const int tid = threadIdx.x;
     const int nh = npasses << digit;
-    const uint32_t dmask = (1u << digit) - 1u;
     for (int i = tid; i < nh; i += kBoxThreads) hl[i] = 0;
     if (tid == 0) sp = param[tl.inst];
     S sg;
@@ -276,24 +305,8 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__
             }
             if (r < crows) keys[c0 + r] = kv[i];
         }
-        // digit histograms: one LDS atomic per wave when all its lanes share
-        // the digit (neighbouring points usually share a cell), else one per lane
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const bool valid = tid + i * kBoxThreads < crows;
-            const uint64_t act = __ballot(valid);
-            if (!act) continue;
-            const int lead = __ffsll((unsigned long long)act) - 1;
-            for (int p = 0; p < npasses; ++p) {
-                const uint32_t dgt = uint32_t(kv[i] >> (digit * p)) & dmask;
-                const uint32_t d0 = __shfl(dgt, lead, kWave);
-                if (__ballot(valid && dgt == d0) == act) {
-                    if (lane == lead) atomicAdd(&hl[(p << digit) + d0], uint32_t(__popcll(act)));
-                } else if (valid) {
-                    atomicAdd(&hl[(p << digit) + dgt], 1u);
-                }
-            }
-        }
+        for (int i = 0; i < RPT; ++i) wave_digit_hist(hl, kv[i], tid + i * kBoxThreads < crows, npasses, digit);
         __syncthreads();  // every row read before the next chunk is stored
         c0 = n0;
         crows = nrows;
@@ -320,9 +333,8 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys_sweep(const T* __rest
     __shared__ uint32_t hl[kHistLds];  // pass p, digit v at (p << digit) + v
     const RowTile tl = tiles[blockIdx.x];
     if (tl.r0 >= tl.r1) return;
-    const int tid = threadIdx.x, lane = lane_id();
+    const int tid = threadIdx.x;
     const int nh = npasses << digit;
-    const uint32_t dmask = (1u << digit) - 1u;
     for (int i = tid; i < nh; i += kBoxThreads) hl[i] = 0;
     S sg;
     int64_t c0 = tl.r0;
@@ -361,21 +373,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys_sweep(const T* __rest
                 if (r < crows) keys[int64_t(j) * n + c0 + r] = kv[i];
             }
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                const bool valid = tid + i * kBoxThreads < crows;
-                const uint64_t act = __ballot(valid);
-                if (!act) continue;
-                const int lead = __ffsll((unsigned long long)act) - 1;
-                for (int p = 0; p < npasses; ++p) {
-                    const uint32_t dgt = uint32_t(kv[i] >> (digit * p)) & dmask;
-                    const uint32_t d0 = __shfl(dgt, lead, kWave);
-                    if (__ballot(valid && dgt == d0) == act) {
-                        if (lane == lead) atomicAdd(&hl[(p << digit) + d0], uint32_t(__popcll(act)));
-                    } else if (valid) {
-                        atomicAdd(&hl[(p << digit) + dgt], 1u);
-                    }
-                }
-            }
+            for (int i = 0; i < RPT; ++i) wave_digit_hist(hl, kv[i], tid + i * kBoxThreads < crows, npasses, digit);
         }
         __syncthreads();  // every row read before the next chunk is stored
         c0 = n0;
@@ -1046,9 +1044,8 @@ __global__ __launch_bounds__(256) void k_merge_prep(CellTable t, int64_t m, cons
                                                     const uint64_t* __restrict__ kappa, K* __restrict__ skey, int d,
                                                     int npasses, int digit, uint32_t* __restrict__ hist) {
     __shared__ uint32_t hl[kHistLds];  // pass p, digit v at (p << digit) + v
-    const int tid = threadIdx.x, lane = lane_id();
+    const int tid = threadIdx.x;
     const int nh = npasses << digit;
-    const uint32_t dmask = (1u << digit) - 1u;
     for (int i = tid; i < nh; i += 256) hl[i] = 0;
     __syncthreads();
     const int64_t j0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1059,19 +1056,7 @@ __global__ __launch_bounds__(256) void k_merge_prep(CellTable t, int64_t m, cons
     K out = K(key);
     if (stc[b].apply) out = K(kappa[j]);
     if (valid) skey[j] = out;
-    const uint64_t act = __ballot(valid);
-    if (act) {
-        const int lead = __ffsll((unsigned long long)act) - 1;
-        for (int p = 0; p < npasses; ++p) {
-            const uint32_t dgt = uint32_t(out >> (digit * p)) & dmask;
-            const uint32_t d0 = __shfl(dgt, lead, kWave);
-            if (__ballot(valid && dgt == d0) == act) {
-                if (lane == lead) atomicAdd(&hl[(p << digit) + d0], uint32_t(__popcll(act)));
-            } else if (valid) {
-                atomicAdd(&hl[(p << digit) + dgt], 1u);
-            }
-        }
-    }
+    wave_digit_hist(hl, out, valid, npasses, digit);
     __syncthreads();
     uint32_t* hc = hist + (blockIdx.x % kHistCopies) * kHistStride;
     for (int i = tid; i < nh; i += 256)
