@@ -807,12 +807,48 @@ __device__ __forceinline__ int64_t hash_find(const uint64_t* __restrict__ hk, co
     }
 }
 
-// Neighbour lookup through the open-addressing hash.
+// Neighbour lookup through the open-addressing hash.  find_all looks up N
+// keys of a lane together: the first slot of every key is loaded at once,
+// then the keys still probing (linear probing) load their next slots
+// together, and the values of the keys found are loaded at once; the chain
+// of dependent loads is the longest probe sequence instead of their sum.
 struct HashLookup {
     const uint64_t* hk;
     const uint32_t* hv;
     int logcap;
     __device__ __forceinline__ int64_t find(uint64_t k) const { return hash_find(hk, hv, k, logcap); }
+    template <int N>
+    __device__ __forceinline__ void find_all(const uint64_t* key, const bool* want, int64_t* idx) const {
+        const uint64_t mask = (1ull << logcap) - 1;
+        uint64_t slot[N];
+        int st[N];  // 0: probing, 1: found, 2: absent or not wanted
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            slot[i] = hash_slot(key[i], logcap);
+            st[i] = want[i] ? 0 : 2;
+        }
+        for (;;) {
+            uint64_t e[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) e[i] = st[i] == 0 ? hk[slot[i]] : 0ull;
+            bool probing = false;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                if (st[i] != 0) continue;
+                if (e[i] == key[i]) {
+                    st[i] = 1;
+                } else if (e[i] == kEmpty) {
+                    st[i] = 2;
+                } else {
+                    slot[i] = (slot[i] + 1) & mask;
+                    probing = true;
+                }
+            }
+            if (!probing) break;
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) idx[i] = st[i] == 1 ? int64_t(hv[slot[i]]) : -1;
+    }
 };
 
 // Neighbour lookup through a dense table over the whole packed key range:
@@ -824,6 +860,14 @@ struct DenseLookup {
     __device__ __forceinline__ int64_t find(uint64_t k) const {
         const uint64_t e = dk[k];
         return uint32_t(e >> 32) == epoch ? int64_t(uint32_t(e)) : -1;
+    }
+    template <int N>
+    __device__ __forceinline__ void find_all(const uint64_t* key, const bool* want, int64_t* idx) const {
+        uint64_t e[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) e[i] = want[i] ? dk[key[i]] : 0ull;
+#pragma unroll
+        for (int i = 0; i < N; ++i) idx[i] = want[i] && uint32_t(e[i] >> 32) == epoch ? int64_t(uint32_t(e[i])) : -1;
     }
 };
 
@@ -867,6 +911,8 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
                                                                int32_t* __restrict__ Wout, SeqStep seq) {
     constexpr int NOFF = pow3(D);
     __shared__ uint32_t list[kShiftWaves][NOFF];
+    __shared__ double gval[kShiftWaves][D][kWave];  // gathered rows of found cells
+    __shared__ int64_t gcnt[kShiftWaves][kWave];
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int64_t j = int64_t(blockIdx.x) * kShiftWaves + w;
     if (j >= m) return;  // wave-uniform
@@ -903,10 +949,13 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
     constexpr int NIT = (NOFF + kWave - 1) / kWave;
     int64_t idx[NIT];
     bool upd[NIT];  // the neighbour was moved earlier in this sweep
+    uint64_t nks[NIT];
+    bool want[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int r = it * kWave + lane;
-        idx[it] = -1;
+        nks[it] = 0;
+        want[it] = false;
         upd[it] = false;
         if (r < NOFF) {
             int rr = r;
@@ -923,9 +972,11 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
                 flip |= (v != 0 ? 1 : 0) << (D - 1 - k);
             }
             upd[it] = sequential && (own_col ^ flip) < own_col;
-            if (inside) idx[it] = lk.find(nk);
+            nks[it] = nk;
+            want[it] = inside;
         }
     }
+    lk.template find_all<NIT>(nks, want, idx);
     if (sequential) {  // wait unless every lower-colour neighbour moved in an earlier step
         bool wait = false;
 #pragma unroll
@@ -948,33 +999,39 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
         nfound += __popcll(bal);
     }
     __builtin_amdgcn_wave_barrier();
-    // lane k < D folds dimension k left to right over the found cells (its
-    // loads issued 16 at a time); lane D adds the counts
+    // The found cells' rows are gathered kWave at a time by the whole wave (a
+    // cell per lane: its D values and its count) into LDS; then lane k < D
+    // folds dimension k left to right over them and lane D adds the counts.
     double acc = 0.0;
     int64_t W = 0;
-    if (lane < D) {
-        const double* col = t.sum + int64_t(lane) * t.cap;
-        const double* pcol = pbuf + int64_t(lane) * t.cap;
-        for (int q0 = 0; q0 < nfound; q0 += 16) {
-            double sv[16];
+    for (int q0 = 0; q0 < nfound; q0 += kWave) {
+        if (q0 + lane < nfound) {
+            const uint32_t e = list[w][q0 + lane];
+            const uint32_t k = e & 0x7fffffffu;
+            const int64_t ck = t.cnt[k];
+            double v[D];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const uint32_t e = q0 + u < nfound ? list[w][q0 + u] : 0u;
-                const uint32_t k = e & 0x7fffffffu;
-                sv[u] = q0 + u >= nfound ? 0.0 : (e >> 31) ? double(t.cnt[k]) * pcol[k] : col[k];
+            for (int dd = 0; dd < D; ++dd)
+                v[dd] = (e >> 31) ? pbuf[int64_t(dd) * t.cap + k] : t.sum[int64_t(dd) * t.cap + k];
+#pragma unroll
+            for (int dd = 0; dd < D; ++dd) gval[w][dd][lane] = (e >> 31) ? double(ck) * v[dd] : v[dd];
+            gcnt[w][lane] = ck;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int nq = nfound - q0 < kWave ? nfound - q0 : kWave;
+        if (lane < D) {
+            for (int u0 = 0; u0 < nq; u0 += 16) {
+                double sv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) sv[u] = u0 + u < nq ? gval[w][lane][u0 + u] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (u0 + u < nq) acc = (q0 + u0 + u == 0) ? sv[u] : acc + sv[u];
             }
-#pragma unroll
-            for (int u = 0; u < 16; ++u)
-                if (q0 + u < nfound) acc = (q0 + u == 0) ? sv[u] : acc + sv[u];
+        } else if (lane == D) {
+            for (int u = 0; u < nq; ++u) W += gcnt[w][u];
         }
-    } else if (lane == D) {
-        for (int q0 = 0; q0 < nfound; q0 += 16) {
-            int64_t cv[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) cv[u] = q0 + u < nfound ? t.cnt[list[w][q0 + u] & 0x7fffffffu] : 0;
-#pragma unroll
-            for (int u = 0; u < 16; ++u) W += cv[u];
-        }
+        __builtin_amdgcn_wave_barrier();  // read before the next rows are written
     }
     W = __shfl(W, D, kWave);
     bool bad = false, chg = false;
@@ -2121,6 +2178,7 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_adj_stencil(const uint6
                                                                      double* __restrict__ out, int64_t cap) {
     constexpr int NOFF = pow3(D);
     __shared__ int32_t list[kShiftWaves][NOFF];
+    __shared__ double gval[kShiftWaves][D][kWave];  // gathered rows of found cells
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int64_t j = int64_t(blockIdx.x) * kShiftWaves + w;
     if (j >= m) return;
@@ -2140,10 +2198,13 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_adj_stencil(const uint6
     // in probe order, as in k_shift
     constexpr int NIT = (NOFF + kWave - 1) / kWave;
     int64_t idx[NIT];
+    uint64_t nks[NIT];
+    bool want[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int r = it * kWave + lane;
-        idx[it] = -1;
+        nks[it] = 0;
+        want[it] = false;
         if (r < NOFF) {
             int rr = r;
             bool inside = true;
@@ -2156,9 +2217,11 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_adj_stencil(const uint6
                 inside = inside && c >= 0 && c < P.E[k];
                 nk += uint64_t(int64_t(v)) * P.stride[k];
             }
-            if (inside) idx[it] = lk.find(nk);
+            nks[it] = nk;
+            want[it] = inside;
         }
     }
+    lk.template find_all<NIT>(nks, want, idx);
     int nfound = 0;
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -2167,19 +2230,30 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_adj_stencil(const uint6
         nfound += __popcll(bal);
     }
     __builtin_amdgcn_wave_barrier();
-    if (lane < D) {  // left fold from -0.0, loads issued 16 at a time
-        const double* col = q + int64_t(lane) * cap;
-        double acc = -0.0;
-        for (int e0 = 0; e0 < nfound; e0 += 16) {
-            double sv[16];
+    // rows of the found cells gathered kWave at a time by the whole wave into
+    // LDS, then lane k < D folds dimension k left to right from -0.0
+    double acc = -0.0;
+    for (int q0 = 0; q0 < nfound; q0 += kWave) {
+        if (q0 + lane < nfound) {
+            const int64_t k = list[w][q0 + lane];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) sv[u] = e0 + u < nfound ? col[list[w][e0 + u]] : -0.0;
-#pragma unroll
-            for (int u = 0; u < 16; ++u)
-                if (e0 + u < nfound) acc = acc + sv[u];
+            for (int dd = 0; dd < D; ++dd) gval[w][dd][lane] = q[int64_t(dd) * cap + k];
         }
-        out[int64_t(lane) * cap + j] = acc;
+        __builtin_amdgcn_wave_barrier();
+        const int nq = nfound - q0 < kWave ? nfound - q0 : kWave;
+        if (lane < D) {
+            for (int u0 = 0; u0 < nq; u0 += 16) {
+                double sv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) sv[u] = u0 + u < nq ? gval[w][lane][u0 + u] : -0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (u0 + u < nq) acc = acc + sv[u];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();  // read before the next rows are written
     }
+    if (lane < D) out[int64_t(lane) * cap + j] = acc;
 }
 
 // Gradient of the points: the Sbar of their initial cell, plus (for the loss)
