@@ -632,10 +632,21 @@ __global__ __launch_bounds__(kSegThreads) void k_segsum_chunks(Src src, CellTabl
     const int lane = lane_id();
     if (task >= *tasks_ptr) return;
     const int64_t m = *m_ptr;
-    int64_t lo = 0, hi = m;  // last cell with choff <= task
+    // last cell with choff <= task, by a 65-way search: the lanes test 64
+    // increasing positions strictly inside (lo, hi) at once, and the bracket
+    // shrinks to the two positions around the last one that passes
+    // (choff[lo] <= task < choff[hi], choff[m] read as infinite)
+    int64_t lo = 0, hi = m;
     while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (t.choff[mid] <= uint32_t(task)) lo = mid; else hi = mid;
+        const int64_t span = hi - lo;
+        const int64_t pos = span <= kWave ? lo + 1 + lane : lo + (int64_t(lane + 1) * span) / (kWave + 1);
+        const bool ok = pos < hi && t.choff[pos] <= uint32_t(task);
+        const uint64_t pass = __ballot(ok), fail = __ballot(pos < hi && !ok);
+        const int64_t new_lo = pass ? int64_t(__shfl((long long)pos, 63 - __clzll(pass), kWave)) : lo;
+        const int64_t new_hi = fail ? int64_t(__shfl((long long)pos, __ffsll((unsigned long long)fail) - 1, kWave)) : hi;
+        lo = new_lo;
+        hi = new_hi;
+        if (span <= kWave) break;  // every position in (lo, hi) was tested
     }
     const int64_t c = lo;
     const int64_t ch = task - t.choff[c];
