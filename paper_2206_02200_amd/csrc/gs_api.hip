@@ -629,6 +629,30 @@ gs_status segsum(gs_context* c, int d, Src src, gs::CellTable t, int64_t m_bound
     return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
 }
 
+// Point gradients: Sbar of the initial cell, plus (x != nullptr: the loss's
+// gradient) the direct term of the point-to-mode loss.
+template <typename T>
+gs_status launch_adj_points(gs_context* c, int d, const double* sb0, double* grad, const T* x,
+                            const int32_t* labels, const double* gloss, hipStream_t s) {
+    const unsigned g = blocks_for(c->N, 256);
+    const double* modes = x ? P<double>(c->modes_i) : nullptr;
+    const int64_t* row_off = x ? P<int64_t>(c->rowoff) : nullptr;
+    const int64_t* koff = x ? P<int64_t>(c->koff) : nullptr;
+    const uint32_t* cell0 = P<uint32_t>(c->cell0);
+#define GS_AP(DD)                                                                                             \
+    case DD:                                                                                                   \
+        gs::k_adj_points<T, DD><<<g, 256, 0, s>>>(cell0, sb0, c->capM, c->N, grad, x, c->ld, labels, modes,   \
+                                                 row_off, koff, c->B, gloss);                                \
+        break;
+    switch (d) {
+        GS_AP(1) GS_AP(2) GS_AP(3) GS_AP(4) GS_AP(5) GS_AP(6)
+        default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
+    }
+#undef GS_AP
+    GS_HIP(hipGetLastError());
+    return GS_OK;
+}
+
 // Look-back storage of the radix sort for n keys of `bits` bits (grown and
 // cleared when too small).
 gs_status sort_look_ensure(gs_context* c, int64_t n, int bits, hipStream_t s) {
@@ -1587,7 +1611,7 @@ static gs_status loss_fwd(gs_context* c, const T* x, const int32_t* labels, doub
     t.cap = B;
     int64_t* ctr = P<int64_t>(c->counters);
     k_set_i64<<<1, 1, 0, s>>>(ctr + 0, B);
-    gs::SrcLoss<T> src{x, c->ld, labels, P<double>(c->modes_i), P<int64_t>(c->rowoff), P<int64_t>(c->koff), B, c->d};
+    gs::SrcLoss<T> src{x, c->ld, labels, P<double>(c->modes_i), P<int64_t>(c->koff), c->d};
     return segsum_d<1>(c, src, t, B, c->N, s, 4.0 + 4.0 + c->d * double(sizeof(T)), false, false);
 }
 
@@ -1634,11 +1658,10 @@ static gs_status loss_bwd(gs_context* c, const T* x, const int32_t* labels, cons
     GS_HIP(hipGetLastError());
     double* sb0 = nullptr;
     GS_TRY(adjoint_core(c, P<double>(c->gmodes), s, &sb0));
+    gs_status ap = GS_OK;
     PROF_LAUNCH("adj_points", c->N * (4.0 + 8.0 * d + d * double(sizeof(T)) + 4.0),
-                gs::k_adj_points<T><<<blocks_for(c->N, 256), 256, 0, s>>>(
-                    P<uint32_t>(c->cell0), sb0, c->capM, c->N, d, grad, x, c->ld, labels, P<double>(c->modes_i),
-                    P<int64_t>(c->rowoff), P<int64_t>(c->koff), B, gloss));
-    GS_HIP(hipGetLastError());
+                ap = launch_adj_points<T>(c, d, sb0, grad, x, labels, gloss, s));
+    GS_TRY(ap);
     return GS_OK;
 }
 
@@ -2243,11 +2266,10 @@ gs_status gs_ctx_backward(gs_context* ctx, const double* grad_modes, double* gra
     if (!grad_points) return fail(GS_ERR_INVALID_ARG, "grad_points is NULL");
     double* sb0 = nullptr;
     GS_TRY(adjoint_core(c, grad_modes, s, &sb0));
+    gs_status ap = GS_OK;
     PROF_LAUNCH("adj_points", c->N * (4.0 + 8.0 * c->d),
-                gs::k_adj_points<float><<<blocks_for(c->N, 256), 256, 0, s>>>(
-                    P<uint32_t>(c->cell0), sb0, c->capM, c->N, c->d, grad_points, nullptr, 0, nullptr, nullptr,
-                    nullptr, nullptr, c->B, nullptr));
-    GS_HIP(hipGetLastError());
+                ap = launch_adj_points<float>(c, c->d, sb0, grad_points, nullptr, nullptr, nullptr, s));
+    GS_TRY(ap);
     return GS_OK;
 }
 

@@ -588,7 +588,7 @@ struct SrcPoints {
     int64_t ld;
     const uint32_t* perm;
     uint32_t src_n = 0;  // > 0: positions are instances of n shared rows (a bandwidth sweep): row = position mod n
-    __device__ int64_t load(int64_t p, double* v, int d) const {
+    __device__ int64_t load(int64_t p, double* v, int d, int64_t) const {
         const int64_t r = src_n ? int64_t(perm[p] % src_n) : int64_t(perm[p]);
         for (int k = 0; k < d; ++k) v[k] = load_coord(x, r, ld, k);
         return 1;
@@ -605,7 +605,7 @@ struct SrcMerge {
     const InstState* st;
     const uint32_t* perm;
     int64_t cap;
-    __device__ int64_t load(int64_t p, double* v, int d) const {
+    __device__ int64_t load(int64_t p, double* v, int d, int64_t) const {
         const int64_t j = perm[p];
         const int64_t C = cnt[j];
         if (st[inst[j]].apply) {
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(kSegThreads) void k_segsum_chunks(Src src, CellTabl
         for (int i = 0; i < 4; ++i) {
             const int64_t r = i * kWave + lane;
             if (r < cnt) {
-                ca[i] = src.load(p0 + r, a[i], D);
+                ca[i] = src.load(p0 + r, a[i], D, c);
             } else {
                 ca[i] = 0;
 #pragma unroll
@@ -2269,25 +2269,42 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_adj_stencil(const uint6
 
 // Gradient of the points: the Sbar of their initial cell, plus (for the loss)
 // the direct term gL * (2 * (x - mode)).
-template <typename T>
-__global__ void k_adj_points(const uint32_t* __restrict__ cell0, const double* __restrict__ sbar0, int64_t cap,
-                             int64_t n, int d, double* __restrict__ grad, const T* __restrict__ x, int64_t ld,
-                             const int32_t* __restrict__ labels, const double* __restrict__ modes,
-                             const int64_t* __restrict__ row_off, const int64_t* __restrict__ koff, int B,
-                             const double* __restrict__ gloss) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_adj_points(const uint32_t* __restrict__ cell0,
+                                                    const double* __restrict__ sbar0, int64_t cap, int64_t n,
+                                                    double* __restrict__ grad, const T* __restrict__ x, int64_t ld,
+                                                    const int32_t* __restrict__ labels,
+                                                    const double* __restrict__ modes,
+                                                    const int64_t* __restrict__ row_off,
+                                                    const int64_t* __restrict__ koff, int B,
+                                                    const double* __restrict__ gloss) {
+    const int64_t i0 = int64_t(blockIdx.x) * blockDim.x;
+    const int64_t i = i0 + threadIdx.x;
+    // instance of the block's first row, searched once; a row's own instance
+    // is at most a few steps further (instances without rows are stepped over)
+    __shared__ int s_b0;
+    if (x) {
+        if (threadIdx.x == 0) s_b0 = inst_of_row(row_off, B, i0 < n ? i0 : n - 1);
+        __syncthreads();
+    }
     if (i >= n) return;
     const uint32_t c = cell0[i];
+    double sb[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) sb[k] = sbar0[k * cap + c];
     if (!x) {
-        for (int k = 0; k < d; ++k) grad[i * d + k] = sbar0[k * cap + c];
+#pragma unroll
+        for (int k = 0; k < D; ++k) grad[i * D + k] = sb[k];
         return;
     }
-    const int b = inst_of_row(row_off, B, i);
+    int b = s_b0;
+    while (b + 1 < B && row_off[b + 1] <= i) ++b;
     const int64_t r = koff[b] + labels[i];
     const double gl = gloss[b];
-    for (int k = 0; k < d; ++k) {
-        const double direct = gl * (2.0 * (load_coord(x, i, ld, k) - modes[r * d + k]));
-        grad[i * d + k] = direct + sbar0[k * cap + c];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double direct = gl * (2.0 * (load_coord(x, i, ld, k) - modes[r * D + k]));
+        grad[i * D + k] = direct + sb[k];
     }
 }
 
@@ -2302,12 +2319,11 @@ struct SrcLoss {
     int64_t ld;
     const int32_t* labels;
     const double* modes;    // [sum K][d]
-    const int64_t* row_off;
     const int64_t* koff;
-    int B;
     int d;
-    __device__ int64_t load(int64_t p, double* v, int) const {
-        const int b = inst_of_row(row_off, B, p);
+    // the cells of the loss table are the instances: b = cell
+    __device__ int64_t load(int64_t p, double* v, int, int64_t cell) const {
+        const int b = int(cell);
         const int64_t r = koff[b] + labels[p];
         double acc = 0.0;
         for (int k = 0; k < d; ++k) {
@@ -2324,7 +2340,7 @@ struct SrcInit {
     const double* sums0;  // [d][m0]
     const uint32_t* perm;
     int64_t m0;
-    __device__ int64_t load(int64_t p, double* v, int d) const {
+    __device__ int64_t load(int64_t p, double* v, int d, int64_t) const {
         const int64_t c = perm[p];
         for (int k = 0; k < d; ++k) v[k] = sums0[k * m0 + c];
         return 1;
