@@ -322,7 +322,7 @@ def main() -> int:
     cpu_s = 0.0 if args.no_cpu_baseline else args.form_cpu_seconds
     out["forms"]["plain"]["result_api"] = bench_result_api(x, w, args.steps, ms_per_step)
     if "batched" in forms:
-        out["forms"]["batched"] = bench_batched(ctx, dev, max(1, args.steps // 10), cpu_s, not args.no_autotune)
+        out["forms"]["batched"] = bench_batched(ctx, dev, max(5, args.steps // 4), cpu_s, not args.no_autotune)
     if "sequential" in forms:
         out["forms"]["sequential"] = bench_sequential(x, w, max(1, args.steps // 2))
     if "gmm" in forms:
@@ -332,7 +332,7 @@ def main() -> int:
     if "track" in forms:
         out["forms"]["track"] = bench_track(dev, max(1, args.steps // 10))
     if "fwd_bwd" in forms:
-        out["forms"]["fwd_bwd"] = bench_fwd_bwd(dev, max(1, args.steps // 10), cpu_s)
+        out["forms"]["fwd_bwd"] = bench_fwd_bwd(dev, max(5, args.steps // 4), cpu_s)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -546,17 +546,22 @@ def bench_batched(ctx, dev, steps: int, cpu_seconds: float, tune: bool = True) -
         t_cached = time.perf_counter() - t_cached
     r = gridshift.fit_batched(X, off, hs, 100, ctx=ctx)  # warm-up of the chosen configuration
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    # each step timed on its own; the median is reported (a single step held
+    # up by the host would otherwise dominate the few steps of this form)
+    step_ms = []
     for _ in range(steps):
+        t0 = time.perf_counter()
         r = gridshift.fit_batched(X, off, hs, 100, ctx=ctx)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+    ms = float(np.median(step_ms))
     rounds = [i["n_iter"] for i in r.infos]
     cells0 = sum(i["n_cells0"] for i in r.infos)
     k = int(r.k_offsets[-1])
     b_alg = n * (3 * 4 + 12) + 2 * cells0 * (16 + 8 * 3) + k * (8 * 3 + 8)
     out = {
         "value": n / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "steps": steps,
+        "step_ms": [round(t, 3) for t in step_ms],
         "workload": "256 Voronoi images, H 240..1080, W 320..1920, 5..60 regions, sigma 4..12, RGB f32, "
                     "h in {12,16,24}, max_iter=100, one batched call, launch configuration autotuned on the batch",
         "n": n, "B": len(specs), "cells0": cells0, "clusters": k, "rounds_max": max(rounds),
@@ -579,6 +584,7 @@ def bench_batched(ctx, dev, steps: int, cpu_seconds: float, tune: bool = True) -
 
 
 def bench_fwd_bwd(dev, steps: int, cpu_seconds: float) -> dict:
+    import numpy as np
     import torch
 
     from paper_2206_02200_amd import gridshift, synth
@@ -597,15 +603,18 @@ def bench_fwd_bwd(dev, steps: int, cpu_seconds: float) -> dict:
 
     loss = step()  # warm-up (allocations)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    step_ms = []  # each step on its own, the median reported
     for _ in range(steps):
+        t0 = time.perf_counter()
         loss = step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+    ms = float(np.median(step_ms))
     # points read twice (fit, loss) plus the backward's read of x, labels and cell map and its f64 write
     b_alg = n * (5 * 4 + 12) + n * (5 * 4 + 4) + n * (4 + 5 * 4 + 4 + 8 * 5)
     out = {
         "value": n / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "steps": steps,
+        "step_ms": [round(t, 3) for t in step_ms],
         "workload": "64 Voronoi images 512x512, 30 regions, ramps, sigma 6, (x,y,L,a,b) f32, h=16, "
                     "point-to-mode loss forward + backward (tail checkpoints every 8 rounds, recomputed in the backward)",
         "n": n, "B": B, "loss_mean": float(loss.detach().mean()), "hbm_GBps_alg": b_alg / (ms * 1e-3) / 1e9,
