@@ -912,13 +912,17 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         const unsigned ksplit = 1;
         const gs::RowTile* tl = P<gs::RowTile>(c->tiles);
         const int tk = prof_begin(c, s, "make_keys");
+        // a sweep's instances in groups over a second grid dimension, so that
+        // the launch holds about 2048 workgroups
+        const unsigned sweep_groups =
+            c->sweep_n > 0 ? unsigned(std::min<int64_t>(B, std::max<int64_t>(1, (2048 + int64_t(g) - 1) / int64_t(g))))
+                           : 1u;
         switch (d) {
 #define GS_MK(D) \
     case D:                                                                                                    \
         if (c->sweep_n > 0)                                                                                    \
-            gs::k_make_keys_sweep<T, K, D><<<g, gs::kBoxThreads, 0, s>>>(x, ld, tl, prm, B, c->sweep_n,         \
-                                                                         P<K>(c->kA), np, plan.digit,          \
-                                                                         c->sort.cur_hist());                  \
+            gs::k_make_keys_sweep<T, K, D><<<dim3(g, sweep_groups), gs::kBoxThreads, 0, s>>>(                  \
+                x, ld, tl, prm, B, c->sweep_n, P<K>(c->kA), np, plan.digit, c->sort.cur_hist());               \
         else                                                                                                   \
             gs::k_make_keys<T, K, D><<<g * ksplit, gs::kBoxThreads, 0, s>>>(x, ld, tl, prm, P<K>(c->kA), np,    \
                                                                             plan.digit, c->sort.cur_hist(),    \

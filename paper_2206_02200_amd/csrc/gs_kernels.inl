@@ -318,8 +318,10 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__
 
 // Keys of a bandwidth sweep: H instances that share one point set of n rows
 // (instance j owns positions j * n .. j * n + n - 1, its keys with bandwidth
-// param[j].h).  The tiles cover the n source rows once; every staged row is
-// keyed for all H instances, so the points are read once.
+// param[j].h).  The tiles cover the n source rows once; workgroup (t, g)
+// keys the staged rows of tile t for the g-th group of ceil(H / gridDim.y)
+// consecutive instances, so the points are read once per group (from L2
+// after the first) and the instances spread over many workgroups.
 template <typename T, typename K, int D>
 __global__ __launch_bounds__(kBoxThreads) void k_make_keys_sweep(const T* __restrict__ x, int64_t ld,
                                                                  const RowTile* __restrict__ tiles,
@@ -346,7 +348,9 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys_sweep(const T* __rest
         const int64_t n0 = c0 + crows;
         const int nrows = int(tl.r1 - n0 < R ? tl.r1 - n0 : R);
         if (nrows > 0) sg.load(x, ld, n0, nrows);  // in flight while this chunk is keyed
-        for (int j = 0; j < H; ++j) {
+        const int hg = (H + int(gridDim.y) - 1) / int(gridDim.y);
+        const int j0 = int(blockIdx.y) * hg, j1 = j0 + hg < H ? j0 + hg : H;
+        for (int j = j0; j < j1; ++j) {
             const InstParam& sp = param[j];
             const double hh = sp.h;
             K kv[RPT];
