@@ -745,23 +745,39 @@ __global__ __launch_bounds__(kSegThreads) void k_segsum_levels(CellTable t, cons
         }
         return;
     }
+    // Each level replaces every 64 partials by their R subtree (piece pc of
+    // the level -> partial pc of the next).  PC pieces are loaded at a time;
+    // piece pc's result is written only after every load of pieces <= pc is
+    // done (pieces are read in ascending order, and piece pc is written to
+    // position pc <= 64 * pc), so the level reads only its own inputs.
+    constexpr int PC = 4;
     while (len > 1) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int64_t pieces = (len + kWave - 1) / kWave;
-        for (int64_t pc = 0; pc < pieces; ++pc) {
-            const int64_t i = pc * kWave + lane;
-            double v[D];
-            int64_t cv = 0;
+        for (int64_t pc0 = 0; pc0 < pieces; pc0 += PC) {
+            double v[PC][D];
+            int64_t cv[PC];
 #pragma unroll
-            for (int k = 0; k < D; ++k) v[k] = i < len ? ld_agent(&part[k * pcap + base + i]) : -0.0;
-            cv = i < len ? ld_agent_i(&partc[base + i]) : 0;
+            for (int u = 0; u < PC; ++u) {
+                const int64_t i = (pc0 + u) * kWave + lane;
 #pragma unroll
-            for (int k = 0; k < D; ++k) v[k] = wave_tree_sum(v[k]);
-            cv = wave_tree_sum_i64(cv);
+                for (int k = 0; k < D; ++k) v[u][k] = i < len ? ld_agent(&part[k * pcap + base + i]) : -0.0;
+                cv[u] = i < len ? ld_agent_i(&partc[base + i]) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < PC; ++u) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) v[u][k] = wave_tree_sum(v[u][k]);
+                cv[u] = wave_tree_sum_i64(cv[u]);
+            }
             if (lane == 0) {
 #pragma unroll
-                for (int k = 0; k < D; ++k) st_agent(&part[k * pcap + base + pc], v[k]);
-                st_agent_i(&partc[base + pc], cv);
+                for (int u = 0; u < PC; ++u) {
+                    if (pc0 + u >= pieces) break;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) st_agent(&part[k * pcap + base + pc0 + u], v[u][k]);
+                    st_agent_i(&partc[base + pc0 + u], cv[u]);
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         }
