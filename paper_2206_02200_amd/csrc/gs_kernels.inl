@@ -409,15 +409,16 @@ struct HeadsOp {
     uint32_t* cell_first;    // [m] member at the start of the run
     uint32_t* member_cell;   // [n] member index -> cell id
     static constexpr bool kBinary = true;  // values are 0 or 1
+    // the key itself is not kept between load and emit (fewer registers per
+    // item, so more workgroups per compute unit): a head reads it again
     struct Item {
-        K key;
         uint32_t mem;
         uint32_t head;
     };
     __device__ Item load(int64_t p) const {
         Item it;
-        it.key = key[p];
-        it.head = (p == 0 || it.key != key[p - 1]) ? 1u : 0u;
+        const K k = key[p];
+        it.head = (p == 0 || k != key[p - 1]) ? 1u : 0u;
         it.mem = perm[p];
         return it;
     }
@@ -425,7 +426,7 @@ struct HeadsOp {
     __device__ void emit(int64_t p, uint64_t excl, const Item& it) const {
         const uint64_t cid = excl + it.head - 1;
         if (it.head) {
-            cell_key[cid] = uint64_t(it.key);
+            cell_key[cid] = uint64_t(key[p]);
             cell_start[cid] = uint32_t(p);
             cell_first[cid] = it.mem;
         }
