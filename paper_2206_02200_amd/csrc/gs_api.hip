@@ -912,6 +912,10 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         const unsigned ksplit = 1;
         const gs::RowTile* tl = P<gs::RowTile>(c->tiles);
         const int tk = prof_begin(c, s, "make_keys");
+        // the LDS digit histograms of the key producers: only the passes and
+        // digits of this sort (more workgroups per compute unit than a
+        // histogram sized for the widest sort)
+        const size_t hist_lds = size_t(np << plan.digit) * sizeof(uint32_t);
         // a sweep's instances in groups over a second grid dimension, so that
         // the launch holds about 2048 workgroups
         const unsigned sweep_groups =
@@ -921,12 +925,11 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
 #define GS_MK(D) \
     case D:                                                                                                    \
         if (c->sweep_n > 0)                                                                                    \
-            gs::k_make_keys_sweep<T, K, D><<<dim3(g, sweep_groups), gs::kBoxThreads, 0, s>>>(                  \
+            gs::k_make_keys_sweep<T, K, D><<<dim3(g, sweep_groups), gs::kBoxThreads, hist_lds, s>>>(           \
                 x, ld, tl, prm, B, c->sweep_n, P<K>(c->kA), np, plan.digit, c->sort.cur_hist());               \
         else                                                                                                   \
-            gs::k_make_keys<T, K, D><<<g * ksplit, gs::kBoxThreads, 0, s>>>(x, ld, tl, prm, P<K>(c->kA), np,    \
-                                                                            plan.digit, c->sort.cur_hist(),    \
-                                                                            ksplit);                           \
+            gs::k_make_keys<T, K, D><<<g * ksplit, gs::kBoxThreads, hist_lds, s>>>(                             \
+                x, ld, tl, prm, P<K>(c->kA), np, plan.digit, c->sort.cur_hist(), ksplit);                      \
         break;
             GS_MK(1) GS_MK(2) GS_MK(3) GS_MK(4) GS_MK(5) GS_MK(6)
 #undef GS_MK

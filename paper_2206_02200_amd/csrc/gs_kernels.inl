@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__
     constexpr int R = S::R;
     constexpr int RPT = R / kBoxThreads;
     __shared__ T stage[R * D];
-    __shared__ uint32_t hl[kHistLds];  // pass p, digit v at (p << digit) + v
+    extern __shared__ uint32_t hl[];  // pass p, digit v at (p << digit) + v (npasses << digit words, sized at launch)
     __shared__ InstParam sp;
     const RowTile tl = tile_part(tiles, split, R);
     if (tl.r0 >= tl.r1) return;
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys_sweep(const T* __rest
     constexpr int R = S::R;
     constexpr int RPT = R / kBoxThreads;
     __shared__ T stage[R * D];
-    __shared__ uint32_t hl[kHistLds];  // pass p, digit v at (p << digit) + v
+    extern __shared__ uint32_t hl[];  // pass p, digit v at (p << digit) + v (npasses << digit words, sized at launch)
     const RowTile tl = tiles[blockIdx.x];
     if (tl.r0 >= tl.r1) return;
     const int tid = threadIdx.x;
