@@ -55,12 +55,16 @@ constexpr int kStageBytes = 24576;
 constexpr int kMaxChunkRows = 2048;
 
 // Rows per chunk for d coordinates of `elem` bytes: a multiple of the block
-// size, at most kMaxChunkRows, with rows * d * elem <= kStageBytes.
-__host__ __device__ constexpr int chunk_rows(int d, int elem) {
-    return (kStageBytes / (d * elem)) / kBoxThreads * kBoxThreads > kMaxChunkRows
+// size, at most kMaxChunkRows, with rows * d * elem <= bytes.
+__host__ __device__ constexpr int chunk_rows(int d, int elem, int bytes = kStageBytes) {
+    return (bytes / (d * elem)) / kBoxThreads * kBoxThreads > kMaxChunkRows
                ? kMaxChunkRows
-               : (kStageBytes / (d * elem)) / kBoxThreads * kBoxThreads;
+               : (bytes / (d * elem)) / kBoxThreads * kBoxThreads;
 }
+// The key producers stage half as much per chunk: fewer registers hold the
+// next chunk's loads and less LDS, so more workgroups share a compute unit
+// (their tiles, sized for the box kernel, take twice as many chunks).
+constexpr int kKeyStageBytes = kStageBytes / 2;
 
 struct RowTile {
     int64_t r0, r1;  // rows [r0, r1) of one instance
@@ -84,9 +88,9 @@ __device__ inline RowTile tile_part(const RowTile* __restrict__ tiles, int split
     return tl;
 }
 
-template <typename T, int D>
+template <typename T, int D, int BYTES = kStageBytes>
 struct Stager {
-    static constexpr int R = chunk_rows(D, int(sizeof(T)));
+    static constexpr int R = chunk_rows(D, int(sizeof(T)), BYTES);
     static constexpr int DW = R * D * int(sizeof(T)) / 4;           // dwords of a full chunk
     static constexpr int PER = (DW + kBoxThreads - 1) / kBoxThreads;  // dwords per thread
     uint32_t v[PER];
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys(const T* __restrict__
                                                            const InstParam* __restrict__ param,
                                                            K* __restrict__ keys, int npasses, int digit,
                                                            uint32_t* __restrict__ hist, int split) {
-    using S = Stager<T, D>;
+    using S = Stager<T, D, kKeyStageBytes>;
     constexpr int R = S::R;
     constexpr int RPT = R / kBoxThreads;
     __shared__ T stage[R * D];
@@ -328,7 +332,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_make_keys_sweep(const T* __rest
                                                                  const InstParam* __restrict__ param, int H,
                                                                  int64_t n, K* __restrict__ keys, int npasses,
                                                                  int digit, uint32_t* __restrict__ hist) {
-    using S = Stager<T, D>;
+    using S = Stager<T, D, kKeyStageBytes>;
     constexpr int R = S::R;
     constexpr int RPT = R / kBoxThreads;
     __shared__ T stage[R * D];
