@@ -26,6 +26,8 @@ The plain form also reports its time per phase (binning, rounds, labels).
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 import json
 import os
 import platform
@@ -38,6 +40,22 @@ if ROOT not in sys.path:
 
 METRIC = "points/sec + HBM GB/s: GridShift 1080p d=5 plain vs batched vs fwd+bwd"
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+@contextlib.contextmanager
+def gc_paused():
+    """Python's cyclic garbage collector held off over a timed region, as
+    timeit does: a full collection of this process's objects (torch's among
+    them) takes about 60 ms on the host and would otherwise land inside
+    whichever step crosses its allocation threshold."""
+    was = gc.isenabled()
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
 
 
 def _profile_values(name: str):
@@ -263,11 +281,12 @@ def main() -> int:
     ctx.profile_reset()
     ctx.profile(dominant)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with gc_paused():
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     ctx.profile(None)
     dom = ctx.profile_table()[dominant]
 
@@ -366,11 +385,12 @@ def bench_sequential(x, w, steps: int) -> dict:
     ctx.set_update("sequential")
     r = gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        r = gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    with gc_paused():
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
     n = x.shape[0]
     out = {"value": n / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "steps": steps,
            "rounds": r.info["n_iter"], "clusters": r.info["n_clusters"], "flags": r.info["flags"],
@@ -392,11 +412,12 @@ def bench_hsweep(dev, steps: int) -> dict:
     ctx = gridshift.Context(0)
     r = gridshift.fit_hsweep(x, hs, 100, ctx=ctx)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        r = gridshift.fit_hsweep(x, hs, 100, ctx=ctx)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    with gc_paused():
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = gridshift.fit_hsweep(x, hs, 100, ctx=ctx)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
     out = {"value": n * len(hs) / (ms * 1e-3), "unit": "points/s (points x bandwidths)", "ms_per_step": ms,
            "steps": steps, "n": n, "d": d, "bandwidths": len(hs),
            "clusters_by_h": {f"{h:.2f}": i["n_clusters"] for h, i in zip(hs, r.infos)},
@@ -422,11 +443,12 @@ def bench_track(dev, steps: int) -> dict:
     args = (fr, centres[0], 48.0, 48.0, 0.8, 16.0, 0.5, 20)
     win = gridshift.track(*args, ctx=ctx)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        win = gridshift.track(*args, ctx=ctx)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    with gc_paused():
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            win = gridshift.track(*args, ctx=ctx)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
     T = frames.shape[0]
     out = {"value": T / (ms * 1e-3), "unit": "frames/s", "ms_per_step": ms, "steps": steps, "frames": T,
            "max_centre_error_px": float(np.abs(win[:, :2] - centres).max()),
@@ -439,11 +461,12 @@ def bench_track(dev, steps: int) -> dict:
     bargs = (fr, centres[0], np.full(nd, 24.0), np.full(nd, 24.0), 0.8, 16.0, 0.5, 20)
     bw = gridshift.track_batched(*bargs, ctx=ctx)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        bw = gridshift.track_batched(*bargs, ctx=ctx)
-    torch.cuda.synchronize()
-    bms = (time.perf_counter() - t0) * 1e3 / steps
+    with gc_paused():
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bw = gridshift.track_batched(*bargs, ctx=ctx)
+        torch.cuda.synchronize()
+        bms = (time.perf_counter() - t0) * 1e3 / steps
     err = np.abs(bw[:, :, :2] - np.transpose(centres, (1, 0, 2)))
     out["batched"] = {"value": nd * T / (bms * 1e-3), "unit": "track-frames/s", "ms_per_step": bms, "tracks": nd,
                       "median_centre_error_px": float(np.median(err)),
@@ -470,11 +493,12 @@ def bench_gmm(dev, steps: int, cpu_seconds: float, dims=(2, 3, 4, 5, 6)) -> dict
         n = w.x.shape[0]
         r = gridshift.fit(x, w.h, w.max_iter, ctx=ctx)  # warm-up (allocations)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            r = gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
+        with gc_paused():
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                r = gridshift.fit(x, w.h, w.max_iter, ctx=ctx)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
         info = r.info
         m0, k = info["n_cells0"], info["n_clusters"]
         b_alg = n * (d * 4 + 12) + 2 * m0 * (16 + 8 * d) + k * (8 * d + 8)
@@ -552,12 +576,13 @@ def bench_batched(ctx, dev, steps: int, cpu_seconds: float, tune: bool = True) -
     torch.cuda.synchronize()
     # each step timed on its own; the median is reported (a single step held
     # up by the host would otherwise dominate the few steps of this form)
-    step_ms = []
-    for _ in range(steps):
-        t0 = time.perf_counter()
-        r = gridshift.fit_batched(X, off, hs, 100, ctx=ctx)
-        torch.cuda.synchronize()
-        step_ms.append((time.perf_counter() - t0) * 1e3)
+    with gc_paused():
+        step_ms = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            r = gridshift.fit_batched(X, off, hs, 100, ctx=ctx)
+            torch.cuda.synchronize()
+            step_ms.append((time.perf_counter() - t0) * 1e3)
     ms = float(np.median(step_ms))
     rounds = [i["n_iter"] for i in r.infos]
     cells0 = sum(i["n_cells0"] for i in r.infos)
@@ -608,12 +633,13 @@ def bench_fwd_bwd(dev, steps: int, cpu_seconds: float) -> dict:
     for _ in range(2):  # warm-up (allocations of two live results)
         loss = step()
     torch.cuda.synchronize()
-    step_ms = []  # each step on its own, the median reported
-    for _ in range(steps):
-        t0 = time.perf_counter()
-        loss = step()
-        torch.cuda.synchronize()
-        step_ms.append((time.perf_counter() - t0) * 1e3)
+    with gc_paused():
+        step_ms = []  # each step on its own, the median reported
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            loss = step()
+            torch.cuda.synchronize()
+            step_ms.append((time.perf_counter() - t0) * 1e3)
     ms = float(np.median(step_ms))
     # points read twice (fit, loss) plus the backward's read of x, labels and cell map and its f64 write
     b_alg = n * (5 * 4 + 12) + n * (5 * 4 + 4) + n * (4 + 5 * 4 + 4 + 8 * 5)
@@ -666,11 +692,12 @@ def bench_result_api(x, w, steps: int, ctx_ms: float) -> dict:
 
     step()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    with gc_paused():
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
     return {"ms_per_step": ms, "value": x.shape[0] / (ms * 1e-3), "unit": "points/s", "steps": steps,
             "vs_context_fit": ms / ctx_ms,
             "workload": "the plain workload through gs_fit + gs_result_copy + gs_result_free, device memory "
