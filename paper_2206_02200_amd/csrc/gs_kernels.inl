@@ -1104,7 +1104,7 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
 
 // Stop test of the round (Section 2.1 (v)): decides whether each instance
 // applies the shift and merge computed by k_shift.
-__device__ inline void decide_state(InstState* __restrict__ sp, int max_iter) {
+__device__ inline int decide_state(InstState* __restrict__ sp, int max_iter) {
     InstState s = *sp;
     s.apply = 0;  // (changed was raised by this round's shift; the round end clears it)
     if (s.active) {
@@ -1122,6 +1122,7 @@ __device__ inline void decide_state(InstState* __restrict__ sp, int max_iter) {
     s.cs = 0;  // the merge's cell setup records the new table's ranges
     s.ce = 0;
     *sp = s;
+    return s.apply;
 }
 
 __global__ void k_decide(InstState* __restrict__ st, int B, int max_iter) {
@@ -1267,22 +1268,32 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
     __shared__ uint16_t gm[kMergeMax];      // merge map (old cell -> new cell)
     __shared__ uint32_t wtot[NW];
     __shared__ uint32_t chmask[kMergeMaxInst / 32];  // instances whose round changed the state
+    __shared__ uint32_t apmask[kMergeMaxInst / 32];  // instances that apply the round
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     const uint64_t lt = lanemask_lt();
     const int mm = int(m);
     for (int i = tid; i < kMergeMaxInst / 32; i += kMergeThreads) chmask[i] = 0;
-    // the round's decision per instance (converged, capped or applying)
-    for (int b = tid; b < B; b += kMergeThreads) decide_state(st + b, max_iter);
-    __syncthreads();
+    // the round's decision per instance (converged, capped or applying); the
+    // 64 lanes of a wave decide 64 consecutive instances and its first lane
+    // writes their two words of the apply mask (every word below B / 32 is
+    // written once, so the mask needs no clearing)
+    for (int b0 = 0; b0 < B; b0 += kMergeThreads) {
+        const int b = b0 + tid;
+        const uint64_t ab = __ballot(b < B && decide_state(st + b, max_iter) != 0);
+        const int bw = b0 + w * kWave;  // first instance of the wave
+        if (lane == 0 && bw < B) {
+            apmask[bw >> 5] = uint32_t(ab);
+            if (bw + 32 < B) apmask[(bw >> 5) + 1] = uint32_t(ab >> 32);
+        }
+    }
 
     // ---- sort keys: landing key for cells of applying instances, own key
     // otherwise (the shift already flagged instances whose cells moved or
-    // whose merge values differ from their sums); all loads of a thread are
-    // issued before any use
+    // whose merge values differ from their sums); the loads are issued before
+    // the barrier that publishes the decisions
     {
         int bi[kMergeIPT];
         uint64_t key[kMergeIPT], kap[kMergeIPT];
-        int ap[kMergeIPT];
 #pragma unroll
         for (int i = 0; i < kMergeIPT; ++i) {
             const int j = min(tid + i * kMergeThreads, mm - 1);
@@ -1290,14 +1301,13 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
             key[i] = t.key[j];
             kap[i] = kappa[j];  // read for every cell, used for applying instances only
         }
-#pragma unroll
-        for (int i = 0; i < kMergeIPT; ++i) ap[i] = st[bi[i]].apply;
-        __syncthreads();  // chmask cleared
+        __syncthreads();  // chmask cleared, apmask written
 #pragma unroll
         for (int i = 0; i < kMergeIPT; ++i) {
             const int j = tid + i * kMergeThreads;
             if (j >= mm) continue;
-            kbuf[0][j] = uint32_t(ap[i] ? kap[i] : key[i]);
+            const bool ap = (apmask[bi[i] >> 5] >> (bi[i] & 31)) & 1u;
+            kbuf[0][j] = uint32_t(ap ? kap[i] : key[i]);
             vbuf[0][j] = uint16_t(j);
         }
     }
@@ -1374,24 +1384,33 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
     const uint32_t* sk = kbuf[src];
     const uint16_t* sv = vbuf[src];
 
-    // ---- run heads -> new cells (thread t owns positions [t * IPT, (t + 1) * IPT))
-    int nh = 0;
-    bool hf[kMergeIPT];
+    // ---- run heads -> new cells (wave w owns positions [w * 64 * IPT,
+    // (w + 1) * 64 * IPT) in slots of 64, as in the ranking: consecutive
+    // lanes read and write consecutive positions)
+    uint64_t hb[kMergeIPT];
+    int nh = 0;  // heads of the wave
 #pragma unroll
     for (int i = 0; i < kMergeIPT; ++i) {
-        const int p = tid * kMergeIPT + i;
-        hf[i] = p < mm && (p == 0 || sk[p] != sk[p - 1]);
-        nh += hf[i] ? 1 : 0;
+        const int p = w * (kWave * kMergeIPT) + i * kWave + lane;
+        hb[i] = __ballot(p < mm && (p == 0 || sk[p] != sk[p - 1]));
+        nh += __popcll(hb[i]);
     }
-    uint32_t mnew_u = 0;
-    int cid = int(merge_block_scan(uint32_t(nh), wtot, &mnew_u)) - 1;
-    const int mnew = int(mnew_u);
+    if (lane == 0) wtot[w] = uint32_t(nh);
+    __syncthreads();
+    int cid_base = 0, mnew = 0;  // heads before this wave, all heads
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) {
+        const int c = int(wtot[ww]);
+        cid_base += ww < w ? c : 0;
+        mnew += c;
+    }
+    const uint64_t le = lt | (1ull << lane);
 #pragma unroll
     for (int i = 0; i < kMergeIPT; ++i) {
-        const int p = tid * kMergeIPT + i;
+        const int p = w * (kWave * kMergeIPT) + i * kWave + lane;
         if (p < mm) {
-            if (hf[i]) {
-                ++cid;
+            const int cid = cid_base + __popcll(hb[i] & le) - 1;  // the last head at or before p
+            if ((hb[i] >> lane) & 1u) {
                 hs[cid] = uint16_t(p);
                 u.key[cid] = uint64_t(sk[p]);
                 if (dk) dk[sk[p]] = (uint64_t(dk_epoch) << 32) | uint64_t(cid);
@@ -1399,53 +1418,51 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
             const int j = sv[p];
             mperm[p] = uint32_t(j);
             gm[j] = uint16_t(cid);
-            gmap[j] = uint32_t(cid);
-            if (gtape) gtape[j] = uint32_t(cid);
         }
+        cid_base += __popcll(hb[i]);
     }
     if (tid == 0) hs[mnew] = uint16_t(mm);
-    __syncthreads();
-
-    // ---- new cells: members, chunks, instance ranges, merged groups
-    // (thread t owns new cells [t * IPT, (t + 1) * IPT))
-    uint32_t nchunks = 0;
-    int bc[kMergeIPT + 1];  // instance of the cells tid * IPT - 1 .. tid * IPT + IPT - 1
-    int apc[kMergeIPT];
-    {
-        const int c0 = tid * kMergeIPT;
-        bc[0] = (c0 > 0 && c0 - 1 < mnew) ? t.inst[sv[hs[c0 - 1]]] : -1;
-#pragma unroll
-        for (int i = 0; i < kMergeIPT; ++i) {
-            const int c = c0 + i;
-            bc[i + 1] = c < mnew ? t.inst[sv[hs[c]]] : -1;
-            if (c < mnew) nchunks += (uint32_t(hs[c + 1] - hs[c]) + kChunk - 1) / kChunk;
-        }
-#pragma unroll
-        for (int i = 0; i < kMergeIPT; ++i) apc[i] = bc[i + 1] >= 0 ? st[bc[i + 1]].apply : 0;
+    __syncthreads();  // hs and gm complete; wtot free again
+    // the merge map in old-cell order
+    for (int j = tid; j < mm; j += kMergeThreads) {
+        const uint32_t g = gm[j];
+        gmap[j] = g;
+        if (gtape) gtape[j] = g;
     }
-    uint32_t tasks = 0;
-    uint32_t choff = merge_block_scan(nchunks, wtot, &tasks);
-#pragma unroll
-    for (int i = 0; i < kMergeIPT; ++i) {
-        const int c = tid * kMergeIPT + i;
-        if (c >= mnew) continue;
-        const int p0 = hs[c];
-        const uint32_t len = uint32_t(hs[c + 1]) - uint32_t(p0);
-        const uint32_t nch = (len + kChunk - 1) / kChunk;
-        const int b = bc[i + 1], bp = bc[i];
-        u.start[c] = uint32_t(p0);
-        u.len[c] = len;
-        u.first[c] = uint32_t(sv[p0]);
-        u.nch[c] = nch;
-        u.choff[c] = choff;
-        u.inst[c] = b;
-        choff += nch;
-        if (bp != b) {
-            st[b].cs = c;
-            if (bp >= 0) st[bp].ce = c;
+
+    // ---- new cells: members, chunks, instance ranges, merged groups (one
+    // cell per thread, kMergeThreads cells at a time; chunk offsets by a
+    // block scan per group of cells)
+    uint32_t tasks = 0;  // chunks of the cells before the current group
+    for (int c0 = 0; c0 < mnew; c0 += kMergeThreads) {
+        const int c = c0 + tid;
+        int p0 = 0, b = -1, bp = -1;
+        uint32_t len = 0, nch = 0;
+        if (c < mnew) {
+            p0 = hs[c];
+            len = uint32_t(hs[c + 1]) - uint32_t(p0);
+            nch = (len + kChunk - 1) / kChunk;
+            b = t.inst[sv[p0]];
+            bp = c > 0 ? t.inst[sv[hs[c - 1]]] : -1;
         }
-        if (c == mnew - 1) st[b].ce = mnew;
-        if (len > 1 && apc[i]) atomicOr(&chmask[b >> 5], 1u << (b & 31));
+        uint32_t group = 0;
+        const uint32_t choff = tasks + merge_block_scan(nch, wtot, &group);
+        tasks += group;
+        if (c < mnew) {
+            u.start[c] = uint32_t(p0);
+            u.len[c] = len;
+            u.first[c] = uint32_t(sv[p0]);
+            u.nch[c] = nch;
+            u.choff[c] = choff;
+            u.inst[c] = b;
+            if (bp != b) {
+                st[b].cs = c;
+                if (bp >= 0) st[bp].ce = c;
+            }
+            if (c == mnew - 1) st[b].ce = mnew;
+            const bool ap = (apmask[b >> 5] >> (b & 31)) & 1u;
+            if (len > 1 && ap) atomicOr(&chmask[b >> 5], 1u << (b & 31));
+        }
     }
     __syncthreads();
     for (int b = tid; b < B; b += kMergeThreads)
