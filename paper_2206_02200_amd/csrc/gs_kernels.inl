@@ -1273,6 +1273,25 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
     const uint64_t lt = lanemask_lt();
     const int mm = int(m);
     for (int i = tid; i < kMergeMaxInst / 32; i += kMergeThreads) chmask[i] = 0;
+    // the cells' instances, keys and landing keys, loaded before the
+    // decisions below (they do not depend on them)
+    int bi[kMergeIPT];
+    uint64_t key[kMergeIPT], kap[kMergeIPT];
+#pragma unroll
+    for (int i = 0; i < kMergeIPT; ++i) {
+        const int j = min(tid + i * kMergeThreads, mm - 1);
+        bi[i] = t.inst[j];
+        key[i] = t.key[j];
+        kap[i] = kappa[j];  // read for every cell, used for applying instances only
+    }
+    // the initial cells' current cells, composed with the merge map at the end
+    constexpr int kCurPT = 4;  // entries per thread and step of the composition
+    uint32_t cur0[kCurPT];
+#pragma unroll
+    for (int i = 0; i < kCurPT; ++i) {
+        const int64_t c = tid + int64_t(i) * kMergeThreads;
+        cur0[i] = c < m0 ? cur[c] : 0u;
+    }
     // the round's decision per instance (converged, capped or applying); the
     // 64 lanes of a wave decide 64 consecutive instances and its first lane
     // writes their two words of the apply mask (every word below B / 32 is
@@ -1289,18 +1308,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
 
     // ---- sort keys: landing key for cells of applying instances, own key
     // otherwise (the shift already flagged instances whose cells moved or
-    // whose merge values differ from their sums); the loads are issued before
-    // the barrier that publishes the decisions
+    // whose merge values differ from their sums)
     {
-        int bi[kMergeIPT];
-        uint64_t key[kMergeIPT], kap[kMergeIPT];
-#pragma unroll
-        for (int i = 0; i < kMergeIPT; ++i) {
-            const int j = min(tid + i * kMergeThreads, mm - 1);
-            bi[i] = t.inst[j];
-            key[i] = t.key[j];
-            kap[i] = kappa[j];  // read for every cell, used for applying instances only
-        }
         __syncthreads();  // chmask cleared, apmask written
 #pragma unroll
         for (int i = 0; i < kMergeIPT; ++i) {
@@ -1312,22 +1321,23 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
         }
     }
 
-    // ---- stable LSD radix sort of (key, cell) in LDS
+    // ---- stable LSD radix sort of (key, cell) in LDS; wave w ranks the
+    // S slots of 64 positions from w * S * 64 (S: the slots spread evenly
+    // over the waves), so (wave, slot, lane) order is position order
+    const int S = ((mm + kWave - 1) / kWave + NW - 1) / NW;  // <= kMergeIPT
     int src = 0;
     for (int p = 0; p < npasses; ++p) {
         const int shift = 8 * p;
         const int nbits = kbits - shift < 8 ? kbits - shift : 8;  // the last digit may be narrower
         for (int i = tid; i < NW * 256; i += kMergeThreads) (&wcnt[0][0])[i] = 0;
         __syncthreads();
-        // wave w ranks positions [w * 64 * IPT, (w + 1) * 64 * IPT); slot i
-        // covers 64 consecutive positions, so (slot, lane) order is input order
         uint32_t kk[kMergeIPT];
         uint16_t vv[kMergeIPT];
         uint32_t rk[kMergeIPT];
 #pragma unroll
         for (int i = 0; i < kMergeIPT; ++i) {
-            const int pos = w * (kWave * kMergeIPT) + i * kWave + lane;
-            if (w * (kWave * kMergeIPT) + i * kWave >= mm) {  // the whole slot is past the end
+            const int pos = (w * S + i) * kWave + lane;
+            if (i >= S || (w * S + i) * kWave >= mm) {  // no slot, or the whole slot is past the end
                 kk[i] = 0u;
                 vv[i] = 0;
                 rk[i] = 0u;
@@ -1370,8 +1380,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kMergeIPT; ++i) {
-            const int pos = w * (kWave * kMergeIPT) + i * kWave + lane;
-            if (pos < mm) {
+            const int pos = (w * S + i) * kWave + lane;
+            if (i < S && pos < mm) {
                 const uint32_t dgt = (kk[i] >> shift) & 255u;
                 const uint32_t dst = wcnt[w][dgt] + rk[i];
                 kbuf[src ^ 1][dst] = kk[i];
@@ -1384,15 +1394,14 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
     const uint32_t* sk = kbuf[src];
     const uint16_t* sv = vbuf[src];
 
-    // ---- run heads -> new cells (wave w owns positions [w * 64 * IPT,
-    // (w + 1) * 64 * IPT) in slots of 64, as in the ranking: consecutive
-    // lanes read and write consecutive positions)
+    // ---- run heads -> new cells (the ranking's slots: consecutive lanes
+    // read and write consecutive positions)
     uint64_t hb[kMergeIPT];
     int nh = 0;  // heads of the wave
 #pragma unroll
     for (int i = 0; i < kMergeIPT; ++i) {
-        const int p = w * (kWave * kMergeIPT) + i * kWave + lane;
-        hb[i] = __ballot(p < mm && (p == 0 || sk[p] != sk[p - 1]));
+        const int p = (w * S + i) * kWave + lane;
+        hb[i] = __ballot(i < S && p < mm && (p == 0 || sk[p] != sk[p - 1]));
         nh += __popcll(hb[i]);
     }
     if (lane == 0) wtot[w] = uint32_t(nh);
@@ -1407,8 +1416,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
     const uint64_t le = lt | (1ull << lane);
 #pragma unroll
     for (int i = 0; i < kMergeIPT; ++i) {
-        const int p = w * (kWave * kMergeIPT) + i * kWave + lane;
-        if (p < mm) {
+        const int p = (w * S + i) * kWave + lane;
+        if (i < S && p < mm) {
             const int cid = cid_base + __popcll(hb[i] & le) - 1;  // the last head at or before p
             if ((hb[i] >> lane) & 1u) {
                 hs[cid] = uint16_t(p);
@@ -1470,15 +1479,15 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_small(CellTable t, int6
 
     // ---- initial cell -> current cell (the per-instance round end follows
     // the sums, which still read which instances apply the round)
-    for (int64_t c0 = tid; c0 < m0; c0 += 4 * kMergeThreads) {
-        uint32_t v[4];
+    for (int64_t c0 = tid; c0 < m0; c0 += kCurPT * kMergeThreads) {
+        uint32_t v[kCurPT];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < kCurPT; ++i) {
             const int64_t c = c0 + int64_t(i) * kMergeThreads;
-            v[i] = c < m0 ? cur[c] : 0u;
+            v[i] = c0 == tid ? cur0[i] : (c < m0 ? cur[c] : 0u);  // the first step's entries were loaded at the start
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < kCurPT; ++i) {
             const int64_t c = c0 + int64_t(i) * kMergeThreads;
             if (c < m0) cur[c] = gm[v[i]];
         }
