@@ -440,7 +440,8 @@ gs_status gs_context_get_config(const gs_context* ctx, int32_t key, int32_t* val
  * Autotuner: fits the given input (the arguments of gs_fit_batched; B = 1 and
  * offsets {0, n} for one point set) once per candidate configuration
  * (GS_CFG_MERGE_SMALL in {1, 0} x GS_CFG_DENSE_TABLE in {1, 0} x
- * GS_CFG_TILE_CHUNKS in {1, 2, 4, 8} x GS_CFG_SORT_DIGIT10 in {1, 0}), one
+ * GS_CFG_TILE_CHUNKS in {1, 2, 4, 8} x GS_CFG_SORT_DIGIT10 in {0, 1} x
+ * GS_CFG_SORT_TILE in {8192, 4096}: 64 candidates), one
  * warm-up run and `reps` timed runs each (host wall time of the whole call,
  * best of the reps), and keeps the fastest configuration in the context.
  * Every candidate's labels, cluster counts and cluster sums are compared bit

@@ -229,8 +229,8 @@ class Context:
         return {i: k for k, i in UPDATE_RULES.items()}[v.value]
 
     def set_config(self, **kv):
-        """Launch choices (merge_small=0/1, tile_chunks=1..64, dense_table=0/1, sort_digit10=0/1); results
-        never depend on them."""
+        """Launch choices (merge_small=0/1, tile_chunks=1..64, dense_table=0/1, sort_digit10=0/1,
+        sort_tile=8192/4096); results never depend on them."""
         for k, v in kv.items():
             _check(_lib.gs_context_set_config(self.handle, CONFIG_KEYS[k], int(v)))
 
