@@ -909,7 +909,12 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
     const int np = plan.passes;
     if (c->ntiles > 0) {  // the current histogram buffer is zero (cleared by the previous sort)
         const unsigned g = unsigned(c->ntiles);
-        const unsigned ksplit = 1;
+        // the key producer stages half-size chunks: with few tiles (under
+        // eight per compute unit) its workgroups take a share of a tile each
+        // (at most four of its chunks), so that more of them run at once
+        // (measured: 1080p keys 27.0 -> 23.1 us; the 256-image batch, with
+        // ~23K tiles, was slower split)
+        const unsigned ksplit = g < 2048 ? unsigned(std::max(1, c->cfg.tile_chunks / 2)) : 1u;
         const gs::RowTile* tl = P<gs::RowTile>(c->tiles);
         const int tk = prof_begin(c, s, "make_keys");
         // the LDS digit histograms of the key producers: only the passes and
