@@ -402,8 +402,9 @@ constexpr int kScanItems = kScanTile / kScanThreads;  // 16
 // issues every load of a thread before any store), value() is its value
 // (< 2^32, and a tile's sum stays below 2^32), emit() writes its results.
 
-// Run heads of a sorted key array: emits the cell table rows and the map
-// member -> cell.
+// Run heads of a sorted key array: emits the cell table rows and, when
+// member_cell is given, the map member -> cell (a scatter by member index;
+// without it the permutation is read at heads only).
 template <typename K>
 struct HeadsOp {
     const K* key;            // sorted keys [n]
@@ -411,7 +412,7 @@ struct HeadsOp {
     uint64_t* cell_key;      // [m] packed key of every cell
     uint32_t* cell_start;    // [m]
     uint32_t* cell_first;    // [m] member at the start of the run
-    uint32_t* member_cell;   // [n] member index -> cell id
+    uint32_t* member_cell;   // [n] member index -> cell id, or nullptr
     static constexpr bool kBinary = true;  // values are 0 or 1
     // the key itself is not kept between load and emit (fewer registers per
     // item, so more workgroups per compute unit): a head reads it again
@@ -423,7 +424,7 @@ struct HeadsOp {
         Item it;
         const K k = key[p];
         it.head = (p == 0 || k != key[p - 1]) ? 1u : 0u;
-        it.mem = perm[p];
+        it.mem = (member_cell || it.head) ? perm[p] : 0u;
         return it;
     }
     __device__ static uint32_t value(const Item& it) { return it.head; }
@@ -434,9 +435,57 @@ struct HeadsOp {
             cell_start[cid] = uint32_t(p);
             cell_first[cid] = it.mem;
         }
-        member_cell[it.mem] = uint32_t(cid);
+        if (member_cell) member_cell[it.mem] = uint32_t(cid);
     }
 };
+
+// Cell of every point from its key, the keys in point order (the map a
+// heads scan would scatter, written in point order instead): through the
+// dense key table, which holds the cells of the table under the current
+// epoch ...
+constexpr int kCellOfPerThread = 4;
+template <typename K>
+__global__ __launch_bounds__(256) void k_cell_of_points_dense(const K* __restrict__ key, int64_t n,
+                                                              const uint64_t* __restrict__ dk,
+                                                              uint32_t* __restrict__ cell) {
+    const int64_t i0 = int64_t(blockIdx.x) * (256 * kCellOfPerThread) + threadIdx.x;
+    K k[kCellOfPerThread];
+#pragma unroll
+    for (int u = 0; u < kCellOfPerThread; ++u) {
+        const int64_t i = i0 + u * 256;
+        k[u] = i < n ? key[i] : K(0);
+    }
+    uint64_t e[kCellOfPerThread];
+#pragma unroll
+    for (int u = 0; u < kCellOfPerThread; ++u) e[u] = i0 + u * 256 < n ? dk[uint64_t(k[u])] : 0ull;
+#pragma unroll
+    for (int u = 0; u < kCellOfPerThread; ++u)
+        if (i0 + u * 256 < n) cell[i0 + u * 256] = uint32_t(e[u]);
+}
+
+// ... or by binary search over the m <= kTailCells sorted cell keys, staged
+// in LDS by every workgroup.
+template <typename K>
+__global__ __launch_bounds__(256) void k_cell_of_points_search(const K* __restrict__ key, int64_t n,
+                                                               const uint64_t* __restrict__ cell_key, int m,
+                                                               uint32_t* __restrict__ cell) {
+    __shared__ uint64_t ck[kTailCells];
+    for (int j = threadIdx.x; j < m; j += 256) ck[j] = cell_key[j];
+    __syncthreads();
+    const int64_t i0 = int64_t(blockIdx.x) * (256 * kCellOfPerThread) + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kCellOfPerThread; ++u) {
+        const int64_t i = i0 + u * 256;
+        if (i >= n) break;
+        const uint64_t k = uint64_t(key[i]);
+        int lo = 0, hi = m - 1;  // the cell with key k exists: the first index whose key is >= k
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ck[mid] < k) lo = mid + 1; else hi = mid;
+        }
+        cell[i] = uint32_t(lo);
+    }
+}
 
 // Exclusive scan of a u32 array.
 struct ExclOp {

@@ -247,10 +247,11 @@ __global__ __launch_bounds__(kPassThreads) void k_sort_pass(const K* __restrict_
 
 template <typename K>
 hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int bits, bool hist_ready,
-                      SortScratch& sc, hipStream_t s, K** kout, uint32_t** vout) {
+                      SortScratch& sc, hipStream_t s, K** kout, uint32_t** vout, const K* kin) {
     const SortPlan plan = sort_plan(bits, sc.allow10);
     const int np = plan.passes, dg = plan.digit;
-    *kout = kA;
+    const K* k0 = kin ? kin : kA;  // keys read by the first pass
+    *kout = const_cast<K*>(k0);
     *vout = vA;
     if (n <= 0) return hipSuccess;
     if (np == 0) {
@@ -268,10 +269,10 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
         int64_t blocks = (n + kSortThreads * 16 - 1) / (kSortThreads * 16);
         if (blocks > 2048) blocks = 2048;
         const int tk = sc.prof_begin ? sc.prof_begin(sc.prof_ctx, s, "sort_hist") : -1;
-        k_sort_hist<K><<<dim3(unsigned(blocks)), dim3(kSortThreads), 0, s>>>(kA, n, np, dg, hcur);
+        k_sort_hist<K><<<dim3(unsigned(blocks)), dim3(kSortThreads), 0, s>>>(k0, n, np, dg, hcur);
         if (sc.prof_end) sc.prof_end(sc.prof_ctx, s, tk, double(n) * sizeof(K));
     }
-    K* ki = kA;
+    const K* ki = k0;
     K* ko = kB;
     uint32_t* vi = nullptr;
     uint32_t* vo = vA;
@@ -302,7 +303,9 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
         // reads keys (and values after the first pass), writes keys and values
         if (sc.prof_end)
             sc.prof_end(sc.prof_ctx, s, tk, double(n) * (sizeof(K) + (p ? 4 : 0) + sizeof(K) + 4));
-        K* kt = ki;
+        // the next pass reads this one's output and writes over the buffer
+        // this one read (kA when the first pass read `kin`)
+        K* kt = (p == 0) ? kA : const_cast<K*>(ki);
         ki = ko;
         ko = kt;
         vi = vo;
@@ -311,14 +314,14 @@ hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int b
     sc.parity ^= 1;  // the next producer accumulates into the buffer cleared above
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) sc.tile_base = 0x7fffffffull;  // counter state unknown: clear it before the next use
-    *kout = ki;
+    *kout = const_cast<K*>(ki);
     *vout = vi;
     return e;
 }
 
 template hipError_t radix_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, int, bool,
-                                         SortScratch&, hipStream_t, uint32_t**, uint32_t**);
+                                         SortScratch&, hipStream_t, uint32_t**, uint32_t**, const uint32_t*);
 template hipError_t radix_sort<uint64_t>(uint64_t*, uint64_t*, uint32_t*, uint32_t*, int64_t, int, bool,
-                                         SortScratch&, hipStream_t, uint64_t**, uint32_t**);
+                                         SortScratch&, hipStream_t, uint64_t**, uint32_t**, const uint64_t*);
 
 }  // namespace gs

@@ -66,13 +66,15 @@ inline int64_t sort_look_words(int64_t n, int bits) {
 }
 
 // Sort n pairs by the low `bits` bits of the key, stably.  The keys are in
+// `kin` when it is given (left unchanged; kA is then a third buffer), else in
 // kA; the values are implicitly 0..n-1.  kB, vA, vB are ping-pong buffers of
 // n entries.  If `hist_ready`, histogram buffer sc.parity already holds the
-// digit histograms of kA for every pass (computed by the key producer).  On return *kout/*vout
-// point at the sorted keys and the permutation (inside kA/kB, vA/vB).
+// digit histograms of the keys for every pass (computed by the key producer).
+// On return *kout/*vout point at the sorted keys and the permutation (inside
+// kA/kB, vA/vB; *kout is `kin` itself when the keys have no bits to sort).
 template <typename K>
 hipError_t radix_sort(K* kA, K* kB, uint32_t* vA, uint32_t* vB, int64_t n, int bits, bool hist_ready,
-                      SortScratch& sc, hipStream_t s, K** kout, uint32_t** vout);
+                      SortScratch& sc, hipStream_t s, K** kout, uint32_t** vout, const K* kin = nullptr);
 
 // Per-pass digit histogram accumulation for a key (device helper used by
 // producers that compute keys and histograms in one pass); the LDS

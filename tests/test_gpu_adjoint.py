@@ -52,14 +52,7 @@ def _gpu_backward(x_np, h, mubar_fn, max_iter=100):
     return r, mubar, g.cpu().numpy(), ctx
 
 
-# d = 6 is held out: a run of this case once ended with a device error (it
-# followed five fits through an experimental lookup of each point's initial
-# cell, since removed; the d = 6 fit takes the hash path, which that lookup
-# did not touch).  The cause is not shown, so the case stays skipped.
-_D6_HELD = pytest.mark.skip(reason="device error seen once in this case; cause not shown")
-
-
-@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, pytest.param(6, marks=_D6_HELD)])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6])
 def test_backward_bitwise_vs_oracle(d):
     _say(f"adjoint d={d}")
     x = _blobs(700 + d, 6000, d)

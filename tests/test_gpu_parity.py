@@ -117,6 +117,18 @@ def test_random_blobs_f32(d):
     assert_parity(x, 3.0, 100, f"blobs f32 d={d}")
 
 
+# at 2^23 points and more the initial cell of every point is looked up from
+# its key (the dense key table when a device-wide round follows, else a
+# binary search over the at most 1024 cells) instead of being scattered by the
+# heads scan: both lookups against the oracle
+@pytest.mark.parametrize("d,h", [(2, 6.0), (3, 2.0)], ids=["search", "dense"])
+def test_cell_lookup_of_large_inputs(d, h):
+    n = (1 << 23) + 1001
+    x = _blobs(3100 + d, n, d)
+    _, o = assert_parity(x, h, 100, f"cell lookup d={d}")
+    assert (o.m_hist[0] > 1024) == (d == 3)  # d = 3 takes a device-wide round, d = 2 does not
+
+
 @pytest.mark.parametrize("t", [0, 1, 2, 3, 5])
 def test_state_after_each_round(t):
     x = _blobs(3001, 8000, 3)
