@@ -681,14 +681,31 @@ constexpr int kSegThreads = 256;
 // cell's first member.  Lane l holds members l, 64 + l, 128 + l and 192 + l
 // of the chunk (consecutive lanes read consecutive members); the subtree is
 // the four 64-leaf trees over the lanes, combined as (t0 + t1) + (t2 + t3).
+// Workgroup b's place in a grid of G when workgroups go round-robin to the
+// chip's 8 XCDs (b % 8) and each XCD is to take one contiguous share.
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G) {
+    constexpr int X = 8;
+    const int64_t x = b % X, k = b / X, q = G / X, r = G % X;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// With xcd != 0 the workgroups that hold tasks are remapped so that each XCD
+// sums one contiguous range of chunk tasks: the rows the chunks gather then
+// stay within one XCD's L2 (the point sets of a batch are contiguous in the
+// task order).
 template <int D, class Src>
 __global__ __launch_bounds__(kSegThreads) void k_segsum_chunks(Src src, CellTable t, const int64_t* __restrict__ m_ptr,
                                                                const int64_t* __restrict__ tasks_ptr,
                                                                double* __restrict__ part,
-                                                               int64_t* __restrict__ partc, int64_t pcap) {
-    const int64_t task = (int64_t(blockIdx.x) * kSegThreads + threadIdx.x) / kWave;
+                                                               int64_t* __restrict__ partc, int64_t pcap, int xcd) {
+    constexpr int TPB = kSegThreads / kWave;  // tasks per workgroup
+    const int64_t ntask = *tasks_ptr;
+    const int64_t G = (ntask + TPB - 1) / TPB;  // workgroups that hold tasks (the grid is sized for a bound)
+    if (int64_t(blockIdx.x) >= G) return;
+    const int64_t blk = xcd ? xcd_contiguous(blockIdx.x, G) : int64_t(blockIdx.x);
+    const int64_t task = (blk * kSegThreads + threadIdx.x) / kWave;
     const int lane = lane_id();
-    if (task >= *tasks_ptr) return;
+    if (task >= ntask) return;
     const int64_t m = *m_ptr;
     // last cell with choff <= task, by a 65-way search: the lanes test 64
     // increasing positions strictly inside (lo, hi) at once, and the bracket
