@@ -165,6 +165,7 @@ struct gs_context {
     // point level
     DBuf kA, kB, vA, vB, cell0;
     DBuf kpt;  // keys in point order, kept through the sort when the cells of the points are looked up
+    int fit_sets = 1;  // point sets (instances) of the fit in progress
     // cell tables (ping-pong) and per-round scratch
     DBuf tkey[2], tcnt[2], tsum[2], tinst[2], tstart[2], tlen[2], tfirst[2], tnch[2], tchoff[2];
     DBuf kappa, pbuf, gmap, cur, tmap, part, partc, hk, hv, ckA, ckB, cvA, cvB;
@@ -717,7 +718,7 @@ gs_status launch_shift(gs_context* c, int d, gs::CellTable t, int64_t m, const g
         const int tk = prof_begin(c, s, "shift");
         switch (d) {
 #define GS_SH(D)                                                                                                  \
-    case D: gs::k_shift<D, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout, seq); break;
+    case D: gs::k_shift<D, Lookup><<<g, 256, 0, s>>>(t, m, prm, st, lk, pbuf, kappa, Wout, seq, c->fit_sets > 1); break;
             GS_SH(1) GS_SH(2) GS_SH(3) GS_SH(4) GS_SH(5) GS_SH(6)
 #undef GS_SH
             default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
@@ -881,6 +882,7 @@ template <typename T, typename K>
 gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const int64_t* offsets, int max_iter,
                     int bits, int32_t* labels, hipStream_t s) {
     const int64_t N = offsets[B];
+    c->fit_sets = B;
     int64_t* ctr = P<int64_t>(c->counters);
     gs::InstParam* prm = P<gs::InstParam>(c->param);
     gs::InstState* st = P<gs::InstState>(c->state);
@@ -1314,7 +1316,7 @@ gs_status launch_adj_stencil(gs_context* c, int d, const uint64_t* key, const in
     const int tk = prof_begin(c, s, "adj_stencil");
     switch (d) {
 #define GS_AS(D)                                                                                                \
-    case D: gs::k_adj_stencil<D, Lookup><<<g, 256, 0, s>>>(key, inst, applied, m, prm, lk, q, out, cap); break;
+    case D: gs::k_adj_stencil<D, Lookup><<<g, 256, 0, s>>>(key, inst, applied, m, prm, lk, q, out, cap, c->B > 1); break;
         GS_AS(1) GS_AS(2) GS_AS(3) GS_AS(4) GS_AS(5) GS_AS(6)
 #undef GS_AS
         default: return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");

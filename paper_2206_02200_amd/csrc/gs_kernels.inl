@@ -1010,13 +1010,16 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_shift(CellTable t, int6
                                                                InstState* __restrict__ st, Lookup lk,
                                                                double* __restrict__ pbuf,
                                                                uint64_t* __restrict__ kappa,
-                                                               int32_t* __restrict__ Wout, SeqStep seq) {
+                                                               int32_t* __restrict__ Wout, SeqStep seq, int xcd) {
     constexpr int NOFF = pow3(D);
     __shared__ uint32_t list[kShiftWaves][NOFF];
     __shared__ double gval[kShiftWaves][D][kWave];  // gathered rows of found cells
     __shared__ int64_t gcnt[kShiftWaves][kWave];
     const int w = threadIdx.x / kWave, lane = lane_id();
-    const int64_t j = int64_t(blockIdx.x) * kShiftWaves + w;
+    // xcd != 0: each XCD takes a contiguous range of cells, whose neighbours'
+    // rows (the same point set's cells) then stay in its L2
+    const int64_t blk = xcd ? xcd_contiguous(blockIdx.x, gridDim.x) : int64_t(blockIdx.x);
+    const int64_t j = blk * kShiftWaves + w;
     if (j >= m) return;  // wave-uniform
     const bool sequential = seq.moved != nullptr;
     if (sequential) {
@@ -2303,12 +2306,13 @@ __global__ __launch_bounds__(kShiftWaves * kWave) void k_adj_stencil(const uint6
                                                                      const int32_t* __restrict__ applied, int64_t m,
                                                                      const InstParam* __restrict__ param, Lookup lk,
                                                                      const double* __restrict__ q,
-                                                                     double* __restrict__ out, int64_t cap) {
+                                                                     double* __restrict__ out, int64_t cap, int xcd) {
     constexpr int NOFF = pow3(D);
     __shared__ int32_t list[kShiftWaves][NOFF];
     __shared__ double gval[kShiftWaves][D][kWave];  // gathered rows of found cells
     const int w = threadIdx.x / kWave, lane = lane_id();
-    const int64_t j = int64_t(blockIdx.x) * kShiftWaves + w;
+    const int64_t blk = xcd ? xcd_contiguous(blockIdx.x, gridDim.x) : int64_t(blockIdx.x);  // as in k_shift
+    const int64_t j = blk * kShiftWaves + w;
     if (j >= m) return;
     const int b = inst[j];
     if (!applied[b]) {
