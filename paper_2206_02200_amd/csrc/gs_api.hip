@@ -597,7 +597,13 @@ gs::CellTable table(gs_context* c, int i) {
 // already on the device.
 template <int D, class Src>
 gs_status segsum_d(gs_context* c, Src src, gs::CellTable t, int64_t m_bound, int64_t npos, hipStream_t s,
-                   double member_bytes, bool have_choff, bool bin, int xcd = 0) {
+                   double member_bytes, bool have_choff, bool bin) {
+    // several point sets: each XCD sums a contiguous range of chunk tasks, so
+    // that the members of one set are gathered through one L2 (measured on
+    // the 256-image batch: binning sums 1.655 -> 1.526 ms; a single set of
+    // points in random order was slower this way, so one set keeps the
+    // round-robin order)
+    const int xcd = c->fit_sets > 1 ? 1 : 0;
     int64_t* ctr = P<int64_t>(c->counters);
     if (!have_choff)
         GS_TRY(run_scan(c, gs::ExclOp{t.nch, t.choff}, ctr + 0, m_bound, ctr + 1, s,
@@ -619,14 +625,14 @@ gs_status segsum_d(gs_context* c, Src src, gs::CellTable t, int64_t m_bound, int
 
 template <class Src>
 gs_status segsum(gs_context* c, int d, Src src, gs::CellTable t, int64_t m_bound, int64_t npos, hipStream_t s,
-                 double member_bytes, bool have_choff = false, bool bin = false, int xcd = 0) {
+                 double member_bytes, bool have_choff = false, bool bin = false) {
     switch (d) {
-        case 1: return segsum_d<1>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin, xcd);
-        case 2: return segsum_d<2>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin, xcd);
-        case 3: return segsum_d<3>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin, xcd);
-        case 4: return segsum_d<4>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin, xcd);
-        case 5: return segsum_d<5>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin, xcd);
-        case 6: return segsum_d<6>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin, xcd);
+        case 1: return segsum_d<1>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin);
+        case 2: return segsum_d<2>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin);
+        case 3: return segsum_d<3>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin);
+        case 4: return segsum_d<4>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin);
+        case 5: return segsum_d<5>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin);
+        case 6: return segsum_d<6>(c, src, t, m_bound, npos, s, member_bytes, have_choff, bin);
     }
     return fail(GS_ERR_UNSUPPORTED, "d must be in 1..6");
 }
@@ -1030,12 +1036,8 @@ gs_status fit_typed(gs_context* c, const T* x, int d, int64_t ld, int B, const i
         }
         GS_HIP(hipGetLastError());
     }
-    // several point sets: each XCD sums a contiguous range of chunk tasks, so
-    // that the rows of one set are gathered through one L2 (measured on the
-    // 256-image batch: 1.655 -> 1.526 ms; a single set of points in random
-    // order was slower this way, so one set keeps the round-robin order)
     GS_TRY(segsum(c, d, gs::SrcPoints<T>{x, ld, perm, uint32_t(c->sweep_n)}, T0, m0, N, s,
-                  4.0 + double(d) * sizeof(T), false, true, B > 1 ? 1 : 0));
+                  4.0 + double(d) * sizeof(T), false, true));
     if (c->tape_on && m0 > 0) {  // the initial cells, for the adjoint and the loss
         GS_TRY(ensure(c->sums0, size_t(m0) * d * 8));
         GS_TRY(ensure(c->inst0, size_t(m0) * 4));
