@@ -77,6 +77,25 @@ def test_sweep_equals_plain_fits():
         np.testing.assert_array_equal(_bits(r.sums[ko].cpu().numpy()), _bits(p.sums.cpu().numpy()))
 
 
+def test_sweep_of_many_positions_equals_plain_fits():
+    # 200,000 points x 42 bandwidths = 8.4M positions: the sweep looks every
+    # position's initial cell up from its key (2^23 positions or more), the
+    # plain fits of 200,000 points scatter it from the heads scan
+    x_np = synth.unit_gmm_f32(200_000, 3, seed=94)
+    x = torch.from_numpy(x_np).to(DEV)
+    hs = synth.hsweep_grid(42)
+    assert x_np.shape[0] * len(hs) >= 1 << 23
+    print("hsweep case: 200000 points x 42 bandwidths against plain fits", flush=True)
+    r = gridshift.fit_hsweep(x, hs, 100, with_sums=True)
+    for j, h in enumerate(hs):
+        p = gridshift.fit(x, float(h), 100, with_sums=True)
+        np.testing.assert_array_equal(r.labels[j].cpu().numpy(), p.labels.cpu().numpy(), err_msg=f"h={h}")
+        ko = slice(r.k_offsets[j], r.k_offsets[j + 1])
+        np.testing.assert_array_equal(_bits(r.sums[ko].cpu().numpy()), _bits(p.sums.cpu().numpy()), err_msg=f"h={h}")
+    o = gs_oracle.fit(x_np.astype(np.float64), float(hs[0]), 100)  # the finest bandwidth against the oracle
+    np.testing.assert_array_equal(r.labels[0].cpu().numpy(), o.labels)
+
+
 def test_sweep_single_h_and_empty():
     x = synth.unit_gmm_f32(3000, 3, seed=94)
     _check_sweep(x, [0.25], what="one h")
