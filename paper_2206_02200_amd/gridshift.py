@@ -109,6 +109,8 @@ _lock = threading.Lock()
 def load_library(path: str = LIB_PATH):
     """Load the built library (raises if it is missing)."""
     global _lib
+    if _lib is not None:  # loaded once per process
+        return _lib
     with _lock:
         if _lib is not None:
             return _lib
@@ -296,9 +298,15 @@ def default_context(device: int | None = None) -> Context:
     return ctx
 
 
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream_ptr(stream) -> ctypes.c_void_p:
-    s = torch.cuda.current_stream() if stream is None else stream
-    return ctypes.c_void_p(s.cuda_stream)
+    if stream is None:
+        if _raw_stream is not None:  # the current stream's handle, without building a Stream object
+            return ctypes.c_void_p(_raw_stream(torch.cuda.current_device()))
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
 
 
 def _points(x: torch.Tensor) -> tuple[torch.Tensor, int, int]:

@@ -14,6 +14,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
+from oracle import gs_oracle  # noqa: E402
 from paper_2206_02200_amd import gridshift, synth  # noqa: E402
 
 DEV = torch.device("cuda:0")
@@ -200,3 +201,19 @@ def test_result_calls_on_another_stream():
     np.testing.assert_array_equal(counts_b.cpu().numpy(), counts_a.cpu().numpy())
     np.testing.assert_array_equal(_bits(grad_b), _bits(grad_a))
     np.testing.assert_array_equal(_bits(loss_b), _bits(loss_a))
+
+
+def test_current_stream_handle():
+    # the binding reads the current stream's raw handle (no Stream object per
+    # call): it must be torch's current stream, on the default stream and
+    # inside a `torch.cuda.stream` block
+    _say("binding: current stream handle")
+    assert (gridshift._stream_ptr(None).value or 0) == torch.cuda.current_stream().cuda_stream
+    s2 = torch.cuda.Stream()
+    with torch.cuda.stream(s2):
+        assert (gridshift._stream_ptr(None).value or 0) == s2.cuda_stream
+        x = torch.from_numpy(_blobs(6600, 5000, 3)).to(DEV)
+        r = gridshift.fit(x, 3.0, 100)  # queued on s2
+    s2.synchronize()
+    o = gs_oracle.fit(x.cpu().numpy(), 3.0, 100)
+    np.testing.assert_array_equal(r.labels.cpu().numpy(), o.labels)
