@@ -129,6 +129,14 @@ def test_cell_lookup_of_large_inputs(d, h):
     assert (o.m_hist[0] > 1024) == (d == 3)  # d = 3 takes a device-wide round, d = 2 does not
 
 
+# 2^24 + 1001 points: 2049 tiles of the look-back scans and 2049 tiles of
+# every radix-sort pass, a ragged last tile, the point-cell lookup
+def test_large_input_of_many_tiles():
+    n = (1 << 24) + 1001
+    x = _blobs(3200, n, 3)
+    assert_parity(x, 2.0, 100, "many tiles d=3")
+
+
 @pytest.mark.parametrize("t", [0, 1, 2, 3, 5])
 def test_state_after_each_round(t):
     x = _blobs(3001, 8000, 3)
