@@ -99,7 +99,8 @@ class Info(ctypes.Structure):
     ]
 
     def as_dict(self) -> dict:
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        return {"n_points": self.n_points, "n_cells0": self.n_cells0, "n_clusters": self.n_clusters,
+                "n_iter": self.n_iter, "flags": self.flags}
 
 
 _lib = None
